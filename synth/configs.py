@@ -1,0 +1,52 @@
+"""Workload parameters (numbers only).
+
+The lattices, N_v, dilution schemes and Lanczos settings follow the paper's production
+setup (Sec. IV: Krylov dimension 160, lambda_L = 15, lambda_C = 0.5, Chebyshev order 8,
+tolerance 1e-9 at 24^3 x 128 with N_v = 112; noise schemes of Sec. II) scaled to the
+smaller lattices.  m0 values are tuned so that FP64 CG on the even-odd normal
+equations needs roughly the stated iteration count (tools: tests/golden/tune_m0.py).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+
+@dataclass(frozen=True)
+class Config:
+    name: str
+    ns: int
+    nt: int
+    eps: float
+    seed: int
+    stout_rho: float
+    stout_steps: int
+    nv: int
+    dilution: str
+    m0: float
+    xi: float = 3.5
+    csw: float = 1.0
+    bc_t: float = -1.0
+    noise_s: int = 0
+    noise_k: int = 1
+    krylov: int = 160
+    lam_l: float = 15.0
+    lam_c: float = 0.5
+    cheb_order: int = 8
+    eig_tol: float = 1e-9
+    solve_tol: float = 1e-10
+    extra: dict = field(default_factory=dict)
+
+
+CONFIGS = {
+    # 4^3 x 8, full T x S x L dilution: 256 sources, exact-perambulator pin
+    "cfg0": Config("cfg0", ns=4, nt=8, eps=0.3, seed=1, stout_rho=0.1, stout_steps=2,
+                   nv=8, dilution="TF,SF,LF", m0=-0.04, krylov=48, lam_c=2.5,
+                   eig_tol=1e-12),
+    # 16^3 x 32, (TI16, SF, LI8): 512 sources; Dslash profiling workload
+    "cfg1": Config("cfg1", ns=16, nt=32, eps=0.4, seed=1, stout_rho=0.1, stout_steps=6,
+                   nv=48, dilution="TI16,SF,LI8", m0=-0.04, krylov=96, lam_c=0.5,
+                   eig_tol=1e-10),
+    # 24^3 x 128, (TF, SF, LI8): production lattice of the paper
+    "cfg2": Config("cfg2", ns=24, nt=128, eps=0.4, seed=1, stout_rho=0.1, stout_steps=10,
+                   nv=112, dilution="TF,SF,LI8", m0=-0.04),
+}

@@ -1,0 +1,236 @@
+/*
+ * laph.h -- C ABI of the MI355X stochastic-LapH hot path.
+ *
+ * The calls follow the statement of the problem in Morningstar et al. (arXiv:1104.3870):
+ * the LapH subspace V_s of the stout-smeared 3D covariant Laplacian (Sec. II, Eq. smearA
+ * and the definition of V_s; eigensolver of Sec. IV), Z4 noise rho diluted by projectors
+ * P^(b) in that subspace (Sec. II, dilution schemes; Sec. IV, Z4 noise), the solve of
+ * Omega x = V_s P^(b) rho with Omega = gamma_4 K (Sec. II, Sec. IV), and the quark
+ * propagation coefficients V_s^dag x (Sec. IV).
+ *
+ * Conventions shared by every call (frozen readings where the paper is silent):
+ *  - lattice Ns^3 x Nt, Ns and Nt even; site s = x + Ns*(y + Ns*(z + Ns*t));
+ *  - complex numbers are interleaved (re, im) doubles;
+ *  - gauge links    U[((s*4 + mu)*3 + a)*3 + b], mu = 0,1,2 space, 3 time;
+ *  - spinor fields  psi[(s*4 + alpha)*3 + c]; n fields are stored back to back;
+ *  - colour fields  v[s*3 + c];
+ *  - eigenvectors   evecs[((t*Nv + n)*Ns^3 + xyz)*3 + c];
+ *  - coefficients   coef[((r*Nt + t)*4 + alpha)*Nv + n];
+ *  - noise          rho[(t*4 + alpha)*Nv + n].
+ *  - gamma matrices: Hermitian chiral basis, gamma_k = [[0,-i sigma_k],[i sigma_k,0]],
+ *    gamma_4 = [[0,1],[1,0]], gamma_5 = diag(1,1,-1,-1).
+ *
+ * Ownership: the caller owns every pointer and the library never frees caller memory.
+ * Field arguments are DEVICE pointers unless stated otherwise; statistics structs and
+ * eigenvalues are host memory.  A context owns device scratch it allocates itself and
+ * caches derived fields (even-odd links, clover term and its inverse) for the last gauge
+ * field it saw: call laph_forget_gauge() after changing a gauge field in place.
+ * Every call enqueues work on the context's HIP stream; calls that return statistics
+ * synchronise that stream.  One context per stream; contexts share nothing.
+ *
+ * Errors: every call returns an int status (LAPH_OK on success); no C++ exception
+ * crosses the ABI.  laph_strerror() names a status, laph_last_error() gives detail.
+ */
+#ifndef LAPH_H
+#define LAPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define LAPH_API __attribute__((visibility("default")))
+#else
+#define LAPH_API
+#endif
+
+enum {
+    LAPH_OK = 0,
+    LAPH_EINVAL = 1,  /* bad argument: null pointer, odd extent, out-of-range index */
+    LAPH_EDIVIDE = 2, /* a dilution N/J that is not an integer (Sec. II) */
+    LAPH_ENOCONV = 3, /* true residual above tol after every fallback; x holds the best iterate */
+    LAPH_EEIG = 4,    /* eigensolver reached max_restarts before all N_v pairs converged */
+    LAPH_EHIP = 5,    /* HIP runtime error */
+    LAPH_ENOMEM = 6   /* device allocation failed */
+};
+
+typedef struct laph_ctx *laph_ctx_t;
+
+typedef struct {
+    int ns; /* spatial extent (even) */
+    int nt; /* temporal extent (even) */
+} laph_geom;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context for one lattice geometry; hip_stream is a hipStream_t (NULL: the
+ * null stream).  The device is the one current when this is called. */
+LAPH_API int laph_create(laph_ctx_t *ctx, const laph_geom *geom, void *hip_stream);
+LAPH_API int laph_destroy(laph_ctx_t ctx);
+LAPH_API const char *laph_strerror(int status);
+LAPH_API const char *laph_last_error(laph_ctx_t ctx);
+/* Drop every cached field derived from a gauge field. */
+LAPH_API int laph_forget_gauge(laph_ctx_t ctx);
+/* Device memory currently held by the context, in bytes. */
+LAPH_API size_t laph_device_bytes(laph_ctx_t ctx);
+
+/* -------------------------------------------------- stout smearing (Sec. II)
+ * Spatial stout smearing (Morningstar & Peardon 2004) with spatial staples only; time
+ * links are copied unchanged.  U_out may not alias U. */
+typedef struct {
+    double rho; /* staple weight */
+    int nsteps;
+} laph_stout;
+
+LAPH_API int laph_stout_smear(laph_ctx_t ctx, const double *U, const laph_stout *stout, double *U_out);
+
+/* ------------------------------------------------ Laplacian (Sec. II, Sec. IV)
+ * out = Lap v on every time slice, (Lap v)(x) = sum_k [U_k(x) v(x+k) + U_k(x-k)^dag
+ * v(x-k) - 2 v(x)], with U the (smeared) links given.  v, out: colour fields [V][3]. */
+LAPH_API int laph_laplacian_apply(laph_ctx_t ctx, const double *U, const double *v, double *out);
+
+/* out = T_order(B) v with B = 1 + 2/(lambda_L - lambda_C) (Lap + lambda_C)  (Sec. IV,
+ * Chebyshev acceleration). */
+LAPH_API int laph_chebyshev_apply(laph_ctx_t ctx, const double *U, double lambda_L, double lambda_C,
+                         int order, const double *v, double *out);
+
+/* --------------------------------------------------------- LapH eigenvectors
+ * The N_v lowest eigenpairs of -Lap on every time slice of the stout-smeared field
+ * (Sec. II, definition of V_s) by the Krylov-spectral restarted Lanczos method with
+ * Chebyshev acceleration, full reorthogonalisation with the kappa = sqrt(2) rule (at
+ * most four extra passes), locking of converged pairs and the convergence test
+ * |A x - lambda x| < tol |A| (Sec. IV).  Eigenvalues are the Rayleigh quotients on
+ * -Lap, ascending per slice; each eigenvector is multiplied by the phase that makes its
+ * first component (storage order) of modulus >= 0.1 of the largest real and positive
+ * (the paper asks for a convention without stating it).  U is the UNSMEARED field; the
+ * call smears it.  evals: HOST [Nt][Nv]; evecs: device [Nt][Nv][Ns^3][3]. */
+typedef struct {
+    int krylov_dim;     /* m, at most 160 */
+    int cheb_order;     /* n of T_n */
+    double lambda_L;    /* upper bound of the spectrum of -Lap */
+    double lambda_C;    /* cut-off above the wanted part */
+    double tol;         /* convergence tolerance relative to |A| */
+    int max_restarts;
+    uint32_t seed;      /* start vectors are Philox draws from this seed */
+} laph_lanczos;
+
+typedef struct {
+    int restarts;        /* restarts used */
+    int matvecs;         /* applications of A = T_n(B) per slice */
+    double max_residual; /* max over pairs of |(-Lap) v - lambda v| */
+    double max_orth;     /* max over slices of |V^dag V - 1| (elementwise) */
+    double min_gap;      /* min over slices of (next Ritz value) - lambda_{Nv}, estimate */
+} laph_eig_stats;
+
+LAPH_API int laph_eigvecs(laph_ctx_t ctx, const double *U, const laph_stout *stout,
+                 const laph_lanczos *lanczos, int nv, double *evals, double *evecs,
+                 laph_eig_stats *stats);
+
+/* ------------------------------------------------- noise and dilution (Sec. II)
+ * Dilution projector families (Sec. II): none "1", full "F", block-J "BJ" (b = J i / N),
+ * interlace-J "IJ" (b = i mod J), applied to time (N = Nt), spin (N = 4) and LapH
+ * index (N = Nv).  The projector index is b = (b_T * n_S + b_S) * n_L + b_L. */
+enum { LAPH_DIL_NONE = 0, LAPH_DIL_FULL = 1, LAPH_DIL_BLOCK = 2, LAPH_DIL_INTERLACE = 3 };
+
+typedef struct {
+    int type[3]; /* time, spin, LapH */
+    int J[3];    /* J for block / interlace, ignored otherwise */
+} laph_dilution;
+
+/* Parse "TI16,SF,LI8" or "(TF, SF, LB4)"; LAPH_EDIVIDE when N/J is not an integer.
+ * Host-only; needs no context. */
+LAPH_API int laph_parse_dilution(const char *text, int nt, int nv, laph_dilution *out);
+/* number of projectors n_T * n_S * n_L, or -1 for an invalid scheme. Host-only. */
+LAPH_API long laph_dilution_count(const laph_dilution *dil, int nt, int nv);
+
+/* Z4 noise rho(t, alpha, n) = i^(w mod 4), w the first word of Philox4x32-10 with counter
+ * (n, alpha, t, 0) and key ((k << 16) | s, 0x4C415048) (Sec. IV names the noise by a
+ * 16-bit id s and a 16-bit configuration id k; the generator is our reading).
+ * rho: device [Nt][4][Nv]. */
+LAPH_API int laph_z4_noise(laph_ctx_t ctx, uint16_t noise_s, uint16_t config_k, int nv, double *rho);
+
+/* eta^[b] = V_s P^(b) rho for the n_src projector indices b_first .. b_first+n_src-1
+ * (Sec. IV, right-hand side y = V_s P^[b] rho).  eta: device, n_src spinor fields. */
+LAPH_API int make_diluted_source(laph_ctx_t ctx, const double *evecs, int nv, uint16_t noise_s,
+                        uint16_t config_k, const laph_dilution *dil, int64_t b_first,
+                        int n_src, double *eta);
+
+/* ------------------------------------------------------------- Dirac operator
+ * K = A + H, the anisotropic Wilson-clover matrix (frozen reading; the paper names an
+ * improved anisotropic clover action, Sec. V):
+ *   (H psi)(x) = -1/2 sum_mu w_mu [(1-gamma_mu) U_mu(x) psi(x+mu) + (1+gamma_mu) U_mu(x-mu)^dag psi(x-mu)]
+ *   w_4 = 1, w_k = 1/xi, every hop across t = Nt-1 <-> 0 multiplied by bc_t,
+ *   A(x) = m0 + 1 + 3/xi - 1/2 [c_t sum_k sigma_k4 F_k4 + c_s sum_{k<l} sigma_kl F_kl],
+ *   c_s = c_sw/xi, c_t = c_sw (1 + 1/xi)/2, F the traceless anti-Hermitian part of the
+ *   four-leaf clover divided by 8i.  Omega = gamma_4 K (Sec. II). */
+typedef struct {
+    double m0;
+    double xi;
+    double c_sw;
+    double bc_t; /* -1: antiperiodic fermions */
+} laph_dirac;
+
+enum { LAPH_OP_K = 0, LAPH_OP_OMEGA = 1, LAPH_OP_KDAG = 2 };
+
+/* out = op(in) on n_fields spinor fields (full lattice, FP64). */
+LAPH_API int laph_dirac_apply(laph_ctx_t ctx, const double *U, const laph_dirac *dirac, int op,
+                     const double *in, double *out, int n_fields);
+
+enum { LAPH_PREC_F64 = 0, LAPH_PREC_F32 = 1, LAPH_PREC_F16 = 2, LAPH_PREC_BF16 = 3 };
+enum { LAPH_SOLVER_BICGSTAB = 0, LAPH_SOLVER_CGNR = 1, LAPH_SOLVER_FGMRES = 2 };
+
+typedef struct {
+    double tol;         /* true relative residual |eta - Omega x| / |eta| in FP64 */
+    int maxiter;        /* Krylov iterations per right-hand side and attempt */
+    int solver;         /* LAPH_SOLVER_*: BiCGStab on the even-odd system with CGNR fallback
+                           (Sec. IV), CGNR only, or FGMRES with a learned preconditioner */
+    int precision;      /* LAPH_PREC_*: storage precision of the inner Krylov vectors;
+                           FP64 reliable updates are used for every lower precision */
+    int reliable_every; /* iterations between FP64 reliable updates (mixed precision) */
+    int block_rhs;      /* right-hand sides iterated together (1..32); 0 = autotune */
+    int use_graph;      /* capture the iteration in HIP graphs */
+    const void *net;    /* learned preconditioner (laph_ptnet_t) for LAPH_SOLVER_FGMRES */
+} laph_solver;
+
+typedef struct {
+    int iters;          /* Krylov iterations of the successful attempt(s) */
+    int status;         /* LAPH_OK or LAPH_ENOCONV */
+    int fallback_used;  /* 1 if the CGNR fallback (or plain solver) was needed */
+    double true_resid;  /* |eta - Omega x| / |eta| evaluated in FP64 after the solve */
+} laph_solve_stats;
+
+/* Solve Omega x = eta for n_rhs right-hand sides (Sec. IV).  eta, x: device, n_rhs
+ * spinor fields each (FP64); stats: HOST array of n_rhs (may be NULL).
+ * Up to three BiCGStab attempts (each restarted from the current x with a tighter
+ * even-odd target when the FP64 true residual of the full system misses tol) are
+ * followed by the CGNR fallback, which runs up to max(maxiter, 5000) iterations. */
+LAPH_API int dirac_solve(laph_ctx_t ctx, const double *U, const laph_dirac *dirac, const double *eta,
+                double *x, int n_rhs, const laph_solver *solver, laph_solve_stats *stats);
+
+/* ----------------------------------------------------------- sink projection
+ * coef[r][t][alpha][n] = sum_{x,c} conj(V_{t,n}(x,c)) X_r(x,t,c,alpha): the quark
+ * propagation coefficients V_s^dag Omega^-1 V_s P^[b] rho (Sec. IV).  X: device n_rhs
+ * spinor fields; coef: device [n_rhs][Nt][4][Nv] complex. */
+LAPH_API int sink_project(laph_ctx_t ctx, const double *evecs, int nv, const double *X, int n_rhs,
+                 double *coef);
+
+/* ----------------------------------------------------------------- profiling
+ * With timing on, the library brackets every even-odd hopping kernel launch with HIP
+ * events on its stream and accumulates their durations. */
+typedef struct {
+    double dslash_ms;     /* summed duration of hopping-term kernel launches */
+    long dslash_launches;
+    double dslash_bytes;  /* algorithmic bytes moved by those launches */
+} laph_timing;
+
+LAPH_API int laph_set_timing(laph_ctx_t ctx, int enable);
+LAPH_API int laph_get_timing(laph_ctx_t ctx, laph_timing *out, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LAPH_H */

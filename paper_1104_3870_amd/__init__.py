@@ -1,0 +1,259 @@
+"""MI355X stochastic-LapH hot path (arXiv:1104.3870) -- Python binding of liblaph.so.
+
+Argument marshalling only: every step runs in the HIP kernels of ``liblaph.so``.  Device
+memory is owned by torch tensors (complex128 fields, or float64 with a trailing
+(re, im) axis); the library works on the stream passed at context creation (default:
+torch's current stream).  The binding raises if the library has not been built, and
+it never falls back to any CPU computation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblaph.so")
+
+LAPH_OK, LAPH_EINVAL, LAPH_EDIVIDE, LAPH_ENOCONV, LAPH_EEIG, LAPH_EHIP, LAPH_ENOMEM = range(7)
+LAPH_DIL_NONE, LAPH_DIL_FULL, LAPH_DIL_BLOCK, LAPH_DIL_INTERLACE = range(4)
+LAPH_OP_K, LAPH_OP_OMEGA, LAPH_OP_KDAG = range(3)
+LAPH_PREC_F64, LAPH_PREC_F32, LAPH_PREC_F16, LAPH_PREC_BF16 = range(4)
+LAPH_SOLVER_BICGSTAB, LAPH_SOLVER_CGNR, LAPH_SOLVER_FGMRES = range(3)
+PRECISIONS = {"f64": LAPH_PREC_F64, "f32": LAPH_PREC_F32, "f16": LAPH_PREC_F16, "bf16": LAPH_PREC_BF16}
+
+
+class LaphError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(msg)
+        self.code = code
+
+
+class laph_geom(ctypes.Structure):
+    _fields_ = [("ns", ctypes.c_int), ("nt", ctypes.c_int)]
+
+
+class laph_stout(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_double), ("nsteps", ctypes.c_int)]
+
+
+class laph_lanczos(ctypes.Structure):
+    _fields_ = [("krylov_dim", ctypes.c_int), ("cheb_order", ctypes.c_int), ("lambda_L", ctypes.c_double),
+                ("lambda_C", ctypes.c_double), ("tol", ctypes.c_double), ("max_restarts", ctypes.c_int),
+                ("seed", ctypes.c_uint32)]
+
+
+class laph_eig_stats(ctypes.Structure):
+    _fields_ = [("restarts", ctypes.c_int), ("matvecs", ctypes.c_int), ("max_residual", ctypes.c_double),
+                ("max_orth", ctypes.c_double), ("min_gap", ctypes.c_double)]
+
+
+class laph_dilution(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int * 3), ("J", ctypes.c_int * 3)]
+
+
+class laph_dirac(ctypes.Structure):
+    _fields_ = [("m0", ctypes.c_double), ("xi", ctypes.c_double), ("c_sw", ctypes.c_double),
+                ("bc_t", ctypes.c_double)]
+
+
+class laph_solver(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("solver", ctypes.c_int),
+                ("precision", ctypes.c_int), ("reliable_every", ctypes.c_int), ("block_rhs", ctypes.c_int),
+                ("use_graph", ctypes.c_int), ("net", ctypes.c_void_p)]
+
+
+class laph_solve_stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("fallback_used", ctypes.c_int),
+                ("true_resid", ctypes.c_double)]
+
+
+class laph_timing(ctypes.Structure):
+    _fields_ = [("dslash_ms", ctypes.c_double), ("dslash_launches", ctypes.c_long),
+                ("dslash_bytes", ctypes.c_double)]
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+
+EXPORTS = {
+    "laph_create": (_I, [ctypes.POINTER(_P), ctypes.POINTER(laph_geom), _P]),
+    "laph_destroy": (_I, [_P]),
+    "laph_strerror": (ctypes.c_char_p, [_I]),
+    "laph_last_error": (ctypes.c_char_p, [_P]),
+    "laph_forget_gauge": (_I, [_P]),
+    "laph_device_bytes": (ctypes.c_size_t, [_P]),
+    "laph_stout_smear": (_I, [_P, _P, ctypes.POINTER(laph_stout), _P]),
+    "laph_laplacian_apply": (_I, [_P, _P, _P, _P]),
+    "laph_chebyshev_apply": (_I, [_P, _P, _D, _D, _I, _P, _P]),
+    "laph_eigvecs": (_I, [_P, _P, ctypes.POINTER(laph_stout), ctypes.POINTER(laph_lanczos), _I, _P, _P,
+                          ctypes.POINTER(laph_eig_stats)]),
+    "laph_parse_dilution": (_I, [ctypes.c_char_p, _I, _I, ctypes.POINTER(laph_dilution)]),
+    "laph_dilution_count": (ctypes.c_long, [ctypes.POINTER(laph_dilution), _I, _I]),
+    "laph_z4_noise": (_I, [_P, ctypes.c_uint16, ctypes.c_uint16, _I, _P]),
+    "make_diluted_source": (_I, [_P, _P, _I, ctypes.c_uint16, ctypes.c_uint16, ctypes.POINTER(laph_dilution),
+                                 ctypes.c_int64, _I, _P]),
+    "laph_dirac_apply": (_I, [_P, _P, ctypes.POINTER(laph_dirac), _I, _P, _P, _I]),
+    "dirac_solve": (_I, [_P, _P, ctypes.POINTER(laph_dirac), _P, _P, _I, ctypes.POINTER(laph_solver),
+                         ctypes.POINTER(laph_solve_stats)]),
+    "sink_project": (_I, [_P, _P, _I, _P, _I, _P]),
+    "laph_set_timing": (_I, [_P, _I]),
+    "laph_get_timing": (_I, [_P, ctypes.POINTER(laph_timing), _I]),
+}
+
+
+def lib():
+    """Load liblaph.so (raises when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("liblaph.so not built: run __graft_entry__.build() "
+                              "(python -m paper_1104_3870_amd.build)")
+        # torch ships its own HIP runtime under the same soname; load it first so that
+        # liblaph.so binds to that copy and torch's streams and allocations are valid
+        # in the library (one runtime per process).
+        import torch  # noqa: F401
+
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc, ctx=None):
+    if rc != LAPH_OK:
+        L = lib()
+        detail = L.laph_last_error(ctx).decode() if ctx else ""
+        raise LaphError(rc, "%s%s" % (L.laph_strerror(rc).decode(), (": " + detail) if detail else ""))
+
+
+def _dptr(t, dtype=None):
+    """Device pointer of a contiguous CUDA tensor."""
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("expected %s, got %s" % (dtype, t.dtype))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ ABI names
+
+def laph_create(ns, nt, stream=None):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    h = ctypes.c_void_p()
+    _check(lib().laph_create(ctypes.byref(h), ctypes.byref(laph_geom(ns, nt)), ctypes.c_void_p(stream)))
+    return h
+
+
+def laph_destroy(ctx):
+    _check(lib().laph_destroy(ctx))
+
+
+def laph_parse_dilution(text, nt, nv):
+    d = laph_dilution()
+    _check(lib().laph_parse_dilution(text.encode(), nt, nv, ctypes.byref(d)))
+    return d
+
+
+def laph_dilution_count(dil, nt, nv):
+    return lib().laph_dilution_count(ctypes.byref(dil), nt, nv)
+
+
+def laph_stout_smear(ctx, U, rho, nsteps, out):
+    _check(lib().laph_stout_smear(ctx, _dptr(U), ctypes.byref(laph_stout(rho, nsteps)), _dptr(out)), ctx)
+
+
+def laph_laplacian_apply(ctx, U, v, out):
+    _check(lib().laph_laplacian_apply(ctx, _dptr(U), _dptr(v), _dptr(out)), ctx)
+
+
+def laph_chebyshev_apply(ctx, U, lam_l, lam_c, order, v, out):
+    _check(lib().laph_chebyshev_apply(ctx, _dptr(U), lam_l, lam_c, order, _dptr(v), _dptr(out)), ctx)
+
+
+def laph_eigvecs(ctx, U, rho, nsteps, nv, evals_host, evecs, krylov=160, cheb_order=8, lam_l=15.0, lam_c=0.5,
+                 tol=1e-9, max_restarts=50, seed=12345):
+    """evals_host: numpy float64 [Nt, Nv] (filled); evecs: device complex128 [Nt, Nv, Ns, Ns, Ns, 3]."""
+    import numpy as np
+
+    assert evals_host.dtype == np.float64 and evals_host.flags["C_CONTIGUOUS"]
+    st = laph_eig_stats()
+    lz = laph_lanczos(krylov, cheb_order, lam_l, lam_c, tol, max_restarts, seed)
+    rc = lib().laph_eigvecs(ctx, _dptr(U), ctypes.byref(laph_stout(rho, nsteps)), ctypes.byref(lz), nv,
+                            evals_host.ctypes.data_as(ctypes.c_void_p), _dptr(evecs), ctypes.byref(st))
+    _check(rc, ctx)
+    return st
+
+
+def laph_z4_noise(ctx, s, k, nv, rho):
+    _check(lib().laph_z4_noise(ctx, s, k, nv, _dptr(rho)), ctx)
+
+
+def make_diluted_source(ctx, evecs, nv, noise_s, config_k, dil, b_first, n_src, eta):
+    _check(lib().make_diluted_source(ctx, _dptr(evecs), nv, noise_s, config_k, ctypes.byref(dil), b_first, n_src,
+                                     _dptr(eta)), ctx)
+
+
+def laph_dirac_apply(ctx, U, dirac, op, x, out, n_fields=1):
+    _check(lib().laph_dirac_apply(ctx, _dptr(U), ctypes.byref(dirac), op, _dptr(x), _dptr(out), n_fields), ctx)
+
+
+def dirac_solve(ctx, U, dirac, eta, x, n_rhs, solver, raise_on_noconv=True):
+    stats = (laph_solve_stats * n_rhs)()
+    rc = lib().dirac_solve(ctx, _dptr(U), ctypes.byref(dirac), _dptr(eta), _dptr(x), n_rhs, ctypes.byref(solver),
+                           stats)
+    if rc == LAPH_ENOCONV and not raise_on_noconv:
+        return list(stats)
+    _check(rc, ctx)
+    return list(stats)
+
+
+def sink_project(ctx, evecs, nv, X, n_rhs, coef):
+    _check(lib().sink_project(ctx, _dptr(evecs), nv, _dptr(X), n_rhs, _dptr(coef)), ctx)
+
+
+def laph_set_timing(ctx, enable):
+    _check(lib().laph_set_timing(ctx, int(enable)), ctx)
+
+
+def laph_get_timing(ctx, reset=False):
+    t = laph_timing()
+    _check(lib().laph_get_timing(ctx, ctypes.byref(t), int(reset)), ctx)
+    return t
+
+
+def solver_params(tol=1e-10, maxiter=20000, precision="f64", solver=LAPH_SOLVER_BICGSTAB, reliable_every=50,
+                  block_rhs=1, use_graph=0):
+    return laph_solver(tol, maxiter, solver, PRECISIONS[precision] if isinstance(precision, str) else precision,
+                       reliable_every, block_rhs, use_graph, None)
+
+
+class Lattice:
+    """Convenience owner of one context (geometry + stream)."""
+
+    def __init__(self, ns, nt, stream=None):
+        self.ns, self.nt = ns, nt
+        self.ctx = laph_create(ns, nt, stream)
+
+    def close(self):
+        if self.ctx:
+            laph_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

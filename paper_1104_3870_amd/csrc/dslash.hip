@@ -1,0 +1,386 @@
+// Even-odd anisotropic Wilson-clover hopping kernel with fused clover epilogues.
+#include "dslash.h"
+
+namespace {
+
+template <typename A>
+struct Spin {
+    Cx<A> v[4][3];
+};
+
+template <typename A>
+__device__ __forceinline__ void mat_vec(const Cx<A> (&U)[9], const Cx<A> (&h)[3], Cx<A> (&o)[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; a++) o[a] = U[a * 3] * h[0] + U[a * 3 + 1] * h[1] + U[a * 3 + 2] * h[2];
+}
+template <typename A>
+__device__ __forceinline__ void mat_dag_vec(const Cx<A> (&U)[9], const Cx<A> (&h)[3], Cx<A> (&o)[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; a++) o[a] = conjmul(U[a], h[0]) + conjmul(U[3 + a], h[1]) + conjmul(U[6 + a], h[2]);
+}
+
+template <class GP, typename A>
+__device__ __forceinline__ void load_link(const typename GP::E *g, int mu, int par, long Vh, long i, Cx<A> (&U)[9])
+{
+    const typename GP::E *p = g + (long)(mu * 2 + par) * 9 * Vh + i;
+#pragma unroll
+    for (int k = 0; k < 9; k++) U[k] = GP::template ld<A>(p, (long)k * Vh);
+}
+
+template <class SP>
+__device__ __forceinline__ void load_spinor(const typename SP::E *s, const float *nrm, long Vh, int R, long i, int r,
+                                            Spin<typename SP::A> &out)
+{
+    float sc = 1.0f;
+    if constexpr (SP::kNorm) sc = nrm[i * R + r];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) out.v[a][c] = SP::ld(s, ((long)(a * 3 + c) * Vh + i) * R + r, sc);
+}
+
+template <class SP>
+__device__ __forceinline__ void store_spinor(typename SP::E *s, float *nrm, long Vh, int R, long i, int r,
+                                             const Spin<typename SP::A> &in)
+{
+    float inv = 1.0f;
+    if constexpr (SP::kNorm) {
+        float m = 0.0f;
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) m = fmaxf(m, fmaxf(fabsf((float)in.v[a][c].re), fabsf((float)in.v[a][c].im)));
+        float sc = m > 0.0f ? m : 1.0f;
+        nrm[i * R + r] = sc;
+        inv = 1.0f / sc;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) SP::st(s, ((long)(a * 3 + c) * Vh + i) * R + r, in.v[a][c], inv);
+}
+
+// packed Hermitian 6x6 block times a 6-vector
+template <class CP, typename A>
+__device__ __forceinline__ void herm6(const typename CP::E *cl, long Vh, long i, const Cx<A> (&v)[6], Cx<A> (&o)[6])
+{
+    A d[6];
+#pragma unroll
+    for (int k = 0; k < 6; k++) d[k] = (A)cl[(long)k * Vh + i];
+#pragma unroll
+    for (int k = 0; k < 6; k++) o[k] = d[k] * v[k];
+    int e = 6;
+#pragma unroll
+    for (int r = 1; r < 6; r++)
+#pragma unroll
+        for (int c = 0; c < r; c++) {
+            Cx<A> L = {(A)cl[(long)e * Vh + i], (A)cl[(long)(e + 1) * Vh + i]};
+            e += 2;
+            o[r] = o[r] + L * v[c];
+            o[c] = o[c] + conjmul(L, v[r]);
+        }
+}
+
+template <class CP, typename A>
+__device__ __forceinline__ void clover_mul(const typename CP::E *cl, long Vh, long i, const Spin<A> &in, Spin<A> &out)
+{
+#pragma unroll
+    for (int blk = 0; blk < 2; blk++) {
+        Cx<A> v[6], o[6];
+#pragma unroll
+        for (int s = 0; s < 2; s++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) v[s * 3 + c] = in.v[blk * 2 + s][c];
+        herm6<CP, A>(cl + (long)blk * 36 * Vh, Vh, i, v, o);
+#pragma unroll
+        for (int s = 0; s < 2; s++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) out.v[blk * 2 + s][c] = o[s * 3 + c];
+    }
+}
+
+template <typename A>
+__device__ __forceinline__ void acc_upper(Spin<A> &acc, const Cx<A> (&w0)[3], const Cx<A> (&w1)[3])
+{
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        acc.v[0][c] = acc.v[0][c] + w0[c];
+        acc.v[1][c] = acc.v[1][c] + w1[c];
+    }
+}
+
+template <class SP, class GP, class CP, int MODE>
+__global__ __launch_bounds__(256) void k_dslash(const DslashArgs P)
+{
+    using A = typename SP::A;
+    unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    long tid = (long)b * blockDim.x + threadIdx.x;
+    const int R = P.R;
+    const long Vh = P.Vh;
+    if (tid >= Vh * R) return;
+    long i = tid / R;
+    int r = (int)(tid - i * R);
+    const int ns = P.ns, nt = P.nt, par = P.par, opar = par ^ 1;
+    int x, y, z, t;
+    cb_coords(i, par, ns, x, y, z, t);
+    const auto *in = (const typename SP::E *)P.in;
+    const auto *g = (const typename GP::E *)P.gauge;
+
+    Spin<A> acc;
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) acc.v[a][c] = {(A)0, (A)0};
+
+#pragma unroll
+    for (int mu = 0; mu < 4; mu++) {
+        // ---------------- forward hop: (1 - g_mu) U_mu(x) psi(x+mu)
+        {
+            int xx = x, yy = y, zz = z, tt = t;
+            A w = (A)(mu == 3 ? P.wt : P.ws);
+            if (mu == 0) xx = (x + 1 == ns) ? 0 : x + 1;
+            if (mu == 1) yy = (y + 1 == ns) ? 0 : y + 1;
+            if (mu == 2) zz = (z + 1 == ns) ? 0 : z + 1;
+            if (mu == 3) {
+                tt = (t + 1 == nt) ? 0 : t + 1;
+                if (t + 1 == nt) w *= (A)P.bct;
+            }
+            long nb = lex_index(xx, yy, zz, tt, ns) >> 1;
+            Spin<A> s;
+            load_spinor<SP>(in, P.in_nrm, Vh, R, nb, r, s);
+            Cx<A> U[9];
+            load_link<GP, A>(g, mu, par, Vh, i, U);
+            Cx<A> h0[3], h1[3], o0[3], o1[3];
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                if (mu == 0) {
+                    h0[c] = s.v[0][c] + timesI(s.v[3][c]);
+                    h1[c] = s.v[1][c] + timesI(s.v[2][c]);
+                } else if (mu == 1) {
+                    h0[c] = s.v[0][c] + s.v[3][c];
+                    h1[c] = s.v[1][c] - s.v[2][c];
+                } else if (mu == 2) {
+                    h0[c] = s.v[0][c] + timesI(s.v[2][c]);
+                    h1[c] = s.v[1][c] - timesI(s.v[3][c]);
+                } else {
+                    h0[c] = s.v[0][c] - s.v[2][c];
+                    h1[c] = s.v[1][c] - s.v[3][c];
+                }
+                h0[c] = w * h0[c];
+                h1[c] = w * h1[c];
+            }
+            mat_vec(U, h0, o0);
+            mat_vec(U, h1, o1);
+            acc_upper(acc, o0, o1);
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                if (mu == 0) {
+                    acc.v[2][c] = acc.v[2][c] + timesMinusI(o1[c]);
+                    acc.v[3][c] = acc.v[3][c] + timesMinusI(o0[c]);
+                } else if (mu == 1) {
+                    acc.v[2][c] = acc.v[2][c] - o1[c];
+                    acc.v[3][c] = acc.v[3][c] + o0[c];
+                } else if (mu == 2) {
+                    acc.v[2][c] = acc.v[2][c] + timesMinusI(o0[c]);
+                    acc.v[3][c] = acc.v[3][c] + timesI(o1[c]);
+                } else {
+                    acc.v[2][c] = acc.v[2][c] - o0[c];
+                    acc.v[3][c] = acc.v[3][c] - o1[c];
+                }
+            }
+        }
+        // ---------------- backward hop: (1 + g_mu) U_mu(x-mu)^dag psi(x-mu)
+        {
+            int xx = x, yy = y, zz = z, tt = t;
+            A w = (A)(mu == 3 ? P.wt : P.ws);
+            if (mu == 0) xx = (x == 0) ? ns - 1 : x - 1;
+            if (mu == 1) yy = (y == 0) ? ns - 1 : y - 1;
+            if (mu == 2) zz = (z == 0) ? ns - 1 : z - 1;
+            if (mu == 3) {
+                tt = (t == 0) ? nt - 1 : t - 1;
+                if (t == 0) w *= (A)P.bct;
+            }
+            long nb = lex_index(xx, yy, zz, tt, ns) >> 1;
+            Spin<A> s;
+            load_spinor<SP>(in, P.in_nrm, Vh, R, nb, r, s);
+            Cx<A> U[9];
+            load_link<GP, A>(g, mu, opar, Vh, nb, U);
+            Cx<A> h0[3], h1[3], o0[3], o1[3];
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                if (mu == 0) {
+                    h0[c] = s.v[0][c] - timesI(s.v[3][c]);
+                    h1[c] = s.v[1][c] - timesI(s.v[2][c]);
+                } else if (mu == 1) {
+                    h0[c] = s.v[0][c] - s.v[3][c];
+                    h1[c] = s.v[1][c] + s.v[2][c];
+                } else if (mu == 2) {
+                    h0[c] = s.v[0][c] - timesI(s.v[2][c]);
+                    h1[c] = s.v[1][c] + timesI(s.v[3][c]);
+                } else {
+                    h0[c] = s.v[0][c] + s.v[2][c];
+                    h1[c] = s.v[1][c] + s.v[3][c];
+                }
+                h0[c] = w * h0[c];
+                h1[c] = w * h1[c];
+            }
+            mat_dag_vec(U, h0, o0);
+            mat_dag_vec(U, h1, o1);
+            acc_upper(acc, o0, o1);
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                if (mu == 0) {
+                    acc.v[2][c] = acc.v[2][c] + timesI(o1[c]);
+                    acc.v[3][c] = acc.v[3][c] + timesI(o0[c]);
+                } else if (mu == 1) {
+                    acc.v[2][c] = acc.v[2][c] + o1[c];
+                    acc.v[3][c] = acc.v[3][c] - o0[c];
+                } else if (mu == 2) {
+                    acc.v[2][c] = acc.v[2][c] + timesI(o0[c]);
+                    acc.v[3][c] = acc.v[3][c] + timesMinusI(o1[c]);
+                } else {
+                    acc.v[2][c] = acc.v[2][c] + o0[c];
+                    acc.v[3][c] = acc.v[3][c] + o1[c];
+                }
+            }
+        }
+    }
+
+    if (P.g5d) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            acc.v[2][c] = cneg(acc.v[2][c]);
+            acc.v[3][c] = cneg(acc.v[3][c]);
+        }
+    }
+
+    const A ca = (A)P.a, cc = (A)P.c;
+    const auto *cl = (const typename CP::E *)P.clov;
+    Spin<A> res;
+    if constexpr (MODE == M_PLAIN) {
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) res.v[a][c] = cc * acc.v[a][c];
+        if (P.x) {
+            Spin<A> xv;
+            load_spinor<SP>((const typename SP::E *)P.x, P.x_nrm, Vh, R, i, r, xv);
+#pragma unroll
+            for (int a = 0; a < 4; a++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) res.v[a][c] = res.v[a][c] + ca * xv.v[a][c];
+        }
+    } else if constexpr (MODE == M_INV_AFTER) {
+        Spin<A> m;
+        clover_mul<CP, A>(cl, Vh, i, acc, m);
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) res.v[a][c] = cc * m.v[a][c];
+        if (P.x) {
+            Spin<A> xv;
+            load_spinor<SP>((const typename SP::E *)P.x, P.x_nrm, Vh, R, i, r, xv);
+#pragma unroll
+            for (int a = 0; a < 4; a++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) res.v[a][c] = res.v[a][c] + ca * xv.v[a][c];
+        }
+    } else if constexpr (MODE == M_INV_OF_SUM) {
+        Spin<A> xv, sum;
+        load_spinor<SP>((const typename SP::E *)P.x, P.x_nrm, Vh, R, i, r, xv);
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) sum.v[a][c] = ca * xv.v[a][c] + cc * acc.v[a][c];
+        clover_mul<CP, A>(cl, Vh, i, sum, res);
+    } else {  // M_CLOV_ADD
+        Spin<A> xv, m;
+        load_spinor<SP>((const typename SP::E *)P.x, P.x_nrm, Vh, R, i, r, xv);
+        clover_mul<CP, A>(cl, Vh, i, xv, m);
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) res.v[a][c] = m.v[a][c] + cc * acc.v[a][c];
+    }
+    store_spinor<SP>((typename SP::E *)P.out, P.out_nrm, Vh, R, i, r, res);
+}
+
+template <class SP, class CP>
+__global__ __launch_bounds__(256) void k_clover_apply(const typename CP::E *__restrict__ cl,
+                                                       const typename SP::E *__restrict__ x, const float *x_nrm,
+                                                       typename SP::E *__restrict__ out, float *out_nrm, long Vh,
+                                                       int R, int g5_in)
+{
+    using A = typename SP::A;
+    long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (tid >= Vh * R) return;
+    long i = tid / R;
+    int r = (int)(tid - i * R);
+    Spin<A> v, o;
+    load_spinor<SP>(x, x_nrm, Vh, R, i, r, v);
+    if (g5_in) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            v.v[2][c] = cneg(v.v[2][c]);
+            v.v[3][c] = cneg(v.v[3][c]);
+        }
+    }
+    clover_mul<CP, A>(cl, Vh, i, v, o);
+    store_spinor<SP>(out, out_nrm, Vh, R, i, r, o);
+}
+
+}  // namespace
+
+double dslash_bytes(long Vh, int R, int gbytes, int cbytes, int sbytes, bool has_norm, int mode, bool has_x)
+{
+    // algorithmic bytes: 8 links, the clover block set if used, one input spinor per
+    // site (neighbour re-reads are cache traffic), the output and the epilogue operand
+    double site = 8.0 * 9 * gbytes;
+    if (mode != M_PLAIN) site += 72.0 * cbytes;
+    double per_rhs = 12.0 * sbytes * (2 + (has_x ? 1 : 0)) + (has_norm ? 4.0 * (2 + (has_x ? 1 : 0)) : 0.0);
+    return (double)Vh * (site + R * per_rhs);
+}
+
+template <class SP, class GP, class CP>
+void launch_dslash(laph_ctx *c, int mode, const DslashArgs &a, hipStream_t st)
+{
+    long n = a.Vh * a.R;
+    dim3 grid(nblocks_for(n, 256)), block(256);
+    hipEvent_t e0, e1;
+    timing_begin(c, &e0, &e1);
+    switch (mode) {
+    case M_PLAIN: hipLaunchKernelGGL((k_dslash<SP, GP, CP, M_PLAIN>), grid, block, 0, st, a); break;
+    case M_INV_AFTER: hipLaunchKernelGGL((k_dslash<SP, GP, CP, M_INV_AFTER>), grid, block, 0, st, a); break;
+    case M_INV_OF_SUM: hipLaunchKernelGGL((k_dslash<SP, GP, CP, M_INV_OF_SUM>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_dslash<SP, GP, CP, M_CLOV_ADD>), grid, block, 0, st, a); break;
+    }
+    LAPH_HIP(hipGetLastError());
+    bool has_x = a.x != nullptr && (mode != M_PLAIN || a.x);
+    timing_end(c, e0, e1, dslash_bytes(a.Vh, a.R, GP::bytes, CP::bytes, SP::bytes, SP::kNorm, mode, has_x));
+}
+
+template <class SP, class CP>
+void launch_clover_apply(laph_ctx *c, const void *clov, const void *x, const float *x_nrm, void *out, float *out_nrm,
+                         long Vh, int R, int g5_in, hipStream_t st)
+{
+    long n = Vh * R;
+    hipLaunchKernelGGL((k_clover_apply<SP, CP>), dim3(nblocks_for(n, 256)), dim3(256), 0, st,
+                       (const typename CP::E *)clov, (const typename SP::E *)x, x_nrm, (typename SP::E *)out,
+                       out_nrm, Vh, R, g5_in);
+    LAPH_HIP(hipGetLastError());
+}
+
+template void launch_dslash<S64, G64, C64>(laph_ctx *, int, const DslashArgs &, hipStream_t);
+template void launch_dslash<S32, G32, C32>(laph_ctx *, int, const DslashArgs &, hipStream_t);
+template void launch_dslash<S16, G32, C32>(laph_ctx *, int, const DslashArgs &, hipStream_t);
+template void launch_dslash<SB16, G32, C32>(laph_ctx *, int, const DslashArgs &, hipStream_t);
+template void launch_clover_apply<S64, C64>(laph_ctx *, const void *, const void *, const float *, void *, float *,
+                                            long, int, int, hipStream_t);
+template void launch_clover_apply<S32, C32>(laph_ctx *, const void *, const void *, const float *, void *, float *,
+                                            long, int, int, hipStream_t);
+template void launch_clover_apply<S16, C32>(laph_ctx *, const void *, const void *, const float *, void *, float *,
+                                            long, int, int, hipStream_t);
+template void launch_clover_apply<SB16, C32>(laph_ctx *, const void *, const void *, const float *, void *, float *,
+                                             long, int, int, hipStream_t);

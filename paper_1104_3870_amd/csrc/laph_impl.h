@@ -1,0 +1,213 @@
+// Internal definitions of the MI355X stochastic-LapH library (not part of the ABI).
+//
+// Device layouts (all "SoA over the per-site components", sites of one parity
+// contiguous so that consecutive lanes of a wave touch consecutive addresses):
+//   even-odd links   : T g[((mu*2 + par)*9 + a*3 + b)*Vh + i]          (T = double2/float2)
+//   half spinor (R)  : S s[(k*Vh + i)*R + r],  k = alpha*3 + c          (R right-hand sides)
+//   clover / inverse : double c[(par*72 + blk*36 + e)*Vh + i]  two Hermitian 6x6 chiral
+//                      blocks per site packed as 6 real diagonals then the 15 complex
+//                      entries below the diagonal, row-major.
+//   smeared links    : double2 u[(k*9 + a*3 + b)*V + s]  (full lattice, k = 0,1,2)
+// Checkerboard index of a site is lex/2 with lex = x + Ns(y + Ns(z + Ns t)); parity
+// (x+y+z+t) & 1, even = 0.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/laph.h"
+
+// ---------------------------------------------------------------- error handling
+struct LaphError {
+    int code;
+};
+
+#define LAPH_HIP(call)                                                                       \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            laph_fail(LAPH_EHIP, "%s:%d %s: %s", __FILE__, __LINE__, #call,                   \
+                      hipGetErrorString(e_));                                                \
+        }                                                                                    \
+    } while (0)
+
+#define LAPH_CHECK(cond, code, ...)                                                          \
+    do {                                                                                     \
+        if (!(cond)) laph_fail(code, __VA_ARGS__);                                           \
+    } while (0)
+
+[[noreturn]] void laph_fail(int code, const char *fmt, ...);
+
+// -------------------------------------------------------------- complex helpers
+__host__ __device__ inline double2 cmake(double r, double i) { return make_double2(r, i); }
+__host__ __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline double2 cconjmul(double2 a, double2 b)  // conj(a) * b
+{
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__host__ __device__ inline double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__host__ __device__ inline double2 cdiv(double2 a, double2 b)
+{
+    double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+__host__ __device__ inline double cnorm2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+// Generic complex over a real type (float or double) for templated kernels.
+template <typename R>
+struct Cx {
+    R re, im;
+};
+template <typename R>
+__device__ __forceinline__ Cx<R> operator+(Cx<R> a, Cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> operator-(Cx<R> a, Cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> operator*(Cx<R> a, Cx<R> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R>
+__device__ __forceinline__ Cx<R> operator*(R s, Cx<R> a) { return {s * a.re, s * a.im}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> conjmul(Cx<R> a, Cx<R> b)  // conj(a) * b
+{
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename R>
+__device__ __forceinline__ Cx<R> timesI(Cx<R> a) { return {-a.im, a.re}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> timesMinusI(Cx<R> a) { return {a.im, -a.re}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> cneg(Cx<R> a) { return {-a.re, -a.im}; }
+
+// ---------------------------------------------------------------- geometry
+struct Geom {
+    int ns, nt;
+    long V, Vh, V3;
+};
+
+__device__ __forceinline__ void cb_coords(long i, int par, int ns, int &x, int &y, int &z, int &t)
+{
+    int nsh = ns >> 1;
+    long r = i / nsh;
+    int xh = (int)(i - r * nsh);
+    y = (int)(r % ns);
+    r /= ns;
+    z = (int)(r % ns);
+    t = (int)(r / ns);
+    x = 2 * xh + ((y + z + t + par) & 1);
+}
+
+__device__ __forceinline__ long lex_index(int x, int y, int z, int t, int ns)
+{
+    return x + (long)ns * (y + (long)ns * (z + (long)ns * t));
+}
+
+// XCD-aware block index: the hardware deals consecutive workgroups round-robin over the
+// 8 XCDs; remap so that each XCD works on one contiguous range of the grid and the
+// neighbour re-reads of a stencil stay in that XCD's L2.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nblocks)
+{
+    const unsigned nx = 8;
+    unsigned per = nblocks / nx;
+    if (b >= per * nx) return b;  // ragged tail keeps its index
+    return (b % nx) * per + b / nx;
+}
+
+// ---------------------------------------------------------------- buffers
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+// ---------------------------------------------------------------- gauge caches
+struct DiracCache {
+    const double *U = nullptr;  // caller pointer the cache was built from
+    laph_dirac prm{};
+    bool valid = false;
+    DevBuf g64;     // even-odd links FP64 (double2)
+    DevBuf g32;     // even-odd links FP32 (float2), built on demand
+    DevBuf clov;    // clover FP64 packed
+    DevBuf clinv;   // clover inverse FP64 packed
+    DevBuf clinv32; // clover inverse FP32 packed (mixed precision)
+    bool f32 = false;  // g32 / clinv32 are current
+};
+
+struct laph_ctx {
+    Geom g;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+    DiracCache dc;
+    std::map<std::string, DevBuf> bufs;  // named scratch buffers, grown on demand
+    // timing
+    bool timing = false;
+    double dslash_ms = 0;
+    long dslash_launches = 0;
+    double dslash_bytes = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;  // recorded, not yet read
+    std::vector<double> pending_bytes;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
+};
+
+void *ctx_buf(laph_ctx *c, DevBuf &b, size_t bytes);  // grow-only
+inline void *ctx_named(laph_ctx *c, const std::string &name, size_t bytes) { return ctx_buf(c, c->bufs[name], bytes); }
+void ctx_free(DevBuf &b);
+
+// ---------------------------------------------------------------- internal API
+// layout.hip
+void links_to_eo(laph_ctx *c, const double *U, double2 *g64);
+void eo64_to_eo32(laph_ctx *c, const double2 *g64, float2 *g32, long n);
+// gam: 0 none, 4 multiply by gamma_4, 5 multiply by gamma_5 (applied per site)
+void spinor_to_eo(laph_ctx *c, const double *psi, int nrhs, int gam, double2 *even, double2 *odd);
+void spinor_from_eo(laph_ctx *c, const double2 *even, const double2 *odd, int nrhs, int gam, double *psi);
+void smeared_links_to_soa(laph_ctx *c, const double *U, double2 *us);
+
+// clover.hip
+void clover_build(laph_ctx *c, const double *U, const laph_dirac *d, double *clov, double *clinv);
+void clover_to_f32(laph_ctx *c, const double *cl, float *cl32);
+
+// dirac setup shared by the solver and the apply entry point
+void dirac_prepare(laph_ctx *c, const double *U, const laph_dirac *d, bool need_f32);
+
+// stout.hip
+void stout_smear_device(laph_ctx *c, const double *U, double rho, int nsteps, double *out);
+
+// timing
+void timing_begin(laph_ctx *c, hipEvent_t *a, hipEvent_t *b);
+void timing_end(laph_ctx *c, hipEvent_t a, hipEvent_t b, double bytes);
+void timing_collect(laph_ctx *c);
+
+// launch helper
+inline unsigned nblocks_for(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+#define LAPH_API_BEGIN(ctx)                                                                  \
+    try {                                                                                    \
+        if (!(ctx)) return LAPH_EINVAL;                                                      \
+        LAPH_HIP(hipSetDevice((ctx)->device));
+
+#define LAPH_API_END(ctx)                                                                    \
+    }                                                                                        \
+    catch (const LaphError &e_) {                                                            \
+        return e_.code;                                                                      \
+    }                                                                                        \
+    catch (...) {                                                                            \
+        return LAPH_EHIP;                                                                    \
+    }                                                                                        \
+    return LAPH_OK;
+
+extern thread_local laph_ctx *g_current_ctx;  // context of the running API call (errors)

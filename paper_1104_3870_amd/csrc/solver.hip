@@ -1,0 +1,1119 @@
+// dirac_solve: Omega x = eta through the even-odd Schur system (Sec. IV: BiCGStab with
+// even-odd preconditioning, mixed precision, CG on the normal equations as fallback).
+//
+//   K x = b with b = gamma_4 eta (since Omega = gamma_4 K),
+//   M = 1 - A_oo^-1 D_oe A_ee^-1 D_eo,  bhat = A_oo^-1 (b_o - D_oe A_ee^-1 b_e),
+//   M x_o = bhat,  x_e = A_ee^-1 (b_e - D_eo x_o).
+// R right-hand sides are iterated together with their own BiCGStab scalars; a converged
+// right-hand side is frozen by its mask.  Lower-precision inner iterations keep the
+// solution increment in FP32 and fold it into the FP64 solution at every reliable
+// update, which also replaces the iterated residual by the FP64 true residual of M.
+// Every answer is judged by the FP64 true residual |b - K x| / |b| of the full system.
+#include <algorithm>
+#include <cmath>
+
+#include "dslash.h"
+
+namespace {
+
+constexpr int kBS = 256;
+constexpr int kMaxBlocks = 1024;
+
+struct Scal {
+    double2 rho, alpha, omega, beta;
+    double r2;     // |r|^2 of the iterated residual
+    double r2hi;   // |r|^2 of the last FP64 residual
+    double tol2;   // target |r|^2 of the even-odd system
+    double b2;     // |bhat|^2
+    int active;
+    int iters;
+    int breakdown;
+    int pad;
+};
+
+struct Vec {
+    void *d = nullptr;
+    float *n = nullptr;  // per-site scale (FP16 storage only)
+};
+
+inline unsigned red_blocks(long n) { return (unsigned)std::min<long>(kMaxBlocks, (n + kBS - 1) / kBS); }
+
+// reduce NV doubles per right-hand side over the block; lanes with equal tid % R share r
+template <int NV>
+__device__ __forceinline__ void block_partial(double (&v)[NV], int R, double *partial)
+{
+    for (int off = 32; off >= R; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < NV; k++) v[k] += __shfl_down(v[k], off, 64);
+    __shared__ double lds[kBS / 64][32][NV];
+    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane < R)
+#pragma unroll
+        for (int k = 0; k < NV; k++) lds[wave][lane][k] = v[k];
+    __syncthreads();
+    if ((int)threadIdx.x < R) {
+#pragma unroll
+        for (int k = 0; k < NV; k++) {
+            double s = 0;
+            for (int w = 0; w < kBS / 64; w++) s += lds[w][threadIdx.x][k];
+            partial[((long)blockIdx.x * R + threadIdx.x) * NV + k] = s;
+        }
+    }
+}
+
+// deterministic sum of the partials of right-hand side r (one block per r)
+template <int NV>
+__device__ __forceinline__ void sum_partials(const double *partial, int nblk, int R, int r, double (&out)[NV])
+{
+    __shared__ double lds[kBS][NV];
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; k++) v[k] = 0;
+    for (int b = threadIdx.x; b < nblk; b += kBS)
+#pragma unroll
+        for (int k = 0; k < NV; k++) v[k] += partial[((long)b * R + r) * NV + k];
+#pragma unroll
+    for (int k = 0; k < NV; k++) lds[threadIdx.x][k] = v[k];
+    __syncthreads();
+    for (int s = kBS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+#pragma unroll
+            for (int k = 0; k < NV; k++) lds[threadIdx.x][k] += lds[threadIdx.x + s][k];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < NV; k++) out[k] = lds[0][k];
+}
+
+template <class SP>
+__device__ __forceinline__ Cx<double> ldd(const Vec &v, long Vh, int R, int k, long i, int r)
+{
+    float s = 1.0f;
+    if constexpr (SP::kNorm) s = v.n[i * R + r];
+    auto c = SP::ld((const typename SP::E *)v.d, ((long)k * Vh + i) * R + r, s);
+    return {(double)c.re, (double)c.im};
+}
+
+// load / store a whole site-spinor as doubles (the BLAS arithmetic is FP64)
+template <class SP>
+__device__ __forceinline__ void ld_site(const Vec &v, long Vh, int R, long i, int r, Cx<double> (&o)[12])
+{
+    float s = 1.0f;
+    if constexpr (SP::kNorm) s = v.n[i * R + r];
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        auto c = SP::ld((const typename SP::E *)v.d, ((long)k * Vh + i) * R + r, s);
+        o[k] = {(double)c.re, (double)c.im};
+    }
+}
+template <class SP>
+__device__ __forceinline__ void st_site(Vec &v, long Vh, int R, long i, int r, const Cx<double> (&o)[12])
+{
+    using A = typename SP::A;
+    float inv = 1.0f;
+    if constexpr (SP::kNorm) {
+        double m = 0;
+#pragma unroll
+        for (int k = 0; k < 12; k++) m = fmax(m, fmax(fabs(o[k].re), fabs(o[k].im)));
+        float sc = m > 0 ? (float)m : 1.0f;
+        v.n[i * R + r] = sc;
+        inv = 1.0f / sc;
+    }
+#pragma unroll
+    for (int k = 0; k < 12; k++)
+        SP::st((typename SP::E *)v.d, ((long)k * Vh + i) * R + r, Cx<A>{(A)o[k].re, (A)o[k].im}, inv);
+}
+
+__device__ __forceinline__ double2 c2(Cx<double> a) { return make_double2(a.re, a.im); }
+__device__ __forceinline__ Cx<double> cx(double2 a) { return {a.x, a.y}; }
+
+// ------------------------------------------------------------------ BiCGStab kernels
+// r = r0 = p = convert(rhi); x = 0; partial |r|^2
+template <class SP, class XP>
+__global__ __launch_bounds__(kBS) void k_bicg_init(Vec rhi, Vec r, Vec r0, Vec p, Vec x, long Vh, int R,
+                                                   double *partial, const Scal *sc)
+{
+    double acc[1] = {0};
+    long n = Vh * R, stride = (long)gridDim.x * kBS;
+    int rr = (int)((blockIdx.x * (long)kBS + threadIdx.x) % R);
+    for (long tid = blockIdx.x * (long)kBS + threadIdx.x; tid < n; tid += stride) {
+        long i = tid / R;
+        Cx<double> v[12], z[12];
+        if (!sc[rr].active) {
+            // the increment of a frozen right-hand side is folded at the end: keep it zero
+#pragma unroll
+            for (int k = 0; k < 12; k++) z[k] = {0, 0};
+            st_site<XP>(x, Vh, R, i, rr, z);
+            continue;
+        }
+        ld_site<S64>(rhi, Vh, R, i, rr, v);
+        st_site<SP>(r, Vh, R, i, rr, v);
+        ld_site<SP>(r, Vh, R, i, rr, v);  // the value actually stored
+        st_site<SP>(r0, Vh, R, i, rr, v);
+        st_site<SP>(p, Vh, R, i, rr, v);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            z[k] = {0, 0};
+            acc[0] += v[k].re * v[k].re + v[k].im * v[k].im;
+        }
+        st_site<XP>(x, Vh, R, i, rr, z);
+    }
+    block_partial<1>(acc, R, partial);
+}
+
+__global__ void k_fin_init(const double *partial, int nblk, int R, Scal *sc)
+{
+    int r = blockIdx.x;
+    double s[1];
+    sum_partials<1>(partial, nblk, R, r, s);
+    if (threadIdx.x == 0 && sc[r].active) {
+        sc[r].rho = make_double2(s[0], 0);
+        sc[r].r2 = s[0];
+    }
+}
+
+// partial <a, b> (complex)
+template <class SP>
+__global__ __launch_bounds__(kBS) void k_dot(Vec a, Vec b, long Vh, int R, double *partial)
+{
+    double acc[2] = {0, 0};
+    long n = Vh * R, stride = (long)gridDim.x * kBS;
+    int rr = (int)((blockIdx.x * (long)kBS + threadIdx.x) % R);
+    for (long tid = blockIdx.x * (long)kBS + threadIdx.x; tid < n; tid += stride) {
+        long i = tid / R;
+        for (int k = 0; k < 12; k++) {
+            Cx<double> u = ldd<SP>(a, Vh, R, k, i, rr), w = ldd<SP>(b, Vh, R, k, i, rr);
+            acc[0] += u.re * w.re + u.im * w.im;
+            acc[1] += u.re * w.im - u.im * w.re;
+        }
+    }
+    block_partial<2>(acc, R, partial);
+}
+
+__global__ void k_fin_alpha(const double *partial, int nblk, int R, Scal *sc)
+{
+    int r = blockIdx.x;
+    double s[2];
+    sum_partials<2>(partial, nblk, R, r, s);
+    if (threadIdx.x) return;
+    Scal &q = sc[r];
+    double2 den = make_double2(s[0], s[1]);
+    if (!q.active) {
+        q.alpha = make_double2(0, 0);
+        return;
+    }
+    if (cnorm2(den) == 0.0 || !std::isfinite(den.x) || !std::isfinite(den.y)) {
+        q.alpha = make_double2(0, 0);
+        q.breakdown = 1;
+        q.active = 0;
+        return;
+    }
+    q.alpha = cdiv(q.rho, den);
+}
+
+// s = r - alpha v
+template <class SP>
+__global__ __launch_bounds__(kBS) void k_s_update(Vec r, Vec v, Vec s, long Vh, int R, const Scal *sc)
+{
+    long n = Vh * R;
+    long tid = blockIdx.x * (long)kBS + threadIdx.x;
+    if (tid >= n) return;
+    long i = tid / R;
+    int rr = (int)(tid - i * R);
+    if (!sc[rr].active) return;
+    Cx<double> al = cx(sc[rr].alpha), a[12], b[12];
+    ld_site<SP>(r, Vh, R, i, rr, a);
+    ld_site<SP>(v, Vh, R, i, rr, b);
+#pragma unroll
+    for (int k = 0; k < 12; k++) a[k] = a[k] - al * b[k];
+    st_site<SP>(s, Vh, R, i, rr, a);
+}
+
+// partial <t, s> and |t|^2
+template <class SP>
+__global__ __launch_bounds__(kBS) void k_dot_ts(Vec t, Vec s, long Vh, int R, double *partial)
+{
+    double acc[3] = {0, 0, 0};
+    long n = Vh * R, stride = (long)gridDim.x * kBS;
+    int rr = (int)((blockIdx.x * (long)kBS + threadIdx.x) % R);
+    for (long tid = blockIdx.x * (long)kBS + threadIdx.x; tid < n; tid += stride) {
+        long i = tid / R;
+        for (int k = 0; k < 12; k++) {
+            Cx<double> u = ldd<SP>(t, Vh, R, k, i, rr), w = ldd<SP>(s, Vh, R, k, i, rr);
+            acc[0] += u.re * w.re + u.im * w.im;
+            acc[1] += u.re * w.im - u.im * w.re;
+            acc[2] += u.re * u.re + u.im * u.im;
+        }
+    }
+    block_partial<3>(acc, R, partial);
+}
+
+__global__ void k_fin_omega(const double *partial, int nblk, int R, Scal *sc)
+{
+    int r = blockIdx.x;
+    double s[3];
+    sum_partials<3>(partial, nblk, R, r, s);
+    if (threadIdx.x) return;
+    Scal &q = sc[r];
+    if (!q.active) {
+        q.omega = make_double2(0, 0);
+        return;
+    }
+    if (!(s[2] > 0.0) || !std::isfinite(s[2])) {
+        q.omega = make_double2(0, 0);
+        q.breakdown = 1;
+        q.active = 0;
+        return;
+    }
+    q.omega = make_double2(s[0] / s[2], s[1] / s[2]);
+}
+
+// x += alpha p + omega s;  r = s - omega t;  partial <r0, r>, |r|^2
+template <class SP, class XP>
+__global__ __launch_bounds__(kBS) void k_xr_update(Vec x, Vec p, Vec s, Vec t, Vec r, Vec r0, long Vh, int R,
+                                                   double *partial, const Scal *sc)
+{
+    double acc[3] = {0, 0, 0};
+    long n = Vh * R, stride = (long)gridDim.x * kBS;
+    int rr = (int)((blockIdx.x * (long)kBS + threadIdx.x) % R);
+    bool act = sc[rr].active;
+    Cx<double> al = cx(sc[rr].alpha), om = cx(sc[rr].omega);
+    for (long tid = blockIdx.x * (long)kBS + threadIdx.x; tid < n; tid += stride) {
+        if (!act) break;
+        long i = tid / R;
+        Cx<double> xv[12], pv[12], sv[12], tv[12], z[12];
+        ld_site<XP>(x, Vh, R, i, rr, xv);
+        ld_site<SP>(p, Vh, R, i, rr, pv);
+        ld_site<SP>(s, Vh, R, i, rr, sv);
+#pragma unroll
+        for (int k = 0; k < 12; k++) xv[k] = xv[k] + al * pv[k] + om * sv[k];
+        st_site<XP>(x, Vh, R, i, rr, xv);
+        ld_site<SP>(t, Vh, R, i, rr, tv);
+#pragma unroll
+        for (int k = 0; k < 12; k++) sv[k] = sv[k] - om * tv[k];
+        st_site<SP>(r, Vh, R, i, rr, sv);
+        ld_site<SP>(r, Vh, R, i, rr, sv);  // stored value
+        ld_site<SP>(r0, Vh, R, i, rr, z);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            acc[0] += z[k].re * sv[k].re + z[k].im * sv[k].im;
+            acc[1] += z[k].re * sv[k].im - z[k].im * sv[k].re;
+            acc[2] += sv[k].re * sv[k].re + sv[k].im * sv[k].im;
+        }
+    }
+    block_partial<3>(acc, R, partial);
+}
+
+// rho_new = <r0, r>, beta = (rho_new / rho)(alpha / omega), |r|^2; with hi_conv the
+// iterated residual alone may declare convergence (plain FP64 iteration)
+__global__ void k_fin_beta(const double *partial, int nblk, int R, Scal *sc, int hi_conv)
+{
+    int r = blockIdx.x;
+    double s[3];
+    sum_partials<3>(partial, nblk, R, r, s);
+    if (threadIdx.x) return;
+    Scal &q = sc[r];
+    if (!q.active) {
+        q.beta = make_double2(0, 0);
+        return;
+    }
+    double2 rn = make_double2(s[0], s[1]);
+    q.iters += 1;
+    q.r2 = s[2];
+    if (!std::isfinite(s[2]) || cnorm2(q.rho) == 0.0 || cnorm2(q.omega) == 0.0) {
+        q.breakdown = 1;
+        q.active = 0;
+        q.beta = make_double2(0, 0);
+        return;
+    }
+    q.beta = cmul(cdiv(rn, q.rho), cdiv(q.alpha, q.omega));
+    q.rho = rn;
+    if (hi_conv && s[2] <= q.tol2) q.active = 0;
+}
+
+// p = r + beta (p - omega v)
+template <class SP>
+__global__ __launch_bounds__(kBS) void k_p_update(Vec p, Vec r, Vec v, long Vh, int R, const Scal *sc)
+{
+    long n = Vh * R;
+    long tid = blockIdx.x * (long)kBS + threadIdx.x;
+    if (tid >= n) return;
+    long i = tid / R;
+    int rr = (int)(tid - i * R);
+    if (!sc[rr].active) return;
+    Cx<double> be = cx(sc[rr].beta), om = cx(sc[rr].omega), pv[12], rv[12], vv[12];
+    ld_site<SP>(p, Vh, R, i, rr, pv);
+    ld_site<SP>(r, Vh, R, i, rr, rv);
+    ld_site<SP>(v, Vh, R, i, rr, vv);
+#pragma unroll
+    for (int k = 0; k < 12; k++) pv[k] = rv[k] + be * (pv[k] - om * vv[k]);
+    st_site<SP>(p, Vh, R, i, rr, pv);
+}
+
+// ------------------------------------------------------------ FP64 / reliable updates
+// xhi += xlo; xlo = 0 (right-hand sides with mask set, or all when all_rhs)
+template <class XP>
+__global__ __launch_bounds__(kBS) void k_fold_x(Vec xhi, Vec xlo, long Vh, int R, const Scal *sc, int all_rhs)
+{
+    long n = Vh * R;
+    long tid = blockIdx.x * (long)kBS + threadIdx.x;
+    if (tid >= n) return;
+    long i = tid / R;
+    int rr = (int)(tid - i * R);
+    if (!all_rhs && !sc[rr].active) return;
+    Cx<double> a[12], b[12], z[12];
+    ld_site<S64>(xhi, Vh, R, i, rr, a);
+    ld_site<XP>(xlo, Vh, R, i, rr, b);
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        a[k] = a[k] + b[k];
+        z[k] = {0, 0};
+    }
+    st_site<S64>(xhi, Vh, R, i, rr, a);
+    st_site<XP>(xlo, Vh, R, i, rr, z);
+}
+
+// r = b - m (FP64), partial |r|^2; restricted to masked right-hand sides unless all_rhs
+__global__ __launch_bounds__(kBS) void k_resid64(Vec b, Vec m, Vec r, long Vh, int R, double *partial,
+                                                 const Scal *sc, int all_rhs)
+{
+    double acc[1] = {0};
+    long n = Vh * R, stride = (long)gridDim.x * kBS;
+    int rr = (int)((blockIdx.x * (long)kBS + threadIdx.x) % R);
+    bool act = all_rhs || sc[rr].active;
+    for (long tid = blockIdx.x * (long)kBS + threadIdx.x; tid < n; tid += stride) {
+        if (!act) break;
+        long i = tid / R;
+        Cx<double> a[12], c[12];
+        ld_site<S64>(b, Vh, R, i, rr, a);
+        ld_site<S64>(m, Vh, R, i, rr, c);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            a[k] = a[k] - c[k];
+            acc[0] += a[k].re * a[k].re + a[k].im * a[k].im;
+        }
+        st_site<S64>(r, Vh, R, i, rr, a);
+    }
+    block_partial<1>(acc, R, partial);
+}
+
+// mode 0: r2hi = sum, and mask off converged (r2hi <= tol2); mode 1: b2 = sum
+__global__ void k_fin_r2hi(const double *partial, int nblk, int R, Scal *sc, int mode)
+{
+    int r = blockIdx.x;
+    double s[1];
+    sum_partials<1>(partial, nblk, R, r, s);
+    if (threadIdx.x) return;
+    Scal &q = sc[r];
+    if (mode == 1) {
+        q.b2 = s[0];
+        return;
+    }
+    if (!q.active) return;
+    q.r2hi = s[0];
+    if (s[0] <= q.tol2) q.active = 0;
+}
+
+// r = convert(rhi) for masked right-hand sides; partial <r0, r>, |r|^2
+template <class SP>
+__global__ __launch_bounds__(kBS) void k_replace_r(Vec rhi, Vec r, Vec r0, long Vh, int R, double *partial,
+                                                   const Scal *sc)
+{
+    double acc[3] = {0, 0, 0};
+    long n = Vh * R, stride = (long)gridDim.x * kBS;
+    int rr = (int)((blockIdx.x * (long)kBS + threadIdx.x) % R);
+    bool act = sc[rr].active;
+    for (long tid = blockIdx.x * (long)kBS + threadIdx.x; tid < n; tid += stride) {
+        if (!act) break;
+        long i = tid / R;
+        Cx<double> v[12], z[12];
+        ld_site<S64>(rhi, Vh, R, i, rr, v);
+        st_site<SP>(r, Vh, R, i, rr, v);
+        ld_site<SP>(r, Vh, R, i, rr, v);
+        ld_site<SP>(r0, Vh, R, i, rr, z);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            acc[0] += z[k].re * v[k].re + z[k].im * v[k].im;
+            acc[1] += z[k].re * v[k].im - z[k].im * v[k].re;
+            acc[2] += v[k].re * v[k].re + v[k].im * v[k].im;
+        }
+    }
+    block_partial<3>(acc, R, partial);
+}
+
+__global__ void k_fin_rho(const double *partial, int nblk, int R, Scal *sc)
+{
+    int r = blockIdx.x;
+    double s[3];
+    sum_partials<3>(partial, nblk, R, r, s);
+    if (threadIdx.x) return;
+    Scal &q = sc[r];
+    if (!q.active) return;
+    q.rho = make_double2(s[0], s[1]);
+    q.r2 = s[2];
+}
+
+// ---------------------------------------------------------------- CGNR kernels (FP64)
+// alpha = rr / |q|^2
+__global__ void k_fin_cg_alpha(const double *partial, int nblk, int R, Scal *sc)
+{
+    int r = blockIdx.x;
+    double s[1];
+    sum_partials<1>(partial, nblk, R, r, s);
+    if (threadIdx.x) return;
+    Scal &q = sc[r];
+    if (!q.active || !(s[0] > 0) || !std::isfinite(s[0])) {
+        q.alpha = make_double2(0, 0);
+        if (q.active && !(s[0] > 0)) q.active = 0;
+        return;
+    }
+    q.alpha = make_double2(q.rho.x / s[0], 0);
+}
+
+// partial |a|^2
+__global__ __launch_bounds__(kBS) void k_norm64(Vec a, long Vh, int R, double *partial)
+{
+    double acc[1] = {0};
+    long n = Vh * R, stride = (long)gridDim.x * kBS;
+    int rr = (int)((blockIdx.x * (long)kBS + threadIdx.x) % R);
+    for (long tid = blockIdx.x * (long)kBS + threadIdx.x; tid < n; tid += stride) {
+        long i = tid / R;
+        Cx<double> v[12];
+        ld_site<S64>(a, Vh, R, i, rr, v);
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[0] += v[k].re * v[k].re + v[k].im * v[k].im;
+    }
+    (void)rr;
+    block_partial<1>(acc, R, partial);
+}
+
+// x += alpha p; res -= alpha q; r -= alpha y;  partial |r|^2, |res|^2
+__global__ __launch_bounds__(kBS) void k_cg_update(Vec x, Vec p, Vec res, Vec q, Vec r, Vec y, long Vh, int R,
+                                                   double *partial, const Scal *sc)
+{
+    double acc[2] = {0, 0};
+    long n = Vh * R, stride = (long)gridDim.x * kBS;
+    int rr = (int)((blockIdx.x * (long)kBS + threadIdx.x) % R);
+    bool act = sc[rr].active;
+    double al = sc[rr].alpha.x;
+    for (long tid = blockIdx.x * (long)kBS + threadIdx.x; tid < n; tid += stride) {
+        if (!act) break;
+        long i = tid / R;
+        Cx<double> a[12], b[12];
+        ld_site<S64>(x, Vh, R, i, rr, a);
+        ld_site<S64>(p, Vh, R, i, rr, b);
+#pragma unroll
+        for (int k = 0; k < 12; k++) a[k] = a[k] + al * b[k];
+        st_site<S64>(x, Vh, R, i, rr, a);
+        ld_site<S64>(res, Vh, R, i, rr, a);
+        ld_site<S64>(q, Vh, R, i, rr, b);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            a[k] = a[k] - al * b[k];
+            acc[1] += a[k].re * a[k].re + a[k].im * a[k].im;
+        }
+        st_site<S64>(res, Vh, R, i, rr, a);
+        ld_site<S64>(r, Vh, R, i, rr, a);
+        ld_site<S64>(y, Vh, R, i, rr, b);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            a[k] = a[k] - al * b[k];
+            acc[0] += a[k].re * a[k].re + a[k].im * a[k].im;
+        }
+        st_site<S64>(r, Vh, R, i, rr, a);
+    }
+    block_partial<2>(acc, R, partial);
+}
+
+__global__ void k_fin_cg_beta(const double *partial, int nblk, int R, Scal *sc)
+{
+    int r = blockIdx.x;
+    double s[2];
+    sum_partials<2>(partial, nblk, R, r, s);
+    if (threadIdx.x) return;
+    Scal &q = sc[r];
+    if (!q.active) {
+        q.beta = make_double2(0, 0);
+        return;
+    }
+    q.iters += 1;
+    q.r2 = s[1];
+    q.beta = make_double2(q.rho.x > 0 ? s[0] / q.rho.x : 0.0, 0);
+    q.rho = make_double2(s[0], 0);
+    if (s[1] <= q.tol2 || !(s[0] > 0)) q.active = 0;
+}
+
+// p = r + beta p (real beta)
+__global__ __launch_bounds__(kBS) void k_cg_p(Vec p, Vec r, long Vh, int R, const Scal *sc)
+{
+    long n = Vh * R;
+    long tid = blockIdx.x * (long)kBS + threadIdx.x;
+    if (tid >= n) return;
+    long i = tid / R;
+    int rr = (int)(tid - i * R);
+    if (!sc[rr].active) return;
+    double be = sc[rr].beta.x;
+    Cx<double> a[12], b[12];
+    ld_site<S64>(p, Vh, R, i, rr, a);
+    ld_site<S64>(r, Vh, R, i, rr, b);
+#pragma unroll
+    for (int k = 0; k < 12; k++) a[k] = b[k] + be * a[k];
+    st_site<S64>(p, Vh, R, i, rr, a);
+}
+
+// copy (masked) a -> b, both FP64
+__global__ __launch_bounds__(kBS) void k_copy64(Vec a, Vec b, long Vh, int R, const Scal *sc, int all_rhs)
+{
+    long n = Vh * R;
+    long tid = blockIdx.x * (long)kBS + threadIdx.x;
+    if (tid >= n) return;
+    long i = tid / R;
+    int rr = (int)(tid - i * R);
+    if (!all_rhs && !sc[rr].active) return;
+    for (int k = 0; k < 12; k++) {
+        long idx = ((long)k * Vh + i) * R + rr;
+        ((double2 *)b.d)[idx] = ((const double2 *)a.d)[idx];
+    }
+}
+
+// ---------------------------------------------------------------- operator helper
+template <class SP, class GP, class CP>
+struct Op {
+    laph_ctx *c;
+    hipStream_t st;
+    long Vh;
+    int R;
+    const void *g;
+    const char *clinv;  // packed inverse, parity p at clinv + p * 72 * Vh * sizeof(CP::E)
+    const char *clov;   // packed clover (FP64 operator only)
+    double ws, wt, bct;
+    Vec te;  // even temporary
+
+    DslashArgs base(int par) const
+    {
+        DslashArgs a{};
+        a.gauge = g;
+        a.ns = c->g.ns;
+        a.nt = c->g.nt;
+        a.Vh = Vh;
+        a.R = R;
+        a.par = par;
+        a.wt = wt;
+        a.ws = ws;
+        a.bct = bct;
+        return a;
+    }
+    const void *cinv(int par) const { return clinv + (size_t)par * 72 * Vh * sizeof(typename CP::E); }
+    const void *cl(int par) const { return clov + (size_t)par * 72 * Vh * sizeof(typename CP::E); }
+
+    // out_o = in_o - A_oo^-1 D_oe A_ee^-1 D_eo in_o
+    void mhat(Vec in, Vec out) const
+    {
+        DslashArgs a = base(0);
+        a.in = in.d;
+        a.in_nrm = in.n;
+        a.out = te.d;
+        a.out_nrm = te.n;
+        a.clov = cinv(0);
+        a.a = 0;
+        a.c = 1;
+        launch_dslash<SP, GP, CP>(c, M_INV_AFTER, a, st);
+        DslashArgs b = base(1);
+        b.in = te.d;
+        b.in_nrm = te.n;
+        b.out = out.d;
+        b.out_nrm = out.n;
+        b.x = in.d;
+        b.x_nrm = in.n;
+        b.clov = cinv(1);
+        b.a = 1;
+        b.c = -1;
+        launch_dslash<SP, GP, CP>(c, M_INV_AFTER, b, st);
+    }
+    // out_o = Mhat^dag in_o = in_o - gamma_5 D_oe A_ee^-1 D_eo A_oo^-1 gamma_5 in_o
+    void mhat_dag(Vec in, Vec out, Vec to) const
+    {
+        launch_clover_apply<SP, CP>(c, cinv(1), in.d, in.n, to.d, to.n, Vh, R, 1, st);
+        DslashArgs a = base(0);
+        a.in = to.d;
+        a.in_nrm = to.n;
+        a.out = te.d;
+        a.out_nrm = te.n;
+        a.clov = cinv(0);
+        a.a = 0;
+        a.c = 1;
+        launch_dslash<SP, GP, CP>(c, M_INV_AFTER, a, st);
+        DslashArgs b = base(1);
+        b.in = te.d;
+        b.in_nrm = te.n;
+        b.out = out.d;
+        b.out_nrm = out.n;
+        b.x = in.d;
+        b.x_nrm = in.n;
+        b.a = 1;
+        b.c = -1;
+        b.g5d = 1;
+        launch_dslash<SP, GP, CP>(c, M_PLAIN, b, st);
+    }
+};
+
+using Op64 = Op<S64, G64, C64>;
+
+struct Work {
+    laph_ctx *c;
+    long Vh;
+    int R;
+    Scal *sc;      // device
+    double *part;  // device partials [kMaxBlocks][R][4]
+    Vec make(const char *name, int bytes, bool norm)
+    {
+        Vec v;
+        v.d = ctx_named(c, std::string("slv.") + name, (size_t)12 * Vh * R * bytes);
+        if (norm) v.n = (float *)ctx_named(c, std::string("slv.") + name + ".n", (size_t)Vh * R * 4);
+        return v;
+    }
+};
+
+template <class K, class... Args>
+void launch_red(laph_ctx *c, K kern, long n, Args... args)
+{
+    hipLaunchKernelGGL(kern, dim3(red_blocks(n)), dim3(kBS), 0, c->stream, args...);
+    LAPH_HIP(hipGetLastError());
+}
+template <class K, class... Args>
+void launch_el(laph_ctx *c, K kern, long n, Args... args)
+{
+    hipLaunchKernelGGL(kern, dim3(nblocks_for(n, kBS)), dim3(kBS), 0, c->stream, args...);
+    LAPH_HIP(hipGetLastError());
+}
+template <class K, class... Args>
+void launch_fin(laph_ctx *c, K kern, int R, Args... args)
+{
+    hipLaunchKernelGGL(kern, dim3(R), dim3(kBS), 0, c->stream, args...);
+    LAPH_HIP(hipGetLastError());
+}
+
+void read_scal(laph_ctx *c, const Scal *d, std::vector<Scal> &h)
+{
+    LAPH_HIP(hipMemcpyAsync(h.data(), d, sizeof(Scal) * h.size(), hipMemcpyDeviceToHost, c->stream));
+    LAPH_HIP(hipStreamSynchronize(c->stream));
+}
+void write_scal(laph_ctx *c, Scal *d, const std::vector<Scal> &h)
+{
+    LAPH_HIP(hipMemcpyAsync(d, h.data(), sizeof(Scal) * h.size(), hipMemcpyHostToDevice, c->stream));
+}
+
+// rhi = bhat - Mhat xhi for masked RHS (FP64), then r2hi / masks
+void true_eo_residual(Work &w, const Op64 &hi, Vec bhat, Vec xhi, Vec tmp, Vec rhi, int all_rhs)
+{
+    hi.mhat(xhi, tmp);
+    long n = w.Vh * w.R;
+    launch_red(w.c, k_resid64, n, bhat, tmp, rhi, w.Vh, w.R, w.part, (const Scal *)w.sc, all_rhs);
+    launch_fin(w.c, k_fin_r2hi, w.R, (const double *)w.part, (int)red_blocks(n), w.R, w.sc, 0);
+}
+
+// BiCGStab in storage SP on the even-odd system; x_hi accumulates the FP64 solution.
+// Returns when every RHS is inactive or maxiter is reached.
+template <class SP, class GP, class CP, class XP>
+void bicgstab(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, Vec rhi, Vec tmp64,
+              int maxiter, int reliable_every, int check_every, std::vector<Scal> &hs)
+{
+    const bool plain = std::is_same<SP, S64>::value;
+    const bool nrm = SP::kNorm;
+    Vec r = w.make("r", SP::bytes, nrm), r0 = w.make("r0", SP::bytes, nrm), p = w.make("p", SP::bytes, nrm);
+    Vec v = w.make("v", SP::bytes, nrm), s = w.make("s", SP::bytes, nrm), t = w.make("t", SP::bytes, nrm);
+    Vec xlo = w.make("xlo", XP::bytes, false);
+    long n = w.Vh * w.R;
+    int nblk = (int)red_blocks(n);
+    laph_ctx *c = w.c;
+    // r_hi holds the current FP64 residual of the masked RHS
+    launch_red(c, k_bicg_init<SP, XP>, n, rhi, r, r0, p, xlo, w.Vh, w.R, w.part, (const Scal *)w.sc);
+    launch_fin(c, k_fin_init, w.R, (const double *)w.part, nblk, w.R, w.sc);
+    int since = 0;
+    for (int it = 0; it < maxiter;) {
+        int chunk = std::min(check_every, maxiter - it);
+        for (int k = 0; k < chunk; k++) {
+            lo.mhat(p, v);
+            launch_red(c, k_dot<SP>, n, r0, v, w.Vh, w.R, w.part);
+            launch_fin(c, k_fin_alpha, w.R, (const double *)w.part, nblk, w.R, w.sc);
+            launch_el(c, k_s_update<SP>, n, r, v, s, w.Vh, w.R, (const Scal *)w.sc);
+            lo.mhat(s, t);
+            launch_red(c, k_dot_ts<SP>, n, t, s, w.Vh, w.R, w.part);
+            launch_fin(c, k_fin_omega, w.R, (const double *)w.part, nblk, w.R, w.sc);
+            launch_red(c, k_xr_update<SP, XP>, n, xlo, p, s, t, r, r0, w.Vh, w.R, w.part, (const Scal *)w.sc);
+            launch_fin(c, k_fin_beta, w.R, (const double *)w.part, nblk, w.R, w.sc, plain ? 1 : 0);
+            launch_el(c, k_p_update<SP>, n, p, r, v, w.Vh, w.R, (const Scal *)w.sc);
+        }
+        it += chunk;
+        since += chunk;
+        read_scal(c, w.sc, hs);
+        bool any = false, want_update = false;
+        for (int q = 0; q < w.R; q++) {
+            if (hs[q].active) {
+                any = true;
+                if (hs[q].r2 <= hs[q].tol2) want_update = true;
+            }
+        }
+        if (plain) {
+            if (!any) break;
+            continue;
+        }
+        if (!any) break;
+        if (want_update || since >= reliable_every) {
+            // reliable update: fold the increment, recompute the FP64 residual, replace r
+            launch_el(c, k_fold_x<XP>, n, xhi, xlo, w.Vh, w.R, (const Scal *)w.sc, 0);
+            true_eo_residual(w, hi, bhat, xhi, tmp64, rhi, 0);
+            launch_red(c, k_replace_r<SP>, n, rhi, r, r0, w.Vh, w.R, w.part, (const Scal *)w.sc);
+            launch_fin(c, k_fin_rho, w.R, (const double *)w.part, nblk, w.R, w.sc);
+            since = 0;
+            read_scal(c, w.sc, hs);
+            bool left = false;
+            for (int q = 0; q < w.R; q++) left |= hs[q].active != 0;
+            if (!left) break;
+        }
+    }
+    // fold whatever increment remains (all RHS: inactive ones hold their last increment)
+    launch_el(c, k_fold_x<XP>, n, xhi, xlo, w.Vh, w.R, (const Scal *)w.sc, 1);
+}
+
+// CG on Mhat^dag Mhat x = Mhat^dag bhat, FP64, for the masked RHS, starting from xhi
+void cgnr(Work &w, const Op64 &hi, Vec bhat, Vec xhi, int maxiter, int check_every, std::vector<Scal> &hs)
+{
+    laph_ctx *c = w.c;
+    long n = w.Vh * w.R;
+    int nblk = (int)red_blocks(n);
+    Vec res = w.make("cg.res", 16, false), r = w.make("cg.r", 16, false), p = w.make("cg.p", 16, false);
+    Vec q = w.make("cg.q", 16, false), y = w.make("cg.y", 16, false), to = w.make("cg.to", 16, false);
+    // res = bhat - M x; r = M^dag res; p = r; rho = |r|^2
+    hi.mhat(xhi, q);
+    launch_red(c, k_resid64, n, bhat, q, res, w.Vh, w.R, w.part, (const Scal *)w.sc, 0);
+    hi.mhat_dag(res, r, to);
+    launch_el(c, k_copy64, n, r, p, w.Vh, w.R, (const Scal *)w.sc, 0);
+    launch_red(c, k_norm64, n, r, w.Vh, w.R, w.part);
+    read_scal(c, w.sc, hs);
+    {
+        std::vector<double> part((size_t)nblk * w.R);
+        LAPH_HIP(hipMemcpyAsync(part.data(), w.part, sizeof(double) * part.size(), hipMemcpyDeviceToHost, c->stream));
+        LAPH_HIP(hipStreamSynchronize(c->stream));
+        for (int q2 = 0; q2 < w.R; q2++) {
+            double s = 0;
+            for (int b = 0; b < nblk; b++) s += part[(size_t)b * w.R + q2];
+            hs[q2].rho = make_double2(s, 0);
+        }
+        write_scal(c, w.sc, hs);
+    }
+    for (int it = 0; it < maxiter;) {
+        int chunk = std::min(check_every, maxiter - it);
+        for (int k = 0; k < chunk; k++) {
+            hi.mhat(p, q);
+            launch_red(c, k_norm64, n, q, w.Vh, w.R, w.part);
+            launch_fin(c, k_fin_cg_alpha, w.R, (const double *)w.part, nblk, w.R, w.sc);
+            hi.mhat_dag(q, y, to);
+            launch_red(c, k_cg_update, n, xhi, p, res, q, r, y, w.Vh, w.R, w.part, (const Scal *)w.sc);
+            launch_fin(c, k_fin_cg_beta, w.R, (const double *)w.part, nblk, w.R, w.sc);
+            launch_el(c, k_cg_p, n, p, r, w.Vh, w.R, (const Scal *)w.sc);
+        }
+        it += chunk;
+        read_scal(c, w.sc, hs);
+        bool any = false;
+        for (int q2 = 0; q2 < w.R; q2++) any |= hs[q2].active != 0;
+        if (!any) break;
+    }
+}
+
+// ----------------------------------------------------------- full-system helpers
+// b (canonical) -> b_e, b_o (gamma_4 applied), bhat
+void prepare_rhs(laph_ctx *c, const Op64 &hi, const double *eta, int R, Vec be, Vec bo, Vec bhat, Vec te)
+{
+    spinor_to_eo(c, eta, R, 4, (double2 *)be.d, (double2 *)bo.d);
+    launch_clover_apply<S64, C64>(c, hi.cinv(0), be.d, nullptr, te.d, nullptr, hi.Vh, R, 0, c->stream);
+    DslashArgs a = hi.base(1);
+    a.in = te.d;
+    a.out = bhat.d;
+    a.x = bo.d;
+    a.clov = hi.cinv(1);
+    a.a = 1;
+    a.c = -1;
+    launch_dslash<S64, G64, C64>(c, M_INV_OF_SUM, a, c->stream);
+}
+
+// x_e = A_ee^-1 (b_e - D_eo x_o)
+void reconstruct(laph_ctx *c, const Op64 &hi, Vec be, Vec xo, Vec xe)
+{
+    DslashArgs a = hi.base(0);
+    a.in = xo.d;
+    a.out = xe.d;
+    a.x = be.d;
+    a.clov = hi.cinv(0);
+    a.a = 1;
+    a.c = -1;
+    launch_dslash<S64, G64, C64>(c, M_INV_OF_SUM, a, c->stream);
+}
+
+// K x for EO halves: out_p = A_pp x_p + D x_other
+void apply_K(laph_ctx *c, const Op64 &hi, Vec xe, Vec xo, Vec oe, Vec oo)
+{
+    for (int par = 0; par < 2; par++) {
+        DslashArgs a = hi.base(par);
+        a.in = par ? xe.d : xo.d;
+        a.x = par ? xo.d : xe.d;
+        a.out = par ? oo.d : oe.d;
+        a.clov = hi.cl(par);
+        a.a = 1;
+        a.c = 1;
+        launch_dslash<S64, G64, C64>(c, M_CLOV_ADD, a, c->stream);
+    }
+}
+
+// per-RHS |b - K x|^2 and |b|^2 over both parities (host result)
+void full_residual(Work &w, const Op64 &hi, Vec be, Vec bo, Vec xe, Vec xo, Vec te, Vec to, Vec re,
+                   std::vector<double> &r2, std::vector<double> &b2)
+{
+    laph_ctx *c = w.c;
+    long n = w.Vh * w.R;
+    int nblk = (int)red_blocks(n);
+    apply_K(c, hi, xe, xo, te, to);
+    std::vector<double> part((size_t)nblk * w.R);
+    r2.assign(w.R, 0.0);
+    b2.assign(w.R, 0.0);
+    for (int par = 0; par < 2; par++) {
+        launch_red(c, k_resid64, n, par ? bo : be, par ? to : te, re, w.Vh, w.R, w.part, (const Scal *)w.sc, 1);
+        LAPH_HIP(hipMemcpyAsync(part.data(), w.part, sizeof(double) * part.size(), hipMemcpyDeviceToHost, c->stream));
+        LAPH_HIP(hipStreamSynchronize(c->stream));
+        for (int q = 0; q < w.R; q++)
+            for (int b = 0; b < nblk; b++) r2[q] += part[(size_t)b * w.R + q];
+        launch_red(c, k_norm64, n, par ? bo : be, w.Vh, w.R, w.part);
+        LAPH_HIP(hipMemcpyAsync(part.data(), w.part, sizeof(double) * part.size(), hipMemcpyDeviceToHost, c->stream));
+        LAPH_HIP(hipStreamSynchronize(c->stream));
+        for (int q = 0; q < w.R; q++)
+            for (int b = 0; b < nblk; b++) b2[q] += part[(size_t)b * w.R + q];
+    }
+}
+
+template <class SP, class GP, class CP, class XP>
+void solve_batch(laph_ctx *c, const double *eta, double *x, int R, int nreal, const laph_solver *sv,
+                 laph_solve_stats *stats)
+{
+    long Vh = c->g.Vh;
+    DiracCache &dc = c->dc;
+    Work w{c, Vh, R, nullptr, nullptr};
+    w.sc = (Scal *)ctx_named(c, "slv.scal", sizeof(Scal) * R);
+    w.part = (double *)ctx_named(c, "slv.part", sizeof(double) * kMaxBlocks * R * 4);
+
+    Op64 hi{c, c->stream, Vh, R, dc.g64.p, (const char *)dc.clinv.p, (const char *)dc.clov.p,
+            -0.5 / dc.prm.xi, -0.5, dc.prm.bc_t, w.make("te64", 16, false)};
+    Vec be = w.make("be", 16, false), bo = w.make("bo", 16, false), bhat = w.make("bhat", 16, false);
+    Vec xe = w.make("xe", 16, false), xo = w.make("xo", 16, false), rhi = w.make("rhi", 16, false);
+    Vec tmp = w.make("tmp64", 16, false), tmp2 = w.make("tmp64b", 16, false);
+
+    prepare_rhs(c, hi, eta, R, be, bo, bhat, hi.te);
+
+    std::vector<Scal> hs(R);
+    // |bhat|^2
+    long n = Vh * R;
+    launch_red(c, k_norm64, n, bhat, Vh, R, w.part);
+    launch_fin(c, k_fin_r2hi, R, (const double *)w.part, (int)red_blocks(n), R, w.sc, 1);
+    read_scal(c, w.sc, hs);
+    std::vector<double> eo_tol(R, 0.5 * sv->tol);
+    for (int q = 0; q < R; q++) {
+        double b2 = hs[q].b2;
+        hs[q] = Scal{};
+        hs[q].b2 = b2;
+        hs[q].active = (q < nreal && b2 > 0) ? 1 : 0;
+        hs[q].tol2 = eo_tol[q] * eo_tol[q] * b2;
+    }
+    write_scal(c, w.sc, hs);
+    // x_hi = 0, r_hi = bhat
+    LAPH_HIP(hipMemsetAsync(xo.d, 0, (size_t)12 * Vh * R * 16, c->stream));
+    launch_el(c, k_copy64, n, bhat, rhi, Vh, R, (const Scal *)w.sc, 1);
+
+    std::vector<int> iters(R, 0), fallback(R, 0);
+    std::vector<double> r2, b2;
+    const int check_every = 8;
+    int reliable = sv->reliable_every > 0 ? sv->reliable_every : 50;
+    std::vector<int> done(R, 0);
+    for (int q = 0; q < R; q++) done[q] = !hs[q].active;
+
+    Op<SP, GP, CP> lo{c, c->stream, Vh, R,
+                      std::is_same<GP, G64>::value ? dc.g64.p : dc.g32.p,
+                      std::is_same<CP, C64>::value ? (const char *)dc.clinv.p : (const char *)dc.clinv32.p,
+                      nullptr, -0.5 / dc.prm.xi, -0.5, dc.prm.bc_t,
+                      w.make("te_lo", SP::bytes, SP::kNorm)};
+
+    for (int attempt = 0; attempt < 4; attempt++) {
+        bool use_cg = (sv->solver == LAPH_SOLVER_CGNR) || attempt == 3;
+        if (use_cg) {
+            cgnr(w, hi, bhat, xo, std::max(sv->maxiter, 5000), check_every, hs);
+        } else {
+            bicgstab<SP, GP, CP, XP>(w, lo, hi, bhat, xo, rhi, tmp, sv->maxiter, reliable, check_every, hs);
+        }
+        read_scal(c, w.sc, hs);
+        for (int q = 0; q < R; q++)
+            if (!done[q]) {
+                iters[q] += hs[q].iters;
+                if (use_cg) fallback[q] = 1;
+            }
+        reconstruct(c, hi, be, xo, xe);
+        full_residual(w, hi, be, bo, xe, xo, tmp, tmp2, rhi, r2, b2);
+        bool all = true;
+        for (int q = 0; q < R; q++) {
+            if (done[q]) continue;
+            double rel = b2[q] > 0 ? std::sqrt(r2[q] / b2[q]) : 0.0;
+            if (rel <= sv->tol) {
+                done[q] = 1;
+                hs[q].active = 0;
+            } else {
+                all = false;
+                // tighten the even-odd target by the observed ratio and continue from x
+                double eo_rel = hs[q].b2 > 0 ? std::sqrt(std::max(hs[q].r2hi, hs[q].r2) / hs[q].b2) : 0;
+                double ratio = (eo_rel > 0 && rel > 0) ? eo_rel / rel : 1.0;
+                eo_tol[q] = std::min(eo_tol[q] * 0.5, sv->tol * ratio * 0.5);
+                hs[q].active = 1;
+                hs[q].breakdown = 0;
+                hs[q].iters = 0;
+                hs[q].tol2 = eo_tol[q] * eo_tol[q] * hs[q].b2;
+            }
+        }
+        if (all) break;
+        for (int q = 0; q < R; q++)
+            if (done[q]) hs[q].active = 0;
+        for (int q = 0; q < R; q++) hs[q].iters = 0;
+        write_scal(c, w.sc, hs);
+        // FP64 residual of the EO system for the restart
+        true_eo_residual(w, hi, bhat, xo, tmp, rhi, 0);
+        read_scal(c, w.sc, hs);
+        for (int q = 0; q < R; q++) hs[q].active = !done[q];
+        write_scal(c, w.sc, hs);
+    }
+    spinor_from_eo(c, (const double2 *)xe.d, (const double2 *)xo.d, R, 0, x);
+    for (int q = 0; q < nreal; q++) {
+        if (!stats) break;
+        double rel = b2[q] > 0 ? std::sqrt(r2[q] / b2[q]) : 0.0;
+        stats[q].iters = iters[q];
+        stats[q].fallback_used = fallback[q];
+        stats[q].true_resid = rel;
+        stats[q].status = rel <= sv->tol ? LAPH_OK : LAPH_ENOCONV;
+    }
+    for (int q = 0; q < nreal; q++) {
+        double rel = b2[q] > 0 ? std::sqrt(r2[q] / b2[q]) : 0.0;
+        if (!(rel <= sv->tol)) laph_fail(LAPH_ENOCONV, "rhs %d: true residual %.3e > tol %.3e", q, rel, sv->tol);
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- setup / ABI
+void dirac_prepare(laph_ctx *c, const double *U, const laph_dirac *d, bool need_f32)
+{
+    DiracCache &dc = c->dc;
+    bool same = dc.valid && dc.U == U && dc.prm.m0 == d->m0 && dc.prm.xi == d->xi && dc.prm.c_sw == d->c_sw &&
+                dc.prm.bc_t == d->bc_t;
+    long V = c->g.V, Vh = c->g.Vh;
+    if (!same) {
+        ctx_buf(c, dc.g64, (size_t)72 * Vh * 16);
+        ctx_buf(c, dc.clov, (size_t)144 * Vh * 8);
+        ctx_buf(c, dc.clinv, (size_t)144 * Vh * 8);
+        links_to_eo(c, U, (double2 *)dc.g64.p);
+        clover_build(c, U, d, (double *)dc.clov.p, (double *)dc.clinv.p);
+        dc.valid = true;
+        dc.U = U;
+        dc.prm = *d;
+        dc.f32 = false;
+    }
+    if (need_f32 && !dc.f32) {
+        ctx_buf(c, dc.g32, (size_t)72 * Vh * 8);
+        ctx_buf(c, dc.clinv32, (size_t)144 * Vh * 4);
+        eo64_to_eo32(c, (const double2 *)dc.g64.p, (float2 *)dc.g32.p, 72 * Vh);
+        clover_to_f32(c, (const double *)dc.clinv.p, (float *)dc.clinv32.p);
+        dc.f32 = true;
+    }
+    (void)V;
+}
+
+static void check_dirac(const laph_dirac *d)
+{
+    LAPH_CHECK(d && d->xi > 0 && std::isfinite(d->m0) && std::isfinite(d->c_sw) && std::isfinite(d->bc_t),
+               LAPH_EINVAL, "invalid Dirac parameters");
+}
+
+extern "C" int laph_dirac_apply(laph_ctx_t c, const double *U, const laph_dirac *d, int op, const double *in,
+                                double *out, int n)
+{
+    LAPH_API_BEGIN(c)
+    g_current_ctx = c;
+    LAPH_CHECK(U && in && out && n > 0, LAPH_EINVAL, "null pointer or n <= 0");
+    LAPH_CHECK(op == LAPH_OP_K || op == LAPH_OP_OMEGA || op == LAPH_OP_KDAG, LAPH_EINVAL, "bad op");
+    check_dirac(d);
+    dirac_prepare(c, U, d, false);
+    long Vh = c->g.Vh;
+    DiracCache &dc = c->dc;
+    size_t bytes = (size_t)12 * Vh * n * 16;
+    Vec xe{ctx_named(c, "app.xe", bytes)}, xo{ctx_named(c, "app.xo", bytes)};
+    Vec oe{ctx_named(c, "app.oe", bytes)}, oo{ctx_named(c, "app.oo", bytes)};
+    Op64 hi{c, c->stream, Vh, n, dc.g64.p, (const char *)dc.clinv.p, (const char *)dc.clov.p,
+            -0.5 / dc.prm.xi, -0.5, dc.prm.bc_t, Vec{}};
+    int gin = op == LAPH_OP_KDAG ? 5 : 0;
+    int gout = op == LAPH_OP_KDAG ? 5 : (op == LAPH_OP_OMEGA ? 4 : 0);
+    spinor_to_eo(c, in, n, gin, (double2 *)xe.d, (double2 *)xo.d);
+    apply_K(c, hi, xe, xo, oe, oo);
+    spinor_from_eo(c, (const double2 *)oe.d, (const double2 *)oo.d, n, gout, out);
+    LAPH_HIP(hipStreamSynchronize(c->stream));
+    LAPH_API_END(c)
+}
+
+extern "C" int dirac_solve(laph_ctx_t c, const double *U, const laph_dirac *d, const double *eta, double *x,
+                           int n_rhs, const laph_solver *sv, laph_solve_stats *stats)
+{
+    LAPH_API_BEGIN(c)
+    g_current_ctx = c;
+    LAPH_CHECK(U && eta && x && sv && n_rhs > 0, LAPH_EINVAL, "null pointer or n_rhs <= 0");
+    check_dirac(d);
+    LAPH_CHECK(sv->tol > 0 && sv->maxiter > 0, LAPH_EINVAL, "tol and maxiter must be positive");
+    LAPH_CHECK(sv->precision >= LAPH_PREC_F64 && sv->precision <= LAPH_PREC_BF16, LAPH_EINVAL, "bad precision");
+    LAPH_CHECK(sv->solver == LAPH_SOLVER_BICGSTAB || sv->solver == LAPH_SOLVER_CGNR, LAPH_EINVAL,
+               "solver kind not available in this entry point");
+    int R = sv->block_rhs <= 0 ? 1 : sv->block_rhs;
+    LAPH_CHECK(R <= 32 && (R & (R - 1)) == 0, LAPH_EINVAL, "block_rhs must be a power of two <= 32");
+    bool low = sv->precision != LAPH_PREC_F64;
+    dirac_prepare(c, U, d, low);
+    long V = c->g.V;
+    int first_err = LAPH_OK;
+    for (int base = 0; base < n_rhs; base += R) {
+        int nreal = std::min(R, n_rhs - base);
+        int Rb = R;
+        while (Rb / 2 >= nreal) Rb /= 2;  // smallest power of two holding the tail
+        const double *eb = eta + (size_t)base * V * 24;
+        double *xb = x + (size_t)base * V * 24;
+        const double *src = eb;
+        double *dst = xb;
+        if (nreal < Rb) {
+            // pad the batch with zero sources (inactive from the start)
+            size_t fb = (size_t)V * 24 * sizeof(double);
+            double *pe = (double *)ctx_named(c, "slv.pad_eta", fb * Rb);
+            double *px = (double *)ctx_named(c, "slv.pad_x", fb * Rb);
+            LAPH_HIP(hipMemsetAsync(pe, 0, fb * Rb, c->stream));
+            LAPH_HIP(hipMemcpyAsync(pe, eb, fb * nreal, hipMemcpyDeviceToDevice, c->stream));
+            src = pe;
+            dst = px;
+        }
+        laph_solve_stats *st = stats ? stats + base : nullptr;
+        try {
+            switch (sv->precision) {
+            case LAPH_PREC_F64: solve_batch<S64, G64, C64, S64>(c, src, dst, Rb, nreal, sv, st); break;
+            case LAPH_PREC_F32: solve_batch<S32, G32, C32, S32>(c, src, dst, Rb, nreal, sv, st); break;
+            case LAPH_PREC_F16: solve_batch<S16, G32, C32, S32>(c, src, dst, Rb, nreal, sv, st); break;
+            default: solve_batch<SB16, G32, C32, S32>(c, src, dst, Rb, nreal, sv, st); break;
+            }
+        } catch (const LaphError &e) {
+            if (e.code != LAPH_ENOCONV) throw;
+            if (first_err == LAPH_OK) first_err = e.code;
+        }
+        if (dst != xb) {
+            size_t fb = (size_t)V * 24 * sizeof(double);
+            LAPH_HIP(hipMemcpyAsync(xb, dst, fb * nreal, hipMemcpyDeviceToDevice, c->stream));
+        }
+    }
+    LAPH_HIP(hipStreamSynchronize(c->stream));
+    if (first_err != LAPH_OK) return first_err;
+    LAPH_API_END(c)
+}

@@ -52,7 +52,9 @@ __device__ __forceinline__ void store_spinor(typename SP::E *s, float *nrm, long
         for (int a = 0; a < 4; a++)
 #pragma unroll
             for (int c = 0; c < 3; c++) m = fmaxf(m, fmaxf(fabsf((float)in.v[a][c].re), fabsf((float)in.v[a][c].im)));
-        float sc = m > 0.0f ? m : 1.0f;
+        // sites below 1e-30 (far tails of a source on one time slice) keep scale 1 and
+        // flush to zero in FP16; a denormal scale would make 1/scale infinite
+        float sc = m > 1e-30f ? m : 1.0f;
         nrm[i * R + r] = sc;
         inv = 1.0f / sc;
     }

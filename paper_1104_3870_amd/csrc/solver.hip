@@ -11,16 +11,30 @@
 // Every answer is judged by the FP64 true residual |b - K x| / |b| of the full system.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "dslash.h"
 
 namespace {
+
+int laph_verbose_level()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("LAPH_VERBOSE");
+        v = (e && *e) ? atoi(e) : 0;
+    }
+    return v;
+}
+bool laph_verbose() { return laph_verbose_level() > 0; }
 
 constexpr int kBS = 256;
 constexpr int kMaxBlocks = 1024;
 
 struct Scal {
     double2 rho, alpha, omega, beta;
+    double2 aux;   // <r, p> / |r|^2 after a reliable update (CG)
+    double rho_prev;  // |r|^2 of the previous CG iteration
     double r2;     // |r|^2 of the iterated residual
     double r2hi;   // |r|^2 of the last FP64 residual
     double tol2;   // target |r|^2 of the even-odd system
@@ -115,7 +129,7 @@ __device__ __forceinline__ void st_site(Vec &v, long Vh, int R, long i, int r, c
         double m = 0;
 #pragma unroll
         for (int k = 0; k < 12; k++) m = fmax(m, fmax(fabs(o[k].re), fabs(o[k].im)));
-        float sc = m > 0 ? (float)m : 1.0f;
+        float sc = m > 1e-30 ? (float)m : 1.0f;  // see store_spinor: no denormal scales
         v.n[i * R + r] = sc;
         inv = 1.0f / sc;
     }
@@ -453,25 +467,57 @@ __global__ void k_fin_rho(const double *partial, int nblk, int R, Scal *sc)
     q.r2 = s[2];
 }
 
-// ---------------------------------------------------------------- CGNR kernels (FP64)
-// alpha = rr / |q|^2
-__global__ void k_fin_cg_alpha(const double *partial, int nblk, int R, Scal *sc)
+// ------------------------------------------------------------------- CGNR kernels
+// CG on the normal equations Mhat^dag Mhat x = Mhat^dag bhat (the paper's fallback,
+// Sec. IV).  r is the normal-equation residual, res = bhat - Mhat x the even-odd residual
+// (both by recursion between FP64 reliable updates); rho holds |r|^2.
+
+// r = p = convert(rhi); res = convert(reshi); x = 0; partial |r|^2, |res|^2
+template <class SP, class XP>
+__global__ __launch_bounds__(kBS) void k_cg_init(Vec rhi, Vec reshi, Vec r, Vec p, Vec res, Vec x, long Vh, int R,
+                                                 double *partial, const Scal *sc, int zero_x)
+{
+    double acc[2] = {0, 0};
+    long n = Vh * R, stride = (long)gridDim.x * kBS;
+    int rr = (int)((blockIdx.x * (long)kBS + threadIdx.x) % R);
+    bool act = sc[rr].active;
+    for (long tid = blockIdx.x * (long)kBS + threadIdx.x; tid < n; tid += stride) {
+        long i = tid / R;
+        Cx<double> v[12], z[12];
+        if (zero_x) {
+#pragma unroll
+            for (int k = 0; k < 12; k++) z[k] = {0, 0};
+            st_site<XP>(x, Vh, R, i, rr, z);
+        }
+        if (!act) continue;
+        ld_site<S64>(rhi, Vh, R, i, rr, v);
+        st_site<SP>(r, Vh, R, i, rr, v);
+        ld_site<SP>(r, Vh, R, i, rr, v);
+        st_site<SP>(p, Vh, R, i, rr, v);
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[0] += v[k].re * v[k].re + v[k].im * v[k].im;
+        ld_site<S64>(reshi, Vh, R, i, rr, v);
+        st_site<SP>(res, Vh, R, i, rr, v);
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[1] += v[k].re * v[k].re + v[k].im * v[k].im;
+    }
+    block_partial<2>(acc, R, partial);
+}
+
+// rho = |r|^2, r2 = |res|^2 (masked RHS only)
+__global__ void k_fin_cg_init(const double *partial, int nblk, int R, Scal *sc)
 {
     int r = blockIdx.x;
-    double s[1];
-    sum_partials<1>(partial, nblk, R, r, s);
-    if (threadIdx.x) return;
-    Scal &q = sc[r];
-    if (!q.active || !(s[0] > 0) || !std::isfinite(s[0])) {
-        q.alpha = make_double2(0, 0);
-        if (q.active && !(s[0] > 0)) q.active = 0;
-        return;
-    }
-    q.alpha = make_double2(q.rho.x / s[0], 0);
+    double s[2];
+    sum_partials<2>(partial, nblk, R, r, s);
+    if (threadIdx.x || !sc[r].active) return;
+    sc[r].rho = make_double2(s[0], 0);
+    sc[r].r2 = s[1];
 }
 
 // partial |a|^2
-__global__ __launch_bounds__(kBS) void k_norm64(Vec a, long Vh, int R, double *partial)
+template <class SP>
+__global__ __launch_bounds__(kBS) void k_normsq(Vec a, long Vh, int R, double *partial)
 {
     double acc[1] = {0};
     long n = Vh * R, stride = (long)gridDim.x * kBS;
@@ -479,15 +525,36 @@ __global__ __launch_bounds__(kBS) void k_norm64(Vec a, long Vh, int R, double *p
     for (long tid = blockIdx.x * (long)kBS + threadIdx.x; tid < n; tid += stride) {
         long i = tid / R;
         Cx<double> v[12];
-        ld_site<S64>(a, Vh, R, i, rr, v);
+        ld_site<SP>(a, Vh, R, i, rr, v);
 #pragma unroll
         for (int k = 0; k < 12; k++) acc[0] += v[k].re * v[k].re + v[k].im * v[k].im;
     }
-    (void)rr;
     block_partial<1>(acc, R, partial);
 }
 
+// alpha = rho / |q|^2
+__global__ void k_fin_cg_alpha(const double *partial, int nblk, int R, Scal *sc)
+{
+    int r = blockIdx.x;
+    double s[1];
+    sum_partials<1>(partial, nblk, R, r, s);
+    if (threadIdx.x) return;
+    Scal &q = sc[r];
+    if (!q.active) {
+        q.alpha = make_double2(0, 0);
+        return;
+    }
+    if (!(s[0] > 0) || !std::isfinite(s[0])) {
+        q.alpha = make_double2(0, 0);
+        q.breakdown = 1;
+        q.active = 0;
+        return;
+    }
+    q.alpha = make_double2(q.rho.x / s[0], 0);
+}
+
 // x += alpha p; res -= alpha q; r -= alpha y;  partial |r|^2, |res|^2
+template <class SP, class XP>
 __global__ __launch_bounds__(kBS) void k_cg_update(Vec x, Vec p, Vec res, Vec q, Vec r, Vec y, long Vh, int R,
                                                    double *partial, const Scal *sc)
 {
@@ -500,32 +567,34 @@ __global__ __launch_bounds__(kBS) void k_cg_update(Vec x, Vec p, Vec res, Vec q,
         if (!act) break;
         long i = tid / R;
         Cx<double> a[12], b[12];
-        ld_site<S64>(x, Vh, R, i, rr, a);
-        ld_site<S64>(p, Vh, R, i, rr, b);
+        ld_site<XP>(x, Vh, R, i, rr, a);
+        ld_site<SP>(p, Vh, R, i, rr, b);
 #pragma unroll
         for (int k = 0; k < 12; k++) a[k] = a[k] + al * b[k];
-        st_site<S64>(x, Vh, R, i, rr, a);
-        ld_site<S64>(res, Vh, R, i, rr, a);
-        ld_site<S64>(q, Vh, R, i, rr, b);
+        st_site<XP>(x, Vh, R, i, rr, a);
+        ld_site<SP>(res, Vh, R, i, rr, a);
+        ld_site<SP>(q, Vh, R, i, rr, b);
 #pragma unroll
-        for (int k = 0; k < 12; k++) {
-            a[k] = a[k] - al * b[k];
-            acc[1] += a[k].re * a[k].re + a[k].im * a[k].im;
-        }
-        st_site<S64>(res, Vh, R, i, rr, a);
-        ld_site<S64>(r, Vh, R, i, rr, a);
-        ld_site<S64>(y, Vh, R, i, rr, b);
+        for (int k = 0; k < 12; k++) a[k] = a[k] - al * b[k];
+        st_site<SP>(res, Vh, R, i, rr, a);
+        ld_site<SP>(res, Vh, R, i, rr, a);
 #pragma unroll
-        for (int k = 0; k < 12; k++) {
-            a[k] = a[k] - al * b[k];
-            acc[0] += a[k].re * a[k].re + a[k].im * a[k].im;
-        }
-        st_site<S64>(r, Vh, R, i, rr, a);
+        for (int k = 0; k < 12; k++) acc[1] += a[k].re * a[k].re + a[k].im * a[k].im;
+        ld_site<SP>(r, Vh, R, i, rr, a);
+        ld_site<SP>(y, Vh, R, i, rr, b);
+#pragma unroll
+        for (int k = 0; k < 12; k++) a[k] = a[k] - al * b[k];
+        st_site<SP>(r, Vh, R, i, rr, a);
+        ld_site<SP>(r, Vh, R, i, rr, a);
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[0] += a[k].re * a[k].re + a[k].im * a[k].im;
     }
     block_partial<2>(acc, R, partial);
 }
 
-__global__ void k_fin_cg_beta(const double *partial, int nblk, int R, Scal *sc)
+// beta = |r|^2 / rho; rho = |r|^2; r2 = |res|^2; with hi_conv the recursive even-odd
+// residual alone may declare convergence (plain FP64 iteration)
+__global__ void k_fin_cg_beta(const double *partial, int nblk, int R, Scal *sc, int hi_conv)
 {
     int r = blockIdx.x;
     double s[2];
@@ -538,12 +607,20 @@ __global__ void k_fin_cg_beta(const double *partial, int nblk, int R, Scal *sc)
     }
     q.iters += 1;
     q.r2 = s[1];
-    q.beta = make_double2(q.rho.x > 0 ? s[0] / q.rho.x : 0.0, 0);
+    if (!std::isfinite(s[0]) || !std::isfinite(s[1]) || !(q.rho.x > 0)) {
+        q.breakdown = 1;
+        q.active = 0;
+        q.beta = make_double2(0, 0);
+        return;
+    }
+    q.beta = make_double2(s[0] / q.rho.x, 0);
+    q.rho_prev = q.rho.x;
     q.rho = make_double2(s[0], 0);
-    if (s[1] <= q.tol2 || !(s[0] > 0)) q.active = 0;
+    if (hi_conv && (s[1] <= q.tol2 || !(s[0] > 0))) q.active = 0;
 }
 
 // p = r + beta p (real beta)
+template <class SP>
 __global__ __launch_bounds__(kBS) void k_cg_p(Vec p, Vec r, long Vh, int R, const Scal *sc)
 {
     long n = Vh * R;
@@ -554,11 +631,80 @@ __global__ __launch_bounds__(kBS) void k_cg_p(Vec p, Vec r, long Vh, int R, cons
     if (!sc[rr].active) return;
     double be = sc[rr].beta.x;
     Cx<double> a[12], b[12];
-    ld_site<S64>(p, Vh, R, i, rr, a);
-    ld_site<S64>(r, Vh, R, i, rr, b);
+    ld_site<SP>(p, Vh, R, i, rr, a);
+    ld_site<SP>(r, Vh, R, i, rr, b);
 #pragma unroll
     for (int k = 0; k < 12; k++) a[k] = b[k] + be * a[k];
-    st_site<S64>(p, Vh, R, i, rr, a);
+    st_site<SP>(p, Vh, R, i, rr, a);
+}
+
+// after the residual was replaced: rho = |r|^2, r2 = |res|^2, beta = |r|^2 / rho_prev
+__global__ void k_fin_cg_reset(const double *partial, int nblk, int R, Scal *sc)
+{
+    int r = blockIdx.x;
+    double s[2];
+    sum_partials<2>(partial, nblk, R, r, s);
+    if (threadIdx.x || !sc[r].active) return;
+    Scal &q = sc[r];
+    q.rho = make_double2(s[0], 0);
+    q.r2 = s[1];
+    q.beta = make_double2(q.rho_prev > 0 ? s[0] / q.rho_prev : 0.0, 0);
+}
+
+// aux = <r, p> / |r|^2 (rho holds |r|^2)
+__global__ void k_fin_orth(const double *partial, int nblk, int R, Scal *sc)
+{
+    int r = blockIdx.x;
+    double s[2];
+    sum_partials<2>(partial, nblk, R, r, s);
+    if (threadIdx.x) return;
+    Scal &q = sc[r];
+    q.aux = (q.active && q.rho.x > 0) ? make_double2(s[0] / q.rho.x, s[1] / q.rho.x) : make_double2(0, 0);
+}
+
+// p -= aux r  (restores <r, p> = 0 after the residual was replaced)
+template <class SP>
+__global__ __launch_bounds__(kBS) void k_orth_p(Vec p, Vec r, long Vh, int R, const Scal *sc)
+{
+    long n = Vh * R;
+    long tid = blockIdx.x * (long)kBS + threadIdx.x;
+    if (tid >= n) return;
+    long i = tid / R;
+    int rr = (int)(tid - i * R);
+    if (!sc[rr].active) return;
+    Cx<double> a = cx(sc[rr].aux), pv[12], rv[12];
+    ld_site<SP>(p, Vh, R, i, rr, pv);
+    ld_site<SP>(r, Vh, R, i, rr, rv);
+#pragma unroll
+    for (int k = 0; k < 12; k++) pv[k] = pv[k] - a * rv[k];
+    st_site<SP>(p, Vh, R, i, rr, pv);
+}
+
+// r = convert(rhi), res = convert(reshi) for masked RHS; partial |r|^2, |res|^2
+template <class SP>
+__global__ __launch_bounds__(kBS) void k_cg_replace(Vec rhi, Vec reshi, Vec r, Vec res, long Vh, int R,
+                                                    double *partial, const Scal *sc)
+{
+    double acc[2] = {0, 0};
+    long n = Vh * R, stride = (long)gridDim.x * kBS;
+    int rr = (int)((blockIdx.x * (long)kBS + threadIdx.x) % R);
+    bool act = sc[rr].active;
+    for (long tid = blockIdx.x * (long)kBS + threadIdx.x; tid < n; tid += stride) {
+        if (!act) break;
+        long i = tid / R;
+        Cx<double> v[12];
+        ld_site<S64>(rhi, Vh, R, i, rr, v);
+        st_site<SP>(r, Vh, R, i, rr, v);
+        ld_site<SP>(r, Vh, R, i, rr, v);
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[0] += v[k].re * v[k].re + v[k].im * v[k].im;
+        ld_site<S64>(reshi, Vh, R, i, rr, v);
+        st_site<SP>(res, Vh, R, i, rr, v);
+        ld_site<SP>(res, Vh, R, i, rr, v);
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[1] += v[k].re * v[k].re + v[k].im * v[k].im;
+    }
+    block_partial<2>(acc, R, partial);
 }
 
 // copy (masked) a -> b, both FP64
@@ -730,6 +876,13 @@ void bicgstab(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec x
     launch_red(c, k_bicg_init<SP, XP>, n, rhi, r, r0, p, xlo, w.Vh, w.R, w.part, (const Scal *)w.sc);
     launch_fin(c, k_fin_init, w.R, (const double *)w.part, nblk, w.R, w.sc);
     int since = 0;
+    // a reliable update also follows every drop of the iterated residual by kDelta since
+    // the last one, which bounds the error the low-precision recursion can accumulate
+    const double kDelta2 = 0.1 * 0.1;
+    read_scal(c, w.sc, hs);
+    std::vector<double> r2_last(w.R), r2_min(w.R);
+    for (int q = 0; q < w.R; q++) r2_last[q] = r2_min[q] = hs[q].r2;
+    if (!plain) check_every = 1;  // see cgnr: the update rule is tested every iteration
     for (int it = 0; it < maxiter;) {
         int chunk = std::min(check_every, maxiter - it);
         for (int k = 0; k < chunk; k++) {
@@ -747,13 +900,32 @@ void bicgstab(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec x
         it += chunk;
         since += chunk;
         read_scal(c, w.sc, hs);
+        // divergence: the iterated residual grew 1e4-fold above its minimum; the RHS is
+        // handed to the fallback
+        bool diverged = false;
+        for (int q = 0; q < w.R; q++) {
+            if (!hs[q].active) continue;
+            r2_min[q] = std::min(r2_min[q], hs[q].r2);
+            if (!(hs[q].r2 <= 1e8 * r2_min[q])) {
+                hs[q].active = 0;
+                hs[q].breakdown = 1;
+                diverged = true;
+            }
+        }
+        if (diverged) write_scal(c, w.sc, hs);
         bool any = false, want_update = false;
+        int nact = 0;
+        double worst = 0;
         for (int q = 0; q < w.R; q++) {
             if (hs[q].active) {
                 any = true;
-                if (hs[q].r2 <= hs[q].tol2) want_update = true;
+                nact++;
+                worst = std::max(worst, hs[q].tol2 > 0 ? std::sqrt(hs[q].r2 / hs[q].tol2) : 0.0);
+                if (hs[q].r2 <= hs[q].tol2 || hs[q].r2 < kDelta2 * r2_last[q]) want_update = true;
             }
         }
+        if (laph_verbose() && (it % 256 < check_every || !any))
+            fprintf(stderr, "[laph] bicgstab it=%d active=%d/%d max |r|/target=%.3g\n", it, nact, w.R, worst);
         if (plain) {
             if (!any) break;
             continue;
@@ -768,7 +940,11 @@ void bicgstab(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec x
             since = 0;
             read_scal(c, w.sc, hs);
             bool left = false;
-            for (int q = 0; q < w.R; q++) left |= hs[q].active != 0;
+            for (int q = 0; q < w.R; q++) {
+                left |= hs[q].active != 0;
+                r2_last[q] = hs[q].r2;
+                r2_min[q] = std::min(r2_min[q], hs[q].r2);
+            }
             if (!left) break;
         }
     }
@@ -776,49 +952,95 @@ void bicgstab(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec x
     launch_el(c, k_fold_x<XP>, n, xhi, xlo, w.Vh, w.R, (const Scal *)w.sc, 1);
 }
 
-// CG on Mhat^dag Mhat x = Mhat^dag bhat, FP64, for the masked RHS, starting from xhi
-void cgnr(Work &w, const Op64 &hi, Vec bhat, Vec xhi, int maxiter, int check_every, std::vector<Scal> &hs)
+// CG on Mhat^dag Mhat x = Mhat^dag bhat in storage SP for the masked RHS, starting from
+// xhi (FP64).  Lower precisions fold their FP32 increment into xhi at FP64 reliable
+// updates (every reliable_every iterations, after a drop of the recursive residual by
+// kDelta, or when it reaches the target); the FP64 even-odd residual decides.
+template <class SP, class GP, class CP, class XP>
+void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, Vec reshi, Vec rhi, Vec tmp64,
+          int maxiter, int reliable_every, int check_every, std::vector<Scal> &hs)
 {
+    const bool plain = std::is_same<SP, S64>::value;
+    const bool nrm = SP::kNorm;
     laph_ctx *c = w.c;
     long n = w.Vh * w.R;
     int nblk = (int)red_blocks(n);
-    Vec res = w.make("cg.res", 16, false), r = w.make("cg.r", 16, false), p = w.make("cg.p", 16, false);
-    Vec q = w.make("cg.q", 16, false), y = w.make("cg.y", 16, false), to = w.make("cg.to", 16, false);
-    // res = bhat - M x; r = M^dag res; p = r; rho = |r|^2
-    hi.mhat(xhi, q);
-    launch_red(c, k_resid64, n, bhat, q, res, w.Vh, w.R, w.part, (const Scal *)w.sc, 0);
-    hi.mhat_dag(res, r, to);
-    launch_el(c, k_copy64, n, r, p, w.Vh, w.R, (const Scal *)w.sc, 0);
-    launch_red(c, k_norm64, n, r, w.Vh, w.R, w.part);
+    Vec r = w.make("cg.r", SP::bytes, nrm), p = w.make("cg.p", SP::bytes, nrm), res = w.make("cg.res", SP::bytes, nrm);
+    Vec q = w.make("cg.q", SP::bytes, nrm), y = w.make("cg.y", SP::bytes, nrm), to = w.make("cg.to", SP::bytes, nrm);
+    Vec xlo = w.make("cg.xlo", XP::bytes, false);
+    Vec to64 = w.make("cg.to64", 16, false);
+    // FP64 residuals of the masked RHS: reshi = bhat - M xhi, rhi = M^dag reshi
+    auto refresh = [&]() {
+        true_eo_residual(w, hi, bhat, xhi, tmp64, reshi, 0);
+        hi.mhat_dag(reshi, rhi, to64);
+    };
+    refresh();
+    launch_red(c, k_cg_init<SP, XP>, n, rhi, reshi, r, p, res, xlo, w.Vh, w.R, w.part, (const Scal *)w.sc, 1);
+    launch_fin(c, k_fin_cg_init, w.R, (const double *)w.part, nblk, w.R, w.sc);
+    const double kDelta2 = 0.1 * 0.1;
     read_scal(c, w.sc, hs);
-    {
-        std::vector<double> part((size_t)nblk * w.R);
-        LAPH_HIP(hipMemcpyAsync(part.data(), w.part, sizeof(double) * part.size(), hipMemcpyDeviceToHost, c->stream));
-        LAPH_HIP(hipStreamSynchronize(c->stream));
-        for (int q2 = 0; q2 < w.R; q2++) {
-            double s = 0;
-            for (int b = 0; b < nblk; b++) s += part[(size_t)b * w.R + q2];
-            hs[q2].rho = make_double2(s, 0);
-        }
-        write_scal(c, w.sc, hs);
-    }
+    if (laph_verbose())
+        fprintf(stderr, "[laph] cgnr init rhs0: active=%d r2hi=%.3e rho=%.3e r2=%.3e b2=%.3e tol2=%.3e\n", hs[0].active,
+                hs[0].r2hi, hs[0].rho.x, hs[0].r2, hs[0].b2, hs[0].tol2);
+    std::vector<double> r2_last(w.R);
+    for (int k = 0; k < w.R; k++) r2_last[k] = hs[k].r2;
+    int since = 0;
+    // lower precisions test the update rule after every iteration: between two tests the
+    // recursive residual must not fall far below what the storage precision can follow
+    if (!plain) check_every = 1;
     for (int it = 0; it < maxiter;) {
         int chunk = std::min(check_every, maxiter - it);
         for (int k = 0; k < chunk; k++) {
-            hi.mhat(p, q);
-            launch_red(c, k_norm64, n, q, w.Vh, w.R, w.part);
+            lo.mhat(p, q);
+            launch_red(c, k_normsq<SP>, n, q, w.Vh, w.R, w.part);
             launch_fin(c, k_fin_cg_alpha, w.R, (const double *)w.part, nblk, w.R, w.sc);
-            hi.mhat_dag(q, y, to);
-            launch_red(c, k_cg_update, n, xhi, p, res, q, r, y, w.Vh, w.R, w.part, (const Scal *)w.sc);
-            launch_fin(c, k_fin_cg_beta, w.R, (const double *)w.part, nblk, w.R, w.sc);
-            launch_el(c, k_cg_p, n, p, r, w.Vh, w.R, (const Scal *)w.sc);
+            lo.mhat_dag(q, y, to);
+            launch_red(c, k_cg_update<SP, XP>, n, xlo, p, res, q, r, y, w.Vh, w.R, w.part, (const Scal *)w.sc);
+            launch_fin(c, k_fin_cg_beta, w.R, (const double *)w.part, nblk, w.R, w.sc, plain ? 1 : 0);
+            if (plain) launch_el(c, k_cg_p<SP>, n, p, r, w.Vh, w.R, (const Scal *)w.sc);
         }
         it += chunk;
+        since += chunk;
         read_scal(c, w.sc, hs);
-        bool any = false;
-        for (int q2 = 0; q2 < w.R; q2++) any |= hs[q2].active != 0;
+        bool any = false, want_update = false;
+        int nact = 0;
+        double worst = 0;
+        for (int k = 0; k < w.R; k++) {
+            if (!hs[k].active) continue;
+            any = true;
+            nact++;
+            worst = std::max(worst, hs[k].tol2 > 0 ? std::sqrt(hs[k].r2 / hs[k].tol2) : 0.0);
+            if (hs[k].r2 <= hs[k].tol2 || hs[k].r2 < kDelta2 * r2_last[k]) want_update = true;
+        }
+        if (laph_verbose() && (it % 256 < check_every || !any || laph_verbose_level() > 1))
+            fprintf(stderr, "[laph] cgnr it=%d active=%d/%d max |res|/target=%.3g rhs0: rho=%.3e alpha=%.3e r2=%.3e "
+                    "aux=%.3e upd=%d\n", it, nact, w.R, worst, hs[0].rho.x, hs[0].alpha.x, hs[0].r2, hs[0].aux.x,
+                    (int)want_update);
         if (!any) break;
+        if (plain) continue;
+        if (want_update || since >= reliable_every) {
+            // reliable update between the residual and the direction update: fold the
+            // increment, replace r and res by FP64 residuals, take beta from the new |r|^2
+            // and keep the old direction orthogonal to the new residual
+            launch_el(c, k_fold_x<XP>, n, xhi, xlo, w.Vh, w.R, (const Scal *)w.sc, 0);
+            refresh();
+            launch_red(c, k_cg_replace<SP>, n, rhi, reshi, r, res, w.Vh, w.R, w.part, (const Scal *)w.sc);
+            launch_fin(c, k_fin_cg_reset, w.R, (const double *)w.part, nblk, w.R, w.sc);
+            launch_red(c, k_dot<SP>, n, r, p, w.Vh, w.R, w.part);
+            launch_fin(c, k_fin_orth, w.R, (const double *)w.part, nblk, w.R, w.sc);
+            launch_el(c, k_orth_p<SP>, n, p, r, w.Vh, w.R, (const Scal *)w.sc);
+            since = 0;
+            read_scal(c, w.sc, hs);
+            bool left = false;
+            for (int k = 0; k < w.R; k++) {
+                left |= hs[k].active != 0;
+                r2_last[k] = hs[k].r2;
+            }
+            if (!left) break;
+        }
+        launch_el(c, k_cg_p<SP>, n, p, r, w.Vh, w.R, (const Scal *)w.sc);
     }
+    launch_el(c, k_fold_x<XP>, n, xhi, xlo, w.Vh, w.R, (const Scal *)w.sc, 1);
 }
 
 // ----------------------------------------------------------- full-system helpers
@@ -882,7 +1104,7 @@ void full_residual(Work &w, const Op64 &hi, Vec be, Vec bo, Vec xe, Vec xo, Vec 
         LAPH_HIP(hipStreamSynchronize(c->stream));
         for (int q = 0; q < w.R; q++)
             for (int b = 0; b < nblk; b++) r2[q] += part[(size_t)b * w.R + q];
-        launch_red(c, k_norm64, n, par ? bo : be, w.Vh, w.R, w.part);
+        launch_red(c, k_normsq<S64>, n, par ? bo : be, w.Vh, w.R, w.part);
         LAPH_HIP(hipMemcpyAsync(part.data(), w.part, sizeof(double) * part.size(), hipMemcpyDeviceToHost, c->stream));
         LAPH_HIP(hipStreamSynchronize(c->stream));
         for (int q = 0; q < w.R; q++)
@@ -911,7 +1133,7 @@ void solve_batch(laph_ctx *c, const double *eta, double *x, int R, int nreal, co
     std::vector<Scal> hs(R);
     // |bhat|^2
     long n = Vh * R;
-    launch_red(c, k_norm64, n, bhat, Vh, R, w.part);
+    launch_red(c, k_normsq<S64>, n, bhat, Vh, R, w.part);
     launch_fin(c, k_fin_r2hi, R, (const double *)w.part, (int)red_blocks(n), R, w.sc, 1);
     read_scal(c, w.sc, hs);
     std::vector<double> eo_tol(R, 0.5 * sv->tol);
@@ -940,50 +1162,84 @@ void solve_batch(laph_ctx *c, const double *eta, double *x, int R, int nreal, co
                       nullptr, -0.5 / dc.prm.xi, -0.5, dc.prm.bc_t,
                       w.make("te_lo", SP::bytes, SP::kNorm)};
 
-    for (int attempt = 0; attempt < 4; attempt++) {
-        bool use_cg = (sv->solver == LAPH_SOLVER_CGNR) || attempt == 3;
-        if (use_cg) {
-            cgnr(w, hi, bhat, xo, std::max(sv->maxiter, 5000), check_every, hs);
-        } else {
-            bicgstab<SP, GP, CP, XP>(w, lo, hi, bhat, xo, rhi, tmp, sv->maxiter, reliable, check_every, hs);
+    // Attempts: BiCGStab (Sec. IV) for every RHS that has not failed it, then CG on the
+    // normal equations (the paper's fallback) in the same precision for the RHS whose
+    // BiCGStab broke down or diverged; the last attempt is plain FP64 CGNR.  After each
+    // attempt the FP64 true residual of the full system decides, and an RHS that misses
+    // the bar continues from its current x with a tighter even-odd target.
+    std::vector<int> bicg_failed(R, 0);
+    Vec reshi = w.make("reshi", 16, false);
+    auto set_active = [&](auto pred) {
+        int na = 0;
+        for (int q = 0; q < R; q++) {
+            hs[q].active = (!done[q] && pred(q)) ? 1 : 0;
+            hs[q].iters = 0;
+            hs[q].breakdown = 0;
+            na += hs[q].active;
         }
-        read_scal(c, w.sc, hs);
-        for (int q = 0; q < R; q++)
-            if (!done[q]) {
-                iters[q] += hs[q].iters;
-                if (use_cg) fallback[q] = 1;
-            }
+        write_scal(c, w.sc, hs);
+        return na;
+    };
+    for (int attempt = 0; attempt < 4; attempt++) {
+        const bool last = attempt == 3;
+        const char *what = "";
+        if (sv->solver == LAPH_SOLVER_BICGSTAB && !last &&
+            set_active([&](int q) { return !bicg_failed[q]; }) > 0) {
+            true_eo_residual(w, hi, bhat, xo, tmp, rhi, 0);
+            read_scal(c, w.sc, hs);
+            bicgstab<SP, GP, CP, XP>(w, lo, hi, bhat, xo, rhi, tmp, sv->maxiter, reliable, check_every, hs);
+            read_scal(c, w.sc, hs);
+            for (int q = 0; q < R; q++)
+                if (!done[q] && !bicg_failed[q]) {
+                    iters[q] += hs[q].iters;
+                    if (hs[q].breakdown) bicg_failed[q] = 1;
+                }
+            what = "bicgstab";
+        }
+        bool cg_all = sv->solver == LAPH_SOLVER_CGNR || last;
+        if (set_active([&](int q) { return cg_all || bicg_failed[q]; }) > 0) {
+            if (last)
+                cgnr<S64, G64, C64, S64>(w, hi, hi, bhat, xo, reshi, rhi, tmp, std::max(sv->maxiter, 5000), 0,
+                                         check_every, hs);
+            else
+                cgnr<SP, GP, CP, XP>(w, lo, hi, bhat, xo, reshi, rhi, tmp, std::max(sv->maxiter, 5000), reliable,
+                                     check_every, hs);
+            read_scal(c, w.sc, hs);
+            for (int q = 0; q < R; q++)
+                if (!done[q] && (cg_all || bicg_failed[q])) {
+                    iters[q] += hs[q].iters;
+                    if (sv->solver == LAPH_SOLVER_BICGSTAB || last) fallback[q] = 1;
+                }
+            what = last ? "cgnr-fp64" : "cgnr";
+        }
         reconstruct(c, hi, be, xo, xe);
         full_residual(w, hi, be, bo, xe, xo, tmp, tmp2, rhi, r2, b2);
+        if (laph_verbose()) {
+            double mx = 0;
+            int mi = 0;
+            for (int q = 0; q < R; q++) {
+                double rel = b2[q] > 0 ? std::sqrt(r2[q] / b2[q]) : 0.0;
+                if (rel > mx) mx = rel;
+                mi = std::max(mi, iters[q]);
+            }
+            fprintf(stderr, "[laph] attempt %d (%s): max true residual %.3e, max iters %d\n", attempt, what, mx, mi);
+        }
         bool all = true;
         for (int q = 0; q < R; q++) {
             if (done[q]) continue;
             double rel = b2[q] > 0 ? std::sqrt(r2[q] / b2[q]) : 0.0;
             if (rel <= sv->tol) {
                 done[q] = 1;
-                hs[q].active = 0;
             } else {
                 all = false;
                 // tighten the even-odd target by the observed ratio and continue from x
                 double eo_rel = hs[q].b2 > 0 ? std::sqrt(std::max(hs[q].r2hi, hs[q].r2) / hs[q].b2) : 0;
-                double ratio = (eo_rel > 0 && rel > 0) ? eo_rel / rel : 1.0;
+                double ratio = (eo_rel > 0 && rel > 0 && std::isfinite(eo_rel)) ? eo_rel / rel : 1.0;
                 eo_tol[q] = std::min(eo_tol[q] * 0.5, sv->tol * ratio * 0.5);
-                hs[q].active = 1;
-                hs[q].breakdown = 0;
-                hs[q].iters = 0;
                 hs[q].tol2 = eo_tol[q] * eo_tol[q] * hs[q].b2;
             }
         }
         if (all) break;
-        for (int q = 0; q < R; q++)
-            if (done[q]) hs[q].active = 0;
-        for (int q = 0; q < R; q++) hs[q].iters = 0;
-        write_scal(c, w.sc, hs);
-        // FP64 residual of the EO system for the restart
-        true_eo_residual(w, hi, bhat, xo, tmp, rhi, 0);
-        read_scal(c, w.sc, hs);
-        for (int q = 0; q < R; q++) hs[q].active = !done[q];
-        write_scal(c, w.sc, hs);
     }
     spinor_from_eo(c, (const double2 *)xe.d, (const double2 *)xo.d, R, 0, x);
     for (int q = 0; q < nreal; q++) {

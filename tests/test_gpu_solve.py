@@ -57,6 +57,17 @@ def test_single_rhs(P, setup, prec):
         assert rel_err(x[r], xs[r]) <= 1e-8
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16", "bf16"])
+def test_cgnr_mixed_multi_rhs(P, setup, prec):
+    """Mixed-precision CG on the normal equations with FP64 reliable updates, 5 RHS in a
+    padded block of 8."""
+    cfg, U, D, etas, xs = setup
+    x, st = _solve(P, cfg, U, etas, precision=prec, block_rhs=8, solver=P.LAPH_SOLVER_CGNR)
+    for r in range(5):
+        assert D.true_residual(etas[r], x[r]) <= 1e-10
+        assert rel_err(x[r], xs[r]) <= 1e-8
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
 def test_multi_rhs_masked(P, setup, prec):
     """5 right-hand sides in blocks of 8 (padded, uneven convergence): each equals the
@@ -73,7 +84,7 @@ def test_multi_rhs_masked(P, setup, prec):
 def test_cgnr(P, setup):
     cfg, U, D, etas, xs = setup
     x, st = _solve(P, cfg, U, etas[:1], solver=P.LAPH_SOLVER_CGNR)
-    assert st[0].fallback_used == 1
+    assert st[0].fallback_used == 0
     assert D.true_residual(etas[0], x[0]) <= 1e-10
     assert rel_err(x[0], xs[0]) <= 1e-8
 
@@ -94,3 +105,30 @@ def test_zero_source(P, setup):
     x, st = _solve(P, cfg, U, z, block_rhs=2)
     assert np.abs(x[0]).max() == 0
     assert D.true_residual(etas[1], x[1]) <= 1e-10
+
+
+@pytest.mark.parametrize("prec,solver", [("f16", "cgnr"), ("f16", "bicgstab"), ("bf16", "cgnr"),
+                                         ("bf16", "bicgstab"), ("f32", "cgnr")])
+def test_tiny_tails_low_precision(P, prec, solver):
+    """Regression: a source on one time slice of a long lattice at a heavy mass has a
+    solution that falls below the FP32 normal range far from the source; the FP16 site
+    scales must stay finite there (they once became denormal and 1/scale infinite)."""
+    import torch
+
+    ns, nt, m0 = 4, 128, 1.5
+    U = synth.gauge_field(ns, nt, 0.3, 2)
+    D = oracle.Dirac(U, m0, 3.5, 1.0, -1.0)
+    eta = np.zeros((1, nt, ns, ns, ns, 4, 3), dtype=np.complex128)
+    eta[0, 0] = synth.random_spinor(ns, 1, 5)[0]
+    L = P.Lattice(ns, nt)
+    x = torch.empty(eta.shape, dtype=torch.complex128, device="cuda")
+    kind = P.LAPH_SOLVER_CGNR if solver == "cgnr" else P.LAPH_SOLVER_BICGSTAB
+    st = P.dirac_solve(L.ctx, dev(U), P.laph_dirac(m0, 3.5, 1.0, -1.0), dev(eta), x, 1,
+                       P.solver_params(precision=prec, solver=kind))
+    xs = host(x)
+    assert np.isfinite(xs).all()
+    assert st[0].fallback_used == 0
+    assert D.true_residual(eta[0], xs[0]) <= 1e-10
+    # the exact solution falls below the FP32 normal range far from the source
+    x64 = D.solve(eta[0], tol=1e-13)[0]
+    assert np.abs(x64[nt // 2]).max() < 1e-30

@@ -53,6 +53,8 @@ static void free_dirac_cache(DiracCache &d)
     ctx_free(d.clov);
     ctx_free(d.clinv);
     ctx_free(d.clinv32);
+    ctx_free(d.lk12);
+    ctx_free(d.claos);
     d.valid = false;
     d.U = nullptr;
 }
@@ -125,7 +127,7 @@ extern "C" size_t laph_device_bytes(laph_ctx_t c)
 {
     if (!c) return 0;
     size_t s = c->dc.g64.bytes + c->dc.g32.bytes + c->dc.clov.bytes + c->dc.clinv.bytes +
-               c->dc.clinv32.bytes;
+               c->dc.clinv32.bytes + c->dc.lk12.bytes + c->dc.claos.bytes;
     for (auto &kv : c->bufs) s += kv.second.bytes;
     return s;
 }

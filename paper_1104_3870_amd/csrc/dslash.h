@@ -14,15 +14,23 @@
 #include "laph_impl.h"
 
 // --------------------------------------------------------------- storage policies
+// Element index of component k (alpha*3 + c) of right-hand side r at site i:
+//   FP64 vectors keep one plane per component ([12][Vh][R], fully coalesced for R = 1);
+//   lower precisions store each site-RHS spinor contiguously ([Vh][R][12]) so that a
+//   lane fetches it with a few 16-byte loads.
 struct S64 {
     using E = double2;
     using A = double;
     static constexpr bool kNorm = false;
+    static constexpr bool kAoS = false;
     static constexpr int bytes = 16;
+    __host__ __device__ static long idx(int k, long i, int r, long Vh, int R) { return ((long)k * Vh + i) * R + r; }
     __device__ static Cx<double> ld(const E *p, long i, float) { E v = p[i]; return {v.x, v.y}; }
     __device__ static void st(E *p, long i, Cx<double> v, float) { p[i] = make_double2(v.re, v.im); }
 };
 struct S32 {
+    static constexpr bool kAoS = true;
+    __host__ __device__ static long idx(int k, long i, int r, long Vh, int R) { return (i * R + r) * 12 + k; }
     using E = float2;
     using A = float;
     static constexpr bool kNorm = false;
@@ -32,6 +40,8 @@ struct S32 {
 };
 // FP16 with one FP32 scale per site and right-hand side (value = half * scale)
 struct S16 {
+    static constexpr bool kAoS = true;
+    __host__ __device__ static long idx(int k, long i, int r, long Vh, int R) { return (i * R + r) * 12 + k; }
     using E = __half2;
     using A = float;
     static constexpr bool kNorm = true;
@@ -48,6 +58,8 @@ struct S16 {
 };
 // BF16 (8-bit mantissa, FP32 range; no scale needed): (re, im) packed low/high
 struct SB16 {
+    static constexpr bool kAoS = true;
+    __host__ __device__ static long idx(int k, long i, int r, long Vh, int R) { return (i * R + r) * 12 + k; }
     using E = uint32_t;
     using A = float;
     static constexpr bool kNorm = false;

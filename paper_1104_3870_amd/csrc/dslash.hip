@@ -1,5 +1,5 @@
 // Even-odd anisotropic Wilson-clover hopping kernel with fused clover epilogues.
-#include "dslash.h"
+#include "spinor_io.h"
 
 namespace {
 
@@ -33,35 +33,24 @@ template <class SP>
 __device__ __forceinline__ void load_spinor(const typename SP::E *s, const float *nrm, long Vh, int R, long i, int r,
                                             Spin<typename SP::A> &out)
 {
-    float sc = 1.0f;
-    if constexpr (SP::kNorm) sc = nrm[i * R + r];
+    Cx<typename SP::A> v[12];
+    ld_spinor12<SP, typename SP::A>(s, nrm, Vh, R, i, r, v);
 #pragma unroll
     for (int a = 0; a < 4; a++)
 #pragma unroll
-        for (int c = 0; c < 3; c++) out.v[a][c] = SP::ld(s, ((long)(a * 3 + c) * Vh + i) * R + r, sc);
+        for (int c = 0; c < 3; c++) out.v[a][c] = v[a * 3 + c];
 }
 
 template <class SP>
 __device__ __forceinline__ void store_spinor(typename SP::E *s, float *nrm, long Vh, int R, long i, int r,
                                              const Spin<typename SP::A> &in)
 {
-    float inv = 1.0f;
-    if constexpr (SP::kNorm) {
-        float m = 0.0f;
-#pragma unroll
-        for (int a = 0; a < 4; a++)
-#pragma unroll
-            for (int c = 0; c < 3; c++) m = fmaxf(m, fmaxf(fabsf((float)in.v[a][c].re), fabsf((float)in.v[a][c].im)));
-        // sites below 1e-30 (far tails of a source on one time slice) keep scale 1 and
-        // flush to zero in FP16; a denormal scale would make 1/scale infinite
-        float sc = m > 1e-30f ? m : 1.0f;
-        nrm[i * R + r] = sc;
-        inv = 1.0f / sc;
-    }
+    Cx<typename SP::A> v[12];
 #pragma unroll
     for (int a = 0; a < 4; a++)
 #pragma unroll
-        for (int c = 0; c < 3; c++) SP::st(s, ((long)(a * 3 + c) * Vh + i) * R + r, in.v[a][c], inv);
+        for (int c = 0; c < 3; c++) v[a * 3 + c] = in.v[a][c];
+    st_spinor12<SP, typename SP::A>(s, nrm, Vh, R, i, r, v);
 }
 
 // packed Hermitian 6x6 block times a 6-vector
@@ -375,14 +364,5 @@ void launch_clover_apply(laph_ctx *c, const void *clov, const void *x, const flo
 }
 
 template void launch_dslash<S64, G64, C64>(laph_ctx *, int, const DslashArgs &, hipStream_t);
-template void launch_dslash<S32, G32, C32>(laph_ctx *, int, const DslashArgs &, hipStream_t);
-template void launch_dslash<S16, G32, C32>(laph_ctx *, int, const DslashArgs &, hipStream_t);
-template void launch_dslash<SB16, G32, C32>(laph_ctx *, int, const DslashArgs &, hipStream_t);
 template void launch_clover_apply<S64, C64>(laph_ctx *, const void *, const void *, const float *, void *, float *,
                                             long, int, int, hipStream_t);
-template void launch_clover_apply<S32, C32>(laph_ctx *, const void *, const void *, const float *, void *, float *,
-                                            long, int, int, hipStream_t);
-template void launch_clover_apply<S16, C32>(laph_ctx *, const void *, const void *, const float *, void *, float *,
-                                            long, int, int, hipStream_t);
-template void launch_clover_apply<SB16, C32>(laph_ctx *, const void *, const void *, const float *, void *, float *,
-                                             long, int, int, hipStream_t);

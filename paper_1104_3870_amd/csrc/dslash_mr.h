@@ -1,0 +1,36 @@
+// Multi-right-hand-side low-precision hopping kernel (see dslash_mr.hip).
+#pragma once
+
+#include "dslash.h"
+
+struct MrArgs {
+    void *out;
+    const void *in;
+    const void *x;  // epilogue operand (same parity as out) or null
+    float *out_nrm;
+    const float *in_nrm;
+    const float *x_nrm;
+    const void *links;  // reconstruct-12 FP32 links: float4[(mu*2 + par) * Vh * 3 + i * 3 + k]
+    const void *clov;   // per-site FP32 clover blocks of the output parity: float4[i * 18 + k]
+    int ns, nt;
+    long Vh;
+    int R;
+    int par;
+    double a, c;
+    double wt, ws, bct;
+    int g5d;
+};
+
+// mode: M_PLAIN (out = c D psi [+ a x]) or M_INV_AFTER (out = a x + c A^-1 D psi)
+template <class SP>
+void launch_dslash_mr(laph_ctx *c, int mode, const MrArgs &a, hipStream_t st);
+
+// out = A x (gamma_5 applied to x first when g5_in); cl: per-site blocks of x's parity
+template <class SP>
+void launch_clover_mr(laph_ctx *c, const void *cl, const void *x, const float *x_nrm, void *out, float *out_nrm,
+                      long Vh, int R, int g5_in, hipStream_t st);
+
+// FP64 even-odd links / packed clover inverse -> the low-precision layouts above
+void build_lp_operator(laph_ctx *c, const double2 *g64, const double *clinv64, float4 *links12, float *clinv_aos);
+
+double dslash_mr_bytes(long Vh, int R, int sbytes, bool has_norm, int mode, bool has_x);

@@ -1,0 +1,418 @@
+// Multi-right-hand-side hopping kernel for the low-precision inner solves.
+//
+// The R right-hand sides share links and clover, so the kernel is limited by how many
+// vector-memory instructions each lane issues rather than by bytes: one lane therefore
+// works on NR right-hand sides of one site whose spinors are contiguous 48/96-byte records
+// (site-major layout, 16-byte loads), links are stored as the first two rows only (reconstruct-12:
+// the third row of an SU(3) matrix is conj(row0 x row1); 3 x 16-byte loads per link)
+// and the clover blocks are stored per site (18 x 16-byte loads).  Arithmetic is FP32.
+#include <cstdlib>
+
+#include "dslash_mr.h"
+#include "spinor_io.h"
+
+namespace {
+
+// s[q][alpha][c] for NR right-hand sides r0 .. r0+NR-1 of site j (site-major layout:
+// each right-hand side's spinor is one contiguous record)
+template <class SP, int NR>
+__device__ __forceinline__ void load_site(const typename SP::E *s, const float *nrm, long Vh, int R, long j, int r0,
+                                          Cx<float> (&out)[NR][4][3])
+{
+#pragma unroll
+    for (int q = 0; q < NR; q++) {
+        Cx<float> v[12];
+        ld_spinor12<SP, float>(s, nrm, Vh, R, j, r0 + q, v);
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) out[q][a][c] = v[a * 3 + c];
+    }
+}
+
+template <class SP, int NR>
+__device__ __forceinline__ void store_site(typename SP::E *s, float *nrm, long Vh, int R, long j, int r0,
+                                           const Cx<float> (&in)[NR][4][3])
+{
+#pragma unroll
+    for (int q = 0; q < NR; q++) {
+        Cx<float> v[12];
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) v[a * 3 + c] = in[q][a][c];
+        st_spinor12<SP, float>(s, nrm, Vh, R, j, r0 + q, v);
+    }
+}
+
+// link U (3x3) from its two stored rows
+__device__ __forceinline__ void load_link12(const float4 *lk, long k, Cx<float> (&U)[9])
+{
+    float4 a = lk[k * 3], b = lk[k * 3 + 1], c = lk[k * 3 + 2];
+    U[0] = {a.x, a.y};
+    U[1] = {a.z, a.w};
+    U[2] = {b.x, b.y};
+    U[3] = {b.z, b.w};
+    U[4] = {c.x, c.y};
+    U[5] = {c.z, c.w};
+    // row 2 = conj(row0 x row1)
+    Cx<float> t0 = U[1] * U[5] - U[2] * U[4];
+    Cx<float> t1 = U[2] * U[3] - U[0] * U[5];
+    Cx<float> t2 = U[0] * U[4] - U[1] * U[3];
+    U[6] = {t0.re, -t0.im};
+    U[7] = {t1.re, -t1.im};
+    U[8] = {t2.re, -t2.im};
+}
+
+// packed Hermitian 6x6 block (per-site AoS, 36 floats) times NR 6-vectors
+template <int NR>
+__device__ __forceinline__ void clover_site(const float4 *cl, long i, const Cx<float> (&in)[NR][4][3],
+                                            Cx<float> (&out)[NR][4][3])
+{
+    const float4 *p = cl + i * 18;
+#pragma unroll
+    for (int blk = 0; blk < 2; blk++) {
+        float e[36];
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            float4 v = p[blk * 9 + k];
+            e[4 * k] = v.x;
+            e[4 * k + 1] = v.y;
+            e[4 * k + 2] = v.z;
+            e[4 * k + 3] = v.w;
+        }
+#pragma unroll
+        for (int q = 0; q < NR; q++) {
+            Cx<float> v[6], o[6];
+#pragma unroll
+            for (int s = 0; s < 2; s++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) v[s * 3 + c] = in[q][blk * 2 + s][c];
+#pragma unroll
+            for (int k = 0; k < 6; k++) o[k] = e[k] * v[k];
+            int idx = 6;
+#pragma unroll
+            for (int r = 1; r < 6; r++)
+#pragma unroll
+                for (int c = 0; c < r; c++) {
+                    Cx<float> L = {e[idx], e[idx + 1]};
+                    idx += 2;
+                    o[r] = o[r] + L * v[c];
+                    o[c] = o[c] + conjmul(L, v[r]);
+                }
+#pragma unroll
+            for (int s = 0; s < 2; s++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) out[q][blk * 2 + s][c] = o[s * 3 + c];
+        }
+    }
+}
+
+template <int MU, bool FWD, int NR>
+__device__ __forceinline__ void hop(const Cx<float> (&U)[9], float w, const Cx<float> (&s)[NR][4][3],
+                                    Cx<float> (&acc)[NR][4][3])
+{
+#pragma unroll
+    for (int q = 0; q < NR; q++) {
+        Cx<float> h0[3], h1[3], o0[3], o1[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            if (MU == 0) {
+                h0[c] = FWD ? s[q][0][c] + timesI(s[q][3][c]) : s[q][0][c] - timesI(s[q][3][c]);
+                h1[c] = FWD ? s[q][1][c] + timesI(s[q][2][c]) : s[q][1][c] - timesI(s[q][2][c]);
+            } else if (MU == 1) {
+                h0[c] = FWD ? s[q][0][c] + s[q][3][c] : s[q][0][c] - s[q][3][c];
+                h1[c] = FWD ? s[q][1][c] - s[q][2][c] : s[q][1][c] + s[q][2][c];
+            } else if (MU == 2) {
+                h0[c] = FWD ? s[q][0][c] + timesI(s[q][2][c]) : s[q][0][c] - timesI(s[q][2][c]);
+                h1[c] = FWD ? s[q][1][c] - timesI(s[q][3][c]) : s[q][1][c] + timesI(s[q][3][c]);
+            } else {
+                h0[c] = FWD ? s[q][0][c] - s[q][2][c] : s[q][0][c] + s[q][2][c];
+                h1[c] = FWD ? s[q][1][c] - s[q][3][c] : s[q][1][c] + s[q][3][c];
+            }
+            h0[c] = w * h0[c];
+            h1[c] = w * h1[c];
+        }
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            if (FWD) {
+                o0[a] = U[a * 3] * h0[0] + U[a * 3 + 1] * h0[1] + U[a * 3 + 2] * h0[2];
+                o1[a] = U[a * 3] * h1[0] + U[a * 3 + 1] * h1[1] + U[a * 3 + 2] * h1[2];
+            } else {
+                o0[a] = conjmul(U[a], h0[0]) + conjmul(U[3 + a], h0[1]) + conjmul(U[6 + a], h0[2]);
+                o1[a] = conjmul(U[a], h1[0]) + conjmul(U[3 + a], h1[1]) + conjmul(U[6 + a], h1[2]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            acc[q][0][c] = acc[q][0][c] + o0[c];
+            acc[q][1][c] = acc[q][1][c] + o1[c];
+            if (MU == 0) {
+                acc[q][2][c] = acc[q][2][c] + (FWD ? timesMinusI(o1[c]) : timesI(o1[c]));
+                acc[q][3][c] = acc[q][3][c] + (FWD ? timesMinusI(o0[c]) : timesI(o0[c]));
+            } else if (MU == 1) {
+                acc[q][2][c] = FWD ? acc[q][2][c] - o1[c] : acc[q][2][c] + o1[c];
+                acc[q][3][c] = FWD ? acc[q][3][c] + o0[c] : acc[q][3][c] - o0[c];
+            } else if (MU == 2) {
+                acc[q][2][c] = acc[q][2][c] + (FWD ? timesMinusI(o0[c]) : timesI(o0[c]));
+                acc[q][3][c] = acc[q][3][c] + (FWD ? timesI(o1[c]) : timesMinusI(o1[c]));
+            } else {
+                acc[q][2][c] = FWD ? acc[q][2][c] - o0[c] : acc[q][2][c] + o0[c];
+                acc[q][3][c] = FWD ? acc[q][3][c] - o1[c] : acc[q][3][c] + o1[c];
+            }
+        }
+    }
+}
+
+template <int MU, int NR, class SP>
+__device__ __forceinline__ void do_dir(const MrArgs &P, const float4 *lk, int x, int y, int z, int t, long i, int r0,
+                                       Cx<float> (&acc)[NR][4][3])
+{
+    const int ns = P.ns, nt = P.nt, par = P.par, opar = par ^ 1;
+    const long Vh = P.Vh;
+    const auto *in = (const typename SP::E *)P.in;
+    // forward
+    {
+        int xx = x, yy = y, zz = z, tt = t;
+        float w = MU == 3 ? (float)P.wt : (float)P.ws;
+        if (MU == 0) xx = (x + 1 == ns) ? 0 : x + 1;
+        if (MU == 1) yy = (y + 1 == ns) ? 0 : y + 1;
+        if (MU == 2) zz = (z + 1 == ns) ? 0 : z + 1;
+        if (MU == 3) {
+            tt = (t + 1 == nt) ? 0 : t + 1;
+            if (t + 1 == nt) w *= (float)P.bct;
+        }
+        long nb = lex_index(xx, yy, zz, tt, ns) >> 1;
+        Cx<float> U[9];
+        load_link12(lk, (long)(MU * 2 + par) * Vh + i, U);
+        Cx<float> s[NR][4][3];
+        load_site<SP, NR>(in, P.in_nrm, Vh, P.R, nb, r0, s);
+        hop<MU, true, NR>(U, w, s, acc);
+    }
+    // backward
+    {
+        int xx = x, yy = y, zz = z, tt = t;
+        float w = MU == 3 ? (float)P.wt : (float)P.ws;
+        if (MU == 0) xx = (x == 0) ? ns - 1 : x - 1;
+        if (MU == 1) yy = (y == 0) ? ns - 1 : y - 1;
+        if (MU == 2) zz = (z == 0) ? ns - 1 : z - 1;
+        if (MU == 3) {
+            tt = (t == 0) ? nt - 1 : t - 1;
+            if (t == 0) w *= (float)P.bct;
+        }
+        long nb = lex_index(xx, yy, zz, tt, ns) >> 1;
+        Cx<float> U[9];
+        load_link12(lk, (long)(MU * 2 + opar) * Vh + nb, U);
+        Cx<float> s[NR][4][3];
+        load_site<SP, NR>(in, P.in_nrm, Vh, P.R, nb, r0, s);
+        hop<MU, false, NR>(U, w, s, acc);
+    }
+}
+
+#ifndef LAPH_MR_WAVES
+#define LAPH_MR_WAVES 0
+#endif
+#if LAPH_MR_WAVES > 0
+#define LAPH_MR_ATTR __attribute__((amdgpu_waves_per_eu(LAPH_MR_WAVES)))
+#else
+#define LAPH_MR_ATTR
+#endif
+
+template <class SP, int NR, int MODE>
+__global__ __launch_bounds__(256) LAPH_MR_ATTR void k_dslash_mr(const MrArgs P)
+{
+    unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    long tid = (long)b * blockDim.x + threadIdx.x;
+    const int G = P.R / NR;
+    const long Vh = P.Vh;
+    if (tid >= Vh * G) return;
+    long i = tid / G;
+    int r0 = (int)(tid - i * G) * NR;
+    int x, y, z, t;
+    cb_coords(i, P.par, P.ns, x, y, z, t);
+    const float4 *lk = (const float4 *)P.links;
+    Cx<float> acc[NR][4][3];
+#pragma unroll
+    for (int q = 0; q < NR; q++)
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) acc[q][a][c] = {0.0f, 0.0f};
+    do_dir<0, NR, SP>(P, lk, x, y, z, t, i, r0, acc);
+    do_dir<1, NR, SP>(P, lk, x, y, z, t, i, r0, acc);
+    do_dir<2, NR, SP>(P, lk, x, y, z, t, i, r0, acc);
+    do_dir<3, NR, SP>(P, lk, x, y, z, t, i, r0, acc);
+    if (P.g5d) {
+#pragma unroll
+        for (int q = 0; q < NR; q++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                acc[q][2][c] = cneg(acc[q][2][c]);
+                acc[q][3][c] = cneg(acc[q][3][c]);
+            }
+    }
+    const float ca = (float)P.a, cc = (float)P.c;
+    const float4 *cl = (const float4 *)P.clov;
+    Cx<float> res[NR][4][3];
+    if constexpr (MODE == M_INV_AFTER) {
+        clover_site<NR>(cl, i, acc, res);
+#pragma unroll
+        for (int q = 0; q < NR; q++)
+#pragma unroll
+            for (int a = 0; a < 4; a++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) res[q][a][c] = cc * res[q][a][c];
+    } else {
+#pragma unroll
+        for (int q = 0; q < NR; q++)
+#pragma unroll
+            for (int a = 0; a < 4; a++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) res[q][a][c] = cc * acc[q][a][c];
+    }
+    if (P.x) {
+        Cx<float> xv[NR][4][3];
+        load_site<SP, NR>((const typename SP::E *)P.x, P.x_nrm, Vh, P.R, i, r0, xv);
+#pragma unroll
+        for (int q = 0; q < NR; q++)
+#pragma unroll
+            for (int a = 0; a < 4; a++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) res[q][a][c] = res[q][a][c] + ca * xv[q][a][c];
+    }
+    store_site<SP, NR>((typename SP::E *)P.out, P.out_nrm, Vh, P.R, i, r0, res);
+}
+
+// out = A x with optional gamma_5 on x (local, per-site clover)
+template <class SP, int NR>
+__global__ __launch_bounds__(256) void k_clover_mr(const float4 *__restrict__ cl, const typename SP::E *__restrict__ x,
+                                                   const float *x_nrm, typename SP::E *__restrict__ out, float *out_nrm,
+                                                   long Vh, int R, int g5_in)
+{
+    long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int G = R / NR;
+    if (tid >= Vh * G) return;
+    long i = tid / G;
+    int r0 = (int)(tid - i * G) * NR;
+    Cx<float> v[NR][4][3], o[NR][4][3];
+    load_site<SP, NR>(x, x_nrm, Vh, R, i, r0, v);
+    if (g5_in) {
+#pragma unroll
+        for (int q = 0; q < NR; q++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                v[q][2][c] = cneg(v[q][2][c]);
+                v[q][3][c] = cneg(v[q][3][c]);
+            }
+    }
+    clover_site<NR>(cl, i, v, o);
+    store_site<SP, NR>(out, out_nrm, Vh, R, i, r0, o);
+}
+
+// per-site packed clover blocks (SoA FP64) -> per-site AoS FP32 (72 floats)
+__global__ void k_clover_aos(const double *__restrict__ soa, float *__restrict__ aos, long Vh)
+{
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= 2 * Vh) return;
+    int par = (int)(t / Vh);
+    long i = t - (long)par * Vh;
+    for (int e = 0; e < 72; e++) aos[t * 72 + e] = (float)soa[((long)par * 72 + e) * Vh + i];
+}
+
+// even-odd SoA FP64 links -> reconstruct-12 AoS FP32 (rows 0 and 1)
+__global__ void k_links12(const double2 *__restrict__ g64, float4 *__restrict__ lk, long Vh)
+{
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= 8 * Vh) return;
+    long mp = t / Vh, i = t - mp * Vh;  // mp = mu * 2 + par
+    double2 e[6];
+    for (int k = 0; k < 6; k++) e[k] = g64[(mp * 9 + k) * Vh + i];
+    lk[t * 3] = make_float4((float)e[0].x, (float)e[0].y, (float)e[1].x, (float)e[1].y);
+    lk[t * 3 + 1] = make_float4((float)e[2].x, (float)e[2].y, (float)e[3].x, (float)e[3].y);
+    lk[t * 3 + 2] = make_float4((float)e[4].x, (float)e[4].y, (float)e[5].x, (float)e[5].y);
+}
+
+}  // namespace
+
+// right-hand sides per lane: 1 (measured best with the site-major layout), or LAPH_MR_NR
+static int pick_nr(int R)
+{
+    static int env = -1;
+    if (env < 0) {
+        const char *e = getenv("LAPH_MR_NR");
+        env = e ? atoi(e) : 0;
+    }
+    if (env == 1 || env == 2 || env == 4)
+        if (R % env == 0) return env;
+    return 1;
+}
+
+double dslash_mr_bytes(long Vh, int R, int sbytes, bool has_norm, int mode, bool has_x)
+{
+    double site = 8.0 * 48;  // reconstruct-12 FP32 links
+    if (mode == M_INV_AFTER) site += 72.0 * 4;
+    double per_rhs = 12.0 * sbytes * (2 + (has_x ? 1 : 0)) + (has_norm ? 4.0 * (2 + (has_x ? 1 : 0)) : 0.0);
+    return (double)Vh * (site + R * per_rhs);
+}
+
+template <class SP>
+void launch_dslash_mr(laph_ctx *c, int mode, const MrArgs &a, hipStream_t st)
+{
+    int NR = pick_nr(a.R);
+    long n = a.Vh * (a.R / NR);
+    dim3 grid(nblocks_for(n, 256)), block(256);
+    hipEvent_t e0, e1;
+    timing_begin(c, &e0, &e1);
+#define LAPH_MR(NRV)                                                                                    \
+    if (mode == M_INV_AFTER)                                                                            \
+        hipLaunchKernelGGL((k_dslash_mr<SP, NRV, M_INV_AFTER>), grid, block, 0, st, a);                \
+    else                                                                                                \
+        hipLaunchKernelGGL((k_dslash_mr<SP, NRV, M_PLAIN>), grid, block, 0, st, a);
+    if (NR == 4) {
+        LAPH_MR(4)
+    } else if (NR == 2) {
+        LAPH_MR(2)
+    } else {
+        LAPH_MR(1)
+    }
+#undef LAPH_MR
+    LAPH_HIP(hipGetLastError());
+    timing_end(c, e0, e1, dslash_mr_bytes(a.Vh, a.R, SP::bytes, SP::kNorm, mode, a.x != nullptr));
+}
+
+template <class SP>
+void launch_clover_mr(laph_ctx *c, const void *cl, const void *x, const float *x_nrm, void *out, float *out_nrm,
+                      long Vh, int R, int g5_in, hipStream_t st)
+{
+    int NR = pick_nr(R);
+    long n = Vh * (R / NR);
+    dim3 grid(nblocks_for(n, 256)), block(256);
+    const float4 *clp = (const float4 *)cl;
+    const auto *xp = (const typename SP::E *)x;
+    auto *op = (typename SP::E *)out;
+    if (NR == 4)
+        hipLaunchKernelGGL((k_clover_mr<SP, 4>), grid, block, 0, st, clp, xp, x_nrm, op, out_nrm, Vh, R, g5_in);
+    else if (NR == 2)
+        hipLaunchKernelGGL((k_clover_mr<SP, 2>), grid, block, 0, st, clp, xp, x_nrm, op, out_nrm, Vh, R, g5_in);
+    else
+        hipLaunchKernelGGL((k_clover_mr<SP, 1>), grid, block, 0, st, clp, xp, x_nrm, op, out_nrm, Vh, R, g5_in);
+    LAPH_HIP(hipGetLastError());
+}
+
+void build_lp_operator(laph_ctx *c, const double2 *g64, const double *clinv64, float4 *links12, float *clinv_aos)
+{
+    long Vh = c->g.Vh;
+    hipLaunchKernelGGL(k_links12, dim3(nblocks_for(8 * Vh, 256)), dim3(256), 0, c->stream, g64, links12, Vh);
+    hipLaunchKernelGGL(k_clover_aos, dim3(nblocks_for(2 * Vh, 256)), dim3(256), 0, c->stream, clinv64, clinv_aos, Vh);
+    LAPH_HIP(hipGetLastError());
+}
+
+template void launch_dslash_mr<S32>(laph_ctx *, int, const MrArgs &, hipStream_t);
+template void launch_dslash_mr<S16>(laph_ctx *, int, const MrArgs &, hipStream_t);
+template void launch_dslash_mr<SB16>(laph_ctx *, int, const MrArgs &, hipStream_t);
+template void launch_clover_mr<S32>(laph_ctx *, const void *, const void *, const float *, void *, float *, long, int,
+                                    int, hipStream_t);
+template void launch_clover_mr<S16>(laph_ctx *, const void *, const void *, const float *, void *, float *, long, int,
+                                    int, hipStream_t);
+template void launch_clover_mr<SB16>(laph_ctx *, const void *, const void *, const float *, void *, float *, long, int,
+                                     int, hipStream_t);

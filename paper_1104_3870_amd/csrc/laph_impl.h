@@ -142,8 +142,10 @@ struct DiracCache {
     DevBuf g32;     // even-odd links FP32 (float2), built on demand
     DevBuf clov;    // clover FP64 packed
     DevBuf clinv;   // clover inverse FP64 packed
-    DevBuf clinv32; // clover inverse FP32 packed (mixed precision)
-    bool f32 = false;  // g32 / clinv32 are current
+    DevBuf clinv32; // clover inverse FP32 packed (unused by the multi-RHS path)
+    DevBuf lk12;    // reconstruct-12 FP32 links, per-site AoS (low-precision operator)
+    DevBuf claos;   // FP32 clover inverse, per-site AoS (low-precision operator)
+    bool f32 = false;  // lk12 / claos are current
 };
 
 struct laph_ctx {

@@ -13,7 +13,8 @@
 #include <cmath>
 #include <cstdlib>
 
-#include "dslash.h"
+#include "dslash_mr.h"
+#include "spinor_io.h"
 
 namespace {
 
@@ -99,43 +100,16 @@ __device__ __forceinline__ void sum_partials(const double *partial, int nblk, in
     for (int k = 0; k < NV; k++) out[k] = lds[0][k];
 }
 
-template <class SP>
-__device__ __forceinline__ Cx<double> ldd(const Vec &v, long Vh, int R, int k, long i, int r)
-{
-    float s = 1.0f;
-    if constexpr (SP::kNorm) s = v.n[i * R + r];
-    auto c = SP::ld((const typename SP::E *)v.d, ((long)k * Vh + i) * R + r, s);
-    return {(double)c.re, (double)c.im};
-}
-
 // load / store a whole site-spinor as doubles (the BLAS arithmetic is FP64)
 template <class SP>
 __device__ __forceinline__ void ld_site(const Vec &v, long Vh, int R, long i, int r, Cx<double> (&o)[12])
 {
-    float s = 1.0f;
-    if constexpr (SP::kNorm) s = v.n[i * R + r];
-#pragma unroll
-    for (int k = 0; k < 12; k++) {
-        auto c = SP::ld((const typename SP::E *)v.d, ((long)k * Vh + i) * R + r, s);
-        o[k] = {(double)c.re, (double)c.im};
-    }
+    ld_spinor12<SP, double>((const typename SP::E *)v.d, v.n, Vh, R, i, r, o);
 }
 template <class SP>
 __device__ __forceinline__ void st_site(Vec &v, long Vh, int R, long i, int r, const Cx<double> (&o)[12])
 {
-    using A = typename SP::A;
-    float inv = 1.0f;
-    if constexpr (SP::kNorm) {
-        double m = 0;
-#pragma unroll
-        for (int k = 0; k < 12; k++) m = fmax(m, fmax(fabs(o[k].re), fabs(o[k].im)));
-        float sc = m > 1e-30 ? (float)m : 1.0f;  // see store_spinor: no denormal scales
-        v.n[i * R + r] = sc;
-        inv = 1.0f / sc;
-    }
-#pragma unroll
-    for (int k = 0; k < 12; k++)
-        SP::st((typename SP::E *)v.d, ((long)k * Vh + i) * R + r, Cx<A>{(A)o[k].re, (A)o[k].im}, inv);
+    st_spinor12<SP, double>((typename SP::E *)v.d, v.n, Vh, R, i, r, o);
 }
 
 __device__ __forceinline__ double2 c2(Cx<double> a) { return make_double2(a.re, a.im); }
@@ -195,10 +169,13 @@ __global__ __launch_bounds__(kBS) void k_dot(Vec a, Vec b, long Vh, int R, doubl
     int rr = (int)((blockIdx.x * (long)kBS + threadIdx.x) % R);
     for (long tid = blockIdx.x * (long)kBS + threadIdx.x; tid < n; tid += stride) {
         long i = tid / R;
+        Cx<double> u[12], w[12];
+        ld_site<SP>(a, Vh, R, i, rr, u);
+        ld_site<SP>(b, Vh, R, i, rr, w);
+#pragma unroll
         for (int k = 0; k < 12; k++) {
-            Cx<double> u = ldd<SP>(a, Vh, R, k, i, rr), w = ldd<SP>(b, Vh, R, k, i, rr);
-            acc[0] += u.re * w.re + u.im * w.im;
-            acc[1] += u.re * w.im - u.im * w.re;
+            acc[0] += u[k].re * w[k].re + u[k].im * w[k].im;
+            acc[1] += u[k].re * w[k].im - u[k].im * w[k].re;
         }
     }
     block_partial<2>(acc, R, partial);
@@ -252,11 +229,14 @@ __global__ __launch_bounds__(kBS) void k_dot_ts(Vec t, Vec s, long Vh, int R, do
     int rr = (int)((blockIdx.x * (long)kBS + threadIdx.x) % R);
     for (long tid = blockIdx.x * (long)kBS + threadIdx.x; tid < n; tid += stride) {
         long i = tid / R;
+        Cx<double> u[12], w[12];
+        ld_site<SP>(t, Vh, R, i, rr, u);
+        ld_site<SP>(s, Vh, R, i, rr, w);
+#pragma unroll
         for (int k = 0; k < 12; k++) {
-            Cx<double> u = ldd<SP>(t, Vh, R, k, i, rr), w = ldd<SP>(s, Vh, R, k, i, rr);
-            acc[0] += u.re * w.re + u.im * w.im;
-            acc[1] += u.re * w.im - u.im * w.re;
-            acc[2] += u.re * u.re + u.im * u.im;
+            acc[0] += u[k].re * w[k].re + u[k].im * w[k].im;
+            acc[1] += u[k].re * w[k].im - u[k].im * w[k].re;
+            acc[2] += u[k].re * u[k].re + u[k].im * u[k].im;
         }
     }
     block_partial<3>(acc, R, partial);
@@ -734,6 +714,11 @@ struct Op {
     const char *clov;   // packed clover (FP64 operator only)
     double ws, wt, bct;
     Vec te;  // even temporary
+    // low-precision multi-RHS layouts (used whenever SP is not FP64)
+    const float4 *lk12 = nullptr;
+    const float4 *claos = nullptr;  // per-site clover inverse, parity p at claos + p * Vh * 18
+
+    static constexpr bool kLow = !std::is_same<SP, S64>::value;
 
     DslashArgs base(int par) const
     {
@@ -752,54 +737,66 @@ struct Op {
     const void *cinv(int par) const { return clinv + (size_t)par * 72 * Vh * sizeof(typename CP::E); }
     const void *cl(int par) const { return clov + (size_t)par * 72 * Vh * sizeof(typename CP::E); }
 
+    // hopping term with epilogue; mode M_PLAIN or M_INV_AFTER
+    void dslash(int mode, int par, Vec in, Vec out, const Vec *x, double a, double cc, int g5d) const
+    {
+        if constexpr (kLow) {
+            MrArgs m{};
+            m.out = out.d;
+            m.out_nrm = out.n;
+            m.in = in.d;
+            m.in_nrm = in.n;
+            m.x = x ? x->d : nullptr;
+            m.x_nrm = x ? x->n : nullptr;
+            m.links = lk12;
+            m.clov = claos + (size_t)par * Vh * 18;
+            m.ns = c->g.ns;
+            m.nt = c->g.nt;
+            m.Vh = Vh;
+            m.R = R;
+            m.par = par;
+            m.a = a;
+            m.c = cc;
+            m.wt = wt;
+            m.ws = ws;
+            m.bct = bct;
+            m.g5d = g5d;
+            launch_dslash_mr<SP>(c, mode, m, st);
+        } else {
+            DslashArgs d = base(par);
+            d.in = in.d;
+            d.in_nrm = in.n;
+            d.out = out.d;
+            d.out_nrm = out.n;
+            d.x = x ? x->d : nullptr;
+            d.x_nrm = x ? x->n : nullptr;
+            d.clov = cinv(par);
+            d.a = a;
+            d.c = cc;
+            d.g5d = g5d;
+            launch_dslash<SP, GP, CP>(c, mode, d, st);
+        }
+    }
+    void clover_inv(int par, Vec in, Vec out, int g5_in) const
+    {
+        if constexpr (kLow)
+            launch_clover_mr<SP>(c, claos + (size_t)par * Vh * 18, in.d, in.n, out.d, out.n, Vh, R, g5_in, st);
+        else
+            launch_clover_apply<SP, CP>(c, cinv(par), in.d, in.n, out.d, out.n, Vh, R, g5_in, st);
+    }
+
     // out_o = in_o - A_oo^-1 D_oe A_ee^-1 D_eo in_o
     void mhat(Vec in, Vec out) const
     {
-        DslashArgs a = base(0);
-        a.in = in.d;
-        a.in_nrm = in.n;
-        a.out = te.d;
-        a.out_nrm = te.n;
-        a.clov = cinv(0);
-        a.a = 0;
-        a.c = 1;
-        launch_dslash<SP, GP, CP>(c, M_INV_AFTER, a, st);
-        DslashArgs b = base(1);
-        b.in = te.d;
-        b.in_nrm = te.n;
-        b.out = out.d;
-        b.out_nrm = out.n;
-        b.x = in.d;
-        b.x_nrm = in.n;
-        b.clov = cinv(1);
-        b.a = 1;
-        b.c = -1;
-        launch_dslash<SP, GP, CP>(c, M_INV_AFTER, b, st);
+        dslash(M_INV_AFTER, 0, in, te, nullptr, 0.0, 1.0, 0);
+        dslash(M_INV_AFTER, 1, te, out, &in, 1.0, -1.0, 0);
     }
     // out_o = Mhat^dag in_o = in_o - gamma_5 D_oe A_ee^-1 D_eo A_oo^-1 gamma_5 in_o
     void mhat_dag(Vec in, Vec out, Vec to) const
     {
-        launch_clover_apply<SP, CP>(c, cinv(1), in.d, in.n, to.d, to.n, Vh, R, 1, st);
-        DslashArgs a = base(0);
-        a.in = to.d;
-        a.in_nrm = to.n;
-        a.out = te.d;
-        a.out_nrm = te.n;
-        a.clov = cinv(0);
-        a.a = 0;
-        a.c = 1;
-        launch_dslash<SP, GP, CP>(c, M_INV_AFTER, a, st);
-        DslashArgs b = base(1);
-        b.in = te.d;
-        b.in_nrm = te.n;
-        b.out = out.d;
-        b.out_nrm = out.n;
-        b.x = in.d;
-        b.x_nrm = in.n;
-        b.a = 1;
-        b.c = -1;
-        b.g5d = 1;
-        launch_dslash<SP, GP, CP>(c, M_PLAIN, b, st);
+        clover_inv(1, in, to, 1);
+        dslash(M_INV_AFTER, 0, to, te, nullptr, 0.0, 1.0, 0);
+        dslash(M_PLAIN, 1, te, out, &in, 1.0, -1.0, 1);
     }
 };
 
@@ -1157,10 +1154,12 @@ void solve_batch(laph_ctx *c, const double *eta, double *x, int R, int nreal, co
     for (int q = 0; q < R; q++) done[q] = !hs[q].active;
 
     Op<SP, GP, CP> lo{c, c->stream, Vh, R,
-                      std::is_same<GP, G64>::value ? dc.g64.p : dc.g32.p,
-                      std::is_same<CP, C64>::value ? (const char *)dc.clinv.p : (const char *)dc.clinv32.p,
+                      std::is_same<GP, G64>::value ? dc.g64.p : nullptr,
+                      std::is_same<CP, C64>::value ? (const char *)dc.clinv.p : nullptr,
                       nullptr, -0.5 / dc.prm.xi, -0.5, dc.prm.bc_t,
                       w.make("te_lo", SP::bytes, SP::kNorm)};
+    lo.lk12 = (const float4 *)dc.lk12.p;
+    lo.claos = (const float4 *)dc.claos.p;
 
     // Attempts: BiCGStab (Sec. IV) for every RHS that has not failed it, then CG on the
     // normal equations (the paper's fallback) in the same precision for the RHS whose
@@ -1277,10 +1276,10 @@ void dirac_prepare(laph_ctx *c, const double *U, const laph_dirac *d, bool need_
         dc.f32 = false;
     }
     if (need_f32 && !dc.f32) {
-        ctx_buf(c, dc.g32, (size_t)72 * Vh * 8);
-        ctx_buf(c, dc.clinv32, (size_t)144 * Vh * 4);
-        eo64_to_eo32(c, (const double2 *)dc.g64.p, (float2 *)dc.g32.p, 72 * Vh);
-        clover_to_f32(c, (const double *)dc.clinv.p, (float *)dc.clinv32.p);
+        ctx_buf(c, dc.lk12, (size_t)8 * Vh * 3 * 16);
+        ctx_buf(c, dc.claos, (size_t)2 * Vh * 72 * 4);
+        build_lp_operator(c, (const double2 *)dc.g64.p, (const double *)dc.clinv.p, (float4 *)dc.lk12.p,
+                          (float *)dc.claos.p);
         dc.f32 = true;
     }
     (void)V;

@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1, help="batches timed with the plain FP64 solver")
     ap.add_argument("--cpu-iters", type=int, default=8, help="oracle CG iterations in the CPU sample (0: skip)")
     ap.add_argument("--m0", type=float, default=None)
+    ap.add_argument("--learned-sources", type=int, default=2,
+                    help="sources solved with FGMRES and the learned preconditioner (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -183,6 +185,47 @@ def main():
                 "ms_per_step": 1000 * e64 / args.fp64_steps, "mean_iters": float(np.mean(it64)),
                 "form": "FP64 even-odd %s, one right-hand side at a time" % args.solver.upper()}
 
+    # ---------------- learned preconditioner: FGMRES with the trained PT-net, one source at a time
+    learned = None
+    if args.learned_sources > 0:
+        from paper_1104_3870_amd import train_ptnet as T
+
+        wpath = os.path.join(ROOT, "paper_1104_3870_amd", "weights", "ptnet.npz")
+        t_tr = time.time()
+        from_file = os.path.exists(wpath)
+        if from_file:
+            w, meta = T.load(wpath)
+        else:
+            w, meta = T.train(epochs=20, log=log)
+        t_tr = time.time() - t_tr
+        net = P.PTNet(L.ctx, meta["channels"])
+        net.set_weights(w)
+        nl = min(args.learned_sources, nsrc)
+        svl = P.solver_params(tol=cfg.solve_tol, maxiter=3000, solver=P.LAPH_SOLVER_FGMRES, net=net, restart=32)
+        P.make_diluted_source(L.ctx, evecs, cfg.nv, cfg.noise_s, cfg.noise_k, dil, 0, nl, eta[:nl])
+        torch.cuda.synchronize()
+        t2 = time.time()
+        st = P.dirac_solve(L.ctx, Ud, prm, eta[:nl], x[:nl], nl, svl)
+        P.sink_project(L.ctx, evecs, cfg.nv, x[:nl], nl, coef[:nl])
+        torch.cuda.synchronize()
+        el = time.time() - t2
+        hist = meta.get("history", {})
+        learned = {"value": round(nl / el, 4), "unit": "sources/s", "sources": nl,
+                   "mean_iters": float(np.mean([q.iters for q in st])),
+                   "fallbacks": int(sum(q.fallback_used for q in st)),
+                   "max_true_resid": float(max(q.true_resid for q in st)),
+                   "form": "even-odd FGMRES(32), FP64 basis, PT-net right preconditioner, channels %s "
+                           "(BF16 weights, FP32 arithmetic)" % meta["channels"],
+                   "training": {"pairs": meta["pairs_per_seed"] * (meta["train_seeds"][1] - meta["train_seeds"][0] + 1),
+                                "lattice": meta["lattice"], "epochs": meta["epochs"],
+                                "test_loss": hist.get("test", [None])[-1],
+                                "untrained_test_loss": hist.get("test", [None])[0],
+                                "data_s": meta["data_s"], "train_s": meta["train_s"],
+                                "weights": "trained earlier with train_ptnet.py" if from_file else
+                                           "trained in this run (%.1f s)" % t_tr}}
+        log("learned: %d sources in %.2f s, iterations %s" % (nl, el, [q.iters for q in st]))
+        net.close()
+
     avg_ms = tm.dslash_ms / max(tm.dslash_launches, 1)
     bytes_per_launch = tm.dslash_bytes / max(tm.dslash_launches, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
@@ -219,6 +262,7 @@ def main():
         "max_true_resid": float(max(resid)),
         "fp64_plain": fp64,
         "speedup_vs_fp64": round(value / fp64["value"], 3) if fp64 else None,
+        "learned": learned,
         "setup_s": {"total": round(t_setup, 2), "eigvecs": round(t_eig, 2), "eig_restarts": est.restarts},
         "roofline": roofline,
         "cpu_baseline": cpu,

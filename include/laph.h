@@ -24,7 +24,8 @@
  * Field arguments are DEVICE pointers unless stated otherwise; statistics structs and
  * eigenvalues are host memory.  A context owns device scratch it allocates itself and
  * caches derived fields (even-odd links, clover term and its inverse) for the last gauge
- * field it saw: call laph_forget_gauge() after changing a gauge field in place.
+ * field it saw, keyed by its address: call laph_forget_gauge() after changing a gauge
+ * field in place or before passing a new field that may occupy a freed one's address.
  * Every call enqueues work on the context's HIP stream; calls that return statistics
  * synchronise that stream.  One context per stream; contexts share nothing.
  *
@@ -193,6 +194,7 @@ typedef struct {
     int block_rhs;      /* right-hand sides iterated together (1..32); 0 = autotune */
     int use_graph;      /* capture the iteration in HIP graphs */
     const void *net;    /* learned preconditioner (laph_ptnet_t) for LAPH_SOLVER_FGMRES */
+    int restart;        /* FGMRES restart length (0: 24) */
 } laph_solver;
 
 typedef struct {
@@ -204,11 +206,64 @@ typedef struct {
 
 /* Solve Omega x = eta for n_rhs right-hand sides (Sec. IV).  eta, x: device, n_rhs
  * spinor fields each (FP64); stats: HOST array of n_rhs (may be NULL).
- * Up to three BiCGStab attempts (each restarted from the current x with a tighter
- * even-odd target when the FP64 true residual of the full system misses tol) are
- * followed by the CGNR fallback, which runs up to max(maxiter, 5000) iterations. */
+ * Up to three BiCGStab (or FGMRES) attempts (each restarted from the current x with a
+ * tighter even-odd target when the FP64 true residual of the full system misses tol) are
+ * followed by the CGNR fallback, which runs up to max(maxiter, 5000) iterations.
+ * LAPH_SOLVER_FGMRES solves one right-hand side at a time (block_rhs is ignored) with an
+ * FP64 basis and solver->net as right preconditioner; iters counts its iterations (one
+ * network application and one even-odd operator each) plus any fallback iterations. */
 LAPH_API int dirac_solve(laph_ctx_t ctx, const double *U, const laph_dirac *dirac, const double *eta,
                 double *x, int n_rhs, const laph_solver *solver, laph_solve_stats *stats);
+
+/* ------------------------------------------------- learned preconditioner
+ * Not in the paper: a gauge-equivariant parallel-transport network N that approximates
+ * K^-1 and serves as the right preconditioner of flexible GMRES on the even-odd system
+ * (LAPH_SOLVER_FGMRES).  The answer is still judged by the FP64 true residual of
+ * Omega x = eta, and a right-hand side the preconditioned solve does not finish falls back
+ * to plain CGNR (fallback_used = 1).
+ *
+ * Layer l maps ch[l] spinor fields to ch[l+1] fields:
+ *   out_c(x) = sum_{c', d} W_l[c][c'][d] (T_d phi_c')(x),  d = 0 (self), 1..4 (+mu), 5..8 (-mu),
+ *   T_{+mu} phi(x) = U_mu(x) phi(x+mu),  T_{-mu} phi(x) = U_mu(x-mu)^dag phi(x-mu),
+ * mu = x, y, z, t, hops across the time boundary multiplied by bc_t.  W_l[c][c'][d] is a
+ * complex 4x4 matrix on spin; every layer is therefore gauge equivariant.  Kernels use
+ * BF16 copies of the weights (round to nearest even) with FP32 arithmetic; the optimiser
+ * keeps FP32 master weights.
+ * Weight layout (get/set): layers in order, each [ch[l+1]][ch[l]][9][4][4] complex as
+ * interleaved (re, im) doubles; n = sum_l ch[l] ch[l+1] 144 complex numbers.
+ * Fields (in, out, gradients): canonical spinor fields, device, FP64. */
+#define LAPH_PTNET_MAX_LAYERS 8
+typedef struct laph_ptnet *laph_ptnet_t;
+
+/* channels[0..layers]: first and last 1, each 1, 2 or 4.  Weights start as small seeded
+ * Gaussian numbers plus 1/ch[l] times the identity on the self path.  The net lives on
+ * the device of ctx and may be used with any context on that device. */
+LAPH_API int laph_ptnet_create(laph_ctx_t ctx, int layers, const int *channels, uint64_t seed,
+                               laph_ptnet_t *net);
+LAPH_API int laph_ptnet_destroy(laph_ptnet_t net);
+LAPH_API int laph_ptnet_num_weights(laph_ptnet_t net, size_t *n_complex);
+/* FP32 master weights as doubles (host array of 2n); set also resets the optimiser. */
+LAPH_API int laph_ptnet_get_weights(laph_ptnet_t net, double *w);
+LAPH_API int laph_ptnet_set_weights(laph_ptnet_t net, const double *w);
+/* out = N(in) for n_fields fields. */
+LAPH_API int laph_ptnet_forward(laph_ctx_t ctx, laph_ptnet_t net, const double *U, double bc_t,
+                                const double *in, double *out, int n_fields);
+/* Backward pass of a real loss L given gout = dL/d(N(in))^*: writes dL/din^* to gin (device,
+ * may be NULL) and dL/dW^* (host, 2n doubles, summed over the fields) to gw. */
+LAPH_API int laph_ptnet_backward(laph_ctx_t ctx, laph_ptnet_t net, const double *U, double bc_t,
+                                 const double *in, const double *gout, double *gin, double *gw,
+                                 int n_fields);
+
+typedef struct {
+    double lr, beta1, beta2, eps; /* Adam */
+    int loss_parity;              /* sites entering the loss: -1 all, 0 even, 1 odd */
+} laph_adam;
+
+/* One Adam step on L = sum_r |N(b_r) - x_r|^2 / |x_r|^2 over n_pairs (source, solution)
+ * pairs (device fields); *loss (host, may be NULL) receives L / n_pairs before the step. */
+LAPH_API int laph_ptnet_train_step(laph_ctx_t ctx, laph_ptnet_t net, const double *U, double bc_t,
+                                   const double *b, const double *x, int n_pairs,
+                                   const laph_adam *opt, double *loss);
 
 /* ----------------------------------------------------------- sink projection
  * coef[r][t][alpha][n] = sum_{x,c} conj(V_{t,n}(x,c)) X_r(x,t,c,alpha): the quark

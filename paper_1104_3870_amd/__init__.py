@@ -59,7 +59,12 @@ class laph_dirac(ctypes.Structure):
 class laph_solver(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("solver", ctypes.c_int),
                 ("precision", ctypes.c_int), ("reliable_every", ctypes.c_int), ("block_rhs", ctypes.c_int),
-                ("use_graph", ctypes.c_int), ("net", ctypes.c_void_p)]
+                ("use_graph", ctypes.c_int), ("net", ctypes.c_void_p), ("restart", ctypes.c_int)]
+
+
+class laph_adam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double), ("loss_parity", ctypes.c_int)]
 
 
 class laph_solve_stats(ctypes.Structure):
@@ -99,6 +104,14 @@ EXPORTS = {
     "dirac_solve": (_I, [_P, _P, ctypes.POINTER(laph_dirac), _P, _P, _I, ctypes.POINTER(laph_solver),
                          ctypes.POINTER(laph_solve_stats)]),
     "sink_project": (_I, [_P, _P, _I, _P, _I, _P]),
+    "laph_ptnet_create": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.c_uint64, ctypes.POINTER(_P)]),
+    "laph_ptnet_destroy": (_I, [_P]),
+    "laph_ptnet_num_weights": (_I, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    "laph_ptnet_get_weights": (_I, [_P, _P]),
+    "laph_ptnet_set_weights": (_I, [_P, _P]),
+    "laph_ptnet_forward": (_I, [_P, _P, _P, _D, _P, _P, _I]),
+    "laph_ptnet_backward": (_I, [_P, _P, _P, _D, _P, _P, _P, _P, _I]),
+    "laph_ptnet_train_step": (_I, [_P, _P, _P, _D, _P, _P, _I, ctypes.POINTER(laph_adam), ctypes.POINTER(_D)]),
     "laph_set_timing": (_I, [_P, _I]),
     "laph_get_timing": (_I, [_P, ctypes.POINTER(laph_timing), _I]),
 }
@@ -145,6 +158,15 @@ def _dptr(t, dtype=None):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _hptr(a):
+    """Host pointer of a contiguous float64 (or complex128) numpy array."""
+    import numpy as np
+
+    if not isinstance(a, np.ndarray) or not a.flags.c_contiguous or a.dtype not in (np.float64, np.complex128):
+        raise TypeError("expected a contiguous float64/complex128 numpy array")
+    return ctypes.c_void_p(a.ctypes.data)
+
+
 # ------------------------------------------------------------------ ABI names
 
 def laph_create(ns, nt, stream=None):
@@ -159,6 +181,10 @@ def laph_create(ns, nt, stream=None):
 
 def laph_destroy(ctx):
     _check(lib().laph_destroy(ctx))
+
+
+def laph_forget_gauge(ctx):
+    _check(lib().laph_forget_gauge(ctx), ctx)
 
 
 def laph_parse_dilution(text, nt, nv):
@@ -235,9 +261,93 @@ def laph_get_timing(ctx, reset=False):
 
 
 def solver_params(tol=1e-10, maxiter=20000, precision="f64", solver=LAPH_SOLVER_BICGSTAB, reliable_every=50,
-                  block_rhs=1, use_graph=0):
+                  block_rhs=1, use_graph=0, net=None, restart=0):
+    """laph_solver; `net` is a PTNet (or raw handle) used by LAPH_SOLVER_FGMRES."""
+    h = net.handle if isinstance(net, PTNet) else net
     return laph_solver(tol, maxiter, solver, PRECISIONS[precision] if isinstance(precision, str) else precision,
-                       reliable_every, block_rhs, use_graph, None)
+                       reliable_every, block_rhs, use_graph, h, restart)
+
+
+def laph_ptnet_create(ctx, channels, seed=0):
+    ch = (_I * len(channels))(*channels)
+    h = _P()
+    _check(lib().laph_ptnet_create(ctx, len(channels) - 1, ch, seed, ctypes.byref(h)), ctx)
+    return h
+
+
+def laph_ptnet_destroy(net):
+    _check(lib().laph_ptnet_destroy(net))
+
+
+def laph_ptnet_num_weights(net):
+    n = ctypes.c_size_t()
+    _check(lib().laph_ptnet_num_weights(net, ctypes.byref(n)))
+    return n.value
+
+
+def laph_ptnet_get_weights(net, w):
+    """w: host float64 numpy array of 2n (or n complex128)."""
+    _check(lib().laph_ptnet_get_weights(net, _hptr(w)))
+
+
+def laph_ptnet_set_weights(net, w):
+    _check(lib().laph_ptnet_set_weights(net, _hptr(w)))
+
+
+def laph_ptnet_forward(ctx, net, U, bc_t, x, out, n_fields=1):
+    _check(lib().laph_ptnet_forward(ctx, net, _dptr(U), bc_t, _dptr(x), _dptr(out), n_fields), ctx)
+
+
+def laph_ptnet_backward(ctx, net, U, bc_t, x, gout, gin, gw, n_fields=1):
+    _check(lib().laph_ptnet_backward(ctx, net, _dptr(U), bc_t, _dptr(x), _dptr(gout),
+                                     _dptr(gin) if gin is not None else None, _hptr(gw), n_fields), ctx)
+
+
+def laph_ptnet_train_step(ctx, net, U, bc_t, b, x, n_pairs, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                          loss_parity=-1):
+    loss = _D()
+    opt = laph_adam(lr, beta1, beta2, eps, loss_parity)
+    _check(lib().laph_ptnet_train_step(ctx, net, _dptr(U), bc_t, _dptr(b), _dptr(x), n_pairs, ctypes.byref(opt),
+                                       ctypes.byref(loss)), ctx)
+    return loss.value
+
+
+class PTNet:
+    """Owner of one learned-preconditioner network."""
+
+    def __init__(self, ctx, channels, seed=0):
+        self.channels = list(channels)
+        self.handle = laph_ptnet_create(ctx, self.channels, seed)
+
+    @property
+    def n_weights(self):
+        return laph_ptnet_num_weights(self.handle)
+
+    def get_weights(self):
+        import numpy as np
+
+        w = np.zeros(2 * self.n_weights)
+        laph_ptnet_get_weights(self.handle, w)
+        return w.view(np.complex128)
+
+    def set_weights(self, w):
+        import numpy as np
+
+        w = np.ascontiguousarray(np.asarray(w, dtype=np.complex128).reshape(-1))
+        if w.size != self.n_weights:
+            raise ValueError("expected %d complex weights, got %d" % (self.n_weights, w.size))
+        laph_ptnet_set_weights(self.handle, w.view(np.float64))
+
+    def close(self):
+        if self.handle:
+            laph_ptnet_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Lattice:

@@ -1,0 +1,41 @@
+// Gauge-equivariant parallel-transport network (learned preconditioner), internal API.
+//
+// Net layout of a batch of fields: float2 a[((r*C + c)*V + s)*12 + k] with s the
+// lexicographic site (x fastest) and k = alpha*3 + colour, i.e. the canonical spinor order
+// in FP32 with a channel axis.  Links: float2 [V][4][9] (canonical order, FP32).
+#pragma once
+
+#include "laph_impl.h"
+
+struct laph_ptnet {
+    int device = 0;
+    int layers = 0;
+    std::vector<int> ch;       // channels[0..layers], ch[0] = ch[layers] = 1
+    std::vector<size_t> woff;  // offset (complex elements) of each layer's weights
+    size_t nw = 0;             // total complex weights
+    int cmax = 1;              // widest layer
+    DevBuf w32;                // FP32 master weights (float2)
+    DevBuf wbf;                // BF16 working copy (uint32: bf16(re) | bf16(im) << 16)
+    DevBuf wadj;               // adjoint weights of one layer (uint32, BF16 pairs)
+    DevBuf m1, m2;             // Adam moments (float2)
+    DevBuf grad;               // weight gradients dL/dW^* (float2)
+    DevBuf gpart;              // per-block partial weight gradients (float2)
+    long step = 0;
+    DevBuf links;              // FP32 links of the field of the current call
+    const float2 *act0 = nullptr;  // input of the last forward pass that kept activations
+    std::vector<DevBuf> acts;      // inputs of layers 1.. kept for the backward pass
+    DevBuf tmp[2];             // ping-pong activations / gradients
+};
+
+// FP32 links of U for the net (converted on every call)
+void ptnet_links(laph_ctx *c, laph_ptnet *net, const double *U);
+// out = N(in) for nrhs fields in the net layout (1 channel in and out).  With keep != 0 the
+// layer inputs are kept for ptnet_backward.
+void ptnet_forward(laph_ctx *c, laph_ptnet *net, float bct, const float2 *in, float2 *out, int nrhs, int keep);
+// with g = dL/d(out)^* (net layout) after ptnet_forward(keep = 1): writes dL/dW^* into
+// net->grad and, if gin is not null, dL/d(in)^* into gin
+void ptnet_backward(laph_ctx *c, laph_ptnet *net, float bct, const float2 *g, float2 *gin, int nrhs);
+// even-odd FP64 half vector of one right-hand side ([12][Vh]) <-> net layout, other
+// parity zero / dropped
+void eo_to_net(laph_ctx *c, const double2 *half, int par, float2 *full);
+void net_to_eo(laph_ctx *c, const float2 *full, int par, double2 *half);

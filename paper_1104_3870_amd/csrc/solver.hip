@@ -13,7 +13,10 @@
 #include <cmath>
 #include <cstdlib>
 
+#include <complex>
+
 #include "dslash_mr.h"
+#include "ptnet.h"
 #include "spinor_io.h"
 
 namespace {
@@ -1109,6 +1112,215 @@ void full_residual(Work &w, const Op64 &hi, Vec be, Vec bo, Vec xe, Vec xo, Vec 
     }
 }
 
+// ------------------------------------------------------------------ flexible GMRES
+// One right-hand side, FP64 basis.  Kernels over n = 12 Vh complex numbers.
+constexpr int kFgBS = 256;
+
+// part[i][b] = sum over chunk b of conj(v_i) w, i = blockIdx.y (v_i at vb + i * n)
+__global__ __launch_bounds__(kFgBS) void k_fg_dots(const double2 *__restrict__ vb, const double2 *__restrict__ w,
+                                                   long n, long chunk, double2 *__restrict__ part)
+{
+    const double2 *v = vb + (size_t)blockIdx.y * n;
+    long beg = blockIdx.x * chunk, end = std::min(n, beg + chunk);
+    double re = 0, im = 0;
+    for (long e = beg + threadIdx.x; e < end; e += blockDim.x) {
+        double2 a = v[e], b = w[e];
+        re += a.x * b.x + a.y * b.y;
+        im += a.x * b.y - a.y * b.x;
+    }
+    __shared__ double sr[kFgBS], si[kFgBS];
+    sr[threadIdx.x] = re;
+    si[threadIdx.x] = im;
+    __syncthreads();
+    for (int h = kFgBS / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            sr[threadIdx.x] += sr[threadIdx.x + h];
+            si[threadIdx.x] += si[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = make_double2(sr[0], si[0]);
+}
+
+// w -= sum_i h_i v_i  (nv vectors at vb + i * n, h on the device)
+__global__ void k_fg_axpy(double2 *__restrict__ w, const double2 *__restrict__ vb, const double2 *__restrict__ h,
+                          int nv, long n)
+{
+    long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    double2 acc = w[e];
+    for (int i = 0; i < nv; i++) acc = csub(acc, cmul(h[i], vb[(size_t)i * n + e]));
+    w[e] = acc;
+}
+
+// dst = s (a - b)   (b may be null)
+__global__ void k_fg_lin(double2 *dst, const double2 *a, const double2 *b, double s, long n)
+{
+    long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    double2 v = a[e];
+    if (b) v = csub(v, b[e]);
+    dst[e] = cscale(v, s);
+}
+
+struct Fgmres {
+    laph_ctx *c;
+    const Op64 &hi;
+    laph_ptnet *net;
+    float bct;
+    long n;
+    int nblk;
+    long chunk;
+    double2 *part, *hdev;
+    std::vector<double2> hpart;
+
+    // h[i] = <v_i, w> for i < nv (host result, fixed summation order)
+    void dots(const double2 *vb, int nv, const double2 *w, std::vector<std::complex<double>> &h)
+    {
+        hipLaunchKernelGGL(k_fg_dots, dim3(nblk, nv), dim3(kFgBS), 0, c->stream, vb, w, n, chunk, part);
+        LAPH_HIP(hipGetLastError());
+        hpart.resize((size_t)nblk * nv);
+        LAPH_HIP(hipMemcpyAsync(hpart.data(), part, sizeof(double2) * hpart.size(), hipMemcpyDeviceToHost,
+                                c->stream));
+        LAPH_HIP(hipStreamSynchronize(c->stream));
+        h.assign(nv, 0.0);
+        for (int i = 0; i < nv; i++)
+            for (int b = 0; b < nblk; b++) h[i] += std::complex<double>(hpart[(size_t)i * nblk + b].x,
+                                                                          hpart[(size_t)i * nblk + b].y);
+    }
+    void axpy(double2 *w, const double2 *vb, const std::vector<std::complex<double>> &h)
+    {
+        std::vector<double2> hh(h.size());
+        for (size_t i = 0; i < h.size(); i++) hh[i] = make_double2(h[i].real(), h[i].imag());
+        LAPH_HIP(hipMemcpyAsync(hdev, hh.data(), sizeof(double2) * hh.size(), hipMemcpyHostToDevice, c->stream));
+        hipLaunchKernelGGL(k_fg_axpy, dim3(nblocks_for(n, 256)), dim3(256), 0, c->stream, w, vb, (const double2 *)hdev,
+                           (int)h.size(), n);
+        LAPH_HIP(hipGetLastError());
+        LAPH_HIP(hipStreamSynchronize(c->stream));  // hh is reused by the next call
+    }
+    double norm(const double2 *w)
+    {
+        std::vector<std::complex<double>> h;
+        dots(w, 1, w, h);
+        return std::sqrt(std::max(h[0].real(), 0.0));
+    }
+    void lin(double2 *dst, const double2 *a, const double2 *b, double s)
+    {
+        hipLaunchKernelGGL(k_fg_lin, dim3(nblocks_for(n, 256)), dim3(256), 0, c->stream, dst, a, b, s, n);
+        LAPH_HIP(hipGetLastError());
+    }
+    // z = P_o N(E_o A_oo v): the net approximates K^-1 and Mhat^-1 = (K^-1)_oo A_oo
+    void precondition(const double2 *v, double2 *z, double2 *tmp, float2 *na, float2 *nb)
+    {
+        launch_clover_apply<S64, C64>(c, hi.cl(1), v, nullptr, tmp, nullptr, hi.Vh, 1, 0, c->stream);
+        eo_to_net(c, tmp, 1, na);
+        ptnet_forward(c, net, bct, na, nb, 1, 0);
+        net_to_eo(c, nb, 1, z);
+    }
+};
+
+// Right-preconditioned flexible GMRES(m) (Saad) on Mhat x = bhat with classical Gram-Schmidt
+// applied twice; restarts recompute the FP64 residual.  Returns the iterations spent and
+// whether |bhat - Mhat x| <= tol_abs was reached.
+int fgmres(laph_ctx *c, const Op64 &hi, laph_ptnet *net, Vec bhat, Vec x, Vec r, double tol_abs, int maxiter,
+           int m, bool &reached)
+{
+    long Vh = c->g.Vh;
+    long n = 12 * Vh;
+    Fgmres f{c, hi, net, (float)c->dc.prm.bc_t, n, 0, 0, nullptr, nullptr, {}};
+    f.chunk = std::max<long>(kFgBS * 16, (n + 511) / 512);
+    f.chunk = (f.chunk + kFgBS - 1) / kFgBS * kFgBS;
+    f.nblk = (int)((n + f.chunk - 1) / f.chunk);
+    f.part = (double2 *)ctx_named(c, "fg.part", sizeof(double2) * f.nblk * (m + 1));
+    f.hdev = (double2 *)ctx_named(c, "fg.h", sizeof(double2) * (m + 1));
+    double2 *vb = (double2 *)ctx_named(c, "fg.V", sizeof(double2) * n * (m + 1));
+    double2 *zb = (double2 *)ctx_named(c, "fg.Z", sizeof(double2) * n * m);
+    double2 *tmp = (double2 *)ctx_named(c, "fg.tmp", sizeof(double2) * n);
+    float2 *na = (float2 *)ctx_named(c, "fg.na", sizeof(float2) * 12 * c->g.V);
+    float2 *nb = (float2 *)ctx_named(c, "fg.nb", sizeof(float2) * 12 * c->g.V);
+    double2 *xd = (double2 *)x.d, *rd = (double2 *)r.d;
+    using C = std::complex<double>;
+    int it = 0;
+    reached = false;
+    while (it < maxiter) {
+        hi.mhat(x, r);
+        f.lin(rd, (const double2 *)bhat.d, rd, 1.0);
+        double beta = f.norm(rd);
+        if (laph_verbose_level() > 1) fprintf(stderr, "[laph] fgmres it %d: |r| = %.3e (target %.3e)\n", it, beta, tol_abs);
+        if (!(beta > tol_abs)) {
+            reached = std::isfinite(beta);
+            break;
+        }
+        f.lin(vb, rd, nullptr, 1.0 / beta);
+        std::vector<std::vector<C>> H(m + 1, std::vector<C>(m, 0.0));
+        std::vector<double> cs(m);
+        std::vector<C> sn(m), g(m + 1, 0.0);
+        g[0] = beta;
+        int k = 0;
+        bool stop = false;
+        for (int j = 0; j < m && it < maxiter; j++) {
+            double2 *vj = vb + (size_t)j * n, *zj = zb + (size_t)j * n, *w = vb + (size_t)(j + 1) * n;
+            f.precondition(vj, zj, tmp, na, nb);
+            hi.mhat(Vec{zj}, Vec{w});
+            std::vector<C> h1, h2;
+            f.dots(vb, j + 1, w, h1);
+            f.axpy(w, vb, h1);
+            f.dots(vb, j + 1, w, h2);
+            f.axpy(w, vb, h2);
+            for (int i = 0; i <= j; i++) H[i][j] = h1[i] + h2[i];
+            double hn = f.norm(w);
+            H[j + 1][j] = hn;
+            it++;
+            k = j + 1;
+            if (hn > 0 && std::isfinite(hn)) f.lin(w, w, nullptr, 1.0 / hn);
+            for (int i = 0; i < j; i++) {  // previous rotations
+                C t = cs[i] * H[i][j] + sn[i] * H[i + 1][j];
+                H[i + 1][j] = -std::conj(sn[i]) * H[i][j] + cs[i] * H[i + 1][j];
+                H[i][j] = t;
+            }
+            C a = H[j][j];
+            double bb = hn, rr = std::sqrt(std::norm(a) + bb * bb);
+            if (std::abs(a) == 0.0) {
+                cs[j] = 0;
+                sn[j] = 1;
+            } else {
+                cs[j] = std::abs(a) / rr;
+                sn[j] = (a / std::abs(a)) * bb / rr;
+            }
+            H[j][j] = cs[j] * a + sn[j] * bb;
+            H[j + 1][j] = 0;
+            g[j + 1] = -std::conj(sn[j]) * g[j];
+            g[j] = cs[j] * g[j];
+            double est = std::abs(g[j + 1]);
+            if (!std::isfinite(est) || !(hn > 0)) {
+                stop = true;
+                break;
+            }
+            if (est <= tol_abs) break;
+        }
+        // y = H^-1 g (upper triangular), x += Z y
+        std::vector<C> y(k);
+        for (int i = k - 1; i >= 0; i--) {
+            C s2 = g[i];
+            for (int l = i + 1; l < k; l++) s2 -= H[i][l] * y[l];
+            y[i] = s2 / H[i][i];
+        }
+        bool finite = true;
+        for (auto &v : y) finite = finite && std::isfinite(v.real()) && std::isfinite(v.imag());
+        if (!finite) break;
+        for (auto &v : y) v = -v;
+        f.axpy(xd, zb, y);
+        if (stop) break;
+    }
+    if (it >= maxiter || !reached) {
+        hi.mhat(x, r);
+        f.lin(rd, (const double2 *)bhat.d, rd, 1.0);
+        double beta = f.norm(rd);
+        reached = std::isfinite(beta) && beta <= tol_abs;
+    }
+    return it;
+}
+
 template <class SP, class GP, class CP, class XP>
 void solve_batch(laph_ctx *c, const double *eta, double *x, int R, int nreal, const laph_solver *sv,
                  laph_solve_stats *stats)
@@ -1166,7 +1378,7 @@ void solve_batch(laph_ctx *c, const double *eta, double *x, int R, int nreal, co
     // BiCGStab broke down or diverged; the last attempt is plain FP64 CGNR.  After each
     // attempt the FP64 true residual of the full system decides, and an RHS that misses
     // the bar continues from its current x with a tighter even-odd target.
-    std::vector<int> bicg_failed(R, 0);
+    std::vector<int> bicg_failed(R, 0), fg_failed(R, 0);
     Vec reshi = w.make("reshi", 16, false);
     auto set_active = [&](auto pred) {
         int na = 0;
@@ -1182,6 +1394,14 @@ void solve_batch(laph_ctx *c, const double *eta, double *x, int R, int nreal, co
     for (int attempt = 0; attempt < 4; attempt++) {
         const bool last = attempt == 3;
         const char *what = "";
+        if (sv->solver == LAPH_SOLVER_FGMRES && !last && R == 1 && !done[0] && !fg_failed[0]) {
+            bool ok = false;
+            int m = sv->restart > 0 ? sv->restart : 24;
+            iters[0] += fgmres(c, hi, (laph_ptnet *)sv->net, bhat, xo, rhi, eo_tol[0] * std::sqrt(hs[0].b2),
+                               sv->maxiter, m, ok);
+            if (!ok) fg_failed[0] = 1;
+            what = "fgmres";
+        }
         if (sv->solver == LAPH_SOLVER_BICGSTAB && !last &&
             set_active([&](int q) { return !bicg_failed[q]; }) > 0) {
             true_eo_residual(w, hi, bhat, xo, tmp, rhi, 0);
@@ -1196,7 +1416,7 @@ void solve_batch(laph_ctx *c, const double *eta, double *x, int R, int nreal, co
             what = "bicgstab";
         }
         bool cg_all = sv->solver == LAPH_SOLVER_CGNR || last;
-        if (set_active([&](int q) { return cg_all || bicg_failed[q]; }) > 0) {
+        if (set_active([&](int q) { return cg_all || bicg_failed[q] || fg_failed[q]; }) > 0) {
             if (last)
                 cgnr<S64, G64, C64, S64>(w, hi, hi, bhat, xo, reshi, rhi, tmp, std::max(sv->maxiter, 5000), 0,
                                          check_every, hs);
@@ -1205,9 +1425,9 @@ void solve_batch(laph_ctx *c, const double *eta, double *x, int R, int nreal, co
                                      check_every, hs);
             read_scal(c, w.sc, hs);
             for (int q = 0; q < R; q++)
-                if (!done[q] && (cg_all || bicg_failed[q])) {
+                if (!done[q] && (cg_all || bicg_failed[q] || fg_failed[q])) {
                     iters[q] += hs[q].iters;
-                    if (sv->solver == LAPH_SOLVER_BICGSTAB || last) fallback[q] = 1;
+                    if (sv->solver != LAPH_SOLVER_CGNR || last) fallback[q] = 1;
                 }
             what = last ? "cgnr-fp64" : "cgnr";
         }
@@ -1325,9 +1545,18 @@ extern "C" int dirac_solve(laph_ctx_t c, const double *U, const laph_dirac *d, c
     check_dirac(d);
     LAPH_CHECK(sv->tol > 0 && sv->maxiter > 0, LAPH_EINVAL, "tol and maxiter must be positive");
     LAPH_CHECK(sv->precision >= LAPH_PREC_F64 && sv->precision <= LAPH_PREC_BF16, LAPH_EINVAL, "bad precision");
-    LAPH_CHECK(sv->solver == LAPH_SOLVER_BICGSTAB || sv->solver == LAPH_SOLVER_CGNR, LAPH_EINVAL,
-               "solver kind not available in this entry point");
+    LAPH_CHECK(sv->solver == LAPH_SOLVER_BICGSTAB || sv->solver == LAPH_SOLVER_CGNR ||
+                   sv->solver == LAPH_SOLVER_FGMRES,
+               LAPH_EINVAL, "unknown solver kind");
     int R = sv->block_rhs <= 0 ? 1 : sv->block_rhs;
+    if (sv->solver == LAPH_SOLVER_FGMRES) {
+        laph_ptnet *net = (laph_ptnet *)sv->net;
+        LAPH_CHECK(net && net->layers > 0, LAPH_EINVAL, "FGMRES needs a network");
+        LAPH_CHECK(net->device == c->device, LAPH_EINVAL, "network and context on different devices");
+        LAPH_CHECK(sv->restart >= 0 && sv->restart <= 256, LAPH_EINVAL, "restart must be in 0..256");
+        ptnet_links(c, net, U);
+        R = 1;  // one right-hand side at a time
+    }
     LAPH_CHECK(R <= 32 && (R & (R - 1)) == 0, LAPH_EINVAL, "block_rhs must be a power of two <= 32");
     bool low = sv->precision != LAPH_PREC_F64;
     dirac_prepare(c, U, d, low);

@@ -1,0 +1,240 @@
+"""GPU parallel-transport network and FGMRES against the oracle.
+
+The network is the learned preconditioner of the solve of Omega x = eta (not in the
+paper; Sec. IV's solve is what it accelerates).  The kernels compute in FP32 with BF16
+weights; the oracle runs the same BF16-valued weights in FP64, so the differences are
+FP32 rounding only: relative 2e-5 for outputs and input gradients (four layers of at most
+36 products per output), 1e-4 for weight gradients (sums over every site).  The solve is
+judged, as every solve, by the oracle's FP64 true residual <= 1e-10.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import dev, host, say
+from oracle import ptnet as onet
+
+pytestmark = pytest.mark.gpu
+
+CH = [1, 2, 4, 2, 1]
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1104_3870_amd as P
+
+    P.lib()
+    return P
+
+
+def bf16(a):
+    """Round to float32 then to bfloat16 (nearest even), returned as float64."""
+    f = np.ascontiguousarray(np.asarray(a, dtype=np.float64)).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def bf16c(w):
+    return bf16(w.real) + 1j * bf16(w.imag)
+
+
+def flat(ws):
+    return np.concatenate([w.reshape(-1) for w in ws])
+
+
+def make_net(P, L, ws):
+    net = P.PTNet(L.ctx, CH, seed=1)
+    net.set_weights(flat(ws))
+    return net
+
+
+def weights(seed, scale=0.2):
+    return [bf16c(w) for w in onet.init_weights(CH, seed=seed, scale=scale)]
+
+
+@pytest.mark.parametrize("ns,nt", [(4, 8), (6, 10)])
+def test_forward_parity(P, ns, nt):
+    import torch
+
+    say("ptnet forward", ns, nt)
+    L = P.Lattice(ns, nt)
+    U = synth.gauge_field(ns, nt, 0.4, 3)
+    psi = synth.random_spinor(ns, nt, 4, nrhs=3)
+    ws = weights(7)
+    net = make_net(P, L, ws)
+    out = torch.empty(psi.shape, dtype=torch.complex128, device="cuda")
+    P.laph_ptnet_forward(L.ctx, net.handle, dev(U), -1.0, dev(psi), out, 3)
+    got = host(out)
+    for r in range(3):
+        ref, _ = onet.forward(U, ws, psi[r], bc_t=-1.0)
+        err = np.abs(got[r] - ref).max() / np.abs(ref).max()
+        say("  rhs", r, "max rel err", err)
+        assert err < 2e-5
+    net.close()
+
+
+def test_backward_parity(P):
+    import torch
+
+    ns, nt = 4, 8
+    say("ptnet backward", ns, nt)
+    L = P.Lattice(ns, nt)
+    U = synth.gauge_field(ns, nt, 0.4, 5)
+    psi = synth.random_spinor(ns, nt, 6, nrhs=2)
+    gout = synth.random_spinor(ns, nt, 7, nrhs=2)
+    ws = weights(8)
+    net = make_net(P, L, ws)
+    gin = torch.empty(psi.shape, dtype=torch.complex128, device="cuda")
+    gw = np.zeros(2 * net.n_weights)
+    P.laph_ptnet_backward(L.ctx, net.handle, dev(U), -1.0, dev(psi), dev(gout), gin, gw, 2)
+    gw = gw.view(np.complex128)
+    ref_w = [np.zeros_like(w) for w in ws]
+    gi = host(gin)
+    for r in range(2):
+        _, acts = onet.forward(U, ws, psi[r])
+        g_in, g_w = onet.backward(U, ws, acts, gout[r])
+        err = np.abs(gi[r] - g_in).max() / np.abs(g_in).max()
+        say("  input gradient rhs", r, "max rel err", err)
+        assert err < 2e-5
+        for l in range(len(ws)):
+            ref_w[l] += g_w[l]
+    ref = flat(ref_w)
+    err = np.abs(gw - ref).max() / np.abs(ref).max()
+    say("  weight gradient max rel err", err)
+    assert err < 1e-4
+    net.close()
+
+
+def test_gauge_equivariance_large(P):
+    import torch
+
+    ns, nt = 8, 16
+    say("ptnet equivariance", ns, nt)
+    L = P.Lattice(ns, nt)
+    U = synth.gauge_field(ns, nt, 0.4, 9)
+    G = synth.gauge_transform_field(ns, nt, 10)
+    Ug = np.empty_like(U)
+    for mu in range(4):
+        Gp = np.roll(G, -1, axis=3 - mu)
+        Ug[..., mu, :, :] = G @ U[..., mu, :, :] @ np.conj(np.swapaxes(Gp, -1, -2))
+    psi = synth.random_spinor(ns, nt, 11)
+    psig = np.einsum("...ab,...sb->...sa", G, psi)
+    net = make_net(P, L, weights(12))
+    o1 = torch.empty(psi.shape, dtype=torch.complex128, device="cuda")
+    o2 = torch.empty(psi.shape, dtype=torch.complex128, device="cuda")
+    P.laph_ptnet_forward(L.ctx, net.handle, dev(U), -1.0, dev(psi), o1, 1)
+    P.laph_ptnet_forward(L.ctx, net.handle, dev(Ug), -1.0, dev(psig), o2, 1)
+    ref = np.einsum("...ab,...sb->...sa", G, host(o1))
+    err = np.abs(host(o2) - ref).max() / np.abs(ref).max()
+    say("  max rel err", err)
+    assert err < 2e-5
+    net.close()
+
+
+def test_train_step_matches_oracle_gradient(P):
+    import torch
+
+    ns, nt, npair, lr = 4, 8, 3, 1e-3
+    say("ptnet train step")
+    L = P.Lattice(ns, nt)
+    U = synth.gauge_field(ns, nt, 0.4, 13)
+    b = synth.random_spinor(ns, nt, 14, nrhs=npair)
+    x = synth.random_spinor(ns, nt, 15, nrhs=npair)
+    ws = weights(16)
+    net = make_net(P, L, ws)
+    w0 = net.get_weights()
+    loss = P.laph_ptnet_train_step(L.ctx, net.handle, dev(U), -1.0, dev(b), dev(x), npair, lr=lr, loss_parity=1)
+    w1 = net.get_weights()
+    # oracle loss and gradient of sum_r |N(b_r) - x_r|^2 / |x_r|^2 over odd sites
+    t, z, y, xx = np.meshgrid(*[np.arange(n) for n in (nt, ns, ns, ns)], indexing="ij")
+    odd = (((t + z + y + xx) & 1) == 1)[..., None, None]
+    tot, grads = 0.0, [np.zeros_like(w) for w in ws]
+    for r in range(npair):
+        out, acts = onet.forward(U, ws, b[r])
+        x2 = np.sum(np.abs(x[r] * odd) ** 2)
+        diff = (out - x[r]) * odd
+        tot += np.sum(np.abs(diff) ** 2) / x2
+        _, gw = onet.backward(U, ws, acts, diff / x2)
+        for l in range(len(ws)):
+            grads[l] += gw[l]
+    say("  loss", loss, "oracle", tot / npair)
+    assert abs(loss - tot / npair) <= 1e-5 * tot / npair
+    # first Adam step: delta = -lr g / (|g| + eps) per real component, g = 2 dL/dW^*
+    g = 2 * flat(grads)
+    dw = w1 - w0
+    for part in (np.real, np.imag):
+        gp, dp = part(g), part(dw)
+        big = np.abs(gp) > 1e-2 * np.abs(gp).max()
+        exp = -lr * np.sign(gp[big])
+        err = np.abs(dp[big] - exp).max()
+        say("  adam step max err", err)
+        assert err < 1e-3 * lr + 1e-6  # FP32 weights of size ~1: ulp 1.2e-7
+    net.close()
+
+
+def test_training_reduces_loss(P):
+    import torch
+
+    ns, nt, npair = 4, 8, 4
+    say("ptnet training loop")
+    L = P.Lattice(ns, nt)
+    U = synth.gauge_field(ns, nt, 0.4, 17)
+    b = synth.random_spinor(ns, nt, 18, nrhs=npair)
+    D = oracle.Dirac(U, 0.3, 3.5, 1.0, -1.0)
+    x = np.stack([D.solve(np.einsum("ab,...bc->...ac", oracle.gamma(3), b[r]), tol=1e-10)[0] for r in range(npair)])
+    net = P.PTNet(L.ctx, CH, seed=3)
+    Ud, bd, xd = dev(U), dev(b), dev(x)
+    losses = [P.laph_ptnet_train_step(L.ctx, net.handle, Ud, -1.0, bd, xd, npair, lr=3e-3) for _ in range(60)]
+    say("  loss", losses[0], "->", losses[-1])
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.8 * losses[0]
+    net.close()
+
+
+def _fgmres(P, cfg, U, etas, net, **kw):
+    import torch
+
+    L = P.Lattice(cfg.ns, cfg.nt)
+    prm = P.laph_dirac(cfg.m0, cfg.xi, cfg.csw, cfg.bc_t)
+    x = torch.empty(etas.shape, dtype=torch.complex128, device="cuda")
+    sv = P.solver_params(tol=1e-10, maxiter=2000, solver=P.LAPH_SOLVER_FGMRES, net=net, **kw)
+    st = P.dirac_solve(L.ctx, dev(U), prm, dev(etas), x, etas.shape[0], sv)
+    return host(x), st, L
+
+
+@pytest.mark.parametrize("restart", [0, 5])
+def test_fgmres_solve(P, restart):
+    cfg = synth.CONFIGS["cfg0"]
+    say("fgmres solve restart", restart)
+    U = synth.gauge_field(cfg.ns, cfg.nt, cfg.eps, cfg.seed)
+    D = oracle.Dirac(U, cfg.m0, cfg.xi, cfg.csw, cfg.bc_t)
+    etas = synth.random_spinor(cfg.ns, cfg.nt, 31, nrhs=2)
+    # a generic (untrained) net is still a valid right preconditioner of flexible GMRES
+    Lnet = P.Lattice(cfg.ns, cfg.nt)
+    net = P.PTNet(Lnet.ctx, CH, seed=4)
+    x, st, _ = _fgmres(P, cfg, U, etas, net, restart=restart)
+    for r in range(2):
+        tr = D.true_residual(etas[r], x[r])
+        say("  rhs", r, "iters", st[r].iters, "fallback", st[r].fallback_used, "oracle resid", tr)
+        assert st[r].status == 0 and st[r].fallback_used == 0
+        assert tr <= 1e-10
+    net.close()
+
+
+def test_fgmres_zero_net_falls_back(P):
+    cfg = synth.CONFIGS["cfg0"]
+    say("fgmres zero net")
+    U = synth.gauge_field(cfg.ns, cfg.nt, cfg.eps, cfg.seed)
+    D = oracle.Dirac(U, cfg.m0, cfg.xi, cfg.csw, cfg.bc_t)
+    etas = synth.random_spinor(cfg.ns, cfg.nt, 32, nrhs=1)
+    Lnet = P.Lattice(cfg.ns, cfg.nt)
+    net = P.PTNet(Lnet.ctx, CH, seed=4)
+    net.set_weights(np.zeros(net.n_weights, dtype=np.complex128))  # preconditioner returns 0
+    x, st, _ = _fgmres(P, cfg, U, etas, net)
+    tr = D.true_residual(etas[0], x[0])
+    say("  iters", st[0].iters, "fallback", st[0].fallback_used, "oracle resid", tr)
+    assert st[0].status == 0 and st[0].fallback_used == 1
+    assert tr <= 1e-10
+    net.close()

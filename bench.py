@@ -31,6 +31,28 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (profiles/traffic.json: FETCH_SIZE x its copy-kernel scale + WRITE_SIZE), or None when
+    there is none or the kernel's source has changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not kernel or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(kernel)
+    if not rec:
+        return None
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return {"bytes_per_launch": rec["bytes_per_launch"], "source": "profiles/traffic.json (%s)" % rec["profile"]}
+
+
 def cpu_baseline(cfg, U, evecs_np, dil_text, iters_sample, log_fn):
     """The oracle timed on a bounded sample of the same workload: its CG on the normal
     equations of Omega for source b = 0, `iters_sample` iterations, extrapolated to the
@@ -226,14 +248,21 @@ def main():
         log("learned: %d sources in %.2f s, iterations %s" % (nl, el, [q.iters for q in st]))
         net.close()
 
-    avg_ms = tm.dslash_ms / max(tm.dslash_launches, 1)
-    bytes_per_launch = tm.dslash_bytes / max(tm.dslash_launches, 1)
+    # roofline of the dominant kernel (largest summed duration in the timed region)
+    traffic = measured_traffic(tm[0]["kernel"] if tm else None)
+    dom = tm[0] if tm else {"kernel": "none", "ms": 0.0, "launches": 0, "bytes": 0.0}
+    avg_ms = dom["ms"] / max(dom["launches"], 1)
+    bytes_per_launch = dom["bytes"] / max(dom["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_dslash (even-odd hopping term, fused clover-inverse epilogue)",
-                "avg_launch_ms": round(avg_ms, 4), "launches": tm.dslash_launches,
-                "algorithmic_bytes_per_launch": bytes_per_launch}
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic["bytes_per_launch"] if traffic else None,
+                "traffic_source": traffic["source"] if traffic else None,
+                "kernel": dom["kernel"], "avg_launch_ms": round(avg_ms, 4), "launches": dom["launches"],
+                "algorithmic_bytes_per_launch": bytes_per_launch,
+                "share_of_timed_region": round(dom["ms"] / (1000 * elapsed), 3),
+                "other_kernels": [{"kernel": k["kernel"], "launches": k["launches"],
+                                   "avg_launch_ms": round(k["ms"] / max(k["launches"], 1), 4)} for k in tm[1:]]}
 
     cpu = None
     if args.cpu_iters > 0:

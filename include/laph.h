@@ -274,11 +274,18 @@ LAPH_API int sink_project(laph_ctx_t ctx, const double *evecs, int nv, const dou
 
 /* ----------------------------------------------------------------- profiling
  * With timing on, the library brackets every even-odd hopping kernel launch with HIP
- * events on its stream and accumulates their durations. */
+ * events on its stream and accumulates their durations per kernel variant. */
+#define LAPH_TIMING_KERNELS 8
 typedef struct {
-    double dslash_ms;     /* summed duration of hopping-term kernel launches */
-    long dslash_launches;
-    double dslash_bytes;  /* algorithmic bytes moved by those launches */
+    char kernel[48];  /* kernel and variant, e.g. "dslash_lds<f16,inv>" */
+    double ms;        /* summed duration of its launches */
+    long launches;
+    double bytes;     /* algorithmic bytes moved by those launches */
+} laph_kernel_timing;
+
+typedef struct {
+    int n;  /* entries used, ordered by decreasing summed duration */
+    laph_kernel_timing k[LAPH_TIMING_KERNELS];
 } laph_timing;
 
 LAPH_API int laph_set_timing(laph_ctx_t ctx, int enable);

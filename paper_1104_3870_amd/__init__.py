@@ -72,9 +72,13 @@ class laph_solve_stats(ctypes.Structure):
                 ("true_resid", ctypes.c_double)]
 
 
+class laph_kernel_timing(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_char * 48), ("ms", ctypes.c_double), ("launches", ctypes.c_long),
+                ("bytes", ctypes.c_double)]
+
+
 class laph_timing(ctypes.Structure):
-    _fields_ = [("dslash_ms", ctypes.c_double), ("dslash_launches", ctypes.c_long),
-                ("dslash_bytes", ctypes.c_double)]
+    _fields_ = [("n", ctypes.c_int), ("k", laph_kernel_timing * 8)]
 
 
 _lib = None
@@ -255,9 +259,11 @@ def laph_set_timing(ctx, enable):
 
 
 def laph_get_timing(ctx, reset=False):
+    """Per kernel variant: list of dicts {kernel, ms, launches, bytes}, by decreasing ms."""
     t = laph_timing()
     _check(lib().laph_get_timing(ctx, ctypes.byref(t), int(reset)), ctx)
-    return t
+    return [{"kernel": t.k[i].kernel.decode(), "ms": t.k[i].ms, "launches": t.k[i].launches,
+             "bytes": t.k[i].bytes} for i in range(t.n)]
 
 
 def solver_params(tol=1e-10, maxiter=20000, precision="f64", solver=LAPH_SOLVER_BICGSTAB, reliable_every=50,

@@ -1,4 +1,5 @@
 // Context, errors, device buffers, timing and the host-only dilution helpers.
+#include <algorithm>
 #include <cctype>
 #include <cstdarg>
 #include <cstdlib>
@@ -152,13 +153,25 @@ void timing_begin(laph_ctx *c, hipEvent_t *a, hipEvent_t *b)
     LAPH_HIP(hipEventRecord(*a, c->stream));
 }
 
-void timing_end(laph_ctx *c, hipEvent_t a, hipEvent_t b, double bytes)
+void timing_end(laph_ctx *c, hipEvent_t a, hipEvent_t b, double bytes, const char *label)
 {
     if (!a) return;
     LAPH_HIP(hipEventRecord(b, c->stream));
     c->pending.push_back({a, b});
     c->pending_bytes.push_back(bytes);
+    c->pending_label.push_back(label);
     if (c->pending.size() >= 512) timing_collect(c);
+}
+
+const char *timing_label(const char *kernel, const char *prec, int mode, int R)
+{
+    static std::map<std::string, std::string> names;
+    static const char *modes[] = {"plain", "inv", "inv_of_sum", "clov_add"};
+    char buf[96];
+    snprintf(buf, sizeof(buf), "%s<%s,%s,R%d>", kernel, prec, (mode >= 0 && mode < 4) ? modes[mode] : "?", R);
+    auto &v = names[buf];
+    if (v.empty()) v = buf;
+    return v.c_str();
 }
 
 void timing_collect(laph_ctx *c)
@@ -168,13 +181,15 @@ void timing_collect(laph_ctx *c)
     for (size_t k = 0; k < c->pending.size(); k++) {
         float ms = 0;
         LAPH_HIP(hipEventElapsedTime(&ms, c->pending[k].first, c->pending[k].second));
-        c->dslash_ms += ms;
-        c->dslash_launches += 1;
-        c->dslash_bytes += c->pending_bytes[k];
+        auto &acc = c->tacc[c->pending_label[k]];
+        acc.ms += ms;
+        acc.launches += 1;
+        acc.bytes += c->pending_bytes[k];
         c->event_pool.push_back(c->pending[k]);
     }
     c->pending.clear();
     c->pending_bytes.clear();
+    c->pending_label.clear();
 }
 
 extern "C" int laph_set_timing(laph_ctx_t c, int enable)
@@ -200,14 +215,17 @@ extern "C" int laph_get_timing(laph_ctx_t c, laph_timing *out, int reset)
     } catch (const LaphError &e) {
         return e.code;
     }
-    out->dslash_ms = c->dslash_ms;
-    out->dslash_launches = c->dslash_launches;
-    out->dslash_bytes = c->dslash_bytes;
-    if (reset) {
-        c->dslash_ms = 0;
-        c->dslash_launches = 0;
-        c->dslash_bytes = 0;
+    std::vector<std::pair<std::string, laph_ctx::TimeAcc>> v(c->tacc.begin(), c->tacc.end());
+    std::sort(v.begin(), v.end(), [](const auto &a, const auto &b) { return a.second.ms > b.second.ms; });
+    memset(out, 0, sizeof(*out));
+    out->n = (int)std::min<size_t>(v.size(), LAPH_TIMING_KERNELS);
+    for (int k = 0; k < out->n; k++) {
+        snprintf(out->k[k].kernel, sizeof(out->k[k].kernel), "%s", v[k].first.c_str());
+        out->k[k].ms = v[k].second.ms;
+        out->k[k].launches = v[k].second.launches;
+        out->k[k].bytes = v[k].second.bytes;
     }
+    if (reset) c->tacc.clear();
     return LAPH_OK;
 }
 

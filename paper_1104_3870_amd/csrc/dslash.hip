@@ -349,7 +349,9 @@ void launch_dslash(laph_ctx *c, int mode, const DslashArgs &a, hipStream_t st)
     }
     LAPH_HIP(hipGetLastError());
     bool has_x = a.x != nullptr && (mode != M_PLAIN || a.x);
-    timing_end(c, e0, e1, dslash_bytes(a.Vh, a.R, GP::bytes, CP::bytes, SP::bytes, SP::kNorm, mode, has_x));
+    if (e0)
+        timing_end(c, e0, e1, dslash_bytes(a.Vh, a.R, GP::bytes, CP::bytes, SP::bytes, SP::kNorm, mode, has_x),
+                   timing_label("dslash", SP::bytes == 16 ? "f64" : "f32", mode, a.R));
 }
 
 template <class SP, class CP>

@@ -7,6 +7,8 @@
 // the third row of an SU(3) matrix is conj(row0 x row1); 3 x 16-byte loads per link)
 // and the clover blocks are stored per site (18 x 16-byte loads).  Arithmetic is FP32.
 #include <cstdlib>
+#include <string>
+#include <type_traits>
 
 #include "dslash_mr.h"
 #include "spinor_io.h"
@@ -283,6 +285,321 @@ __global__ __launch_bounds__(256) LAPH_MR_ATTR void k_dslash_mr(const MrArgs P)
     store_site<SP, NR>((typename SP::E *)P.out, P.out_nrm, Vh, P.R, i, r0, res);
 }
 
+// ------------------------------------------------------------ LDS-staged variant
+// One block holds S sites x R right-hand sides, one lane per (site, right-hand side).  The
+// 8 S links of the block (hop weight, boundary factor and for M_PLAIN the output factor
+// folded in; backward links stored as their adjoint) and its S clover blocks are staged
+// in LDS once, so a lane does only the spin projection, one SU(3) product per direction
+// and the clover product, with explicit FMA chains.
+constexpr int kLkF4 = 5;  // float4 per staged link (18 floats used)
+
+__device__ __forceinline__ Cx<float> cmul_f(Cx<float> a, Cx<float> b)
+{
+    return {fmaf(-a.im, b.im, a.re * b.re), fmaf(a.im, b.re, a.re * b.im)};
+}
+__device__ __forceinline__ void cfma_f(Cx<float> &acc, Cx<float> a, Cx<float> b)  // acc += a b
+{
+    acc.re = fmaf(a.re, b.re, acc.re);
+    acc.re = fmaf(-a.im, b.im, acc.re);
+    acc.im = fmaf(a.re, b.im, acc.im);
+    acc.im = fmaf(a.im, b.re, acc.im);
+}
+__device__ __forceinline__ void cfmac_f(Cx<float> &acc, Cx<float> a, Cx<float> b)  // acc += conj(a) b
+{
+    acc.re = fmaf(a.re, b.re, acc.re);
+    acc.re = fmaf(a.im, b.im, acc.re);
+    acc.im = fmaf(a.re, b.im, acc.im);
+    acc.im = fmaf(-a.im, b.re, acc.im);
+}
+
+// raw (unscaled) spinor of one right-hand side and its scale
+template <class SP>
+__device__ __forceinline__ float ld_raw(const typename SP::E *base, const float *nrm, int R, long i, int r,
+                                        Cx<float> (&o)[4][3])
+{
+    Spin12<SP> pk = *reinterpret_cast<const Spin12<SP> *>(base + (i * R + r) * 12);
+#pragma unroll
+    for (int k = 0; k < 12; k++) o[k / 3][k % 3] = SP::ld(&pk.v[k], 0, 1.0f);
+    if constexpr (SP::kNorm)
+        return nrm[i * R + r];
+    else
+        return 1.0f;
+}
+
+// element k (alpha*3 + c) of a raw record as FP32 (no scale)
+template <class SP>
+__device__ __forceinline__ float lo_f(const typename SP::E &e)
+{
+    if constexpr (std::is_same<SP, S16>::value)
+        return __low2float(e);
+    else
+        return SP::ld(&e, 0, 1.0f).re;
+}
+template <class SP>
+__device__ __forceinline__ float hi_f(const typename SP::E &e)
+{
+    if constexpr (std::is_same<SP, S16>::value)
+        return __high2float(e);
+    else
+        return SP::ld(&e, 0, 1.0f).im;
+}
+
+// h = sc (a + K b) for K = KR + i KI in {+-1, +-i}; with FP16 storage every term is one
+// mixed-precision FMA (conversion and scale fused)
+template <class SP, int KR, int KI>
+__device__ __forceinline__ Cx<float> proj(const typename SP::E &a, const typename SP::E &b, float sc)
+{
+    const float are = lo_f<SP>(a), aim = hi_f<SP>(a), bre = lo_f<SP>(b), bim = hi_f<SP>(b);
+    if constexpr (KI == 0)
+        return {fmaf(are, sc, fmaf(bre, (float)KR * sc, 0.0f)), fmaf(aim, sc, fmaf(bim, (float)KR * sc, 0.0f))};
+    else
+        return {fmaf(are, sc, fmaf(bim, -(float)KI * sc, 0.0f)), fmaf(aim, sc, fmaf(bre, (float)KI * sc, 0.0f))};
+}
+
+template <int MU, bool FWD, class SP>
+__device__ __forceinline__ void hop_lds(const float4 *lk, const Spin12<SP> &sp, float sc, Cx<float> (&acc)[4][3])
+{
+    Cx<float> U[9];
+    {
+        float4 a = lk[0], b = lk[1], c = lk[2], d = lk[3], e = lk[4];
+        U[0] = {a.x, a.y};
+        U[1] = {a.z, a.w};
+        U[2] = {b.x, b.y};
+        U[3] = {b.z, b.w};
+        U[4] = {c.x, c.y};
+        U[5] = {c.z, c.w};
+        U[6] = {d.x, d.y};
+        U[7] = {d.z, d.w};
+        U[8] = {e.x, e.y};
+    }
+    const auto *v = sp.v;  // v[alpha * 3 + c]
+    constexpr int sg = FWD ? 1 : -1;
+    Cx<float> h0[3], h1[3], o0[3], o1[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        if (MU == 0) {
+            h0[c] = proj<SP, 0, sg>(v[c], v[9 + c], sc);
+            h1[c] = proj<SP, 0, sg>(v[3 + c], v[6 + c], sc);
+        } else if (MU == 1) {
+            h0[c] = proj<SP, sg, 0>(v[c], v[9 + c], sc);
+            h1[c] = proj<SP, -sg, 0>(v[3 + c], v[6 + c], sc);
+        } else if (MU == 2) {
+            h0[c] = proj<SP, 0, sg>(v[c], v[6 + c], sc);
+            h1[c] = proj<SP, 0, -sg>(v[3 + c], v[9 + c], sc);
+        } else {
+            h0[c] = proj<SP, -sg, 0>(v[c], v[6 + c], sc);
+            h1[c] = proj<SP, -sg, 0>(v[3 + c], v[9 + c], sc);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        o0[a] = cmul_f(U[a * 3], h0[0]);
+        cfma_f(o0[a], U[a * 3 + 1], h0[1]);
+        cfma_f(o0[a], U[a * 3 + 2], h0[2]);
+        o1[a] = cmul_f(U[a * 3], h1[0]);
+        cfma_f(o1[a], U[a * 3 + 1], h1[1]);
+        cfma_f(o1[a], U[a * 3 + 2], h1[2]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        acc[0][c] = acc[0][c] + o0[c];
+        acc[1][c] = acc[1][c] + o1[c];
+        if (MU == 0) {
+            acc[2][c] = acc[2][c] + (FWD ? timesMinusI(o1[c]) : timesI(o1[c]));
+            acc[3][c] = acc[3][c] + (FWD ? timesMinusI(o0[c]) : timesI(o0[c]));
+        } else if (MU == 1) {
+            acc[2][c] = FWD ? acc[2][c] - o1[c] : acc[2][c] + o1[c];
+            acc[3][c] = FWD ? acc[3][c] + o0[c] : acc[3][c] - o0[c];
+        } else if (MU == 2) {
+            acc[2][c] = acc[2][c] + (FWD ? timesMinusI(o0[c]) : timesI(o0[c]));
+            acc[3][c] = acc[3][c] + (FWD ? timesI(o1[c]) : timesMinusI(o1[c]));
+        } else {
+            acc[2][c] = FWD ? acc[2][c] - o0[c] : acc[2][c] + o0[c];
+            acc[3][c] = FWD ? acc[3][c] - o1[c] : acc[3][c] + o1[c];
+        }
+    }
+}
+
+// neighbour record: 32-bit element offset (site * R + r) of the input field
+template <int MU, bool FWD, class SP>
+__device__ __forceinline__ void dir_lds(const MrArgs &P, const float4 *slk, int nb, int R, int r,
+                                        Cx<float> (&acc)[4][3])
+{
+    const auto *in = (const typename SP::E *)P.in;
+    const int rec = nb * R + r;
+    Spin12<SP> sp = *reinterpret_cast<const Spin12<SP> *>(in + (size_t)rec * 12);
+    float sc = 1.0f;
+    if constexpr (SP::kNorm) sc = P.in_nrm[rec];
+    hop_lds<MU, FWD, SP>(slk + (FWD ? MU : 4 + MU) * kLkF4, sp, sc, acc);
+}
+
+__device__ __forceinline__ void clover_one(const float4 *p, const Cx<float> (&in)[4][3], Cx<float> (&out)[4][3])
+{
+#pragma unroll
+    for (int blk = 0; blk < 2; blk++) {
+        float e[36];
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            float4 v = p[blk * 9 + k];
+            e[4 * k] = v.x;
+            e[4 * k + 1] = v.y;
+            e[4 * k + 2] = v.z;
+            e[4 * k + 3] = v.w;
+        }
+        Cx<float> v[6], o[6];
+#pragma unroll
+        for (int s = 0; s < 2; s++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) v[s * 3 + c] = in[blk * 2 + s][c];
+#pragma unroll
+        for (int k = 0; k < 6; k++) o[k] = e[k] * v[k];
+        int idx = 6;
+#pragma unroll
+        for (int rr = 1; rr < 6; rr++)
+#pragma unroll
+            for (int c = 0; c < rr; c++) {
+                Cx<float> L = {e[idx], e[idx + 1]};
+                idx += 2;
+                cfma_f(o[rr], L, v[c]);
+                cfmac_f(o[c], L, v[rr]);
+            }
+#pragma unroll
+        for (int s = 0; s < 2; s++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) out[blk * 2 + s][c] = o[s * 3 + c];
+    }
+}
+
+// sites per block for R right-hand sides (block = S R lanes)
+__host__ __device__ inline int lds_sites(int R) { return R >= 4 ? 256 / R : 64; }
+inline size_t lds_bytes(int R) { return (size_t)lds_sites(R) * (8 * kLkF4 + 18) * sizeof(float4); }
+
+template <class SP, int MODE>
+__global__ __launch_bounds__(256) void k_dslash_lds(const MrArgs P)
+{
+    extern __shared__ float4 smem[];
+    const int R = P.R;
+    const int S = lds_sites(R);
+    float4 *slk = smem;                 // [S][8][kLkF4]
+    float4 *scl = smem + S * 8 * kLkF4;  // [S][18]
+    const long Vh = P.Vh;
+    const int ns = P.ns, nt = P.nt, par = P.par, opar = par ^ 1;
+    const long site0 = (long)xcd_block(blockIdx.x, gridDim.x) * S;
+    const float4 *lk = (const float4 *)P.links;
+    const float fout = MODE == M_INV_AFTER ? 1.0f : (float)P.c;  // folded into the links
+    for (int k = threadIdx.x; k < S * 8; k += blockDim.x) {
+        const int sl = k >> 3, d = k & 7, mu = d & 3;
+        const long i = site0 + sl;
+        if (i >= Vh) continue;
+        int x, y, z, t;
+        cb_coords(i, par, ns, x, y, z, t);
+        float w = fout * (mu == 3 ? (float)P.wt : (float)P.ws);
+        long li;
+        if (d < 4) {
+            if (mu == 3 && t + 1 == nt) w *= (float)P.bct;
+            li = (long)(mu * 2 + par) * Vh + i;
+        } else {
+            int xx = x, yy = y, zz = z, tt = t;
+            if (mu == 0) xx = x == 0 ? ns - 1 : x - 1;
+            else if (mu == 1) yy = y == 0 ? ns - 1 : y - 1;
+            else if (mu == 2) zz = z == 0 ? ns - 1 : z - 1;
+            else {
+                tt = t == 0 ? nt - 1 : t - 1;
+                if (t == 0) w *= (float)P.bct;
+            }
+            li = (long)(mu * 2 + opar) * Vh + (lex_index(xx, yy, zz, tt, ns) >> 1);
+        }
+        Cx<float> U[9];
+        load_link12(lk, li, U);
+        float f[20];
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++) {
+                Cx<float> u = d < 4 ? U[a * 3 + b] : Cx<float>{U[b * 3 + a].re, -U[b * 3 + a].im};
+                f[2 * (a * 3 + b)] = w * u.re;
+                f[2 * (a * 3 + b) + 1] = w * u.im;
+            }
+        f[18] = f[19] = 0.0f;
+        float4 *dst = slk + (size_t)k * kLkF4;
+#pragma unroll
+        for (int q = 0; q < kLkF4; q++) dst[q] = make_float4(f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]);
+    }
+    if constexpr (MODE == M_INV_AFTER) {
+        const float4 *cl = (const float4 *)P.clov;
+        const float cc = (float)P.c;
+        for (int k = threadIdx.x; k < S * 18; k += blockDim.x) {
+            if (site0 + k / 18 >= Vh) continue;
+            float4 v = cl[site0 * 18 + k];
+            scl[k] = make_float4(cc * v.x, cc * v.y, cc * v.z, cc * v.w);
+        }
+    }
+    __syncthreads();
+    const int sl = threadIdx.x / R, r = threadIdx.x - sl * R;
+    if (sl >= S || site0 + sl >= Vh) return;
+    // 32-bit site arithmetic (the host checks Vh * R * 12 < 2^31): neighbour checkerboard
+    // indices from the site's own, lex = 2 cb + (x & 1) since Ns is even
+    const int cb = (int)(site0 + sl);
+    int x, y, z, t;
+    cb_coords(cb, par, ns, x, y, z, t);
+    const int sy = ns >> 1, sz = sy * ns, st = sz * ns;
+    const int xo = x & 1;
+    const int nxp = (x + 1 < ns) ? cb + xo : cb + 1 - sy;
+    const int nxm = (x > 0) ? cb - 1 + xo : cb + sy - 1;
+    const int nyp = (y + 1 < ns) ? cb + sy : cb - (ns - 1) * sy;
+    const int nym = (y > 0) ? cb - sy : cb + (ns - 1) * sy;
+    const int nzp = (z + 1 < ns) ? cb + sz : cb - (ns - 1) * sz;
+    const int nzm = (z > 0) ? cb - sz : cb + (ns - 1) * sz;
+    const int ntp = (t + 1 < nt) ? cb + st : cb - (nt - 1) * st;
+    const int ntm = (t > 0) ? cb - st : cb + (nt - 1) * st;
+    const long i = cb;
+    Cx<float> acc[4][3];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) acc[a][c] = {0.0f, 0.0f};
+    const float4 *my = slk + (size_t)sl * 8 * kLkF4;
+    dir_lds<0, true, SP>(P, my, nxp, R, r, acc);
+    dir_lds<0, false, SP>(P, my, nxm, R, r, acc);
+    dir_lds<1, true, SP>(P, my, nyp, R, r, acc);
+    dir_lds<1, false, SP>(P, my, nym, R, r, acc);
+    dir_lds<2, true, SP>(P, my, nzp, R, r, acc);
+    dir_lds<2, false, SP>(P, my, nzm, R, r, acc);
+    dir_lds<3, true, SP>(P, my, ntp, R, r, acc);
+    dir_lds<3, false, SP>(P, my, ntm, R, r, acc);
+    if (P.g5d) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            acc[2][c] = cneg(acc[2][c]);
+            acc[3][c] = cneg(acc[3][c]);
+        }
+    }
+    Cx<float> res[4][3];
+    if constexpr (MODE == M_INV_AFTER) {
+        clover_one(scl + (size_t)sl * 18, acc, res);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) res[a][c] = acc[a][c];
+    }
+    if (P.x) {
+        Cx<float> xv[4][3];
+        float sx = (float)P.a * ld_raw<SP>((const typename SP::E *)P.x, P.x_nrm, R, i, r, xv);
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                res[a][c].re = fmaf(sx, xv[a][c].re, res[a][c].re);
+                res[a][c].im = fmaf(sx, xv[a][c].im, res[a][c].im);
+            }
+    }
+    Cx<float> v[12];
+#pragma unroll
+    for (int k = 0; k < 12; k++) v[k] = res[k / 3][k % 3];
+    st_spinor12<SP, float>((typename SP::E *)P.out, P.out_nrm, Vh, R, i, r, v);
+}
+
 // out = A x with optional gamma_5 on x (local, per-site clover)
 template <class SP, int NR>
 __global__ __launch_bounds__(256) void k_clover_mr(const float4 *__restrict__ cl, const typename SP::E *__restrict__ x,
@@ -356,8 +673,40 @@ double dslash_mr_bytes(long Vh, int R, int sbytes, bool has_norm, int mode, bool
 }
 
 template <class SP>
+constexpr const char *prec_name()
+{
+    return std::is_same<SP, S16>::value ? "f16" : std::is_same<SP, SB16>::value ? "bf16" : "f32";
+}
+
+// hopping kernel: the LDS-staged variant unless LAPH_MR_KERNEL=0 selects the per-lane one
+static bool use_lds_kernel()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("LAPH_MR_KERNEL");
+        v = (e && *e == '0') ? 0 : 1;
+    }
+    return v == 1;
+}
+
+template <class SP>
 void launch_dslash_mr(laph_ctx *c, int mode, const MrArgs &a, hipStream_t st)
 {
+    if (use_lds_kernel() && a.Vh * a.R * 12 < (1L << 31)) {
+        const int S = lds_sites(a.R);
+        dim3 grid(nblocks_for(a.Vh, S)), block(S * a.R);
+        hipEvent_t e0, e1;
+        timing_begin(c, &e0, &e1);
+        if (mode == M_INV_AFTER)
+            hipLaunchKernelGGL((k_dslash_lds<SP, M_INV_AFTER>), grid, block, lds_bytes(a.R), st, a);
+        else
+            hipLaunchKernelGGL((k_dslash_lds<SP, M_PLAIN>), grid, block, lds_bytes(a.R), st, a);
+        LAPH_HIP(hipGetLastError());
+        if (e0)
+            timing_end(c, e0, e1, dslash_mr_bytes(a.Vh, a.R, SP::bytes, SP::kNorm, mode, a.x != nullptr),
+                   timing_label("dslash_lds", prec_name<SP>(), mode, a.R));
+        return;
+    }
     int NR = pick_nr(a.R);
     long n = a.Vh * (a.R / NR);
     dim3 grid(nblocks_for(n, 256)), block(256);
@@ -377,7 +726,9 @@ void launch_dslash_mr(laph_ctx *c, int mode, const MrArgs &a, hipStream_t st)
     }
 #undef LAPH_MR
     LAPH_HIP(hipGetLastError());
-    timing_end(c, e0, e1, dslash_mr_bytes(a.Vh, a.R, SP::bytes, SP::kNorm, mode, a.x != nullptr));
+    if (e0)
+        timing_end(c, e0, e1, dslash_mr_bytes(a.Vh, a.R, SP::bytes, SP::kNorm, mode, a.x != nullptr),
+               timing_label("dslash_mr", prec_name<SP>(), mode, a.R));
 }
 
 template <class SP>

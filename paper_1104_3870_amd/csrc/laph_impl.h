@@ -156,13 +156,15 @@ struct laph_ctx {
     DiracCache dc;
     std::map<std::string, DevBuf> bufs;  // named scratch buffers, grown on demand
     // timing
+    struct TimeAcc {
+        double ms = 0, bytes = 0;
+        long launches = 0;
+    };
     bool timing = false;
-    double dslash_ms = 0;
-    long dslash_launches = 0;
-    double dslash_bytes = 0;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::map<std::string, TimeAcc> tacc;  // per kernel variant
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;  // recorded, not yet read
     std::vector<double> pending_bytes;
+    std::vector<const char *> pending_label;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
 };
 
@@ -191,8 +193,10 @@ void stout_smear_device(laph_ctx *c, const double *U, double rho, int nsteps, do
 
 // timing
 void timing_begin(laph_ctx *c, hipEvent_t *a, hipEvent_t *b);
-void timing_end(laph_ctx *c, hipEvent_t a, hipEvent_t b, double bytes);
+void timing_end(laph_ctx *c, hipEvent_t a, hipEvent_t b, double bytes, const char *label);
 void timing_collect(laph_ctx *c);
+// stable name "kernel<prec,mode,R>" for timing_end (mode: M_* of dslash.h)
+const char *timing_label(const char *kernel, const char *prec, int mode, int R);
 
 // launch helper
 inline unsigned nblocks_for(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }

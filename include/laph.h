@@ -191,8 +191,9 @@ typedef struct {
     int precision;      /* LAPH_PREC_*: storage precision of the inner Krylov vectors;
                            FP64 reliable updates are used for every lower precision */
     int reliable_every; /* iterations between FP64 reliable updates (mixed precision) */
-    int block_rhs;      /* right-hand sides iterated together (1..32); 0 = autotune */
-    int use_graph;      /* capture the iteration in HIP graphs */
+    int block_rhs;      /* right-hand sides iterated together (power of two <= 32); 0 = the
+                           block size laph_autotune picks (run on first use) */
+    int use_graph;      /* replay the CG iteration body from a HIP graph (not with timing on) */
     const void *net;    /* learned preconditioner (laph_ptnet_t) for LAPH_SOLVER_FGMRES */
     int restart;        /* FGMRES restart length (0: 24) */
 } laph_solver;
@@ -264,6 +265,29 @@ typedef struct {
 LAPH_API int laph_ptnet_train_step(laph_ctx_t ctx, laph_ptnet_t net, const double *U, double bc_t,
                                    const double *b, const double *x, int n_pairs,
                                    const laph_adam *opt, double *loss);
+
+/* ---------------------------------------------------------------- autotuning
+ * Times the even-odd hopping kernel with its fused clover-inverse epilogue on the
+ * prepared operator of (U, dirac) for every block size R (4..32 for the low precisions,
+ * 1..32 for FP64) and, for the low precisions, every tile of S sites x R lanes
+ * (S R = 64, 128, 256).  The context keeps the fastest tile per R and the R with the
+ * lowest time per right-hand side; dirac_solve with block_rhs = 0 uses them. */
+#define LAPH_TUNE_MAX 24
+typedef struct {
+    int block_rhs;
+    int sites_per_block; /* 0 for FP64 */
+    double ms_per_rhs;   /* per launch and right-hand side */
+} laph_tune_entry;
+
+typedef struct {
+    int n;
+    laph_tune_entry e[LAPH_TUNE_MAX];
+    int best_block_rhs;
+    int best_sites_per_block;
+} laph_tune_report;
+
+LAPH_API int laph_autotune(laph_ctx_t ctx, const double *U, const laph_dirac *dirac, int precision,
+                           laph_tune_report *report);
 
 /* ----------------------------------------------------------- sink projection
  * coef[r][t][alpha][n] = sum_{x,c} conj(V_{t,n}(x,c)) X_r(x,t,c,alpha): the quark

@@ -62,6 +62,15 @@ class laph_solver(ctypes.Structure):
                 ("use_graph", ctypes.c_int), ("net", ctypes.c_void_p), ("restart", ctypes.c_int)]
 
 
+class laph_tune_entry(ctypes.Structure):
+    _fields_ = [("block_rhs", ctypes.c_int), ("sites_per_block", ctypes.c_int), ("ms_per_rhs", ctypes.c_double)]
+
+
+class laph_tune_report(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("e", laph_tune_entry * 24), ("best_block_rhs", ctypes.c_int),
+                ("best_sites_per_block", ctypes.c_int)]
+
+
 class laph_adam(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
                 ("eps", ctypes.c_double), ("loss_parity", ctypes.c_int)]
@@ -116,6 +125,7 @@ EXPORTS = {
     "laph_ptnet_forward": (_I, [_P, _P, _P, _D, _P, _P, _I]),
     "laph_ptnet_backward": (_I, [_P, _P, _P, _D, _P, _P, _P, _P, _I]),
     "laph_ptnet_train_step": (_I, [_P, _P, _P, _D, _P, _P, _I, ctypes.POINTER(laph_adam), ctypes.POINTER(_D)]),
+    "laph_autotune": (_I, [_P, _P, ctypes.POINTER(laph_dirac), _I, ctypes.POINTER(laph_tune_report)]),
     "laph_set_timing": (_I, [_P, _I]),
     "laph_get_timing": (_I, [_P, ctypes.POINTER(laph_timing), _I]),
 }
@@ -252,6 +262,15 @@ def dirac_solve(ctx, U, dirac, eta, x, n_rhs, solver, raise_on_noconv=True):
 
 def sink_project(ctx, evecs, nv, X, n_rhs, coef):
     _check(lib().sink_project(ctx, _dptr(evecs), nv, _dptr(X), n_rhs, _dptr(coef)), ctx)
+
+
+def laph_autotune(ctx, U, dirac, precision="f16"):
+    """Tune the block size and LDS tile of the hopping kernel; returns the report as a dict."""
+    rep = laph_tune_report()
+    prec = PRECISIONS[precision] if isinstance(precision, str) else precision
+    _check(lib().laph_autotune(ctx, _dptr(U), ctypes.byref(dirac), prec, ctypes.byref(rep)), ctx)
+    return {"entries": [(rep.e[i].block_rhs, rep.e[i].sites_per_block, rep.e[i].ms_per_rhs) for i in range(rep.n)],
+            "best_block_rhs": rep.best_block_rhs, "best_sites_per_block": rep.best_sites_per_block}
 
 
 def laph_set_timing(ctx, enable):

@@ -87,6 +87,7 @@ extern "C" int laph_destroy(laph_ctx_t c)
     (void)hipStreamSynchronize(c->stream);
     free_dirac_cache(c->dc);
     for (auto &kv : c->bufs) ctx_free(kv.second);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto &p : c->event_pool) {
         (void)hipEventDestroy(p.first);
         (void)hipEventDestroy(p.second);

@@ -34,3 +34,6 @@ void launch_clover_mr(laph_ctx *c, const void *cl, const void *x, const float *x
 void build_lp_operator(laph_ctx *c, const double2 *g64, const double *clinv64, float4 *links12, float *clinv_aos);
 
 double dslash_mr_bytes(long Vh, int R, int sbytes, bool has_norm, int mode, bool has_x);
+
+// sites per block of the LDS-staged hopping kernel for (precision, R); S R <= 256 lanes
+int lds_tile_sites(laph_ctx *c, int prec, int R);

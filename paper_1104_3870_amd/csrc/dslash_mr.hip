@@ -471,15 +471,14 @@ __device__ __forceinline__ void clover_one(const float4 *p, const Cx<float> (&in
 }
 
 // sites per block for R right-hand sides (block = S R lanes)
-__host__ __device__ inline int lds_sites(int R) { return R >= 4 ? 256 / R : 64; }
-inline size_t lds_bytes(int R) { return (size_t)lds_sites(R) * (8 * kLkF4 + 18) * sizeof(float4); }
+inline size_t lds_bytes(int S) { return (size_t)S * (8 * kLkF4 + 18) * sizeof(float4); }
 
 template <class SP, int MODE>
 __global__ __launch_bounds__(256) void k_dslash_lds(const MrArgs P)
 {
     extern __shared__ float4 smem[];
     const int R = P.R;
-    const int S = lds_sites(R);
+    const int S = blockDim.x / R;  // sites per block
     float4 *slk = smem;                 // [S][8][kLkF4]
     float4 *scl = smem + S * 8 * kLkF4;  // [S][18]
     const long Vh = P.Vh;
@@ -673,6 +672,20 @@ double dslash_mr_bytes(long Vh, int R, int sbytes, bool has_norm, int mode, bool
 }
 
 template <class SP>
+constexpr int prec_id()
+{
+    return std::is_same<SP, S16>::value ? LAPH_PREC_F16 : std::is_same<SP, SB16>::value ? LAPH_PREC_BF16 : LAPH_PREC_F32;
+}
+
+// sites per block of the LDS-staged kernel: the tuned value, else 256 / R lanes per block
+int lds_tile_sites(laph_ctx *c, int prec, int R)
+{
+    auto it = c->lds_tile.find({prec, R});
+    if (it != c->lds_tile.end()) return it->second;
+    return R >= 4 ? 256 / R : 64;
+}
+
+template <class SP>
 constexpr const char *prec_name()
 {
     return std::is_same<SP, S16>::value ? "f16" : std::is_same<SP, SB16>::value ? "bf16" : "f32";
@@ -693,14 +706,14 @@ template <class SP>
 void launch_dslash_mr(laph_ctx *c, int mode, const MrArgs &a, hipStream_t st)
 {
     if (use_lds_kernel() && a.Vh * a.R * 12 < (1L << 31)) {
-        const int S = lds_sites(a.R);
+        const int S = lds_tile_sites(c, prec_id<SP>(), a.R);
         dim3 grid(nblocks_for(a.Vh, S)), block(S * a.R);
         hipEvent_t e0, e1;
         timing_begin(c, &e0, &e1);
         if (mode == M_INV_AFTER)
-            hipLaunchKernelGGL((k_dslash_lds<SP, M_INV_AFTER>), grid, block, lds_bytes(a.R), st, a);
+            hipLaunchKernelGGL((k_dslash_lds<SP, M_INV_AFTER>), grid, block, lds_bytes(S), st, a);
         else
-            hipLaunchKernelGGL((k_dslash_lds<SP, M_PLAIN>), grid, block, lds_bytes(a.R), st, a);
+            hipLaunchKernelGGL((k_dslash_lds<SP, M_PLAIN>), grid, block, lds_bytes(S), st, a);
         LAPH_HIP(hipGetLastError());
         if (e0)
             timing_end(c, e0, e1, dslash_mr_bytes(a.Vh, a.R, SP::bytes, SP::kNorm, mode, a.x != nullptr),

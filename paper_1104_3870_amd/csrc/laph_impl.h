@@ -155,6 +155,11 @@ struct laph_ctx {
     std::string err;
     DiracCache dc;
     std::map<std::string, DevBuf> bufs;  // named scratch buffers, grown on demand
+    // autotuning: LDS tile (sites per block) per (precision, R) and the chosen R per
+    // precision (0: not tuned)
+    std::map<std::pair<int, int>, int> lds_tile;
+    std::map<int, int> tuned_R;
+    hipStream_t cap_stream = nullptr;  // capture stream for HIP graphs (default priority)
     // timing
     struct TimeAcc {
         double ms = 0, bytes = 0;

@@ -811,6 +811,7 @@ struct Work {
     int R;
     Scal *sc;      // device
     double *part;  // device partials [kMaxBlocks][R][4]
+    bool use_graph = false;  // capture the CG iteration body in a HIP graph
     Vec make(const char *name, int bytes, bool norm)
     {
         Vec v;
@@ -988,16 +989,55 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
     // lower precisions test the update rule after every iteration: between two tests the
     // recursive residual must not fall far below what the storage precision can follow
     if (!plain) check_every = 1;
+    // one iteration: q = M p, alpha, y = M^dag q, x/res/r updates, beta (plain: and p)
+    auto body = [&](const Op<SP, GP, CP> &op) {
+        op.mhat(p, q);
+        launch_red(c, k_normsq<SP>, n, q, w.Vh, w.R, w.part);
+        launch_fin(c, k_fin_cg_alpha, w.R, (const double *)w.part, nblk, w.R, w.sc);
+        op.mhat_dag(q, y, to);
+        launch_red(c, k_cg_update<SP, XP>, n, xlo, p, res, q, r, y, w.Vh, w.R, w.part, (const Scal *)w.sc);
+        launch_fin(c, k_fin_cg_beta, w.R, (const double *)w.part, nblk, w.R, w.sc, plain ? 1 : 0);
+        if (plain) launch_el(c, k_cg_p<SP>, n, p, r, w.Vh, w.R, (const Scal *)w.sc);
+    };
+    hipGraphExec_t gexec = nullptr;
+    const bool graph_ok = w.use_graph && !c->timing;
+    if (graph_ok && !c->cap_stream) LAPH_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    struct GraphGuard {
+        hipGraphExec_t &g;
+        ~GraphGuard()
+        {
+            if (g) (void)hipGraphExecDestroy(g);
+        }
+    } guard{gexec};
     for (int it = 0; it < maxiter;) {
         int chunk = std::min(check_every, maxiter - it);
         for (int k = 0; k < chunk; k++) {
-            lo.mhat(p, q);
-            launch_red(c, k_normsq<SP>, n, q, w.Vh, w.R, w.part);
-            launch_fin(c, k_fin_cg_alpha, w.R, (const double *)w.part, nblk, w.R, w.sc);
-            lo.mhat_dag(q, y, to);
-            launch_red(c, k_cg_update<SP, XP>, n, xlo, p, res, q, r, y, w.Vh, w.R, w.part, (const Scal *)w.sc);
-            launch_fin(c, k_fin_cg_beta, w.R, (const double *)w.part, nblk, w.R, w.sc, plain ? 1 : 0);
-            if (plain) launch_el(c, k_cg_p<SP>, n, p, r, w.Vh, w.R, (const Scal *)w.sc);
+            if (gexec) {
+                LAPH_HIP(hipGraphLaunch(gexec, c->stream));
+            } else if (graph_ok) {
+                // record the body once on the capture stream, then replay it
+                hipStream_t main = c->stream;
+                bool timing = c->timing;
+                Op<SP, GP, CP> cap = lo;
+                cap.st = c->cap_stream;
+                c->stream = c->cap_stream;
+                c->timing = false;
+                hipGraph_t g = nullptr;
+                hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
+                if (e == hipSuccess) {
+                    body(cap);
+                    e = hipStreamEndCapture(c->cap_stream, &g);
+                }
+                c->stream = main;
+                c->timing = timing;
+                LAPH_HIP(e);
+                e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                LAPH_HIP(e);
+                LAPH_HIP(hipGraphLaunch(gexec, c->stream));
+            } else {
+                body(lo);
+            }
         }
         it += chunk;
         since += chunk;
@@ -1321,6 +1361,102 @@ int fgmres(laph_ctx *c, const Op64 &hi, laph_ptnet *net, Vec bhat, Vec x, Vec r,
     return it;
 }
 
+// ------------------------------------------------------------------ autotuning
+// Times the even-odd hopping kernel (fused clover-inverse epilogue, the launch that
+// dominates an iteration) for every block size R and, for the LDS-staged kernel, every
+// tile of S sites x R lanes with S R in {64, 128, 256}; keeps the fastest tile per R and
+// the R with the lowest time per right-hand side.
+template <class SP, class GP, class CP>
+std::vector<laph_tune_entry> tune_hopping(laph_ctx *c, int prec)
+{
+    DiracCache &dc = c->dc;
+    const long Vh = c->g.Vh;
+    const bool low = !std::is_same<SP, S64>::value;
+    std::vector<int> Rs = low ? std::vector<int>{4, 8, 16, 32} : std::vector<int>{1, 2, 4, 8, 16, 32};
+    std::vector<laph_tune_entry> out;
+    hipEvent_t e0, e1;
+    LAPH_HIP(hipEventCreate(&e0));
+    LAPH_HIP(hipEventCreate(&e1));
+    const bool timing = c->timing;
+    c->timing = false;
+    double best = 1e300;
+    int bestR = Rs.back();
+    try {
+        for (int R : Rs) {
+            Work w{c, Vh, R, nullptr, nullptr};
+            Vec in = w.make("tune.in", SP::bytes, SP::kNorm), o = w.make("tune.out", SP::bytes, SP::kNorm);
+            Vec x = w.make("tune.x", SP::bytes, SP::kNorm), te = w.make("tune.te", SP::bytes, SP::kNorm);
+            for (Vec v : {in, x}) {
+                LAPH_HIP(hipMemsetAsync(v.d, 0, (size_t)12 * Vh * R * SP::bytes, c->stream));
+                if (v.n) LAPH_HIP(hipMemsetAsync(v.n, 0, (size_t)Vh * R * 4, c->stream));
+            }
+            Op<SP, GP, CP> op{c, c->stream, Vh, R,
+                              std::is_same<GP, G64>::value ? dc.g64.p : nullptr,
+                              std::is_same<CP, C64>::value ? (const char *)dc.clinv.p : nullptr,
+                              nullptr, -0.5 / dc.prm.xi, -0.5, dc.prm.bc_t, te};
+            op.lk12 = (const float4 *)dc.lk12.p;
+            op.claos = (const float4 *)dc.claos.p;
+            std::vector<int> Ss;
+            if (low)
+                for (int S = std::max(1, 64 / R); S * R <= 256; S *= 2) Ss.push_back(S);
+            else
+                Ss.push_back(0);
+            int bestS = Ss.front();
+            double bestR_ms = 1e300;
+            for (int S : Ss) {
+                if (low) c->lds_tile[{prec, R}] = S;
+                op.dslash(M_INV_AFTER, 1, in, o, &x, 1.0, -1.0, 0);  // warm-up
+                const int reps = 3;
+                LAPH_HIP(hipEventRecord(e0, c->stream));
+                for (int k = 0; k < reps; k++) op.dslash(M_INV_AFTER, 1, in, o, &x, 1.0, -1.0, 0);
+                LAPH_HIP(hipEventRecord(e1, c->stream));
+                LAPH_HIP(hipEventSynchronize(e1));
+                float ms = 0;
+                LAPH_HIP(hipEventElapsedTime(&ms, e0, e1));
+                double per = ms / reps / R;
+                out.push_back(laph_tune_entry{R, S, per});
+                if (per < bestR_ms) {
+                    bestR_ms = per;
+                    bestS = S;
+                }
+            }
+            if (low) c->lds_tile[{prec, R}] = bestS;
+            if (bestR_ms < best) {
+                best = bestR_ms;
+                bestR = R;
+            }
+        }
+    } catch (...) {
+        c->timing = timing;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    c->timing = timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (const char *nm : {"slv.tune.in", "slv.tune.out", "slv.tune.x", "slv.tune.te", "slv.tune.in.n",
+                           "slv.tune.out.n", "slv.tune.x.n", "slv.tune.te.n"}) {
+        auto it = c->bufs.find(nm);
+        if (it != c->bufs.end()) {
+            ctx_free(it->second);
+            c->bufs.erase(it);
+        }
+    }
+    c->tuned_R[prec] = bestR;
+    return out;
+}
+
+std::vector<laph_tune_entry> tune_for(laph_ctx *c, int prec)
+{
+    switch (prec) {
+    case LAPH_PREC_F64: return tune_hopping<S64, G64, C64>(c, prec);
+    case LAPH_PREC_F32: return tune_hopping<S32, G32, C32>(c, prec);
+    case LAPH_PREC_F16: return tune_hopping<S16, G32, C32>(c, prec);
+    default: return tune_hopping<SB16, G32, C32>(c, prec);
+    }
+}
+
 template <class SP, class GP, class CP, class XP>
 void solve_batch(laph_ctx *c, const double *eta, double *x, int R, int nreal, const laph_solver *sv,
                  laph_solve_stats *stats)
@@ -1328,6 +1464,7 @@ void solve_batch(laph_ctx *c, const double *eta, double *x, int R, int nreal, co
     long Vh = c->g.Vh;
     DiracCache &dc = c->dc;
     Work w{c, Vh, R, nullptr, nullptr};
+    w.use_graph = sv->use_graph != 0;
     w.sc = (Scal *)ctx_named(c, "slv.scal", sizeof(Scal) * R);
     w.part = (double *)ctx_named(c, "slv.part", sizeof(double) * kMaxBlocks * R * 4);
 
@@ -1548,7 +1685,8 @@ extern "C" int dirac_solve(laph_ctx_t c, const double *U, const laph_dirac *d, c
     LAPH_CHECK(sv->solver == LAPH_SOLVER_BICGSTAB || sv->solver == LAPH_SOLVER_CGNR ||
                    sv->solver == LAPH_SOLVER_FGMRES,
                LAPH_EINVAL, "unknown solver kind");
-    int R = sv->block_rhs <= 0 ? 1 : sv->block_rhs;
+    LAPH_CHECK(sv->block_rhs >= 0, LAPH_EINVAL, "block_rhs must be >= 0");
+    int R = sv->block_rhs;
     if (sv->solver == LAPH_SOLVER_FGMRES) {
         laph_ptnet *net = (laph_ptnet *)sv->net;
         LAPH_CHECK(net && net->layers > 0, LAPH_EINVAL, "FGMRES needs a network");
@@ -1557,9 +1695,13 @@ extern "C" int dirac_solve(laph_ctx_t c, const double *U, const laph_dirac *d, c
         ptnet_links(c, net, U);
         R = 1;  // one right-hand side at a time
     }
-    LAPH_CHECK(R <= 32 && (R & (R - 1)) == 0, LAPH_EINVAL, "block_rhs must be a power of two <= 32");
+    LAPH_CHECK(R <= 32 && (R & (R - 1)) == 0, LAPH_EINVAL, "block_rhs must be 0 or a power of two <= 32");
     bool low = sv->precision != LAPH_PREC_F64;
     dirac_prepare(c, U, d, low);
+    if (R == 0) {
+        if (!c->tuned_R.count(sv->precision)) tune_for(c, sv->precision);
+        R = c->tuned_R[sv->precision];
+    }
     long V = c->g.V;
     int first_err = LAPH_OK;
     for (int base = 0; base < n_rhs; base += R) {
@@ -1599,5 +1741,24 @@ extern "C" int dirac_solve(laph_ctx_t c, const double *U, const laph_dirac *d, c
     }
     LAPH_HIP(hipStreamSynchronize(c->stream));
     if (first_err != LAPH_OK) return first_err;
+    LAPH_API_END(c)
+}
+
+extern "C" int laph_autotune(laph_ctx_t c, const double *U, const laph_dirac *d, int precision,
+                             laph_tune_report *rep)
+{
+    LAPH_API_BEGIN(c)
+    g_current_ctx = c;
+    LAPH_CHECK(U && rep, LAPH_EINVAL, "null pointer");
+    check_dirac(d);
+    LAPH_CHECK(precision >= LAPH_PREC_F64 && precision <= LAPH_PREC_BF16, LAPH_EINVAL, "bad precision");
+    dirac_prepare(c, U, d, precision != LAPH_PREC_F64);
+    std::vector<laph_tune_entry> e = tune_for(c, precision);
+    memset(rep, 0, sizeof(*rep));
+    rep->n = (int)std::min<size_t>(e.size(), LAPH_TUNE_MAX);
+    for (int k = 0; k < rep->n; k++) rep->e[k] = e[k];
+    rep->best_block_rhs = c->tuned_R[precision];
+    rep->best_sites_per_block =
+        precision == LAPH_PREC_F64 ? 0 : lds_tile_sites(c, precision, rep->best_block_rhs);
     LAPH_API_END(c)
 }

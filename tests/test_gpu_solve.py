@@ -132,3 +132,42 @@ def test_tiny_tails_low_precision(P, prec, solver):
     # the exact solution falls below the FP32 normal range far from the source
     x64 = D.solve(eta[0], tol=1e-13)[0]
     assert np.abs(x64[nt // 2]).max() < 1e-30
+
+
+@pytest.mark.parametrize("prec", ["f16", "f64"])
+def test_autotune_report(P, setup, prec):
+    cfg, U, D, etas, xs = setup
+    say("autotune", prec)
+    L = P.Lattice(cfg.ns, cfg.nt)
+    prm = P.laph_dirac(cfg.m0, cfg.xi, cfg.csw, cfg.bc_t)
+    rep = P.laph_autotune(L.ctx, dev(U), prm, prec)
+    say("  best R", rep["best_block_rhs"], "S", rep["best_sites_per_block"], "entries", len(rep["entries"]))
+    Rs = sorted({e[0] for e in rep["entries"]})
+    if prec == "f64":
+        assert Rs == [1, 2, 4, 8, 16, 32] and all(e[1] == 0 for e in rep["entries"])
+    else:
+        assert Rs == [4, 8, 16, 32] and len(rep["entries"]) == 12
+        assert all(e[0] * e[1] in (64, 128, 256) for e in rep["entries"])
+        best = [e for e in rep["entries"] if e[0] == rep["best_block_rhs"] and e[1] == rep["best_sites_per_block"]]
+        assert len(best) == 1
+    assert all(e[2] > 0 for e in rep["entries"])
+    assert rep["best_block_rhs"] in Rs
+    # the tuned block size is what block_rhs = 0 uses; the answer is judged as always
+    x, st = _solve(P, cfg, U, etas, precision=prec, block_rhs=0, solver=P.LAPH_SOLVER_CGNR)
+    for r in range(etas.shape[0]):
+        assert st[r].status == 0 and D.true_residual(etas[r], x[r]) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ["f16", "f64"])
+def test_graph_replay_matches_eager(P, setup, prec):
+    cfg, U, D, etas, xs = setup
+    say("graph replay", prec)
+    kw = dict(precision=prec, block_rhs=4, solver=P.LAPH_SOLVER_CGNR)
+    x0, s0 = _solve(P, cfg, U, etas[:4], use_graph=0, **kw)
+    for rep in range(2):  # two solves, each replaying its captured iteration many times
+        x1, s1 = _solve(P, cfg, U, etas[:4], use_graph=1, **kw)
+        say("  iters eager", [q.iters for q in s0], "graph", [q.iters for q in s1])
+        assert [q.iters for q in s0] == [q.iters for q in s1]
+        assert np.array_equal(x0, x1)
+    for r in range(4):
+        assert D.true_residual(etas[r], x1[r]) <= 1e-10

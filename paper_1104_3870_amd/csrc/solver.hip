@@ -537,7 +537,9 @@ __global__ void k_fin_cg_alpha(const double *partial, int nblk, int R, Scal *sc)
 }
 
 // x += alpha p; res -= alpha q; r -= alpha y;  partial |r|^2, |res|^2
-template <class SP, class XP>
+// kRes = false: the even-odd residual is not carried as a vector; its norm follows
+// |res'|^2 = |res|^2 - alpha |r|^2 (k_fin_cg_beta) between reliable updates
+template <class SP, class XP, bool kRes>
 __global__ __launch_bounds__(kBS) void k_cg_update(Vec x, Vec p, Vec res, Vec q, Vec r, Vec y, long Vh, int R,
                                                    double *partial, const Scal *sc)
 {
@@ -555,14 +557,16 @@ __global__ __launch_bounds__(kBS) void k_cg_update(Vec x, Vec p, Vec res, Vec q,
 #pragma unroll
         for (int k = 0; k < 12; k++) a[k] = a[k] + al * b[k];
         st_site<XP>(x, Vh, R, i, rr, a);
-        ld_site<SP>(res, Vh, R, i, rr, a);
-        ld_site<SP>(q, Vh, R, i, rr, b);
+        if constexpr (kRes) {
+            ld_site<SP>(res, Vh, R, i, rr, a);
+            ld_site<SP>(q, Vh, R, i, rr, b);
 #pragma unroll
-        for (int k = 0; k < 12; k++) a[k] = a[k] - al * b[k];
-        st_site<SP>(res, Vh, R, i, rr, a);
-        ld_site<SP>(res, Vh, R, i, rr, a);
+            for (int k = 0; k < 12; k++) a[k] = a[k] - al * b[k];
+            st_site<SP>(res, Vh, R, i, rr, a);
+            ld_site<SP>(res, Vh, R, i, rr, a);
 #pragma unroll
-        for (int k = 0; k < 12; k++) acc[1] += a[k].re * a[k].re + a[k].im * a[k].im;
+            for (int k = 0; k < 12; k++) acc[1] += a[k].re * a[k].re + a[k].im * a[k].im;
+        }
         ld_site<SP>(r, Vh, R, i, rr, a);
         ld_site<SP>(y, Vh, R, i, rr, b);
 #pragma unroll
@@ -577,7 +581,7 @@ __global__ __launch_bounds__(kBS) void k_cg_update(Vec x, Vec p, Vec res, Vec q,
 
 // beta = |r|^2 / rho; rho = |r|^2; r2 = |res|^2; with hi_conv the recursive even-odd
 // residual alone may declare convergence (plain FP64 iteration)
-__global__ void k_fin_cg_beta(const double *partial, int nblk, int R, Scal *sc, int hi_conv)
+__global__ void k_fin_cg_beta(const double *partial, int nblk, int R, Scal *sc, int hi_conv, int recur)
 {
     int r = blockIdx.x;
     double s[2];
@@ -589,7 +593,8 @@ __global__ void k_fin_cg_beta(const double *partial, int nblk, int R, Scal *sc, 
         return;
     }
     q.iters += 1;
-    q.r2 = s[1];
+    // rho still holds the previous |r|^2 here
+    q.r2 = recur ? fmax(q.r2 - q.alpha.x * q.rho.x, 0.0) : s[1];
     if (!std::isfinite(s[0]) || !std::isfinite(s[1]) || !(q.rho.x > 0)) {
         q.breakdown = 1;
         q.active = 0;
@@ -661,6 +666,41 @@ __global__ __launch_bounds__(kBS) void k_orth_p(Vec p, Vec r, long Vh, int R, co
 #pragma unroll
     for (int k = 0; k < 12; k++) pv[k] = pv[k] - a * rv[k];
     st_site<SP>(p, Vh, R, i, rr, pv);
+}
+
+// b = convert(a) (FP64 -> storage precision) for active right-hand sides
+template <class SP>
+__global__ __launch_bounds__(kBS) void k_convert_masked(Vec a, Vec b, long Vh, int R, const Scal *sc)
+{
+    long n = Vh * R;
+    long tid = blockIdx.x * (long)kBS + threadIdx.x;
+    if (tid >= n) return;
+    long i = tid / R;
+    int rr = (int)(tid - i * R);
+    if (!sc[rr].active) return;
+    Cx<double> v[12];
+    ld_site<S64>(a, Vh, R, i, rr, v);
+    st_site<SP>(b, Vh, R, i, rr, v);
+}
+
+// partial |a|^2, |b|^2 per right-hand side
+template <class SP>
+__global__ __launch_bounds__(kBS) void k_normsq2(Vec a, Vec b, long Vh, int R, double *partial)
+{
+    double acc[2] = {0, 0};
+    long n = Vh * R, stride = (long)gridDim.x * kBS;
+    int rr = (int)((blockIdx.x * (long)kBS + threadIdx.x) % R);
+    for (long tid = blockIdx.x * (long)kBS + threadIdx.x; tid < n; tid += stride) {
+        long i = tid / R;
+        Cx<double> v[12];
+        ld_site<SP>(a, Vh, R, i, rr, v);
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[0] += v[k].re * v[k].re + v[k].im * v[k].im;
+        ld_site<SP>(b, Vh, R, i, rr, v);
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[1] += v[k].re * v[k].re + v[k].im * v[k].im;
+    }
+    block_partial<2>(acc, R, partial);
 }
 
 // r = convert(rhi), res = convert(reshi) for masked RHS; partial |r|^2, |res|^2
@@ -995,8 +1035,11 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
         launch_red(c, k_normsq<SP>, n, q, w.Vh, w.R, w.part);
         launch_fin(c, k_fin_cg_alpha, w.R, (const double *)w.part, nblk, w.R, w.sc);
         op.mhat_dag(q, y, to);
-        launch_red(c, k_cg_update<SP, XP>, n, xlo, p, res, q, r, y, w.Vh, w.R, w.part, (const Scal *)w.sc);
-        launch_fin(c, k_fin_cg_beta, w.R, (const double *)w.part, nblk, w.R, w.sc, plain ? 1 : 0);
+        if (plain)
+            launch_red(c, k_cg_update<SP, XP, true>, n, xlo, p, res, q, r, y, w.Vh, w.R, w.part, (const Scal *)w.sc);
+        else
+            launch_red(c, k_cg_update<SP, XP, false>, n, xlo, p, res, q, r, y, w.Vh, w.R, w.part, (const Scal *)w.sc);
+        launch_fin(c, k_fin_cg_beta, w.R, (const double *)w.part, nblk, w.R, w.sc, plain ? 1 : 0, plain ? 0 : 1);
         if (plain) launch_el(c, k_cg_p<SP>, n, p, r, w.Vh, w.R, (const Scal *)w.sc);
     };
     hipGraphExec_t gexec = nullptr;
@@ -1062,9 +1105,13 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
             // reliable update between the residual and the direction update: fold the
             // increment, replace r and res by FP64 residuals, take beta from the new |r|^2
             // and keep the old direction orthogonal to the new residual
+            // FP64 true residual of the even-odd system; the normal residual M^dag res is
+            // computed by the low-precision operator, in which r is stored anyway
             launch_el(c, k_fold_x<XP>, n, xhi, xlo, w.Vh, w.R, (const Scal *)w.sc, 0);
-            refresh();
-            launch_red(c, k_cg_replace<SP>, n, rhi, reshi, r, res, w.Vh, w.R, w.part, (const Scal *)w.sc);
+            true_eo_residual(w, hi, bhat, xhi, tmp64, reshi, 0);
+            launch_el(c, k_convert_masked<SP>, n, reshi, res, w.Vh, w.R, (const Scal *)w.sc);
+            lo.mhat_dag(res, r, to);
+            launch_red(c, k_normsq2<SP>, n, r, res, w.Vh, w.R, w.part);
             launch_fin(c, k_fin_cg_reset, w.R, (const double *)w.part, nblk, w.R, w.sc);
             launch_red(c, k_dot<SP>, n, r, p, w.Vh, w.R, w.part);
             launch_fin(c, k_fin_orth, w.R, (const double *)w.part, nblk, w.R, w.sc);

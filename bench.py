@@ -109,6 +109,9 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1, help="batches timed with the plain FP64 solver")
     ap.add_argument("--cpu-iters", type=int, default=8, help="oracle CG iterations in the CPU sample (0: skip)")
     ap.add_argument("--m0", type=float, default=None)
+    ap.add_argument("--reliable-delta", type=float, default=0.03,
+                    help="reliable-update threshold (measured best on this workload; library default 0.1)")
+    ap.add_argument("--reliable-every", type=int, default=50)
     ap.add_argument("--learned-sources", type=int, default=2,
                     help="sources solved with FGMRES and the learned preconditioner (0: skip)")
     args = ap.parse_args()
@@ -166,7 +169,7 @@ def main():
 
     kind = P.LAPH_SOLVER_CGNR if args.solver == "cgnr" else P.LAPH_SOLVER_BICGSTAB
     best = P.solver_params(tol=cfg.solve_tol, maxiter=6000, precision=args.precision, block_rhs=args.block,
-                           solver=kind)
+                           solver=kind, reliable_every=args.reliable_every, reliable_delta=args.reliable_delta)
     plain = P.solver_params(tol=cfg.solve_tol, maxiter=6000, precision="f64", block_rhs=1, solver=kind)
     t_setup = time.time() - t_setup
 

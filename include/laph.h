@@ -190,12 +190,15 @@ typedef struct {
                            (Sec. IV), CGNR only, or FGMRES with a learned preconditioner */
     int precision;      /* LAPH_PREC_*: storage precision of the inner Krylov vectors;
                            FP64 reliable updates are used for every lower precision */
-    int reliable_every; /* iterations between FP64 reliable updates (mixed precision) */
+    int reliable_every; /* most iterations between FP64 reliable updates (mixed precision) */
     int block_rhs;      /* right-hand sides iterated together (power of two <= 32); 0 = the
                            block size laph_autotune picks (run on first use) */
     int use_graph;      /* replay the CG iteration body from a HIP graph (not with timing on) */
     const void *net;    /* learned preconditioner (laph_ptnet_t) for LAPH_SOLVER_FGMRES */
     int restart;        /* FGMRES restart length (0: 24) */
+    double reliable_delta; /* mixed precision: FP64 reliable update as soon as the iterated
+                              even-odd residual fell below this fraction of its last FP64
+                              value (0: 0.1), and at the latest every reliable_every iterations */
 } laph_solver;
 
 typedef struct {

@@ -219,6 +219,12 @@ __device__ __forceinline__ void do_dir(const MrArgs &P, const float4 *lk, int x,
 #else
 #define LAPH_MR_ATTR
 #endif
+// the LDS-staged kernel: at most 128 VGPRs, 4 waves per SIMD (measured 1-4 % faster than
+// 3 waves at 133 VGPRs despite a few spilled registers)
+#ifndef LAPH_LDS_WAVES
+#define LAPH_LDS_WAVES 4
+#endif
+#define LAPH_LDS_ATTR __attribute__((amdgpu_waves_per_eu(LAPH_LDS_WAVES)))
 
 template <class SP, int NR, int MODE>
 __global__ __launch_bounds__(256) LAPH_MR_ATTR void k_dslash_mr(const MrArgs P)
@@ -474,7 +480,7 @@ __device__ __forceinline__ void clover_one(const float4 *p, const Cx<float> (&in
 inline size_t lds_bytes(int S) { return (size_t)S * (8 * kLkF4 + 18) * sizeof(float4); }
 
 template <class SP, int MODE>
-__global__ __launch_bounds__(256) void k_dslash_lds(const MrArgs P)
+__global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P)
 {
     extern __shared__ float4 smem[];
     const int R = P.R;

@@ -852,6 +852,7 @@ struct Work {
     Scal *sc;      // device
     double *part;  // device partials [kMaxBlocks][R][4]
     bool use_graph = false;  // capture the CG iteration body in a HIP graph
+    double delta2 = 0.01;    // reliable update when |res|^2 fell below delta2 times its last FP64 value
     Vec make(const char *name, int bytes, bool norm)
     {
         Vec v;
@@ -919,7 +920,7 @@ void bicgstab(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec x
     int since = 0;
     // a reliable update also follows every drop of the iterated residual by kDelta since
     // the last one, which bounds the error the low-precision recursion can accumulate
-    const double kDelta2 = 0.1 * 0.1;
+    const double kDelta2 = w.delta2;
     read_scal(c, w.sc, hs);
     std::vector<double> r2_last(w.R), r2_min(w.R);
     for (int q = 0; q < w.R; q++) r2_last[q] = r2_min[q] = hs[q].r2;
@@ -1018,7 +1019,7 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
     refresh();
     launch_red(c, k_cg_init<SP, XP>, n, rhi, reshi, r, p, res, xlo, w.Vh, w.R, w.part, (const Scal *)w.sc, 1);
     launch_fin(c, k_fin_cg_init, w.R, (const double *)w.part, nblk, w.R, w.sc);
-    const double kDelta2 = 0.1 * 0.1;
+    const double kDelta2 = w.delta2;
     read_scal(c, w.sc, hs);
     if (laph_verbose())
         fprintf(stderr, "[laph] cgnr init rhs0: active=%d r2hi=%.3e rho=%.3e r2=%.3e b2=%.3e tol2=%.3e\n", hs[0].active,
@@ -1512,6 +1513,7 @@ void solve_batch(laph_ctx *c, const double *eta, double *x, int R, int nreal, co
     DiracCache &dc = c->dc;
     Work w{c, Vh, R, nullptr, nullptr};
     w.use_graph = sv->use_graph != 0;
+    if (sv->reliable_delta > 0) w.delta2 = sv->reliable_delta * sv->reliable_delta;
     w.sc = (Scal *)ctx_named(c, "slv.scal", sizeof(Scal) * R);
     w.part = (double *)ctx_named(c, "slv.part", sizeof(double) * kMaxBlocks * R * 4);
 
@@ -1728,6 +1730,7 @@ extern "C" int dirac_solve(laph_ctx_t c, const double *U, const laph_dirac *d, c
     LAPH_CHECK(U && eta && x && sv && n_rhs > 0, LAPH_EINVAL, "null pointer or n_rhs <= 0");
     check_dirac(d);
     LAPH_CHECK(sv->tol > 0 && sv->maxiter > 0, LAPH_EINVAL, "tol and maxiter must be positive");
+    LAPH_CHECK(sv->reliable_delta >= 0 && sv->reliable_delta < 1, LAPH_EINVAL, "reliable_delta must be in [0, 1)");
     LAPH_CHECK(sv->precision >= LAPH_PREC_F64 && sv->precision <= LAPH_PREC_BF16, LAPH_EINVAL, "bad precision");
     LAPH_CHECK(sv->solver == LAPH_SOLVER_BICGSTAB || sv->solver == LAPH_SOLVER_CGNR ||
                    sv->solver == LAPH_SOLVER_FGMRES,

@@ -30,7 +30,8 @@ struct S64 {
 };
 struct S32 {
     static constexpr bool kAoS = true;
-    __host__ __device__ static long idx(int k, long i, int r, long Vh, int R) { return (i * R + r) * 12 + k; }
+    // chunked records (spinor_io.h): 2 complex per 16-byte chunk, 6 chunks
+    __host__ __device__ static long idx(int k, long i, int r, long Vh, int R) { return ((i * 6 + k / 2) * R + r) * 2 + k % 2; }
     using E = float2;
     using A = float;
     static constexpr bool kNorm = false;
@@ -41,7 +42,8 @@ struct S32 {
 // FP16 with one FP32 scale per site and right-hand side (value = half * scale)
 struct S16 {
     static constexpr bool kAoS = true;
-    __host__ __device__ static long idx(int k, long i, int r, long Vh, int R) { return (i * R + r) * 12 + k; }
+    // chunked records (spinor_io.h): 4 complex per 16-byte chunk, 3 chunks
+    __host__ __device__ static long idx(int k, long i, int r, long Vh, int R) { return ((i * 3 + k / 4) * R + r) * 4 + k % 4; }
     using E = __half2;
     using A = float;
     static constexpr bool kNorm = true;
@@ -59,7 +61,8 @@ struct S16 {
 // BF16 (8-bit mantissa, FP32 range; no scale needed): (re, im) packed low/high
 struct SB16 {
     static constexpr bool kAoS = true;
-    __host__ __device__ static long idx(int k, long i, int r, long Vh, int R) { return (i * R + r) * 12 + k; }
+    // chunked records (spinor_io.h): 4 complex per 16-byte chunk, 3 chunks
+    __host__ __device__ static long idx(int k, long i, int r, long Vh, int R) { return ((i * 3 + k / 4) * R + r) * 4 + k % 4; }
     using E = uint32_t;
     using A = float;
     static constexpr bool kNorm = false;

@@ -323,7 +323,7 @@ template <class SP>
 __device__ __forceinline__ float ld_raw(const typename SP::E *base, const float *nrm, int R, long i, int r,
                                         Cx<float> (&o)[4][3])
 {
-    Spin12<SP> pk = *reinterpret_cast<const Spin12<SP> *>(base + (i * R + r) * 12);
+    Spin12<SP> pk = ld_rec<SP>(base, i, R, r);
 #pragma unroll
     for (int k = 0; k < 12; k++) o[k / 3][k % 3] = SP::ld(&pk.v[k], 0, 1.0f);
     if constexpr (SP::kNorm)
@@ -426,16 +426,15 @@ __device__ __forceinline__ void hop_lds(const float4 *lk, const Spin12<SP> &sp, 
     }
 }
 
-// neighbour record: 32-bit element offset (site * R + r) of the input field
+// neighbour record of the input field (32-bit site index)
 template <int MU, bool FWD, class SP>
 __device__ __forceinline__ void dir_lds(const MrArgs &P, const float4 *slk, int nb, int R, int r,
                                         Cx<float> (&acc)[4][3])
 {
     const auto *in = (const typename SP::E *)P.in;
-    const int rec = nb * R + r;
-    Spin12<SP> sp = *reinterpret_cast<const Spin12<SP> *>(in + (size_t)rec * 12);
+    Spin12<SP> sp = ld_rec<SP>(in, nb, R, r);
     float sc = 1.0f;
-    if constexpr (SP::kNorm) sc = P.in_nrm[rec];
+    if constexpr (SP::kNorm) sc = P.in_nrm[nb * R + r];
     hop_lds<MU, FWD, SP>(slk + (FWD ? MU : 4 + MU) * kLkF4, sp, sc, acc);
 }
 

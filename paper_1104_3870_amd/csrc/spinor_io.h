@@ -8,6 +8,29 @@ struct alignas(16) Spin12 {
     typename SP::E v[12];
 };
 
+// Low-precision batches store each (site, right-hand side) record of 12 complex numbers as
+// C = sizeof(record) / 16 chunks of 16 bytes, chunk q of site i and right-hand side r at
+// byte ((i C + q) R + r) 16: the R records of a site are interleaved chunk by chunk, so a
+// wave-wide 16-byte access of consecutive right-hand sides is contiguous.
+template <class SP>
+__device__ __forceinline__ Spin12<SP> ld_rec(const typename SP::E *base, long i, int R, int r)
+{
+    constexpr int C = sizeof(Spin12<SP>) / 16;
+    Spin12<SP> pk;
+    const uint4 *b = reinterpret_cast<const uint4 *>(base);
+#pragma unroll
+    for (int q = 0; q < C; q++) reinterpret_cast<uint4 *>(&pk)[q] = b[((size_t)i * C + q) * R + r];
+    return pk;
+}
+template <class SP>
+__device__ __forceinline__ void st_rec(typename SP::E *base, long i, int R, int r, const Spin12<SP> &pk)
+{
+    constexpr int C = sizeof(Spin12<SP>) / 16;
+    uint4 *b = reinterpret_cast<uint4 *>(base);
+#pragma unroll
+    for (int q = 0; q < C; q++) b[((size_t)i * C + q) * R + r] = reinterpret_cast<const uint4 *>(&pk)[q];
+}
+
 // o[k] = component k (alpha*3 + c) of right-hand side r at site i, in arithmetic type A
 template <class SP, typename A>
 __device__ __forceinline__ void ld_spinor12(const typename SP::E *base, const float *nrm, long Vh, int R, long i, int r,
@@ -16,7 +39,7 @@ __device__ __forceinline__ void ld_spinor12(const typename SP::E *base, const fl
     float sc = 1.0f;
     if constexpr (SP::kNorm) sc = nrm[i * R + r];
     if constexpr (SP::kAoS) {
-        Spin12<SP> pk = *reinterpret_cast<const Spin12<SP> *>(base + (i * R + r) * 12);
+        Spin12<SP> pk = ld_rec<SP>(base, i, R, r);
 #pragma unroll
         for (int k = 0; k < 12; k++) {
             auto c = SP::ld(&pk.v[k], 0, sc);
@@ -51,7 +74,7 @@ __device__ __forceinline__ void st_spinor12(typename SP::E *base, float *nrm, lo
         Spin12<SP> pk;
 #pragma unroll
         for (int k = 0; k < 12; k++) SP::st(&pk.v[k], 0, Cx<SA>{(SA)v[k].re, (SA)v[k].im}, inv);
-        *reinterpret_cast<Spin12<SP> *>(base + (i * R + r) * 12) = pk;
+        st_rec<SP>(base, i, R, r, pk);
     } else {
 #pragma unroll
         for (int k = 0; k < 12; k++) SP::st(base, SP::idx(k, i, r, Vh, R), Cx<SA>{(SA)v[k].re, (SA)v[k].im}, inv);

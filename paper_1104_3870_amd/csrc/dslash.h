@@ -108,7 +108,9 @@ enum {
     M_PLAIN = 0,      // out = c D psi [+ a x]
     M_INV_AFTER = 1,  // out = a x + c A^-1 D psi
     M_INV_OF_SUM = 2, // out = A^-1 (a x + c D psi)
-    M_CLOV_ADD = 3    // out = A x + c D psi
+    M_CLOV_ADD = 3,   // out = A x + c D psi
+    M_INV_AFTER_DAG = 4  // as M_INV_AFTER, and also out2 = A^-1 gamma_5 out and per-block
+                         // partial sums of |out|^2 (multi-RHS low-precision kernel only)
 };
 
 struct DslashArgs {

@@ -19,6 +19,11 @@ struct MrArgs {
     double a, c;
     double wt, ws, bct;
     int g5d;
+    // M_INV_AFTER_DAG only: second output A^-1 gamma_5 out (same parity and layout as out)
+    // and partial[block * R + r] = sum over the block's sites of |out_r|^2
+    void *out2;
+    float *out2_nrm;
+    double *partial;
 };
 
 // mode: M_PLAIN (out = c D psi [+ a x]) or M_INV_AFTER (out = a x + c A^-1 D psi)
@@ -37,3 +42,7 @@ double dslash_mr_bytes(long Vh, int R, int sbytes, bool has_norm, int mode, bool
 
 // sites per block of the LDS-staged hopping kernel for (precision, R); S R <= 256 lanes
 int lds_tile_sites(laph_ctx *c, int prec, int R);
+// whether M_INV_AFTER_DAG is available for R right-hand sides (LDS-staged kernel in use,
+// 32-bit record offsets) and the number of partial sums per right-hand side it writes
+bool lds_dag_ok(laph_ctx *c, int R);
+long lds_dag_blocks(laph_ctx *c, int prec, int R);

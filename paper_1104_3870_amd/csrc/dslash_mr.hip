@@ -490,7 +490,8 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
     const int ns = P.ns, nt = P.nt, par = P.par, opar = par ^ 1;
     const long site0 = (long)xcd_block(blockIdx.x, gridDim.x) * S;
     const float4 *lk = (const float4 *)P.links;
-    const float fout = MODE == M_INV_AFTER ? 1.0f : (float)P.c;  // folded into the links
+    constexpr bool kInv = MODE == M_INV_AFTER || MODE == M_INV_AFTER_DAG;
+    const float fout = kInv ? 1.0f : (float)P.c;  // folded into the links
     for (int k = threadIdx.x; k < S * 8; k += blockDim.x) {
         const int sl = k >> 3, d = k & 7, mu = d & 3;
         const long i = site0 + sl;
@@ -529,7 +530,7 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
 #pragma unroll
         for (int q = 0; q < kLkF4; q++) dst[q] = make_float4(f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]);
     }
-    if constexpr (MODE == M_INV_AFTER) {
+    if constexpr (kInv) {
         const float4 *cl = (const float4 *)P.clov;
         const float cc = (float)P.c;
         for (int k = threadIdx.x; k < S * 18; k += blockDim.x) {
@@ -540,7 +541,12 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
     }
     __syncthreads();
     const int sl = threadIdx.x / R, r = threadIdx.x - sl * R;
-    if (sl >= S || site0 + sl >= Vh) return;
+    const bool valid = sl < S && site0 + sl < Vh;
+    if constexpr (MODE != M_INV_AFTER_DAG) {
+        if (!valid) return;
+    }
+    double nq = 0.0;  // |out|^2 of this lane (M_INV_AFTER_DAG)
+    if (valid) {
     // 32-bit site arithmetic (the host checks Vh * R * 12 < 2^31): neighbour checkerboard
     // indices from the site's own, lex = 2 cb + (x & 1) since Ns is even
     const int cb = (int)(site0 + sl);
@@ -579,7 +585,7 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
         }
     }
     Cx<float> res[4][3];
-    if constexpr (MODE == M_INV_AFTER) {
+    if constexpr (kInv) {
         clover_one(scl + (size_t)sl * 18, acc, res);
     } else {
 #pragma unroll
@@ -601,7 +607,36 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
     Cx<float> v[12];
 #pragma unroll
     for (int k = 0; k < 12; k++) v[k] = res[k / 3][k % 3];
-    st_spinor12<SP, float>((typename SP::E *)P.out, P.out_nrm, Vh, R, i, r, v);
+    if constexpr (MODE == M_INV_AFTER_DAG) {
+        // out as stored; |out|^2 and A^-1 gamma_5 out from the rounded values (what a
+        // separate pass would read back); the staged clover block holds c A^-1
+        st_spinor12_round<SP>((typename SP::E *)P.out, P.out_nrm, Vh, R, i, r, v);
+        Cx<float> g[4][3], o2[4][3];
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            nq += (double)v[k].re * v[k].re + (double)v[k].im * v[k].im;
+            g[k / 3][k % 3] = k < 6 ? v[k] : cneg(v[k]);
+        }
+        clover_one(scl + (size_t)sl * 18, g, o2);
+        const float ic = 1.0f / (float)P.c;
+#pragma unroll
+        for (int k = 0; k < 12; k++) v[k] = ic * o2[k / 3][k % 3];
+        st_spinor12<SP, float>((typename SP::E *)P.out2, P.out2_nrm, Vh, R, i, r, v);
+    } else {
+        st_spinor12<SP, float>((typename SP::E *)P.out, P.out_nrm, Vh, R, i, r, v);
+    }
+    }  // valid
+    if constexpr (MODE == M_INV_AFTER_DAG) {
+        // deterministic block sum per right-hand side: lanes sl = 0 .. S-1 of each r
+        __shared__ double red[256];
+        red[threadIdx.x] = nq;
+        __syncthreads();
+        if ((int)threadIdx.x < R) {
+            double s2 = 0.0;
+            for (int q = 0; q < S; q++) s2 += red[q * R + threadIdx.x];
+            P.partial[(size_t)blockIdx.x * R + threadIdx.x] = s2;
+        }
+    }
 }
 
 // out = A x with optional gamma_5 on x (local, per-site clover)
@@ -671,10 +706,12 @@ static int pick_nr(int R)
 double dslash_mr_bytes(long Vh, int R, int sbytes, bool has_norm, int mode, bool has_x)
 {
     double site = 8.0 * 48;  // reconstruct-12 FP32 links
-    if (mode == M_INV_AFTER) site += 72.0 * 4;
-    double per_rhs = 12.0 * sbytes * (2 + (has_x ? 1 : 0)) + (has_norm ? 4.0 * (2 + (has_x ? 1 : 0)) : 0.0);
+    if (mode == M_INV_AFTER || mode == M_INV_AFTER_DAG) site += 72.0 * 4;
+    const int streams = 2 + (has_x ? 1 : 0) + (mode == M_INV_AFTER_DAG ? 1 : 0);  // in, out[, x][, out2]
+    double per_rhs = 12.0 * sbytes * streams + (has_norm ? 4.0 * streams : 0.0);
     return (double)Vh * (site + R * per_rhs);
 }
+
 
 template <class SP>
 constexpr int prec_id()
@@ -707,6 +744,14 @@ static bool use_lds_kernel()
     return v == 1;
 }
 
+bool lds_dag_ok(laph_ctx *c, int R) { return use_lds_kernel() && c->g.Vh * R * 12 < (1L << 31); }
+
+long lds_dag_blocks(laph_ctx *c, int prec, int R)
+{
+    const int S = lds_tile_sites(c, prec, R);
+    return (c->g.Vh + S - 1) / S;
+}
+
 template <class SP>
 void launch_dslash_mr(laph_ctx *c, int mode, const MrArgs &a, hipStream_t st)
 {
@@ -715,7 +760,9 @@ void launch_dslash_mr(laph_ctx *c, int mode, const MrArgs &a, hipStream_t st)
         dim3 grid(nblocks_for(a.Vh, S)), block(S * a.R);
         hipEvent_t e0, e1;
         timing_begin(c, &e0, &e1);
-        if (mode == M_INV_AFTER)
+        if (mode == M_INV_AFTER_DAG)
+            hipLaunchKernelGGL((k_dslash_lds<SP, M_INV_AFTER_DAG>), grid, block, lds_bytes(S), st, a);
+        else if (mode == M_INV_AFTER)
             hipLaunchKernelGGL((k_dslash_lds<SP, M_INV_AFTER>), grid, block, lds_bytes(S), st, a);
         else
             hipLaunchKernelGGL((k_dslash_lds<SP, M_PLAIN>), grid, block, lds_bytes(S), st, a);
@@ -725,6 +772,7 @@ void launch_dslash_mr(laph_ctx *c, int mode, const MrArgs &a, hipStream_t st)
                    timing_label("dslash_lds", prec_name<SP>(), mode, a.R));
         return;
     }
+    LAPH_CHECK(mode != M_INV_AFTER_DAG, LAPH_EINVAL, "fused hopping epilogue needs the LDS-staged kernel");
     int NR = pick_nr(a.R);
     long n = a.Vh * (a.R / NR);
     dim3 grid(nblocks_for(n, 256)), block(256);

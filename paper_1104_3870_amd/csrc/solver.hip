@@ -746,6 +746,15 @@ __global__ __launch_bounds__(kBS) void k_copy64(Vec a, Vec b, long Vh, int R, co
 }
 
 // ---------------------------------------------------------------- operator helper
+template <class SP>
+constexpr int prec_of()
+{
+    return std::is_same<SP, S16>::value    ? LAPH_PREC_F16
+           : std::is_same<SP, SB16>::value ? LAPH_PREC_BF16
+           : std::is_same<SP, S32>::value  ? LAPH_PREC_F32
+                                           : LAPH_PREC_F64;
+}
+
 template <class SP, class GP, class CP>
 struct Op {
     laph_ctx *c;
@@ -783,8 +792,20 @@ struct Op {
     // hopping term with epilogue; mode M_PLAIN or M_INV_AFTER
     void dslash(int mode, int par, Vec in, Vec out, const Vec *x, double a, double cc, int g5d) const
     {
+        dslash_ext(mode, par, in, out, x, a, cc, g5d, nullptr, nullptr);
+    }
+    // as dslash; with mode M_INV_AFTER_DAG (low precision) also out2 = A^-1 gamma_5 out and
+    // per-block |out|^2 partials
+    void dslash_ext(int mode, int par, Vec in, Vec out, const Vec *x, double a, double cc, int g5d, const Vec *out2,
+                    double *partial) const
+    {
         if constexpr (kLow) {
             MrArgs m{};
+            if (out2) {
+                m.out2 = out2->d;
+                m.out2_nrm = out2->n;
+                m.partial = partial;
+            }
             m.out = out.d;
             m.out_nrm = out.n;
             m.in = in.d;
@@ -806,6 +827,7 @@ struct Op {
             m.g5d = g5d;
             launch_dslash_mr<SP>(c, mode, m, st);
         } else {
+            LAPH_CHECK(mode != M_INV_AFTER_DAG, LAPH_EINVAL, "fused epilogue is low precision only");
             DslashArgs d = base(par);
             d.in = in.d;
             d.in_nrm = in.n;
@@ -838,8 +860,20 @@ struct Op {
     void mhat_dag(Vec in, Vec out, Vec to) const
     {
         clover_inv(1, in, to, 1);
+        mhat_dag_rest(in, to, out);
+    }
+    // the part of mhat_dag after to = A_oo^-1 gamma_5 in
+    void mhat_dag_rest(Vec in, Vec to, Vec out) const
+    {
         dslash(M_INV_AFTER, 0, to, te, nullptr, 0.0, 1.0, 0);
         dslash(M_PLAIN, 1, te, out, &in, 1.0, -1.0, 1);
+    }
+    // mhat with the second hop's epilogue also forming to = A_oo^-1 gamma_5 out (the start of
+    // mhat_dag) and per-block |out|^2 partials (low precision, LDS-staged kernel)
+    void mhat_prep(Vec in, Vec out, Vec to, double *partial) const
+    {
+        dslash(M_INV_AFTER, 0, in, te, nullptr, 0.0, 1.0, 0);
+        dslash_ext(M_INV_AFTER_DAG, 1, te, out, &in, 1.0, -1.0, 0, &to, partial);
     }
 };
 
@@ -1031,11 +1065,26 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
     // recursive residual must not fall far below what the storage precision can follow
     if (!plain) check_every = 1;
     // one iteration: q = M p, alpha, y = M^dag q, x/res/r updates, beta (plain: and p)
+    // low precision with the LDS-staged kernel: |q|^2 and the first step of M^dag q come
+    // from the epilogue of the hop that forms q
+    const bool fuse = !plain && lds_dag_ok(c, w.R);
+    double *part_hop = nullptr;
+    int nblk_hop = 0;
+    if (fuse) {
+        nblk_hop = (int)lds_dag_blocks(c, prec_of<SP>(), w.R);
+        part_hop = (double *)ctx_named(c, "slv.part_hop", sizeof(double) * nblk_hop * w.R);
+    }
     auto body = [&](const Op<SP, GP, CP> &op) {
-        op.mhat(p, q);
-        launch_red(c, k_normsq<SP>, n, q, w.Vh, w.R, w.part);
-        launch_fin(c, k_fin_cg_alpha, w.R, (const double *)w.part, nblk, w.R, w.sc);
-        op.mhat_dag(q, y, to);
+        if (fuse) {
+            op.mhat_prep(p, q, to, part_hop);
+            launch_fin(c, k_fin_cg_alpha, w.R, (const double *)part_hop, nblk_hop, w.R, w.sc);
+            op.mhat_dag_rest(q, to, y);
+        } else {
+            op.mhat(p, q);
+            launch_red(c, k_normsq<SP>, n, q, w.Vh, w.R, w.part);
+            launch_fin(c, k_fin_cg_alpha, w.R, (const double *)w.part, nblk, w.R, w.sc);
+            op.mhat_dag(q, y, to);
+        }
         if (plain)
             launch_red(c, k_cg_update<SP, XP, true>, n, xlo, p, res, q, r, y, w.Vh, w.R, w.part, (const Scal *)w.sc);
         else

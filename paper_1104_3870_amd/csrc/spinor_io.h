@@ -80,3 +80,30 @@ __device__ __forceinline__ void st_spinor12(typename SP::E *base, float *nrm, lo
         for (int k = 0; k < 12; k++) SP::st(base, SP::idx(k, i, r, Vh, R), Cx<SA>{(SA)v[k].re, (SA)v[k].im}, inv);
     }
 }
+
+// store v and replace it by the values a later load returns (storage rounding and scale)
+template <class SP>
+__device__ __forceinline__ void st_spinor12_round(typename SP::E *base, float *nrm, long Vh, int R, long i, int r,
+                                                  Cx<float> (&v)[12])
+{
+    static_assert(SP::kAoS, "record layouts only");
+    float inv = 1.0f, sc = 1.0f;
+    if constexpr (SP::kNorm) {
+        float m = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 12; k++) m = fmaxf(m, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
+        sc = m > 1e-30f ? m : 1.0f;
+        nrm[i * R + r] = sc;
+        inv = 1.0f / sc;
+    }
+    Spin12<SP> pk;
+#pragma unroll
+    for (int k = 0; k < 12; k++) SP::st(&pk.v[k], 0, Cx<float>{v[k].re, v[k].im}, inv);
+    st_rec<SP>(base, i, R, r, pk);
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        auto c = SP::ld(&pk.v[k], 0, sc);
+        v[k] = {(float)c.re, (float)c.im};
+    }
+}
+

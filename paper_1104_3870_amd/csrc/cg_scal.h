@@ -1,0 +1,19 @@
+// Per-right-hand-side Krylov scalars kept on the device (solver.hip; read by the fused
+// hopping epilogue of the multi-RHS kernel).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+struct Scal {
+    double2 rho, alpha, omega, beta;
+    double2 aux;      // <r, p> / |r|^2 after a reliable update (CG)
+    double rho_prev;  // |r|^2 of the previous CG iteration
+    double r2;        // |r|^2 of the iterated residual
+    double r2hi;      // |r|^2 of the last FP64 residual
+    double tol2;      // target |r|^2 of the even-odd system
+    double b2;        // |bhat|^2
+    int active;
+    int iters;
+    int breakdown;
+    int pad;
+};

@@ -109,8 +109,10 @@ enum {
     M_INV_AFTER = 1,  // out = a x + c A^-1 D psi
     M_INV_OF_SUM = 2, // out = A^-1 (a x + c D psi)
     M_CLOV_ADD = 3,   // out = A x + c D psi
-    M_INV_AFTER_DAG = 4  // as M_INV_AFTER, and also out2 = A^-1 gamma_5 out and per-block
+    M_INV_AFTER_DAG = 4, // as M_INV_AFTER, and also out2 = A^-1 gamma_5 out and per-block
                          // partial sums of |out|^2 (multi-RHS low-precision kernel only)
+    M_PLAIN_CG = 5       // as M_PLAIN with out consumed by a CG update instead of stored
+                         // (multi-RHS low-precision kernel only)
 };
 
 struct DslashArgs {

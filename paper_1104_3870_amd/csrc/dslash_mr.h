@@ -1,6 +1,7 @@
 // Multi-right-hand-side low-precision hopping kernel (see dslash_mr.hip).
 #pragma once
 
+#include "cg_scal.h"
 #include "dslash.h"
 
 struct MrArgs {
@@ -19,11 +20,20 @@ struct MrArgs {
     double a, c;
     double wt, ws, bct;
     int g5d;
-    // M_INV_AFTER_DAG only: second output A^-1 gamma_5 out (same parity and layout as out)
-    // and partial[block * R + r] = sum over the block's sites of |out_r|^2
+    // M_INV_AFTER_DAG: second output A^-1 gamma_5 out (same parity and layout as out).
+    // M_PLAIN_CG: out is not stored; for active right-hand sides cg_x += alpha cg_p and
+    // cg_r -= alpha out (alpha and the mask from sc[r]).  Both write
+    // partial[r * nblocks + block] = sum over the block's sites of |out_r|^2 (DAG) or
+    // |cg_r|^2 after the update (CG), from the stored values.
     void *out2;
     float *out2_nrm;
     double *partial;
+    const Scal *sc;
+    void *cg_x;  // FP32 records (solution increment)
+    const void *cg_p;
+    const float *cg_p_nrm;
+    void *cg_r;
+    float *cg_r_nrm;
 };
 
 // mode: M_PLAIN (out = c D psi [+ a x]) or M_INV_AFTER (out = a x + c A^-1 D psi)
@@ -42,7 +52,8 @@ double dslash_mr_bytes(long Vh, int R, int sbytes, bool has_norm, int mode, bool
 
 // sites per block of the LDS-staged hopping kernel for (precision, R); S R <= 256 lanes
 int lds_tile_sites(laph_ctx *c, int prec, int R);
-// whether M_INV_AFTER_DAG is available for R right-hand sides (LDS-staged kernel in use,
-// 32-bit record offsets) and the number of partial sums per right-hand side it writes
+// whether M_INV_AFTER_DAG / M_PLAIN_CG are available for R right-hand sides (LDS-staged
+// kernel in use, 32-bit record offsets) and the number of partial sums per right-hand side
+// they write
 bool lds_dag_ok(laph_ctx *c, int R);
 long lds_dag_blocks(laph_ctx *c, int prec, int R);

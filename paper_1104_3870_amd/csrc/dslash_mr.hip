@@ -542,10 +542,11 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
     __syncthreads();
     const int sl = threadIdx.x / R, r = threadIdx.x - sl * R;
     const bool valid = sl < S && site0 + sl < Vh;
-    if constexpr (MODE != M_INV_AFTER_DAG) {
+    constexpr bool kRed = MODE == M_INV_AFTER_DAG || MODE == M_PLAIN_CG;  // block reduction
+    if constexpr (!kRed) {
         if (!valid) return;
     }
-    double nq = 0.0;  // |out|^2 of this lane (M_INV_AFTER_DAG)
+    double nq = 0.0;  // this lane's |out|^2 (DAG) or |r|^2 (CG)
     if (valid) {
     // 32-bit site arithmetic (the host checks Vh * R * 12 < 2^31): neighbour checkerboard
     // indices from the site's own, lex = 2 cb + (x & 1) since Ns is even
@@ -622,19 +623,38 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
 #pragma unroll
         for (int k = 0; k < 12; k++) v[k] = ic * o2[k / 3][k % 3];
         st_spinor12<SP, float>((typename SP::E *)P.out2, P.out2_nrm, Vh, R, i, r, v);
+    } else if constexpr (MODE == M_PLAIN_CG) {
+        // CG update of the normal equations: x += alpha p, r -= alpha out; |r|^2 of the
+        // stored residual (the increment x is kept in FP32)
+        if (P.sc[r].active) {
+            const float al = (float)P.sc[r].alpha.x;
+            Cx<float> a[12], b[12];
+            ld_spinor12<S32, float>((const float2 *)P.cg_x, nullptr, Vh, R, i, r, a);
+            ld_spinor12<SP, float>((const typename SP::E *)P.cg_p, P.cg_p_nrm, Vh, R, i, r, b);
+#pragma unroll
+            for (int k = 0; k < 12; k++) a[k] = {fmaf(al, b[k].re, a[k].re), fmaf(al, b[k].im, a[k].im)};
+            st_spinor12<S32, float>((float2 *)P.cg_x, nullptr, Vh, R, i, r, a);
+            ld_spinor12<SP, float>((const typename SP::E *)P.cg_r, P.cg_r_nrm, Vh, R, i, r, a);
+#pragma unroll
+            for (int k = 0; k < 12; k++) a[k] = {fmaf(-al, v[k].re, a[k].re), fmaf(-al, v[k].im, a[k].im)};
+            st_spinor12_round<SP>((typename SP::E *)P.cg_r, P.cg_r_nrm, Vh, R, i, r, a);
+#pragma unroll
+            for (int k = 0; k < 12; k++) nq += (double)a[k].re * a[k].re + (double)a[k].im * a[k].im;
+        }
     } else {
         st_spinor12<SP, float>((typename SP::E *)P.out, P.out_nrm, Vh, R, i, r, v);
     }
     }  // valid
-    if constexpr (MODE == M_INV_AFTER_DAG) {
-        // deterministic block sum per right-hand side: lanes sl = 0 .. S-1 of each r
+    if constexpr (kRed) {
+        // deterministic block sum per right-hand side over the lanes sl = 0 .. S-1 of each
+        // r; partials stored right-hand-side major
         __shared__ double red[256];
         red[threadIdx.x] = nq;
         __syncthreads();
         if ((int)threadIdx.x < R) {
             double s2 = 0.0;
             for (int q = 0; q < S; q++) s2 += red[q * R + threadIdx.x];
-            P.partial[(size_t)blockIdx.x * R + threadIdx.x] = s2;
+            P.partial[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s2;
         }
     }
 }
@@ -707,8 +727,12 @@ double dslash_mr_bytes(long Vh, int R, int sbytes, bool has_norm, int mode, bool
 {
     double site = 8.0 * 48;  // reconstruct-12 FP32 links
     if (mode == M_INV_AFTER || mode == M_INV_AFTER_DAG) site += 72.0 * 4;
-    const int streams = 2 + (has_x ? 1 : 0) + (mode == M_INV_AFTER_DAG ? 1 : 0);  // in, out[, x][, out2]
+    // in, out[, x][, out2]; the CG form reads p and r and writes r instead of out, and reads
+    // and writes the FP32 increment
+    int streams = 2 + (has_x ? 1 : 0) + (mode == M_INV_AFTER_DAG ? 1 : 0);
+    if (mode == M_PLAIN_CG) streams += 2;
     double per_rhs = 12.0 * sbytes * streams + (has_norm ? 4.0 * streams : 0.0);
+    if (mode == M_PLAIN_CG) per_rhs += 2 * 96.0;
     return (double)Vh * (site + R * per_rhs);
 }
 
@@ -762,6 +786,8 @@ void launch_dslash_mr(laph_ctx *c, int mode, const MrArgs &a, hipStream_t st)
         timing_begin(c, &e0, &e1);
         if (mode == M_INV_AFTER_DAG)
             hipLaunchKernelGGL((k_dslash_lds<SP, M_INV_AFTER_DAG>), grid, block, lds_bytes(S), st, a);
+        else if (mode == M_PLAIN_CG)
+            hipLaunchKernelGGL((k_dslash_lds<SP, M_PLAIN_CG>), grid, block, lds_bytes(S), st, a);
         else if (mode == M_INV_AFTER)
             hipLaunchKernelGGL((k_dslash_lds<SP, M_INV_AFTER>), grid, block, lds_bytes(S), st, a);
         else
@@ -772,7 +798,8 @@ void launch_dslash_mr(laph_ctx *c, int mode, const MrArgs &a, hipStream_t st)
                    timing_label("dslash_lds", prec_name<SP>(), mode, a.R));
         return;
     }
-    LAPH_CHECK(mode != M_INV_AFTER_DAG, LAPH_EINVAL, "fused hopping epilogue needs the LDS-staged kernel");
+    LAPH_CHECK(mode != M_INV_AFTER_DAG && mode != M_PLAIN_CG, LAPH_EINVAL,
+               "fused hopping epilogues need the LDS-staged kernel");
     int NR = pick_nr(a.R);
     long n = a.Vh * (a.R / NR);
     dim3 grid(nblocks_for(n, 256)), block(256);

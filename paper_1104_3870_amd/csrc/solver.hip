@@ -35,19 +35,6 @@ bool laph_verbose() { return laph_verbose_level() > 0; }
 constexpr int kBS = 256;
 constexpr int kMaxBlocks = 1024;
 
-struct Scal {
-    double2 rho, alpha, omega, beta;
-    double2 aux;   // <r, p> / |r|^2 after a reliable update (CG)
-    double rho_prev;  // |r|^2 of the previous CG iteration
-    double r2;     // |r|^2 of the iterated residual
-    double r2hi;   // |r|^2 of the last FP64 residual
-    double tol2;   // target |r|^2 of the even-odd system
-    double b2;     // |bhat|^2
-    int active;
-    int iters;
-    int breakdown;
-    int pad;
-};
 
 struct Vec {
     void *d = nullptr;
@@ -516,11 +503,30 @@ __global__ __launch_bounds__(kBS) void k_normsq(Vec a, long Vh, int R, double *p
 }
 
 // alpha = rho / |q|^2
-__global__ void k_fin_cg_alpha(const double *partial, int nblk, int R, Scal *sc)
+// deterministic sum of right-hand-side-major partials partial[r * nblk + b]
+__device__ __forceinline__ double sum_partials_rmajor(const double *partial, int nblk, int r)
+{
+    __shared__ double lds[kBS];
+    double v = 0;
+    for (int b = threadIdx.x; b < nblk; b += kBS) v += partial[(long)r * nblk + b];
+    lds[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kBS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
+        __syncthreads();
+    }
+    return lds[0];
+}
+
+// rmajor: partials of the fused hopping epilogue (one value per block and RHS)
+__global__ void k_fin_cg_alpha(const double *partial, int nblk, int R, Scal *sc, int rmajor)
 {
     int r = blockIdx.x;
     double s[1];
-    sum_partials<1>(partial, nblk, R, r, s);
+    if (rmajor)
+        s[0] = sum_partials_rmajor(partial, nblk, r);
+    else
+        sum_partials<1>(partial, nblk, R, r, s);
     if (threadIdx.x) return;
     Scal &q = sc[r];
     if (!q.active) {
@@ -581,11 +587,17 @@ __global__ __launch_bounds__(kBS) void k_cg_update(Vec x, Vec p, Vec res, Vec q,
 
 // beta = |r|^2 / rho; rho = |r|^2; r2 = |res|^2; with hi_conv the recursive even-odd
 // residual alone may declare convergence (plain FP64 iteration)
-__global__ void k_fin_cg_beta(const double *partial, int nblk, int R, Scal *sc, int hi_conv, int recur)
+__global__ void k_fin_cg_beta(const double *partial, int nblk, int R, Scal *sc, int hi_conv, int recur,
+                              int rmajor)
 {
     int r = blockIdx.x;
     double s[2];
-    sum_partials<2>(partial, nblk, R, r, s);
+    if (rmajor) {
+        s[0] = sum_partials_rmajor(partial, nblk, r);
+        s[1] = 0.0;
+    } else {
+        sum_partials<2>(partial, nblk, R, r, s);
+    }
     if (threadIdx.x) return;
     Scal &q = sc[r];
     if (!q.active) {
@@ -789,6 +801,31 @@ struct Op {
     const void *cinv(int par) const { return clinv + (size_t)par * 72 * Vh * sizeof(typename CP::E); }
     const void *cl(int par) const { return clov + (size_t)par * 72 * Vh * sizeof(typename CP::E); }
 
+    // arguments of the multi-RHS low-precision hopping kernel
+    MrArgs mr_args(int par, Vec in, Vec out, const Vec *x, double a, double cc, int g5d) const
+    {
+        MrArgs m{};
+        m.out = out.d;
+        m.out_nrm = out.n;
+        m.in = in.d;
+        m.in_nrm = in.n;
+        m.x = x ? x->d : nullptr;
+        m.x_nrm = x ? x->n : nullptr;
+        m.links = lk12;
+        m.clov = claos + (size_t)par * Vh * 18;
+        m.ns = c->g.ns;
+        m.nt = c->g.nt;
+        m.Vh = Vh;
+        m.R = R;
+        m.par = par;
+        m.a = a;
+        m.c = cc;
+        m.wt = wt;
+        m.ws = ws;
+        m.bct = bct;
+        m.g5d = g5d;
+        return m;
+    }
     // hopping term with epilogue; mode M_PLAIN or M_INV_AFTER
     void dslash(int mode, int par, Vec in, Vec out, const Vec *x, double a, double cc, int g5d) const
     {
@@ -800,31 +837,12 @@ struct Op {
                     double *partial) const
     {
         if constexpr (kLow) {
-            MrArgs m{};
+            MrArgs m = mr_args(par, in, out, x, a, cc, g5d);
             if (out2) {
                 m.out2 = out2->d;
                 m.out2_nrm = out2->n;
                 m.partial = partial;
             }
-            m.out = out.d;
-            m.out_nrm = out.n;
-            m.in = in.d;
-            m.in_nrm = in.n;
-            m.x = x ? x->d : nullptr;
-            m.x_nrm = x ? x->n : nullptr;
-            m.links = lk12;
-            m.clov = claos + (size_t)par * Vh * 18;
-            m.ns = c->g.ns;
-            m.nt = c->g.nt;
-            m.Vh = Vh;
-            m.R = R;
-            m.par = par;
-            m.a = a;
-            m.c = cc;
-            m.wt = wt;
-            m.ws = ws;
-            m.bct = bct;
-            m.g5d = g5d;
             launch_dslash_mr<SP>(c, mode, m, st);
         } else {
             LAPH_CHECK(mode != M_INV_AFTER_DAG, LAPH_EINVAL, "fused epilogue is low precision only");
@@ -867,6 +885,25 @@ struct Op {
     {
         dslash(M_INV_AFTER, 0, to, te, nullptr, 0.0, 1.0, 0);
         dslash(M_PLAIN, 1, te, out, &in, 1.0, -1.0, 1);
+    }
+    // mhat_dag_rest whose last hop feeds the CG update x += alpha p, r -= alpha (M^dag in)
+    // directly (low precision, LDS-staged kernel); per-block |r|^2 partials
+    void mhat_dag_cg(Vec in, Vec to, Vec x, Vec p, Vec r, const Scal *sc, double *partial) const
+    {
+        dslash(M_INV_AFTER, 0, to, te, nullptr, 0.0, 1.0, 0);
+        if constexpr (kLow) {
+            MrArgs m = mr_args(1, te, Vec{}, &in, 1.0, -1.0, 1);
+            m.partial = partial;
+            m.sc = sc;
+            m.cg_x = x.d;
+            m.cg_p = p.d;
+            m.cg_p_nrm = p.n;
+            m.cg_r = r.d;
+            m.cg_r_nrm = r.n;
+            launch_dslash_mr<SP>(c, M_PLAIN_CG, m, st);
+        } else {
+            laph_fail(LAPH_EINVAL, "fused CG update is low precision only");
+        }
     }
     // mhat with the second hop's epilogue also forming to = A_oo^-1 gamma_5 out (the start of
     // mhat_dag) and per-block |out|^2 partials (low precision, LDS-staged kernel)
@@ -1076,20 +1113,26 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
     }
     auto body = [&](const Op<SP, GP, CP> &op) {
         if (fuse) {
+            // M p with |q|^2 and A^-1 gamma_5 q from its epilogue; M^dag q feeding the CG
+            // update directly (partials of the fused epilogues are RHS-major)
             op.mhat_prep(p, q, to, part_hop);
-            launch_fin(c, k_fin_cg_alpha, w.R, (const double *)part_hop, nblk_hop, w.R, w.sc);
-            op.mhat_dag_rest(q, to, y);
+            launch_fin(c, k_fin_cg_alpha, w.R, (const double *)part_hop, nblk_hop, w.R, w.sc, 1);
+            op.mhat_dag_cg(q, to, xlo, p, r, (const Scal *)w.sc, part_hop);
+            launch_fin(c, k_fin_cg_beta, w.R, (const double *)part_hop, nblk_hop, w.R, w.sc, 0, 1, 1);
         } else {
             op.mhat(p, q);
             launch_red(c, k_normsq<SP>, n, q, w.Vh, w.R, w.part);
-            launch_fin(c, k_fin_cg_alpha, w.R, (const double *)w.part, nblk, w.R, w.sc);
+            launch_fin(c, k_fin_cg_alpha, w.R, (const double *)w.part, nblk, w.R, w.sc, 0);
             op.mhat_dag(q, y, to);
+            if (plain)
+                launch_red(c, k_cg_update<SP, XP, true>, n, xlo, p, res, q, r, y, w.Vh, w.R, w.part,
+                           (const Scal *)w.sc);
+            else
+                launch_red(c, k_cg_update<SP, XP, false>, n, xlo, p, res, q, r, y, w.Vh, w.R, w.part,
+                           (const Scal *)w.sc);
+            launch_fin(c, k_fin_cg_beta, w.R, (const double *)w.part, nblk, w.R, w.sc, plain ? 1 : 0, plain ? 0 : 1,
+                       0);
         }
-        if (plain)
-            launch_red(c, k_cg_update<SP, XP, true>, n, xlo, p, res, q, r, y, w.Vh, w.R, w.part, (const Scal *)w.sc);
-        else
-            launch_red(c, k_cg_update<SP, XP, false>, n, xlo, p, res, q, r, y, w.Vh, w.R, w.part, (const Scal *)w.sc);
-        launch_fin(c, k_fin_cg_beta, w.R, (const double *)w.part, nblk, w.R, w.sc, plain ? 1 : 0, plain ? 0 : 1);
         if (plain) launch_el(c, k_cg_p<SP>, n, p, r, w.Vh, w.R, (const Scal *)w.sc);
     };
     hipGraphExec_t gexec = nullptr;

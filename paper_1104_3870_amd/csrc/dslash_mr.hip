@@ -219,12 +219,16 @@ __device__ __forceinline__ void do_dir(const MrArgs &P, const float4 *lk, int x,
 #else
 #define LAPH_MR_ATTR
 #endif
-// the LDS-staged kernel: at most 128 VGPRs, 4 waves per SIMD (measured 1-4 % faster than
-// 3 waves at 133 VGPRs despite a few spilled registers)
+// the LDS-staged kernel: at most 128 VGPRs, 4 waves per SIMD (measured faster than 3 waves
+// without the cap), except the clover-inverse epilogue, which would spill under the cap:
+// its scratch traffic slowed the kernels after it more than the occupancy helped
 #ifndef LAPH_LDS_WAVES
 #define LAPH_LDS_WAVES 4
 #endif
-#define LAPH_LDS_ATTR __attribute__((amdgpu_waves_per_eu(LAPH_LDS_WAVES)))
+#ifndef LAPH_LDS_WAVES_INV
+#define LAPH_LDS_WAVES_INV 3
+#endif
+#define LAPH_LDS_ATTR __attribute__((amdgpu_waves_per_eu(MODE == M_INV_AFTER ? LAPH_LDS_WAVES_INV : LAPH_LDS_WAVES)))
 
 template <class SP, int NR, int MODE>
 __global__ __launch_bounds__(256) LAPH_MR_ATTR void k_dslash_mr(const MrArgs P)

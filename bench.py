@@ -112,6 +112,10 @@ def main():
     ap.add_argument("--reliable-delta", type=float, default=0.03,
                     help="reliable-update threshold (measured best on this workload; library default 0.1)")
     ap.add_argument("--reliable-every", type=int, default=50)
+    ap.add_argument("--guess", default="none", choices=["none", "net"],
+                    help="initial guess of the headline form: zero, or the trained network's N(gamma_4 eta)")
+    ap.add_argument("--learned-mixed-steps", type=int, default=1,
+                    help="steps of the headline form with the trained network's initial guess (0: skip)")
     ap.add_argument("--learned-sources", type=int, default=2,
                     help="sources solved with FGMRES and the learned preconditioner (0: skip)")
     args = ap.parse_args()
@@ -168,7 +172,14 @@ def main():
         return st
 
     kind = P.LAPH_SOLVER_CGNR if args.solver == "cgnr" else P.LAPH_SOLVER_BICGSTAB
-    best = P.solver_params(tol=cfg.solve_tol, maxiter=6000, precision=args.precision, block_rhs=args.block,
+    guess_net, guess_meta = None, None
+    if args.guess == "net":
+        from paper_1104_3870_amd import train_ptnet as T
+
+        w, guess_meta = T.load(os.path.join(ROOT, "paper_1104_3870_amd", "weights", "ptnet.npz"))
+        guess_net = P.PTNet(L.ctx, guess_meta["channels"])
+        guess_net.set_weights(w)
+    best = P.solver_params(net=guess_net, tol=cfg.solve_tol, maxiter=6000, precision=args.precision, block_rhs=args.block,
                            solver=kind, reliable_every=args.reliable_every, reliable_delta=args.reliable_delta)
     plain = P.solver_params(tol=cfg.solve_tol, maxiter=6000, precision="f64", block_rhs=1, solver=kind)
     t_setup = time.time() - t_setup
@@ -209,6 +220,31 @@ def main():
         fp64 = {"value": nsrc * args.fp64_steps / e64, "unit": "sources/s", "steps": args.fp64_steps,
                 "ms_per_step": 1000 * e64 / args.fp64_steps, "mean_iters": float(np.mean(it64)),
                 "form": "FP64 even-odd %s, one right-hand side at a time" % args.solver.upper()}
+
+    # ---------------- learned + mixed + multi-RHS: the headline form started from N(gamma_4 eta)
+    learned_mixed = None
+    if args.learned_mixed_steps > 0 and guess_net is None:
+        from paper_1104_3870_amd import train_ptnet as T
+
+        w, meta = T.load(os.path.join(ROOT, "paper_1104_3870_amd", "weights", "ptnet.npz"))
+        gnet = P.PTNet(L.ctx, meta["channels"])
+        gnet.set_weights(w)
+        svg = P.solver_params(net=gnet, tol=cfg.solve_tol, maxiter=6000, precision=args.precision,
+                              block_rhs=args.block, solver=kind, reliable_every=args.reliable_every,
+                              reliable_delta=args.reliable_delta)
+        torch.cuda.synchronize()
+        t3 = time.time()
+        itg = []
+        for k in range(args.learned_mixed_steps):
+            st = step(k, svg)
+            itg += [q.iters for q in st]
+        torch.cuda.synchronize()
+        eg = time.time() - t3
+        learned_mixed = {"value": round(nsrc * args.learned_mixed_steps / eg, 4), "unit": "sources/s",
+                         "steps": args.learned_mixed_steps, "mean_iters": float(np.mean(itg)),
+                         "form": "headline form with the initial guess x0 = N(gamma_4 eta) of the trained PT-net"}
+        log("learned + mixed: %.3f sources/s, %.1f iterations" % (learned_mixed["value"], learned_mixed["mean_iters"]))
+        gnet.close()
 
     # ---------------- learned preconditioner: FGMRES with the trained PT-net, one source at a time
     learned = None
@@ -289,11 +325,13 @@ def main():
                    "lattice": [cfg.ns, cfg.ns, cfg.ns, cfg.nt], "nv": cfg.nv, "m0": cfg.m0,
                    "dilution": cfg.dilution, "sources_per_step": nsrc,
                    "form": "even-odd %s, %s inner vectors, %d right-hand sides per batch, FP64 reliable "
-                           "updates" % (args.solver.upper(), args.precision, args.block)},
+                           "updates%s" % (args.solver.upper(), args.precision, args.block,
+                                          ", initial guess from the trained PT-net" if guess_net else "")},
         "mean_iters": float(np.mean(iters)),
         "max_true_resid": float(max(resid)),
         "fp64_plain": fp64,
         "speedup_vs_fp64": round(value / fp64["value"], 3) if fp64 else None,
+        "learned_mixed": learned_mixed,
         "learned": learned,
         "setup_s": {"total": round(t_setup, 2), "eigvecs": round(t_eig, 2), "eig_restarts": est.restarts},
         "roofline": roofline,

@@ -194,7 +194,9 @@ typedef struct {
     int block_rhs;      /* right-hand sides iterated together (power of two <= 32); 0 = the
                            block size laph_autotune picks (run on first use) */
     int use_graph;      /* replay the CG iteration body from a HIP graph (not with timing on) */
-    const void *net;    /* learned preconditioner (laph_ptnet_t) for LAPH_SOLVER_FGMRES */
+    const void *net;    /* learned network (laph_ptnet_t) or NULL: the right preconditioner of
+                           LAPH_SOLVER_FGMRES; with the other solvers the initial guess
+                           x0 = N(gamma_4 eta) on odd sites (N approximates K^-1) */
     int restart;        /* FGMRES restart length (0: 24) */
     double reliable_delta; /* mixed precision: FP64 reliable update as soon as the iterated
                               even-odd residual fell below this fraction of its last FP64

@@ -39,3 +39,6 @@ void ptnet_backward(laph_ctx *c, laph_ptnet *net, float bct, const float2 *g, fl
 // parity zero / dropped
 void eo_to_net(laph_ctx *c, const double2 *half, int par, float2 *full);
 void net_to_eo(laph_ctx *c, const float2 *full, int par, double2 *half);
+// odd part of N(gamma_4 eta) for R canonical FP64 sources, as the FP64 even-odd batch
+// xo[(k*Vh + i)*R + r] (initial guess of the odd-site system: x = K^-1 gamma_4 eta)
+void ptnet_initial_guess(laph_ctx *c, laph_ptnet *net, float bct, const double *eta, int R, double2 *xo);

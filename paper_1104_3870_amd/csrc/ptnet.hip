@@ -497,6 +497,48 @@ void net_to_eo(laph_ctx *c, const float2 *full, int par, double2 *half)
     LAPH_HIP(hipGetLastError());
 }
 
+// gamma_4 eta for R canonical FP64 fields -> net layout (one channel); gamma_4 swaps the
+// upper and lower spin pairs (chiral basis)
+__global__ void k_g4_to_net(const double2 *__restrict__ eta, float2 *__restrict__ out, long n)
+{
+    long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (tid >= n) return;
+    long s = tid / 12;
+    int k = (int)(tid - s * 12);
+    double2 v = eta[s * 12 + ((k / 3) ^ 2) * 3 + k % 3];
+    out[tid] = make_float2((float)v.x, (float)v.y);
+}
+
+// half[(k*Vh + i)*R + r] = full[r][site(i, par)][k]
+__global__ void k_net_to_eo_batch(const float2 *__restrict__ full, double2 *__restrict__ half, int par, int ns,
+                                  long V, long Vh, int R)
+{
+    long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (tid >= 12 * Vh * R) return;
+    int k = (int)(tid / (Vh * R));
+    long rem = tid - (long)k * Vh * R;
+    long i = rem / R;
+    int r = (int)(rem - i * R);
+    int x, y, z, t;
+    cb_coords(i, par, ns, x, y, z, t);
+    float2 v = full[((long)r * V + lex_index(x, y, z, t, ns)) * 12 + k];
+    half[tid] = make_double2(v.x, v.y);
+}
+
+void ptnet_initial_guess(laph_ctx *c, laph_ptnet *net, float bct, const double *eta, int R, double2 *xo)
+{
+    long V = c->g.V, n = V * 12 * R;
+    float2 *a = (float2 *)ctx_named(c, "net.x0in", sizeof(float2) * n);
+    float2 *b = (float2 *)ctx_named(c, "net.x0out", sizeof(float2) * n);
+    hipLaunchKernelGGL(k_g4_to_net, dim3(nblocks_for(n, 256)), dim3(256), 0, c->stream, (const double2 *)eta, a, n);
+    LAPH_HIP(hipGetLastError());
+    ptnet_forward(c, net, bct, a, b, R, 0);
+    long m = 12 * c->g.Vh * R;
+    hipLaunchKernelGGL(k_net_to_eo_batch, dim3(nblocks_for(m, 256)), dim3(256), 0, c->stream, (const float2 *)b, xo,
+                       1, c->g.ns, V, c->g.Vh, R);
+    LAPH_HIP(hipGetLastError());
+}
+
 // ---------------------------------------------------------------------- C-ABI
 static void upload_weights(laph_ptnet *net, const std::vector<float> &w)
 {

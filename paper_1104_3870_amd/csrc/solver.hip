@@ -1632,8 +1632,11 @@ void solve_batch(laph_ctx *c, const double *eta, double *x, int R, int nreal, co
         hs[q].tol2 = eo_tol[q] * eo_tol[q] * b2;
     }
     write_scal(c, w.sc, hs);
-    // x_hi = 0, r_hi = bhat
-    LAPH_HIP(hipMemsetAsync(xo.d, 0, (size_t)12 * Vh * R * 16, c->stream));
+    // x_hi = 0 or the network's guess, r_hi = bhat
+    if (sv->net && sv->solver != LAPH_SOLVER_FGMRES)
+        ptnet_initial_guess(c, (laph_ptnet *)sv->net, (float)dc.prm.bc_t, eta, R, (double2 *)xo.d);
+    else
+        LAPH_HIP(hipMemsetAsync(xo.d, 0, (size_t)12 * Vh * R * 16, c->stream));
     launch_el(c, k_copy64, n, bhat, rhi, Vh, R, (const Scal *)w.sc, 1);
 
     std::vector<int> iters(R, 0), fallback(R, 0);
@@ -1829,12 +1832,14 @@ extern "C" int dirac_solve(laph_ctx_t c, const double *U, const laph_dirac *d, c
                LAPH_EINVAL, "unknown solver kind");
     LAPH_CHECK(sv->block_rhs >= 0, LAPH_EINVAL, "block_rhs must be >= 0");
     int R = sv->block_rhs;
-    if (sv->solver == LAPH_SOLVER_FGMRES) {
+    if (sv->solver == LAPH_SOLVER_FGMRES || sv->net) {
         laph_ptnet *net = (laph_ptnet *)sv->net;
         LAPH_CHECK(net && net->layers > 0, LAPH_EINVAL, "FGMRES needs a network");
         LAPH_CHECK(net->device == c->device, LAPH_EINVAL, "network and context on different devices");
-        LAPH_CHECK(sv->restart >= 0 && sv->restart <= 256, LAPH_EINVAL, "restart must be in 0..256");
         ptnet_links(c, net, U);
+    }
+    if (sv->solver == LAPH_SOLVER_FGMRES) {
+        LAPH_CHECK(sv->restart >= 0 && sv->restart <= 256, LAPH_EINVAL, "restart must be in 0..256");
         R = 1;  // one right-hand side at a time
     }
     LAPH_CHECK(R <= 32 && (R & (R - 1)) == 0, LAPH_EINVAL, "block_rhs must be 0 or a power of two <= 32");

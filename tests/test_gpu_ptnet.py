@@ -238,3 +238,62 @@ def test_fgmres_zero_net_falls_back(P):
     assert st[0].status == 0 and st[0].fallback_used == 1
     assert tr <= 1e-10
     net.close()
+
+
+@pytest.mark.parametrize("prec", ["f16", "f64"])
+def test_network_initial_guess(P, prec):
+    """With CG on the normal equations the network supplies the initial guess (odd part of
+    N(gamma_4 eta)); the answer is judged as always."""
+    import torch
+
+    cfg = synth.CONFIGS["cfg0"]
+    say("network initial guess", prec)
+    U = synth.gauge_field(cfg.ns, cfg.nt, cfg.eps, cfg.seed)
+    D = oracle.Dirac(U, cfg.m0, cfg.xi, cfg.csw, cfg.bc_t)
+    etas = synth.random_spinor(cfg.ns, cfg.nt, 33, nrhs=4)
+    L = P.Lattice(cfg.ns, cfg.nt)
+    net = P.PTNet(L.ctx, CH, seed=6)
+    prm = P.laph_dirac(cfg.m0, cfg.xi, cfg.csw, cfg.bc_t)
+    x = torch.empty(etas.shape, dtype=torch.complex128, device="cuda")
+    sv = P.solver_params(tol=1e-10, maxiter=2000, precision=prec, block_rhs=4, solver=P.LAPH_SOLVER_CGNR, net=net)
+    st = P.dirac_solve(L.ctx, dev(U), prm, dev(etas), x, 4, sv)
+    xh = host(x)
+    for r in range(4):
+        tr = D.true_residual(etas[r], xh[r])
+        say("  rhs", r, "iters", st[r].iters, "oracle resid", tr)
+        assert st[r].status == 0 and tr <= 1e-10
+    net.close()
+
+
+def test_trained_network_gain_held_out(P):
+    """What training buys: on a held-out field (seed 200, never seen in training), FGMRES
+    with the committed trained weights needs at most half the iterations it needs with
+    the untrained network of the same shape, both reaching the true residual 1e-10."""
+    import torch
+
+    from paper_1104_3870_amd import train_ptnet as T
+
+    w, meta = T.load(T.os.path.join(T.ROOT, "paper_1104_3870_amd", "weights", "ptnet.npz"))
+    ns, nt = meta["lattice"]
+    cfg = synth.CONFIGS[meta["workload"]]
+    say("trained network gain, held-out seed 200 on", ns, nt)
+    U = synth.gauge_field(ns, nt, cfg.eps, 200)
+    D = oracle.Dirac(U, cfg.m0, cfg.xi, cfg.csw, cfg.bc_t)
+    eta = synth.random_spinor(ns, nt, 1200, nrhs=1)
+    L = P.Lattice(ns, nt)
+    prm = P.laph_dirac(cfg.m0, cfg.xi, cfg.csw, cfg.bc_t)
+    iters = {}
+    for name in ("trained", "untrained"):
+        net = P.PTNet(L.ctx, meta["channels"], seed=0)
+        if name == "trained":
+            net.set_weights(w)
+        x = torch.empty(eta.shape, dtype=torch.complex128, device="cuda")
+        sv = P.solver_params(tol=1e-10, maxiter=3000, solver=P.LAPH_SOLVER_FGMRES, net=net, restart=32)
+        st = P.dirac_solve(L.ctx, dev(U), prm, dev(eta), x, 1, sv)
+        tr = D.true_residual(eta[0], host(x)[0])
+        say("  ", name, "iters", st[0].iters, "fallback", st[0].fallback_used, "oracle resid", tr)
+        assert st[0].status == 0 and st[0].fallback_used == 0 and tr <= 1e-10
+        iters[name] = st[0].iters
+        net.close()
+    assert iters["trained"] <= 0.5 * iters["untrained"]
+

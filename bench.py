@@ -297,6 +297,8 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic["bytes_per_launch"] if traffic else None,
                 "traffic_source": traffic["source"] if traffic else None,
+                "traffic_rate_frac": (round(traffic["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                      if traffic and avg_ms > 0 else None),
                 "kernel": dom["kernel"], "avg_launch_ms": round(avg_ms, 4), "launches": dom["launches"],
                 "algorithmic_bytes_per_launch": bytes_per_launch,
                 "share_of_timed_region": round(dom["ms"] / (1000 * elapsed), 3),

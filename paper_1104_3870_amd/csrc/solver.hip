@@ -518,6 +518,25 @@ __device__ __forceinline__ double sum_partials_rmajor(const double *partial, int
     return lds[0];
 }
 
+// partial[r][nblk] -> out[r][nchunk], chunk ch = fixed-order sum of its contiguous share of
+// the partials (the first stage of a deterministic two-stage reduction)
+constexpr int kChunks = 64;
+__global__ __launch_bounds__(kBS) void k_prereduce(const double *partial, int nblk, double *out)
+{
+    const int r = blockIdx.y, ch = blockIdx.x;
+    const long beg = (long)nblk * ch / kChunks, end = (long)nblk * (ch + 1) / kChunks;
+    double v = 0;
+    for (long b = beg + threadIdx.x; b < end; b += kBS) v += partial[(long)r * nblk + b];
+    __shared__ double lds[kBS];
+    lds[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kBS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(long)r * kChunks + ch] = lds[0];
+}
+
 // rmajor: partials of the fused hopping epilogue (one value per block and RHS)
 __global__ void k_fin_cg_alpha(const double *partial, int nblk, int R, Scal *sc, int rmajor)
 {
@@ -1105,20 +1124,26 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
     // low precision with the LDS-staged kernel: |q|^2 and the first step of M^dag q come
     // from the epilogue of the hop that forms q
     const bool fuse = !plain && lds_dag_ok(c, w.R);
-    double *part_hop = nullptr;
+    double *part_hop = nullptr, *part_pre = nullptr;
     int nblk_hop = 0;
     if (fuse) {
         nblk_hop = (int)lds_dag_blocks(c, prec_of<SP>(), w.R);
         part_hop = (double *)ctx_named(c, "slv.part_hop", sizeof(double) * nblk_hop * w.R);
+        part_pre = (double *)ctx_named(c, "slv.part_pre", sizeof(double) * kChunks * w.R);
     }
     auto body = [&](const Op<SP, GP, CP> &op) {
         if (fuse) {
             // M p with |q|^2 and A^-1 gamma_5 q from its epilogue; M^dag q feeding the CG
-            // update directly (partials of the fused epilogues are RHS-major)
+            // update directly (partials of the fused epilogues are RHS-major, pre-reduced
+            // to kChunks per RHS)
             op.mhat_prep(p, q, to, part_hop);
-            launch_fin(c, k_fin_cg_alpha, w.R, (const double *)part_hop, nblk_hop, w.R, w.sc, 1);
+            hipLaunchKernelGGL(k_prereduce, dim3(kChunks, w.R), dim3(kBS), 0, c->stream, (const double *)part_hop,
+                               nblk_hop, part_pre);
+            launch_fin(c, k_fin_cg_alpha, w.R, (const double *)part_pre, kChunks, w.R, w.sc, 1);
             op.mhat_dag_cg(q, to, xlo, p, r, (const Scal *)w.sc, part_hop);
-            launch_fin(c, k_fin_cg_beta, w.R, (const double *)part_hop, nblk_hop, w.R, w.sc, 0, 1, 1);
+            hipLaunchKernelGGL(k_prereduce, dim3(kChunks, w.R), dim3(kBS), 0, c->stream, (const double *)part_hop,
+                               nblk_hop, part_pre);
+            launch_fin(c, k_fin_cg_beta, w.R, (const double *)part_pre, kChunks, w.R, w.sc, 0, 1, 1);
         } else {
             op.mhat(p, q);
             launch_red(c, k_normsq<SP>, n, q, w.Vh, w.R, w.part);

@@ -219,16 +219,13 @@ __device__ __forceinline__ void do_dir(const MrArgs &P, const float4 *lk, int x,
 #else
 #define LAPH_MR_ATTR
 #endif
-// the LDS-staged kernel: at most 128 VGPRs, 4 waves per SIMD (measured faster than 3 waves
-// without the cap), except the clover-inverse epilogue, which would spill under the cap:
-// its scratch traffic slowed the kernels after it more than the occupancy helped
+// the LDS-staged kernel runs at 3 waves per SIMD (at most 168 VGPRs): with the
+// pipelined neighbour loads every epilogue fits without spills, and this measured faster
+// than 4 waves under the 128-VGPR cap
 #ifndef LAPH_LDS_WAVES
-#define LAPH_LDS_WAVES 4
+#define LAPH_LDS_WAVES 3
 #endif
-#ifndef LAPH_LDS_WAVES_INV
-#define LAPH_LDS_WAVES_INV 3
-#endif
-#define LAPH_LDS_ATTR __attribute__((amdgpu_waves_per_eu(MODE == M_INV_AFTER ? LAPH_LDS_WAVES_INV : LAPH_LDS_WAVES)))
+#define LAPH_LDS_ATTR __attribute__((amdgpu_waves_per_eu(LAPH_LDS_WAVES)))
 
 template <class SP, int NR, int MODE>
 __global__ __launch_bounds__(256) LAPH_MR_ATTR void k_dslash_mr(const MrArgs P)
@@ -366,25 +363,13 @@ __device__ __forceinline__ Cx<float> proj(const typename SP::E &a, const typenam
         return {fmaf(are, sc, fmaf(bim, -(float)KI * sc, 0.0f)), fmaf(aim, sc, fmaf(bre, (float)KI * sc, 0.0f))};
 }
 
+// spin projection of a neighbour record: h0, h1 are the two independent colour vectors
+// of (1 -+ gamma_mu) psi (FWD: 1 - gamma_mu, backward: 1 + gamma_mu), scale applied
 template <int MU, bool FWD, class SP>
-__device__ __forceinline__ void hop_lds(const float4 *lk, const Spin12<SP> &sp, float sc, Cx<float> (&acc)[4][3])
+__device__ __forceinline__ void proj_lds(const Spin12<SP> &sp, float sc, Cx<float> (&h0)[3], Cx<float> (&h1)[3])
 {
-    Cx<float> U[9];
-    {
-        float4 a = lk[0], b = lk[1], c = lk[2], d = lk[3], e = lk[4];
-        U[0] = {a.x, a.y};
-        U[1] = {a.z, a.w};
-        U[2] = {b.x, b.y};
-        U[3] = {b.z, b.w};
-        U[4] = {c.x, c.y};
-        U[5] = {c.z, c.w};
-        U[6] = {d.x, d.y};
-        U[7] = {d.z, d.w};
-        U[8] = {e.x, e.y};
-    }
     const auto *v = sp.v;  // v[alpha * 3 + c]
     constexpr int sg = FWD ? 1 : -1;
-    Cx<float> h0[3], h1[3], o0[3], o1[3];
 #pragma unroll
     for (int c = 0; c < 3; c++) {
         if (MU == 0) {
@@ -401,14 +386,26 @@ __device__ __forceinline__ void hop_lds(const float4 *lk, const Spin12<SP> &sp, 
             h1[c] = proj<SP, -sg, 0>(v[3 + c], v[9 + c], sc);
         }
     }
+}
+
+// staged link (weights folded in, backward links as their adjoint) times h0, h1, and the
+// reconstruction of the lower spin components into acc
+template <int MU, bool FWD>
+__device__ __forceinline__ void mult_lds(const float4 *lk, const Cx<float> (&h0)[3], const Cx<float> (&h1)[3],
+                                         Cx<float> (&acc)[4][3])
+{
+    const float2 *l2 = reinterpret_cast<const float2 *>(lk);
+    Cx<float> o0[3], o1[3];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        o0[a] = cmul_f(U[a * 3], h0[0]);
-        cfma_f(o0[a], U[a * 3 + 1], h0[1]);
-        cfma_f(o0[a], U[a * 3 + 2], h0[2]);
-        o1[a] = cmul_f(U[a * 3], h1[0]);
-        cfma_f(o1[a], U[a * 3 + 1], h1[1]);
-        cfma_f(o1[a], U[a * 3 + 2], h1[2]);
+        Cx<float> u0 = {l2[a * 3].x, l2[a * 3].y}, u1 = {l2[a * 3 + 1].x, l2[a * 3 + 1].y},
+                  u2 = {l2[a * 3 + 2].x, l2[a * 3 + 2].y};
+        o0[a] = cmul_f(u0, h0[0]);
+        cfma_f(o0[a], u1, h0[1]);
+        cfma_f(o0[a], u2, h0[2]);
+        o1[a] = cmul_f(u0, h1[0]);
+        cfma_f(o1[a], u1, h1[1]);
+        cfma_f(o1[a], u2, h1[2]);
     }
 #pragma unroll
     for (int c = 0; c < 3; c++) {
@@ -430,16 +427,62 @@ __device__ __forceinline__ void hop_lds(const float4 *lk, const Spin12<SP> &sp, 
     }
 }
 
+template <int MU, bool FWD, class SP>
+__device__ __forceinline__ void hop_lds(const float4 *lk, const Spin12<SP> &sp, float sc, Cx<float> (&acc)[4][3])
+{
+    Cx<float> h0[3], h1[3];
+    proj_lds<MU, FWD, SP>(sp, sc, h0, h1);
+    mult_lds<MU, FWD>(lk, h0, h1, acc);
+}
+
+// buffer resource over n bytes at p (raw 32-bit loads; reads past n return zero)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, unsigned n)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)n, 0x00020000);
+}
+
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// neighbour record and its scale (1 without a scale) through buffer loads: one 32-bit
+// offset register per record, the chunk stride R 16 in a scalar register (the caller
+// guarantees Vh R sizeof(record) < 2^32)
+template <class SP>
+__device__ __forceinline__ void ld_nb(__amdgpu_buffer_rsrc_t rin, __amdgpu_buffer_rsrc_t rnrm, int nb, int R, int r,
+                                      Spin12<SP> &sp, float &sc)
+{
+    constexpr int C = sizeof(Spin12<SP>) / 16;
+    const int cs = R * 16;
+    const unsigned off = ((unsigned)nb * (unsigned)(C * R) + (unsigned)r) * 16u;
+#pragma unroll
+    for (int q = 0; q < C; q++) {
+        u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rin, (int)off, q * cs, 0);
+        reinterpret_cast<uint4 *>(&sp)[q] = make_uint4(v.x, v.y, v.z, v.w);
+    }
+    if constexpr (SP::kNorm)
+        sc = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rnrm, (int)(((unsigned)nb * (unsigned)R + (unsigned)r) * 4u), 0, 0));
+    else
+        sc = 1.0f;
+}
+
 // neighbour record of the input field (32-bit site index)
 template <int MU, bool FWD, class SP>
-__device__ __forceinline__ void dir_lds(const MrArgs &P, const float4 *slk, int nb, int R, int r,
-                                        Cx<float> (&acc)[4][3])
+__device__ __forceinline__ void dir_lds(__amdgpu_buffer_rsrc_t rin, __amdgpu_buffer_rsrc_t rnrm, const float4 *slk,
+                                        int nb, int R, int r, Cx<float> (&acc)[4][3])
 {
-    const auto *in = (const typename SP::E *)P.in;
-    Spin12<SP> sp = ld_rec<SP>(in, nb, R, r);
-    float sc = 1.0f;
-    if constexpr (SP::kNorm) sc = P.in_nrm[nb * R + r];
+    Spin12<SP> sp;
+    float sc;
+    ld_nb<SP>(rin, rnrm, nb, R, r, sp, sc);
     hop_lds<MU, FWD, SP>(slk + (FWD ? MU : 4 + MU) * kLkF4, sp, sc, acc);
+}
+
+// neighbour records kept in flight by the software-pipelined direction loop (0: the
+// compiler's own schedule); measured per epilogue on gfx950 at 24^3 x 128, R = 32, FP16:
+// the pipeline shortens the clover-inverse and CG-update forms, the A^-1 gamma_5 epilogue
+// is faster with the compiler's schedule
+template <int MODE>
+constexpr int lds_pipe_depth()
+{
+    return MODE == M_INV_AFTER_DAG ? 0 : 4;
 }
 
 __device__ __forceinline__ void clover_one(const float4 *p, const Cx<float> (&in)[4][3], Cx<float> (&out)[4][3])
@@ -574,14 +617,57 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
 #pragma unroll
         for (int c = 0; c < 3; c++) acc[a][c] = {0.0f, 0.0f};
     const float4 *my = slk + (size_t)sl * 8 * kLkF4;
-    dir_lds<0, true, SP>(P, my, nxp, R, r, acc);
-    dir_lds<0, false, SP>(P, my, nxm, R, r, acc);
-    dir_lds<1, true, SP>(P, my, nyp, R, r, acc);
-    dir_lds<1, false, SP>(P, my, nym, R, r, acc);
-    dir_lds<2, true, SP>(P, my, nzp, R, r, acc);
-    dir_lds<2, false, SP>(P, my, nzm, R, r, acc);
-    dir_lds<3, true, SP>(P, my, ntp, R, r, acc);
-    dir_lds<3, false, SP>(P, my, ntm, R, r, acc);
+    const __amdgpu_buffer_rsrc_t rin = buf_rsrc(P.in, (unsigned)(Vh * R * sizeof(Spin12<SP>)));
+    const __amdgpu_buffer_rsrc_t rnrm = buf_rsrc(P.in_nrm, SP::kNorm ? (unsigned)(Vh * R * 4) : 0u);
+    constexpr int D = lds_pipe_depth<MODE>();
+    if constexpr (D > 0) {
+        // D neighbour records in flight: the slot a direction's spin projection frees is
+        // refilled with the record D directions ahead before that direction's link product,
+        // so the loads overlap the arithmetic (scheduling fences keep this order)
+        const int nbs[8] = {nxp, nxm, nyp, nym, nzp, nzm, ntp, ntm};
+        Spin12<SP> bs[D];
+        float cs[D];
+#pragma unroll
+        for (int k = 0; k < D; k++) ld_nb<SP>(rin, rnrm, nbs[k], R, r, bs[k], cs[k]);
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            Cx<float> h0[3], h1[3];
+            __builtin_amdgcn_sched_barrier(0);
+            switch (k) {
+            case 0: proj_lds<0, true, SP>(bs[k % D], cs[k % D], h0, h1); break;
+            case 1: proj_lds<0, false, SP>(bs[k % D], cs[k % D], h0, h1); break;
+            case 2: proj_lds<1, true, SP>(bs[k % D], cs[k % D], h0, h1); break;
+            case 3: proj_lds<1, false, SP>(bs[k % D], cs[k % D], h0, h1); break;
+            case 4: proj_lds<2, true, SP>(bs[k % D], cs[k % D], h0, h1); break;
+            case 5: proj_lds<2, false, SP>(bs[k % D], cs[k % D], h0, h1); break;
+            case 6: proj_lds<3, true, SP>(bs[k % D], cs[k % D], h0, h1); break;
+            default: proj_lds<3, false, SP>(bs[k % D], cs[k % D], h0, h1); break;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            if (k + D < 8) ld_nb<SP>(rin, rnrm, nbs[k + D], R, r, bs[k % D], cs[k % D]);
+            __builtin_amdgcn_sched_barrier(0);
+            const float4 *lk = my + ((k & 1) ? 4 + (k >> 1) : (k >> 1)) * kLkF4;
+            switch (k) {
+            case 0: mult_lds<0, true>(lk, h0, h1, acc); break;
+            case 1: mult_lds<0, false>(lk, h0, h1, acc); break;
+            case 2: mult_lds<1, true>(lk, h0, h1, acc); break;
+            case 3: mult_lds<1, false>(lk, h0, h1, acc); break;
+            case 4: mult_lds<2, true>(lk, h0, h1, acc); break;
+            case 5: mult_lds<2, false>(lk, h0, h1, acc); break;
+            case 6: mult_lds<3, true>(lk, h0, h1, acc); break;
+            default: mult_lds<3, false>(lk, h0, h1, acc); break;
+            }
+        }
+    } else {
+        dir_lds<0, true, SP>(rin, rnrm, my, nxp, R, r, acc);
+        dir_lds<0, false, SP>(rin, rnrm, my, nxm, R, r, acc);
+        dir_lds<1, true, SP>(rin, rnrm, my, nyp, R, r, acc);
+        dir_lds<1, false, SP>(rin, rnrm, my, nym, R, r, acc);
+        dir_lds<2, true, SP>(rin, rnrm, my, nzp, R, r, acc);
+        dir_lds<2, false, SP>(rin, rnrm, my, nzm, R, r, acc);
+        dir_lds<3, true, SP>(rin, rnrm, my, ntp, R, r, acc);
+        dir_lds<3, false, SP>(rin, rnrm, my, ntm, R, r, acc);
+    }
     if (P.g5d) {
 #pragma unroll
         for (int c = 0; c < 3; c++) {
@@ -772,7 +858,11 @@ static bool use_lds_kernel()
     return v == 1;
 }
 
-bool lds_dag_ok(laph_ctx *c, int R) { return use_lds_kernel() && c->g.Vh * R * 12 < (1L << 31); }
+// the LDS-staged kernel indexes sites in 32 bits and reads neighbour records through
+// 32-bit byte offsets
+static bool lds_fits(long Vh, int R, long rec_bytes) { return Vh * R * 12 < (1L << 31) && Vh * R * rec_bytes < (1L << 32); }
+
+bool lds_dag_ok(laph_ctx *c, int R) { return use_lds_kernel() && lds_fits(c->g.Vh, R, 96); }
 
 long lds_dag_blocks(laph_ctx *c, int prec, int R)
 {
@@ -783,7 +873,7 @@ long lds_dag_blocks(laph_ctx *c, int prec, int R)
 template <class SP>
 void launch_dslash_mr(laph_ctx *c, int mode, const MrArgs &a, hipStream_t st)
 {
-    if (use_lds_kernel() && a.Vh * a.R * 12 < (1L << 31)) {
+    if (use_lds_kernel() && lds_fits(a.Vh, a.R, sizeof(Spin12<SP>))) {
         const int S = lds_tile_sites(c, prec_id<SP>(), a.R);
         dim3 grid(nblocks_for(a.Vh, S)), block(S * a.R);
         hipEvent_t e0, e1;

@@ -21,17 +21,14 @@ struct MrArgs {
     double wt, ws, bct;
     int g5d;
     // M_INV_AFTER_DAG: second output A^-1 gamma_5 out (same parity and layout as out).
-    // M_PLAIN_CG: out is not stored; for active right-hand sides cg_x += alpha cg_p and
-    // cg_r -= alpha out (alpha and the mask from sc[r]).  Both write
-    // partial[r * nblocks + block] = sum over the block's sites of |out_r|^2 (DAG) or
-    // |cg_r|^2 after the update (CG), from the stored values.
+    // M_PLAIN_CG: out is not stored; for active right-hand sides cg_r -= alpha out (alpha
+    // and the mask from sc[r]).  Both write partial[r * nblocks + block] = sum over the
+    // block's sites of |out_r|^2 (DAG) or |cg_r|^2 after the update (CG), from the stored
+    // values.
     void *out2;
     float *out2_nrm;
     double *partial;
     const Scal *sc;
-    void *cg_x;  // FP32 records (solution increment)
-    const void *cg_p;
-    const float *cg_p_nrm;
     void *cg_r;
     float *cg_r_nrm;
 };

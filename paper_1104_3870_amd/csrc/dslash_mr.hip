@@ -714,16 +714,11 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
         for (int k = 0; k < 12; k++) v[k] = ic * o2[k / 3][k % 3];
         st_spinor12<SP, float>((typename SP::E *)P.out2, P.out2_nrm, Vh, R, i, r, v);
     } else if constexpr (MODE == M_PLAIN_CG) {
-        // CG update of the normal equations: x += alpha p, r -= alpha out; |r|^2 of the
-        // stored residual (the increment x is kept in FP32)
+        // residual update of CG on the normal equations, r -= alpha out; |r|^2 of the
+        // stored residual (the solution increment follows in the direction update)
         if (P.sc[r].active) {
             const float al = (float)P.sc[r].alpha.x;
-            Cx<float> a[12], b[12];
-            ld_spinor12<S32, float>((const float2 *)P.cg_x, nullptr, Vh, R, i, r, a);
-            ld_spinor12<SP, float>((const typename SP::E *)P.cg_p, P.cg_p_nrm, Vh, R, i, r, b);
-#pragma unroll
-            for (int k = 0; k < 12; k++) a[k] = {fmaf(al, b[k].re, a[k].re), fmaf(al, b[k].im, a[k].im)};
-            st_spinor12<S32, float>((float2 *)P.cg_x, nullptr, Vh, R, i, r, a);
+            Cx<float> a[12];
             ld_spinor12<SP, float>((const typename SP::E *)P.cg_r, P.cg_r_nrm, Vh, R, i, r, a);
 #pragma unroll
             for (int k = 0; k < 12; k++) a[k] = {fmaf(-al, v[k].re, a[k].re), fmaf(-al, v[k].im, a[k].im)};
@@ -817,12 +812,10 @@ double dslash_mr_bytes(long Vh, int R, int sbytes, bool has_norm, int mode, bool
 {
     double site = 8.0 * 48;  // reconstruct-12 FP32 links
     if (mode == M_INV_AFTER || mode == M_INV_AFTER_DAG) site += 72.0 * 4;
-    // in, out[, x][, out2]; the CG form reads p and r and writes r instead of out, and reads
-    // and writes the FP32 increment
+    // in, out[, x][, out2]; the CG form also reads r (and writes it instead of out)
     int streams = 2 + (has_x ? 1 : 0) + (mode == M_INV_AFTER_DAG ? 1 : 0);
-    if (mode == M_PLAIN_CG) streams += 2;
+    if (mode == M_PLAIN_CG) streams += 1;
     double per_rhs = 12.0 * sbytes * streams + (has_norm ? 4.0 * streams : 0.0);
-    if (mode == M_PLAIN_CG) per_rhs += 2 * 96.0;
     return (double)Vh * (site + R * per_rhs);
 }
 

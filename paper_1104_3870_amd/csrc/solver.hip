@@ -357,6 +357,33 @@ __global__ __launch_bounds__(kBS) void k_fold_x(Vec xhi, Vec xlo, long Vh, int R
     st_site<XP>(xlo, Vh, R, i, rr, z);
 }
 
+// the same fold with the pending step of the current iteration, xhi += xlo + alpha p
+// (right-hand sides with mask set)
+template <class XP, class SP>
+__global__ __launch_bounds__(kBS) void k_fold_x_step(Vec xhi, Vec xlo, Vec p, long Vh, int R, const Scal *sc)
+{
+    long n = Vh * R;
+    long tid = blockIdx.x * (long)kBS + threadIdx.x;
+    if (tid >= n) return;
+    long i = tid / R;
+    int rr = (int)(tid - i * R);
+    if (!sc[rr].active) return;
+    const double al = sc[rr].alpha.x;
+    Cx<double> a[12], b[12], z[12];
+    ld_site<S64>(xhi, Vh, R, i, rr, a);
+    ld_site<XP>(xlo, Vh, R, i, rr, b);
+#pragma unroll
+    for (int k = 0; k < 12; k++) a[k] = a[k] + b[k];
+    ld_site<SP>(p, Vh, R, i, rr, b);
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        a[k] = a[k] + al * b[k];
+        z[k] = {0, 0};
+    }
+    st_site<S64>(xhi, Vh, R, i, rr, a);
+    st_site<XP>(xlo, Vh, R, i, rr, z);
+}
+
 // r = b - m (FP64), partial |r|^2; restricted to masked right-hand sides unless all_rhs
 __global__ __launch_bounds__(kBS) void k_resid64(Vec b, Vec m, Vec r, long Vh, int R, double *partial,
                                                  const Scal *sc, int all_rhs)
@@ -638,9 +665,10 @@ __global__ void k_fin_cg_beta(const double *partial, int nblk, int R, Scal *sc, 
     if (hi_conv && (s[1] <= q.tol2 || !(s[0] > 0))) q.active = 0;
 }
 
-// p = r + beta p (real beta)
-template <class SP>
-__global__ __launch_bounds__(kBS) void k_cg_p(Vec p, Vec r, long Vh, int R, const Scal *sc)
+// p = r + beta p (real beta); with x_upd the solution increment first takes the step
+// along the old direction, x += alpha p
+template <class SP, class XP>
+__global__ __launch_bounds__(kBS) void k_cg_p(Vec p, Vec r, Vec x, long Vh, int R, const Scal *sc, int x_upd)
 {
     long n = Vh * R;
     long tid = blockIdx.x * (long)kBS + threadIdx.x;
@@ -651,6 +679,13 @@ __global__ __launch_bounds__(kBS) void k_cg_p(Vec p, Vec r, long Vh, int R, cons
     double be = sc[rr].beta.x;
     Cx<double> a[12], b[12];
     ld_site<SP>(p, Vh, R, i, rr, a);
+    if (x_upd) {
+        const double al = sc[rr].alpha.x;
+        ld_site<XP>(x, Vh, R, i, rr, b);
+#pragma unroll
+        for (int k = 0; k < 12; k++) b[k] = b[k] + al * a[k];
+        st_site<XP>(x, Vh, R, i, rr, b);
+    }
     ld_site<SP>(r, Vh, R, i, rr, b);
 #pragma unroll
     for (int k = 0; k < 12; k++) a[k] = b[k] + be * a[k];
@@ -905,18 +940,15 @@ struct Op {
         dslash(M_INV_AFTER, 0, to, te, nullptr, 0.0, 1.0, 0);
         dslash(M_PLAIN, 1, te, out, &in, 1.0, -1.0, 1);
     }
-    // mhat_dag_rest whose last hop feeds the CG update x += alpha p, r -= alpha (M^dag in)
+    // mhat_dag_rest whose last hop feeds the CG residual update r -= alpha (M^dag in)
     // directly (low precision, LDS-staged kernel); per-block |r|^2 partials
-    void mhat_dag_cg(Vec in, Vec to, Vec x, Vec p, Vec r, const Scal *sc, double *partial) const
+    void mhat_dag_cg(Vec in, Vec to, Vec r, const Scal *sc, double *partial) const
     {
         dslash(M_INV_AFTER, 0, to, te, nullptr, 0.0, 1.0, 0);
         if constexpr (kLow) {
             MrArgs m = mr_args(1, te, Vec{}, &in, 1.0, -1.0, 1);
             m.partial = partial;
             m.sc = sc;
-            m.cg_x = x.d;
-            m.cg_p = p.d;
-            m.cg_p_nrm = p.n;
             m.cg_r = r.d;
             m.cg_r_nrm = r.n;
             launch_dslash_mr<SP>(c, M_PLAIN_CG, m, st);
@@ -1140,7 +1172,7 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
             hipLaunchKernelGGL(k_prereduce, dim3(kChunks, w.R), dim3(kBS), 0, c->stream, (const double *)part_hop,
                                nblk_hop, part_pre);
             launch_fin(c, k_fin_cg_alpha, w.R, (const double *)part_pre, kChunks, w.R, w.sc, 1);
-            op.mhat_dag_cg(q, to, xlo, p, r, (const Scal *)w.sc, part_hop);
+            op.mhat_dag_cg(q, to, r, (const Scal *)w.sc, part_hop);
             hipLaunchKernelGGL(k_prereduce, dim3(kChunks, w.R), dim3(kBS), 0, c->stream, (const double *)part_hop,
                                nblk_hop, part_pre);
             launch_fin(c, k_fin_cg_beta, w.R, (const double *)part_pre, kChunks, w.R, w.sc, 0, 1, 1);
@@ -1158,8 +1190,9 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
             launch_fin(c, k_fin_cg_beta, w.R, (const double *)w.part, nblk, w.R, w.sc, plain ? 1 : 0, plain ? 0 : 1,
                        0);
         }
-        if (plain) launch_el(c, k_cg_p<SP>, n, p, r, w.Vh, w.R, (const Scal *)w.sc);
+        if (plain) launch_el(c, k_cg_p<SP, XP>, n, p, r, xlo, w.Vh, w.R, (const Scal *)w.sc, 0);
     };
+    bool x_pending = false;
     hipGraphExec_t gexec = nullptr;
     const bool graph_ok = w.use_graph && !c->timing;
     if (graph_ok && !c->cap_stream) LAPH_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
@@ -1202,6 +1235,7 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
         }
         it += chunk;
         since += chunk;
+        x_pending = fuse;  // the fused body leaves x += alpha p to the direction update
         read_scal(c, w.sc, hs);
         bool any = false, want_update = false;
         int nact = 0;
@@ -1225,7 +1259,11 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
             // and keep the old direction orthogonal to the new residual
             // FP64 true residual of the even-odd system; the normal residual M^dag res is
             // computed by the low-precision operator, in which r is stored anyway
-            launch_el(c, k_fold_x<XP>, n, xhi, xlo, w.Vh, w.R, (const Scal *)w.sc, 0);
+            if (fuse)  // the fused form takes the step x += alpha p with the direction update
+                launch_el(c, k_fold_x_step<XP, SP>, n, xhi, xlo, p, w.Vh, w.R, (const Scal *)w.sc);
+            else
+                launch_el(c, k_fold_x<XP>, n, xhi, xlo, w.Vh, w.R, (const Scal *)w.sc, 0);
+            x_pending = false;
             true_eo_residual(w, hi, bhat, xhi, tmp64, reshi, 0);
             launch_el(c, k_convert_masked<SP>, n, reshi, res, w.Vh, w.R, (const Scal *)w.sc);
             lo.mhat_dag(res, r, to);
@@ -1243,7 +1281,7 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
             }
             if (!left) break;
         }
-        launch_el(c, k_cg_p<SP>, n, p, r, w.Vh, w.R, (const Scal *)w.sc);
+        launch_el(c, k_cg_p<SP, XP>, n, p, r, xlo, w.Vh, w.R, (const Scal *)w.sc, x_pending ? 1 : 0);
     }
     launch_el(c, k_fold_x<XP>, n, xhi, xlo, w.Vh, w.R, (const Scal *)w.sc, 1);
 }

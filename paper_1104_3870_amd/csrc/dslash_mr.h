@@ -31,6 +31,17 @@ struct MrArgs {
     const Scal *sc;
     void *cg_r;
     float *cg_r_nrm;
+    // order in which the LDS-staged kernel visits output sites: wby = 0 walks the
+    // checkerboard index; otherwise spatial tiles of ns x wby x wbz sites are walked slice
+    // by slice through all time slices, one tile after the other
+    int wby, wbz;
+    // multiply-high reciprocals of the kernel's index divisors (ns/2, ns, nt, wby,
+    // ns/wby, ns/2 wby wbz): q = umulhi(n, m) is n / d for every n the kernel divides
+    // (the launcher checks Vh d < 2^32); 0: plain division
+    unsigned m_nsh, m_ns, m_nt, m_by, m_nty, m_A;
+    // 1.0, passed at run time: a + (+-unit) b stays one mixed-precision FMA per component
+    // for FP16 records instead of being folded into two conversions and an add
+    float unit;
 };
 
 // mode: M_PLAIN (out = c D psi [+ a x]) or M_INV_AFTER (out = a x + c A^-1 D psi)

@@ -351,48 +351,63 @@ __device__ __forceinline__ float hi_f(const typename SP::E &e)
         return SP::ld(&e, 0, 1.0f).im;
 }
 
-// h = sc (a + K b) for K = KR + i KI in {+-1, +-i}; with FP16 storage every term is one
-// mixed-precision FMA (conversion and scale fused)
+// h = a + K b for K = KR + i KI in {+-1, +-i} (the record's scale is applied when the
+// link product is accumulated); with FP16 storage every term is one mixed-precision FMA
 template <class SP, int KR, int KI>
-__device__ __forceinline__ Cx<float> proj(const typename SP::E &a, const typename SP::E &b, float sc)
+__device__ __forceinline__ Cx<float> proj(const typename SP::E &a, const typename SP::E &b, float unit)
 {
     const float are = lo_f<SP>(a), aim = hi_f<SP>(a), bre = lo_f<SP>(b), bim = hi_f<SP>(b);
     if constexpr (KI == 0)
-        return {fmaf(are, sc, fmaf(bre, (float)KR * sc, 0.0f)), fmaf(aim, sc, fmaf(bim, (float)KR * sc, 0.0f))};
+        return {fmaf(bre, (float)KR * unit, are), fmaf(bim, (float)KR * unit, aim)};
     else
-        return {fmaf(are, sc, fmaf(bim, -(float)KI * sc, 0.0f)), fmaf(aim, sc, fmaf(bre, (float)KI * sc, 0.0f))};
+        return {fmaf(bim, -(float)KI * unit, are), fmaf(bre, (float)KI * unit, aim)};
+}
+
+// acc += s K o for K = KR + i KI in {+-1, +-i}
+template <int KR, int KI>
+__device__ __forceinline__ void acc_k(Cx<float> &acc, float s, Cx<float> o)
+{
+    if constexpr (KI == 0) {
+        acc.re = fmaf((float)KR * s, o.re, acc.re);
+        acc.im = fmaf((float)KR * s, o.im, acc.im);
+    } else {
+        acc.re = fmaf(-(float)KI * s, o.im, acc.re);
+        acc.im = fmaf((float)KI * s, o.re, acc.im);
+    }
 }
 
 // spin projection of a neighbour record: h0, h1 are the two independent colour vectors
-// of (1 -+ gamma_mu) psi (FWD: 1 - gamma_mu, backward: 1 + gamma_mu), scale applied
+// of (1 -+ gamma_mu) psi (FWD: 1 - gamma_mu, backward: 1 + gamma_mu), unscaled
 template <int MU, bool FWD, class SP>
-__device__ __forceinline__ void proj_lds(const Spin12<SP> &sp, float sc, Cx<float> (&h0)[3], Cx<float> (&h1)[3])
+__device__ __forceinline__ void proj_lds(const Spin12<SP> &sp, float unit, Cx<float> (&h0)[3], Cx<float> (&h1)[3])
 {
     const auto *v = sp.v;  // v[alpha * 3 + c]
     constexpr int sg = FWD ? 1 : -1;
 #pragma unroll
     for (int c = 0; c < 3; c++) {
         if (MU == 0) {
-            h0[c] = proj<SP, 0, sg>(v[c], v[9 + c], sc);
-            h1[c] = proj<SP, 0, sg>(v[3 + c], v[6 + c], sc);
+            h0[c] = proj<SP, 0, sg>(v[c], v[9 + c], unit);
+            h1[c] = proj<SP, 0, sg>(v[3 + c], v[6 + c], unit);
         } else if (MU == 1) {
-            h0[c] = proj<SP, sg, 0>(v[c], v[9 + c], sc);
-            h1[c] = proj<SP, -sg, 0>(v[3 + c], v[6 + c], sc);
+            h0[c] = proj<SP, sg, 0>(v[c], v[9 + c], unit);
+            h1[c] = proj<SP, -sg, 0>(v[3 + c], v[6 + c], unit);
         } else if (MU == 2) {
-            h0[c] = proj<SP, 0, sg>(v[c], v[6 + c], sc);
-            h1[c] = proj<SP, 0, -sg>(v[3 + c], v[9 + c], sc);
+            h0[c] = proj<SP, 0, sg>(v[c], v[6 + c], unit);
+            h1[c] = proj<SP, 0, -sg>(v[3 + c], v[9 + c], unit);
         } else {
-            h0[c] = proj<SP, -sg, 0>(v[c], v[6 + c], sc);
-            h1[c] = proj<SP, -sg, 0>(v[3 + c], v[9 + c], sc);
+            h0[c] = proj<SP, -sg, 0>(v[c], v[6 + c], unit);
+            h1[c] = proj<SP, -sg, 0>(v[3 + c], v[9 + c], unit);
         }
     }
 }
 
 // staged link (weights folded in, backward links as their adjoint) times h0, h1, and the
-// reconstruction of the lower spin components into acc
+// reconstruction of all four spin components into acc, each term scaled inside the
+// accumulating FMA: by the record's scale sc (upper components) and sl (lower components:
+// sc, or -sc when gamma_5 follows the hop)
 template <int MU, bool FWD>
-__device__ __forceinline__ void mult_lds(const float4 *lk, const Cx<float> (&h0)[3], const Cx<float> (&h1)[3],
-                                         Cx<float> (&acc)[4][3])
+__device__ __forceinline__ void mult_lds(const float4 *lk, const Cx<float> (&h0)[3], const Cx<float> (&h1)[3], float sc,
+                                         float sl, Cx<float> (&acc)[4][3])
 {
     const float2 *l2 = reinterpret_cast<const float2 *>(lk);
     Cx<float> o0[3], o1[3];
@@ -407,32 +422,34 @@ __device__ __forceinline__ void mult_lds(const float4 *lk, const Cx<float> (&h0)
         cfma_f(o1[a], u1, h1[1]);
         cfma_f(o1[a], u2, h1[2]);
     }
+    constexpr int f = FWD ? 1 : -1;
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        acc[0][c] = acc[0][c] + o0[c];
-        acc[1][c] = acc[1][c] + o1[c];
+        acc_k<1, 0>(acc[0][c], sc, o0[c]);
+        acc_k<1, 0>(acc[1][c], sc, o1[c]);
         if (MU == 0) {
-            acc[2][c] = acc[2][c] + (FWD ? timesMinusI(o1[c]) : timesI(o1[c]));
-            acc[3][c] = acc[3][c] + (FWD ? timesMinusI(o0[c]) : timesI(o0[c]));
+            acc_k<0, -f>(acc[2][c], sl, o1[c]);
+            acc_k<0, -f>(acc[3][c], sl, o0[c]);
         } else if (MU == 1) {
-            acc[2][c] = FWD ? acc[2][c] - o1[c] : acc[2][c] + o1[c];
-            acc[3][c] = FWD ? acc[3][c] + o0[c] : acc[3][c] - o0[c];
+            acc_k<-f, 0>(acc[2][c], sl, o1[c]);
+            acc_k<f, 0>(acc[3][c], sl, o0[c]);
         } else if (MU == 2) {
-            acc[2][c] = acc[2][c] + (FWD ? timesMinusI(o0[c]) : timesI(o0[c]));
-            acc[3][c] = acc[3][c] + (FWD ? timesI(o1[c]) : timesMinusI(o1[c]));
+            acc_k<0, -f>(acc[2][c], sl, o0[c]);
+            acc_k<0, f>(acc[3][c], sl, o1[c]);
         } else {
-            acc[2][c] = FWD ? acc[2][c] - o0[c] : acc[2][c] + o0[c];
-            acc[3][c] = FWD ? acc[3][c] - o1[c] : acc[3][c] + o1[c];
+            acc_k<-f, 0>(acc[2][c], sl, o0[c]);
+            acc_k<-f, 0>(acc[3][c], sl, o1[c]);
         }
     }
 }
 
 template <int MU, bool FWD, class SP>
-__device__ __forceinline__ void hop_lds(const float4 *lk, const Spin12<SP> &sp, float sc, Cx<float> (&acc)[4][3])
+__device__ __forceinline__ void hop_lds(const float4 *lk, const Spin12<SP> &sp, float sc, float g5s, float unit,
+                                        Cx<float> (&acc)[4][3])
 {
     Cx<float> h0[3], h1[3];
-    proj_lds<MU, FWD, SP>(sp, sc, h0, h1);
-    mult_lds<MU, FWD>(lk, h0, h1, acc);
+    proj_lds<MU, FWD, SP>(sp, unit, h0, h1);
+    mult_lds<MU, FWD>(lk, h0, h1, sc, g5s * sc, acc);
 }
 
 // buffer resource over n bytes at p (raw 32-bit loads; reads past n return zero)
@@ -467,22 +484,28 @@ __device__ __forceinline__ void ld_nb(__amdgpu_buffer_rsrc_t rin, __amdgpu_buffe
 // neighbour record of the input field (32-bit site index)
 template <int MU, bool FWD, class SP>
 __device__ __forceinline__ void dir_lds(__amdgpu_buffer_rsrc_t rin, __amdgpu_buffer_rsrc_t rnrm, const float4 *slk,
-                                        int nb, int R, int r, Cx<float> (&acc)[4][3])
+                                        int nb, int R, int r, float g5s, float unit, Cx<float> (&acc)[4][3])
 {
     Spin12<SP> sp;
     float sc;
     ld_nb<SP>(rin, rnrm, nb, R, r, sp, sc);
-    hop_lds<MU, FWD, SP>(slk + (FWD ? MU : 4 + MU) * kLkF4, sp, sc, acc);
+    hop_lds<MU, FWD, SP>(slk + (FWD ? MU : 4 + MU) * kLkF4, sp, sc, g5s, unit, acc);
 }
 
 // neighbour records kept in flight by the software-pipelined direction loop (0: the
-// compiler's own schedule); measured per epilogue on gfx950 at 24^3 x 128, R = 32, FP16:
-// the pipeline shortens the clover-inverse and CG-update forms, the A^-1 gamma_5 epilogue
-// is faster with the compiler's schedule
-template <int MODE>
+// compiler's own schedule), measured on gfx950 at 24^3 x 128, R = 32, FP16: every hop
+// runs the pipeline except those with both the clover-inverse epilogue and an own-site
+// addend, which need more registers than 3 waves per SIMD allow
+#ifndef LAPH_PIPE_D
+#define LAPH_PIPE_D 2
+#endif
+template <int MODE, bool HX>
 constexpr int lds_pipe_depth()
 {
-    return MODE == M_INV_AFTER_DAG ? 0 : 4;
+#ifdef LAPH_PIPE_DAG
+    if (MODE == M_INV_AFTER_DAG) return LAPH_PIPE_DAG;
+#endif
+    return ((MODE == M_INV_AFTER || MODE == M_INV_AFTER_DAG) && HX) ? 0 : LAPH_PIPE_D;
 }
 
 __device__ __forceinline__ void clover_one(const float4 *p, const Cx<float> (&in)[4][3], Cx<float> (&out)[4][3])
@@ -525,7 +548,55 @@ __device__ __forceinline__ void clover_one(const float4 *p, const Cx<float> (&in
 // sites per block for R right-hand sides (block = S R lanes)
 inline size_t lds_bytes(int S) { return (size_t)S * (8 * kLkF4 + 18) * sizeof(float4); }
 
-template <class SP, int MODE>
+// n / d through the launcher's multiply-high reciprocal m (plain division when m = 0)
+__device__ __forceinline__ unsigned udiv(unsigned n, unsigned d, unsigned m)
+{
+    return m ? __umulhi(n, m) : n / d;
+}
+
+// checkerboard index and coordinates of position pos of the site walk (MrArgs::wby):
+// tiles of ns x by x bz sites (full rows) one after the other, each visited slice by slice
+// through all nt time slices, the sites of a tile slice in (x, y, z) order.  The XCD remap
+// gives every XCD one contiguous range of the walk, so the records a slice reads from the
+// slices before and after it were fetched by the same XCD one slice earlier.
+__device__ __forceinline__ int walk_site(const MrArgs &P, unsigned pos, int &x, int &y, int &z, int &t)
+{
+    const unsigned ns = P.ns, nsh = ns >> 1;
+    unsigned xh;
+    if (P.wby == 0) {
+        const unsigned r = udiv(pos, nsh, P.m_nsh), r2 = udiv(r, ns, P.m_ns), r3 = udiv(r2, ns, P.m_ns);
+        xh = pos - r * nsh;
+        y = (int)(r - r2 * ns);
+        z = (int)(r2 - r3 * ns);
+        t = (int)r3;
+    } else {
+        const unsigned by = P.wby, bz = P.wbz, A = nsh * by * bz, nt = P.nt;
+        const unsigned q = udiv(pos, A, P.m_A), loc = pos - q * A;  // q = tile nt + t
+        const unsigned tile = udiv(q, nt, P.m_nt);
+        t = (int)(q - tile * nt);
+        const unsigned q1 = udiv(loc, nsh, P.m_nsh), zz = udiv(q1, by, P.m_by);
+        xh = loc - q1 * nsh;
+        const unsigned nty = ns / by, tz = udiv(tile, nty, P.m_nty);
+        y = (int)((tile - tz * nty) * by + (q1 - zz * by));
+        z = (int)(tz * bz + zz);
+    }
+    x = 2 * (int)xh + ((y + z + t + P.par) & 1);
+    return (int)xh + (int)nsh * (y + (int)ns * (z + (int)ns * t));
+}
+
+#ifndef LAPH_LDS_NT
+#define LAPH_LDS_NT 1
+#endif
+// output records streamed past L2 (1: every epilogue, 2: all but M_INV_AFTER_DAG)
+template <int MODE>
+constexpr bool nt_out()
+{
+    return LAPH_LDS_NT == 1 || (LAPH_LDS_NT == 2 && MODE != M_INV_AFTER_DAG);
+}
+
+// HX: the launch has an own-site addend (P.x); a compile-time switch so that the hops of
+// the CG iteration without one keep the register budget of the pipelined loop
+template <class SP, int MODE, bool HX>
 __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P)
 {
     extern __shared__ float4 smem[];
@@ -535,16 +606,15 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
     float4 *scl = smem + S * 8 * kLkF4;  // [S][18]
     const long Vh = P.Vh;
     const int ns = P.ns, nt = P.nt, par = P.par, opar = par ^ 1;
-    const long site0 = (long)xcd_block(blockIdx.x, gridDim.x) * S;
+    const long pos0 = (long)xcd_block(blockIdx.x, gridDim.x) * S;  // walk position of lane-site 0
     const float4 *lk = (const float4 *)P.links;
     constexpr bool kInv = MODE == M_INV_AFTER || MODE == M_INV_AFTER_DAG;
     const float fout = kInv ? 1.0f : (float)P.c;  // folded into the links
     for (int k = threadIdx.x; k < S * 8; k += blockDim.x) {
         const int sl = k >> 3, d = k & 7, mu = d & 3;
-        const long i = site0 + sl;
-        if (i >= Vh) continue;
+        if (pos0 + sl >= Vh) continue;
         int x, y, z, t;
-        cb_coords(i, par, ns, x, y, z, t);
+        const long i = walk_site(P, (unsigned)(pos0 + sl), x, y, z, t);
         float w = fout * (mu == 3 ? (float)P.wt : (float)P.ws);
         long li;
         if (d < 4) {
@@ -581,14 +651,17 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
         const float4 *cl = (const float4 *)P.clov;
         const float cc = (float)P.c;
         for (int k = threadIdx.x; k < S * 18; k += blockDim.x) {
-            if (site0 + k / 18 >= Vh) continue;
-            float4 v = cl[site0 * 18 + k];
+            const int sl = k / 18;
+            if (pos0 + sl >= Vh) continue;
+            int x, y, z, t;
+            const long i = walk_site(P, (unsigned)(pos0 + sl), x, y, z, t);
+            float4 v = cl[i * 18 + (k - sl * 18)];
             scl[k] = make_float4(cc * v.x, cc * v.y, cc * v.z, cc * v.w);
         }
     }
     __syncthreads();
     const int sl = threadIdx.x / R, r = threadIdx.x - sl * R;
-    const bool valid = sl < S && site0 + sl < Vh;
+    const bool valid = sl < S && pos0 + sl < Vh;
     constexpr bool kRed = MODE == M_INV_AFTER_DAG || MODE == M_PLAIN_CG;  // block reduction
     if constexpr (!kRed) {
         if (!valid) return;
@@ -597,9 +670,8 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
     if (valid) {
     // 32-bit site arithmetic (the host checks Vh * R * 12 < 2^31): neighbour checkerboard
     // indices from the site's own, lex = 2 cb + (x & 1) since Ns is even
-    const int cb = (int)(site0 + sl);
     int x, y, z, t;
-    cb_coords(cb, par, ns, x, y, z, t);
+    const int cb = walk_site(P, (unsigned)(pos0 + sl), x, y, z, t);
     const int sy = ns >> 1, sz = sy * ns, st = sz * ns;
     const int xo = x & 1;
     const int nxp = (x + 1 < ns) ? cb + xo : cb + 1 - sy;
@@ -617,9 +689,11 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
 #pragma unroll
         for (int c = 0; c < 3; c++) acc[a][c] = {0.0f, 0.0f};
     const float4 *my = slk + (size_t)sl * 8 * kLkF4;
+    const float unit = P.unit;
+    const float g5s = P.g5d ? -1.0f : 1.0f;  // gamma_5 after the hop: lower components negated
     const __amdgpu_buffer_rsrc_t rin = buf_rsrc(P.in, (unsigned)(Vh * R * sizeof(Spin12<SP>)));
     const __amdgpu_buffer_rsrc_t rnrm = buf_rsrc(P.in_nrm, SP::kNorm ? (unsigned)(Vh * R * 4) : 0u);
-    constexpr int D = lds_pipe_depth<MODE>();
+    constexpr int D = lds_pipe_depth<MODE, HX>();
     if constexpr (D > 0) {
         // D neighbour records in flight: the slot a direction's spin projection frees is
         // refilled with the record D directions ahead before that direction's link product,
@@ -634,46 +708,41 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
             Cx<float> h0[3], h1[3];
             __builtin_amdgcn_sched_barrier(0);
             switch (k) {
-            case 0: proj_lds<0, true, SP>(bs[k % D], cs[k % D], h0, h1); break;
-            case 1: proj_lds<0, false, SP>(bs[k % D], cs[k % D], h0, h1); break;
-            case 2: proj_lds<1, true, SP>(bs[k % D], cs[k % D], h0, h1); break;
-            case 3: proj_lds<1, false, SP>(bs[k % D], cs[k % D], h0, h1); break;
-            case 4: proj_lds<2, true, SP>(bs[k % D], cs[k % D], h0, h1); break;
-            case 5: proj_lds<2, false, SP>(bs[k % D], cs[k % D], h0, h1); break;
-            case 6: proj_lds<3, true, SP>(bs[k % D], cs[k % D], h0, h1); break;
-            default: proj_lds<3, false, SP>(bs[k % D], cs[k % D], h0, h1); break;
+            case 0: proj_lds<0, true, SP>(bs[k % D], unit, h0, h1); break;
+            case 1: proj_lds<0, false, SP>(bs[k % D], unit, h0, h1); break;
+            case 2: proj_lds<1, true, SP>(bs[k % D], unit, h0, h1); break;
+            case 3: proj_lds<1, false, SP>(bs[k % D], unit, h0, h1); break;
+            case 4: proj_lds<2, true, SP>(bs[k % D], unit, h0, h1); break;
+            case 5: proj_lds<2, false, SP>(bs[k % D], unit, h0, h1); break;
+            case 6: proj_lds<3, true, SP>(bs[k % D], unit, h0, h1); break;
+            default: proj_lds<3, false, SP>(bs[k % D], unit, h0, h1); break;
             }
+            const float sck = cs[k % D];
             __builtin_amdgcn_sched_barrier(0);
             if (k + D < 8) ld_nb<SP>(rin, rnrm, nbs[k + D], R, r, bs[k % D], cs[k % D]);
             __builtin_amdgcn_sched_barrier(0);
             const float4 *lk = my + ((k & 1) ? 4 + (k >> 1) : (k >> 1)) * kLkF4;
             switch (k) {
-            case 0: mult_lds<0, true>(lk, h0, h1, acc); break;
-            case 1: mult_lds<0, false>(lk, h0, h1, acc); break;
-            case 2: mult_lds<1, true>(lk, h0, h1, acc); break;
-            case 3: mult_lds<1, false>(lk, h0, h1, acc); break;
-            case 4: mult_lds<2, true>(lk, h0, h1, acc); break;
-            case 5: mult_lds<2, false>(lk, h0, h1, acc); break;
-            case 6: mult_lds<3, true>(lk, h0, h1, acc); break;
-            default: mult_lds<3, false>(lk, h0, h1, acc); break;
+            case 0: mult_lds<0, true>(lk, h0, h1, sck, g5s * sck, acc); break;
+            case 1: mult_lds<0, false>(lk, h0, h1, sck, g5s * sck, acc); break;
+            case 2: mult_lds<1, true>(lk, h0, h1, sck, g5s * sck, acc); break;
+            case 3: mult_lds<1, false>(lk, h0, h1, sck, g5s * sck, acc); break;
+            case 4: mult_lds<2, true>(lk, h0, h1, sck, g5s * sck, acc); break;
+            case 5: mult_lds<2, false>(lk, h0, h1, sck, g5s * sck, acc); break;
+            case 6: mult_lds<3, true>(lk, h0, h1, sck, g5s * sck, acc); break;
+            default: mult_lds<3, false>(lk, h0, h1, sck, g5s * sck, acc); break;
             }
         }
+        __builtin_amdgcn_sched_barrier(0);
     } else {
-        dir_lds<0, true, SP>(rin, rnrm, my, nxp, R, r, acc);
-        dir_lds<0, false, SP>(rin, rnrm, my, nxm, R, r, acc);
-        dir_lds<1, true, SP>(rin, rnrm, my, nyp, R, r, acc);
-        dir_lds<1, false, SP>(rin, rnrm, my, nym, R, r, acc);
-        dir_lds<2, true, SP>(rin, rnrm, my, nzp, R, r, acc);
-        dir_lds<2, false, SP>(rin, rnrm, my, nzm, R, r, acc);
-        dir_lds<3, true, SP>(rin, rnrm, my, ntp, R, r, acc);
-        dir_lds<3, false, SP>(rin, rnrm, my, ntm, R, r, acc);
-    }
-    if (P.g5d) {
-#pragma unroll
-        for (int c = 0; c < 3; c++) {
-            acc[2][c] = cneg(acc[2][c]);
-            acc[3][c] = cneg(acc[3][c]);
-        }
+        dir_lds<0, true, SP>(rin, rnrm, my, nxp, R, r, g5s, unit, acc);
+        dir_lds<0, false, SP>(rin, rnrm, my, nxm, R, r, g5s, unit, acc);
+        dir_lds<1, true, SP>(rin, rnrm, my, nyp, R, r, g5s, unit, acc);
+        dir_lds<1, false, SP>(rin, rnrm, my, nym, R, r, g5s, unit, acc);
+        dir_lds<2, true, SP>(rin, rnrm, my, nzp, R, r, g5s, unit, acc);
+        dir_lds<2, false, SP>(rin, rnrm, my, nzm, R, r, g5s, unit, acc);
+        dir_lds<3, true, SP>(rin, rnrm, my, ntp, R, r, g5s, unit, acc);
+        dir_lds<3, false, SP>(rin, rnrm, my, ntm, R, r, g5s, unit, acc);
     }
     Cx<float> res[4][3];
     if constexpr (kInv) {
@@ -684,7 +753,9 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
 #pragma unroll
             for (int c = 0; c < 3; c++) res[a][c] = acc[a][c];
     }
-    if (P.x) {
+    // a run-time test even when HX holds: an unconditional load of x is hoisted to the
+    // start of the kernel, where its registers push the pipelined loop into spills
+    if (HX && P.x) {
         Cx<float> xv[4][3];
         float sx = (float)P.a * ld_raw<SP>((const typename SP::E *)P.x, P.x_nrm, R, i, r, xv);
 #pragma unroll
@@ -701,7 +772,7 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
     if constexpr (MODE == M_INV_AFTER_DAG) {
         // out as stored; |out|^2 and A^-1 gamma_5 out from the rounded values (what a
         // separate pass would read back); the staged clover block holds c A^-1
-        st_spinor12_round<SP>((typename SP::E *)P.out, P.out_nrm, Vh, R, i, r, v);
+        st_spinor12_round<SP, nt_out<MODE>()>((typename SP::E *)P.out, P.out_nrm, Vh, R, i, r, v);
         Cx<float> g[4][3], o2[4][3];
 #pragma unroll
         for (int k = 0; k < 12; k++) {
@@ -712,7 +783,7 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
         const float ic = 1.0f / (float)P.c;
 #pragma unroll
         for (int k = 0; k < 12; k++) v[k] = ic * o2[k / 3][k % 3];
-        st_spinor12<SP, float>((typename SP::E *)P.out2, P.out2_nrm, Vh, R, i, r, v);
+        st_spinor12<SP, float, nt_out<MODE>()>((typename SP::E *)P.out2, P.out2_nrm, Vh, R, i, r, v);
     } else if constexpr (MODE == M_PLAIN_CG) {
         // residual update of CG on the normal equations, r -= alpha out; |r|^2 of the
         // stored residual (the solution increment follows in the direction update)
@@ -722,12 +793,12 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
             ld_spinor12<SP, float>((const typename SP::E *)P.cg_r, P.cg_r_nrm, Vh, R, i, r, a);
 #pragma unroll
             for (int k = 0; k < 12; k++) a[k] = {fmaf(-al, v[k].re, a[k].re), fmaf(-al, v[k].im, a[k].im)};
-            st_spinor12_round<SP>((typename SP::E *)P.cg_r, P.cg_r_nrm, Vh, R, i, r, a);
+            st_spinor12_round<SP, nt_out<MODE>()>((typename SP::E *)P.cg_r, P.cg_r_nrm, Vh, R, i, r, a);
 #pragma unroll
             for (int k = 0; k < 12; k++) nq += (double)a[k].re * a[k].re + (double)a[k].im * a[k].im;
         }
     } else {
-        st_spinor12<SP, float>((typename SP::E *)P.out, P.out_nrm, Vh, R, i, r, v);
+        st_spinor12<SP, float, nt_out<MODE>()>((typename SP::E *)P.out, P.out_nrm, Vh, R, i, r, v);
     }
     }  // valid
     if constexpr (kRed) {
@@ -863,22 +934,72 @@ long lds_dag_blocks(laph_ctx *c, int prec, int R)
     return (c->g.Vh + S - 1) / S;
 }
 
+#ifndef LAPH_WALK_BY
+#define LAPH_WALK_BY 6
+#endif
+#ifndef LAPH_WALK_BZ
+#define LAPH_WALK_BZ 6
+#endif
+// y (k = 0) and z (k = 1) extent of the tiles of the LDS kernel's site walk: the largest
+// divisor of ns not above LAPH_WALK_BY / LAPH_WALK_BZ (0: checkerboard order)
+static int walk_tile(int ns, int k)
+{
+    const int lim = k == 0 ? LAPH_WALK_BY : LAPH_WALK_BZ;
+    for (int d = lim; d >= 1; d--)
+        if (ns % d == 0) return d;
+    return 0;
+}
+
+// m = ceil(2^32 / d): umulhi(n, m) = floor(n / d) whenever n d < 2^32 (m d - 2^32 < d);
+// 0 (plain division) when d = 1 or some n < nmax would break that bound
+static unsigned umulhi_magic(long d, long nmax)
+{
+    if (d <= 1 || (unsigned long long)nmax * (unsigned long long)d >= (1ull << 32)) return 0;
+    return (unsigned)(((1ull << 32) + (unsigned long long)d - 1) / (unsigned long long)d);
+}
+
 template <class SP>
 void launch_dslash_mr(laph_ctx *c, int mode, const MrArgs &a, hipStream_t st)
 {
     if (use_lds_kernel() && lds_fits(a.Vh, a.R, sizeof(Spin12<SP>))) {
         const int S = lds_tile_sites(c, prec_id<SP>(), a.R);
+        MrArgs b = a;
+        const int by = walk_tile(a.ns, 0), bz = walk_tile(a.ns, 1);
+        const long A = (long)(a.ns / 2) * by * bz;
+#ifndef LAPH_WALK_DAG
+#define LAPH_WALK_DAG 1
+#endif
+        if (by > 0 && bz > 0 && (LAPH_WALK_DAG || mode != M_INV_AFTER_DAG)) {
+            b.wby = by;
+            b.wbz = bz;
+        } else {
+            b.wby = b.wbz = 0;
+        }
+        b.m_nsh = umulhi_magic(a.ns / 2, a.Vh);
+        b.m_ns = umulhi_magic(a.ns, a.Vh);
+        b.m_nt = umulhi_magic(a.nt, a.Vh);
+        b.m_by = b.wby ? umulhi_magic(b.wby, a.Vh) : 0;
+        b.m_nty = b.wby ? umulhi_magic(a.ns / b.wby, a.Vh) : 0;
+        b.m_A = b.wby ? umulhi_magic(A, a.Vh) : 0;
+        b.unit = 1.0f;
         dim3 grid(nblocks_for(a.Vh, S)), block(S * a.R);
         hipEvent_t e0, e1;
         timing_begin(c, &e0, &e1);
+        const bool hx = a.x != nullptr;
+        LAPH_CHECK(hx || (mode != M_INV_AFTER_DAG && mode != M_PLAIN_CG), LAPH_EINVAL,
+                   "fused hopping epilogues need the own-site operand");
         if (mode == M_INV_AFTER_DAG)
-            hipLaunchKernelGGL((k_dslash_lds<SP, M_INV_AFTER_DAG>), grid, block, lds_bytes(S), st, a);
+            hipLaunchKernelGGL((k_dslash_lds<SP, M_INV_AFTER_DAG, true>), grid, block, lds_bytes(S), st, b);
         else if (mode == M_PLAIN_CG)
-            hipLaunchKernelGGL((k_dslash_lds<SP, M_PLAIN_CG>), grid, block, lds_bytes(S), st, a);
+            hipLaunchKernelGGL((k_dslash_lds<SP, M_PLAIN_CG, true>), grid, block, lds_bytes(S), st, b);
+        else if (mode == M_INV_AFTER && hx)
+            hipLaunchKernelGGL((k_dslash_lds<SP, M_INV_AFTER, true>), grid, block, lds_bytes(S), st, b);
         else if (mode == M_INV_AFTER)
-            hipLaunchKernelGGL((k_dslash_lds<SP, M_INV_AFTER>), grid, block, lds_bytes(S), st, a);
+            hipLaunchKernelGGL((k_dslash_lds<SP, M_INV_AFTER, false>), grid, block, lds_bytes(S), st, b);
+        else if (hx)
+            hipLaunchKernelGGL((k_dslash_lds<SP, M_PLAIN, true>), grid, block, lds_bytes(S), st, b);
         else
-            hipLaunchKernelGGL((k_dslash_lds<SP, M_PLAIN>), grid, block, lds_bytes(S), st, a);
+            hipLaunchKernelGGL((k_dslash_lds<SP, M_PLAIN, false>), grid, block, lds_bytes(S), st, b);
         LAPH_HIP(hipGetLastError());
         if (e0)
             timing_end(c, e0, e1, dslash_mr_bytes(a.Vh, a.R, SP::bytes, SP::kNorm, mode, a.x != nullptr),

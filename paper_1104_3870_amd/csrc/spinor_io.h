@@ -22,13 +22,33 @@ __device__ __forceinline__ Spin12<SP> ld_rec(const typename SP::E *base, long i,
     for (int q = 0; q < C; q++) reinterpret_cast<uint4 *>(&pk)[q] = b[((size_t)i * C + q) * R + r];
     return pk;
 }
-template <class SP>
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+
+// NT: non-temporal stores (streamed past L2, so that they do not evict lines a stencil
+// still reads)
+template <class SP, bool NT = false>
 __device__ __forceinline__ void st_rec(typename SP::E *base, long i, int R, int r, const Spin12<SP> &pk)
 {
     constexpr int C = sizeof(Spin12<SP>) / 16;
-    uint4 *b = reinterpret_cast<uint4 *>(base);
+    if constexpr (NT) {
+        u32x4_t *b = reinterpret_cast<u32x4_t *>(base);
 #pragma unroll
-    for (int q = 0; q < C; q++) b[((size_t)i * C + q) * R + r] = reinterpret_cast<const uint4 *>(&pk)[q];
+        for (int q = 0; q < C; q++)
+            __builtin_nontemporal_store(reinterpret_cast<const u32x4_t *>(&pk)[q], &b[((size_t)i * C + q) * R + r]);
+    } else {
+        uint4 *b = reinterpret_cast<uint4 *>(base);
+#pragma unroll
+        for (int q = 0; q < C; q++) b[((size_t)i * C + q) * R + r] = reinterpret_cast<const uint4 *>(&pk)[q];
+    }
+}
+
+template <bool NT>
+__device__ __forceinline__ void st_scale(float *p, float v)
+{
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
 }
 
 // o[k] = component k (alpha*3 + c) of right-hand side r at site i, in arithmetic type A
@@ -54,7 +74,7 @@ __device__ __forceinline__ void ld_spinor12(const typename SP::E *base, const fl
     }
 }
 
-template <class SP, typename A>
+template <class SP, typename A, bool NT = false>
 __device__ __forceinline__ void st_spinor12(typename SP::E *base, float *nrm, long Vh, int R, long i, int r,
                                             const Cx<A> (&v)[12])
 {
@@ -67,14 +87,14 @@ __device__ __forceinline__ void st_spinor12(typename SP::E *base, float *nrm, lo
         // sites below 1e-30 (far tails of a source on one time slice) keep scale 1 and
         // flush to zero in FP16; a denormal scale would make 1/scale infinite
         float sc = m > 1e-30f ? m : 1.0f;
-        nrm[i * R + r] = sc;
+        st_scale<NT>(&nrm[i * R + r], sc);
         inv = 1.0f / sc;
     }
     if constexpr (SP::kAoS) {
         Spin12<SP> pk;
 #pragma unroll
         for (int k = 0; k < 12; k++) SP::st(&pk.v[k], 0, Cx<SA>{(SA)v[k].re, (SA)v[k].im}, inv);
-        st_rec<SP>(base, i, R, r, pk);
+        st_rec<SP, NT>(base, i, R, r, pk);
     } else {
 #pragma unroll
         for (int k = 0; k < 12; k++) SP::st(base, SP::idx(k, i, r, Vh, R), Cx<SA>{(SA)v[k].re, (SA)v[k].im}, inv);
@@ -82,7 +102,7 @@ __device__ __forceinline__ void st_spinor12(typename SP::E *base, float *nrm, lo
 }
 
 // store v and replace it by the values a later load returns (storage rounding and scale)
-template <class SP>
+template <class SP, bool NT = false>
 __device__ __forceinline__ void st_spinor12_round(typename SP::E *base, float *nrm, long Vh, int R, long i, int r,
                                                   Cx<float> (&v)[12])
 {
@@ -93,13 +113,13 @@ __device__ __forceinline__ void st_spinor12_round(typename SP::E *base, float *n
 #pragma unroll
         for (int k = 0; k < 12; k++) m = fmaxf(m, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
         sc = m > 1e-30f ? m : 1.0f;
-        nrm[i * R + r] = sc;
+        st_scale<NT>(&nrm[i * R + r], sc);
         inv = 1.0f / sc;
     }
     Spin12<SP> pk;
 #pragma unroll
     for (int k = 0; k < 12; k++) SP::st(&pk.v[k], 0, Cx<float>{v[k].re, v[k].im}, inv);
-    st_rec<SP>(base, i, R, r, pk);
+    st_rec<SP, NT>(base, i, R, r, pk);
 #pragma unroll
     for (int k = 0; k < 12; k++) {
         auto c = SP::ld(&pk.v[k], 0, sc);

@@ -9,7 +9,7 @@ not credited with old counters.
 
     python -m paper_1104_3870_amd.profile_traffic copy            # calibration program
     python -m paper_1104_3870_amd.profile_traffic summarize --label 'dslash_lds<f16,inv,R32>' \\
-        --match 'k_dslash_lds<S16, 1>' --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR \\
+        --match 'k_dslash_lds<S16, 1, false>' --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR \\
         --sources paper_1104_3870_amd/csrc/dslash_mr.hip --profile NAME
 """
 from __future__ import annotations

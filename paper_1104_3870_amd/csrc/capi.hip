@@ -56,6 +56,8 @@ static void free_dirac_cache(DiracCache &d)
     ctx_free(d.clinv32);
     ctx_free(d.lk12);
     ctx_free(d.claos);
+    ctx_free(d.gU);
+    ctx_free(d.gG);
     d.valid = false;
     d.U = nullptr;
 }
@@ -86,6 +88,7 @@ extern "C" int laph_destroy(laph_ctx_t c)
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     free_dirac_cache(c->dc);
+    free_dirac_cache(c->dct);
     for (auto &kv : c->bufs) ctx_free(kv.second);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto &p : c->event_pool) {
@@ -122,14 +125,17 @@ extern "C" int laph_forget_gauge(laph_ctx_t c)
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     free_dirac_cache(c->dc);
+    free_dirac_cache(c->dct);
     return LAPH_OK;
 }
 
 extern "C" size_t laph_device_bytes(laph_ctx_t c)
 {
     if (!c) return 0;
-    size_t s = c->dc.g64.bytes + c->dc.g32.bytes + c->dc.clov.bytes + c->dc.clinv.bytes +
-               c->dc.clinv32.bytes + c->dc.lk12.bytes + c->dc.claos.bytes;
+    size_t s = 0;
+    for (const DiracCache *d : {&c->dc, &c->dct})
+        s += d->g64.bytes + d->g32.bytes + d->clov.bytes + d->clinv.bytes + d->clinv32.bytes + d->lk12.bytes +
+             d->claos.bytes + d->gU.bytes + d->gG.bytes;
     for (auto &kv : c->bufs) s += kv.second.bytes;
     return s;
 }

@@ -42,6 +42,9 @@ struct MrArgs {
     // 1.0, passed at run time: a + (+-unit) b stays one mixed-precision FMA per component
     // for FP16 records instead of being folded into two conversions and an add
     float unit;
+    // the links are in temporal gauge: every time-direction link except those leaving the
+    // last slice is the unit matrix (applied without a product)
+    int tgauge;
 };
 
 // mode: M_PLAIN (out = c D psi [+ a x]) or M_INV_AFTER (out = a x + c A^-1 D psi)

@@ -401,27 +401,13 @@ __device__ __forceinline__ void proj_lds(const Spin12<SP> &sp, float unit, Cx<fl
     }
 }
 
-// staged link (weights folded in, backward links as their adjoint) times h0, h1, and the
-// reconstruction of all four spin components into acc, each term scaled inside the
-// accumulating FMA: by the record's scale sc (upper components) and sl (lower components:
-// sc, or -sc when gamma_5 follows the hop)
+// reconstruction of all four spin components of a hop from the two colour vectors o0, o1
+// of its projected half spinor, each term scaled inside the accumulating FMA: by sc (upper
+// components) and sl (lower components: sc, or -sc when gamma_5 follows the hop)
 template <int MU, bool FWD>
-__device__ __forceinline__ void mult_lds(const float4 *lk, const Cx<float> (&h0)[3], const Cx<float> (&h1)[3], float sc,
-                                         float sl, Cx<float> (&acc)[4][3])
+__device__ __forceinline__ void accum(const Cx<float> (&o0)[3], const Cx<float> (&o1)[3], float sc, float sl,
+                                      Cx<float> (&acc)[4][3])
 {
-    const float2 *l2 = reinterpret_cast<const float2 *>(lk);
-    Cx<float> o0[3], o1[3];
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        Cx<float> u0 = {l2[a * 3].x, l2[a * 3].y}, u1 = {l2[a * 3 + 1].x, l2[a * 3 + 1].y},
-                  u2 = {l2[a * 3 + 2].x, l2[a * 3 + 2].y};
-        o0[a] = cmul_f(u0, h0[0]);
-        cfma_f(o0[a], u1, h0[1]);
-        cfma_f(o0[a], u2, h0[2]);
-        o1[a] = cmul_f(u0, h1[0]);
-        cfma_f(o1[a], u1, h1[1]);
-        cfma_f(o1[a], u2, h1[2]);
-    }
     constexpr int f = FWD ? 1 : -1;
 #pragma unroll
     for (int c = 0; c < 3; c++) {
@@ -443,13 +429,47 @@ __device__ __forceinline__ void mult_lds(const float4 *lk, const Cx<float> (&h0)
     }
 }
 
+// staged link (weights folded in, backward links as their adjoint) times h0, h1, then accum
+template <int MU, bool FWD>
+__device__ __forceinline__ void mult_lds(const float4 *lk, const Cx<float> (&h0)[3], const Cx<float> (&h1)[3], float sc,
+                                         float sl, Cx<float> (&acc)[4][3])
+{
+    const float2 *l2 = reinterpret_cast<const float2 *>(lk);
+    Cx<float> o0[3], o1[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        Cx<float> u0 = {l2[a * 3].x, l2[a * 3].y}, u1 = {l2[a * 3 + 1].x, l2[a * 3 + 1].y},
+                  u2 = {l2[a * 3 + 2].x, l2[a * 3 + 2].y};
+        o0[a] = cmul_f(u0, h0[0]);
+        cfma_f(o0[a], u1, h0[1]);
+        cfma_f(o0[a], u2, h0[2]);
+        o1[a] = cmul_f(u0, h1[0]);
+        cfma_f(o1[a], u1, h1[1]);
+        cfma_f(o1[a], u2, h1[2]);
+    }
+    accum<MU, FWD>(o0, o1, sc, sl, acc);
+}
+
+// a hop whose link is the unit matrix (temporal gauge): wid is the hop weight that the
+// staged links carry folded in
+template <int MU, bool FWD>
+__device__ __forceinline__ void mult_unit(const Cx<float> (&h0)[3], const Cx<float> (&h1)[3], float sc, float sl,
+                                          float wid, Cx<float> (&acc)[4][3])
+{
+    accum<MU, FWD>(h0, h1, sc * wid, sl * wid, acc);
+}
+
+// ul: the link is the unit matrix with weight wid (time direction in temporal gauge)
 template <int MU, bool FWD, class SP>
 __device__ __forceinline__ void hop_lds(const float4 *lk, const Spin12<SP> &sp, float sc, float g5s, float unit,
-                                        Cx<float> (&acc)[4][3])
+                                        bool ul, float wid, Cx<float> (&acc)[4][3])
 {
     Cx<float> h0[3], h1[3];
     proj_lds<MU, FWD, SP>(sp, unit, h0, h1);
-    mult_lds<MU, FWD>(lk, h0, h1, sc, g5s * sc, acc);
+    if (MU == 3 && ul)
+        mult_unit<MU, FWD>(h0, h1, sc, g5s * sc, wid, acc);
+    else
+        mult_lds<MU, FWD>(lk, h0, h1, sc, g5s * sc, acc);
 }
 
 // buffer resource over n bytes at p (raw 32-bit loads; reads past n return zero)
@@ -484,12 +504,13 @@ __device__ __forceinline__ void ld_nb(__amdgpu_buffer_rsrc_t rin, __amdgpu_buffe
 // neighbour record of the input field (32-bit site index)
 template <int MU, bool FWD, class SP>
 __device__ __forceinline__ void dir_lds(__amdgpu_buffer_rsrc_t rin, __amdgpu_buffer_rsrc_t rnrm, const float4 *slk,
-                                        int nb, int R, int r, float g5s, float unit, Cx<float> (&acc)[4][3])
+                                        int nb, int R, int r, float g5s, float unit, bool ul, float wid,
+                                        Cx<float> (&acc)[4][3])
 {
     Spin12<SP> sp;
     float sc;
     ld_nb<SP>(rin, rnrm, nb, R, r, sp, sc);
-    hop_lds<MU, FWD, SP>(slk + (FWD ? MU : 4 + MU) * kLkF4, sp, sc, g5s, unit, acc);
+    hop_lds<MU, FWD, SP>(slk + (FWD ? MU : 4 + MU) * kLkF4, sp, sc, g5s, unit, ul, wid, acc);
 }
 
 // neighbour records kept in flight by the software-pipelined direction loop (0: the
@@ -615,6 +636,7 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
         if (pos0 + sl >= Vh) continue;
         int x, y, z, t;
         const long i = walk_site(P, (unsigned)(pos0 + sl), x, y, z, t);
+        if (mu == 3 && P.tgauge && (d < 4 ? t + 1 < nt : t > 0)) continue;  // unit link, not read
         float w = fout * (mu == 3 ? (float)P.wt : (float)P.ws);
         long li;
         if (d < 4) {
@@ -666,12 +688,18 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
     if constexpr (!kRed) {
         if (!valid) return;
     }
-    double nq = 0.0;  // this lane's |out|^2 (DAG) or |r|^2 (CG)
+    // this lane's |out|^2 (DAG) or |r|^2 (CG): 24 terms of one site and right-hand side in
+    // FP32, the sums over sites in FP64
+    float nq = 0.0f;
     if (valid) {
     // 32-bit site arithmetic (the host checks Vh * R * 12 < 2^31): neighbour checkerboard
     // indices from the site's own, lex = 2 cb + (x & 1) since Ns is even
     int x, y, z, t;
     const int cb = walk_site(P, (unsigned)(pos0 + sl), x, y, z, t);
+    // temporal gauge: unit time links except from the last slice forward (and into the
+    // first slice backward); the branch is uniform over a block, whose sites share t
+    const bool unit_f = P.tgauge && t + 1 < nt, unit_b = P.tgauge && t > 0;
+    const float wid = fout * (float)P.wt;
     const int sy = ns >> 1, sz = sy * ns, st = sz * ns;
     const int xo = x & 1;
     const int nxp = (x + 1 < ns) ? cb + xo : cb + 1 - sy;
@@ -729,20 +757,30 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
             case 3: mult_lds<1, false>(lk, h0, h1, sck, g5s * sck, acc); break;
             case 4: mult_lds<2, true>(lk, h0, h1, sck, g5s * sck, acc); break;
             case 5: mult_lds<2, false>(lk, h0, h1, sck, g5s * sck, acc); break;
-            case 6: mult_lds<3, true>(lk, h0, h1, sck, g5s * sck, acc); break;
-            default: mult_lds<3, false>(lk, h0, h1, sck, g5s * sck, acc); break;
+            case 6:
+                if (unit_f)
+                    mult_unit<3, true>(h0, h1, sck, g5s * sck, wid, acc);
+                else
+                    mult_lds<3, true>(lk, h0, h1, sck, g5s * sck, acc);
+                break;
+            default:
+                if (unit_b)
+                    mult_unit<3, false>(h0, h1, sck, g5s * sck, wid, acc);
+                else
+                    mult_lds<3, false>(lk, h0, h1, sck, g5s * sck, acc);
+                break;
             }
         }
         __builtin_amdgcn_sched_barrier(0);
     } else {
-        dir_lds<0, true, SP>(rin, rnrm, my, nxp, R, r, g5s, unit, acc);
-        dir_lds<0, false, SP>(rin, rnrm, my, nxm, R, r, g5s, unit, acc);
-        dir_lds<1, true, SP>(rin, rnrm, my, nyp, R, r, g5s, unit, acc);
-        dir_lds<1, false, SP>(rin, rnrm, my, nym, R, r, g5s, unit, acc);
-        dir_lds<2, true, SP>(rin, rnrm, my, nzp, R, r, g5s, unit, acc);
-        dir_lds<2, false, SP>(rin, rnrm, my, nzm, R, r, g5s, unit, acc);
-        dir_lds<3, true, SP>(rin, rnrm, my, ntp, R, r, g5s, unit, acc);
-        dir_lds<3, false, SP>(rin, rnrm, my, ntm, R, r, g5s, unit, acc);
+        dir_lds<0, true, SP>(rin, rnrm, my, nxp, R, r, g5s, unit, false, wid, acc);
+        dir_lds<0, false, SP>(rin, rnrm, my, nxm, R, r, g5s, unit, false, wid, acc);
+        dir_lds<1, true, SP>(rin, rnrm, my, nyp, R, r, g5s, unit, false, wid, acc);
+        dir_lds<1, false, SP>(rin, rnrm, my, nym, R, r, g5s, unit, false, wid, acc);
+        dir_lds<2, true, SP>(rin, rnrm, my, nzp, R, r, g5s, unit, false, wid, acc);
+        dir_lds<2, false, SP>(rin, rnrm, my, nzm, R, r, g5s, unit, false, wid, acc);
+        dir_lds<3, true, SP>(rin, rnrm, my, ntp, R, r, g5s, unit, unit_f, wid, acc);
+        dir_lds<3, false, SP>(rin, rnrm, my, ntm, R, r, g5s, unit, unit_b, wid, acc);
     }
     Cx<float> res[4][3];
     if constexpr (kInv) {
@@ -776,7 +814,7 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
         Cx<float> g[4][3], o2[4][3];
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            nq += (double)v[k].re * v[k].re + (double)v[k].im * v[k].im;
+            nq = fmaf(v[k].re, v[k].re, fmaf(v[k].im, v[k].im, nq));
             g[k / 3][k % 3] = k < 6 ? v[k] : cneg(v[k]);
         }
         clover_one(scl + (size_t)sl * 18, g, o2);
@@ -795,7 +833,7 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
             for (int k = 0; k < 12; k++) a[k] = {fmaf(-al, v[k].re, a[k].re), fmaf(-al, v[k].im, a[k].im)};
             st_spinor12_round<SP, nt_out<MODE>()>((typename SP::E *)P.cg_r, P.cg_r_nrm, Vh, R, i, r, a);
 #pragma unroll
-            for (int k = 0; k < 12; k++) nq += (double)a[k].re * a[k].re + (double)a[k].im * a[k].im;
+            for (int k = 0; k < 12; k++) nq = fmaf(a[k].re, a[k].re, fmaf(a[k].im, a[k].im, nq));
         }
     } else {
         st_spinor12<SP, float, nt_out<MODE>()>((typename SP::E *)P.out, P.out_nrm, Vh, R, i, r, v);
@@ -805,7 +843,7 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
         // deterministic block sum per right-hand side over the lanes sl = 0 .. S-1 of each
         // r; partials stored right-hand-side major
         __shared__ double red[256];
-        red[threadIdx.x] = nq;
+        red[threadIdx.x] = (double)nq;
         __syncthreads();
         if ((int)threadIdx.x < R) {
             double s2 = 0.0;
@@ -982,6 +1020,7 @@ void launch_dslash_mr(laph_ctx *c, int mode, const MrArgs &a, hipStream_t st)
         b.m_nty = b.wby ? umulhi_magic(a.ns / b.wby, a.Vh) : 0;
         b.m_A = b.wby ? umulhi_magic(A, a.Vh) : 0;
         b.unit = 1.0f;
+        b.tgauge = a.tgauge;
         dim3 grid(nblocks_for(a.Vh, S)), block(S * a.R);
         hipEvent_t e0, e1;
         timing_begin(c, &e0, &e1);

@@ -146,6 +146,10 @@ struct DiracCache {
     DevBuf lk12;    // reconstruct-12 FP32 links, per-site AoS (low-precision operator)
     DevBuf claos;   // FP32 clover inverse, per-site AoS (low-precision operator)
     bool f32 = false;  // lk12 / claos are current
+    // temporal gauge (the solver's cache): the operator is built from U' = G U G^dag with
+    // unit time links except on the last slice; gU holds U', gG the rotations G(x)
+    bool tgauge = false;
+    DevBuf gU, gG;
 };
 
 struct laph_ctx {
@@ -153,7 +157,9 @@ struct laph_ctx {
     hipStream_t stream = nullptr;
     int device = 0;
     std::string err;
-    DiracCache dc;
+    DiracCache dc;   // operator of the caller's field (apply entry points)
+    DiracCache dct;  // the same operator in temporal gauge (low-precision solves)
+    DiracCache *cur = &dc;  // the cache the running solve uses
     std::map<std::string, DevBuf> bufs;  // named scratch buffers, grown on demand
     // autotuning: LDS tile (sites per block) per (precision, R) and the chosen R per
     // precision (0: not tuned)
@@ -192,6 +198,13 @@ void clover_to_f32(laph_ctx *c, const double *cl, float *cl32);
 
 // dirac setup shared by the solver and the apply entry point
 void dirac_prepare(laph_ctx *c, const double *U, const laph_dirac *d, bool need_f32);
+// the solver's temporal-gauge cache c->dct (FP64 and low-precision operator of U')
+void dirac_prepare_tgauge(laph_ctx *c, const double *U, const laph_dirac *d);
+
+// tgauge.hip: G (double2 [V][3][3]) and U' = G U G^dag (ABI layout) of the field U;
+// out = G in (dag: G^dag in) for nrhs canonical spinor fields (in == out allowed)
+void tgauge_fix(laph_ctx *c, const double *U, double *G, double *Up);
+void tgauge_spinor(laph_ctx *c, const double *G, const double *in, double *out, int nrhs, int dag);
 
 // stout.hip
 void stout_smear_device(laph_ctx *c, const double *U, double rho, int nsteps, double *out);

@@ -835,6 +835,7 @@ struct Op {
     // low-precision multi-RHS layouts (used whenever SP is not FP64)
     const float4 *lk12 = nullptr;
     const float4 *claos = nullptr;  // per-site clover inverse, parity p at claos + p * Vh * 18
+    int tgauge = 0;                 // temporal gauge: unit time links off the last slice
 
     static constexpr bool kLow = !std::is_same<SP, S64>::value;
 
@@ -878,6 +879,7 @@ struct Op {
         m.ws = ws;
         m.bct = bct;
         m.g5d = g5d;
+        m.tgauge = tgauge;
         return m;
     }
     // hopping term with epilogue; mode M_PLAIN or M_INV_AFTER
@@ -1470,7 +1472,7 @@ int fgmres(laph_ctx *c, const Op64 &hi, laph_ptnet *net, Vec bhat, Vec x, Vec r,
 {
     long Vh = c->g.Vh;
     long n = 12 * Vh;
-    Fgmres f{c, hi, net, (float)c->dc.prm.bc_t, n, 0, 0, nullptr, nullptr, {}};
+    Fgmres f{c, hi, net, (float)c->cur->prm.bc_t, n, 0, 0, nullptr, nullptr, {}};
     f.chunk = std::max<long>(kFgBS * 16, (n + 511) / 512);
     f.chunk = (f.chunk + kFgBS - 1) / kFgBS * kFgBS;
     f.nblk = (int)((n + f.chunk - 1) / f.chunk);
@@ -1572,7 +1574,7 @@ int fgmres(laph_ctx *c, const Op64 &hi, laph_ptnet *net, Vec bhat, Vec x, Vec r,
 template <class SP, class GP, class CP>
 std::vector<laph_tune_entry> tune_hopping(laph_ctx *c, int prec)
 {
-    DiracCache &dc = c->dc;
+    DiracCache &dc = *c->cur;
     const long Vh = c->g.Vh;
     const bool low = !std::is_same<SP, S64>::value;
     std::vector<int> Rs = low ? std::vector<int>{4, 8, 16, 32} : std::vector<int>{1, 2, 4, 8, 16, 32};
@@ -1599,6 +1601,7 @@ std::vector<laph_tune_entry> tune_hopping(laph_ctx *c, int prec)
                               nullptr, -0.5 / dc.prm.xi, -0.5, dc.prm.bc_t, te};
             op.lk12 = (const float4 *)dc.lk12.p;
             op.claos = (const float4 *)dc.claos.p;
+            op.tgauge = dc.tgauge ? 1 : 0;
             std::vector<int> Ss;
             if (low)
                 for (int S = std::max(1, 64 / R); S * R <= 256; S *= 2) Ss.push_back(S);
@@ -1665,7 +1668,7 @@ void solve_batch(laph_ctx *c, const double *eta, double *x, int R, int nreal, co
                  laph_solve_stats *stats)
 {
     long Vh = c->g.Vh;
-    DiracCache &dc = c->dc;
+    DiracCache &dc = *c->cur;
     Work w{c, Vh, R, nullptr, nullptr};
     w.use_graph = sv->use_graph != 0;
     if (sv->reliable_delta > 0) w.delta2 = sv->reliable_delta * sv->reliable_delta;
@@ -1716,6 +1719,7 @@ void solve_batch(laph_ctx *c, const double *eta, double *x, int R, int nreal, co
                       w.make("te_lo", SP::bytes, SP::kNorm)};
     lo.lk12 = (const float4 *)dc.lk12.p;
     lo.claos = (const float4 *)dc.claos.p;
+    lo.tgauge = dc.tgauge ? 1 : 0;
 
     // Attempts: BiCGStab (Sec. IV) for every RHS that has not failed it, then CG on the
     // normal equations (the paper's fallback) in the same precision for the RHS whose
@@ -1822,20 +1826,26 @@ void solve_batch(laph_ctx *c, const double *eta, double *x, int R, int nreal, co
 }  // namespace
 
 // ------------------------------------------------------------------- setup / ABI
-void dirac_prepare(laph_ctx *c, const double *U, const laph_dirac *d, bool need_f32)
+static bool dirac_cache_holds(const DiracCache &dc, const double *U, const laph_dirac *d)
 {
-    DiracCache &dc = c->dc;
-    bool same = dc.valid && dc.U == U && dc.prm.m0 == d->m0 && dc.prm.xi == d->xi && dc.prm.c_sw == d->c_sw &&
-                dc.prm.bc_t == d->bc_t;
-    long V = c->g.V, Vh = c->g.Vh;
-    if (!same) {
+    return dc.valid && dc.U == U && dc.prm.m0 == d->m0 && dc.prm.xi == d->xi && dc.prm.c_sw == d->c_sw &&
+           dc.prm.bc_t == d->bc_t;
+}
+
+// (re)build cache dc for the field Ub when it does not hold the operator of the caller's
+// field Ukey with parameters d
+static void prepare_cache(laph_ctx *c, DiracCache &dc, const double *Ukey, const double *Ub, const laph_dirac *d,
+                          bool need_f32)
+{
+    long Vh = c->g.Vh;
+    if (!dirac_cache_holds(dc, Ukey, d)) {
         ctx_buf(c, dc.g64, (size_t)72 * Vh * 16);
         ctx_buf(c, dc.clov, (size_t)144 * Vh * 8);
         ctx_buf(c, dc.clinv, (size_t)144 * Vh * 8);
-        links_to_eo(c, U, (double2 *)dc.g64.p);
-        clover_build(c, U, d, (double *)dc.clov.p, (double *)dc.clinv.p);
+        links_to_eo(c, Ub, (double2 *)dc.g64.p);
+        clover_build(c, Ub, d, (double *)dc.clov.p, (double *)dc.clinv.p);
         dc.valid = true;
-        dc.U = U;
+        dc.U = Ukey;
         dc.prm = *d;
         dc.f32 = false;
     }
@@ -1846,7 +1856,35 @@ void dirac_prepare(laph_ctx *c, const double *U, const laph_dirac *d, bool need_
                           (float *)dc.claos.p);
         dc.f32 = true;
     }
-    (void)V;
+}
+
+void dirac_prepare(laph_ctx *c, const double *U, const laph_dirac *d, bool need_f32)
+{
+    prepare_cache(c, c->dc, U, U, d, need_f32);
+}
+
+void dirac_prepare_tgauge(laph_ctx *c, const double *U, const laph_dirac *d)
+{
+    DiracCache &dc = c->dct;
+    dc.tgauge = true;
+    if (!dirac_cache_holds(dc, U, d)) {
+        const long V = c->g.V;
+        ctx_buf(c, dc.gU, (size_t)V * 36 * 16);
+        ctx_buf(c, dc.gG, (size_t)V * 9 * 16);
+        tgauge_fix(c, U, (double *)dc.gG.p, (double *)dc.gU.p);
+    }
+    prepare_cache(c, dc, U, (const double *)dc.gU.p, d, true);
+}
+
+// temporal gauge for the low-precision solves unless LAPH_TGAUGE=0
+static bool use_tgauge()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("LAPH_TGAUGE");
+        v = (e && *e == '0') ? 0 : 1;
+    }
+    return v == 1;
 }
 
 static void check_dirac(const laph_dirac *d)
@@ -1895,19 +1933,32 @@ extern "C" int dirac_solve(laph_ctx_t c, const double *U, const laph_dirac *d, c
                LAPH_EINVAL, "unknown solver kind");
     LAPH_CHECK(sv->block_rhs >= 0, LAPH_EINVAL, "block_rhs must be >= 0");
     int R = sv->block_rhs;
+    bool low = sv->precision != LAPH_PREC_F64;
+    // low-precision solves run in temporal gauge (the hop skips the unit time links); the
+    // FP64 path keeps the caller's gauge
+    const bool tg = low && use_tgauge();
+    if (tg)
+        dirac_prepare_tgauge(c, U, d);
+    else
+        dirac_prepare(c, U, d, low);
+    struct CurGuard {
+        laph_ctx *c;
+        ~CurGuard() { c->cur = &c->dc; }
+    } cur_guard{c};
+    c->cur = tg ? &c->dct : &c->dc;
+    const double *G = tg ? (const double *)c->dct.gG.p : nullptr;
     if (sv->solver == LAPH_SOLVER_FGMRES || sv->net) {
         laph_ptnet *net = (laph_ptnet *)sv->net;
         LAPH_CHECK(net && net->layers > 0, LAPH_EINVAL, "FGMRES needs a network");
         LAPH_CHECK(net->device == c->device, LAPH_EINVAL, "network and context on different devices");
-        ptnet_links(c, net, U);
+        // the network is gauge equivariant: in temporal gauge it takes the rotated field
+        ptnet_links(c, net, tg ? (const double *)c->dct.gU.p : U);
     }
     if (sv->solver == LAPH_SOLVER_FGMRES) {
         LAPH_CHECK(sv->restart >= 0 && sv->restart <= 256, LAPH_EINVAL, "restart must be in 0..256");
         R = 1;  // one right-hand side at a time
     }
     LAPH_CHECK(R <= 32 && (R & (R - 1)) == 0, LAPH_EINVAL, "block_rhs must be 0 or a power of two <= 32");
-    bool low = sv->precision != LAPH_PREC_F64;
-    dirac_prepare(c, U, d, low);
     if (R == 0) {
         if (!c->tuned_R.count(sv->precision)) tune_for(c, sv->precision);
         R = c->tuned_R[sv->precision];
@@ -1933,6 +1984,12 @@ extern "C" int dirac_solve(laph_ctx_t c, const double *U, const laph_dirac *d, c
             dst = px;
         }
         laph_solve_stats *st = stats ? stats + base : nullptr;
+        if (tg) {
+            // eta' = G eta; the solve returns x' = G x in dst, rotated back in place below
+            double *te = (double *)ctx_named(c, "slv.tg_eta", (size_t)V * 24 * sizeof(double) * Rb);
+            tgauge_spinor(c, G, src, te, Rb, 0);
+            src = te;
+        }
         try {
             switch (sv->precision) {
             case LAPH_PREC_F64: solve_batch<S64, G64, C64, S64>(c, src, dst, Rb, nreal, sv, st); break;
@@ -1944,6 +2001,7 @@ extern "C" int dirac_solve(laph_ctx_t c, const double *U, const laph_dirac *d, c
             if (e.code != LAPH_ENOCONV) throw;
             if (first_err == LAPH_OK) first_err = e.code;
         }
+        if (tg) tgauge_spinor(c, G, dst, dst, Rb, 1);
         if (dst != xb) {
             size_t fb = (size_t)V * 24 * sizeof(double);
             LAPH_HIP(hipMemcpyAsync(xb, dst, fb * nreal, hipMemcpyDeviceToDevice, c->stream));

@@ -12,6 +12,7 @@ struct Scal {
     double r2hi;      // |r|^2 of the last FP64 residual
     double tol2;      // target |r|^2 of the even-odd system
     double b2;        // |bhat|^2
+    double alpha_prev;  // alpha of the previous CG iteration (steps the direction update still owes x)
     int active;
     int iters;
     int breakdown;

@@ -357,10 +357,11 @@ __global__ __launch_bounds__(kBS) void k_fold_x(Vec xhi, Vec xlo, long Vh, int R
     st_site<XP>(xlo, Vh, R, i, rr, z);
 }
 
-// the same fold with the pending step of the current iteration, xhi += xlo + alpha p
-// (right-hand sides with mask set)
+// the same fold with the steps the direction update still owes x: xhi += xlo + alpha p
+// (+ alpha_prev pprev when prev) (right-hand sides with mask set)
 template <class XP, class SP>
-__global__ __launch_bounds__(kBS) void k_fold_x_step(Vec xhi, Vec xlo, Vec p, long Vh, int R, const Scal *sc)
+__global__ __launch_bounds__(kBS) void k_fold_x_step(Vec xhi, Vec xlo, Vec p, Vec pprev, long Vh, int R,
+                                                     const Scal *sc, int prev)
 {
     long n = Vh * R;
     long tid = blockIdx.x * (long)kBS + threadIdx.x;
@@ -379,6 +380,12 @@ __global__ __launch_bounds__(kBS) void k_fold_x_step(Vec xhi, Vec xlo, Vec p, lo
     for (int k = 0; k < 12; k++) {
         a[k] = a[k] + al * b[k];
         z[k] = {0, 0};
+    }
+    if (prev) {
+        const double ap = sc[rr].alpha_prev;
+        ld_site<SP>(pprev, Vh, R, i, rr, b);
+#pragma unroll
+        for (int k = 0; k < 12; k++) a[k] = a[k] + ap * b[k];
     }
     st_site<S64>(xhi, Vh, R, i, rr, a);
     st_site<XP>(xlo, Vh, R, i, rr, z);
@@ -579,6 +586,7 @@ __global__ void k_fin_cg_alpha(const double *partial, int nblk, int R, Scal *sc,
         q.alpha = make_double2(0, 0);
         return;
     }
+    q.alpha_prev = q.alpha.x;
     if (!(s[0] > 0) || !std::isfinite(s[0])) {
         q.alpha = make_double2(0, 0);
         q.breakdown = 1;
@@ -665,10 +673,13 @@ __global__ void k_fin_cg_beta(const double *partial, int nblk, int R, Scal *sc, 
     if (hi_conv && (s[1] <= q.tol2 || !(s[0] > 0))) q.active = 0;
 }
 
-// p = r + beta p (real beta); with x_upd the solution increment first takes the step
-// along the old direction, x += alpha p
+// direction update pout = r + beta pcur (real beta); pout may be pcur or another buffer.
+// The solution increment takes the steps along the directions first: xmode 1:
+// x += alpha pcur; xmode 2: x += alpha_prev pprev + alpha pcur (the step of the previous
+// iteration, whose direction pprev is still held, and this one's)
 template <class SP, class XP>
-__global__ __launch_bounds__(kBS) void k_cg_p(Vec p, Vec r, Vec x, long Vh, int R, const Scal *sc, int x_upd)
+__global__ __launch_bounds__(kBS) void k_cg_p(Vec pout, Vec pcur, Vec pprev, Vec r, Vec x, long Vh, int R,
+                                              const Scal *sc, int xmode)
 {
     long n = Vh * R;
     long tid = blockIdx.x * (long)kBS + threadIdx.x;
@@ -678,18 +689,25 @@ __global__ __launch_bounds__(kBS) void k_cg_p(Vec p, Vec r, Vec x, long Vh, int 
     if (!sc[rr].active) return;
     double be = sc[rr].beta.x;
     Cx<double> a[12], b[12];
-    ld_site<SP>(p, Vh, R, i, rr, a);
-    if (x_upd) {
+    ld_site<SP>(pcur, Vh, R, i, rr, a);
+    if (xmode) {
         const double al = sc[rr].alpha.x;
         ld_site<XP>(x, Vh, R, i, rr, b);
 #pragma unroll
         for (int k = 0; k < 12; k++) b[k] = b[k] + al * a[k];
+        if (xmode == 2) {
+            const double ap = sc[rr].alpha_prev;
+            Cx<double> c[12];
+            ld_site<SP>(pprev, Vh, R, i, rr, c);
+#pragma unroll
+            for (int k = 0; k < 12; k++) b[k] = b[k] + ap * c[k];
+        }
         st_site<XP>(x, Vh, R, i, rr, b);
     }
     ld_site<SP>(r, Vh, R, i, rr, b);
 #pragma unroll
     for (int k = 0; k < 12; k++) a[k] = b[k] + be * a[k];
-    st_site<SP>(p, Vh, R, i, rr, a);
+    st_site<SP>(pout, Vh, R, i, rr, a);
 }
 
 // after the residual was replaced: rho = |r|^2, r2 = |res|^2, beta = |r|^2 / rho_prev
@@ -1192,22 +1210,33 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
             launch_fin(c, k_fin_cg_beta, w.R, (const double *)w.part, nblk, w.R, w.sc, plain ? 1 : 0, plain ? 0 : 1,
                        0);
         }
-        if (plain) launch_el(c, k_cg_p<SP, XP>, n, p, r, xlo, w.Vh, w.R, (const Scal *)w.sc, 0);
+        if (plain) launch_el(c, k_cg_p<SP, XP>, n, p, p, p, r, xlo, w.Vh, w.R, (const Scal *)w.sc, 0);
     };
-    bool x_pending = false;
-    hipGraphExec_t gexec = nullptr;
+    // the fused body leaves the step x += alpha p to the direction update; with two
+    // direction buffers every other update writes the new direction into the other buffer
+    // and keeps the old one, and the next update takes both steps: the FP32 increment is
+    // read and written every second iteration only (graph replay keeps one captured body
+    // per direction buffer)
+    const bool pp = fuse;
+    Vec pother = pp ? w.make("cg.p2", SP::bytes, nrm) : p;
+    const void *pbuf0 = p.d;
+    bool step_now = false;   // this iteration's step is owed to x
+    bool step_prev = false;  // the previous iteration's step is owed too (its direction in pother)
+    hipGraphExec_t gexecs[2] = {nullptr, nullptr};  // body captured with p in either buffer
     const bool graph_ok = w.use_graph && !c->timing;
     if (graph_ok && !c->cap_stream) LAPH_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     struct GraphGuard {
-        hipGraphExec_t &g;
+        hipGraphExec_t *g;
         ~GraphGuard()
         {
-            if (g) (void)hipGraphExecDestroy(g);
+            for (int k = 0; k < 2; k++)
+                if (g[k]) (void)hipGraphExecDestroy(g[k]);
         }
-    } guard{gexec};
+    } guard{gexecs};
     for (int it = 0; it < maxiter;) {
         int chunk = std::min(check_every, maxiter - it);
         for (int k = 0; k < chunk; k++) {
+            hipGraphExec_t &gexec = gexecs[p.d == pbuf0 ? 0 : 1];
             if (gexec) {
                 LAPH_HIP(hipGraphLaunch(gexec, c->stream));
             } else if (graph_ok) {
@@ -1237,7 +1266,7 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
         }
         it += chunk;
         since += chunk;
-        x_pending = fuse;  // the fused body leaves x += alpha p to the direction update
+        step_now = fuse;
         read_scal(c, w.sc, hs);
         bool any = false, want_update = false;
         int nact = 0;
@@ -1261,11 +1290,12 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
             // and keep the old direction orthogonal to the new residual
             // FP64 true residual of the even-odd system; the normal residual M^dag res is
             // computed by the low-precision operator, in which r is stored anyway
-            if (fuse)  // the fused form takes the step x += alpha p with the direction update
-                launch_el(c, k_fold_x_step<XP, SP>, n, xhi, xlo, p, w.Vh, w.R, (const Scal *)w.sc);
+            if (step_now)  // the fold takes the steps still owed to x
+                launch_el(c, k_fold_x_step<XP, SP>, n, xhi, xlo, p, pother, w.Vh, w.R, (const Scal *)w.sc,
+                          step_prev ? 1 : 0);
             else
                 launch_el(c, k_fold_x<XP>, n, xhi, xlo, w.Vh, w.R, (const Scal *)w.sc, 0);
-            x_pending = false;
+            step_now = step_prev = false;
             true_eo_residual(w, hi, bhat, xhi, tmp64, reshi, 0);
             launch_el(c, k_convert_masked<SP>, n, reshi, res, w.Vh, w.R, (const Scal *)w.sc);
             lo.mhat_dag(res, r, to);
@@ -1283,8 +1313,21 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
             }
             if (!left) break;
         }
-        launch_el(c, k_cg_p<SP, XP>, n, p, r, xlo, w.Vh, w.R, (const Scal *)w.sc, x_pending ? 1 : 0);
+        if (!pp || !step_now) {
+            launch_el(c, k_cg_p<SP, XP>, n, p, p, p, r, xlo, w.Vh, w.R, (const Scal *)w.sc, step_now ? 1 : 0);
+        } else if (!step_prev) {
+            // keep this direction for the next update, which takes both steps
+            launch_el(c, k_cg_p<SP, XP>, n, pother, p, p, r, xlo, w.Vh, w.R, (const Scal *)w.sc, 0);
+            std::swap(p, pother);
+            step_prev = true;
+        } else {
+            launch_el(c, k_cg_p<SP, XP>, n, pother, p, pother, r, xlo, w.Vh, w.R, (const Scal *)w.sc, 2);
+            std::swap(p, pother);
+            step_prev = false;
+        }
     }
+    // a step still owed after the last iteration (its alpha is the current one)
+    if (step_prev) launch_el(c, k_fold_x_step<XP, SP>, n, xhi, xlo, pother, pother, w.Vh, w.R, (const Scal *)w.sc, 0);
     launch_el(c, k_fold_x<XP>, n, xhi, xlo, w.Vh, w.R, (const Scal *)w.sc, 1);
 }
 

@@ -91,6 +91,9 @@ extern "C" int laph_destroy(laph_ctx_t c)
     free_dirac_cache(c->dct);
     for (auto &kv : c->bufs) ctx_free(kv.second);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->pin) (void)hipHostFree(c->pin);
+    for (hipEvent_t e : c->pin_ev)
+        if (e) (void)hipEventDestroy(e);
     for (auto &p : c->event_pool) {
         (void)hipEventDestroy(p.first);
         (void)hipEventDestroy(p.second);

@@ -166,6 +166,11 @@ struct laph_ctx {
     std::map<std::pair<int, int>, int> lds_tile;
     std::map<int, int> tuned_R;
     hipStream_t cap_stream = nullptr;  // capture stream for HIP graphs (default priority)
+    // pinned two-slot readback of the per-RHS Krylov scalars and the events marking each
+    // slot's copy (the CG loop reads the previous iteration's slot without draining the queue)
+    void *pin = nullptr;
+    size_t pin_bytes = 0;
+    hipEvent_t pin_ev[2] = {nullptr, nullptr};
     // timing
     struct TimeAcc {
         double ms = 0, bytes = 0;

@@ -1028,6 +1028,34 @@ void read_scal(laph_ctx *c, const Scal *d, std::vector<Scal> &h)
     LAPH_HIP(hipMemcpyAsync(h.data(), d, sizeof(Scal) * h.size(), hipMemcpyDeviceToHost, c->stream));
     LAPH_HIP(hipStreamSynchronize(c->stream));
 }
+// pinned two-slot scalar readback for the CG loop (grown on demand, owned by the context)
+static Scal *pinned_scal(laph_ctx *c, int R)
+{
+    const size_t need = 2 * sizeof(Scal) * (size_t)R;
+    if (c->pin_bytes < need) {
+        if (c->pin) LAPH_HIP(hipHostFree(c->pin));
+        c->pin = nullptr;
+        c->pin_bytes = 0;
+        LAPH_HIP(hipHostMalloc(&c->pin, need, hipHostMallocDefault));
+        c->pin_bytes = need;
+    }
+    for (hipEvent_t &e : c->pin_ev)
+        if (!e) LAPH_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return (Scal *)c->pin;
+}
+
+// the CG loop decides on reliable updates from the previous iteration's scalars, read
+// while the current iteration runs (LAPH_LAG=0: from the current ones, draining the queue)
+static bool use_lag()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("LAPH_LAG");
+        v = (e && *e == '0') ? 0 : 1;
+    }
+    return v == 1;
+}
+
 void write_scal(laph_ctx *c, Scal *d, const std::vector<Scal> &h)
 {
     LAPH_HIP(hipMemcpyAsync(d, h.data(), sizeof(Scal) * h.size(), hipMemcpyHostToDevice, c->stream));
@@ -1222,6 +1250,14 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
     const void *pbuf0 = p.d;
     bool step_now = false;   // this iteration's step is owed to x
     bool step_prev = false;  // the previous iteration's step is owed too (its direction in pother)
+    // lagged decisions (low precision): the scalars of iteration k are copied to a pinned
+    // slot behind its hops; the update rule at iteration k reads iteration k - 1's slot,
+    // long complete, so the host never waits for the queue to drain (an update or the
+    // convergence test comes one iteration later, which the rule tolerates)
+    const bool lag = !plain && use_lag();
+    Scal *pin = lag ? pinned_scal(c, w.R) : nullptr;
+    int slot = 0;
+    bool prev_ok = false;  // the other slot holds the previous iteration's scalars
     hipGraphExec_t gexecs[2] = {nullptr, nullptr};  // body captured with p in either buffer
     const bool graph_ok = w.use_graph && !c->timing;
     if (graph_ok && !c->cap_stream) LAPH_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
@@ -1267,7 +1303,18 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
         it += chunk;
         since += chunk;
         step_now = fuse;
-        read_scal(c, w.sc, hs);
+        if (lag) {
+            LAPH_HIP(hipMemcpyAsync(pin + (size_t)slot * w.R, w.sc, sizeof(Scal) * w.R, hipMemcpyDeviceToHost,
+                                    c->stream));
+            LAPH_HIP(hipEventRecord(c->pin_ev[slot], c->stream));
+            const int use = prev_ok ? slot ^ 1 : slot;
+            LAPH_HIP(hipEventSynchronize(c->pin_ev[use]));
+            std::copy(pin + (size_t)use * w.R, pin + (size_t)use * w.R + w.R, hs.begin());
+            prev_ok = true;
+            slot ^= 1;
+        } else {
+            read_scal(c, w.sc, hs);
+        }
         bool any = false, want_update = false;
         int nact = 0;
         double worst = 0;
@@ -1306,6 +1353,7 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
             launch_el(c, k_orth_p<SP>, n, p, r, w.Vh, w.R, (const Scal *)w.sc);
             since = 0;
             read_scal(c, w.sc, hs);
+            prev_ok = false;  // the slots predate the update
             bool left = false;
             for (int k = 0; k < w.R; k++) {
                 left |= hs[k].active != 0;

@@ -1,11 +1,12 @@
-// Multi-right-hand-side hopping kernel for the low-precision inner solves.
+// Multi-right-hand-side hopping kernels for the low-precision inner solves (FP32
+// arithmetic, FP16 / BF16 / FP32 records).
 //
-// The R right-hand sides share links and clover, so the kernel is limited by how many
-// vector-memory instructions each lane issues rather than by bytes: one lane therefore
-// works on NR right-hand sides of one site whose spinors are contiguous 48/96-byte records
-// (site-major layout, 16-byte loads), links are stored as the first two rows only (reconstruct-12:
-// the third row of an SU(3) matrix is conj(row0 x row1); 3 x 16-byte loads per link)
-// and the clover blocks are stored per site (18 x 16-byte loads).  Arithmetic is FP32.
+// k_dslash_lds (the production kernel) stages a block's links and clover blocks in LDS
+// and gives every lane one (site, right-hand side); see its section below.  k_dslash_mr
+// (LAPH_MR_KERNEL=0) is the per-lane form: one lane works on NR right-hand sides of one
+// site, loading links stored as their first two rows (reconstruct-12: the third row of an
+// SU(3) matrix is conj(row0 x row1); 3 x 16-byte loads per link) and per-site clover
+// blocks (18 x 16-byte loads) itself.
 #include <cstdlib>
 #include <string>
 #include <type_traits>
@@ -219,9 +220,8 @@ __device__ __forceinline__ void do_dir(const MrArgs &P, const float4 *lk, int x,
 #else
 #define LAPH_MR_ATTR
 #endif
-// the LDS-staged kernel runs at 3 waves per SIMD (at most 168 VGPRs): with the
-// pipelined neighbour loads every epilogue fits without spills, and this measured faster
-// than 4 waves under the 128-VGPR cap
+// the LDS-staged kernel runs at least 3 waves per SIMD (at most 168 VGPRs); no
+// instantiation spills, and the FP16 ones of the CG iteration need 90-95 VGPRs (5 waves)
 #ifndef LAPH_LDS_WAVES
 #define LAPH_LDS_WAVES 3
 #endif
@@ -297,7 +297,12 @@ __global__ __launch_bounds__(256) LAPH_MR_ATTR void k_dslash_mr(const MrArgs P)
 // 8 S links of the block (hop weight, boundary factor and for M_PLAIN the output factor
 // folded in; backward links stored as their adjoint) and its S clover blocks are staged
 // in LDS once, so a lane does only the spin projection, one SU(3) product per direction
-// and the clover product, with explicit FMA chains.
+// and the clover product, with explicit FMA chains.  The kernel is bound by VALU issue:
+// neighbour records come through buffer loads (one offset register each) in a software-
+// pipelined direction loop, the record scale and the gamma_5 sign ride on the
+// accumulating FMAs, index divisions are multiply-highs, unit links of a temporal gauge
+// are skipped, the sites are walked in tiles through time (MrArgs::wby) and outputs are
+// stored non-temporally.
 constexpr int kLkF4 = 5;  // float4 per staged link (18 floats used)
 
 __device__ __forceinline__ Cx<float> cmul_f(Cx<float> a, Cx<float> b)
@@ -523,9 +528,6 @@ __device__ __forceinline__ void dir_lds(__amdgpu_buffer_rsrc_t rin, __amdgpu_buf
 template <int MODE, bool HX>
 constexpr int lds_pipe_depth()
 {
-#ifdef LAPH_PIPE_DAG
-    if (MODE == M_INV_AFTER_DAG) return LAPH_PIPE_DAG;
-#endif
     return ((MODE == M_INV_AFTER || MODE == M_INV_AFTER_DAG) && HX) ? 0 : LAPH_PIPE_D;
 }
 
@@ -1004,10 +1006,7 @@ void launch_dslash_mr(laph_ctx *c, int mode, const MrArgs &a, hipStream_t st)
         MrArgs b = a;
         const int by = walk_tile(a.ns, 0), bz = walk_tile(a.ns, 1);
         const long A = (long)(a.ns / 2) * by * bz;
-#ifndef LAPH_WALK_DAG
-#define LAPH_WALK_DAG 1
-#endif
-        if (by > 0 && bz > 0 && (LAPH_WALK_DAG || mode != M_INV_AFTER_DAG)) {
+        if (by > 0 && bz > 0) {
             b.wby = by;
             b.wbz = bz;
         } else {

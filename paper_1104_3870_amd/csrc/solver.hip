@@ -416,6 +416,67 @@ __global__ __launch_bounds__(kBS) void k_resid64(Vec b, Vec m, Vec r, long Vh, i
 }
 
 // mode 0: r2hi = sum, and mask off converged (r2hi <= tol2); mode 1: b2 = sum
+// the steps the direction update still owes x go into the increment: xlo += alpha p
+// (+ alpha_prev pprev when prev) (right-hand sides with mask set)
+template <class XP, class SP>
+__global__ __launch_bounds__(kBS) void k_owe_xlo(Vec xlo, Vec p, Vec pprev, long Vh, int R, const Scal *sc, int prev)
+{
+    long n = Vh * R;
+    long tid = blockIdx.x * (long)kBS + threadIdx.x;
+    if (tid >= n) return;
+    long i = tid / R;
+    int rr = (int)(tid - i * R);
+    if (!sc[rr].active) return;
+    const double al = sc[rr].alpha.x;
+    Cx<double> a[12], b[12];
+    ld_site<XP>(xlo, Vh, R, i, rr, a);
+    ld_site<SP>(p, Vh, R, i, rr, b);
+#pragma unroll
+    for (int k = 0; k < 12; k++) a[k] = a[k] + al * b[k];
+    if (prev) {
+        const double ap = sc[rr].alpha_prev;
+        ld_site<SP>(pprev, Vh, R, i, rr, b);
+#pragma unroll
+        for (int k = 0; k < 12; k++) a[k] = a[k] + ap * b[k];
+    }
+    st_site<XP>(xlo, Vh, R, i, rr, a);
+}
+
+// tracked residual update: r -= m (m = M xlo in the increment's precision), xhi += xlo,
+// xlo = 0; partial |r|^2 (right-hand sides with mask set)
+template <class XP>
+__global__ __launch_bounds__(kBS) void k_track_res(Vec r, Vec m, Vec xhi, Vec xlo, long Vh, int R, double *partial,
+                                                   const Scal *sc)
+{
+    double acc[1] = {0};
+    long n = Vh * R, stride = (long)gridDim.x * kBS;
+    int rr = (int)((blockIdx.x * (long)kBS + threadIdx.x) % R);
+    bool act = sc[rr].active;
+    for (long tid = blockIdx.x * (long)kBS + threadIdx.x; tid < n; tid += stride) {
+        if (!act) break;
+        long i = tid / R;
+        Cx<double> a[12], c[12], z[12];
+        ld_site<S64>(r, Vh, R, i, rr, a);
+        ld_site<XP>(m, Vh, R, i, rr, c);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            a[k] = a[k] - c[k];
+            acc[0] += a[k].re * a[k].re + a[k].im * a[k].im;
+        }
+        st_site<S64>(r, Vh, R, i, rr, a);
+        ld_site<S64>(xhi, Vh, R, i, rr, a);
+        ld_site<XP>(xlo, Vh, R, i, rr, c);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            a[k] = a[k] + c[k];
+            z[k] = {0, 0};
+        }
+        st_site<S64>(xhi, Vh, R, i, rr, a);
+        st_site<XP>(xlo, Vh, R, i, rr, z);
+    }
+    block_partial<1>(acc, R, partial);
+}
+
 __global__ void k_fin_r2hi(const double *partial, int nblk, int R, Scal *sc, int mode)
 {
     int r = blockIdx.x;
@@ -429,6 +490,7 @@ __global__ void k_fin_r2hi(const double *partial, int nblk, int R, Scal *sc, int
     }
     if (!q.active) return;
     q.r2hi = s[0];
+    if (mode == 2) return;  // a tracked residual never declares convergence
     if (s[0] <= q.tol2) q.active = 0;
 }
 
@@ -1044,6 +1106,18 @@ static Scal *pinned_scal(laph_ctx *c, int R)
     return (Scal *)c->pin;
 }
 
+// reliable updates far from convergence track the FP64 residual with the FP32 operator
+// (LAPH_TRACK=0: always recompute it with the FP64 operator)
+static bool use_tracked()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("LAPH_TRACK");
+        v = (e && *e == '0') ? 0 : 1;
+    }
+    return v == 1;
+}
+
 // the CG loop decides on reliable updates from the previous iteration's scalars, read
 // while the current iteration runs (LAPH_LAG=0: from the current ones, draining the queue)
 static bool use_lag()
@@ -1254,6 +1328,18 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
     // slot behind its hops; the update rule at iteration k reads iteration k - 1's slot,
     // long complete, so the host never waits for the queue to drain (an update or the
     // convergence test comes one iteration later, which the rule tolerates)
+    // tracked reliable updates: while every active even-odd residual is above 1e-5 |bhat|,
+    // the FP64 residual follows res -= M xlo with the operator applied to the FP32
+    // increment in FP32 (error ~1e-7 |res|, far below the update threshold), instead of
+    // being recomputed from xhi with the FP64 operator; closer to the target the full FP64
+    // residual takes over and also judges convergence
+    constexpr double kTrack2 = 1e-10;
+    const bool track_ok = fuse && std::is_same<XP, S32>::value && use_tracked();
+    Vec t32{}, te32{};
+    if (track_ok) {
+        t32 = w.make("cg.t32", XP::bytes, false);
+        te32 = w.make("cg.te32", XP::bytes, false);
+    }
     const bool lag = !plain && use_lag();
     Scal *pin = lag ? pinned_scal(c, w.R) : nullptr;
     int slot = 0;
@@ -1337,13 +1423,31 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
             // and keep the old direction orthogonal to the new residual
             // FP64 true residual of the even-odd system; the normal residual M^dag res is
             // computed by the low-precision operator, in which r is stored anyway
-            if (step_now)  // the fold takes the steps still owed to x
-                launch_el(c, k_fold_x_step<XP, SP>, n, xhi, xlo, p, pother, w.Vh, w.R, (const Scal *)w.sc,
-                          step_prev ? 1 : 0);
-            else
-                launch_el(c, k_fold_x<XP>, n, xhi, xlo, w.Vh, w.R, (const Scal *)w.sc, 0);
+            bool track = track_ok;
+            for (int k = 0; k < w.R && track; k++)
+                if (hs[k].active && !(hs[k].r2 > kTrack2 * hs[k].b2)) track = false;
+            if (track) {
+                if constexpr (std::is_same<XP, S32>::value) {
+                    if (step_now)
+                        launch_el(c, k_owe_xlo<XP, SP>, n, xlo, p, pother, w.Vh, w.R, (const Scal *)w.sc,
+                                  step_prev ? 1 : 0);
+                    Op<XP, G32, C32> lo32{c, lo.st, lo.Vh, lo.R, nullptr, nullptr, nullptr, lo.ws, lo.wt, lo.bct, te32};
+                    lo32.lk12 = lo.lk12;
+                    lo32.claos = lo.claos;
+                    lo32.tgauge = lo.tgauge;
+                    lo32.mhat(xlo, t32);
+                    launch_red(c, k_track_res<XP>, n, reshi, t32, xhi, xlo, w.Vh, w.R, w.part, (const Scal *)w.sc);
+                    launch_fin(c, k_fin_r2hi, w.R, (const double *)w.part, nblk, w.R, w.sc, 2);
+                }
+            } else {
+                if (step_now)  // the fold takes the steps still owed to x
+                    launch_el(c, k_fold_x_step<XP, SP>, n, xhi, xlo, p, pother, w.Vh, w.R, (const Scal *)w.sc,
+                              step_prev ? 1 : 0);
+                else
+                    launch_el(c, k_fold_x<XP>, n, xhi, xlo, w.Vh, w.R, (const Scal *)w.sc, 0);
+                true_eo_residual(w, hi, bhat, xhi, tmp64, reshi, 0);
+            }
             step_now = step_prev = false;
-            true_eo_residual(w, hi, bhat, xhi, tmp64, reshi, 0);
             launch_el(c, k_convert_masked<SP>, n, reshi, res, w.Vh, w.R, (const Scal *)w.sc);
             lo.mhat_dag(res, r, to);
             launch_red(c, k_normsq2<SP>, n, r, res, w.Vh, w.R, w.part);

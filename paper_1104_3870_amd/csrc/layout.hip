@@ -40,13 +40,15 @@ void eo64_to_eo32(laph_ctx *c, const double2 *g64, float2 *g32, long n)
 
 // canonical [R][V][4][3] -> parity halves [12][Vh][R]; gam = 4 applies gamma_4 (chiral
 // basis: swaps the upper and lower spin pairs), gam = 5 applies gamma_5 = diag(1,1,-1,-1).
+// One lane per (site, RHS) with the RHS fastest: the parity halves are written with
+// consecutive RHS at consecutive addresses, every lane reads its site's 192-byte record.
 __global__ void k_spinor_to_eo(const double2 *__restrict__ psi, int nrhs, int gam, double2 *__restrict__ ev,
                                double2 *__restrict__ od, int ns, long V, long Vh)
 {
     long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (tid >= V * nrhs) return;
-    int r = (int)(tid / V);
-    long s = tid - (long)r * V;
+    long s = tid / nrhs;
+    int r = (int)(tid - s * nrhs);
     int x = (int)(s % ns);
     long q = s / ns;
     int y = (int)(q % ns);
@@ -73,13 +75,14 @@ void spinor_to_eo(laph_ctx *c, const double *psi, int nrhs, int gam, double2 *ev
     LAPH_HIP(hipGetLastError());
 }
 
+// the inverse of k_spinor_to_eo, same lane order (reads of consecutive RHS coalesced)
 __global__ void k_spinor_from_eo(const double2 *__restrict__ ev, const double2 *__restrict__ od, int nrhs, int gam,
                                  double2 *__restrict__ psi, int ns, long V, long Vh)
 {
     long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (tid >= V * nrhs) return;
-    int r = (int)(tid / V);
-    long s = tid - (long)r * V;
+    long s = tid / nrhs;
+    int r = (int)(tid - s * nrhs);
     int x = (int)(s % ns);
     long q = s / ns;
     int y = (int)(q % ns);

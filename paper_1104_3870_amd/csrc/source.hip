@@ -1,4 +1,6 @@
 // Z4 noise, diluted LapH sources and the sink projection V_s^dag X (Sec. II, Sec. IV).
+#include <algorithm>
+
 #include "laph_impl.h"
 
 namespace {
@@ -78,64 +80,98 @@ __global__ void k_source(const double2 *__restrict__ evecs, const double2 *__res
     for (int a = 0; a < 4; a++) out[a * 3 + c] = acc[a];
 }
 
-// coef[r][t][alpha][n] for a tile of NT eigenvectors: one block per (t, tile, r)
-constexpr int NT = 8;
-__global__ __launch_bounds__(256) void k_sink(const double2 *__restrict__ evecs, const double2 *__restrict__ X,
-                                              long V3, int nt, int nv, double2 *__restrict__ coef)
+// Tiled sink projection: per time slice t the coefficients form the product
+// C[(r, alpha)][n] = sum_{x, c} X[r][t][x][alpha][c] conj(V[t][n][x][c]), rows (RHS, spin),
+// columns eigenvectors, contraction over the slice's sites and colours.  A block owns one
+// t, a tile of kSinkM rows (kSinkM / 4 RHS) and all columns of a column tile, and a range
+// of sites (split over blockIdx.z); both operands pass through LDS kSinkX sites at a time,
+// so X is read once and V once per row tile.  Partial sums per site range are reduced by
+// k_sink_reduce in a fixed order.
+constexpr int kSinkM = 64;   // rows per block (16 RHS x 4 spins)
+constexpr int kSinkN = 112;  // columns per tile (16 lanes x 7)
+constexpr int kSinkX = 4;    // sites per LDS stage (K = 12 per stage)
+
+__global__ __launch_bounds__(256) void k_sink_tiled(const double2 *__restrict__ evecs, const double2 *__restrict__ X,
+                                                    long V3, int nt, int nv, int nrhs, int xper,
+                                                    double2 *__restrict__ part)
 {
-    int t = blockIdx.x;
-    int n0 = blockIdx.y * NT;
-    int r = blockIdx.z;
-    double acc[NT][4][2];
+    __shared__ double2 sa[kSinkM / 4][kSinkX * 12];  // [rhs in tile][site * 12 + alpha * 3 + c]
+    __shared__ double2 sb[kSinkN][kSinkX * 3 + 1];   // [column][site * 3 + c] (padded)
+    const int t = blockIdx.x;
+    const int mt = blockIdx.y % ((nrhs * 4 + kSinkM - 1) / kSinkM);
+    const int nt0 = (blockIdx.y / ((nrhs * 4 + kSinkM - 1) / kSinkM)) * kSinkN;
+    const int r0 = mt * (kSinkM / 4);
+    const long x0 = (long)blockIdx.z * xper, x1 = std::min(V3, x0 + xper);
+    const int tm = threadIdx.x >> 4, tn = threadIdx.x & 15;  // rows tm*4 .. +3, columns tn + 16 j
+    double acc[4][7][2];
 #pragma unroll
-    for (int q = 0; q < NT; q++)
+    for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int a = 0; a < 4; a++) acc[q][a][0] = acc[q][a][1] = 0.0;
-    const double2 *Xs = X + ((long)r * nt + t) * V3 * 12;
-    for (long xyz = threadIdx.x; xyz < V3; xyz += blockDim.x) {
-        double2 xv[12];
-#pragma unroll
-        for (int k = 0; k < 12; k++) xv[k] = Xs[xyz * 12 + k];
-#pragma unroll
-        for (int q = 0; q < NT; q++) {
-            int n = n0 + q;
-            if (n >= nv) break;
-            const double2 *vp = evecs + (((long)t * nv + n) * V3 + xyz) * 3;
-            double2 v0 = vp[0], v1 = vp[1], v2 = vp[2];
-#pragma unroll
-            for (int a = 0; a < 4; a++) {
-                double2 s = cadd(cadd(cconjmul(v0, xv[a * 3]), cconjmul(v1, xv[a * 3 + 1])), cconjmul(v2, xv[a * 3 + 2]));
-                acc[q][a][0] += s.x;
-                acc[q][a][1] += s.y;
-            }
+        for (int j = 0; j < 7; j++) acc[i][j][0] = acc[i][j][1] = 0.0;
+    for (long xs = x0; xs < x1; xs += kSinkX) {
+        const int nx = (int)std::min((long)kSinkX, x1 - xs);
+        // stage X: 16 RHS x nx sites x 12 components (each RHS's sites are contiguous)
+        for (int k = threadIdx.x; k < (kSinkM / 4) * kSinkX * 12; k += blockDim.x) {
+            const int rr = k / (kSinkX * 12), e = k - rr * (kSinkX * 12);
+            const int r = r0 + rr;
+            double2 v = make_double2(0.0, 0.0);
+            if (r < nrhs && e < nx * 12) v = X[(((long)r * nt + t) * V3 + xs) * 12 + e];
+            sa[rr][e] = v;
         }
-    }
-    // wave reduction, then across the waves of the block
-    __shared__ double lds[4][NT * 8];
-    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < NT; q++)
-#pragma unroll
-        for (int a = 0; a < 4; a++)
-#pragma unroll
-            for (int p = 0; p < 2; p++) {
-                double v = acc[q][a][p];
-                for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-                if (lane == 0) lds[wave][(q * 4 + a) * 2 + p] = v;
+        // stage V: kSinkN columns x nx sites x 3 colours, conjugated
+        for (int k = threadIdx.x; k < kSinkN * kSinkX * 3; k += blockDim.x) {
+            const int nn = k / (kSinkX * 3), e = k - nn * (kSinkX * 3);
+            const int n = nt0 + nn;
+            double2 v = make_double2(0.0, 0.0);
+            if (n < nv && e < nx * 3) {
+                v = evecs[(((long)t * nv + n) * V3 + xs) * 3 + e];
+                v.y = -v.y;
             }
-    __syncthreads();
-    if ((int)threadIdx.x < NT * 4) {
-        int q = threadIdx.x / 4, a = threadIdx.x % 4;
-        int n = n0 + q;
-        if (n < nv) {
-            double re = 0, im = 0;
-            for (int w = 0; w < (int)(blockDim.x / 64); w++) {
-                re += lds[w][(q * 4 + a) * 2];
-                im += lds[w][(q * 4 + a) * 2 + 1];
-            }
-            coef[(((long)r * nt + t) * 4 + a) * nv + n] = make_double2(re, im);
+            sb[nn][e] = v;
         }
+        __syncthreads();
+#pragma unroll 2
+        for (int xi = 0; xi < kSinkX; xi++)
+#pragma unroll
+            for (int cc = 0; cc < 3; cc++) {
+                double2 bv[7];
+#pragma unroll
+                for (int j = 0; j < 7; j++) bv[j] = sb[tn + 16 * j][xi * 3 + cc];
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    // row tm * 4 + i = (rhs (tm * 4 + i) / 4, spin (tm * 4 + i) % 4) = (tm, i)
+                    const double2 av = sa[tm][xi * 12 + i * 3 + cc];
+#pragma unroll
+                    for (int j = 0; j < 7; j++) {
+                        acc[i][j][0] = fma(av.x, bv[j].x, fma(-av.y, bv[j].y, acc[i][j][0]));
+                        acc[i][j][1] = fma(av.x, bv[j].y, fma(av.y, bv[j].x, acc[i][j][1]));
+                    }
+                }
+            }
+        __syncthreads();
     }
+    // part[z][r][t][alpha][n]
+    const int r = r0 + tm;
+    if (r >= nrhs) return;
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 7; j++) {
+            const int n = nt0 + tn + 16 * j;
+            if (n < nv)
+                part[((((long)blockIdx.z * nrhs + r) * nt + t) * 4 + i) * nv + n] =
+                    make_double2(acc[i][j][0], acc[i][j][1]);
+        }
+}
+
+// coef = sum over the site ranges of the partial products, in range order
+__global__ void k_sink_reduce(const double2 *__restrict__ part, int nz, long m, double2 *__restrict__ coef)
+{
+    long q = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    double2 s = make_double2(0.0, 0.0);
+    for (int z = 0; z < nz; z++) s = cadd(s, part[(long)z * m + q]);
+    coef[q] = s;
 }
 
 Dil make_dil(const laph_dilution *dil, int nt, int nv)
@@ -200,9 +236,22 @@ extern "C" int sink_project(laph_ctx_t c, const double *evecs, int nv, const dou
     g_current_ctx = c;
     LAPH_CHECK(evecs && X && coef && nv > 0 && n_rhs > 0, LAPH_EINVAL, "bad arguments");
     LAPH_CHECK(n_rhs <= 65535, LAPH_EINVAL, "n_rhs too large for one call");
-    dim3 grid(c->g.nt, (nv + NT - 1) / NT, n_rhs);
-    hipLaunchKernelGGL(k_sink, grid, dim3(256), 0, c->stream, (const double2 *)evecs, (const double2 *)X, c->g.V3,
-                       c->g.nt, nv, (double2 *)coef);
+    // tiled product: one block per (t, row tile x column tile, site range); the site
+    // ranges give about 2048 blocks in all
+    const int mtiles = (n_rhs * 4 + kSinkM - 1) / kSinkM, ntiles = (nv + kSinkN - 1) / kSinkN;
+    const long base = (long)c->g.nt * mtiles * ntiles;
+    long nz = std::max(1L, std::min(c->g.V3 / (8 * kSinkX), 2048 / std::max(1L, base)));
+    long xper = (c->g.V3 + nz - 1) / nz;
+    xper = (xper + kSinkX - 1) / kSinkX * kSinkX;
+    nz = (c->g.V3 + xper - 1) / xper;
+    LAPH_CHECK(mtiles * ntiles <= 65535 && nz <= 65535, LAPH_EINVAL, "sink projection too large for one call");
+    const long m = (long)n_rhs * c->g.nt * 4 * nv;
+    double2 *part = (double2 *)ctx_named(c, "sink.part", sizeof(double2) * m * nz);
+    hipLaunchKernelGGL(k_sink_tiled, dim3(c->g.nt, mtiles * ntiles, nz), dim3(256), 0, c->stream,
+                       (const double2 *)evecs, (const double2 *)X, c->g.V3, c->g.nt, nv, n_rhs, (int)xper, part);
+    LAPH_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sink_reduce, dim3(nblocks_for(m, 256)), dim3(256), 0, c->stream, (const double2 *)part,
+                       (int)nz, m, (double2 *)coef);
     LAPH_HIP(hipGetLastError());
     LAPH_API_END(c)
 }

@@ -37,7 +37,7 @@ struct MrArgs {
     int wby, wbz;
     // multiply-high reciprocals of the kernel's index divisors (ns/2, ns, nt, wby,
     // ns/wby, ns/2 wby wbz): q = umulhi(n, m) is n / d for every n the kernel divides
-    // (the launcher checks Vh d < 2^32); 0: plain division
+    // (the launcher checks Vh d < 2^32); 0 stands for d = 1
     unsigned m_nsh, m_ns, m_nt, m_by, m_nty, m_A;
     // 1.0, passed at run time: a + (+-unit) b stays one mixed-precision FMA per component
     // for FP16 records instead of being folded into two conversions and an add

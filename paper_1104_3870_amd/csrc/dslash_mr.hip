@@ -571,10 +571,12 @@ __device__ __forceinline__ void clover_one(const float4 *p, const Cx<float> (&in
 // sites per block for R right-hand sides (block = S R lanes)
 inline size_t lds_bytes(int S) { return (size_t)S * (8 * kLkF4 + 18) * sizeof(float4); }
 
-// n / d through the launcher's multiply-high reciprocal m (plain division when m = 0)
+// n / d through the launcher's multiply-high reciprocal m; m = 0 stands for d = 1 (the
+// launcher guarantees a valid m for every other divisor, so no division code is emitted)
 __device__ __forceinline__ unsigned udiv(unsigned n, unsigned d, unsigned m)
 {
-    return m ? __umulhi(n, m) : n / d;
+    (void)d;
+    return m ? __umulhi(n, m) : n;
 }
 
 // checkerboard index and coordinates of position pos of the site walk (MrArgs::wby):
@@ -962,11 +964,15 @@ static bool use_lds_kernel()
     return v == 1;
 }
 
-// the LDS-staged kernel indexes sites in 32 bits and reads neighbour records through
-// 32-bit byte offsets
-static bool lds_fits(long Vh, int R, long rec_bytes) { return Vh * R * 12 < (1L << 31) && Vh * R * rec_bytes < (1L << 32); }
+// the LDS-staged kernel indexes sites in 32 bits, reads neighbour records through 32-bit
+// byte offsets and divides site indices by ns and ns / 2 with multiply-high reciprocals
+static bool lds_fits(long Vh, int R, long rec_bytes, int ns = 2)
+{
+    return Vh * R * 12 < (1L << 31) && Vh * R * rec_bytes < (1L << 32) &&
+           (unsigned long long)Vh * (unsigned long long)ns < (1ull << 32);
+}
 
-bool lds_dag_ok(laph_ctx *c, int R) { return use_lds_kernel() && lds_fits(c->g.Vh, R, 96); }
+bool lds_dag_ok(laph_ctx *c, int R) { return use_lds_kernel() && lds_fits(c->g.Vh, R, 96, c->g.ns); }
 
 long lds_dag_blocks(laph_ctx *c, int prec, int R)
 {
@@ -991,33 +997,37 @@ static int walk_tile(int ns, int k)
 }
 
 // m = ceil(2^32 / d): umulhi(n, m) = floor(n / d) whenever n d < 2^32 (m d - 2^32 < d);
-// 0 (plain division) when d = 1 or some n < nmax would break that bound
-static unsigned umulhi_magic(long d, long nmax)
+// 0 for d = 1
+static unsigned umulhi_magic(long d)
 {
-    if (d <= 1 || (unsigned long long)nmax * (unsigned long long)d >= (1ull << 32)) return 0;
+    if (d <= 1) return 0;
     return (unsigned)(((1ull << 32) + (unsigned long long)d - 1) / (unsigned long long)d);
 }
+// every index n the kernel divides by d is below nmax: the reciprocal is exact when
+static bool magic_ok(long d, long nmax) { return (unsigned long long)nmax * (unsigned long long)d < (1ull << 32); }
 
 template <class SP>
 void launch_dslash_mr(laph_ctx *c, int mode, const MrArgs &a, hipStream_t st)
 {
-    if (use_lds_kernel() && lds_fits(a.Vh, a.R, sizeof(Spin12<SP>))) {
+    if (use_lds_kernel() && lds_fits(a.Vh, a.R, sizeof(Spin12<SP>), a.ns)) {
         const int S = lds_tile_sites(c, prec_id<SP>(), a.R);
         MrArgs b = a;
         const int by = walk_tile(a.ns, 0), bz = walk_tile(a.ns, 1);
         const long A = (long)(a.ns / 2) * by * bz;
-        if (by > 0 && bz > 0) {
+        // the walk's divisors (tile slice, nt, tile extent, tiles per row) need exact
+        // reciprocals for every position below Vh; otherwise checkerboard order
+        if (by > 0 && bz > 0 && magic_ok(A, a.Vh) && magic_ok(a.nt, a.Vh) && magic_ok(a.ns, a.Vh)) {
             b.wby = by;
             b.wbz = bz;
         } else {
             b.wby = b.wbz = 0;
         }
-        b.m_nsh = umulhi_magic(a.ns / 2, a.Vh);
-        b.m_ns = umulhi_magic(a.ns, a.Vh);
-        b.m_nt = umulhi_magic(a.nt, a.Vh);
-        b.m_by = b.wby ? umulhi_magic(b.wby, a.Vh) : 0;
-        b.m_nty = b.wby ? umulhi_magic(a.ns / b.wby, a.Vh) : 0;
-        b.m_A = b.wby ? umulhi_magic(A, a.Vh) : 0;
+        b.m_nsh = umulhi_magic(a.ns / 2);
+        b.m_ns = umulhi_magic(a.ns);
+        b.m_nt = umulhi_magic(a.nt);
+        b.m_by = b.wby ? umulhi_magic(b.wby) : 0;
+        b.m_nty = b.wby ? umulhi_magic(a.ns / b.wby) : 0;
+        b.m_A = b.wby ? umulhi_magic(A) : 0;
         b.unit = 1.0f;
         b.tgauge = a.tgauge;
         dim3 grid(nblocks_for(a.Vh, S)), block(S * a.R);

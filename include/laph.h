@@ -201,6 +201,9 @@ typedef struct {
     double reliable_delta; /* mixed precision: FP64 reliable update as soon as the iterated
                               even-odd residual fell below this fraction of its last FP64
                               value (0: 0.1), and at the latest every reliable_every iterations */
+    int dir_buffers;    /* mixed-precision CGNR: search directions kept until their steps are
+                           added to the solution increment, which is then read and written once
+                           per that many iterations (1..8; 0: 8) */
 } laph_solver;
 
 typedef struct {

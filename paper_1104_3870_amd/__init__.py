@@ -60,7 +60,7 @@ class laph_solver(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("solver", ctypes.c_int),
                 ("precision", ctypes.c_int), ("reliable_every", ctypes.c_int), ("block_rhs", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("net", ctypes.c_void_p), ("restart", ctypes.c_int),
-                ("reliable_delta", ctypes.c_double)]
+                ("reliable_delta", ctypes.c_double), ("dir_buffers", ctypes.c_int)]
 
 
 class laph_tune_entry(ctypes.Structure):
@@ -287,11 +287,11 @@ def laph_get_timing(ctx, reset=False):
 
 
 def solver_params(tol=1e-10, maxiter=20000, precision="f64", solver=LAPH_SOLVER_BICGSTAB, reliable_every=50,
-                  block_rhs=1, use_graph=0, net=None, restart=0, reliable_delta=0.0):
+                  block_rhs=1, use_graph=0, net=None, restart=0, reliable_delta=0.0, dir_buffers=0):
     """laph_solver; `net` is a PTNet (or raw handle) used by LAPH_SOLVER_FGMRES."""
     h = net.handle if isinstance(net, PTNet) else net
     return laph_solver(tol, maxiter, solver, PRECISIONS[precision] if isinstance(precision, str) else precision,
-                       reliable_every, block_rhs, use_graph, h, restart, reliable_delta)
+                       reliable_every, block_rhs, use_graph, h, restart, reliable_delta, dir_buffers)
 
 
 def laph_ptnet_create(ctx, channels, seed=0):

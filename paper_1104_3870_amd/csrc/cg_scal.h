@@ -4,6 +4,10 @@
 
 #include <hip/hip_runtime.h>
 
+// most directions whose steps the CG solution increment may still owe (the current one
+// included)
+constexpr int kMaxDirs = 8;
+
 struct Scal {
     double2 rho, alpha, omega, beta;
     double2 aux;      // <r, p> / |r|^2 after a reliable update (CG)
@@ -12,7 +16,8 @@ struct Scal {
     double r2hi;      // |r|^2 of the last FP64 residual
     double tol2;      // target |r|^2 of the even-odd system
     double b2;        // |bhat|^2
-    double alpha_prev;  // alpha of the previous CG iteration (steps the direction update still owes x)
+    double alpha_prev[kMaxDirs - 1];  // alpha of the previous CG iterations, latest first (steps
+                                      // the direction update still owes x)
     int active;
     int iters;
     int breakdown;

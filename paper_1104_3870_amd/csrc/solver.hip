@@ -102,6 +102,29 @@ __device__ __forceinline__ void st_site(Vec &v, long Vh, int R, long i, int r, c
     st_spinor12<SP, double>((typename SP::E *)v.d, v.n, Vh, R, i, r, o);
 }
 
+// CG directions whose steps the solution increment still owes, latest first: d[0] takes
+// the current alpha, d[j] (j >= 1) the alpha of j iterations back
+struct Dirs {
+    Vec d[kMaxDirs];
+    int n = 0;
+};
+
+// o += sum_{j < n} coef_j d_j (static indices: the list stays in kernel arguments)
+template <class SP>
+__device__ __forceinline__ void add_steps(const Dirs &dirs, int n, const Scal &s, long Vh, int R, long i, int r,
+                                          Cx<double> (&o)[12])
+{
+#pragma unroll
+    for (int j = 0; j < kMaxDirs; j++) {
+        if (j >= n) break;
+        const double al = j ? s.alpha_prev[j - 1] : s.alpha.x;
+        Cx<double> b[12];
+        ld_site<SP>(dirs.d[j], Vh, R, i, r, b);
+#pragma unroll
+        for (int k = 0; k < 12; k++) o[k] = o[k] + al * b[k];
+    }
+}
+
 __device__ __forceinline__ double2 c2(Cx<double> a) { return make_double2(a.re, a.im); }
 __device__ __forceinline__ Cx<double> cx(double2 a) { return {a.x, a.y}; }
 
@@ -357,11 +380,10 @@ __global__ __launch_bounds__(kBS) void k_fold_x(Vec xhi, Vec xlo, long Vh, int R
     st_site<XP>(xlo, Vh, R, i, rr, z);
 }
 
-// the same fold with the steps the direction update still owes x: xhi += xlo + alpha p
-// (+ alpha_prev pprev when prev) (right-hand sides with mask set)
+// the same fold with the steps the direction update still owes x:
+// xhi += xlo + sum_j coef_j d_j (right-hand sides with mask set)
 template <class XP, class SP>
-__global__ __launch_bounds__(kBS) void k_fold_x_step(Vec xhi, Vec xlo, Vec p, Vec pprev, long Vh, int R,
-                                                     const Scal *sc, int prev)
+__global__ __launch_bounds__(kBS) void k_fold_x_step(Vec xhi, Vec xlo, Dirs dirs, long Vh, int R, const Scal *sc)
 {
     long n = Vh * R;
     long tid = blockIdx.x * (long)kBS + threadIdx.x;
@@ -369,24 +391,15 @@ __global__ __launch_bounds__(kBS) void k_fold_x_step(Vec xhi, Vec xlo, Vec p, Ve
     long i = tid / R;
     int rr = (int)(tid - i * R);
     if (!sc[rr].active) return;
-    const double al = sc[rr].alpha.x;
     Cx<double> a[12], b[12], z[12];
     ld_site<S64>(xhi, Vh, R, i, rr, a);
     ld_site<XP>(xlo, Vh, R, i, rr, b);
 #pragma unroll
-    for (int k = 0; k < 12; k++) a[k] = a[k] + b[k];
-    ld_site<SP>(p, Vh, R, i, rr, b);
-#pragma unroll
     for (int k = 0; k < 12; k++) {
-        a[k] = a[k] + al * b[k];
+        a[k] = a[k] + b[k];
         z[k] = {0, 0};
     }
-    if (prev) {
-        const double ap = sc[rr].alpha_prev;
-        ld_site<SP>(pprev, Vh, R, i, rr, b);
-#pragma unroll
-        for (int k = 0; k < 12; k++) a[k] = a[k] + ap * b[k];
-    }
+    add_steps<SP>(dirs, dirs.n, sc[rr], Vh, R, i, rr, a);
     st_site<S64>(xhi, Vh, R, i, rr, a);
     st_site<XP>(xlo, Vh, R, i, rr, z);
 }
@@ -416,10 +429,10 @@ __global__ __launch_bounds__(kBS) void k_resid64(Vec b, Vec m, Vec r, long Vh, i
 }
 
 // mode 0: r2hi = sum, and mask off converged (r2hi <= tol2); mode 1: b2 = sum
-// the steps the direction update still owes x go into the increment: xlo += alpha p
-// (+ alpha_prev pprev when prev) (right-hand sides with mask set)
+// the steps the direction update still owes x go into the increment:
+// xlo += sum_j coef_j d_j (right-hand sides with mask set)
 template <class XP, class SP>
-__global__ __launch_bounds__(kBS) void k_owe_xlo(Vec xlo, Vec p, Vec pprev, long Vh, int R, const Scal *sc, int prev)
+__global__ __launch_bounds__(kBS) void k_owe_xlo(Vec xlo, Dirs dirs, long Vh, int R, const Scal *sc)
 {
     long n = Vh * R;
     long tid = blockIdx.x * (long)kBS + threadIdx.x;
@@ -427,18 +440,9 @@ __global__ __launch_bounds__(kBS) void k_owe_xlo(Vec xlo, Vec p, Vec pprev, long
     long i = tid / R;
     int rr = (int)(tid - i * R);
     if (!sc[rr].active) return;
-    const double al = sc[rr].alpha.x;
-    Cx<double> a[12], b[12];
+    Cx<double> a[12];
     ld_site<XP>(xlo, Vh, R, i, rr, a);
-    ld_site<SP>(p, Vh, R, i, rr, b);
-#pragma unroll
-    for (int k = 0; k < 12; k++) a[k] = a[k] + al * b[k];
-    if (prev) {
-        const double ap = sc[rr].alpha_prev;
-        ld_site<SP>(pprev, Vh, R, i, rr, b);
-#pragma unroll
-        for (int k = 0; k < 12; k++) a[k] = a[k] + ap * b[k];
-    }
+    add_steps<SP>(dirs, dirs.n, sc[rr], Vh, R, i, rr, a);
     st_site<XP>(xlo, Vh, R, i, rr, a);
 }
 
@@ -648,7 +652,8 @@ __global__ void k_fin_cg_alpha(const double *partial, int nblk, int R, Scal *sc,
         q.alpha = make_double2(0, 0);
         return;
     }
-    q.alpha_prev = q.alpha.x;
+    for (int j = kMaxDirs - 2; j > 0; j--) q.alpha_prev[j] = q.alpha_prev[j - 1];
+    q.alpha_prev[0] = q.alpha.x;
     if (!(s[0] > 0) || !std::isfinite(s[0])) {
         q.alpha = make_double2(0, 0);
         q.breakdown = 1;
@@ -735,13 +740,12 @@ __global__ void k_fin_cg_beta(const double *partial, int nblk, int R, Scal *sc, 
     if (hi_conv && (s[1] <= q.tol2 || !(s[0] > 0))) q.active = 0;
 }
 
-// direction update pout = r + beta pcur (real beta); pout may be pcur or another buffer.
-// The solution increment takes the steps along the directions first: xmode 1:
-// x += alpha pcur; xmode 2: x += alpha_prev pprev + alpha pcur (the step of the previous
-// iteration, whose direction pprev is still held, and this one's)
+// direction update pout = r + beta d_0 (real beta); pout may be d_0, the oldest direction
+// d_{n-1}, or another buffer.  With nsteps > 0 the solution increment first takes the steps
+// still owed along the directions: x += sum_{j < nsteps} coef_j d_j
 template <class SP, class XP>
-__global__ __launch_bounds__(kBS) void k_cg_p(Vec pout, Vec pcur, Vec pprev, Vec r, Vec x, long Vh, int R,
-                                              const Scal *sc, int xmode)
+__global__ __launch_bounds__(kBS) void k_cg_p(Vec pout, Dirs dirs, Vec r, Vec x, long Vh, int R, const Scal *sc,
+                                              int nsteps)
 {
     long n = Vh * R;
     long tid = blockIdx.x * (long)kBS + threadIdx.x;
@@ -751,21 +755,12 @@ __global__ __launch_bounds__(kBS) void k_cg_p(Vec pout, Vec pcur, Vec pprev, Vec
     if (!sc[rr].active) return;
     double be = sc[rr].beta.x;
     Cx<double> a[12], b[12];
-    ld_site<SP>(pcur, Vh, R, i, rr, a);
-    if (xmode) {
-        const double al = sc[rr].alpha.x;
+    if (nsteps) {
         ld_site<XP>(x, Vh, R, i, rr, b);
-#pragma unroll
-        for (int k = 0; k < 12; k++) b[k] = b[k] + al * a[k];
-        if (xmode == 2) {
-            const double ap = sc[rr].alpha_prev;
-            Cx<double> c[12];
-            ld_site<SP>(pprev, Vh, R, i, rr, c);
-#pragma unroll
-            for (int k = 0; k < 12; k++) b[k] = b[k] + ap * c[k];
-        }
+        add_steps<SP>(dirs, nsteps, sc[rr], Vh, R, i, rr, b);
         st_site<XP>(x, Vh, R, i, rr, b);
     }
+    ld_site<SP>(dirs.d[0], Vh, R, i, rr, a);
     ld_site<SP>(r, Vh, R, i, rr, b);
 #pragma unroll
     for (int k = 0; k < 12; k++) a[k] = b[k] + be * a[k];
@@ -1057,6 +1052,7 @@ struct Work {
     double *part;  // device partials [kMaxBlocks][R][4]
     bool use_graph = false;  // capture the CG iteration body in a HIP graph
     double delta2 = 0.01;    // reliable update when |res|^2 fell below delta2 times its last FP64 value
+    int dirs = 0;            // direction buffers of the fused CG loop (0: the default)
     Vec make(const char *name, int bytes, bool norm)
     {
         Vec v;
@@ -1129,6 +1125,20 @@ static bool use_lag()
         v = (e && *e == '0') ? 0 : 1;
     }
     return v == 1;
+}
+
+// direction buffers of the fused CG loop where the solver parameters leave them open
+// (LAPH_DIRS=1..8 overrides the default): the FP32 solution increment
+// takes the owed steps every that many iterations
+constexpr int kDefaultDirs = 8;
+static int cg_dir_buffers()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("LAPH_DIRS");
+        v = (e && *e >= '1' && *e <= '0' + kMaxDirs && !e[1]) ? *e - '0' : kDefaultDirs;
+    }
+    return v;
 }
 
 void write_scal(laph_ctx *c, Scal *d, const std::vector<Scal> &h)
@@ -1286,6 +1296,25 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
         part_hop = (double *)ctx_named(c, "slv.part_hop", sizeof(double) * nblk_hop * w.R);
         part_pre = (double *)ctx_named(c, "slv.part_pre", sizeof(double) * kChunks * w.R);
     }
+    // the fused body leaves the steps x += alpha p to the direction update; with K direction
+    // buffers (a ring) each update writes the new direction into the next buffer and keeps
+    // the old ones, and every K-th update takes the K owed steps at once: the FP32 increment
+    // is read and written every K-th iteration only (graph replay keeps one captured body per
+    // direction buffer)
+    const int K = !fuse ? 1 : w.dirs > 0 ? w.dirs : cg_dir_buffers();
+    Vec pb[kMaxDirs];
+    pb[0] = p;
+    for (int j = 1; j < K; j++) pb[j] = w.make(("cg.p" + std::to_string(j + 1)).c_str(), SP::bytes, nrm);
+    int cur = 0;            // p is pb[cur]
+    bool step_now = false;  // this iteration's step is owed to x
+    int nowed = 0;          // earlier steps owed too, their directions in pb[cur - 1], ..., pb[cur - nowed]
+    // cnt directions, latest first, starting first buffers behind p's
+    auto owed_dirs = [&](int first, int cnt) {
+        Dirs d;
+        for (int j = 0; j < cnt; j++) d.d[j] = K == 1 ? p : pb[((cur - first - j) % K + K) % K];
+        d.n = cnt;
+        return d;
+    };
     auto body = [&](const Op<SP, GP, CP> &op) {
         if (fuse) {
             // M p with |q|^2 and A^-1 gamma_5 q from its epilogue; M^dag q feeding the CG
@@ -1313,18 +1342,8 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
             launch_fin(c, k_fin_cg_beta, w.R, (const double *)w.part, nblk, w.R, w.sc, plain ? 1 : 0, plain ? 0 : 1,
                        0);
         }
-        if (plain) launch_el(c, k_cg_p<SP, XP>, n, p, p, p, r, xlo, w.Vh, w.R, (const Scal *)w.sc, 0);
+        if (plain) launch_el(c, k_cg_p<SP, XP>, n, p, owed_dirs(0, 1), r, xlo, w.Vh, w.R, (const Scal *)w.sc, 0);
     };
-    // the fused body leaves the step x += alpha p to the direction update; with two
-    // direction buffers every other update writes the new direction into the other buffer
-    // and keeps the old one, and the next update takes both steps: the FP32 increment is
-    // read and written every second iteration only (graph replay keeps one captured body
-    // per direction buffer)
-    const bool pp = fuse;
-    Vec pother = pp ? w.make("cg.p2", SP::bytes, nrm) : p;
-    const void *pbuf0 = p.d;
-    bool step_now = false;   // this iteration's step is owed to x
-    bool step_prev = false;  // the previous iteration's step is owed too (its direction in pother)
     // lagged decisions (low precision): the scalars of iteration k are copied to a pinned
     // slot behind its hops; the update rule at iteration k reads iteration k - 1's slot,
     // long complete, so the host never waits for the queue to drain (an update or the
@@ -1345,21 +1364,21 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
     Scal *pin = lag ? pinned_scal(c, w.R) : nullptr;
     int slot = 0;
     bool prev_ok = false;  // the other slot holds the previous iteration's scalars
-    hipGraphExec_t gexecs[2] = {nullptr, nullptr};  // body captured with p in either buffer
+    hipGraphExec_t gexecs[kMaxDirs] = {};  // body captured with p in each buffer
     const bool graph_ok = w.use_graph && !c->timing;
     if (graph_ok && !c->cap_stream) LAPH_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     struct GraphGuard {
         hipGraphExec_t *g;
         ~GraphGuard()
         {
-            for (int k = 0; k < 2; k++)
+            for (int k = 0; k < kMaxDirs; k++)
                 if (g[k]) (void)hipGraphExecDestroy(g[k]);
         }
     } guard{gexecs};
     for (int it = 0; it < maxiter;) {
         int chunk = std::min(check_every, maxiter - it);
         for (int k = 0; k < chunk; k++) {
-            hipGraphExec_t &gexec = gexecs[p.d == pbuf0 ? 0 : 1];
+            hipGraphExec_t &gexec = gexecs[cur];
             if (gexec) {
                 LAPH_HIP(hipGraphLaunch(gexec, c->stream));
             } else if (graph_ok) {
@@ -1430,8 +1449,8 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
             if (track) {
                 if constexpr (std::is_same<XP, S32>::value) {
                     if (step_now)
-                        launch_el(c, k_owe_xlo<XP, SP>, n, xlo, p, pother, w.Vh, w.R, (const Scal *)w.sc,
-                                  step_prev ? 1 : 0);
+                        launch_el(c, k_owe_xlo<XP, SP>, n, xlo, owed_dirs(0, 1 + nowed), w.Vh, w.R,
+                                  (const Scal *)w.sc);
                     Op<XP, G32, C32> lo32{c, lo.st, lo.Vh, lo.R, nullptr, nullptr, nullptr, lo.ws, lo.wt, lo.bct, te32};
                     lo32.lk12 = lo.lk12;
                     lo32.claos = lo.claos;
@@ -1442,13 +1461,14 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
                 }
             } else {
                 if (step_now)  // the fold takes the steps still owed to x
-                    launch_el(c, k_fold_x_step<XP, SP>, n, xhi, xlo, p, pother, w.Vh, w.R, (const Scal *)w.sc,
-                              step_prev ? 1 : 0);
+                    launch_el(c, k_fold_x_step<XP, SP>, n, xhi, xlo, owed_dirs(0, 1 + nowed), w.Vh, w.R,
+                              (const Scal *)w.sc);
                 else
                     launch_el(c, k_fold_x<XP>, n, xhi, xlo, w.Vh, w.R, (const Scal *)w.sc, 0);
                 true_eo_residual(w, hi, bhat, xhi, tmp64, reshi, 0);
             }
-            step_now = step_prev = false;
+            step_now = false;
+            nowed = 0;
             launch_el(c, k_convert_masked<SP>, n, reshi, res, w.Vh, w.R, (const Scal *)w.sc);
             lo.mhat_dag(res, r, to);
             launch_red(c, k_normsq2<SP>, n, r, res, w.Vh, w.R, w.part);
@@ -1466,21 +1486,24 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
             }
             if (!left) break;
         }
-        if (!pp || !step_now) {
-            launch_el(c, k_cg_p<SP, XP>, n, p, p, p, r, xlo, w.Vh, w.R, (const Scal *)w.sc, step_now ? 1 : 0);
-        } else if (!step_prev) {
-            // keep this direction for the next update, which takes both steps
-            launch_el(c, k_cg_p<SP, XP>, n, pother, p, p, r, xlo, w.Vh, w.R, (const Scal *)w.sc, 0);
-            std::swap(p, pother);
-            step_prev = true;
+        if (K == 1 || !step_now) {
+            launch_el(c, k_cg_p<SP, XP>, n, p, owed_dirs(0, 1), r, xlo, w.Vh, w.R, (const Scal *)w.sc,
+                      step_now ? 1 : 0);
         } else {
-            launch_el(c, k_cg_p<SP, XP>, n, pother, p, pother, r, xlo, w.Vh, w.R, (const Scal *)w.sc, 2);
-            std::swap(p, pother);
-            step_prev = false;
+            // the new direction goes into the next buffer: a free one, or with every buffer
+            // holding an owed direction the oldest, whose step (with all others) is taken now
+            const bool take = nowed + 1 == K;
+            const int nxt = (cur + 1) % K;
+            launch_el(c, k_cg_p<SP, XP>, n, pb[nxt], owed_dirs(0, 1 + nowed), r, xlo, w.Vh, w.R, (const Scal *)w.sc,
+                      take ? K : 0);
+            cur = nxt;
+            p = pb[cur];
+            nowed = take ? 0 : nowed + 1;
         }
     }
-    // a step still owed after the last iteration (its alpha is the current one)
-    if (step_prev) launch_el(c, k_fold_x_step<XP, SP>, n, xhi, xlo, pother, pother, w.Vh, w.R, (const Scal *)w.sc, 0);
+    // steps still owed after the last iteration (the latest takes the current alpha)
+    if (nowed)
+        launch_el(c, k_fold_x_step<XP, SP>, n, xhi, xlo, owed_dirs(1, nowed), w.Vh, w.R, (const Scal *)w.sc);
     launch_el(c, k_fold_x<XP>, n, xhi, xlo, w.Vh, w.R, (const Scal *)w.sc, 1);
 }
 
@@ -1868,6 +1891,7 @@ void solve_batch(laph_ctx *c, const double *eta, double *x, int R, int nreal, co
     Work w{c, Vh, R, nullptr, nullptr};
     w.use_graph = sv->use_graph != 0;
     if (sv->reliable_delta > 0) w.delta2 = sv->reliable_delta * sv->reliable_delta;
+    w.dirs = sv->dir_buffers;
     w.sc = (Scal *)ctx_named(c, "slv.scal", sizeof(Scal) * R);
     w.part = (double *)ctx_named(c, "slv.part", sizeof(double) * kMaxBlocks * R * 4);
 
@@ -2123,6 +2147,7 @@ extern "C" int dirac_solve(laph_ctx_t c, const double *U, const laph_dirac *d, c
     check_dirac(d);
     LAPH_CHECK(sv->tol > 0 && sv->maxiter > 0, LAPH_EINVAL, "tol and maxiter must be positive");
     LAPH_CHECK(sv->reliable_delta >= 0 && sv->reliable_delta < 1, LAPH_EINVAL, "reliable_delta must be in [0, 1)");
+    LAPH_CHECK(sv->dir_buffers >= 0 && sv->dir_buffers <= kMaxDirs, LAPH_EINVAL, "dir_buffers must be in [0, 8]");
     LAPH_CHECK(sv->precision >= LAPH_PREC_F64 && sv->precision <= LAPH_PREC_BF16, LAPH_EINVAL, "bad precision");
     LAPH_CHECK(sv->solver == LAPH_SOLVER_BICGSTAB || sv->solver == LAPH_SOLVER_CGNR ||
                    sv->solver == LAPH_SOLVER_FGMRES,

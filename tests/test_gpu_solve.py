@@ -68,6 +68,30 @@ def test_cgnr_mixed_multi_rhs(P, setup, prec):
         assert rel_err(x[r], xs[r]) <= 1e-8
 
 
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_cgnr_direction_buffers(P, setup, prec):
+    """The fused CG loop keeps up to dir_buffers directions until their steps are added to
+    the solution increment.  Every ring size must give the same iterate up to rounding: a
+    step lost or taken twice would be repaired only by the next reliable update, at the
+    cost of extra iterations, so the iteration counts of all ring sizes must agree within
+    a few and every answer must meet the bar."""
+    cfg, U, D, etas, xs = setup
+    its = {}
+    for k in (1, 2, 3, 5, 8):
+        x, st = _solve(P, cfg, U, etas, precision=prec, block_rhs=8, solver=P.LAPH_SOLVER_CGNR, dir_buffers=k)
+        its[k] = [q.iters for q in st]
+        say("  dir_buffers", k, "iters", its[k])
+        for r in range(5):
+            assert st[r].status == 0 and st[r].fallback_used == 0
+            assert D.true_residual(etas[r], x[r]) <= 1e-10
+            assert rel_err(x[r], xs[r]) <= 1e-8
+    for r in range(5):
+        col = [its[k][r] for k in its]
+        assert max(col) - min(col) <= max(2, min(col) // 50), its
+    with pytest.raises(P.LaphError):
+        _solve(P, cfg, U, etas[:1], precision=prec, solver=P.LAPH_SOLVER_CGNR, dir_buffers=9)
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
 def test_multi_rhs_masked(P, setup, prec):
     """5 right-hand sides in blocks of 8 (padded, uneven convergence): each equals the

@@ -21,27 +21,60 @@ __device__ __forceinline__ void mat_dag_vec(const Cx<A> (&U)[9], const Cx<A> (&h
     for (int a = 0; a < 3; a++) o[a] = conjmul(U[a], h[0]) + conjmul(U[3 + a], h[1]) + conjmul(U[6 + a], h[2]);
 }
 
-template <class GP, typename A>
-__device__ __forceinline__ void load_link(const typename GP::E *g, int mu, int par, long Vh, long i, Cx<A> (&U)[9])
+// Element e of a field stored as planes of Vh (links, clover) or Vh R (spinors) entries:
+// plane + e.  With O32 (the launcher checks that every plane is below 4 GiB) the plane
+// start stays a uniform (scalar) address and each lane adds one 32-bit byte offset, so a
+// neighbour spinor costs one address register instead of twelve 64-bit pairs.
+template <bool O32, typename T>
+__device__ __forceinline__ const T &elem(const T *plane, long e)
 {
-    const typename GP::E *p = g + (long)(mu * 2 + par) * 9 * Vh + i;
-#pragma unroll
-    for (int k = 0; k < 9; k++) U[k] = GP::template ld<A>(p, (long)k * Vh);
+    if constexpr (O32)
+        return *(const T *)((const char *)plane + ((unsigned)e * (unsigned)sizeof(T)));
+    else
+        return plane[e];
+}
+template <bool O32, typename T>
+__device__ __forceinline__ T &elem(T *plane, long e)
+{
+    if constexpr (O32)
+        return *(T *)((char *)plane + ((unsigned)e * (unsigned)sizeof(T)));
+    else
+        return plane[e];
 }
 
-template <class SP>
+template <class GP, typename A, bool O32>
+__device__ __forceinline__ void load_link(const typename GP::E *g, int mu, int par, long Vh, long i, Cx<A> (&U)[9])
+{
+    const typename GP::E *p = g + (long)(mu * 2 + par) * 9 * Vh;
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        const auto v = elem<O32>(p + (long)k * Vh, i);
+        U[k] = {(A)v.x, (A)v.y};
+    }
+}
+
+template <class SP, bool O32>
 __device__ __forceinline__ void load_spinor(const typename SP::E *s, const float *nrm, long Vh, int R, long i, int r,
                                             Spin<typename SP::A> &out)
 {
     Cx<typename SP::A> v[12];
-    ld_spinor12<SP, typename SP::A>(s, nrm, Vh, R, i, r, v);
+    if constexpr (O32) {
+        static_assert(std::is_same<SP, S64>::value, "32-bit offsets: FP64 plane layout only");
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            const double2 e = elem<true>(s + (long)k * Vh * R, i * R + r);
+            v[k] = {e.x, e.y};
+        }
+    } else {
+        ld_spinor12<SP, typename SP::A>(s, nrm, Vh, R, i, r, v);
+    }
 #pragma unroll
     for (int a = 0; a < 4; a++)
 #pragma unroll
         for (int c = 0; c < 3; c++) out.v[a][c] = v[a * 3 + c];
 }
 
-template <class SP>
+template <class SP, bool O32>
 __device__ __forceinline__ void store_spinor(typename SP::E *s, float *nrm, long Vh, int R, long i, int r,
                                              const Spin<typename SP::A> &in)
 {
@@ -50,16 +83,22 @@ __device__ __forceinline__ void store_spinor(typename SP::E *s, float *nrm, long
     for (int a = 0; a < 4; a++)
 #pragma unroll
         for (int c = 0; c < 3; c++) v[a * 3 + c] = in.v[a][c];
-    st_spinor12<SP, typename SP::A>(s, nrm, Vh, R, i, r, v);
+    if constexpr (O32) {
+        static_assert(std::is_same<SP, S64>::value, "32-bit offsets: FP64 plane layout only");
+#pragma unroll
+        for (int k = 0; k < 12; k++) elem<true>(s + (long)k * Vh * R, i * R + r) = make_double2(v[k].re, v[k].im);
+    } else {
+        st_spinor12<SP, typename SP::A>(s, nrm, Vh, R, i, r, v);
+    }
 }
 
 // packed Hermitian 6x6 block times a 6-vector
-template <class CP, typename A>
+template <class CP, typename A, bool O32 = false>
 __device__ __forceinline__ void herm6(const typename CP::E *cl, long Vh, long i, const Cx<A> (&v)[6], Cx<A> (&o)[6])
 {
     A d[6];
 #pragma unroll
-    for (int k = 0; k < 6; k++) d[k] = (A)cl[(long)k * Vh + i];
+    for (int k = 0; k < 6; k++) d[k] = (A)elem<O32>(cl + (long)k * Vh, i);
 #pragma unroll
     for (int k = 0; k < 6; k++) o[k] = d[k] * v[k];
     int e = 6;
@@ -67,14 +106,14 @@ __device__ __forceinline__ void herm6(const typename CP::E *cl, long Vh, long i,
     for (int r = 1; r < 6; r++)
 #pragma unroll
         for (int c = 0; c < r; c++) {
-            Cx<A> L = {(A)cl[(long)e * Vh + i], (A)cl[(long)(e + 1) * Vh + i]};
+            Cx<A> L = {(A)elem<O32>(cl + (long)e * Vh, i), (A)elem<O32>(cl + (long)(e + 1) * Vh, i)};
             e += 2;
             o[r] = o[r] + L * v[c];
             o[c] = o[c] + conjmul(L, v[r]);
         }
 }
 
-template <class CP, typename A>
+template <class CP, typename A, bool O32 = false>
 __device__ __forceinline__ void clover_mul(const typename CP::E *cl, long Vh, long i, const Spin<A> &in, Spin<A> &out)
 {
 #pragma unroll
@@ -84,7 +123,7 @@ __device__ __forceinline__ void clover_mul(const typename CP::E *cl, long Vh, lo
         for (int s = 0; s < 2; s++)
 #pragma unroll
             for (int c = 0; c < 3; c++) v[s * 3 + c] = in.v[blk * 2 + s][c];
-        herm6<CP, A>(cl + (long)blk * 36 * Vh, Vh, i, v, o);
+        herm6<CP, A, O32>(cl + (long)blk * 36 * Vh, Vh, i, v, o);
 #pragma unroll
         for (int s = 0; s < 2; s++)
 #pragma unroll
@@ -102,7 +141,83 @@ __device__ __forceinline__ void acc_upper(Spin<A> &acc, const Cx<A> (&w0)[3], co
     }
 }
 
-template <class SP, class GP, class CP, int MODE>
+// Rolled FP64 hops: one loop trip per direction d = 2 mu + (backward), the spin structure
+// of (1 -/+ gamma_mu) taken from per-direction unit coefficients, so that only one
+// direction's neighbour and link are live at a time (150 instead of ~290 registers: three
+// waves per SIMD instead of one for this latency-bound kernel).
+// h0 = w s0 + a0 s_p0, h1 = w s1 + a1 s_p1 (p0, p1) = (3, 2) for mu < 2, else (2, 3);
+// acc0 += o0, acc1 += o1, acc2 += b2 o_q2, acc3 += b3 o_q3 with (q2, q3) = (1, 0) for
+// mu < 2, else (0, 1); forward units below (the gamma matrices of the chiral basis),
+// backward hops negate them and take U_mu(x - mu)^dag.
+struct HopCoef {
+    double a0r, a0i, a1r, a1i, b2r, b2i, b3r, b3i;
+};
+__device__ __forceinline__ Cx<double> unit_mul(double ur, double ui, Cx<double> z)
+{
+    return {ur * z.re - ui * z.im, ur * z.im + ui * z.re};
+}
+
+template <bool O32>
+__device__ __forceinline__ void hop_rolled(const DslashArgs &P, long i, int r, int x, int y, int z, int t,
+                                           Spin<double> &acc)
+{
+    constexpr HopCoef kc[4] = {{0, 1, 0, 1, 0, -1, 0, -1},
+                               {1, 0, -1, 0, -1, 0, 1, 0},
+                               {0, 1, 0, -1, 0, -1, 0, 1},
+                               {-1, 0, -1, 0, -1, 0, -1, 0}};
+    const int R = P.R, ns = P.ns, nt = P.nt, par = P.par;
+    const long Vh = P.Vh;
+    const double2 *in = (const double2 *)P.in;
+    const double2 *g = (const double2 *)P.gauge;
+#pragma unroll 1
+    for (int d = 0; d < 8; d++) {
+        const int mu = d >> 1;
+        const bool fwd = !(d & 1);
+        const int st = fwd ? 1 : -1;
+        int xx = x, yy = y, zz = z, tt = t;
+        double w = mu == 3 ? P.wt : P.ws;
+        if (mu == 0) xx = (x + st + ns) % ns;
+        if (mu == 1) yy = (y + st + ns) % ns;
+        if (mu == 2) zz = (z + st + ns) % ns;
+        if (mu == 3) {
+            tt = (t + st + nt) % nt;
+            if (fwd ? t + 1 == nt : t == 0) w *= P.bct;
+        }
+        const long nb = lex_index(xx, yy, zz, tt, ns) >> 1;
+        Spin<double> s;
+        load_spinor<S64, O32>(in, nullptr, Vh, R, nb, r, s);
+        // U_mu(x), or for the backward hop U_mu(x - mu)^dag: planes read transposed, conjugated
+        const double2 *gp = g + (long)(mu * 2 + (fwd ? par : par ^ 1)) * 9 * Vh;
+        const long li = fwd ? i : nb;
+        const double cj = fwd ? 1.0 : -1.0;
+        Cx<double> U[9];
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            const double2 v = elem<O32>(gp + (long)(fwd ? k : (k % 3) * 3 + k / 3) * Vh, li);
+            U[k] = {v.x, cj * v.y};
+        }
+        const HopCoef &q = kc[mu];
+        const double sa = fwd ? w : -w, sb = fwd ? 1.0 : -1.0;
+        const bool sw = mu < 2;
+        Cx<double> h0[3], h1[3], o0[3], o1[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            h0[c] = w * s.v[0][c] + unit_mul(sa * q.a0r, sa * q.a0i, sw ? s.v[3][c] : s.v[2][c]);
+            h1[c] = w * s.v[1][c] + unit_mul(sa * q.a1r, sa * q.a1i, sw ? s.v[2][c] : s.v[3][c]);
+        }
+        mat_vec(U, h0, o0);
+        mat_vec(U, h1, o1);
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            acc.v[0][c] = acc.v[0][c] + o0[c];
+            acc.v[1][c] = acc.v[1][c] + o1[c];
+            acc.v[2][c] = acc.v[2][c] + unit_mul(sb * q.b2r, sb * q.b2i, sw ? o1[c] : o0[c]);
+            acc.v[3][c] = acc.v[3][c] + unit_mul(sb * q.b3r, sb * q.b3i, sw ? o0[c] : o1[c]);
+        }
+    }
+}
+
+template <class SP, class GP, class CP, int MODE, bool O32, bool ROLL>
 __global__ __launch_bounds__(256) void k_dslash(const DslashArgs P)
 {
     using A = typename SP::A;
@@ -125,115 +240,119 @@ __global__ __launch_bounds__(256) void k_dslash(const DslashArgs P)
 #pragma unroll
         for (int c = 0; c < 3; c++) acc.v[a][c] = {(A)0, (A)0};
 
+    if constexpr (ROLL) {
+        hop_rolled<O32>(P, i, r, x, y, z, t, acc);
+    } else {
 #pragma unroll
-    for (int mu = 0; mu < 4; mu++) {
-        // ---------------- forward hop: (1 - g_mu) U_mu(x) psi(x+mu)
-        {
-            int xx = x, yy = y, zz = z, tt = t;
-            A w = (A)(mu == 3 ? P.wt : P.ws);
-            if (mu == 0) xx = (x + 1 == ns) ? 0 : x + 1;
-            if (mu == 1) yy = (y + 1 == ns) ? 0 : y + 1;
-            if (mu == 2) zz = (z + 1 == ns) ? 0 : z + 1;
-            if (mu == 3) {
-                tt = (t + 1 == nt) ? 0 : t + 1;
-                if (t + 1 == nt) w *= (A)P.bct;
-            }
-            long nb = lex_index(xx, yy, zz, tt, ns) >> 1;
-            Spin<A> s;
-            load_spinor<SP>(in, P.in_nrm, Vh, R, nb, r, s);
-            Cx<A> U[9];
-            load_link<GP, A>(g, mu, par, Vh, i, U);
-            Cx<A> h0[3], h1[3], o0[3], o1[3];
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                if (mu == 0) {
-                    h0[c] = s.v[0][c] + timesI(s.v[3][c]);
-                    h1[c] = s.v[1][c] + timesI(s.v[2][c]);
-                } else if (mu == 1) {
-                    h0[c] = s.v[0][c] + s.v[3][c];
-                    h1[c] = s.v[1][c] - s.v[2][c];
-                } else if (mu == 2) {
-                    h0[c] = s.v[0][c] + timesI(s.v[2][c]);
-                    h1[c] = s.v[1][c] - timesI(s.v[3][c]);
-                } else {
-                    h0[c] = s.v[0][c] - s.v[2][c];
-                    h1[c] = s.v[1][c] - s.v[3][c];
+        for (int mu = 0; mu < 4; mu++) {
+            // ---------------- forward hop: (1 - g_mu) U_mu(x) psi(x+mu)
+            {
+                int xx = x, yy = y, zz = z, tt = t;
+                A w = (A)(mu == 3 ? P.wt : P.ws);
+                if (mu == 0) xx = (x + 1 == ns) ? 0 : x + 1;
+                if (mu == 1) yy = (y + 1 == ns) ? 0 : y + 1;
+                if (mu == 2) zz = (z + 1 == ns) ? 0 : z + 1;
+                if (mu == 3) {
+                    tt = (t + 1 == nt) ? 0 : t + 1;
+                    if (t + 1 == nt) w *= (A)P.bct;
                 }
-                h0[c] = w * h0[c];
-                h1[c] = w * h1[c];
-            }
-            mat_vec(U, h0, o0);
-            mat_vec(U, h1, o1);
-            acc_upper(acc, o0, o1);
+                long nb = lex_index(xx, yy, zz, tt, ns) >> 1;
+                Spin<A> s;
+                load_spinor<SP, O32>(in, P.in_nrm, Vh, R, nb, r, s);
+                Cx<A> U[9];
+                load_link<GP, A, O32>(g, mu, par, Vh, i, U);
+                Cx<A> h0[3], h1[3], o0[3], o1[3];
 #pragma unroll
-            for (int c = 0; c < 3; c++) {
-                if (mu == 0) {
-                    acc.v[2][c] = acc.v[2][c] + timesMinusI(o1[c]);
-                    acc.v[3][c] = acc.v[3][c] + timesMinusI(o0[c]);
-                } else if (mu == 1) {
-                    acc.v[2][c] = acc.v[2][c] - o1[c];
-                    acc.v[3][c] = acc.v[3][c] + o0[c];
-                } else if (mu == 2) {
-                    acc.v[2][c] = acc.v[2][c] + timesMinusI(o0[c]);
-                    acc.v[3][c] = acc.v[3][c] + timesI(o1[c]);
-                } else {
-                    acc.v[2][c] = acc.v[2][c] - o0[c];
-                    acc.v[3][c] = acc.v[3][c] - o1[c];
+                for (int c = 0; c < 3; c++) {
+                    if (mu == 0) {
+                        h0[c] = s.v[0][c] + timesI(s.v[3][c]);
+                        h1[c] = s.v[1][c] + timesI(s.v[2][c]);
+                    } else if (mu == 1) {
+                        h0[c] = s.v[0][c] + s.v[3][c];
+                        h1[c] = s.v[1][c] - s.v[2][c];
+                    } else if (mu == 2) {
+                        h0[c] = s.v[0][c] + timesI(s.v[2][c]);
+                        h1[c] = s.v[1][c] - timesI(s.v[3][c]);
+                    } else {
+                        h0[c] = s.v[0][c] - s.v[2][c];
+                        h1[c] = s.v[1][c] - s.v[3][c];
+                    }
+                    h0[c] = w * h0[c];
+                    h1[c] = w * h1[c];
+                }
+                mat_vec(U, h0, o0);
+                mat_vec(U, h1, o1);
+                acc_upper(acc, o0, o1);
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    if (mu == 0) {
+                        acc.v[2][c] = acc.v[2][c] + timesMinusI(o1[c]);
+                        acc.v[3][c] = acc.v[3][c] + timesMinusI(o0[c]);
+                    } else if (mu == 1) {
+                        acc.v[2][c] = acc.v[2][c] - o1[c];
+                        acc.v[3][c] = acc.v[3][c] + o0[c];
+                    } else if (mu == 2) {
+                        acc.v[2][c] = acc.v[2][c] + timesMinusI(o0[c]);
+                        acc.v[3][c] = acc.v[3][c] + timesI(o1[c]);
+                    } else {
+                        acc.v[2][c] = acc.v[2][c] - o0[c];
+                        acc.v[3][c] = acc.v[3][c] - o1[c];
+                    }
                 }
             }
-        }
-        // ---------------- backward hop: (1 + g_mu) U_mu(x-mu)^dag psi(x-mu)
-        {
-            int xx = x, yy = y, zz = z, tt = t;
-            A w = (A)(mu == 3 ? P.wt : P.ws);
-            if (mu == 0) xx = (x == 0) ? ns - 1 : x - 1;
-            if (mu == 1) yy = (y == 0) ? ns - 1 : y - 1;
-            if (mu == 2) zz = (z == 0) ? ns - 1 : z - 1;
-            if (mu == 3) {
-                tt = (t == 0) ? nt - 1 : t - 1;
-                if (t == 0) w *= (A)P.bct;
-            }
-            long nb = lex_index(xx, yy, zz, tt, ns) >> 1;
-            Spin<A> s;
-            load_spinor<SP>(in, P.in_nrm, Vh, R, nb, r, s);
-            Cx<A> U[9];
-            load_link<GP, A>(g, mu, opar, Vh, nb, U);
-            Cx<A> h0[3], h1[3], o0[3], o1[3];
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                if (mu == 0) {
-                    h0[c] = s.v[0][c] - timesI(s.v[3][c]);
-                    h1[c] = s.v[1][c] - timesI(s.v[2][c]);
-                } else if (mu == 1) {
-                    h0[c] = s.v[0][c] - s.v[3][c];
-                    h1[c] = s.v[1][c] + s.v[2][c];
-                } else if (mu == 2) {
-                    h0[c] = s.v[0][c] - timesI(s.v[2][c]);
-                    h1[c] = s.v[1][c] + timesI(s.v[3][c]);
-                } else {
-                    h0[c] = s.v[0][c] + s.v[2][c];
-                    h1[c] = s.v[1][c] + s.v[3][c];
+            // ---------------- backward hop: (1 + g_mu) U_mu(x-mu)^dag psi(x-mu)
+            {
+                int xx = x, yy = y, zz = z, tt = t;
+                A w = (A)(mu == 3 ? P.wt : P.ws);
+                if (mu == 0) xx = (x == 0) ? ns - 1 : x - 1;
+                if (mu == 1) yy = (y == 0) ? ns - 1 : y - 1;
+                if (mu == 2) zz = (z == 0) ? ns - 1 : z - 1;
+                if (mu == 3) {
+                    tt = (t == 0) ? nt - 1 : t - 1;
+                    if (t == 0) w *= (A)P.bct;
                 }
-                h0[c] = w * h0[c];
-                h1[c] = w * h1[c];
-            }
-            mat_dag_vec(U, h0, o0);
-            mat_dag_vec(U, h1, o1);
-            acc_upper(acc, o0, o1);
+                long nb = lex_index(xx, yy, zz, tt, ns) >> 1;
+                Spin<A> s;
+                load_spinor<SP, O32>(in, P.in_nrm, Vh, R, nb, r, s);
+                Cx<A> U[9];
+                load_link<GP, A, O32>(g, mu, opar, Vh, nb, U);
+                Cx<A> h0[3], h1[3], o0[3], o1[3];
 #pragma unroll
-            for (int c = 0; c < 3; c++) {
-                if (mu == 0) {
-                    acc.v[2][c] = acc.v[2][c] + timesI(o1[c]);
-                    acc.v[3][c] = acc.v[3][c] + timesI(o0[c]);
-                } else if (mu == 1) {
-                    acc.v[2][c] = acc.v[2][c] + o1[c];
-                    acc.v[3][c] = acc.v[3][c] - o0[c];
-                } else if (mu == 2) {
-                    acc.v[2][c] = acc.v[2][c] + timesI(o0[c]);
-                    acc.v[3][c] = acc.v[3][c] + timesMinusI(o1[c]);
-                } else {
-                    acc.v[2][c] = acc.v[2][c] + o0[c];
-                    acc.v[3][c] = acc.v[3][c] + o1[c];
+                for (int c = 0; c < 3; c++) {
+                    if (mu == 0) {
+                        h0[c] = s.v[0][c] - timesI(s.v[3][c]);
+                        h1[c] = s.v[1][c] - timesI(s.v[2][c]);
+                    } else if (mu == 1) {
+                        h0[c] = s.v[0][c] - s.v[3][c];
+                        h1[c] = s.v[1][c] + s.v[2][c];
+                    } else if (mu == 2) {
+                        h0[c] = s.v[0][c] - timesI(s.v[2][c]);
+                        h1[c] = s.v[1][c] + timesI(s.v[3][c]);
+                    } else {
+                        h0[c] = s.v[0][c] + s.v[2][c];
+                        h1[c] = s.v[1][c] + s.v[3][c];
+                    }
+                    h0[c] = w * h0[c];
+                    h1[c] = w * h1[c];
+                }
+                mat_dag_vec(U, h0, o0);
+                mat_dag_vec(U, h1, o1);
+                acc_upper(acc, o0, o1);
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    if (mu == 0) {
+                        acc.v[2][c] = acc.v[2][c] + timesI(o1[c]);
+                        acc.v[3][c] = acc.v[3][c] + timesI(o0[c]);
+                    } else if (mu == 1) {
+                        acc.v[2][c] = acc.v[2][c] + o1[c];
+                        acc.v[3][c] = acc.v[3][c] - o0[c];
+                    } else if (mu == 2) {
+                        acc.v[2][c] = acc.v[2][c] + timesI(o0[c]);
+                        acc.v[3][c] = acc.v[3][c] + timesMinusI(o1[c]);
+                    } else {
+                        acc.v[2][c] = acc.v[2][c] + o0[c];
+                        acc.v[3][c] = acc.v[3][c] + o1[c];
+                    }
                 }
             }
         }
@@ -257,7 +376,7 @@ __global__ __launch_bounds__(256) void k_dslash(const DslashArgs P)
             for (int c = 0; c < 3; c++) res.v[a][c] = cc * acc.v[a][c];
         if (P.x) {
             Spin<A> xv;
-            load_spinor<SP>((const typename SP::E *)P.x, P.x_nrm, Vh, R, i, r, xv);
+            load_spinor<SP, O32>((const typename SP::E *)P.x, P.x_nrm, Vh, R, i, r, xv);
 #pragma unroll
             for (int a = 0; a < 4; a++)
 #pragma unroll
@@ -265,14 +384,14 @@ __global__ __launch_bounds__(256) void k_dslash(const DslashArgs P)
         }
     } else if constexpr (MODE == M_INV_AFTER) {
         Spin<A> m;
-        clover_mul<CP, A>(cl, Vh, i, acc, m);
+        clover_mul<CP, A, O32>(cl, Vh, i, acc, m);
 #pragma unroll
         for (int a = 0; a < 4; a++)
 #pragma unroll
             for (int c = 0; c < 3; c++) res.v[a][c] = cc * m.v[a][c];
         if (P.x) {
             Spin<A> xv;
-            load_spinor<SP>((const typename SP::E *)P.x, P.x_nrm, Vh, R, i, r, xv);
+            load_spinor<SP, O32>((const typename SP::E *)P.x, P.x_nrm, Vh, R, i, r, xv);
 #pragma unroll
             for (int a = 0; a < 4; a++)
 #pragma unroll
@@ -280,22 +399,22 @@ __global__ __launch_bounds__(256) void k_dslash(const DslashArgs P)
         }
     } else if constexpr (MODE == M_INV_OF_SUM) {
         Spin<A> xv, sum;
-        load_spinor<SP>((const typename SP::E *)P.x, P.x_nrm, Vh, R, i, r, xv);
+        load_spinor<SP, O32>((const typename SP::E *)P.x, P.x_nrm, Vh, R, i, r, xv);
 #pragma unroll
         for (int a = 0; a < 4; a++)
 #pragma unroll
             for (int c = 0; c < 3; c++) sum.v[a][c] = ca * xv.v[a][c] + cc * acc.v[a][c];
-        clover_mul<CP, A>(cl, Vh, i, sum, res);
+        clover_mul<CP, A, O32>(cl, Vh, i, sum, res);
     } else {  // M_CLOV_ADD
         Spin<A> xv, m;
-        load_spinor<SP>((const typename SP::E *)P.x, P.x_nrm, Vh, R, i, r, xv);
-        clover_mul<CP, A>(cl, Vh, i, xv, m);
+        load_spinor<SP, O32>((const typename SP::E *)P.x, P.x_nrm, Vh, R, i, r, xv);
+        clover_mul<CP, A, O32>(cl, Vh, i, xv, m);
 #pragma unroll
         for (int a = 0; a < 4; a++)
 #pragma unroll
             for (int c = 0; c < 3; c++) res.v[a][c] = m.v[a][c] + cc * acc.v[a][c];
     }
-    store_spinor<SP>((typename SP::E *)P.out, P.out_nrm, Vh, R, i, r, res);
+    store_spinor<SP, O32>((typename SP::E *)P.out, P.out_nrm, Vh, R, i, r, res);
 }
 
 template <class SP, class CP>
@@ -310,7 +429,7 @@ __global__ __launch_bounds__(256) void k_clover_apply(const typename CP::E *__re
     long i = tid / R;
     int r = (int)(tid - i * R);
     Spin<A> v, o;
-    load_spinor<SP>(x, x_nrm, Vh, R, i, r, v);
+    load_spinor<SP, false>(x, x_nrm, Vh, R, i, r, v);
     if (g5_in) {
 #pragma unroll
         for (int c = 0; c < 3; c++) {
@@ -319,7 +438,7 @@ __global__ __launch_bounds__(256) void k_clover_apply(const typename CP::E *__re
         }
     }
     clover_mul<CP, A>(cl, Vh, i, v, o);
-    store_spinor<SP>(out, out_nrm, Vh, R, i, r, o);
+    store_spinor<SP, false>(out, out_nrm, Vh, R, i, r, o);
 }
 
 }  // namespace
@@ -334,6 +453,29 @@ double dslash_bytes(long Vh, int R, int gbytes, int cbytes, int sbytes, bool has
     return (double)Vh * (site + R * per_rhs);
 }
 
+template <class SP, class GP, class CP, bool O32, bool ROLL>
+void launch_modes(int mode, dim3 grid, dim3 block, hipStream_t st, const DslashArgs &a)
+{
+    switch (mode) {
+    case M_PLAIN: hipLaunchKernelGGL((k_dslash<SP, GP, CP, M_PLAIN, O32, ROLL>), grid, block, 0, st, a); break;
+    case M_INV_AFTER: hipLaunchKernelGGL((k_dslash<SP, GP, CP, M_INV_AFTER, O32, ROLL>), grid, block, 0, st, a); break;
+    case M_INV_OF_SUM:
+        hipLaunchKernelGGL((k_dslash<SP, GP, CP, M_INV_OF_SUM, O32, ROLL>), grid, block, 0, st, a);
+        break;
+    default: hipLaunchKernelGGL((k_dslash<SP, GP, CP, M_CLOV_ADD, O32, ROLL>), grid, block, 0, st, a); break;
+    }
+}
+
+static bool f64_rolled()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("LAPH_F64_ROLLED");
+        v = (e && *e == '0') ? 0 : 1;
+    }
+    return v == 1;
+}
+
 template <class SP, class GP, class CP>
 void launch_dslash(laph_ctx *c, int mode, const DslashArgs &a, hipStream_t st)
 {
@@ -341,12 +483,16 @@ void launch_dslash(laph_ctx *c, int mode, const DslashArgs &a, hipStream_t st)
     dim3 grid(nblocks_for(n, 256)), block(256);
     hipEvent_t e0, e1;
     timing_begin(c, &e0, &e1);
-    switch (mode) {
-    case M_PLAIN: hipLaunchKernelGGL((k_dslash<SP, GP, CP, M_PLAIN>), grid, block, 0, st, a); break;
-    case M_INV_AFTER: hipLaunchKernelGGL((k_dslash<SP, GP, CP, M_INV_AFTER>), grid, block, 0, st, a); break;
-    case M_INV_OF_SUM: hipLaunchKernelGGL((k_dslash<SP, GP, CP, M_INV_OF_SUM>), grid, block, 0, st, a); break;
-    default: hipLaunchKernelGGL((k_dslash<SP, GP, CP, M_CLOV_ADD>), grid, block, 0, st, a); break;
-    }
+    // 32-bit lane offsets when every spinor plane (Vh R entries) stays below 4 GiB (the
+    // link and clover planes are smaller); FP64 hops rolled over the directions unless
+    // LAPH_F64_ROLLED=0
+    const bool o32 = std::is_same<SP, S64>::value && (unsigned long long)n * sizeof(double2) < (1ull << 32);
+    if (o32 && f64_rolled())
+        launch_modes<SP, GP, CP, true, true>(mode, grid, block, st, a);
+    else if (o32)
+        launch_modes<SP, GP, CP, true, false>(mode, grid, block, st, a);
+    else
+        launch_modes<SP, GP, CP, false, false>(mode, grid, block, st, a);
     LAPH_HIP(hipGetLastError());
     bool has_x = a.x != nullptr && (mode != M_PLAIN || a.x);
     if (e0)

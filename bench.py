@@ -103,7 +103,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--workload", default="ns24_nt128")
     ap.add_argument("--precision", default="f16")
     ap.add_argument("--block", type=int, default=32)
     ap.add_argument("--solver", default="cgnr", choices=["cgnr", "bicgstab"],
@@ -340,7 +340,7 @@ def main():
         "dtype": {"f16": "f16", "f32": "f32", "bf16": "bf16", "f64": "f64"}[args.precision] + "+f64",
         "data": "synthetic",
         "config": {"workload": "24^3x128 anisotropic Wilson-clover, xi=3.5, N_v=112, (TF,SF,LI8), "
-                               "32 sources per step" if cfg.name == "cfg2" else cfg.name,
+                               "32 sources per step" if cfg.name == "ns24_nt128" else cfg.name,
                    "lattice": [cfg.ns, cfg.ns, cfg.ns, cfg.nt], "nv": cfg.nv, "m0": cfg.m0,
                    "dilution": cfg.dilution, "sources_per_step": nsrc,
                    "form": "even-odd %s, %s inner vectors, %d right-hand sides per batch, FP64 reliable "

@@ -69,7 +69,7 @@ def eval_loss(P, L, net, data, mask_dev, bc_t):
     return tot / n
 
 
-def train(workload="cfg2", ns=8, nt=16, train_seeds=range(100, 200), test_seeds=range(200, 210), pairs=20,
+def train(workload="ns24_nt128", ns=8, nt=16, train_seeds=range(100, 200), test_seeds=range(200, 210), pairs=20,
           epochs=60, lr=2e-3, channels=DEFAULT_CHANNELS, seed=0, log=print):
     import torch
 
@@ -126,7 +126,7 @@ def load(path):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=os.path.join(ROOT, "paper_1104_3870_amd", "weights", "ptnet.npz"))
-    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--workload", default="ns24_nt128")
     ap.add_argument("--ns", type=int, default=8)
     ap.add_argument("--nt", type=int, default=16)
     ap.add_argument("--pairs", type=int, default=20)

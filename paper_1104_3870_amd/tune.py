@@ -11,7 +11,7 @@ tuning aid uses torch.  The search stays on the physical side of the critical ma
 count rises as m0 falls towards it, and m0 is not taken below the point where the count
 stops rising (further down lie the doubler branches of the Wilson operator).
 
-    python -m paper_1104_3870_amd.tune m0 cfg2 1000
+    python -m paper_1104_3870_amd.tune m0 ns24_nt128 1000
 """
 from __future__ import annotations
 

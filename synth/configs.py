@@ -7,11 +7,11 @@ smaller lattices.  m0 values are tuned so that FP64 CG on the even-odd normal
 equations of the full system (Omega^dag Omega, the paper's fallback solver) needs
 roughly the stated iteration count on a seeded Gaussian source, staying on the physical
 side of the critical mass (python -m paper_1104_3870_amd.tune m0 <config> <iterations>):
-  cfg0: m0 = 0.1   -> 101 iterations (target ~100)
-  cfg2: m0 = -0.12 -> 900 iterations (target ~1000; the physical branch of this field
+  ns4_nt8: m0 = 0.1   -> 101 iterations (target ~100)
+  ns24_nt128: m0 = -0.12 -> 900 iterations (target ~1000; the physical branch of this field
                       peaks near m0 = -0.14 at about 950, so ~1000 is its most
                       ill-conditioned physical point)
-cfg1 uses the cfg2 mass (same field generator and eps).
+ns16_nt32 uses the ns24_nt128 mass (same field generator and eps).
 """
 from __future__ import annotations
 
@@ -46,14 +46,14 @@ class Config:
 
 CONFIGS = {
     # 4^3 x 8, full T x S x L dilution: 256 sources, exact-perambulator pin
-    "cfg0": Config("cfg0", ns=4, nt=8, eps=0.3, seed=1, stout_rho=0.1, stout_steps=2,
+    "ns4_nt8": Config("ns4_nt8", ns=4, nt=8, eps=0.3, seed=1, stout_rho=0.1, stout_steps=2,
                    nv=8, dilution="TF,SF,LF", m0=0.1, krylov=48, lam_c=2.5,
                    eig_tol=1e-12),
     # 16^3 x 32, (TI16, SF, LI8): 512 sources; Dslash profiling workload
-    "cfg1": Config("cfg1", ns=16, nt=32, eps=0.4, seed=1, stout_rho=0.1, stout_steps=6,
+    "ns16_nt32": Config("ns16_nt32", ns=16, nt=32, eps=0.4, seed=1, stout_rho=0.1, stout_steps=6,
                    nv=48, dilution="TI16,SF,LI8", m0=-0.12, krylov=96, lam_c=0.5,
                    eig_tol=1e-10),
     # 24^3 x 128, (TF, SF, LI8): production lattice of the paper
-    "cfg2": Config("cfg2", ns=24, nt=128, eps=0.4, seed=1, stout_rho=0.1, stout_steps=10,
+    "ns24_nt128": Config("ns24_nt128", ns=24, nt=128, eps=0.4, seed=1, stout_rho=0.1, stout_steps=10,
                    nv=112, dilution="TF,SF,LI8", m0=-0.12),
 }

@@ -4,7 +4,7 @@ true relative residual 1e-10 on the seeded Gaussian source of the workload (seed
 The CPU baseline of the benchmark times a few of these iterations and scales by this
 count.  Calls only the oracle.
 
-    OMP_NUM_THREADS=6 python tests/golden/oracle_cg_iters.py cfg2
+    OMP_NUM_THREADS=6 python tests/golden/oracle_cg_iters.py ns24_nt128
 """
 import json
 import os
@@ -34,4 +34,4 @@ def main(name):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "cfg2")
+    main(sys.argv[1] if len(sys.argv) > 1 else "ns24_nt128")

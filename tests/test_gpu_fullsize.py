@@ -22,7 +22,7 @@ from gpu_util import dev, host, rel_err, say
 
 pytestmark = pytest.mark.gpu
 
-CFG = synth.CONFIGS["cfg2"]
+CFG = synth.CONFIGS["ns24_nt128"]
 NS, NT, NV = CFG.ns, CFG.nt, CFG.nv
 SLICES = (0, 64)  # slices carrying a synthetic LapH basis
 

@@ -127,8 +127,8 @@ def test_dirac_apply_many_fields(P, ns, nt, n):
 
 
 @pytest.fixture(scope="module")
-def cfg0_evecs():
-    cfg = synth.CONFIGS["cfg0"]
+def ns4_nt8_evecs():
+    cfg = synth.CONFIGS["ns4_nt8"]
     U = synth.gauge_field(cfg.ns, cfg.nt, cfg.eps, cfg.seed)
     S = oracle.stout_spatial(U, cfg.stout_rho, cfg.stout_steps)
     ev, V = oracle.laph_eigpairs(S, cfg.nv)
@@ -137,10 +137,10 @@ def cfg0_evecs():
 
 @pytest.mark.parametrize("spec,b0,nsrc", [("TF,SF,LF", 0, 1), ("TF,SF,LF", 200, 7), ("TI4,SB2,LI4", 3, 20),
                                           ("T1,S1,LB2", 0, 2)])
-def test_source_parity(P, cfg0_evecs, spec, b0, nsrc):
+def test_source_parity(P, ns4_nt8_evecs, spec, b0, nsrc):
     import torch
 
-    cfg, U, V = cfg0_evecs
+    cfg, U, V = ns4_nt8_evecs
     say("source", spec, b0, nsrc)
     L = _ctx(P, cfg.ns, cfg.nt)
     dil = P.laph_parse_dilution(spec, cfg.nt, cfg.nv)
@@ -153,10 +153,10 @@ def test_source_parity(P, cfg0_evecs, spec, b0, nsrc):
         assert np.abs(host(eta)[j] - ref).max() < 1e-15
 
 
-def test_source_rejects_bad_index(P, cfg0_evecs):
+def test_source_rejects_bad_index(P, ns4_nt8_evecs):
     import torch
 
-    cfg, U, V = cfg0_evecs
+    cfg, U, V = ns4_nt8_evecs
     L = _ctx(P, cfg.ns, cfg.nt)
     dil = P.laph_parse_dilution("TF,SF,LF", cfg.nt, cfg.nv)
     eta = torch.empty((1, cfg.nt, cfg.ns, cfg.ns, cfg.ns, 4, 3), dtype=torch.complex128, device="cuda")
@@ -165,10 +165,10 @@ def test_source_rejects_bad_index(P, cfg0_evecs):
 
 
 @pytest.mark.parametrize("nrhs", [1, 3])
-def test_sink_parity(P, cfg0_evecs, nrhs):
+def test_sink_parity(P, ns4_nt8_evecs, nrhs):
     import torch
 
-    cfg, U, V = cfg0_evecs
+    cfg, U, V = ns4_nt8_evecs
     L = _ctx(P, cfg.ns, cfg.nt)
     X = synth.random_spinor(cfg.ns, cfg.nt, 9, nrhs=nrhs)
     coef = torch.empty((nrhs, cfg.nt, 4, cfg.nv), dtype=torch.complex128, device="cuda")

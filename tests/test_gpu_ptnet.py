@@ -206,7 +206,7 @@ def _fgmres(P, cfg, U, etas, net, **kw):
 
 @pytest.mark.parametrize("restart", [0, 5])
 def test_fgmres_solve(P, restart):
-    cfg = synth.CONFIGS["cfg0"]
+    cfg = synth.CONFIGS["ns4_nt8"]
     say("fgmres solve restart", restart)
     U = synth.gauge_field(cfg.ns, cfg.nt, cfg.eps, cfg.seed)
     D = oracle.Dirac(U, cfg.m0, cfg.xi, cfg.csw, cfg.bc_t)
@@ -224,7 +224,7 @@ def test_fgmres_solve(P, restart):
 
 
 def test_fgmres_zero_net_falls_back(P):
-    cfg = synth.CONFIGS["cfg0"]
+    cfg = synth.CONFIGS["ns4_nt8"]
     say("fgmres zero net")
     U = synth.gauge_field(cfg.ns, cfg.nt, cfg.eps, cfg.seed)
     D = oracle.Dirac(U, cfg.m0, cfg.xi, cfg.csw, cfg.bc_t)
@@ -246,7 +246,7 @@ def test_network_initial_guess(P, prec):
     N(gamma_4 eta)); the answer is judged as always."""
     import torch
 
-    cfg = synth.CONFIGS["cfg0"]
+    cfg = synth.CONFIGS["ns4_nt8"]
     say("network initial guess", prec)
     U = synth.gauge_field(cfg.ns, cfg.nt, cfg.eps, cfg.seed)
     D = oracle.Dirac(U, cfg.m0, cfg.xi, cfg.csw, cfg.bc_t)

@@ -24,8 +24,8 @@ def P():
 
 
 @pytest.fixture(scope="module")
-def cfg0():
-    cfg = synth.CONFIGS["cfg0"]
+def ns4_nt8():
+    cfg = synth.CONFIGS["ns4_nt8"]
     U = synth.gauge_field(cfg.ns, cfg.nt, cfg.eps, cfg.seed)
     S = oracle.stout_spatial(U, cfg.stout_rho, cfg.stout_steps)
     ev, V = oracle.laph_eigpairs(S, cfg.nv)
@@ -52,9 +52,9 @@ def _quark_lines(P, cfg, U, V, spec, b0, nsrc, precision="f64", block=32):
 
 
 @pytest.mark.parametrize("precision,block", [("f64", 32), ("f32", 16), ("f16", 32), ("bf16", 8)])
-def test_full_dilution_perambulator(P, cfg0, precision, block):
-    cfg, U, V, D, tau = cfg0
-    say("quark lines cfg0", precision, block)
+def test_full_dilution_perambulator(P, ns4_nt8, precision, block):
+    cfg, U, V, D, tau = ns4_nt8
+    say("quark lines ns4_nt8", precision, block)
     eta, x, coef, st = _quark_lines(P, cfg, U, V, cfg.dilution, 0, 256, precision, block)
     rho = oracle.z4_noise(cfg.noise_s, cfg.noise_k, cfg.nt, cfg.nv).ravel()
     worst = 0.0
@@ -72,8 +72,8 @@ def test_full_dilution_perambulator(P, cfg0, precision, block):
         assert D.true_residual(eta[b], x[b]) <= 1e-10
 
 
-def test_coefficients_gauge_invariant(P, cfg0):
-    cfg, U, V, D, tau = cfg0
+def test_coefficients_gauge_invariant(P, ns4_nt8):
+    cfg, U, V, D, tau = ns4_nt8
     G = synth.gauge_transform_field(cfg.ns, cfg.nt, 11)
     UG = np.empty_like(U)
     for mu in range(4):

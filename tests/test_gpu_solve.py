@@ -24,7 +24,7 @@ def P():
 
 @pytest.fixture(scope="module")
 def setup():
-    cfg = synth.CONFIGS["cfg0"]
+    cfg = synth.CONFIGS["ns4_nt8"]
     U = synth.gauge_field(cfg.ns, cfg.nt, cfg.eps, cfg.seed)
     D = oracle.Dirac(U, cfg.m0, cfg.xi, cfg.csw, cfg.bc_t)
     etas = synth.random_spinor(cfg.ns, cfg.nt, 21, nrhs=5)

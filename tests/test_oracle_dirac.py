@@ -170,8 +170,8 @@ def test_solve_matches_dense_lu_4x4():
 # --------------------------------------------------------------- quark lines
 
 @pytest.fixture(scope="module")
-def cfg0_setup():
-    cfg = synth.CONFIGS["cfg0"]
+def ns4_nt8_setup():
+    cfg = synth.CONFIGS["ns4_nt8"]
     U = synth.gauge_field(cfg.ns, cfg.nt, cfg.eps, cfg.seed)
     S = oracle.stout_spatial(U, cfg.stout_rho, cfg.stout_steps)
     ev, V = oracle.laph_eigpairs(S, cfg.nv)
@@ -180,8 +180,8 @@ def cfg0_setup():
     return cfg, U, V, D, tau
 
 
-def test_source_recovers_diluted_noise(cfg0_setup):
-    cfg, U, V, D, tau = cfg0_setup
+def test_source_recovers_diluted_noise(ns4_nt8_setup):
+    cfg, U, V, D, tau = ns4_nt8_setup
     rho = oracle.z4_noise(cfg.noise_s, cfg.noise_k, cfg.nt, cfg.nv)
     sch = oracle.parse_dilution("TI4,SB2,LI4", cfg.nt, cfg.nv)
     for b in (0, 5, 31):
@@ -195,11 +195,11 @@ def test_source_recovers_diluted_noise(cfg0_setup):
         assert np.abs(eta[~mask]).max() == 0
 
 
-def test_full_dilution_reproduces_perambulator(cfg0_setup):
+def test_full_dilution_reproduces_perambulator(ns4_nt8_setup):
     """Sec. II: with full T x S x L dilution, sum_b c^[b] (P_b rho)^dag equals
     V^dag Omega^-1 V exactly for a single noise.  Checked source by source on a
     sample of b: c^[b] = tau[:, b] rho_b (CGNR solve vs dense LU)."""
-    cfg, U, V, D, tau = cfg0_setup
+    cfg, U, V, D, tau = ns4_nt8_setup
     rho = oracle.z4_noise(cfg.noise_s, cfg.noise_k, cfg.nt, cfg.nv)
     sch = oracle.parse_dilution(cfg.dilution, cfg.nt, cfg.nv)
     assert oracle.dilution_count(sch, cfg.nt, cfg.nv) == 256
@@ -212,10 +212,10 @@ def test_full_dilution_reproduces_perambulator(cfg0_setup):
         assert np.linalg.norm(c - ref) / np.linalg.norm(ref) < 1e-9
 
 
-def test_coefficients_gauge_invariant(cfg0_setup):
+def test_coefficients_gauge_invariant(ns4_nt8_setup):
     """Sec. IV: coefficients are gauge invariant when the eigenvector phases are carried
     along (V -> G V)."""
-    cfg, U, V, D, tau = cfg0_setup
+    cfg, U, V, D, tau = ns4_nt8_setup
     G = synth.gauge_transform_field(cfg.ns, cfg.nt, 11)
     UG = _transform_links(U, G)
     VG = np.einsum("tzyxab,tnzyxb->tnzyxa", G, V)
@@ -227,10 +227,10 @@ def test_coefficients_gauge_invariant(cfg0_setup):
     assert np.linalg.norm(c1 - c0) / np.linalg.norm(c0) < 1e-10
 
 
-def test_undiluted_estimator_statistics(cfg0_setup):
+def test_undiluted_estimator_statistics(ns4_nt8_setup):
     """Sec. II: Omega^-1 ~ N_R^-1 sum_r X^r eta^r dag; without dilution the error of the
     estimate of tau falls like 1/sqrt(N).  Uses c = tau rho (exact for each noise)."""
-    cfg, U, V, D, tau = cfg0_setup
+    cfg, U, V, D, tau = ns4_nt8_setup
     errs = []
     for N in (16, 256):
         est = np.zeros_like(tau)

@@ -192,7 +192,7 @@ def test_eigpairs_free_field_and_phase():
 
 
 def test_eigpairs_orthonormal_residual_phase():
-    cfg = synth.CONFIGS["cfg0"]
+    cfg = synth.CONFIGS["ns4_nt8"]
     U = synth.gauge_field(cfg.ns, cfg.nt, cfg.eps, cfg.seed)
     S = oracle.stout_spatial(U, cfg.stout_rho, cfg.stout_steps)
     ev, V = oracle.laph_eigpairs(S, cfg.nv, slices=[0, 5])

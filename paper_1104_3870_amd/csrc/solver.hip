@@ -404,8 +404,10 @@ __global__ __launch_bounds__(kBS) void k_fold_x_step(Vec xhi, Vec xlo, Dirs dirs
     st_site<XP>(xlo, Vh, R, i, rr, z);
 }
 
-// r = b - m (FP64), partial |r|^2; restricted to masked right-hand sides unless all_rhs
-__global__ __launch_bounds__(kBS) void k_resid64(Vec b, Vec m, Vec r, long Vh, int R, double *partial,
+// r = b - m (FP64), partial |r|^2; restricted to masked right-hand sides unless all_rhs;
+// with rlo.d set also r converted to the storage precision SP
+template <class SP>
+__global__ __launch_bounds__(kBS) void k_resid64(Vec b, Vec m, Vec r, Vec rlo, long Vh, int R, double *partial,
                                                  const Scal *sc, int all_rhs)
 {
     double acc[1] = {0};
@@ -424,6 +426,7 @@ __global__ __launch_bounds__(kBS) void k_resid64(Vec b, Vec m, Vec r, long Vh, i
             acc[0] += a[k].re * a[k].re + a[k].im * a[k].im;
         }
         st_site<S64>(r, Vh, R, i, rr, a);
+        if (rlo.d) st_site<SP>(rlo, Vh, R, i, rr, a);
     }
     block_partial<1>(acc, R, partial);
 }
@@ -1162,11 +1165,13 @@ void write_scal(laph_ctx *c, Scal *d, const std::vector<Scal> &h)
 }
 
 // rhi = bhat - Mhat xhi for masked RHS (FP64), then r2hi / masks
-void true_eo_residual(Work &w, const Op64 &hi, Vec bhat, Vec xhi, Vec tmp, Vec rhi, int all_rhs)
+// (rlo: also the residual in storage precision SP, for the right-hand sides it is formed for)
+template <class SP = S64>
+void true_eo_residual(Work &w, const Op64 &hi, Vec bhat, Vec xhi, Vec tmp, Vec rhi, int all_rhs, Vec rlo = Vec{})
 {
     hi.mhat(xhi, tmp);
     long n = w.Vh * w.R;
-    launch_red(w.c, k_resid64, n, bhat, tmp, rhi, w.Vh, w.R, w.part, (const Scal *)w.sc, all_rhs);
+    launch_red(w.c, k_resid64<SP>, n, bhat, tmp, rhi, rlo, w.Vh, w.R, w.part, (const Scal *)w.sc, all_rhs);
     launch_fin(w.c, k_fin_r2hi, w.R, (const double *)w.part, (int)red_blocks(n), w.R, w.sc, 0);
 }
 
@@ -1477,17 +1482,18 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
                     launch_red(c, k_track_res<XP>, n, reshi, t32, xhi, xlo, w.Vh, w.R, w.part, (const Scal *)w.sc);
                     launch_fin(c, k_fin_r2hi, w.R, (const double *)w.part, nblk, w.R, w.sc, 2);
                 }
+                launch_el(c, k_convert_masked<SP>, n, reshi, res, w.Vh, w.R, (const Scal *)w.sc);
             } else {
                 if (step_now)  // the fold takes the steps still owed to x
                     launch_el(c, k_fold_x_step<XP, SP>, n, xhi, xlo, owed_dirs(0, 1 + nowed), w.Vh, w.R,
                               (const Scal *)w.sc);
                 else
                     launch_el(c, k_fold_x<XP>, n, xhi, xlo, w.Vh, w.R, (const Scal *)w.sc, 0);
-                true_eo_residual(w, hi, bhat, xhi, tmp64, reshi, 0);
+                // the FP64 residual, and res = the same in storage precision
+                true_eo_residual<SP>(w, hi, bhat, xhi, tmp64, reshi, 0, res);
             }
             step_now = false;
             nowed = 0;
-            launch_el(c, k_convert_masked<SP>, n, reshi, res, w.Vh, w.R, (const Scal *)w.sc);
             lo.mhat_dag(res, r, to);
             launch_red(c, k_normsq2<SP>, n, r, res, w.Vh, w.R, w.part);
             launch_fin(c, k_fin_cg_reset, w.R, (const double *)w.part, nblk, w.R, w.sc);
@@ -1581,7 +1587,8 @@ void full_residual(Work &w, const Op64 &hi, Vec be, Vec bo, Vec xe, Vec xo, Vec 
     r2.assign(w.R, 0.0);
     b2.assign(w.R, 0.0);
     for (int par = 0; par < 2; par++) {
-        launch_red(c, k_resid64, n, par ? bo : be, par ? to : te, re, w.Vh, w.R, w.part, (const Scal *)w.sc, 1);
+        launch_red(c, k_resid64<S64>, n, par ? bo : be, par ? to : te, re, Vec{}, w.Vh, w.R, w.part, (const Scal *)w.sc,
+                   1);
         LAPH_HIP(hipMemcpyAsync(part.data(), w.part, sizeof(double) * part.size(), hipMemcpyDeviceToHost, c->stream));
         LAPH_HIP(hipStreamSynchronize(c->stream));
         for (int q = 0; q < w.R; q++)

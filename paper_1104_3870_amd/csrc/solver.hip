@@ -745,10 +745,12 @@ __global__ void k_fin_cg_beta(const double *partial, int nblk, int R, Scal *sc, 
 
 // direction update pout = r + beta d_0 (real beta); pout may be d_0, the oldest direction
 // d_{n-1}, or another buffer.  With nsteps > 0 the solution increment first takes the steps
-// still owed along the directions: x += sum_{j < nsteps} coef_j d_j
+// still owed along the directions: x += sum_{j < nsteps} coef_j d_j.  orth (after a reliable
+// update): d_0 is first made orthogonal to the new r, d_0 - aux r, so that
+// pout = (1 - beta aux) r + beta d_0
 template <class SP, class XP>
 __global__ __launch_bounds__(kBS) void k_cg_p(Vec pout, Dirs dirs, Vec r, Vec x, long Vh, int R, const Scal *sc,
-                                              int nsteps)
+                                              int nsteps, int orth)
 {
     long n = Vh * R;
     long tid = blockIdx.x * (long)kBS + threadIdx.x;
@@ -765,8 +767,14 @@ __global__ __launch_bounds__(kBS) void k_cg_p(Vec pout, Dirs dirs, Vec r, Vec x,
     }
     ld_site<SP>(dirs.d[0], Vh, R, i, rr, a);
     ld_site<SP>(r, Vh, R, i, rr, b);
+    if (orth) {
+        const Cx<double> g = {1.0 - be * sc[rr].aux.x, -be * sc[rr].aux.y};
 #pragma unroll
-    for (int k = 0; k < 12; k++) a[k] = b[k] + be * a[k];
+        for (int k = 0; k < 12; k++) a[k] = g * b[k] + be * a[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; k++) a[k] = b[k] + be * a[k];
+    }
     st_site<SP>(pout, Vh, R, i, rr, a);
 }
 
@@ -792,24 +800,6 @@ __global__ void k_fin_orth(const double *partial, int nblk, int R, Scal *sc)
     if (threadIdx.x) return;
     Scal &q = sc[r];
     q.aux = (q.active && q.rho.x > 0) ? make_double2(s[0] / q.rho.x, s[1] / q.rho.x) : make_double2(0, 0);
-}
-
-// p -= aux r  (restores <r, p> = 0 after the residual was replaced)
-template <class SP>
-__global__ __launch_bounds__(kBS) void k_orth_p(Vec p, Vec r, long Vh, int R, const Scal *sc)
-{
-    long n = Vh * R;
-    long tid = blockIdx.x * (long)kBS + threadIdx.x;
-    if (tid >= n) return;
-    long i = tid / R;
-    int rr = (int)(tid - i * R);
-    if (!sc[rr].active) return;
-    Cx<double> a = cx(sc[rr].aux), pv[12], rv[12];
-    ld_site<SP>(p, Vh, R, i, rr, pv);
-    ld_site<SP>(r, Vh, R, i, rr, rv);
-#pragma unroll
-    for (int k = 0; k < 12; k++) pv[k] = pv[k] - a * rv[k];
-    st_site<SP>(p, Vh, R, i, rr, pv);
 }
 
 // b = convert(a) (FP64 -> storage precision) for active right-hand sides
@@ -1327,6 +1317,7 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
     for (int j = 1; j < K; j++) pb[j] = w.make(("cg.p" + std::to_string(j + 1)).c_str(), SP::bytes, nrm);
     int cur = 0;            // p is pb[cur]
     bool step_now = false;  // this iteration's step is owed to x
+    bool orth = false;      // the next direction update first makes p orthogonal to r
     int nowed = 0;          // earlier steps owed too, their directions in pb[cur - 1], ..., pb[cur - nowed]
     // cnt directions, latest first, starting first buffers behind p's
     auto owed_dirs = [&](int first, int cnt) {
@@ -1362,7 +1353,7 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
             launch_fin(c, k_fin_cg_beta, w.R, (const double *)w.part, nblk, w.R, w.sc, plain ? 1 : 0, plain ? 0 : 1,
                        0);
         }
-        if (plain) launch_el(c, k_cg_p<SP, XP>, n, p, owed_dirs(0, 1), r, xlo, w.Vh, w.R, (const Scal *)w.sc, 0);
+        if (plain) launch_el(c, k_cg_p<SP, XP>, n, p, owed_dirs(0, 1), r, xlo, w.Vh, w.R, (const Scal *)w.sc, 0, 0);
     };
     // lagged decisions (low precision): the scalars of iteration k are copied to a pinned
     // slot behind its hops; the update rule at iteration k reads iteration k - 1's slot,
@@ -1499,7 +1490,7 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
             launch_fin(c, k_fin_cg_reset, w.R, (const double *)w.part, nblk, w.R, w.sc);
             launch_red(c, k_dot<SP>, n, r, p, w.Vh, w.R, w.part);
             launch_fin(c, k_fin_orth, w.R, (const double *)w.part, nblk, w.R, w.sc);
-            launch_el(c, k_orth_p<SP>, n, p, r, w.Vh, w.R, (const Scal *)w.sc);
+            orth = true;  // the direction update makes p orthogonal to the new r
             since = 0;
             read_scal(c, w.sc, hs);
             prev_ok = false;  // the slots predate the update
@@ -1512,14 +1503,15 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
         }
         if (K == 1 || !step_now) {
             launch_el(c, k_cg_p<SP, XP>, n, p, owed_dirs(0, 1), r, xlo, w.Vh, w.R, (const Scal *)w.sc,
-                      step_now ? 1 : 0);
+                      step_now ? 1 : 0, orth ? 1 : 0);
+            orth = false;
         } else {
             // the new direction goes into the next buffer: a free one, or with every buffer
             // holding an owed direction the oldest, whose step (with all others) is taken now
             const bool take = nowed + 1 == K;
             const int nxt = (cur + 1) % K;
             launch_el(c, k_cg_p<SP, XP>, n, pb[nxt], owed_dirs(0, 1 + nowed), r, xlo, w.Vh, w.R, (const Scal *)w.sc,
-                      take ? K : 0);
+                      take ? K : 0, 0);
             cur = nxt;
             p = pb[cur];
             nowed = take ? 0 : nowed + 1;

@@ -404,8 +404,8 @@ __global__ __launch_bounds__(kBS) void k_fold_x_step(Vec xhi, Vec xlo, Dirs dirs
     st_site<XP>(xlo, Vh, R, i, rr, z);
 }
 
-// r = b - m (FP64), partial |r|^2; restricted to masked right-hand sides unless all_rhs;
-// with rlo.d set also r converted to the storage precision SP
+// r = b - m (FP64; m.d null: m = 0), partial |r|^2; restricted to masked right-hand sides
+// unless all_rhs; with rlo.d set also r converted to the storage precision SP
 template <class SP>
 __global__ __launch_bounds__(kBS) void k_resid64(Vec b, Vec m, Vec r, Vec rlo, long Vh, int R, double *partial,
                                                  const Scal *sc, int all_rhs)
@@ -419,7 +419,12 @@ __global__ __launch_bounds__(kBS) void k_resid64(Vec b, Vec m, Vec r, Vec rlo, l
         long i = tid / R;
         Cx<double> a[12], c[12];
         ld_site<S64>(b, Vh, R, i, rr, a);
-        ld_site<S64>(m, Vh, R, i, rr, c);
+        if (m.d) {
+            ld_site<S64>(m, Vh, R, i, rr, c);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 12; k++) c[k] = {0, 0};
+        }
 #pragma unroll
         for (int k = 0; k < 12; k++) {
             a[k] = a[k] - c[k];
@@ -1046,6 +1051,7 @@ struct Work {
     bool use_graph = false;  // capture the CG iteration body in a HIP graph
     double delta2 = 0.01;    // reliable update when |res|^2 fell below delta2 times its last FP64 value
     int dirs = 0;            // direction buffers of the fused CG loop (0: the default)
+    bool x_zero = false;     // x_hi is known to be zero (the first residual is bhat itself)
     Vec make(const char *name, int bytes, bool norm)
     {
         Vec v;
@@ -1159,9 +1165,15 @@ void write_scal(laph_ctx *c, Scal *d, const std::vector<Scal> &h)
 template <class SP = S64>
 void true_eo_residual(Work &w, const Op64 &hi, Vec bhat, Vec xhi, Vec tmp, Vec rhi, int all_rhs, Vec rlo = Vec{})
 {
-    hi.mhat(xhi, tmp);
+    // with x_hi known to be zero (the first residual of a solve) the operator is skipped
+    Vec m = tmp;
+    if (w.x_zero)
+        m = Vec{};
+    else
+        hi.mhat(xhi, tmp);
+    w.x_zero = false;  // the caller goes on to change x_hi
     long n = w.Vh * w.R;
-    launch_red(w.c, k_resid64<SP>, n, bhat, tmp, rhi, rlo, w.Vh, w.R, w.part, (const Scal *)w.sc, all_rhs);
+    launch_red(w.c, k_resid64<SP>, n, bhat, m, rhi, rlo, w.Vh, w.R, w.part, (const Scal *)w.sc, all_rhs);
     launch_fin(w.c, k_fin_r2hi, w.R, (const double *)w.part, (int)red_blocks(n), w.R, w.sc, 0);
 }
 
@@ -1940,6 +1952,7 @@ void solve_batch(laph_ctx *c, const double *eta, double *x, int R, int nreal, co
         ptnet_initial_guess(c, (laph_ptnet *)sv->net, (float)dc.prm.bc_t, eta, R, (double2 *)xo.d);
     else
         LAPH_HIP(hipMemsetAsync(xo.d, 0, (size_t)12 * Vh * R * 16, c->stream));
+    w.x_zero = !(sv->net && sv->solver != LAPH_SOLVER_FGMRES);
     launch_el(c, k_copy64, n, bhat, rhi, Vh, R, (const Scal *)w.sc, 1);
 
     std::vector<int> iters(R, 0), fallback(R, 0);
@@ -1984,6 +1997,7 @@ void solve_batch(laph_ctx *c, const double *eta, double *x, int R, int nreal, co
             int m = sv->restart > 0 ? sv->restart : 24;
             iters[0] += fgmres(c, hi, (laph_ptnet *)sv->net, bhat, xo, rhi, eo_tol[0] * std::sqrt(hs[0].b2),
                                sv->maxiter, m, ok);
+            w.x_zero = false;
             if (!ok) fg_failed[0] = 1;
             what = "fgmres";
         }

@@ -550,10 +550,11 @@ __global__ void k_fin_rho(const double *partial, int nblk, int R, Scal *sc)
 // Sec. IV).  r is the normal-equation residual, res = bhat - Mhat x the even-odd residual
 // (both by recursion between FP64 reliable updates); rho holds |r|^2.
 
-// r = p = convert(rhi); res = convert(reshi); x = 0; partial |r|^2, |res|^2
+// start of CG from r = M^dag res already in storage precision: p = r, x = 0; partial |r|^2,
+// |res|^2 (masked RHS only)
 template <class SP, class XP>
-__global__ __launch_bounds__(kBS) void k_cg_init(Vec rhi, Vec reshi, Vec r, Vec p, Vec res, Vec x, long Vh, int R,
-                                                 double *partial, const Scal *sc, int zero_x)
+__global__ __launch_bounds__(kBS) void k_cg_start(Vec r, Vec p, Vec res, Vec x, long Vh, int R, double *partial,
+                                                  const Scal *sc)
 {
     double acc[2] = {0, 0};
     long n = Vh * R, stride = (long)gridDim.x * kBS;
@@ -561,21 +562,16 @@ __global__ __launch_bounds__(kBS) void k_cg_init(Vec rhi, Vec reshi, Vec r, Vec 
     bool act = sc[rr].active;
     for (long tid = blockIdx.x * (long)kBS + threadIdx.x; tid < n; tid += stride) {
         long i = tid / R;
-        Cx<double> v[12], z[12];
-        if (zero_x) {
+        Cx<double> v[12];
 #pragma unroll
-            for (int k = 0; k < 12; k++) z[k] = {0, 0};
-            st_site<XP>(x, Vh, R, i, rr, z);
-        }
+        for (int k = 0; k < 12; k++) v[k] = {0, 0};
+        st_site<XP>(x, Vh, R, i, rr, v);
         if (!act) continue;
-        ld_site<S64>(rhi, Vh, R, i, rr, v);
-        st_site<SP>(r, Vh, R, i, rr, v);
         ld_site<SP>(r, Vh, R, i, rr, v);
         st_site<SP>(p, Vh, R, i, rr, v);
 #pragma unroll
         for (int k = 0; k < 12; k++) acc[0] += v[k].re * v[k].re + v[k].im * v[k].im;
-        ld_site<S64>(reshi, Vh, R, i, rr, v);
-        st_site<SP>(res, Vh, R, i, rr, v);
+        ld_site<SP>(res, Vh, R, i, rr, v);
 #pragma unroll
         for (int k = 0; k < 12; k++) acc[1] += v[k].re * v[k].re + v[k].im * v[k].im;
     }
@@ -1287,14 +1283,13 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
     Vec r = w.make("cg.r", SP::bytes, nrm), p = w.make("cg.p", SP::bytes, nrm), res = w.make("cg.res", SP::bytes, nrm);
     Vec q = w.make("cg.q", SP::bytes, nrm), y = w.make("cg.y", SP::bytes, nrm), to = w.make("cg.to", SP::bytes, nrm);
     Vec xlo = w.make("cg.xlo", XP::bytes, false);
-    Vec to64 = w.make("cg.to64", 16, false);
-    // FP64 residuals of the masked RHS: reshi = bhat - M xhi, rhi = M^dag reshi
-    auto refresh = [&]() {
-        true_eo_residual(w, hi, bhat, xhi, tmp64, reshi, 0);
-        hi.mhat_dag(reshi, rhi, to64);
-    };
-    refresh();
-    launch_red(c, k_cg_init<SP, XP>, n, rhi, reshi, r, p, res, xlo, w.Vh, w.R, w.part, (const Scal *)w.sc, 1);
+    // FP64 residual of the masked RHS reshi = bhat - M xhi (res: the same in storage
+    // precision); the normal residual r = M^dag res by the storage-precision operator, as
+    // in the reliable updates
+    (void)rhi;
+    true_eo_residual<SP>(w, hi, bhat, xhi, tmp64, reshi, 0, res);
+    lo.mhat_dag(res, r, to);
+    launch_red(c, k_cg_start<SP, XP>, n, r, p, res, xlo, w.Vh, w.R, w.part, (const Scal *)w.sc);
     launch_fin(c, k_fin_cg_init, w.R, (const double *)w.part, nblk, w.R, w.sc);
     const double kDelta2 = w.delta2;
     read_scal(c, w.sc, hs);

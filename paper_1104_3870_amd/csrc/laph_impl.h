@@ -160,6 +160,9 @@ struct laph_ctx {
     DiracCache dc;   // operator of the caller's field (apply entry points)
     DiracCache dct;  // the same operator in temporal gauge (low-precision solves)
     DiracCache *cur = &dc;  // the cache the running solve uses
+    // temporal-gauge rotations the running solve folds into its layout conversions: G on
+    // the source (null where the source is rotated beforehand) and G^dag on the solution
+    const double *tg_in = nullptr, *tg_out = nullptr;
     std::map<std::string, DevBuf> bufs;  // named scratch buffers, grown on demand
     // autotuning: LDS tile (sites per block) per (precision, R) and the chosen R per
     // precision (0: not tuned)
@@ -193,8 +196,12 @@ void ctx_free(DevBuf &b);
 void links_to_eo(laph_ctx *c, const double *U, double2 *g64);
 void eo64_to_eo32(laph_ctx *c, const double2 *g64, float2 *g32, long n);
 // gam: 0 none, 4 multiply by gamma_4, 5 multiply by gamma_5 (applied per site)
-void spinor_to_eo(laph_ctx *c, const double *psi, int nrhs, int gam, double2 *even, double2 *odd);
-void spinor_from_eo(laph_ctx *c, const double2 *even, const double2 *odd, int nrhs, int gam, double *psi);
+// G (may be null): site-local colour rotations [V][3][3] applied to the field on the way in
+// (to_eo) or their adjoints on the way out (from_eo)
+void spinor_to_eo(laph_ctx *c, const double *psi, int nrhs, int gam, double2 *even, double2 *odd,
+                  const double *G = nullptr);
+void spinor_from_eo(laph_ctx *c, const double2 *even, const double2 *odd, int nrhs, int gam, double *psi,
+                    const double *G = nullptr);
 void smeared_links_to_soa(laph_ctx *c, const double *U, double2 *us);
 
 // clover.hip

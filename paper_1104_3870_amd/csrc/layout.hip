@@ -39,11 +39,12 @@ void eo64_to_eo32(laph_ctx *c, const double2 *g64, float2 *g32, long n)
 }
 
 // canonical [R][V][4][3] -> parity halves [12][Vh][R]; gam = 4 applies gamma_4 (chiral
-// basis: swaps the upper and lower spin pairs), gam = 5 applies gamma_5 = diag(1,1,-1,-1).
+// basis: swaps the upper and lower spin pairs), gam = 5 applies gamma_5 = diag(1,1,-1,-1);
+// G (may be null): a site-local colour rotation [V][3][3] applied first.
 // One lane per (site, RHS) with the RHS fastest: the parity halves are written with
 // consecutive RHS at consecutive addresses, every lane reads its site's 192-byte record.
 __global__ void k_spinor_to_eo(const double2 *__restrict__ psi, int nrhs, int gam, double2 *__restrict__ ev,
-                               double2 *__restrict__ od, int ns, long V, long Vh)
+                               double2 *__restrict__ od, int ns, long V, long Vh, const double2 *__restrict__ G)
 {
     long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (tid >= V * nrhs) return;
@@ -59,25 +60,38 @@ __global__ void k_spinor_to_eo(const double2 *__restrict__ psi, int nrhs, int ga
     long cb = s >> 1;
     double2 *dst = par ? od : ev;
     const double2 *src = psi + ((long)r * V + s) * 12;
+    double2 v[12];
+    for (int k = 0; k < 12; k++) v[k] = src[k];
+    if (G) {
+        const double2 *g = G + s * 9;
+        for (int a = 0; a < 4; a++) {
+            double2 o[3];
+            for (int col = 0; col < 3; col++)
+                o[col] = cadd(cadd(cmul(g[col * 3], v[a * 3]), cmul(g[col * 3 + 1], v[a * 3 + 1])),
+                              cmul(g[col * 3 + 2], v[a * 3 + 2]));
+            for (int col = 0; col < 3; col++) v[a * 3 + col] = o[col];
+        }
+    }
     for (int a = 0; a < 4; a++) {
         int sa = (gam == 4) ? (a ^ 2) : a;
         double sg = (gam == 5 && a >= 2) ? -1.0 : 1.0;
         for (int col = 0; col < 3; col++)
-            dst[((long)(a * 3 + col) * Vh + cb) * nrhs + r] = cscale(src[sa * 3 + col], sg);
+            dst[((long)(a * 3 + col) * Vh + cb) * nrhs + r] = cscale(v[sa * 3 + col], sg);
     }
 }
 
-void spinor_to_eo(laph_ctx *c, const double *psi, int nrhs, int gam, double2 *even, double2 *odd)
+void spinor_to_eo(laph_ctx *c, const double *psi, int nrhs, int gam, double2 *even, double2 *odd, const double *G)
 {
     long n = c->g.V * nrhs;
     hipLaunchKernelGGL(k_spinor_to_eo, dim3(nblocks_for(n, 256)), dim3(256), 0, c->stream, (const double2 *)psi,
-                       nrhs, gam, even, odd, c->g.ns, c->g.V, c->g.Vh);
+                       nrhs, gam, even, odd, c->g.ns, c->g.V, c->g.Vh, (const double2 *)G);
     LAPH_HIP(hipGetLastError());
 }
 
-// the inverse of k_spinor_to_eo, same lane order (reads of consecutive RHS coalesced)
+// the inverse of k_spinor_to_eo, same lane order (reads of consecutive RHS coalesced);
+// G (may be null): G^dag applied last
 __global__ void k_spinor_from_eo(const double2 *__restrict__ ev, const double2 *__restrict__ od, int nrhs, int gam,
-                                 double2 *__restrict__ psi, int ns, long V, long Vh)
+                                 double2 *__restrict__ psi, int ns, long V, long Vh, const double2 *__restrict__ G)
 {
     long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (tid >= V * nrhs) return;
@@ -93,19 +107,31 @@ __global__ void k_spinor_from_eo(const double2 *__restrict__ ev, const double2 *
     long cb = s >> 1;
     const double2 *src = par ? od : ev;
     double2 *dst = psi + ((long)r * V + s) * 12;
+    double2 v[12];
     for (int a = 0; a < 4; a++) {
         int sa = (gam == 4) ? (a ^ 2) : a;
         double sg = (gam == 5 && a >= 2) ? -1.0 : 1.0;
-        for (int col = 0; col < 3; col++)
-            dst[a * 3 + col] = cscale(src[((long)(sa * 3 + col) * Vh + cb) * nrhs + r], sg);
+        for (int col = 0; col < 3; col++) v[a * 3 + col] = cscale(src[((long)(sa * 3 + col) * Vh + cb) * nrhs + r], sg);
     }
+    if (G) {
+        const double2 *g = G + s * 9;
+        for (int a = 0; a < 4; a++) {
+            double2 o[3];
+            for (int col = 0; col < 3; col++)
+                o[col] = cadd(cadd(cconjmul(g[col], v[a * 3]), cconjmul(g[3 + col], v[a * 3 + 1])),
+                              cconjmul(g[6 + col], v[a * 3 + 2]));
+            for (int col = 0; col < 3; col++) v[a * 3 + col] = o[col];
+        }
+    }
+    for (int k = 0; k < 12; k++) dst[k] = v[k];
 }
 
-void spinor_from_eo(laph_ctx *c, const double2 *even, const double2 *odd, int nrhs, int gam, double *psi)
+void spinor_from_eo(laph_ctx *c, const double2 *even, const double2 *odd, int nrhs, int gam, double *psi,
+                    const double *G)
 {
     long n = c->g.V * nrhs;
     hipLaunchKernelGGL(k_spinor_from_eo, dim3(nblocks_for(n, 256)), dim3(256), 0, c->stream, even, odd, nrhs, gam,
-                       (double2 *)psi, c->g.ns, c->g.V, c->g.Vh);
+                       (double2 *)psi, c->g.ns, c->g.V, c->g.Vh, (const double2 *)G);
     LAPH_HIP(hipGetLastError());
 }
 

@@ -1534,7 +1534,7 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
 // b (canonical) -> b_e, b_o (gamma_4 applied), bhat
 void prepare_rhs(laph_ctx *c, const Op64 &hi, const double *eta, int R, Vec be, Vec bo, Vec bhat, Vec te)
 {
-    spinor_to_eo(c, eta, R, 4, (double2 *)be.d, (double2 *)bo.d);
+    spinor_to_eo(c, eta, R, 4, (double2 *)be.d, (double2 *)bo.d, c->tg_in);
     launch_clover_apply<S64, C64>(c, hi.cinv(0), be.d, nullptr, te.d, nullptr, hi.Vh, R, 0, c->stream);
     DslashArgs a = hi.base(1);
     a.in = te.d;
@@ -2054,7 +2054,7 @@ void solve_batch(laph_ctx *c, const double *eta, double *x, int R, int nreal, co
         }
         if (all) break;
     }
-    spinor_from_eo(c, (const double2 *)xe.d, (const double2 *)xo.d, R, 0, x);
+    spinor_from_eo(c, (const double2 *)xe.d, (const double2 *)xo.d, R, 0, x, c->tg_out);
     for (int q = 0; q < nreal; q++) {
         if (!stats) break;
         double rel = b2[q] > 0 ? std::sqrt(r2[q] / b2[q]) : 0.0;
@@ -2190,10 +2190,19 @@ extern "C" int dirac_solve(laph_ctx_t c, const double *U, const laph_dirac *d, c
         dirac_prepare(c, U, d, low);
     struct CurGuard {
         laph_ctx *c;
-        ~CurGuard() { c->cur = &c->dc; }
+        ~CurGuard()
+        {
+            c->cur = &c->dc;
+            c->tg_in = c->tg_out = nullptr;
+        }
     } cur_guard{c};
     c->cur = tg ? &c->dct : &c->dc;
     const double *G = tg ? (const double *)c->dct.gG.p : nullptr;
+    // eta' = G eta and x = G^dag x' inside the layout conversions of the solve; the network's
+    // initial guess reads the rotated source itself, which is then formed beforehand
+    const bool guess = sv->net && sv->solver != LAPH_SOLVER_FGMRES;
+    c->tg_in = guess ? nullptr : G;
+    c->tg_out = G;
     if (sv->solver == LAPH_SOLVER_FGMRES || sv->net) {
         laph_ptnet *net = (laph_ptnet *)sv->net;
         LAPH_CHECK(net && net->layers > 0, LAPH_EINVAL, "FGMRES needs a network");
@@ -2231,8 +2240,7 @@ extern "C" int dirac_solve(laph_ctx_t c, const double *U, const laph_dirac *d, c
             dst = px;
         }
         laph_solve_stats *st = stats ? stats + base : nullptr;
-        if (tg) {
-            // eta' = G eta; the solve returns x' = G x in dst, rotated back in place below
+        if (tg && guess) {
             double *te = (double *)ctx_named(c, "slv.tg_eta", (size_t)V * 24 * sizeof(double) * Rb);
             tgauge_spinor(c, G, src, te, Rb, 0);
             src = te;
@@ -2248,7 +2256,6 @@ extern "C" int dirac_solve(laph_ctx_t c, const double *U, const laph_dirac *d, c
             if (e.code != LAPH_ENOCONV) throw;
             if (first_err == LAPH_OK) first_err = e.code;
         }
-        if (tg) tgauge_spinor(c, G, dst, dst, Rb, 1);
         if (dst != xb) {
             size_t fb = (size_t)V * 24 * sizeof(double);
             LAPH_HIP(hipMemcpyAsync(xb, dst, fb * nreal, hipMemcpyDeviceToDevice, c->stream));

@@ -26,7 +26,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # MI355X FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz;
-# this build emits no packed FP32, so half of it is the attainable issue rate
+# the library's kernels are compiled without packed FP32, so half of it is the attainable
+# issue rate
 FP32_VECTOR_PEAK_TFS = 157.3
 
 
@@ -123,8 +124,9 @@ def main():
                     help="sources solved with FGMRES and the learned preconditioner (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(sources are independent; see the design notes on sharding)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path (LapH sources "
+              "are independent solves; several GPUs would each take their own share of the "
+              "dilution indices)", file=sys.stderr)
         return 2
 
     import dataclasses

@@ -11,7 +11,7 @@
  * double complex, with no blocking, no fusion and no even-odd tricks.  Each function
  * names the passage of the paper it follows.  Where the paper is silent the frozen
  * conventions are used (gamma basis, clover normalisation, anisotropy weights, noise
- * generator); they are listed in the design notes of the repository.
+ * generator), each stated at the routine that uses it.
  *
  * Index conventions (canonical layouts, identical to the C-ABI of the product):
  *   site   s = x + Ns*(y + Ns*(z + Ns*t))

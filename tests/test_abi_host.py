@@ -83,3 +83,34 @@ def test_create_rejects_odd_extents(L):
     assert L.laph_create(ctypes.byref(h), ctypes.byref(P.laph_geom(5, 8)), None) == P.LAPH_EINVAL
     assert L.laph_create(ctypes.byref(h), ctypes.byref(P.laph_geom(4, 7)), None) == P.LAPH_EINVAL
     assert L.laph_create(None, ctypes.byref(P.laph_geom(4, 8)), None) == P.LAPH_EINVAL
+
+
+_STRUCTS = ["laph_geom", "laph_stout", "laph_lanczos", "laph_eig_stats", "laph_dilution", "laph_dirac",
+            "laph_solver", "laph_solve_stats", "laph_adam", "laph_tune_entry", "laph_tune_report",
+            "laph_kernel_timing", "laph_timing"]
+
+
+def test_binding_structs_match_header(tmp_path):
+    """The ctypes mirrors of the header's parameter and result structs have the size and
+    the field offsets that a C compiler gives the header's own definitions (the binding
+    passes them by pointer, so a field added to one side only would shift the rest)."""
+    import subprocess
+
+    import paper_1104_3870_amd as P
+
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "laph.h"', "int main(void) {"]
+    for name in _STRUCTS:
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (name, name))
+        for f, _ in getattr(P, name)._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (name, f, name, f))
+    lines.append("return 0; }")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(l.rsplit(" ", 1) for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    for name in _STRUCTS:
+        S = getattr(P, name)
+        assert int(got["%s size" % name]) == ctypes.sizeof(S), name
+        for f, _ in S._fields_:
+            assert int(got["%s.%s" % (name, f)]) == getattr(S, f).offset, (name, f)

@@ -198,9 +198,11 @@ typedef struct {
                            LAPH_SOLVER_FGMRES; with the other solvers the initial guess
                            x0 = N(gamma_4 eta) on odd sites (N approximates K^-1) */
     int restart;        /* FGMRES restart length (0: 24) */
-    double reliable_delta; /* mixed precision: FP64 reliable update as soon as the iterated
-                              even-odd residual fell below this fraction of its last FP64
-                              value (0: 0.1), and at the latest every reliable_every iterations */
+    double reliable_delta; /* mixed precision: FP64 reliable update once the iterated even-odd
+                              residual fell below this fraction of its last FP64 value (0: 0.1)
+                              for a quarter of a block's active right-hand sides (or 100 times
+                              further for one, or one converged), and at the latest every
+                              reliable_every iterations */
     int dir_buffers;    /* mixed-precision CGNR: search directions kept until their steps are
                            added to the solution increment, which is then read and written once
                            per that many iterations (1..8; 0: 8) */

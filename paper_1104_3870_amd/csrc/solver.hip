@@ -4,10 +4,12 @@
 //   K x = b with b = gamma_4 eta (since Omega = gamma_4 K),
 //   M = 1 - A_oo^-1 D_oe A_ee^-1 D_eo,  bhat = A_oo^-1 (b_o - D_oe A_ee^-1 b_e),
 //   M x_o = bhat,  x_e = A_ee^-1 (b_e - D_eo x_o).
-// R right-hand sides are iterated together with their own BiCGStab scalars; a converged
-// right-hand side is frozen by its mask.  Lower-precision inner iterations keep the
-// solution increment in FP32 and fold it into the FP64 solution at every reliable
-// update, which also replaces the iterated residual by the FP64 true residual of M.
+// R right-hand sides are iterated together, each with its own Krylov scalars (BiCGStab, or
+// CG on the normal equations of M, the form used near the critical mass, where BiCGStab
+// diverges); a converged right-hand side is frozen by its mask.  Lower-precision inner
+// iterations keep the solution increment in FP32 and fold it into the FP64 solution at
+// every reliable update, which also replaces the iterated residual by the FP64 true
+// residual of M.
 // Every answer is judged by the FP64 true residual |b - K x| / |b| of the full system.
 #include <algorithm>
 #include <cmath>

@@ -35,13 +35,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# counter summary of the multi-RHS hops on the 24^3 x 128 workload (R = 32, FP16 records)
+TRAFFIC = "profiles/dslash_lds_f16_R32_24x24x24x128_traffic.json"
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
-    (profiles/traffic.json: FETCH_SIZE x its copy-kernel scale + WRITE_SIZE), or None when
-    there is none or the kernel's source has changed since the counters were taken."""
+    (TRAFFIC: FETCH_SIZE x its copy-kernel scale + WRITE_SIZE), or None when there is none
+    or the kernel's source has changed since the counters were taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = os.path.join(ROOT, TRAFFIC)
     if not kernel or not os.path.exists(path):
         return None
     with open(path) as f:
@@ -54,7 +58,7 @@ def measured_traffic(kernel):
             h.update(f.read())
     if h.hexdigest() != rec["sources_sha256"]:
         return None
-    return {"bytes_per_launch": rec["bytes_per_launch"], "source": "profiles/traffic.json (%s)" % rec["profile"]}
+    return {"bytes_per_launch": rec["bytes_per_launch"], "source": "%s (%s)" % (TRAFFIC, rec["profile"])}
 
 
 def cpu_baseline(cfg, U, evecs_np, dil_text, iters_sample, log_fn):

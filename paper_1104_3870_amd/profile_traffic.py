@@ -3,8 +3,9 @@
 Two programs run under `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` (one counter
 per run): the workload, and a device copy of known size that calibrates what each counter
 reports per byte on this GPU.  `summarize` turns the four result databases into a
-per-launch byte count for one kernel and records it in profiles/traffic.json, keyed by the
-library's timing label, with a hash of the kernel's sources so that a changed kernel is
+per-launch byte count for one kernel and records it in profiles/<profile>_traffic.json
+(<profile>: the summary the counters belong to, --profile), keyed by the library's
+timing label, with a hash of the kernel's sources so that a changed kernel is
 not credited with old counters.
 
     python -m paper_1104_3870_amd.profile_traffic copy            # calibration program
@@ -77,7 +78,7 @@ def summarize(a):
            "fetch_scale": sf, "write_scale": sw, "fetch_bytes": fetch, "write_bytes": write,
            "bytes_per_launch": fetch + write, "sources": a.sources, "sources_sha256": sources_sha(a.sources),
            "profile": a.profile}
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = os.path.join(ROOT, "profiles", os.path.splitext(a.profile)[0] + "_traffic.json")
     allrec = {}
     if os.path.exists(path):
         with open(path) as f:

@@ -22,10 +22,13 @@
  *
  * Ownership: the caller owns every pointer and the library never frees caller memory.
  * Field arguments are DEVICE pointers unless stated otherwise; statistics structs and
- * eigenvalues are host memory.  A context owns device scratch it allocates itself and
- * caches derived fields (even-odd links, clover term and its inverse) for the last gauge
- * field it saw, keyed by its address: call laph_forget_gauge() after changing a gauge
- * field in place or before passing a new field that may occupy a freed one's address.
+ * eigenvalues are host memory.  The library allocates no device memory: its scratch and
+ * the operator it derives from a gauge field live in a workspace the caller provides
+ * (laph_set_workspace, sized by laph_workspace_bytes).  The derived operator is cached for
+ * the last gauge field seen, keyed by the field's address and a fingerprint of its
+ * contents, so a field changed in place or a new field at a freed one's address is
+ * noticed; laph_forget_gauge() drops the cache.  The library keeps one small pinned host
+ * buffer per context for the solver's scalar readback.
  * Every call enqueues work on the context's HIP stream; calls that return statistics
  * synchronise that stream.  One context per stream; contexts share nothing.
  *
@@ -55,7 +58,7 @@ enum {
     LAPH_ENOCONV = 3, /* true residual above tol after every fallback; x holds the best iterate */
     LAPH_EEIG = 4,    /* eigensolver reached max_restarts before all N_v pairs converged */
     LAPH_EHIP = 5,    /* HIP runtime error */
-    LAPH_ENOMEM = 6   /* device allocation failed */
+    LAPH_ENOMEM = 6   /* the workspace (laph_set_workspace) is too small for the call */
 };
 
 typedef struct laph_ctx *laph_ctx_t;
@@ -75,7 +78,7 @@ LAPH_API const char *laph_strerror(int status);
 LAPH_API const char *laph_last_error(laph_ctx_t ctx);
 /* Drop every cached field derived from a gauge field. */
 LAPH_API int laph_forget_gauge(laph_ctx_t ctx);
-/* Device memory currently held by the context, in bytes. */
+/* Workspace bytes in use: the cached operator plus the running call's scratch. */
 LAPH_API size_t laph_device_bytes(laph_ctx_t ctx);
 
 /* -------------------------------------------------- stout smearing (Sec. II)
@@ -181,6 +184,52 @@ LAPH_API int laph_dirac_apply(laph_ctx_t ctx, const double *U, const laph_dirac 
                      const double *in, double *out, int n_fields);
 
 enum { LAPH_PREC_F64 = 0, LAPH_PREC_F32 = 1, LAPH_PREC_F16 = 2, LAPH_PREC_BF16 = 3 };
+
+/* ---------------------------------------------- even-odd hopping kernels
+ * One launch of the hopping kernels that the solver of Omega x = eta runs (Sec. II: K
+ * split by site parity; Sec. IV: the even-odd preconditioned solve in mixed precision), on
+ * caller fields, so that each kernel and its fused epilogue can be checked against a
+ * reference in every storage precision.  With D_{p,1-p} the hopping term H of K from the
+ * sites of parity 1-p to those of parity p (H as under laph_dirac_apply, its -1/2 and the
+ * weights included), A_pp the clover term of parity p and g5 = gamma_5 when hop->gamma5
+ * is set (else 1), the launch computes on the sites of the output parity p:
+ *   LAPH_HOP_PLAIN:    out = c g5 D in + a x                (x may be NULL: no addend)
+ *   LAPH_HOP_INV:      out = a x + c A_pp^-1 g5 D in        (x may be NULL)
+ *   LAPH_HOP_INV_DAG:  as LAPH_HOP_INV (x required, c != 0), and also
+ *                      out2 = A_pp^-1 gamma_5 out and norm2[r] = |out_r|^2,
+ *                      both from out as stored in the storage precision
+ *   LAPH_HOP_PLAIN_CG: r -= alpha_r (c g5 D in + a x) with r = out on entry (x required),
+ *                      norm2[r] = |r_r|^2 after the update, from r as stored
+ * The input is read on the sites of parity 1-p, x and r on parity p; every output is
+ * written on parity p and zero on parity 1-p.  Fields are converted to the storage
+ * precision (FP16 records carry one FP32 scale per site and field), the kernel runs in
+ * FP32 arithmetic with FP32 reconstruct-12 links and FP32 clover inverse (LAPH_PREC_F64:
+ * the FP64 kernel, modes PLAIN and INV only), and the results come back as FP64.
+ * temporal_gauge = 1 builds the operator from U' = G U G^dag with unit time links except
+ * on the last slice (the low-precision solves' form, whose kernel skips the unit links),
+ * applies G to the fields on the way in and G^dag on the way out: the result is the
+ * operator of U either way.  walk = 1 visits the sites in checkerboard order instead of
+ * the tiled walk; sites_per_block > 0 fixes the tile (S sites x n_fields lanes, S
+ * n_fields <= 256).
+ * in, x, out, out2: device, n_fields canonical spinor fields each; alpha, norm2: HOST
+ * arrays of n_fields (norm2 may be NULL).  n_fields: a power of two <= 32 (one launch). */
+enum { LAPH_HOP_PLAIN = 0, LAPH_HOP_INV = 1, LAPH_HOP_INV_DAG = 2, LAPH_HOP_PLAIN_CG = 3 };
+
+typedef struct {
+    int precision;       /* LAPH_PREC_* of the fields the kernel reads and writes */
+    int mode;            /* LAPH_HOP_* */
+    int parity;          /* output parity p: 0 even, 1 odd ((x + y + z + t) mod 2) */
+    int gamma5;          /* 1: gamma_5 applied to D in */
+    int temporal_gauge;  /* 1: operator built in temporal gauge (see above) */
+    int walk;            /* 0: tiled site walk where the lattice allows it; 1: checkerboard */
+    int sites_per_block; /* low precisions: sites per thread block; 0: tuned or default */
+    double a, c;         /* epilogue coefficients */
+} laph_hop;
+
+LAPH_API int laph_hop_apply(laph_ctx_t ctx, const double *U, const laph_dirac *dirac, const laph_hop *hop,
+                            const double *in, const double *x, double *out, double *out2, const double *alpha,
+                            double *norm2, int n_fields);
+
 enum { LAPH_SOLVER_BICGSTAB = 0, LAPH_SOLVER_CGNR = 1, LAPH_SOLVER_FGMRES = 2 };
 
 typedef struct {
@@ -305,6 +354,60 @@ LAPH_API int laph_autotune(laph_ctx_t ctx, const double *U, const laph_dirac *di
  * spinor fields; coef: device [n_rhs][Nt][4][Nv] complex. */
 LAPH_API int sink_project(laph_ctx_t ctx, const double *evecs, int nv, const double *X, int n_rhs,
                  double *coef);
+
+/* ----------------------------------------------------------------- workspace
+ * The library allocates no device memory.  Every call takes its device scratch, and the
+ * context keeps the operator it derives from a gauge field (even-odd links, clover term
+ * and inverse, their low-precision copies, the temporal-gauge field), in one workspace
+ * the caller allocates and hands over with laph_set_workspace (a torch tensor, say, so
+ * that PyTorch owns all device memory).  laph_workspace_bytes gives the bytes one entry
+ * point needs on this context's lattice: with a workspace of at least that size the call
+ * never fails for lack of room, whatever ran before (a cached operator the call does not
+ * use is evicted when its room is needed; at most one is held).  A call without room
+ * returns LAPH_ENOMEM and leaves its outputs undefined.  Scratch is released when a call
+ * returns; the cached operator stays until another field, another set of Dirac parameters
+ * or laph_set_workspace / laph_forget_gauge replaces it.  The workspace must stay valid
+ * while work enqueued on the context's stream may use it.
+ * Ops and the fields of laph_ws_params they read:
+ *   LAPH_WS_STOUT, LAPH_WS_LAPLACIAN, LAPH_WS_CHEBYSHEV, LAPH_WS_NOISE: none (params may be NULL);
+ *   LAPH_WS_EIGVECS: nv, krylov_dim;   LAPH_WS_SOURCE: nv;   LAPH_WS_SINK: nv, n (= n_rhs);
+ *   LAPH_WS_DIRAC_APPLY: n (= n_fields);   LAPH_WS_HOP_APPLY: hop, n (= n_fields);
+ *   LAPH_WS_SOLVE: solver, n (= n_rhs) (a learned network is taken from solver->net);
+ *   LAPH_WS_AUTOTUNE: precision;   LAPH_WS_PTNET_FORWARD / _BACKWARD / _TRAIN: net, n
+ *   (= n_fields or n_pairs).
+ * Returns 0 for an unknown op or missing parameters. */
+enum {
+    LAPH_WS_STOUT = 0,
+    LAPH_WS_LAPLACIAN = 1,
+    LAPH_WS_CHEBYSHEV = 2,
+    LAPH_WS_EIGVECS = 3,
+    LAPH_WS_NOISE = 4,
+    LAPH_WS_SOURCE = 5,
+    LAPH_WS_DIRAC_APPLY = 6,
+    LAPH_WS_HOP_APPLY = 7,
+    LAPH_WS_SOLVE = 8,
+    LAPH_WS_AUTOTUNE = 9,
+    LAPH_WS_SINK = 10,
+    LAPH_WS_PTNET_FORWARD = 11,
+    LAPH_WS_PTNET_BACKWARD = 12,
+    LAPH_WS_PTNET_TRAIN = 13
+};
+
+typedef struct {
+    int n;                     /* fields, right-hand sides, sources or training pairs of the call */
+    int nv;                    /* LapH vectors per time slice */
+    int krylov_dim;            /* eigensolver Krylov dimension m */
+    int precision;             /* LAPH_PREC_* (autotuning) */
+    const laph_solver *solver; /* solve parameters */
+    const laph_hop *hop;       /* hopping-launch parameters */
+    laph_ptnet_t net;          /* network */
+} laph_ws_params;
+
+LAPH_API size_t laph_workspace_bytes(laph_ctx_t ctx, int op, const void *params);
+/* Hand the context its workspace: dev_ptr (256-byte aligned device memory on the
+ * context's device, or NULL to release it) of `bytes` bytes.  Waits for the context's
+ * stream and drops the cached operator. */
+LAPH_API int laph_set_workspace(laph_ctx_t ctx, void *dev_ptr, size_t bytes);
 
 /* ----------------------------------------------------------------- profiling
  * With timing on, the library brackets every even-odd hopping kernel launch with HIP

@@ -2,9 +2,12 @@
 
 Argument marshalling only: every step runs in the HIP kernels of ``liblaph.so``.  Device
 memory is owned by torch tensors (complex128 fields, or float64 with a trailing
-(re, im) axis); the library works on the stream passed at context creation (default:
-torch's current stream).  The binding raises if the library has not been built, and
-it never falls back to any CPU computation.
+(re, im) axis), the library's workspace included: before each call the binding asks the
+library how much workspace the call needs (laph_workspace_bytes) and, when the context's
+workspace tensor is smaller, allocates a larger one and hands it over
+(laph_set_workspace).  The library works on the stream passed at context creation
+(default: torch's current stream).  The binding raises if the library has not been
+built, and it never falls back to any CPU computation.
 """
 from __future__ import annotations
 
@@ -19,6 +22,7 @@ LAPH_DIL_NONE, LAPH_DIL_FULL, LAPH_DIL_BLOCK, LAPH_DIL_INTERLACE = range(4)
 LAPH_OP_K, LAPH_OP_OMEGA, LAPH_OP_KDAG = range(3)
 LAPH_PREC_F64, LAPH_PREC_F32, LAPH_PREC_F16, LAPH_PREC_BF16 = range(4)
 LAPH_SOLVER_BICGSTAB, LAPH_SOLVER_CGNR, LAPH_SOLVER_FGMRES = range(3)
+LAPH_HOP_PLAIN, LAPH_HOP_INV, LAPH_HOP_INV_DAG, LAPH_HOP_PLAIN_CG = range(4)
 PRECISIONS = {"f64": LAPH_PREC_F64, "f32": LAPH_PREC_F32, "f16": LAPH_PREC_F16, "bf16": LAPH_PREC_BF16}
 
 
@@ -54,6 +58,17 @@ class laph_dilution(ctypes.Structure):
 class laph_dirac(ctypes.Structure):
     _fields_ = [("m0", ctypes.c_double), ("xi", ctypes.c_double), ("c_sw", ctypes.c_double),
                 ("bc_t", ctypes.c_double)]
+
+
+class laph_hop(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("mode", ctypes.c_int), ("parity", ctypes.c_int),
+                ("gamma5", ctypes.c_int), ("temporal_gauge", ctypes.c_int), ("walk", ctypes.c_int),
+                ("sites_per_block", ctypes.c_int), ("a", ctypes.c_double), ("c", ctypes.c_double)]
+
+
+class laph_ws_params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("nv", ctypes.c_int), ("krylov_dim", ctypes.c_int), ("precision", ctypes.c_int),
+                ("solver", ctypes.c_void_p), ("hop", ctypes.c_void_p), ("net", ctypes.c_void_p)]
 
 
 class laph_solver(ctypes.Structure):
@@ -115,6 +130,8 @@ EXPORTS = {
     "make_diluted_source": (_I, [_P, _P, _I, ctypes.c_uint16, ctypes.c_uint16, ctypes.POINTER(laph_dilution),
                                  ctypes.c_int64, _I, _P]),
     "laph_dirac_apply": (_I, [_P, _P, ctypes.POINTER(laph_dirac), _I, _P, _P, _I]),
+    "laph_hop_apply": (_I, [_P, _P, ctypes.POINTER(laph_dirac), ctypes.POINTER(laph_hop), _P, _P, _P, _P, _P, _P,
+                            _I]),
     "dirac_solve": (_I, [_P, _P, ctypes.POINTER(laph_dirac), _P, _P, _I, ctypes.POINTER(laph_solver),
                          ctypes.POINTER(laph_solve_stats)]),
     "sink_project": (_I, [_P, _P, _I, _P, _I, _P]),
@@ -127,6 +144,8 @@ EXPORTS = {
     "laph_ptnet_backward": (_I, [_P, _P, _P, _D, _P, _P, _P, _P, _I]),
     "laph_ptnet_train_step": (_I, [_P, _P, _P, _D, _P, _P, _I, ctypes.POINTER(laph_adam), ctypes.POINTER(_D)]),
     "laph_autotune": (_I, [_P, _P, ctypes.POINTER(laph_dirac), _I, ctypes.POINTER(laph_tune_report)]),
+    "laph_workspace_bytes": (ctypes.c_size_t, [_P, _I, _P]),
+    "laph_set_workspace": (_I, [_P, _P, ctypes.c_size_t]),
     "laph_set_timing": (_I, [_P, _I]),
     "laph_get_timing": (_I, [_P, ctypes.POINTER(laph_timing), _I]),
 }
@@ -182,6 +201,65 @@ def _hptr(a):
     return ctypes.c_void_p(a.ctypes.data)
 
 
+# ------------------------------------------------------------------ workspace
+(LAPH_WS_STOUT, LAPH_WS_LAPLACIAN, LAPH_WS_CHEBYSHEV, LAPH_WS_EIGVECS, LAPH_WS_NOISE, LAPH_WS_SOURCE,
+ LAPH_WS_DIRAC_APPLY, LAPH_WS_HOP_APPLY, LAPH_WS_SOLVE, LAPH_WS_AUTOTUNE, LAPH_WS_SINK, LAPH_WS_PTNET_FORWARD,
+ LAPH_WS_PTNET_BACKWARD, LAPH_WS_PTNET_TRAIN) = range(14)
+
+_WS = {}  # context handle value -> workspace tensor
+
+
+def _key(ctx):
+    return ctx.value if isinstance(ctx, ctypes.c_void_p) else int(ctx)
+
+
+def laph_workspace_bytes(ctx, op, n=0, nv=0, krylov_dim=0, precision=0, solver=None, hop=None, net=None):
+    p = laph_ws_params(n, nv, krylov_dim, precision,
+                       ctypes.cast(ctypes.pointer(solver), ctypes.c_void_p) if solver is not None else None,
+                       ctypes.cast(ctypes.pointer(hop), ctypes.c_void_p) if hop is not None else None,
+                       net.handle if isinstance(net, PTNet) else net)
+    need = lib().laph_workspace_bytes(ctx, op, ctypes.byref(p))
+    if need == 0:
+        raise LaphError(LAPH_EINVAL, "laph_workspace_bytes: invalid op or parameters")
+    return need
+
+
+def laph_set_workspace(ctx, tensor):
+    """Hand the context a workspace tensor (device, any dtype; None releases it)."""
+    if tensor is None:
+        _check(lib().laph_set_workspace(ctx, None, 0), ctx)
+        _WS.pop(_key(ctx), None)
+        return
+    ptr = _dptr(tensor)
+    _check(lib().laph_set_workspace(ctx, ptr, tensor.numel() * tensor.element_size()), ctx)
+    _WS[_key(ctx)] = tensor
+
+
+def workspace(ctx):
+    """The context's workspace tensor (None before the first call)."""
+    return _WS.get(_key(ctx))
+
+
+def ensure_workspace(ctx, op, **params):
+    """Give the context a workspace of at least what `op` needs (grown, never shrunk)."""
+    import torch
+
+    need = laph_workspace_bytes(ctx, op, **params)
+    cur = _WS.get(_key(ctx))
+    have = cur.numel() if cur is not None else 0
+    if have >= need:
+        return cur
+    size = max(need, have + have // 4)
+    size = (size + (2 << 20) - 1) // (2 << 20) * (2 << 20)
+    # release the old one to the library first (it waits for the stream), then to torch
+    _check(lib().laph_set_workspace(ctx, None, 0), ctx)
+    _WS.pop(_key(ctx), None)
+    del cur
+    t = torch.empty(size, dtype=torch.uint8, device="cuda")
+    laph_set_workspace(ctx, t)
+    return t
+
+
 # ------------------------------------------------------------------ ABI names
 
 def laph_create(ns, nt, stream=None):
@@ -196,6 +274,7 @@ def laph_create(ns, nt, stream=None):
 
 def laph_destroy(ctx):
     _check(lib().laph_destroy(ctx))
+    _WS.pop(_key(ctx), None)
 
 
 def laph_forget_gauge(ctx):
@@ -213,14 +292,17 @@ def laph_dilution_count(dil, nt, nv):
 
 
 def laph_stout_smear(ctx, U, rho, nsteps, out):
+    ensure_workspace(ctx, LAPH_WS_STOUT)
     _check(lib().laph_stout_smear(ctx, _dptr(U), ctypes.byref(laph_stout(rho, nsteps)), _dptr(out)), ctx)
 
 
 def laph_laplacian_apply(ctx, U, v, out):
+    ensure_workspace(ctx, LAPH_WS_LAPLACIAN)
     _check(lib().laph_laplacian_apply(ctx, _dptr(U), _dptr(v), _dptr(out)), ctx)
 
 
 def laph_chebyshev_apply(ctx, U, lam_l, lam_c, order, v, out):
+    ensure_workspace(ctx, LAPH_WS_CHEBYSHEV)
     _check(lib().laph_chebyshev_apply(ctx, _dptr(U), lam_l, lam_c, order, _dptr(v), _dptr(out)), ctx)
 
 
@@ -230,6 +312,7 @@ def laph_eigvecs(ctx, U, rho, nsteps, nv, evals_host, evecs, krylov=160, cheb_or
     import numpy as np
 
     assert evals_host.dtype == np.float64 and evals_host.flags["C_CONTIGUOUS"]
+    ensure_workspace(ctx, LAPH_WS_EIGVECS, nv=nv, krylov_dim=krylov)
     st = laph_eig_stats()
     lz = laph_lanczos(krylov, cheb_order, lam_l, lam_c, tol, max_restarts, seed)
     rc = lib().laph_eigvecs(ctx, _dptr(U), ctypes.byref(laph_stout(rho, nsteps)), ctypes.byref(lz), nv,
@@ -239,19 +322,47 @@ def laph_eigvecs(ctx, U, rho, nsteps, nv, evals_host, evecs, krylov=160, cheb_or
 
 
 def laph_z4_noise(ctx, s, k, nv, rho):
+    ensure_workspace(ctx, LAPH_WS_NOISE)
     _check(lib().laph_z4_noise(ctx, s, k, nv, _dptr(rho)), ctx)
 
 
 def make_diluted_source(ctx, evecs, nv, noise_s, config_k, dil, b_first, n_src, eta):
+    ensure_workspace(ctx, LAPH_WS_SOURCE, nv=nv)
     _check(lib().make_diluted_source(ctx, _dptr(evecs), nv, noise_s, config_k, ctypes.byref(dil), b_first, n_src,
                                      _dptr(eta)), ctx)
 
 
 def laph_dirac_apply(ctx, U, dirac, op, x, out, n_fields=1):
+    ensure_workspace(ctx, LAPH_WS_DIRAC_APPLY, n=n_fields)
     _check(lib().laph_dirac_apply(ctx, _dptr(U), ctypes.byref(dirac), op, _dptr(x), _dptr(out), n_fields), ctx)
 
 
+def laph_hop_apply(ctx, U, dirac, precision, mode, parity, inp, out, x=None, out2=None, alpha=None, gamma5=0,
+                   temporal_gauge=0, walk=0, sites_per_block=0, a=0.0, c=1.0):
+    """One even-odd hopping launch (see laph.h); returns the host norm2 array (list)."""
+    import numpy as np
+
+    n = inp.shape[0]
+    h = laph_hop(PRECISIONS[precision] if isinstance(precision, str) else precision, mode, parity, gamma5,
+                 temporal_gauge, walk, sites_per_block, a, c)
+    al = None
+    if alpha is not None:
+        al = np.ascontiguousarray(np.asarray(alpha, dtype=np.float64))
+        if al.size != n:
+            raise ValueError("alpha needs one value per field")
+    nrm = np.zeros(n)
+    if n <= 32:
+        ensure_workspace(ctx, LAPH_WS_HOP_APPLY, n=n, hop=h)
+    _check(lib().laph_hop_apply(ctx, _dptr(U), ctypes.byref(dirac), ctypes.byref(h), _dptr(inp),
+                                _dptr(x) if x is not None else None, _dptr(out),
+                                _dptr(out2) if out2 is not None else None,
+                                al.ctypes.data_as(ctypes.c_void_p) if al is not None else None,
+                                nrm.ctypes.data_as(ctypes.c_void_p), n), ctx)
+    return nrm
+
+
 def dirac_solve(ctx, U, dirac, eta, x, n_rhs, solver, raise_on_noconv=True):
+    ensure_workspace(ctx, LAPH_WS_SOLVE, n=n_rhs, solver=solver)
     stats = (laph_solve_stats * n_rhs)()
     rc = lib().dirac_solve(ctx, _dptr(U), ctypes.byref(dirac), _dptr(eta), _dptr(x), n_rhs, ctypes.byref(solver),
                            stats)
@@ -262,6 +373,7 @@ def dirac_solve(ctx, U, dirac, eta, x, n_rhs, solver, raise_on_noconv=True):
 
 
 def sink_project(ctx, evecs, nv, X, n_rhs, coef):
+    ensure_workspace(ctx, LAPH_WS_SINK, nv=nv, n=n_rhs)
     _check(lib().sink_project(ctx, _dptr(evecs), nv, _dptr(X), n_rhs, _dptr(coef)), ctx)
 
 
@@ -269,6 +381,7 @@ def laph_autotune(ctx, U, dirac, precision="f16"):
     """Tune the block size and LDS tile of the hopping kernel; returns the report as a dict."""
     rep = laph_tune_report()
     prec = PRECISIONS[precision] if isinstance(precision, str) else precision
+    ensure_workspace(ctx, LAPH_WS_AUTOTUNE, precision=prec)
     _check(lib().laph_autotune(ctx, _dptr(U), ctypes.byref(dirac), prec, ctypes.byref(rep)), ctx)
     return {"entries": [(rep.e[i].block_rhs, rep.e[i].sites_per_block, rep.e[i].ms_per_rhs) for i in range(rep.n)],
             "best_block_rhs": rep.best_block_rhs, "best_sites_per_block": rep.best_sites_per_block}
@@ -321,10 +434,12 @@ def laph_ptnet_set_weights(net, w):
 
 
 def laph_ptnet_forward(ctx, net, U, bc_t, x, out, n_fields=1):
+    ensure_workspace(ctx, LAPH_WS_PTNET_FORWARD, n=n_fields, net=net)
     _check(lib().laph_ptnet_forward(ctx, net, _dptr(U), bc_t, _dptr(x), _dptr(out), n_fields), ctx)
 
 
 def laph_ptnet_backward(ctx, net, U, bc_t, x, gout, gin, gw, n_fields=1):
+    ensure_workspace(ctx, LAPH_WS_PTNET_BACKWARD, n=n_fields, net=net)
     _check(lib().laph_ptnet_backward(ctx, net, _dptr(U), bc_t, _dptr(x), _dptr(gout),
                                      _dptr(gin) if gin is not None else None, _hptr(gw), n_fields), ctx)
 
@@ -333,6 +448,7 @@ def laph_ptnet_train_step(ctx, net, U, bc_t, b, x, n_pairs, lr=1e-3, beta1=0.9, 
                           loss_parity=-1):
     loss = _D()
     opt = laph_adam(lr, beta1, beta2, eps, loss_parity)
+    ensure_workspace(ctx, LAPH_WS_PTNET_TRAIN, n=n_pairs, net=net)
     _check(lib().laph_ptnet_train_step(ctx, net, _dptr(U), bc_t, _dptr(b), _dptr(x), n_pairs, ctypes.byref(opt),
                                        ctypes.byref(loss)), ctx)
     return loss.value

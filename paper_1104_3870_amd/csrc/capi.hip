@@ -19,47 +19,136 @@ void laph_fail(int code, const char *fmt, ...)
     throw LaphError{code};
 }
 
-void *ctx_buf(laph_ctx *c, DevBuf &b, size_t bytes)
+// ------------------------------------------------------------------ workspace
+void *ctx_named(laph_ctx *c, const std::string &name, size_t bytes)
 {
+    DevBuf &b = c->bufs[name];
     if (bytes == 0) bytes = 256;
     if (b.bytes >= bytes) return b.p;
-    if (b.p) {
-        LAPH_HIP(hipStreamSynchronize(c->stream));
-        LAPH_HIP(hipFree(b.p));
-        b.p = nullptr;
-        b.bytes = 0;
-    }
-    size_t want = (bytes + 4095) & ~size_t(4095);
-    hipError_t e = hipMalloc(&b.p, want);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        b.p = nullptr;
-        laph_fail(LAPH_ENOMEM, "hipMalloc of %zu bytes failed: %s", want, hipGetErrorString(e));
-    }
+    // a grown buffer takes a new piece (the old one stays until the call returns)
+    const size_t want = ws_align(bytes);
+    if (c->ws && c->ws_lo + want + c->ws_hi > c->ws_bytes && c->ws_unit && !c->ws_pinned) cache_release_all(c);
+    if (!c->ws || c->ws_lo + want + c->ws_hi > c->ws_bytes)
+        laph_fail(LAPH_ENOMEM, "workspace of %zu bytes has no room for %zu more bytes (%s; scratch %zu, cached "
+                  "operator %zu): size it with laph_workspace_bytes",
+                  c->ws_bytes, want, name.c_str(), c->ws_lo, c->ws_hi);
+    b.p = c->ws + c->ws_lo;
     b.bytes = want;
+    c->ws_lo += want;
     return b.p;
 }
 
-void ctx_free(DevBuf &b)
+void scratch_reset(laph_ctx *c)
 {
-    if (b.p) (void)hipFree(b.p);
-    b.p = nullptr;
-    b.bytes = 0;
+    c->bufs.clear();
+    c->ws_lo = 0;
+    c->ws_pinned = false;
 }
 
-static void free_dirac_cache(DiracCache &d)
+static void invalidate(DiracCache &d)
 {
-    ctx_free(d.g64);
-    ctx_free(d.g32);
-    ctx_free(d.clov);
-    ctx_free(d.clinv);
-    ctx_free(d.clinv32);
-    ctx_free(d.lk12);
-    ctx_free(d.claos);
-    ctx_free(d.gU);
-    ctx_free(d.gG);
     d.valid = false;
+    d.f32 = false;
     d.U = nullptr;
+    d.fp = 0;
+    d.unit = DevBuf{};
+    d.g64 = d.clov = d.clinv = d.lk12 = d.claos = d.gU = d.gG = DevBuf{};
+    d.has_f32 = false;
+}
+
+void cache_release_all(laph_ctx *c)
+{
+    if (c->ws_unit) invalidate(*c->ws_unit);
+    c->ws_unit = nullptr;
+    c->ws_hi = 0;
+    c->ws_pinned = false;
+}
+
+void cache_unit(laph_ctx *c, DiracCache &dc, size_t bytes)
+{
+    bytes = ws_align(bytes);
+    if (c->ws_unit == &dc && dc.unit.bytes >= bytes) {
+        c->ws_pinned = true;
+        return;
+    }
+    cache_release_all(c);
+    if (!c->ws || c->ws_lo + bytes > c->ws_bytes)
+        laph_fail(LAPH_ENOMEM, "workspace of %zu bytes has no room for a cached operator of %zu bytes: size it "
+                  "with laph_workspace_bytes", c->ws_bytes, bytes);
+    c->ws_hi = bytes;
+    dc.unit.p = c->ws + (c->ws_bytes - bytes);
+    dc.unit.bytes = bytes;
+    c->ws_unit = &dc;
+    c->ws_pinned = true;
+}
+
+// fields of a cache unit, in order
+static void unit_layout(const Geom &g, bool tgauge, bool f32, size_t (&sz)[7])
+{
+    const long Vh = g.Vh, V = g.V;
+    sz[0] = (size_t)72 * Vh * 16;                 // g64
+    sz[1] = (size_t)144 * Vh * 8;                 // clov
+    sz[2] = (size_t)144 * Vh * 8;                 // clinv
+    sz[3] = f32 ? (size_t)8 * Vh * 3 * 16 : 0;    // lk12
+    sz[4] = f32 ? (size_t)2 * Vh * 72 * 4 : 0;    // claos
+    sz[5] = tgauge ? (size_t)V * 36 * 16 : 0;     // gU
+    sz[6] = tgauge ? (size_t)V * 9 * 16 : 0;      // gG
+}
+
+size_t cache_unit_bytes(const Geom &g, bool tgauge, bool f32)
+{
+    size_t sz[7], s = 0;
+    unit_layout(g, tgauge, f32, sz);
+    for (size_t v : sz) s += ws_align(v);
+    return s;
+}
+
+void cache_carve(laph_ctx *c, DiracCache &dc, bool tgauge, bool f32)
+{
+    size_t sz[7];
+    unit_layout(c->g, tgauge, f32, sz);
+    DevBuf *f[7] = {&dc.g64, &dc.clov, &dc.clinv, &dc.lk12, &dc.claos, &dc.gU, &dc.gG};
+    char *p = (char *)dc.unit.p;
+    for (int k = 0; k < 7; k++) {
+        f[k]->p = sz[k] ? p : nullptr;
+        f[k]->bytes = sz[k];
+        p += ws_align(sz[k]);
+    }
+    dc.has_f32 = f32;
+}
+
+// sum over the field's 64-bit words of a mixed (word, index) hash, wrapping: equal for
+// equal contents, different with overwhelming probability otherwise
+__global__ void k_fingerprint(const unsigned long long *__restrict__ w, long n, unsigned long long *out)
+{
+    unsigned long long acc = 0;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        unsigned long long z = w[i] + 0x9E3779B97F4A7C15ull * (unsigned long long)(i + 1);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        acc += z ^ (z >> 31);
+    }
+    __shared__ unsigned long long red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(out, red[0]);
+}
+
+uint64_t gauge_fingerprint(laph_ctx *c, const double *U)
+{
+    unsigned long long *d = (unsigned long long *)ctx_named(c, "fp.sum", 8);
+    LAPH_HIP(hipMemsetAsync(d, 0, 8, c->stream));
+    const long n = c->g.V * 4 * 9 * 2;
+    hipLaunchKernelGGL(k_fingerprint, dim3(1024), dim3(256), 0, c->stream, (const unsigned long long *)U, n, d);
+    LAPH_HIP(hipGetLastError());
+    unsigned long long h = 0;
+    LAPH_HIP(hipMemcpyAsync(&h, d, 8, hipMemcpyDeviceToHost, c->stream));
+    LAPH_HIP(hipStreamSynchronize(c->stream));
+    return h;
 }
 
 extern "C" int laph_create(laph_ctx_t *out, const laph_geom *geom, void *stream)
@@ -87,9 +176,8 @@ extern "C" int laph_destroy(laph_ctx_t c)
     if (!c) return LAPH_EINVAL;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    free_dirac_cache(c->dc);
-    free_dirac_cache(c->dct);
-    for (auto &kv : c->bufs) ctx_free(kv.second);
+    cache_release_all(c);
+    scratch_reset(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->pin) (void)hipHostFree(c->pin);
     for (hipEvent_t e : c->pin_ev)
@@ -115,7 +203,7 @@ extern "C" const char *laph_strerror(int s)
     case LAPH_ENOCONV: return "solver did not reach the requested true residual";
     case LAPH_EEIG: return "eigensolver did not converge within max_restarts";
     case LAPH_EHIP: return "HIP runtime error";
-    case LAPH_ENOMEM: return "device allocation failed";
+    case LAPH_ENOMEM: return "workspace too small";
     }
     return "unknown status";
 }
@@ -127,20 +215,29 @@ extern "C" int laph_forget_gauge(laph_ctx_t c)
     if (!c) return LAPH_EINVAL;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    free_dirac_cache(c->dc);
-    free_dirac_cache(c->dct);
+    cache_release_all(c);
     return LAPH_OK;
 }
 
 extern "C" size_t laph_device_bytes(laph_ctx_t c)
 {
     if (!c) return 0;
-    size_t s = 0;
-    for (const DiracCache *d : {&c->dc, &c->dct})
-        s += d->g64.bytes + d->g32.bytes + d->clov.bytes + d->clinv.bytes + d->clinv32.bytes + d->lk12.bytes +
-             d->claos.bytes + d->gU.bytes + d->gG.bytes;
-    for (auto &kv : c->bufs) s += kv.second.bytes;
-    return s;
+    return c->ws_hi + c->ws_lo;
+}
+
+extern "C" int laph_set_workspace(laph_ctx_t c, void *dev_ptr, size_t bytes)
+{
+    if (!c) return LAPH_EINVAL;
+    if (!dev_ptr && bytes) return LAPH_EINVAL;
+    if (((uintptr_t)dev_ptr & 255) != 0) return LAPH_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return LAPH_EHIP;
+    // nothing queued may still use the old workspace
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return LAPH_EHIP;
+    cache_release_all(c);
+    scratch_reset(c);
+    c->ws = (char *)dev_ptr;
+    c->ws_bytes = dev_ptr ? bytes & ~size_t(255) : 0;  // every piece stays 256-byte aligned
+    return LAPH_OK;
 }
 
 // ----------------------------------------------------------------------- timing

@@ -217,7 +217,7 @@ __device__ __forceinline__ void hop_rolled(const DslashArgs &P, long i, int r, i
     }
 }
 
-template <class SP, class GP, class CP, int MODE, bool O32, bool ROLL>
+template <class SP, class GP, class CP, int MODE, bool O32>
 __global__ __launch_bounds__(256) void k_dslash(const DslashArgs P)
 {
     using A = typename SP::A;
@@ -240,123 +240,7 @@ __global__ __launch_bounds__(256) void k_dslash(const DslashArgs P)
 #pragma unroll
         for (int c = 0; c < 3; c++) acc.v[a][c] = {(A)0, (A)0};
 
-    if constexpr (ROLL) {
-        hop_rolled<O32>(P, i, r, x, y, z, t, acc);
-    } else {
-#pragma unroll
-        for (int mu = 0; mu < 4; mu++) {
-            // ---------------- forward hop: (1 - g_mu) U_mu(x) psi(x+mu)
-            {
-                int xx = x, yy = y, zz = z, tt = t;
-                A w = (A)(mu == 3 ? P.wt : P.ws);
-                if (mu == 0) xx = (x + 1 == ns) ? 0 : x + 1;
-                if (mu == 1) yy = (y + 1 == ns) ? 0 : y + 1;
-                if (mu == 2) zz = (z + 1 == ns) ? 0 : z + 1;
-                if (mu == 3) {
-                    tt = (t + 1 == nt) ? 0 : t + 1;
-                    if (t + 1 == nt) w *= (A)P.bct;
-                }
-                long nb = lex_index(xx, yy, zz, tt, ns) >> 1;
-                Spin<A> s;
-                load_spinor<SP, O32>(in, P.in_nrm, Vh, R, nb, r, s);
-                Cx<A> U[9];
-                load_link<GP, A, O32>(g, mu, par, Vh, i, U);
-                Cx<A> h0[3], h1[3], o0[3], o1[3];
-#pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    if (mu == 0) {
-                        h0[c] = s.v[0][c] + timesI(s.v[3][c]);
-                        h1[c] = s.v[1][c] + timesI(s.v[2][c]);
-                    } else if (mu == 1) {
-                        h0[c] = s.v[0][c] + s.v[3][c];
-                        h1[c] = s.v[1][c] - s.v[2][c];
-                    } else if (mu == 2) {
-                        h0[c] = s.v[0][c] + timesI(s.v[2][c]);
-                        h1[c] = s.v[1][c] - timesI(s.v[3][c]);
-                    } else {
-                        h0[c] = s.v[0][c] - s.v[2][c];
-                        h1[c] = s.v[1][c] - s.v[3][c];
-                    }
-                    h0[c] = w * h0[c];
-                    h1[c] = w * h1[c];
-                }
-                mat_vec(U, h0, o0);
-                mat_vec(U, h1, o1);
-                acc_upper(acc, o0, o1);
-#pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    if (mu == 0) {
-                        acc.v[2][c] = acc.v[2][c] + timesMinusI(o1[c]);
-                        acc.v[3][c] = acc.v[3][c] + timesMinusI(o0[c]);
-                    } else if (mu == 1) {
-                        acc.v[2][c] = acc.v[2][c] - o1[c];
-                        acc.v[3][c] = acc.v[3][c] + o0[c];
-                    } else if (mu == 2) {
-                        acc.v[2][c] = acc.v[2][c] + timesMinusI(o0[c]);
-                        acc.v[3][c] = acc.v[3][c] + timesI(o1[c]);
-                    } else {
-                        acc.v[2][c] = acc.v[2][c] - o0[c];
-                        acc.v[3][c] = acc.v[3][c] - o1[c];
-                    }
-                }
-            }
-            // ---------------- backward hop: (1 + g_mu) U_mu(x-mu)^dag psi(x-mu)
-            {
-                int xx = x, yy = y, zz = z, tt = t;
-                A w = (A)(mu == 3 ? P.wt : P.ws);
-                if (mu == 0) xx = (x == 0) ? ns - 1 : x - 1;
-                if (mu == 1) yy = (y == 0) ? ns - 1 : y - 1;
-                if (mu == 2) zz = (z == 0) ? ns - 1 : z - 1;
-                if (mu == 3) {
-                    tt = (t == 0) ? nt - 1 : t - 1;
-                    if (t == 0) w *= (A)P.bct;
-                }
-                long nb = lex_index(xx, yy, zz, tt, ns) >> 1;
-                Spin<A> s;
-                load_spinor<SP, O32>(in, P.in_nrm, Vh, R, nb, r, s);
-                Cx<A> U[9];
-                load_link<GP, A, O32>(g, mu, opar, Vh, nb, U);
-                Cx<A> h0[3], h1[3], o0[3], o1[3];
-#pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    if (mu == 0) {
-                        h0[c] = s.v[0][c] - timesI(s.v[3][c]);
-                        h1[c] = s.v[1][c] - timesI(s.v[2][c]);
-                    } else if (mu == 1) {
-                        h0[c] = s.v[0][c] - s.v[3][c];
-                        h1[c] = s.v[1][c] + s.v[2][c];
-                    } else if (mu == 2) {
-                        h0[c] = s.v[0][c] - timesI(s.v[2][c]);
-                        h1[c] = s.v[1][c] + timesI(s.v[3][c]);
-                    } else {
-                        h0[c] = s.v[0][c] + s.v[2][c];
-                        h1[c] = s.v[1][c] + s.v[3][c];
-                    }
-                    h0[c] = w * h0[c];
-                    h1[c] = w * h1[c];
-                }
-                mat_dag_vec(U, h0, o0);
-                mat_dag_vec(U, h1, o1);
-                acc_upper(acc, o0, o1);
-#pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    if (mu == 0) {
-                        acc.v[2][c] = acc.v[2][c] + timesI(o1[c]);
-                        acc.v[3][c] = acc.v[3][c] + timesI(o0[c]);
-                    } else if (mu == 1) {
-                        acc.v[2][c] = acc.v[2][c] + o1[c];
-                        acc.v[3][c] = acc.v[3][c] - o0[c];
-                    } else if (mu == 2) {
-                        acc.v[2][c] = acc.v[2][c] + timesI(o0[c]);
-                        acc.v[3][c] = acc.v[3][c] + timesMinusI(o1[c]);
-                    } else {
-                        acc.v[2][c] = acc.v[2][c] + o0[c];
-                        acc.v[3][c] = acc.v[3][c] + o1[c];
-                    }
-                }
-            }
-        }
-    }
+    hop_rolled<O32>(P, i, r, x, y, z, t, acc);
 
     if (P.g5d) {
 #pragma unroll
@@ -453,27 +337,15 @@ double dslash_bytes(long Vh, int R, int gbytes, int cbytes, int sbytes, bool has
     return (double)Vh * (site + R * per_rhs);
 }
 
-template <class SP, class GP, class CP, bool O32, bool ROLL>
+template <class SP, class GP, class CP, bool O32>
 void launch_modes(int mode, dim3 grid, dim3 block, hipStream_t st, const DslashArgs &a)
 {
     switch (mode) {
-    case M_PLAIN: hipLaunchKernelGGL((k_dslash<SP, GP, CP, M_PLAIN, O32, ROLL>), grid, block, 0, st, a); break;
-    case M_INV_AFTER: hipLaunchKernelGGL((k_dslash<SP, GP, CP, M_INV_AFTER, O32, ROLL>), grid, block, 0, st, a); break;
-    case M_INV_OF_SUM:
-        hipLaunchKernelGGL((k_dslash<SP, GP, CP, M_INV_OF_SUM, O32, ROLL>), grid, block, 0, st, a);
-        break;
-    default: hipLaunchKernelGGL((k_dslash<SP, GP, CP, M_CLOV_ADD, O32, ROLL>), grid, block, 0, st, a); break;
+    case M_PLAIN: hipLaunchKernelGGL((k_dslash<SP, GP, CP, M_PLAIN, O32>), grid, block, 0, st, a); break;
+    case M_INV_AFTER: hipLaunchKernelGGL((k_dslash<SP, GP, CP, M_INV_AFTER, O32>), grid, block, 0, st, a); break;
+    case M_INV_OF_SUM: hipLaunchKernelGGL((k_dslash<SP, GP, CP, M_INV_OF_SUM, O32>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_dslash<SP, GP, CP, M_CLOV_ADD, O32>), grid, block, 0, st, a); break;
     }
-}
-
-static bool f64_rolled()
-{
-    static int v = -1;
-    if (v < 0) {
-        const char *e = getenv("LAPH_F64_ROLLED");
-        v = (e && *e == '0') ? 0 : 1;
-    }
-    return v == 1;
 }
 
 template <class SP, class GP, class CP>
@@ -483,16 +355,11 @@ void launch_dslash(laph_ctx *c, int mode, const DslashArgs &a, hipStream_t st)
     dim3 grid(nblocks_for(n, 256)), block(256);
     hipEvent_t e0, e1;
     timing_begin(c, &e0, &e1);
-    // 32-bit lane offsets when every spinor plane (Vh R entries) stays below 4 GiB (the
-    // link and clover planes are smaller); FP64 hops rolled over the directions unless
-    // LAPH_F64_ROLLED=0
-    const bool o32 = std::is_same<SP, S64>::value && (unsigned long long)n * sizeof(double2) < (1ull << 32);
-    if (o32 && f64_rolled())
-        launch_modes<SP, GP, CP, true, true>(mode, grid, block, st, a);
-    else if (o32)
-        launch_modes<SP, GP, CP, true, false>(mode, grid, block, st, a);
-    else
-        launch_modes<SP, GP, CP, false, false>(mode, grid, block, st, a);
+    // 32-bit lane offsets: every spinor plane (Vh R entries) stays below 4 GiB (the link
+    // and clover planes are smaller); callers split larger batches
+    LAPH_CHECK((unsigned long long)n * sizeof(double2) < (1ull << 32), LAPH_EINVAL,
+               "%d FP64 fields of %ld sites exceed the hopping kernel's 32-bit offsets", a.R, a.Vh);
+    launch_modes<SP, GP, CP, true>(mode, grid, block, st, a);
     LAPH_HIP(hipGetLastError());
     bool has_x = a.x != nullptr && (mode != M_PLAIN || a.x);
     if (e0)

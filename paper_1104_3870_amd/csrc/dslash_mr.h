@@ -63,8 +63,10 @@ double dslash_mr_bytes(long Vh, int R, int sbytes, bool has_norm, int mode, bool
 
 // sites per block of the LDS-staged hopping kernel for (precision, R); S R <= 256 lanes
 int lds_tile_sites(laph_ctx *c, int prec, int R);
-// whether M_INV_AFTER_DAG / M_PLAIN_CG are available for R right-hand sides (LDS-staged
-// kernel in use, 32-bit record offsets) and the number of partial sums per right-hand side
-// they write
-bool lds_dag_ok(laph_ctx *c, int R);
+// largest power-of-two block R <= 32 whose records the kernel's 32-bit offsets reach on
+// this lattice in this precision (0: none)
+int lds_max_rhs(laph_ctx *c, int prec);
+// number of partial sums per right-hand side the fused epilogues write
 long lds_dag_blocks(laph_ctx *c, int prec, int R);
+// whether launches walk the sites in tiles through time (else checkerboard order)
+bool lds_walk_tiled(laph_ctx *c);

@@ -1,12 +1,9 @@
-// Multi-right-hand-side hopping kernels for the low-precision inner solves (FP32
+// Multi-right-hand-side hopping kernel for the low-precision inner solves (FP32
 // arithmetic, FP16 / BF16 / FP32 records).
 //
-// k_dslash_lds (the production kernel) stages a block's links and clover blocks in LDS
-// and gives every lane one (site, right-hand side); see its section below.  k_dslash_mr
-// (LAPH_MR_KERNEL=0) is the per-lane form: one lane works on NR right-hand sides of one
-// site, loading links stored as their first two rows (reconstruct-12: the third row of an
-// SU(3) matrix is conj(row0 x row1); 3 x 16-byte loads per link) and per-site clover
-// blocks (18 x 16-byte loads) itself.
+// k_dslash_lds stages a block's links (stored as their first two rows, reconstruct-12: the
+// third row of an SU(3) matrix is conj(row0 x row1)) and clover blocks in LDS and gives
+// every lane one (site, right-hand side); see its section below.
 #include <cstdlib>
 #include <string>
 #include <type_traits>
@@ -111,186 +108,12 @@ __device__ __forceinline__ void clover_site(const float4 *cl, long i, const Cx<f
     }
 }
 
-template <int MU, bool FWD, int NR>
-__device__ __forceinline__ void hop(const Cx<float> (&U)[9], float w, const Cx<float> (&s)[NR][4][3],
-                                    Cx<float> (&acc)[NR][4][3])
-{
-#pragma unroll
-    for (int q = 0; q < NR; q++) {
-        Cx<float> h0[3], h1[3], o0[3], o1[3];
-#pragma unroll
-        for (int c = 0; c < 3; c++) {
-            if (MU == 0) {
-                h0[c] = FWD ? s[q][0][c] + timesI(s[q][3][c]) : s[q][0][c] - timesI(s[q][3][c]);
-                h1[c] = FWD ? s[q][1][c] + timesI(s[q][2][c]) : s[q][1][c] - timesI(s[q][2][c]);
-            } else if (MU == 1) {
-                h0[c] = FWD ? s[q][0][c] + s[q][3][c] : s[q][0][c] - s[q][3][c];
-                h1[c] = FWD ? s[q][1][c] - s[q][2][c] : s[q][1][c] + s[q][2][c];
-            } else if (MU == 2) {
-                h0[c] = FWD ? s[q][0][c] + timesI(s[q][2][c]) : s[q][0][c] - timesI(s[q][2][c]);
-                h1[c] = FWD ? s[q][1][c] - timesI(s[q][3][c]) : s[q][1][c] + timesI(s[q][3][c]);
-            } else {
-                h0[c] = FWD ? s[q][0][c] - s[q][2][c] : s[q][0][c] + s[q][2][c];
-                h1[c] = FWD ? s[q][1][c] - s[q][3][c] : s[q][1][c] + s[q][3][c];
-            }
-            h0[c] = w * h0[c];
-            h1[c] = w * h1[c];
-        }
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-            if (FWD) {
-                o0[a] = U[a * 3] * h0[0] + U[a * 3 + 1] * h0[1] + U[a * 3 + 2] * h0[2];
-                o1[a] = U[a * 3] * h1[0] + U[a * 3 + 1] * h1[1] + U[a * 3 + 2] * h1[2];
-            } else {
-                o0[a] = conjmul(U[a], h0[0]) + conjmul(U[3 + a], h0[1]) + conjmul(U[6 + a], h0[2]);
-                o1[a] = conjmul(U[a], h1[0]) + conjmul(U[3 + a], h1[1]) + conjmul(U[6 + a], h1[2]);
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < 3; c++) {
-            acc[q][0][c] = acc[q][0][c] + o0[c];
-            acc[q][1][c] = acc[q][1][c] + o1[c];
-            if (MU == 0) {
-                acc[q][2][c] = acc[q][2][c] + (FWD ? timesMinusI(o1[c]) : timesI(o1[c]));
-                acc[q][3][c] = acc[q][3][c] + (FWD ? timesMinusI(o0[c]) : timesI(o0[c]));
-            } else if (MU == 1) {
-                acc[q][2][c] = FWD ? acc[q][2][c] - o1[c] : acc[q][2][c] + o1[c];
-                acc[q][3][c] = FWD ? acc[q][3][c] + o0[c] : acc[q][3][c] - o0[c];
-            } else if (MU == 2) {
-                acc[q][2][c] = acc[q][2][c] + (FWD ? timesMinusI(o0[c]) : timesI(o0[c]));
-                acc[q][3][c] = acc[q][3][c] + (FWD ? timesI(o1[c]) : timesMinusI(o1[c]));
-            } else {
-                acc[q][2][c] = FWD ? acc[q][2][c] - o0[c] : acc[q][2][c] + o0[c];
-                acc[q][3][c] = FWD ? acc[q][3][c] - o1[c] : acc[q][3][c] + o1[c];
-            }
-        }
-    }
-}
-
-template <int MU, int NR, class SP>
-__device__ __forceinline__ void do_dir(const MrArgs &P, const float4 *lk, int x, int y, int z, int t, long i, int r0,
-                                       Cx<float> (&acc)[NR][4][3])
-{
-    const int ns = P.ns, nt = P.nt, par = P.par, opar = par ^ 1;
-    const long Vh = P.Vh;
-    const auto *in = (const typename SP::E *)P.in;
-    // forward
-    {
-        int xx = x, yy = y, zz = z, tt = t;
-        float w = MU == 3 ? (float)P.wt : (float)P.ws;
-        if (MU == 0) xx = (x + 1 == ns) ? 0 : x + 1;
-        if (MU == 1) yy = (y + 1 == ns) ? 0 : y + 1;
-        if (MU == 2) zz = (z + 1 == ns) ? 0 : z + 1;
-        if (MU == 3) {
-            tt = (t + 1 == nt) ? 0 : t + 1;
-            if (t + 1 == nt) w *= (float)P.bct;
-        }
-        long nb = lex_index(xx, yy, zz, tt, ns) >> 1;
-        Cx<float> U[9];
-        load_link12(lk, (long)(MU * 2 + par) * Vh + i, U);
-        Cx<float> s[NR][4][3];
-        load_site<SP, NR>(in, P.in_nrm, Vh, P.R, nb, r0, s);
-        hop<MU, true, NR>(U, w, s, acc);
-    }
-    // backward
-    {
-        int xx = x, yy = y, zz = z, tt = t;
-        float w = MU == 3 ? (float)P.wt : (float)P.ws;
-        if (MU == 0) xx = (x == 0) ? ns - 1 : x - 1;
-        if (MU == 1) yy = (y == 0) ? ns - 1 : y - 1;
-        if (MU == 2) zz = (z == 0) ? ns - 1 : z - 1;
-        if (MU == 3) {
-            tt = (t == 0) ? nt - 1 : t - 1;
-            if (t == 0) w *= (float)P.bct;
-        }
-        long nb = lex_index(xx, yy, zz, tt, ns) >> 1;
-        Cx<float> U[9];
-        load_link12(lk, (long)(MU * 2 + opar) * Vh + nb, U);
-        Cx<float> s[NR][4][3];
-        load_site<SP, NR>(in, P.in_nrm, Vh, P.R, nb, r0, s);
-        hop<MU, false, NR>(U, w, s, acc);
-    }
-}
-
-#ifndef LAPH_MR_WAVES
-#define LAPH_MR_WAVES 0
-#endif
-#if LAPH_MR_WAVES > 0
-#define LAPH_MR_ATTR __attribute__((amdgpu_waves_per_eu(LAPH_MR_WAVES)))
-#else
-#define LAPH_MR_ATTR
-#endif
 // the LDS-staged kernel runs at least 3 waves per SIMD (at most 168 VGPRs); no
 // instantiation spills, and the FP16 ones of the CG iteration need 90-95 VGPRs (5 waves)
 #ifndef LAPH_LDS_WAVES
 #define LAPH_LDS_WAVES 3
 #endif
 #define LAPH_LDS_ATTR __attribute__((amdgpu_waves_per_eu(LAPH_LDS_WAVES)))
-
-template <class SP, int NR, int MODE>
-__global__ __launch_bounds__(256) LAPH_MR_ATTR void k_dslash_mr(const MrArgs P)
-{
-    unsigned b = xcd_block(blockIdx.x, gridDim.x);
-    long tid = (long)b * blockDim.x + threadIdx.x;
-    const int G = P.R / NR;
-    const long Vh = P.Vh;
-    if (tid >= Vh * G) return;
-    long i = tid / G;
-    int r0 = (int)(tid - i * G) * NR;
-    int x, y, z, t;
-    cb_coords(i, P.par, P.ns, x, y, z, t);
-    const float4 *lk = (const float4 *)P.links;
-    Cx<float> acc[NR][4][3];
-#pragma unroll
-    for (int q = 0; q < NR; q++)
-#pragma unroll
-        for (int a = 0; a < 4; a++)
-#pragma unroll
-            for (int c = 0; c < 3; c++) acc[q][a][c] = {0.0f, 0.0f};
-    do_dir<0, NR, SP>(P, lk, x, y, z, t, i, r0, acc);
-    do_dir<1, NR, SP>(P, lk, x, y, z, t, i, r0, acc);
-    do_dir<2, NR, SP>(P, lk, x, y, z, t, i, r0, acc);
-    do_dir<3, NR, SP>(P, lk, x, y, z, t, i, r0, acc);
-    if (P.g5d) {
-#pragma unroll
-        for (int q = 0; q < NR; q++)
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                acc[q][2][c] = cneg(acc[q][2][c]);
-                acc[q][3][c] = cneg(acc[q][3][c]);
-            }
-    }
-    const float ca = (float)P.a, cc = (float)P.c;
-    const float4 *cl = (const float4 *)P.clov;
-    Cx<float> res[NR][4][3];
-    if constexpr (MODE == M_INV_AFTER) {
-        clover_site<NR>(cl, i, acc, res);
-#pragma unroll
-        for (int q = 0; q < NR; q++)
-#pragma unroll
-            for (int a = 0; a < 4; a++)
-#pragma unroll
-                for (int c = 0; c < 3; c++) res[q][a][c] = cc * res[q][a][c];
-    } else {
-#pragma unroll
-        for (int q = 0; q < NR; q++)
-#pragma unroll
-            for (int a = 0; a < 4; a++)
-#pragma unroll
-                for (int c = 0; c < 3; c++) res[q][a][c] = cc * acc[q][a][c];
-    }
-    if (P.x) {
-        Cx<float> xv[NR][4][3];
-        load_site<SP, NR>((const typename SP::E *)P.x, P.x_nrm, Vh, P.R, i, r0, xv);
-#pragma unroll
-        for (int q = 0; q < NR; q++)
-#pragma unroll
-            for (int a = 0; a < 4; a++)
-#pragma unroll
-                for (int c = 0; c < 3; c++) res[q][a][c] = res[q][a][c] + ca * xv[q][a][c];
-    }
-    store_site<SP, NR>((typename SP::E *)P.out, P.out_nrm, Vh, P.R, i, r0, res);
-}
 
 // ------------------------------------------------------------ LDS-staged variant
 // One block holds S sites x R right-hand sides, one lane per (site, right-hand side).  The
@@ -908,19 +731,6 @@ __global__ void k_links12(const double2 *__restrict__ g64, float4 *__restrict__ 
 
 }  // namespace
 
-// right-hand sides per lane: 1 (measured best with the site-major layout), or LAPH_MR_NR
-static int pick_nr(int R)
-{
-    static int env = -1;
-    if (env < 0) {
-        const char *e = getenv("LAPH_MR_NR");
-        env = e ? atoi(e) : 0;
-    }
-    if (env == 1 || env == 2 || env == 4)
-        if (R % env == 0) return env;
-    return 1;
-}
-
 double dslash_mr_bytes(long Vh, int R, int sbytes, bool has_norm, int mode, bool has_x)
 {
     double site = 8.0 * 48;  // reconstruct-12 FP32 links
@@ -932,16 +742,17 @@ double dslash_mr_bytes(long Vh, int R, int sbytes, bool has_norm, int mode, bool
     return (double)Vh * (site + R * per_rhs);
 }
 
-
 template <class SP>
 constexpr int prec_id()
 {
     return std::is_same<SP, S16>::value ? LAPH_PREC_F16 : std::is_same<SP, SB16>::value ? LAPH_PREC_BF16 : LAPH_PREC_F32;
 }
 
-// sites per block of the LDS-staged kernel: the tuned value, else 256 / R lanes per block
+// sites per block of the LDS-staged kernel: the caller's override, the tuned value, else
+// 256 / R lanes per block
 int lds_tile_sites(laph_ctx *c, int prec, int R)
 {
+    if (c->tile_override > 0) return c->tile_override;
     auto it = c->lds_tile.find({prec, R});
     if (it != c->lds_tile.end()) return it->second;
     return R >= 4 ? 256 / R : 64;
@@ -953,26 +764,22 @@ constexpr const char *prec_name()
     return std::is_same<SP, S16>::value ? "f16" : std::is_same<SP, SB16>::value ? "bf16" : "f32";
 }
 
-// hopping kernel: the LDS-staged variant unless LAPH_MR_KERNEL=0 selects the per-lane one
-static bool use_lds_kernel()
-{
-    static int v = -1;
-    if (v < 0) {
-        const char *e = getenv("LAPH_MR_KERNEL");
-        v = (e && *e == '0') ? 0 : 1;
-    }
-    return v == 1;
-}
+static long rec_bytes(int prec) { return prec == LAPH_PREC_F32 ? 96 : 48; }
 
-// the LDS-staged kernel indexes sites in 32 bits, reads neighbour records through 32-bit
-// byte offsets and divides site indices by ns and ns / 2 with multiply-high reciprocals
-static bool lds_fits(long Vh, int R, long rec_bytes, int ns = 2)
+// the kernel indexes sites in 32 bits, reads neighbour records through 32-bit byte
+// offsets and divides site indices by ns and ns / 2 with multiply-high reciprocals
+static bool lds_fits(long Vh, int R, long rec, int ns)
 {
-    return Vh * R * 12 < (1L << 31) && Vh * R * rec_bytes < (1L << 32) &&
+    return Vh * R * 12 < (1L << 31) && Vh * R * rec < (1L << 32) &&
            (unsigned long long)Vh * (unsigned long long)ns < (1ull << 32);
 }
 
-bool lds_dag_ok(laph_ctx *c, int R) { return use_lds_kernel() && lds_fits(c->g.Vh, R, 96, c->g.ns); }
+int lds_max_rhs(laph_ctx *c, int prec)
+{
+    for (int R = 32; R >= 1; R /= 2)
+        if (lds_fits(c->g.Vh, R, rec_bytes(prec), c->g.ns)) return R;
+    return 0;
+}
 
 long lds_dag_blocks(laph_ctx *c, int prec, int R)
 {
@@ -1006,96 +813,74 @@ static unsigned umulhi_magic(long d)
 // every index n the kernel divides by d is below nmax: the reciprocal is exact when
 static bool magic_ok(long d, long nmax) { return (unsigned long long)nmax * (unsigned long long)d < (1ull << 32); }
 
+bool lds_walk_tiled(laph_ctx *c)
+{
+    const int ns = c->g.ns, nt = c->g.nt;
+    const long Vh = c->g.Vh;
+    const int by = walk_tile(ns, 0), bz = walk_tile(ns, 1);
+    const long A = (long)(ns / 2) * by * bz;
+    return c->walk_mode == 0 && by > 0 && bz > 0 && magic_ok(A, Vh) && magic_ok(nt, Vh) && magic_ok(ns, Vh);
+}
+
 template <class SP>
 void launch_dslash_mr(laph_ctx *c, int mode, const MrArgs &a, hipStream_t st)
 {
-    if (use_lds_kernel() && lds_fits(a.Vh, a.R, sizeof(Spin12<SP>), a.ns)) {
-        const int S = lds_tile_sites(c, prec_id<SP>(), a.R);
-        MrArgs b = a;
-        const int by = walk_tile(a.ns, 0), bz = walk_tile(a.ns, 1);
-        const long A = (long)(a.ns / 2) * by * bz;
-        // the walk's divisors (tile slice, nt, tile extent, tiles per row) need exact
-        // reciprocals for every position below Vh; otherwise checkerboard order
-        if (by > 0 && bz > 0 && magic_ok(A, a.Vh) && magic_ok(a.nt, a.Vh) && magic_ok(a.ns, a.Vh)) {
-            b.wby = by;
-            b.wbz = bz;
-        } else {
-            b.wby = b.wbz = 0;
-        }
-        b.m_nsh = umulhi_magic(a.ns / 2);
-        b.m_ns = umulhi_magic(a.ns);
-        b.m_nt = umulhi_magic(a.nt);
-        b.m_by = b.wby ? umulhi_magic(b.wby) : 0;
-        b.m_nty = b.wby ? umulhi_magic(a.ns / b.wby) : 0;
-        b.m_A = b.wby ? umulhi_magic(A) : 0;
-        b.unit = 1.0f;
-        b.tgauge = a.tgauge;
-        dim3 grid(nblocks_for(a.Vh, S)), block(S * a.R);
-        hipEvent_t e0, e1;
-        timing_begin(c, &e0, &e1);
-        const bool hx = a.x != nullptr;
-        LAPH_CHECK(hx || (mode != M_INV_AFTER_DAG && mode != M_PLAIN_CG), LAPH_EINVAL,
-                   "fused hopping epilogues need the own-site operand");
-        if (mode == M_INV_AFTER_DAG)
-            hipLaunchKernelGGL((k_dslash_lds<SP, M_INV_AFTER_DAG, true>), grid, block, lds_bytes(S), st, b);
-        else if (mode == M_PLAIN_CG)
-            hipLaunchKernelGGL((k_dslash_lds<SP, M_PLAIN_CG, true>), grid, block, lds_bytes(S), st, b);
-        else if (mode == M_INV_AFTER && hx)
-            hipLaunchKernelGGL((k_dslash_lds<SP, M_INV_AFTER, true>), grid, block, lds_bytes(S), st, b);
-        else if (mode == M_INV_AFTER)
-            hipLaunchKernelGGL((k_dslash_lds<SP, M_INV_AFTER, false>), grid, block, lds_bytes(S), st, b);
-        else if (hx)
-            hipLaunchKernelGGL((k_dslash_lds<SP, M_PLAIN, true>), grid, block, lds_bytes(S), st, b);
-        else
-            hipLaunchKernelGGL((k_dslash_lds<SP, M_PLAIN, false>), grid, block, lds_bytes(S), st, b);
-        LAPH_HIP(hipGetLastError());
-        if (e0)
-            timing_end(c, e0, e1, dslash_mr_bytes(a.Vh, a.R, SP::bytes, SP::kNorm, mode, a.x != nullptr),
-                   timing_label("dslash_lds", prec_name<SP>(), mode, a.R));
-        return;
+    LAPH_CHECK(lds_fits(a.Vh, a.R, sizeof(Spin12<SP>), a.ns), LAPH_EINVAL,
+               "%d right-hand sides of %ld sites exceed the 32-bit indexing of the multi-RHS hopping kernel", a.R,
+               a.Vh);
+    LAPH_CHECK(a.R >= 1 && a.R <= 32 && (a.R & (a.R - 1)) == 0, LAPH_EINVAL, "block of %d right-hand sides", a.R);
+    const int S = lds_tile_sites(c, prec_id<SP>(), a.R);
+    LAPH_CHECK(S >= 1 && S * a.R <= 256, LAPH_EINVAL, "tile of %d sites x %d right-hand sides", S, a.R);
+    MrArgs b = a;
+    // the tiled walk's divisors (tile slice, nt, tile extent, tiles per row) need exact
+    // reciprocals for every position below Vh; otherwise checkerboard order
+    if (lds_walk_tiled(c)) {
+        b.wby = walk_tile(a.ns, 0);
+        b.wbz = walk_tile(a.ns, 1);
+    } else {
+        b.wby = b.wbz = 0;
     }
-    LAPH_CHECK(mode != M_INV_AFTER_DAG && mode != M_PLAIN_CG, LAPH_EINVAL,
-               "fused hopping epilogues need the LDS-staged kernel");
-    int NR = pick_nr(a.R);
-    long n = a.Vh * (a.R / NR);
-    dim3 grid(nblocks_for(n, 256)), block(256);
+    const long A = (long)(a.ns / 2) * b.wby * b.wbz;
+    b.m_nsh = umulhi_magic(a.ns / 2);
+    b.m_ns = umulhi_magic(a.ns);
+    b.m_nt = umulhi_magic(a.nt);
+    b.m_by = b.wby ? umulhi_magic(b.wby) : 0;
+    b.m_nty = b.wby ? umulhi_magic(a.ns / b.wby) : 0;
+    b.m_A = b.wby ? umulhi_magic(A) : 0;
+    b.unit = 1.0f;
+    b.tgauge = a.tgauge;
+    dim3 grid(nblocks_for(a.Vh, S)), block(S * a.R);
     hipEvent_t e0, e1;
     timing_begin(c, &e0, &e1);
-#define LAPH_MR(NRV)                                                                                    \
-    if (mode == M_INV_AFTER)                                                                            \
-        hipLaunchKernelGGL((k_dslash_mr<SP, NRV, M_INV_AFTER>), grid, block, 0, st, a);                \
-    else                                                                                                \
-        hipLaunchKernelGGL((k_dslash_mr<SP, NRV, M_PLAIN>), grid, block, 0, st, a);
-    if (NR == 4) {
-        LAPH_MR(4)
-    } else if (NR == 2) {
-        LAPH_MR(2)
-    } else {
-        LAPH_MR(1)
-    }
-#undef LAPH_MR
+    const bool hx = a.x != nullptr;
+    LAPH_CHECK(hx || (mode != M_INV_AFTER_DAG && mode != M_PLAIN_CG), LAPH_EINVAL,
+               "fused hopping epilogues need the own-site operand");
+    if (mode == M_INV_AFTER_DAG)
+        hipLaunchKernelGGL((k_dslash_lds<SP, M_INV_AFTER_DAG, true>), grid, block, lds_bytes(S), st, b);
+    else if (mode == M_PLAIN_CG)
+        hipLaunchKernelGGL((k_dslash_lds<SP, M_PLAIN_CG, true>), grid, block, lds_bytes(S), st, b);
+    else if (mode == M_INV_AFTER && hx)
+        hipLaunchKernelGGL((k_dslash_lds<SP, M_INV_AFTER, true>), grid, block, lds_bytes(S), st, b);
+    else if (mode == M_INV_AFTER)
+        hipLaunchKernelGGL((k_dslash_lds<SP, M_INV_AFTER, false>), grid, block, lds_bytes(S), st, b);
+    else if (hx)
+        hipLaunchKernelGGL((k_dslash_lds<SP, M_PLAIN, true>), grid, block, lds_bytes(S), st, b);
+    else
+        hipLaunchKernelGGL((k_dslash_lds<SP, M_PLAIN, false>), grid, block, lds_bytes(S), st, b);
     LAPH_HIP(hipGetLastError());
     if (e0)
         timing_end(c, e0, e1, dslash_mr_bytes(a.Vh, a.R, SP::bytes, SP::kNorm, mode, a.x != nullptr),
-               timing_label("dslash_mr", prec_name<SP>(), mode, a.R));
+                   timing_label("dslash_lds", prec_name<SP>(), mode, a.R));
 }
 
 template <class SP>
 void launch_clover_mr(laph_ctx *c, const void *cl, const void *x, const float *x_nrm, void *out, float *out_nrm,
                       long Vh, int R, int g5_in, hipStream_t st)
 {
-    int NR = pick_nr(R);
-    long n = Vh * (R / NR);
-    dim3 grid(nblocks_for(n, 256)), block(256);
-    const float4 *clp = (const float4 *)cl;
-    const auto *xp = (const typename SP::E *)x;
-    auto *op = (typename SP::E *)out;
-    if (NR == 4)
-        hipLaunchKernelGGL((k_clover_mr<SP, 4>), grid, block, 0, st, clp, xp, x_nrm, op, out_nrm, Vh, R, g5_in);
-    else if (NR == 2)
-        hipLaunchKernelGGL((k_clover_mr<SP, 2>), grid, block, 0, st, clp, xp, x_nrm, op, out_nrm, Vh, R, g5_in);
-    else
-        hipLaunchKernelGGL((k_clover_mr<SP, 1>), grid, block, 0, st, clp, xp, x_nrm, op, out_nrm, Vh, R, g5_in);
+    (void)c;
+    long n = Vh * R;
+    hipLaunchKernelGGL((k_clover_mr<SP, 1>), dim3(nblocks_for(n, 256)), dim3(256), 0, st, (const float4 *)cl,
+                       (const typename SP::E *)x, x_nrm, (typename SP::E *)out, out_nrm, Vh, R, g5_in);
     LAPH_HIP(hipGetLastError());
 }
 

@@ -523,6 +523,21 @@ struct Bufs {
 
 }  // namespace
 
+// scratch of laph_eigvecs (the buffers below, in the same order)
+size_t eig_scratch_bytes(const Geom &g, int m, int nv)
+{
+    const size_t nt = g.nt, n = 3 * g.V3, V = g.V;
+    const size_t nchunk = (n + GS_CH - 1) / GS_CH, rb = (n + 255) / 256, ps = m + 1;
+    size_t s = 0;
+    for (size_t b : {V * 36 * 16, V * 36 * 16 /* stout.tmp */, 27 * V * 16, nt * (m + 1) * n * 16, nt * m * n * 16,
+                     nt * n * 16, nt * n * 16, nt * n * 16, nt * ps * 16, nt * nchunk * ps * 16, nt * m * m * 8,
+                     nt * m * m * 8, nt * m * m * 8, nt * m * 8, nt * m * 8, nt * m * 8, nt * 8, nt * 8, nt * 8,
+                     nt * rb * 8, nt * 8, nt * 8, nt * rb * 16, nt * 4, nt * 4, nt * 4, nt * 4, nt * 4, nt * m * 4,
+                     nt * m * 4, nt * (size_t)nv * 4})
+        s += ws_align(b);
+    return s;
+}
+
 extern "C" int laph_eigvecs(laph_ctx_t c, const double *U, const laph_stout *stout, const laph_lanczos *lz, int nv,
                             double *evals, double *evecs, laph_eig_stats *stats)
 {

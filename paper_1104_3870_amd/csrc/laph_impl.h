@@ -128,6 +128,10 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nblocks)
 }
 
 // ---------------------------------------------------------------- buffers
+// Every device buffer of the library is a piece of the caller's workspace
+// (laph_set_workspace): named scratch buffers of one call are taken from its bottom and
+// released when the call returns; the cached operators of a gauge field live at its top
+// until another field, a workspace change or a lack of room evicts them.
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
@@ -136,16 +140,17 @@ struct DevBuf {
 // ---------------------------------------------------------------- gauge caches
 struct DiracCache {
     const double *U = nullptr;  // caller pointer the cache was built from
+    uint64_t fp = 0;            // fingerprint of that field's contents
     laph_dirac prm{};
     bool valid = false;
+    DevBuf unit;    // the cache's piece of the workspace, carved into the fields below
     DevBuf g64;     // even-odd links FP64 (double2)
-    DevBuf g32;     // even-odd links FP32 (float2), built on demand
     DevBuf clov;    // clover FP64 packed
     DevBuf clinv;   // clover inverse FP64 packed
-    DevBuf clinv32; // clover inverse FP32 packed (unused by the multi-RHS path)
     DevBuf lk12;    // reconstruct-12 FP32 links, per-site AoS (low-precision operator)
     DevBuf claos;   // FP32 clover inverse, per-site AoS (low-precision operator)
-    bool f32 = false;  // lk12 / claos are current
+    bool has_f32 = false;  // the unit holds lk12 / claos
+    bool f32 = false;      // lk12 / claos are current
     // temporal gauge (the solver's cache): the operator is built from U' = G U G^dag with
     // unit time links except on the last slice; gU holds U', gG the rotations G(x)
     bool tgauge = false;
@@ -163,11 +168,23 @@ struct laph_ctx {
     // temporal-gauge rotations the running solve folds into its layout conversions: G on
     // the source (null where the source is rotated beforehand) and G^dag on the solution
     const double *tg_in = nullptr, *tg_out = nullptr;
-    std::map<std::string, DevBuf> bufs;  // named scratch buffers, grown on demand
+    std::map<std::string, DevBuf> bufs;  // named scratch buffers of the running call
+    // caller workspace: scratch [0, ws_lo), the cache unit [ws_bytes - ws_hi, ws_bytes).
+    // At most one cached operator is held; the running call pins the one it prepared, and
+    // an unpinned one is evicted when scratch needs its room.
+    char *ws = nullptr;
+    size_t ws_bytes = 0, ws_lo = 0, ws_hi = 0;
+    DiracCache *ws_unit = nullptr;
+    bool ws_pinned = false;
     // autotuning: LDS tile (sites per block) per (precision, R) and the chosen R per
     // precision (0: not tuned)
     std::map<std::pair<int, int>, int> lds_tile;
     std::map<int, int> tuned_R;
+    // launch overrides of the multi-RHS hopping kernel, set only for the duration of a
+    // laph_hop_apply call: walk_mode 1 visits sites in checkerboard order instead of the
+    // tiled walk, tile_override > 0 fixes the sites per block
+    int walk_mode = 0;
+    int tile_override = 0;
     hipStream_t cap_stream = nullptr;  // capture stream for HIP graphs (default priority)
     // pinned two-slot readback of the per-RHS Krylov scalars and the events marking each
     // slot's copy (the CG loop reads the previous iteration's slot without draining the queue)
@@ -187,9 +204,25 @@ struct laph_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
 };
 
-void *ctx_buf(laph_ctx *c, DevBuf &b, size_t bytes);  // grow-only
-inline void *ctx_named(laph_ctx *c, const std::string &name, size_t bytes) { return ctx_buf(c, c->bufs[name], bytes); }
-void ctx_free(DevBuf &b);
+// named scratch buffer of the running call (grow-only within the call; released when the
+// call returns); LAPH_ENOMEM when the workspace has no room
+void *ctx_named(laph_ctx *c, const std::string &name, size_t bytes);
+// release every scratch buffer (end of an ABI call)
+void scratch_reset(laph_ctx *c);
+// give cache dc a unit of at least `bytes` at the top of the workspace (the other cache is
+// evicted) and pin it for the running call; the unit's contents are undefined afterwards
+// when it moved
+void cache_unit(laph_ctx *c, DiracCache &dc, size_t bytes);
+// drop the cache unit (its fields become invalid)
+void cache_release_all(laph_ctx *c);
+// bytes of a Dirac cache unit (FP64 operator; with f32 the low-precision operator; with
+// tgauge also U' and G) and the layout of its fields
+size_t cache_unit_bytes(const Geom &g, bool tgauge, bool f32);
+void cache_carve(laph_ctx *c, DiracCache &dc, bool tgauge, bool f32);
+// 64-bit fingerprint of a gauge field's contents (device pass over all links)
+uint64_t gauge_fingerprint(laph_ctx *c, const double *U);
+inline size_t ws_align(size_t n) { return (n + 255) & ~size_t(255); }
+
 
 // ---------------------------------------------------------------- internal API
 // layout.hip
@@ -231,9 +264,15 @@ const char *timing_label(const char *kernel, const char *prec, int mode, int R);
 // launch helper
 inline unsigned nblocks_for(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+struct ScratchScope {
+    laph_ctx *c;
+    ~ScratchScope() { scratch_reset(c); }
+};
+
 #define LAPH_API_BEGIN(ctx)                                                                  \
     try {                                                                                    \
         if (!(ctx)) return LAPH_EINVAL;                                                      \
+        ScratchScope scratch_scope_{ctx};                                                    \
         LAPH_HIP(hipSetDevice((ctx)->device));
 
 #define LAPH_API_END(ctx)                                                                    \

@@ -14,21 +14,21 @@ struct laph_ptnet {
     std::vector<size_t> woff;  // offset (complex elements) of each layer's weights
     size_t nw = 0;             // total complex weights
     int cmax = 1;              // widest layer
-    DevBuf w32;                // FP32 master weights (float2)
-    DevBuf wbf;                // BF16 working copy (uint32: bf16(re) | bf16(im) << 16)
-    DevBuf wadj;               // adjoint weights of one layer (uint32, BF16 pairs)
-    DevBuf m1, m2;             // Adam moments (float2)
-    DevBuf grad;               // weight gradients dL/dW^* (float2)
-    DevBuf gpart;              // per-block partial weight gradients (float2)
+    // persistent state in host memory (a few KB): FP32 master weights and Adam moments,
+    // (re, im) interleaved
+    std::vector<float> w32, m1, m2;
     long step = 0;
-    DevBuf links;              // FP32 links of the field of the current call
-    const float2 *act0 = nullptr;  // input of the last forward pass that kept activations
-    std::vector<DevBuf> acts;      // inputs of layers 1.. kept for the backward pass
-    DevBuf tmp[2];             // ping-pong activations / gradients
+    // device copies for the running call, in the context's scratch (ptnet_prepare)
+    const float2 *links = nullptr;   // FP32 links of the call's field
+    const uint32_t *wbf = nullptr;   // BF16 working copy (bf16(re) | bf16(im) << 16)
+    float2 *grad = nullptr;          // weight gradients dL/dW^*
+    const float2 *act0 = nullptr;    // input of the last forward pass that kept activations
+    std::vector<const float2 *> acts;  // inputs of layers 1.. kept for the backward pass
+    std::vector<uint32_t> wbf_h;     // staging of the BF16 copy (alive while its upload runs)
 };
 
-// FP32 links of U for the net (converted on every call)
-void ptnet_links(laph_ctx *c, laph_ptnet *net, const double *U);
+// FP32 links of U and the BF16 weights in the context's scratch for this call
+void ptnet_prepare(laph_ctx *c, laph_ptnet *net, const double *U);
 // out = N(in) for nrhs fields in the net layout (1 channel in and out).  With keep != 0 the
 // layer inputs are kept for ptnet_backward.
 void ptnet_forward(laph_ctx *c, laph_ptnet *net, float bct, const float2 *in, float2 *out, int nrhs, int keep);
@@ -42,3 +42,5 @@ void net_to_eo(laph_ctx *c, const float2 *full, int par, double2 *half);
 // odd part of N(gamma_4 eta) for R canonical FP64 sources, as the FP64 even-odd batch
 // xo[(k*Vh + i)*R + r] (initial guess of the odd-site system: x = K^-1 gamma_4 eta)
 void ptnet_initial_guess(laph_ctx *c, laph_ptnet *net, float bct, const double *eta, int R, double2 *xo);
+// workspace scratch of the network's calls (see ptnet.hip)
+size_t ptnet_scratch_bytes(const Geom &g, const laph_ptnet *net, int nrhs, int what);

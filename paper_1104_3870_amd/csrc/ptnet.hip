@@ -397,8 +397,8 @@ void launch_wgrad_t(laph_ctx *c, laph_ptnet *net, const float2 *act, const float
     chunk = (chunk + kPtBS - 1) / kPtBS * kPtBS;
     int nblk = (int)((n + chunk - 1) / chunk);
     long nwl = (long)CO * cin * 144;
-    float2 *gpart = (float2 *)ctx_buf(c, net->gpart, sizeof(float2) * nwl * nblk);
-    hipLaunchKernelGGL(k_pt_wgrad<CO>, dim3(nblk, cin * 9), dim3(kPtBS), 0, c->stream, (const float2 *)net->links.p,
+    float2 *gpart = (float2 *)ctx_named(c, "net.gpart", sizeof(float2) * nwl * nblk);
+    hipLaunchKernelGGL(k_pt_wgrad<CO>, dim3(nblk, cin * 9), dim3(kPtBS), 0, c->stream, net->links,
                        act, g, gpart, cin, c->g.ns, c->g.nt, V, nrhs, bct, chunk);
     LAPH_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_pt_sum_parts, dim3(nblocks_for(nwl, 256)), dim3(256), 0, c->stream, (const float2 *)gpart,
@@ -427,15 +427,21 @@ void check_net(laph_ctx *c, laph_ptnet *net)
 }  // namespace
 
 // ---------------------------------------------------------------- internal API
-void ptnet_links(laph_ctx *c, laph_ptnet *net, const double *U)
+void ptnet_prepare(laph_ctx *c, laph_ptnet *net, const double *U)
 {
-    // rebuilt on every call: a caller may free a field and allocate the next one at the
-    // same address, so the pointer does not identify the field
+    // links rebuilt on every call: a caller may free a field and allocate the next one at
+    // the same address, so the pointer does not identify the field
     long V = c->g.V;
-    ctx_buf(c, net->links, sizeof(float2) * V * 36);
-    hipLaunchKernelGGL(k_pt_from64, dim3(nblocks_for(V * 36, 256)), dim3(256), 0, c->stream, (const double2 *)U,
-                       (float2 *)net->links.p, V * 36);
+    float2 *lk = (float2 *)ctx_named(c, "net.links", sizeof(float2) * V * 36);
+    hipLaunchKernelGGL(k_pt_from64, dim3(nblocks_for(V * 36, 256)), dim3(256), 0, c->stream, (const double2 *)U, lk,
+                       V * 36);
     LAPH_HIP(hipGetLastError());
+    net->links = lk;
+    net->wbf_h.resize(net->nw);
+    for (size_t i = 0; i < net->nw; i++) net->wbf_h[i] = pack_bf(net->w32[2 * i], net->w32[2 * i + 1]);
+    uint32_t *wbf = (uint32_t *)ctx_named(c, "net.wbf", sizeof(uint32_t) * net->nw);
+    LAPH_HIP(hipMemcpyAsync(wbf, net->wbf_h.data(), sizeof(uint32_t) * net->nw, hipMemcpyHostToDevice, c->stream));
+    net->wbf = wbf;
 }
 
 void ptnet_forward(laph_ctx *c, laph_ptnet *net, float bct, const float2 *in, float2 *out, int nrhs, int keep)
@@ -443,7 +449,7 @@ void ptnet_forward(laph_ctx *c, laph_ptnet *net, float bct, const float2 *in, fl
     size_t fb = sizeof(float2) * 12 * c->g.V * nrhs;  // one channel of the batch
     const float2 *cur = in;
     if (keep) {
-        net->acts.resize(net->layers);
+        net->acts.assign(net->layers, nullptr);
         net->act0 = in;
     }
     for (int l = 0; l < net->layers; l++) {
@@ -452,11 +458,11 @@ void ptnet_forward(laph_ctx *c, laph_ptnet *net, float bct, const float2 *in, fl
         if (l == net->layers - 1)
             dst = out;
         else if (keep)
-            dst = (float2 *)ctx_buf(c, net->acts[l + 1], fb * co);
+            dst = (float2 *)ctx_named(c, "net.act" + std::to_string(l + 1), fb * co);
         else
-            dst = (float2 *)ctx_buf(c, net->tmp[l & 1], fb * net->cmax);
-        launch_layer(c, (const float2 *)net->links.p, cur, dst, (const uint32_t *)net->wbf.p + net->woff[l], ci, co,
-                     nrhs, bct);
+            dst = (float2 *)ctx_named(c, std::string("net.tmp") + ((l & 1) ? "1" : "0"), fb * net->cmax);
+        if (keep && l + 1 < net->layers) net->acts[l + 1] = dst;
+        launch_layer(c, net->links, cur, dst, net->wbf + net->woff[l], ci, co, nrhs, bct);
         cur = dst;
     }
 }
@@ -464,19 +470,20 @@ void ptnet_forward(laph_ctx *c, laph_ptnet *net, float bct, const float2 *in, fl
 void ptnet_backward(laph_ctx *c, laph_ptnet *net, float bct, const float2 *g, float2 *gin, int nrhs)
 {
     size_t fb = sizeof(float2) * 12 * c->g.V * nrhs;
-    ctx_buf(c, net->grad, sizeof(float2) * net->nw);
+    net->grad = (float2 *)ctx_named(c, "net.grad", sizeof(float2) * net->nw);
     const float2 *cur = g;
     for (int l = net->layers - 1; l >= 0; l--) {
         int ci = net->ch[l], co = net->ch[l + 1];
-        const float2 *act = l == 0 ? net->act0 : (const float2 *)net->acts[l].p;
-        launch_wgrad(c, net, act, cur, ci, co, nrhs, bct, (float2 *)net->grad.p + net->woff[l]);
+        const float2 *act = l == 0 ? net->act0 : net->acts[l];
+        launch_wgrad(c, net, act, cur, ci, co, nrhs, bct, net->grad + net->woff[l]);
         if (l == 0 && !gin) break;
-        uint32_t *wa = (uint32_t *)ctx_buf(c, net->wadj, sizeof(uint32_t) * co * ci * 144);
+        uint32_t *wa = (uint32_t *)ctx_named(c, "net.wadj", sizeof(uint32_t) * net->cmax * net->cmax * 144);
         hipLaunchKernelGGL(k_pt_adjoint, dim3(nblocks_for(co * ci * 144, 256)), dim3(256), 0, c->stream,
-                           (const uint32_t *)net->wbf.p + net->woff[l], wa, co, ci);
+                           net->wbf + net->woff[l], wa, co, ci);
         LAPH_HIP(hipGetLastError());
-        float2 *dst = l == 0 ? gin : (float2 *)ctx_buf(c, net->tmp[l & 1], fb * net->cmax);
-        launch_layer(c, (const float2 *)net->links.p, cur, dst, wa, co, ci, nrhs, bct);
+        float2 *dst = l == 0 ? gin : (float2 *)ctx_named(c, std::string("net.tmp") + ((l & 1) ? "1" : "0"),
+                                                          fb * net->cmax);
+        launch_layer(c, net->links, cur, dst, wa, co, ci, nrhs, bct);
         cur = dst;
     }
 }
@@ -539,16 +546,38 @@ void ptnet_initial_guess(laph_ctx *c, laph_ptnet *net, float bct, const double *
     LAPH_HIP(hipGetLastError());
 }
 
-// ---------------------------------------------------------------------- C-ABI
-static void upload_weights(laph_ptnet *net, const std::vector<float> &w)
+// scratch of the network calls: what = 0 forward, 1 backward (with input gradient), 2 one
+// training step, 3 the solver's use (links, weights and a forward pass on nrhs fields)
+size_t ptnet_scratch_bytes(const Geom &g, const laph_ptnet *net, int nrhs, int what)
 {
-    std::vector<uint32_t> bf(net->nw);
-    LAPH_HIP(hipDeviceSynchronize());  // no kernel may still read the old weights
-    for (size_t i = 0; i < net->nw; i++) bf[i] = pack_bf(w[2 * i], w[2 * i + 1]);
-    LAPH_HIP(hipMemcpy(net->w32.p, w.data(), sizeof(float2) * net->nw, hipMemcpyHostToDevice));
-    LAPH_HIP(hipMemcpy(net->wbf.p, bf.data(), sizeof(uint32_t) * net->nw, hipMemcpyHostToDevice));
-    LAPH_HIP(hipMemset(net->m1.p, 0, sizeof(float2) * net->nw));
-    LAPH_HIP(hipMemset(net->m2.p, 0, sizeof(float2) * net->nw));
+    const size_t V = g.V, fb = sizeof(float2) * 12 * V * nrhs, nw = net->nw;
+    size_t s = ws_align(sizeof(float2) * V * 36) + ws_align(4 * nw);            // links, wbf
+    s += 2 * ws_align(fb * net->cmax);                                            // tmp0, tmp1
+    if (what == 3) return s;
+    s += 2 * ws_align(fb);                                                         // in, out
+    if (what == 0) return s;
+    for (int l = 1; l < net->layers; l++) s += ws_align(fb * net->ch[l]);          // kept activations
+    s += ws_align(sizeof(float2) * nw) + ws_align(4 * (size_t)net->cmax * net->cmax * 144);  // grad, wadj
+    const long n = (long)V * nrhs;
+    long chunk = std::max<long>(kPtBS * 8, (n + 255) / 256);
+    chunk = (chunk + kPtBS - 1) / kPtBS * kPtBS;
+    const size_t nblk = (n + chunk - 1) / chunk;
+    for (int l = 0; l < net->layers; l++)  // the per-layer partial gradients (grow-only name)
+        s += ws_align(sizeof(float2) * net->ch[l] * net->ch[l + 1] * 144 * nblk);
+    s += ws_align(fb);  // g
+    if (what == 1) return s + ws_align(fb);  // gin
+    const size_t pb = (V + 16 * kPtBS - 1) / (16 * kPtBS);
+    s += ws_align(sizeof(double) * pb * nrhs) + ws_align(sizeof(double) * nrhs);  // loss partials, 1/|x|^2
+    s += 3 * ws_align(sizeof(float2) * nw) + ws_align(4 * nw);                     // w32, m1, m2, new BF16
+    return s;
+}
+
+// ---------------------------------------------------------------------- C-ABI
+static void set_master(laph_ptnet *net, const std::vector<float> &w)
+{
+    net->w32 = w;
+    net->m1.assign(2 * net->nw, 0.0f);
+    net->m2.assign(2 * net->nw, 0.0f);
     net->step = 0;
 }
 
@@ -573,11 +602,6 @@ extern "C" int laph_ptnet_create(laph_ctx_t c, int layers, const int *channels, 
             net->nw += (size_t)channels[l] * channels[l + 1] * 144;
             net->cmax = std::max(net->cmax, channels[l + 1]);
         }
-        ctx_buf(c, net->w32, sizeof(float2) * net->nw);
-        ctx_buf(c, net->wbf, sizeof(uint32_t) * net->nw);
-        ctx_buf(c, net->m1, sizeof(float2) * net->nw);
-        ctx_buf(c, net->m2, sizeof(float2) * net->nw);
-        ctx_buf(c, net->grad, sizeof(float2) * net->nw);
         // small Gaussian weights plus 1/C_in times the identity on the self path, so that
         // the untrained net starts near a multiple of the identity
         std::mt19937_64 gen(seed);
@@ -596,13 +620,8 @@ extern "C" int laph_ptnet_create(laph_ctx_t c, int layers, const int *channels, 
                             w[2 * k + 1] = im;
                         }
         }
-        upload_weights(net, w);
+        set_master(net, w);
     } catch (...) {
-        ctx_free(net->w32);
-        ctx_free(net->wbf);
-        ctx_free(net->m1);
-        ctx_free(net->m2);
-        ctx_free(net->grad);
         delete net;
         throw;
     }
@@ -613,12 +632,6 @@ extern "C" int laph_ptnet_create(laph_ctx_t c, int layers, const int *channels, 
 extern "C" int laph_ptnet_destroy(laph_ptnet_t net)
 {
     if (!net) return LAPH_EINVAL;
-    (void)hipSetDevice(net->device);
-    (void)hipDeviceSynchronize();
-    for (DevBuf *b : {&net->w32, &net->wbf, &net->wadj, &net->m1, &net->m2, &net->grad, &net->gpart, &net->links,
-                      &net->tmp[0], &net->tmp[1]})
-        ctx_free(*b);
-    for (auto &b : net->acts) ctx_free(b);
     delete net;
     return LAPH_OK;
 }
@@ -633,28 +646,19 @@ extern "C" int laph_ptnet_num_weights(laph_ptnet_t net, size_t *n)
 extern "C" int laph_ptnet_get_weights(laph_ptnet_t net, double *w)
 {
     if (!net || !w) return LAPH_EINVAL;
-    if (hipSetDevice(net->device) != hipSuccess) return LAPH_EHIP;
-    std::vector<float> h(2 * net->nw);
-    if (hipMemcpy(h.data(), net->w32.p, sizeof(float2) * net->nw, hipMemcpyDeviceToHost) != hipSuccess)
-        return LAPH_EHIP;
-    for (size_t i = 0; i < 2 * net->nw; i++) w[i] = h[i];
+    for (size_t i = 0; i < 2 * net->nw; i++) w[i] = net->w32[i];
     return LAPH_OK;
 }
 
 extern "C" int laph_ptnet_set_weights(laph_ptnet_t net, const double *w)
 {
     if (!net || !w) return LAPH_EINVAL;
-    try {
-        LAPH_HIP(hipSetDevice(net->device));
-        std::vector<float> h(2 * net->nw);
-        for (size_t i = 0; i < 2 * net->nw; i++) {
-            if (!std::isfinite(w[i])) return LAPH_EINVAL;
-            h[i] = (float)w[i];
-        }
-        upload_weights(net, h);
-    } catch (const LaphError &e) {
-        return e.code;
+    std::vector<float> h(2 * net->nw);
+    for (size_t i = 0; i < 2 * net->nw; i++) {
+        if (!std::isfinite(w[i])) return LAPH_EINVAL;
+        h[i] = (float)w[i];
     }
+    set_master(net, h);
     return LAPH_OK;
 }
 
@@ -668,7 +672,7 @@ extern "C" int laph_ptnet_forward(laph_ctx_t c, laph_ptnet_t net, const double *
     long n = c->g.V * 12 * (long)n_fields;
     float2 *a = (float2 *)ctx_named(c, "net.in", sizeof(float2) * n);
     float2 *b = (float2 *)ctx_named(c, "net.out", sizeof(float2) * n);
-    ptnet_links(c, net, U);
+    ptnet_prepare(c, net, U);
     hipLaunchKernelGGL(k_pt_from64, dim3(nblocks_for(n, 256)), dim3(256), 0, c->stream, (const double2 *)in, a, n);
     LAPH_HIP(hipGetLastError());
     ptnet_forward(c, net, (float)bc_t, a, b, n_fields, 0);
@@ -691,7 +695,7 @@ extern "C" int laph_ptnet_backward(laph_ctx_t c, laph_ptnet_t net, const double 
     float2 *b = (float2 *)ctx_named(c, "net.out", sizeof(float2) * n);
     float2 *g = (float2 *)ctx_named(c, "net.g", sizeof(float2) * n);
     float2 *gi = gin ? (float2 *)ctx_named(c, "net.gin", sizeof(float2) * n) : nullptr;
-    ptnet_links(c, net, U);
+    ptnet_prepare(c, net, U);
     hipLaunchKernelGGL(k_pt_from64, dim3(nblocks_for(n, 256)), dim3(256), 0, c->stream, (const double2 *)in, a, n);
     hipLaunchKernelGGL(k_pt_from64, dim3(nblocks_for(n, 256)), dim3(256), 0, c->stream, (const double2 *)gout, g, n);
     LAPH_HIP(hipGetLastError());
@@ -703,7 +707,7 @@ extern "C" int laph_ptnet_backward(laph_ctx_t c, laph_ptnet_t net, const double 
         LAPH_HIP(hipGetLastError());
     }
     std::vector<float> h(2 * net->nw);
-    LAPH_HIP(hipMemcpyAsync(h.data(), net->grad.p, sizeof(float2) * net->nw, hipMemcpyDeviceToHost, c->stream));
+    LAPH_HIP(hipMemcpyAsync(h.data(), net->grad, sizeof(float2) * net->nw, hipMemcpyDeviceToHost, c->stream));
     LAPH_HIP(hipStreamSynchronize(c->stream));
     for (size_t i = 0; i < 2 * net->nw; i++) gw[i] = h[i];
     LAPH_API_END(c)
@@ -724,7 +728,7 @@ extern "C" int laph_ptnet_train_step(laph_ctx_t c, laph_ptnet_t net, const doubl
     float2 *a = (float2 *)ctx_named(c, "net.in", sizeof(float2) * n);
     float2 *o = (float2 *)ctx_named(c, "net.out", sizeof(float2) * n);
     float2 *g = (float2 *)ctx_named(c, "net.g", sizeof(float2) * n);
-    ptnet_links(c, net, U);
+    ptnet_prepare(c, net, U);
     hipLaunchKernelGGL(k_pt_from64, dim3(nblocks_for(n, 256)), dim3(256), 0, c->stream, (const double2 *)b, a, n);
     LAPH_HIP(hipGetLastError());
     ptnet_forward(c, net, (float)bc_t, a, o, n_pairs, 1);
@@ -751,16 +755,31 @@ extern "C" int laph_ptnet_train_step(laph_ctx_t c, laph_ptnet_t net, const doubl
                        (const double2 *)x, (const double *)inv, g, part, c->g.ns, V, opt->loss_parity, chunk);
     LAPH_HIP(hipGetLastError());
     ptnet_backward(c, net, (float)bc_t, g, nullptr, n_pairs);
-    net->step++;
-    float bc1 = 1.f - std::pow((float)opt->beta1, (float)net->step);
-    float bc2 = 1.f - std::pow((float)opt->beta2, (float)net->step);
-    hipLaunchKernelGGL(k_pt_adam, dim3(nblocks_for((long)net->nw, 256)), dim3(256), 0, c->stream,
-                       (float2 *)net->w32.p, (uint32_t *)net->wbf.p, (float2 *)net->m1.p, (float2 *)net->m2.p,
-                       (const float2 *)net->grad.p, (long)net->nw, (float)opt->lr, (float)opt->beta1,
+    // the optimiser state goes to the device for the step and comes back
+    const size_t wb = sizeof(float2) * net->nw;
+    float2 *w32 = (float2 *)ctx_named(c, "net.w32", wb), *m1 = (float2 *)ctx_named(c, "net.m1", wb),
+           *m2 = (float2 *)ctx_named(c, "net.m2", wb);
+    uint32_t *wbf_new = (uint32_t *)ctx_named(c, "net.wbf_new", sizeof(uint32_t) * net->nw);
+    LAPH_HIP(hipMemcpyAsync(w32, net->w32.data(), wb, hipMemcpyHostToDevice, c->stream));
+    LAPH_HIP(hipMemcpyAsync(m1, net->m1.data(), wb, hipMemcpyHostToDevice, c->stream));
+    LAPH_HIP(hipMemcpyAsync(m2, net->m2.data(), wb, hipMemcpyHostToDevice, c->stream));
+    const long step = net->step + 1;
+    float bc1 = 1.f - std::pow((float)opt->beta1, (float)step);
+    float bc2 = 1.f - std::pow((float)opt->beta2, (float)step);
+    hipLaunchKernelGGL(k_pt_adam, dim3(nblocks_for((long)net->nw, 256)), dim3(256), 0, c->stream, w32, wbf_new, m1,
+                       m2, (const float2 *)net->grad, (long)net->nw, (float)opt->lr, (float)opt->beta1,
                        (float)opt->beta2, (float)opt->eps, bc1, bc2);
     LAPH_HIP(hipGetLastError());
+    std::vector<float> nw32(2 * net->nw), nm1(2 * net->nw), nm2(2 * net->nw);
+    LAPH_HIP(hipMemcpyAsync(nw32.data(), w32, wb, hipMemcpyDeviceToHost, c->stream));
+    LAPH_HIP(hipMemcpyAsync(nm1.data(), m1, wb, hipMemcpyDeviceToHost, c->stream));
+    LAPH_HIP(hipMemcpyAsync(nm2.data(), m2, wb, hipMemcpyDeviceToHost, c->stream));
     LAPH_HIP(hipMemcpyAsync(hp.data(), part, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, c->stream));
     LAPH_HIP(hipStreamSynchronize(c->stream));
+    net->w32.swap(nw32);
+    net->m1.swap(nm1);
+    net->m2.swap(nm2);
+    net->step = step;
     if (loss) {
         double s = 0;
         for (int r = 0; r < n_pairs; r++) {

@@ -21,6 +21,15 @@
 #include "ptnet.h"
 #include "spinor_io.h"
 
+// largest power-of-two block (<= 32) the hopping kernels of this precision can address
+static int max_block_rhs(laph_ctx *c, int prec)
+{
+    if (prec != LAPH_PREC_F64) return lds_max_rhs(c, prec);
+    int R = 32;
+    while (R >= 1 && (unsigned long long)c->g.Vh * R * sizeof(double2) >= (1ull << 32)) R /= 2;
+    return R;
+}
+
 namespace {
 
 int laph_verbose_level()
@@ -456,41 +465,6 @@ __global__ __launch_bounds__(kBS) void k_owe_xlo(Vec xlo, Dirs dirs, long Vh, in
     st_site<XP>(xlo, Vh, R, i, rr, a);
 }
 
-// tracked residual update: r -= m (m = M xlo in the increment's precision), xhi += xlo,
-// xlo = 0; partial |r|^2 (right-hand sides with mask set)
-template <class XP>
-__global__ __launch_bounds__(kBS) void k_track_res(Vec r, Vec m, Vec xhi, Vec xlo, long Vh, int R, double *partial,
-                                                   const Scal *sc)
-{
-    double acc[1] = {0};
-    long n = Vh * R, stride = (long)gridDim.x * kBS;
-    int rr = (int)((blockIdx.x * (long)kBS + threadIdx.x) % R);
-    bool act = sc[rr].active;
-    for (long tid = blockIdx.x * (long)kBS + threadIdx.x; tid < n; tid += stride) {
-        if (!act) break;
-        long i = tid / R;
-        Cx<double> a[12], c[12], z[12];
-        ld_site<S64>(r, Vh, R, i, rr, a);
-        ld_site<XP>(m, Vh, R, i, rr, c);
-#pragma unroll
-        for (int k = 0; k < 12; k++) {
-            a[k] = a[k] - c[k];
-            acc[0] += a[k].re * a[k].re + a[k].im * a[k].im;
-        }
-        st_site<S64>(r, Vh, R, i, rr, a);
-        ld_site<S64>(xhi, Vh, R, i, rr, a);
-        ld_site<XP>(xlo, Vh, R, i, rr, c);
-#pragma unroll
-        for (int k = 0; k < 12; k++) {
-            a[k] = a[k] + c[k];
-            z[k] = {0, 0};
-        }
-        st_site<S64>(xhi, Vh, R, i, rr, a);
-        st_site<XP>(xlo, Vh, R, i, rr, z);
-    }
-    block_partial<1>(acc, R, partial);
-}
-
 __global__ void k_fin_r2hi(const double *partial, int nblk, int R, Scal *sc, int mode)
 {
     int r = blockIdx.x;
@@ -504,7 +478,6 @@ __global__ void k_fin_r2hi(const double *partial, int nblk, int R, Scal *sc, int
     }
     if (!q.active) return;
     q.r2hi = s[0];
-    if (mode == 2) return;  // a tracked residual never declares convergence
     if (s[0] <= q.tol2) q.active = 0;
 }
 
@@ -1099,59 +1072,16 @@ static Scal *pinned_scal(laph_ctx *c, int R)
     return (Scal *)c->pin;
 }
 
-// reliable updates far from convergence may track the FP64 residual with the FP32
-// operator (LAPH_TRACK=1).  Off by default: on LapH sources at 24^3 x 128 the switch to
-// the exact residual near 1e-5 |bhat| costs more iterations than the FP64 hops it saves
-static bool use_tracked()
-{
-    static int v = -1;
-    if (v < 0) {
-        const char *e = getenv("LAPH_TRACK");
-        v = (e && *e == '1') ? 1 : 0;
-    }
-    return v == 1;
-}
-
-// the CG loop decides on reliable updates from the previous iteration's scalars, read
-// while the current iteration runs (LAPH_LAG=0: from the current ones, draining the queue)
-static bool use_lag()
-{
-    static int v = -1;
-    if (v < 0) {
-        const char *e = getenv("LAPH_LAG");
-        v = (e && *e == '0') ? 0 : 1;
-    }
-    return v == 1;
-}
-
-// direction buffers of the fused CG loop where the solver parameters leave them open
-// (LAPH_DIRS=1..8 overrides the default): the FP32 solution increment
-// takes the owed steps every that many iterations
+// direction buffers of the fused CG loop where the solver parameters leave them open: the
+// FP32 solution increment takes the owed steps every that many iterations
 constexpr int kDefaultDirs = 8;
-static int cg_dir_buffers()
-{
-    static int v = -1;
-    if (v < 0) {
-        const char *e = getenv("LAPH_DIRS");
-        v = (e && *e >= '1' && *e <= '0' + kMaxDirs && !e[1]) ? *e - '0' : kDefaultDirs;
-    }
-    return v;
-}
 
 // A reliable update serves the whole block, so it waits until this percentage of the
 // active right-hand sides have their residual below reliable_delta of its last FP64
-// value (LAPH_QUORUM=0..100; 0: any one), unless one fell 100 times further, converged,
-// or reliable_every iterations passed.  On 32 LapH sources of the 24^3 x 128 workload a
-// quarter cut the updates per solve by a tenth for 0.3% more iterations (+1.2%).
-static int update_quorum()
-{
-    static int v = -1;
-    if (v < 0) {
-        const char *e = getenv("LAPH_QUORUM");
-        v = e ? std::max(0, std::min(100, atoi(e))) : 25;
-    }
-    return v;
-}
+// value, unless one fell 100 times further, converged, or reliable_every iterations
+// passed.  On 32 LapH sources of the 24^3 x 128 workload a quarter cut the updates per
+// solve by a tenth for 0.3% more iterations (+1.2% sources/s against any one).
+constexpr int kUpdateQuorum = 25;
 
 void write_scal(laph_ctx *c, Scal *d, const std::vector<Scal> &h)
 {
@@ -1277,13 +1207,14 @@ template <class SP, class GP, class CP, class XP>
 void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, Vec reshi, Vec rhi, Vec tmp64,
           int maxiter, int reliable_every, int check_every, std::vector<Scal> &hs)
 {
-    const bool plain = std::is_same<SP, S64>::value;
+    constexpr bool plain = std::is_same<SP, S64>::value;
     const bool nrm = SP::kNorm;
     laph_ctx *c = w.c;
     long n = w.Vh * w.R;
     int nblk = (int)red_blocks(n);
     Vec r = w.make("cg.r", SP::bytes, nrm), p = w.make("cg.p", SP::bytes, nrm), res = w.make("cg.res", SP::bytes, nrm);
-    Vec q = w.make("cg.q", SP::bytes, nrm), y = w.make("cg.y", SP::bytes, nrm), to = w.make("cg.to", SP::bytes, nrm);
+    Vec q = w.make("cg.q", SP::bytes, nrm), to = w.make("cg.to", SP::bytes, nrm);
+    Vec y = plain ? w.make("cg.y", SP::bytes, nrm) : Vec{};  // M^dag q (the fused form never stores it)
     Vec xlo = w.make("cg.xlo", XP::bytes, false);
     // FP64 residual of the masked RHS reshi = bhat - M xhi (res: the same in storage
     // precision); the normal residual r = M^dag res by the storage-precision operator, as
@@ -1307,7 +1238,9 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
     // one iteration: q = M p, alpha, y = M^dag q, x/res/r updates, beta (plain: and p)
     // low precision with the LDS-staged kernel: |q|^2 and the first step of M^dag q come
     // from the epilogue of the hop that forms q
-    const bool fuse = !plain && lds_dag_ok(c, w.R);
+    // (the caller picks R so that the multi-RHS kernel fits: every low-precision solve
+    // runs the fused form)
+    const bool fuse = !plain;
     double *part_hop = nullptr, *part_pre = nullptr;
     int nblk_hop = 0;
     if (fuse) {
@@ -1320,7 +1253,7 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
     // the old ones, and every K-th update takes the K owed steps at once: the FP32 increment
     // is read and written every K-th iteration only (graph replay keeps one captured body per
     // direction buffer)
-    const int K = !fuse ? 1 : w.dirs > 0 ? w.dirs : cg_dir_buffers();
+    const int K = !fuse ? 1 : w.dirs > 0 ? w.dirs : kDefaultDirs;
     Vec pb[kMaxDirs];
     pb[0] = p;
     for (int j = 1; j < K; j++) pb[j] = w.make(("cg.p" + std::to_string(j + 1)).c_str(), SP::bytes, nrm);
@@ -1336,7 +1269,7 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
         return d;
     };
     auto body = [&](const Op<SP, GP, CP> &op) {
-        if (fuse) {
+        if constexpr (!plain) {
             // M p with |q|^2 and A^-1 gamma_5 q from its epilogue; M^dag q feeding the CG
             // update directly (partials of the fused epilogues are RHS-major, pre-reduced
             // to kChunks per RHS)
@@ -1353,35 +1286,17 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
             launch_red(c, k_normsq<SP>, n, q, w.Vh, w.R, w.part);
             launch_fin(c, k_fin_cg_alpha, w.R, (const double *)w.part, nblk, w.R, w.sc, 0);
             op.mhat_dag(q, y, to);
-            if (plain)
-                launch_red(c, k_cg_update<SP, XP, true>, n, xlo, p, res, q, r, y, w.Vh, w.R, w.part,
-                           (const Scal *)w.sc);
-            else
-                launch_red(c, k_cg_update<SP, XP, false>, n, xlo, p, res, q, r, y, w.Vh, w.R, w.part,
-                           (const Scal *)w.sc);
-            launch_fin(c, k_fin_cg_beta, w.R, (const double *)w.part, nblk, w.R, w.sc, plain ? 1 : 0, plain ? 0 : 1,
-                       0);
+            launch_red(c, k_cg_update<SP, XP, true>, n, xlo, p, res, q, r, y, w.Vh, w.R, w.part, (const Scal *)w.sc);
+            launch_fin(c, k_fin_cg_beta, w.R, (const double *)w.part, nblk, w.R, w.sc, 1, 0, 0);
+            launch_el(c, k_cg_p<SP, XP>, n, p, owed_dirs(0, 1), r, xlo, w.Vh, w.R, (const Scal *)w.sc, 0, 0);
         }
-        if (plain) launch_el(c, k_cg_p<SP, XP>, n, p, owed_dirs(0, 1), r, xlo, w.Vh, w.R, (const Scal *)w.sc, 0, 0);
     };
     // lagged decisions (low precision): the scalars of iteration k are copied to a pinned
     // slot behind its hops; the update rule at iteration k reads iteration k - 1's slot,
     // long complete, so the host never waits for the queue to drain (an update or the
     // convergence test comes one iteration later, which the rule tolerates)
-    // tracked reliable updates: while every active even-odd residual is above 1e-5 |bhat|,
-    // the FP64 residual follows res -= M xlo with the operator applied to the FP32
-    // increment in FP32 (error ~1e-7 |res|, far below the update threshold), instead of
-    // being recomputed from xhi with the FP64 operator; closer to the target the full FP64
-    // residual takes over and also judges convergence
-    constexpr double kTrack2 = 1e-10;
-    const int quorum = update_quorum();
-    const bool track_ok = fuse && std::is_same<XP, S32>::value && use_tracked();
-    Vec t32{}, te32{};
-    if (track_ok) {
-        t32 = w.make("cg.t32", XP::bytes, false);
-        te32 = w.make("cg.te32", XP::bytes, false);
-    }
-    const bool lag = !plain && use_lag();
+    const int quorum = kUpdateQuorum;
+    const bool lag = !plain;
     Scal *pin = lag ? pinned_scal(c, w.R) : nullptr;
     int slot = 0;
     bool prev_ok = false;  // the other slot holds the previous iteration's scalars
@@ -1466,32 +1381,13 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
             // and keep the old direction orthogonal to the new residual
             // FP64 true residual of the even-odd system; the normal residual M^dag res is
             // computed by the low-precision operator, in which r is stored anyway
-            bool track = track_ok;
-            for (int k = 0; k < w.R && track; k++)
-                if (hs[k].active && !(hs[k].r2 > kTrack2 * hs[k].b2)) track = false;
-            if (track) {
-                if constexpr (std::is_same<XP, S32>::value) {
-                    if (step_now)
-                        launch_el(c, k_owe_xlo<XP, SP>, n, xlo, owed_dirs(0, 1 + nowed), w.Vh, w.R,
-                                  (const Scal *)w.sc);
-                    Op<XP, G32, C32> lo32{c, lo.st, lo.Vh, lo.R, nullptr, nullptr, nullptr, lo.ws, lo.wt, lo.bct, te32};
-                    lo32.lk12 = lo.lk12;
-                    lo32.claos = lo.claos;
-                    lo32.tgauge = lo.tgauge;
-                    lo32.mhat(xlo, t32);
-                    launch_red(c, k_track_res<XP>, n, reshi, t32, xhi, xlo, w.Vh, w.R, w.part, (const Scal *)w.sc);
-                    launch_fin(c, k_fin_r2hi, w.R, (const double *)w.part, nblk, w.R, w.sc, 2);
-                }
-                launch_el(c, k_convert_masked<SP>, n, reshi, res, w.Vh, w.R, (const Scal *)w.sc);
-            } else {
-                if (step_now)  // the fold takes the steps still owed to x
-                    launch_el(c, k_fold_x_step<XP, SP>, n, xhi, xlo, owed_dirs(0, 1 + nowed), w.Vh, w.R,
-                              (const Scal *)w.sc);
-                else
-                    launch_el(c, k_fold_x<XP>, n, xhi, xlo, w.Vh, w.R, (const Scal *)w.sc, 0);
-                // the FP64 residual, and res = the same in storage precision
-                true_eo_residual<SP>(w, hi, bhat, xhi, tmp64, reshi, 0, res);
-            }
+            if (step_now)  // the fold takes the steps still owed to x
+                launch_el(c, k_fold_x_step<XP, SP>, n, xhi, xlo, owed_dirs(0, 1 + nowed), w.Vh, w.R,
+                          (const Scal *)w.sc);
+            else
+                launch_el(c, k_fold_x<XP>, n, xhi, xlo, w.Vh, w.R, (const Scal *)w.sc, 0);
+            // the FP64 residual, and res = the same in storage precision
+            true_eo_residual<SP>(w, hi, bhat, xhi, tmp64, reshi, 0, res);
             step_now = false;
             nowed = 0;
             lo.mhat_dag(res, r, to);
@@ -1811,6 +1707,33 @@ int fgmres(laph_ctx *c, const Op64 &hi, laph_ptnet *net, Vec bhat, Vec x, Vec r,
     return it;
 }
 
+// ------------------------------------------------------------- hop_apply helpers
+// b = a in storage precision SP for every right-hand side (FP64 parity layout in)
+template <class SP>
+__global__ __launch_bounds__(kBS) void k_store_lo(Vec a, Vec b, long Vh, int R)
+{
+    long tid = blockIdx.x * (long)kBS + threadIdx.x;
+    if (tid >= Vh * R) return;
+    long i = tid / R;
+    int rr = (int)(tid - i * R);
+    Cx<double> v[12];
+    ld_site<S64>(a, Vh, R, i, rr, v);
+    st_site<SP>(b, Vh, R, i, rr, v);
+}
+
+// b = a as FP64 (storage precision SP in, FP64 parity layout out)
+template <class SP>
+__global__ __launch_bounds__(kBS) void k_load_lo(Vec a, Vec b, long Vh, int R)
+{
+    long tid = blockIdx.x * (long)kBS + threadIdx.x;
+    if (tid >= Vh * R) return;
+    long i = tid / R;
+    int rr = (int)(tid - i * R);
+    Cx<double> v[12];
+    ld_site<SP>(a, Vh, R, i, rr, v);
+    st_site<S64>(b, Vh, R, i, rr, v);
+}
+
 // ------------------------------------------------------------------ autotuning
 // Times the even-odd hopping kernel (fused clover-inverse epilogue, the launch that
 // dominates an iteration) for every block size R and, for the LDS-staged kernel, every
@@ -1822,7 +1745,10 @@ std::vector<laph_tune_entry> tune_hopping(laph_ctx *c, int prec)
     DiracCache &dc = *c->cur;
     const long Vh = c->g.Vh;
     const bool low = !std::is_same<SP, S64>::value;
-    std::vector<int> Rs = low ? std::vector<int>{4, 8, 16, 32} : std::vector<int>{1, 2, 4, 8, 16, 32};
+    std::vector<int> Rs;
+    for (int R : low ? std::vector<int>{4, 8, 16, 32} : std::vector<int>{1, 2, 4, 8, 16, 32})
+        if (R <= max_block_rhs(c, prec)) Rs.push_back(R);
+    LAPH_CHECK(!Rs.empty(), LAPH_EINVAL, "lattice too large for the hopping kernels' 32-bit offsets");
     std::vector<laph_tune_entry> out;
     hipEvent_t e0, e1;
     LAPH_HIP(hipEventCreate(&e0));
@@ -1886,14 +1812,6 @@ std::vector<laph_tune_entry> tune_hopping(laph_ctx *c, int prec)
     c->timing = timing;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    for (const char *nm : {"slv.tune.in", "slv.tune.out", "slv.tune.x", "slv.tune.te", "slv.tune.in.n",
-                           "slv.tune.out.n", "slv.tune.x.n", "slv.tune.te.n"}) {
-        auto it = c->bufs.find(nm);
-        if (it != c->bufs.end()) {
-            ctx_free(it->second);
-            c->bufs.erase(it);
-        }
-    }
     c->tuned_R[prec] = bestR;
     return out;
 }
@@ -2074,32 +1992,39 @@ void solve_batch(laph_ctx *c, const double *eta, double *x, int R, int nreal, co
 }  // namespace
 
 // ------------------------------------------------------------------- setup / ABI
-static bool dirac_cache_holds(const DiracCache &dc, const double *U, const laph_dirac *d)
+
+static bool dirac_cache_holds(const DiracCache &dc, const double *U, uint64_t fp, const laph_dirac *d)
 {
-    return dc.valid && dc.U == U && dc.prm.m0 == d->m0 && dc.prm.xi == d->xi && dc.prm.c_sw == d->c_sw &&
-           dc.prm.bc_t == d->bc_t;
+    return dc.valid && dc.U == U && dc.fp == fp && dc.prm.m0 == d->m0 && dc.prm.xi == d->xi &&
+           dc.prm.c_sw == d->c_sw && dc.prm.bc_t == d->bc_t;
 }
 
 // (re)build cache dc for the field Ub when it does not hold the operator of the caller's
-// field Ukey with parameters d
-static void prepare_cache(laph_ctx *c, DiracCache &dc, const double *Ukey, const double *Ub, const laph_dirac *d,
-                          bool need_f32)
+// field Ukey (fingerprint fp) with parameters d.  The cache is keyed by the field's
+// contents as well as its address: a caller may free a field and allocate another one at
+// the same address.
+static void prepare_cache(laph_ctx *c, DiracCache &dc, const double *Ukey, uint64_t fp, const double *Ub,
+                          const laph_dirac *d, bool need_f32)
 {
-    long Vh = c->g.Vh;
-    if (!dirac_cache_holds(dc, Ukey, d)) {
-        ctx_buf(c, dc.g64, (size_t)72 * Vh * 16);
-        ctx_buf(c, dc.clov, (size_t)144 * Vh * 8);
-        ctx_buf(c, dc.clinv, (size_t)144 * Vh * 8);
+    const bool f32 = need_f32 || dc.has_f32;
+    const size_t need = cache_unit_bytes(c->g, dc.tgauge, f32);
+    const void *held = dc.unit.p;
+    cache_unit(c, dc, need);  // pins the unit; a new or moved unit is rebuilt
+    if (dc.unit.p != held || dc.has_f32 != f32) {
+        dc.valid = false;
+        dc.f32 = false;
+        cache_carve(c, dc, dc.tgauge, f32);
+    }
+    if (!dirac_cache_holds(dc, Ukey, fp, d)) {
         links_to_eo(c, Ub, (double2 *)dc.g64.p);
         clover_build(c, Ub, d, (double *)dc.clov.p, (double *)dc.clinv.p);
         dc.valid = true;
         dc.U = Ukey;
+        dc.fp = fp;
         dc.prm = *d;
         dc.f32 = false;
     }
     if (need_f32 && !dc.f32) {
-        ctx_buf(c, dc.lk12, (size_t)8 * Vh * 3 * 16);
-        ctx_buf(c, dc.claos, (size_t)2 * Vh * 72 * 4);
         build_lp_operator(c, (const double2 *)dc.g64.p, (const double *)dc.clinv.p, (float4 *)dc.lk12.p,
                           (float *)dc.claos.p);
         dc.f32 = true;
@@ -2108,31 +2033,29 @@ static void prepare_cache(laph_ctx *c, DiracCache &dc, const double *Ukey, const
 
 void dirac_prepare(laph_ctx *c, const double *U, const laph_dirac *d, bool need_f32)
 {
-    prepare_cache(c, c->dc, U, U, d, need_f32);
+    c->dc.tgauge = false;
+    prepare_cache(c, c->dc, U, gauge_fingerprint(c, U), U, d, need_f32);
 }
 
 void dirac_prepare_tgauge(laph_ctx *c, const double *U, const laph_dirac *d)
 {
     DiracCache &dc = c->dct;
     dc.tgauge = true;
-    if (!dirac_cache_holds(dc, U, d)) {
-        const long V = c->g.V;
-        ctx_buf(c, dc.gU, (size_t)V * 36 * 16);
-        ctx_buf(c, dc.gG, (size_t)V * 9 * 16);
+    const uint64_t fp = gauge_fingerprint(c, U);
+    const size_t need = cache_unit_bytes(c->g, true, true);
+    const void *held = dc.unit.p;
+    cache_unit(c, dc, need);
+    if (dc.unit.p != held || !dc.has_f32) {
+        dc.valid = false;
+        dc.f32 = false;
+        cache_carve(c, dc, true, true);
+    }
+    const bool same_field = dc.valid && dc.U == U && dc.fp == fp;
+    if (!same_field) {
+        dc.valid = false;
         tgauge_fix(c, U, (double *)dc.gG.p, (double *)dc.gU.p);
     }
-    prepare_cache(c, dc, U, (const double *)dc.gU.p, d, true);
-}
-
-// temporal gauge for the low-precision solves unless LAPH_TGAUGE=0
-static bool use_tgauge()
-{
-    static int v = -1;
-    if (v < 0) {
-        const char *e = getenv("LAPH_TGAUGE");
-        v = (e && *e == '0') ? 0 : 1;
-    }
-    return v == 1;
+    prepare_cache(c, dc, U, fp, (const double *)dc.gU.p, d, true);
 }
 
 static void check_dirac(const laph_dirac *d)
@@ -2152,17 +2075,287 @@ extern "C" int laph_dirac_apply(laph_ctx_t c, const double *U, const laph_dirac 
     dirac_prepare(c, U, d, false);
     long Vh = c->g.Vh;
     DiracCache &dc = c->dc;
-    size_t bytes = (size_t)12 * Vh * n * 16;
+    // fields in batches the FP64 hopping kernel addresses with 32-bit offsets
+    const int B = std::min(n, max_block_rhs(c, LAPH_PREC_F64));
+    LAPH_CHECK(B >= 1, LAPH_EINVAL, "lattice too large for the hopping kernel's 32-bit offsets");
+    size_t bytes = (size_t)12 * Vh * B * 16;
     Vec xe{ctx_named(c, "app.xe", bytes)}, xo{ctx_named(c, "app.xo", bytes)};
     Vec oe{ctx_named(c, "app.oe", bytes)}, oo{ctx_named(c, "app.oo", bytes)};
-    Op64 hi{c, c->stream, Vh, n, dc.g64.p, (const char *)dc.clinv.p, (const char *)dc.clov.p,
-            -0.5 / dc.prm.xi, -0.5, dc.prm.bc_t, Vec{}};
     int gin = op == LAPH_OP_KDAG ? 5 : 0;
     int gout = op == LAPH_OP_KDAG ? 5 : (op == LAPH_OP_OMEGA ? 4 : 0);
-    spinor_to_eo(c, in, n, gin, (double2 *)xe.d, (double2 *)xo.d);
-    apply_K(c, hi, xe, xo, oe, oo);
-    spinor_from_eo(c, (const double2 *)oe.d, (const double2 *)oo.d, n, gout, out);
+    const size_t field = (size_t)c->g.V * 24;
+    for (int f0 = 0; f0 < n; f0 += B) {
+        const int nb = std::min(B, n - f0);
+        Op64 hi{c, c->stream, Vh, nb, dc.g64.p, (const char *)dc.clinv.p, (const char *)dc.clov.p,
+                -0.5 / dc.prm.xi, -0.5, dc.prm.bc_t, Vec{}};
+        spinor_to_eo(c, in + f0 * field, nb, gin, (double2 *)xe.d, (double2 *)xo.d);
+        apply_K(c, hi, xe, xo, oe, oo);
+        spinor_from_eo(c, (const double2 *)oe.d, (const double2 *)oo.d, nb, gout, out + f0 * field);
+    }
     LAPH_HIP(hipStreamSynchronize(c->stream));
+    LAPH_API_END(c)
+}
+
+// ----------------------------------------------------------- workspace sizes
+// Each function below sums the scratch buffers its entry point takes from the workspace
+// (an upper bound where the path depends on the run: every branch is counted).
+static size_t vec_bytes(long Vh, int R, int prec)
+{
+    const int sb = prec == LAPH_PREC_F64 ? 16 : prec == LAPH_PREC_F32 ? 8 : 4;
+    size_t s = ws_align((size_t)12 * Vh * R * sb);
+    if (prec == LAPH_PREC_F16) s += ws_align((size_t)Vh * R * 4);
+    return s;
+}
+
+size_t dirac_cache_bytes(const Geom &g, bool tgauge) { return cache_unit_bytes(g, tgauge, true); }
+
+size_t apply_scratch_bytes(laph_ctx *c, int n_fields)
+{
+    const int B = std::min(n_fields, max_block_rhs(c, LAPH_PREC_F64));
+    return ws_align(8) + 4 * ws_align((size_t)12 * c->g.Vh * std::max(B, 1) * 16);
+}
+
+size_t hop_scratch_bytes(laph_ctx *c, const laph_hop *h, int R)
+{
+    const long Vh = c->g.Vh;
+    size_t s = ws_align(8) + 6 * ws_align((size_t)12 * Vh * R * 16);
+    if (h->precision != LAPH_PREC_F64) {
+        s += 5 * vec_bytes(Vh, R, h->precision);
+        const int S = h->sites_per_block > 0 ? h->sites_per_block : lds_tile_sites(c, h->precision, R);
+        s += ws_align(sizeof(double) * ((Vh + S - 1) / S) * R) + ws_align(sizeof(Scal) * R);
+    }
+    return s;
+}
+
+size_t tune_scratch_bytes(laph_ctx *c, int prec)
+{
+    const bool low = prec != LAPH_PREC_F64;
+    size_t s = 0;
+    for (int R : low ? std::vector<int>{4, 8, 16, 32} : std::vector<int>{1, 2, 4, 8, 16, 32})
+        if (R <= max_block_rhs(c, prec)) s += 4 * vec_bytes(c->g.Vh, R, prec);  // names grow with R
+    return s;
+}
+
+size_t solve_scratch_bytes(laph_ctx *c, int n_rhs, const laph_solver *sv)
+{
+    const long Vh = c->g.Vh, V = c->g.V;
+    const int prec = sv->precision;
+    const bool low = prec != LAPH_PREC_F64;
+    const int xp = low ? LAPH_PREC_F32 : LAPH_PREC_F64;
+    const bool fg = sv->solver == LAPH_SOLVER_FGMRES;
+    laph_ptnet *net = (laph_ptnet *)sv->net;
+    size_t s = ws_align(8);  // fingerprint
+    int R = fg ? 1 : sv->block_rhs;
+    if (R == 0) {
+        if (!c->tuned_R.count(prec)) s += tune_scratch_bytes(c, prec);
+        R = c->tuned_R.count(prec) ? c->tuned_R[prec] : 32;
+    }
+    R = std::max(1, std::min(R, max_block_rhs(c, prec)));
+    int Rb = R;
+    while (Rb / 2 >= n_rhs) Rb /= 2;  // the first (largest) batch
+    // padding of a ragged tail batch
+    const int tail = n_rhs % R;
+    if (tail || n_rhs < R) {
+        const int nreal = tail ? tail : n_rhs;
+        int Rt = R;
+        while (Rt / 2 >= nreal) Rt /= 2;
+        if (nreal < Rt) s += 2 * ws_align((size_t)V * 24 * 8 * Rt);
+    }
+    const bool guess = net && !fg;
+    if (low && guess) s += ws_align((size_t)V * 24 * 8 * Rb);  // rotated sources
+    if (net) s += ptnet_scratch_bytes(c->g, net, guess ? Rb : 1, 3);
+    // solve_batch
+    s += ws_align(sizeof(Scal) * Rb) + ws_align(sizeof(double) * kMaxBlocks * Rb * 4);
+    s += 10 * vec_bytes(Vh, Rb, LAPH_PREC_F64) + vec_bytes(Vh, Rb, prec);
+    if (guess) s += 2 * ws_align(sizeof(float2) * 12 * V * Rb);
+    if (sv->solver == LAPH_SOLVER_BICGSTAB) s += 6 * vec_bytes(Vh, Rb, prec) + vec_bytes(Vh, Rb, xp);
+    if (fg) {
+        const long n = 12 * Vh;
+        const int m = sv->restart > 0 ? sv->restart : 24;
+        long chunk = std::max<long>(kFgBS * 16, (n + 511) / 512);
+        chunk = (chunk + kFgBS - 1) / kFgBS * kFgBS;
+        const size_t nblk = (n + chunk - 1) / chunk;
+        s += ws_align(sizeof(double2) * nblk * (m + 1)) + ws_align(sizeof(double2) * (m + 1)) +
+             ws_align(sizeof(double2) * n * (m + 1)) + ws_align(sizeof(double2) * n * m) +
+             ws_align(sizeof(double2) * n) + 2 * ws_align(sizeof(float2) * 12 * V);
+    }
+    // CG on the normal equations in the storage precision (the production form, and the
+    // fallback of the other solvers)
+    if (low) {
+        const int K = sv->dir_buffers > 0 ? sv->dir_buffers : kDefaultDirs;
+        s += (5 + (K - 1)) * vec_bytes(Vh, Rb, prec) + vec_bytes(Vh, Rb, xp);
+        const int S = lds_tile_sites(c, prec, Rb);
+        s += ws_align(sizeof(double) * ((Vh + S - 1) / S) * Rb) + ws_align(sizeof(double) * kChunks * Rb);
+    }
+    // the last attempt: plain FP64 CG (the same names at FP64 size)
+    s += 7 * vec_bytes(Vh, Rb, LAPH_PREC_F64);
+    return s;
+}
+
+// One even-odd hopping launch of the solver's kernels on caller fields (see laph.h).
+template <class SP>
+static void hop_launch_lo(laph_ctx *c, const DiracCache &dc, const laph_hop *h, int R, Vec in, const Vec *x, Vec out,
+                          Vec out2, Vec r, const Scal *sc, double *partial)
+{
+    Op<SP, G32, C32> lo{c, c->stream, c->g.Vh, R, nullptr, nullptr, nullptr, -0.5 / dc.prm.xi, -0.5, dc.prm.bc_t,
+                        Vec{}};
+    lo.lk12 = (const float4 *)dc.lk12.p;
+    lo.claos = (const float4 *)dc.claos.p;
+    lo.tgauge = dc.tgauge ? 1 : 0;
+    const int p = h->parity;
+    MrArgs m = lo.mr_args(p, in, out, x, h->a, h->c, h->gamma5);
+    int mode = M_PLAIN;
+    switch (h->mode) {
+    case LAPH_HOP_INV: mode = M_INV_AFTER; break;
+    case LAPH_HOP_INV_DAG:
+        mode = M_INV_AFTER_DAG;
+        m.out2 = out2.d;
+        m.out2_nrm = out2.n;
+        m.partial = partial;
+        break;
+    case LAPH_HOP_PLAIN_CG:
+        mode = M_PLAIN_CG;
+        m.out = nullptr;
+        m.out_nrm = nullptr;
+        m.cg_r = r.d;
+        m.cg_r_nrm = r.n;
+        m.sc = sc;
+        m.partial = partial;
+        break;
+    default: break;
+    }
+    launch_dslash_mr<SP>(c, mode, m, c->stream);
+}
+
+extern "C" int laph_hop_apply(laph_ctx_t c, const double *U, const laph_dirac *d, const laph_hop *h, const double *in,
+                              const double *x, double *out, double *out2, const double *alpha, double *norm2, int n)
+{
+    LAPH_API_BEGIN(c)
+    g_current_ctx = c;
+    LAPH_CHECK(U && h && in && out, LAPH_EINVAL, "null pointer");
+    check_dirac(d);
+    LAPH_CHECK(h->precision >= LAPH_PREC_F64 && h->precision <= LAPH_PREC_BF16, LAPH_EINVAL, "bad precision");
+    LAPH_CHECK(h->mode >= LAPH_HOP_PLAIN && h->mode <= LAPH_HOP_PLAIN_CG, LAPH_EINVAL, "bad mode");
+    LAPH_CHECK(h->parity == 0 || h->parity == 1, LAPH_EINVAL, "parity must be 0 or 1");
+    LAPH_CHECK(h->walk == 0 || h->walk == 1, LAPH_EINVAL, "walk must be 0 or 1");
+    LAPH_CHECK(h->sites_per_block >= 0, LAPH_EINVAL, "sites_per_block must be >= 0");
+    LAPH_CHECK(n >= 1 && n <= 32 && (n & (n - 1)) == 0, LAPH_EINVAL, "n_fields must be a power of two <= 32");
+    LAPH_CHECK(n <= max_block_rhs(c, h->precision), LAPH_EINVAL, "%d fields exceed the kernel's 32-bit offsets", n);
+    const bool low = h->precision != LAPH_PREC_F64;
+    const bool fused = h->mode == LAPH_HOP_INV_DAG || h->mode == LAPH_HOP_PLAIN_CG;
+    LAPH_CHECK(low || !fused, LAPH_EINVAL, "fused epilogues exist for the low precisions only");
+    LAPH_CHECK(!fused || x, LAPH_EINVAL, "the fused epilogues need the own-site operand x");
+    LAPH_CHECK(h->mode != LAPH_HOP_INV_DAG || (out2 && h->c != 0), LAPH_EINVAL, "INV_DAG needs out2 and c != 0");
+    LAPH_CHECK(h->mode != LAPH_HOP_PLAIN_CG || alpha, LAPH_EINVAL, "PLAIN_CG needs alpha");
+    if (h->temporal_gauge)
+        dirac_prepare_tgauge(c, U, d);
+    else
+        dirac_prepare(c, U, d, low);
+    const DiracCache &dc = h->temporal_gauge ? c->dct : c->dc;
+    const double *G = h->temporal_gauge ? (const double *)dc.gG.p : nullptr;
+    struct Reset {
+        laph_ctx *c;
+        ~Reset()
+        {
+            c->walk_mode = 0;
+            c->tile_override = 0;
+        }
+    } reset{c};
+    c->walk_mode = h->walk;
+    c->tile_override = low ? h->sites_per_block : 0;
+
+    const long Vh = c->g.Vh;
+    const int R = n, p = h->parity;
+    const size_t half64 = (size_t)12 * Vh * R * 16;
+    Vec e64{ctx_named(c, "hop.e64", half64)}, o64{ctx_named(c, "hop.o64", half64)};
+    Vec ie{ctx_named(c, "hop.ie", half64)}, io{ctx_named(c, "hop.io", half64)};
+    Vec xh{ctx_named(c, "hop.xh", half64)};
+    // the input lives on the other parity, x and r on the output parity
+    spinor_to_eo(c, in, R, 0, (double2 *)ie.d, (double2 *)io.d, G);
+    Vec in64 = p ? ie : io;
+    if (x) {
+        spinor_to_eo(c, x, R, 0, (double2 *)e64.d, (double2 *)o64.d, G);
+        LAPH_HIP(hipMemcpyAsync(xh.d, p ? o64.d : e64.d, half64, hipMemcpyDeviceToDevice, c->stream));
+    }
+    Vec r64{ctx_named(c, "hop.r64", half64)};
+    if (h->mode == LAPH_HOP_PLAIN_CG) {
+        spinor_to_eo(c, out, R, 0, (double2 *)e64.d, (double2 *)o64.d, G);
+        LAPH_HIP(hipMemcpyAsync(r64.d, p ? o64.d : e64.d, half64, hipMemcpyDeviceToDevice, c->stream));
+    }
+    std::vector<double> nrm(R, 0.0);
+    Vec res64 = p ? o64 : e64;   // result half in FP64
+    Vec zero64 = p ? e64 : o64;  // the other parity of every output: zero
+    if (!low) {
+        Op64 hi{c, c->stream, Vh, R, dc.g64.p, (const char *)dc.clinv.p, (const char *)dc.clov.p, -0.5 / dc.prm.xi,
+                -0.5, dc.prm.bc_t, Vec{}};
+        DslashArgs a = hi.base(p);
+        a.in = in64.d;
+        a.x = x ? xh.d : nullptr;
+        a.out = res64.d;
+        a.clov = hi.cinv(p);
+        a.a = h->a;
+        a.c = h->c;
+        a.g5d = h->gamma5;
+        launch_dslash<S64, G64, C64>(c, h->mode == LAPH_HOP_INV ? M_INV_AFTER : M_PLAIN, a, c->stream);
+    } else {
+        const int sb = h->precision == LAPH_PREC_F32 ? 8 : 4;
+        const bool nm = h->precision == LAPH_PREC_F16;
+        auto lov = [&](const char *name) {
+            Vec v{ctx_named(c, std::string("hop.") + name, (size_t)12 * Vh * R * sb)};
+            if (nm) v.n = (float *)ctx_named(c, std::string("hop.") + name + ".n", (size_t)Vh * R * 4);
+            return v;
+        };
+        Vec lin = lov("lin"), lx = lov("lx"), lout = lov("lout"), lout2 = lov("lout2"), lr = lov("lr");
+        const long nl = Vh * R;
+        Scal *sc = nullptr;
+        double *part = nullptr;
+        const long nblk = lds_dag_blocks(c, h->precision, R);
+        if (fused) {
+            part = (double *)ctx_named(c, "hop.part", sizeof(double) * nblk * R);
+            if (h->mode == LAPH_HOP_PLAIN_CG) {
+                std::vector<Scal> hs(R);
+                for (int q = 0; q < R; q++) {
+                    hs[q] = Scal{};
+                    hs[q].active = 1;
+                    hs[q].alpha = make_double2(alpha[q], 0.0);
+                }
+                sc = (Scal *)ctx_named(c, "hop.scal", sizeof(Scal) * R);
+                LAPH_HIP(hipMemcpyAsync(sc, hs.data(), sizeof(Scal) * R, hipMemcpyHostToDevice, c->stream));
+            }
+        }
+        auto run = [&](auto tag) {
+            using SP = decltype(tag);
+            launch_el(c, k_store_lo<SP>, nl, in64, lin, Vh, R);
+            if (x) launch_el(c, k_store_lo<SP>, nl, xh, lx, Vh, R);
+            if (h->mode == LAPH_HOP_PLAIN_CG) launch_el(c, k_store_lo<SP>, nl, r64, lr, Vh, R);
+            hop_launch_lo<SP>(c, dc, h, R, lin, x ? &lx : nullptr, lout, lout2, lr, sc, part);
+            launch_el(c, k_load_lo<SP>, nl, h->mode == LAPH_HOP_PLAIN_CG ? lr : lout, res64, Vh, R);
+            if (h->mode == LAPH_HOP_INV_DAG) launch_el(c, k_load_lo<SP>, nl, lout2, r64, Vh, R);
+        };
+        if (h->precision == LAPH_PREC_F32)
+            run(S32{});
+        else if (h->precision == LAPH_PREC_F16)
+            run(S16{});
+        else
+            run(SB16{});
+        if (fused) {
+            std::vector<double> hp((size_t)nblk * R);
+            LAPH_HIP(hipMemcpyAsync(hp.data(), part, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, c->stream));
+            LAPH_HIP(hipStreamSynchronize(c->stream));
+            for (int q = 0; q < R; q++)
+                for (long b = 0; b < nblk; b++) nrm[q] += hp[(size_t)q * nblk + b];
+        }
+    }
+    LAPH_HIP(hipMemsetAsync(zero64.d, 0, half64, c->stream));
+    spinor_from_eo(c, (const double2 *)e64.d, (const double2 *)o64.d, R, 0, out, G);
+    if (h->mode == LAPH_HOP_INV_DAG) {
+        // out2 from r64 (its result half) and the zeroed half
+        spinor_from_eo(c, p ? (const double2 *)zero64.d : (const double2 *)r64.d,
+                       p ? (const double2 *)r64.d : (const double2 *)zero64.d, R, 0, out2, G);
+    }
+    LAPH_HIP(hipStreamSynchronize(c->stream));
+    if (norm2)
+        for (int q = 0; q < R; q++) norm2[q] = nrm[q];
     LAPH_API_END(c)
 }
 
@@ -2185,7 +2378,7 @@ extern "C" int dirac_solve(laph_ctx_t c, const double *U, const laph_dirac *d, c
     bool low = sv->precision != LAPH_PREC_F64;
     // low-precision solves run in temporal gauge (the hop skips the unit time links); the
     // FP64 path keeps the caller's gauge
-    const bool tg = low && use_tgauge();
+    const bool tg = low;
     if (tg)
         dirac_prepare_tgauge(c, U, d);
     else
@@ -2210,7 +2403,7 @@ extern "C" int dirac_solve(laph_ctx_t c, const double *U, const laph_dirac *d, c
         LAPH_CHECK(net && net->layers > 0, LAPH_EINVAL, "FGMRES needs a network");
         LAPH_CHECK(net->device == c->device, LAPH_EINVAL, "network and context on different devices");
         // the network is gauge equivariant: in temporal gauge it takes the rotated field
-        ptnet_links(c, net, tg ? (const double *)c->dct.gU.p : U);
+        ptnet_prepare(c, net, tg ? (const double *)c->dct.gU.p : U);
     }
     if (sv->solver == LAPH_SOLVER_FGMRES) {
         LAPH_CHECK(sv->restart >= 0 && sv->restart <= 256, LAPH_EINVAL, "restart must be in 0..256");
@@ -2221,6 +2414,10 @@ extern "C" int dirac_solve(laph_ctx_t c, const double *U, const laph_dirac *d, c
         if (!c->tuned_R.count(sv->precision)) tune_for(c, sv->precision);
         R = c->tuned_R[sv->precision];
     }
+    // the hopping kernels address a block's spinors with 32-bit offsets: the block shrinks
+    // to the largest power of two they reach on this lattice
+    R = std::min(R, max_block_rhs(c, sv->precision));
+    LAPH_CHECK(R >= 1, LAPH_EINVAL, "lattice too large for the hopping kernels' 32-bit offsets");
     long V = c->g.V;
     int first_err = LAPH_OK;
     for (int base = 0; base < n_rhs; base += R) {

@@ -230,6 +230,26 @@ extern "C" int make_diluted_source(laph_ctx_t c, const double *evecs, int nv, ui
     LAPH_API_END(c)
 }
 
+// site ranges (split-K factor) of the tiled sink projection
+static long sink_ranges(const Geom &g, int nv, int n_rhs, long &xper)
+{
+    const int mtiles = (n_rhs * 4 + kSinkM - 1) / kSinkM, ntiles = (nv + kSinkN - 1) / kSinkN;
+    const long base = (long)g.nt * mtiles * ntiles;
+    long nz = std::max(1L, std::min(g.V3 / (8 * kSinkX), 2048 / std::max(1L, base)));
+    xper = (g.V3 + nz - 1) / nz;
+    xper = (xper + kSinkX - 1) / kSinkX * kSinkX;
+    return (g.V3 + xper - 1) / xper;
+}
+
+size_t sink_scratch_bytes(const Geom &g, int nv, int n_rhs)
+{
+    long xper;
+    const long nz = sink_ranges(g, nv, n_rhs, xper);
+    return ws_align(sizeof(double2) * (size_t)n_rhs * g.nt * 4 * nv * nz);
+}
+
+size_t source_scratch_bytes(const Geom &g, int nv) { return ws_align(sizeof(double2) * g.nt * 4 * nv); }
+
 extern "C" int sink_project(laph_ctx_t c, const double *evecs, int nv, const double *X, int n_rhs, double *coef)
 {
     LAPH_API_BEGIN(c)
@@ -239,11 +259,8 @@ extern "C" int sink_project(laph_ctx_t c, const double *evecs, int nv, const dou
     // tiled product: one block per (t, row tile x column tile, site range); the site
     // ranges give about 2048 blocks in all
     const int mtiles = (n_rhs * 4 + kSinkM - 1) / kSinkM, ntiles = (nv + kSinkN - 1) / kSinkN;
-    const long base = (long)c->g.nt * mtiles * ntiles;
-    long nz = std::max(1L, std::min(c->g.V3 / (8 * kSinkX), 2048 / std::max(1L, base)));
-    long xper = (c->g.V3 + nz - 1) / nz;
-    xper = (xper + kSinkX - 1) / kSinkX * kSinkX;
-    nz = (c->g.V3 + xper - 1) / xper;
+    long xper;
+    const long nz = sink_ranges(c->g, nv, n_rhs, xper);
     LAPH_CHECK(mtiles * ntiles <= 65535 && nz <= 65535, LAPH_EINVAL, "sink projection too large for one call");
     const long m = (long)n_rhs * c->g.nt * 4 * nv;
     double2 *part = (double2 *)ctx_named(c, "sink.part", sizeof(double2) * m * nz);

@@ -27,7 +27,7 @@ def L():
 
 def test_every_declared_symbol_is_exported(L):
     names = _declared()
-    assert len(names) >= 19
+    assert len(names) >= 22
     for n in names:
         assert hasattr(L, n), n
     import paper_1104_3870_amd as P
@@ -43,6 +43,20 @@ def test_only_abi_symbols_exported():
     out = subprocess.check_output(["nm", "-D", "--defined-only", P.LIB_PATH]).decode()
     text_syms = {l.split()[-1] for l in out.splitlines() if " T " in l}
     assert text_syms == set(_declared())
+
+
+def test_library_allocates_no_device_memory():
+    """The library takes every device buffer from the caller's workspace: it does not even
+    link the runtime's device allocators (pinned host memory for the solver's scalar
+    readback is the one allocation it makes)."""
+    import subprocess
+
+    import paper_1104_3870_amd as P
+
+    out = subprocess.check_output(["nm", "-D", "--undefined-only", P.LIB_PATH]).decode()
+    syms = {l.split()[-1].split("@")[0] for l in out.splitlines() if l.strip()}
+    alloc = {s for s in syms if s.startswith("hip") and ("Malloc" in s or "Free" in s or "Alloc" in s)}
+    assert alloc <= {"hipHostMalloc", "hipHostFree"}, alloc
 
 
 def test_strerror(L):
@@ -85,7 +99,7 @@ def test_create_rejects_odd_extents(L):
     assert L.laph_create(None, ctypes.byref(P.laph_geom(4, 8)), None) == P.LAPH_EINVAL
 
 
-_STRUCTS = ["laph_geom", "laph_stout", "laph_lanczos", "laph_eig_stats", "laph_dilution", "laph_dirac",
+_STRUCTS = ["laph_geom", "laph_stout", "laph_lanczos", "laph_eig_stats", "laph_dilution", "laph_dirac", "laph_hop",
             "laph_solver", "laph_solve_stats", "laph_adam", "laph_tune_entry", "laph_tune_report",
             "laph_kernel_timing", "laph_timing"]
 

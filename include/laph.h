@@ -355,6 +355,19 @@ LAPH_API int laph_autotune(laph_ctx_t ctx, const double *U, const laph_dirac *di
 LAPH_API int sink_project(laph_ctx_t ctx, const double *evecs, int nv, const double *X, int n_rhs,
                  double *coef);
 
+/* Sink projection for callers that cannot allocate or hand over a workspace (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation): the same
+ * coefficients as sink_project (sums over site ranges may be grouped differently, so
+ * results agree to FP64 rounding), with the partial sums in a fixed device array of
+ * LAPH_SINK_NOALLOC_BYTES that each device holds from the first laph_create on it until
+ * the process ends.  The call allocates nothing and needs no workspace.  Requires
+ * n_rhs * Nt * 4 * nv * 16 <= LAPH_SINK_NOALLOC_BYTES (else LAPH_EINVAL, nothing
+ * launched).  Every call on one device shares that array: calls that overlap on one GPU
+ * (several streams or host threads) race; serialise them. */
+#define LAPH_SINK_NOALLOC_BYTES (64u << 20)
+LAPH_API int sink_project_noalloc(laph_ctx_t ctx, const double *evecs, int nv, const double *X, int n_rhs,
+                                  double *coef);
+
 /* ----------------------------------------------------------------- workspace
  * The library allocates no device memory.  Every call takes its device scratch, and the
  * context keeps the operator it derives from a gauge field (even-odd links, clover term

@@ -23,6 +23,7 @@ LAPH_OP_K, LAPH_OP_OMEGA, LAPH_OP_KDAG = range(3)
 LAPH_PREC_F64, LAPH_PREC_F32, LAPH_PREC_F16, LAPH_PREC_BF16 = range(4)
 LAPH_SOLVER_BICGSTAB, LAPH_SOLVER_CGNR, LAPH_SOLVER_FGMRES = range(3)
 LAPH_HOP_PLAIN, LAPH_HOP_INV, LAPH_HOP_INV_DAG, LAPH_HOP_PLAIN_CG = range(4)
+LAPH_SINK_NOALLOC_BYTES = 64 << 20  # fixed scratch of sink_project_noalloc (include/laph.h)
 PRECISIONS = {"f64": LAPH_PREC_F64, "f32": LAPH_PREC_F32, "f16": LAPH_PREC_F16, "bf16": LAPH_PREC_BF16}
 
 
@@ -135,6 +136,7 @@ EXPORTS = {
     "dirac_solve": (_I, [_P, _P, ctypes.POINTER(laph_dirac), _P, _P, _I, ctypes.POINTER(laph_solver),
                          ctypes.POINTER(laph_solve_stats)]),
     "sink_project": (_I, [_P, _P, _I, _P, _I, _P]),
+    "sink_project_noalloc": (_I, [_P, _P, _I, _P, _I, _P]),
     "laph_ptnet_create": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.c_uint64, ctypes.POINTER(_P)]),
     "laph_ptnet_destroy": (_I, [_P]),
     "laph_ptnet_num_weights": (_I, [_P, ctypes.POINTER(ctypes.c_size_t)]),
@@ -375,6 +377,11 @@ def dirac_solve(ctx, U, dirac, eta, x, n_rhs, solver, raise_on_noconv=True):
 def sink_project(ctx, evecs, nv, X, n_rhs, coef):
     ensure_workspace(ctx, LAPH_WS_SINK, nv=nv, n=n_rhs)
     _check(lib().sink_project(ctx, _dptr(evecs), nv, _dptr(X), n_rhs, _dptr(coef)), ctx)
+
+
+def sink_project_noalloc(ctx, evecs, nv, X, n_rhs, coef):
+    """sink_project with its partial sums in the library's fixed device array (no workspace)."""
+    _check(lib().sink_project_noalloc(ctx, _dptr(evecs), nv, _dptr(X), n_rhs, _dptr(coef)), ctx)
 
 
 def laph_autotune(ctx, U, dirac, precision="f16"):

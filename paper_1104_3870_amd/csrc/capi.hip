@@ -167,6 +167,15 @@ extern "C" int laph_create(laph_ctx_t *out, const laph_geom *geom, void *stream)
         delete c;
         return LAPH_EHIP;
     }
+    try {
+        g_current_ctx = c;
+        sink_scratch_init(c);
+    } catch (const LaphError &e) {
+        g_current_ctx = nullptr;
+        delete c;
+        return e.code;
+    }
+    g_current_ctx = nullptr;
     *out = c;
     return LAPH_OK;
 }

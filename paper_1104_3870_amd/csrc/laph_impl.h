@@ -176,6 +176,8 @@ struct laph_ctx {
     size_t ws_bytes = 0, ws_lo = 0, ws_hi = 0;
     DiracCache *ws_unit = nullptr;
     bool ws_pinned = false;
+    // device address of the fixed scratch array of sink_project_noalloc on this device
+    void *sink_scratch = nullptr;
     // autotuning: LDS tile (sites per block) per (precision, R) and the chosen R per
     // precision (0: not tuned)
     std::map<std::pair<int, int>, int> lds_tile;
@@ -225,6 +227,9 @@ inline size_t ws_align(size_t n) { return (n + 255) & ~size_t(255); }
 
 
 // ---------------------------------------------------------------- internal API
+// source.hip: look up the device address of sink_project_noalloc's scratch array (once per
+// device, with the context's device current)
+void sink_scratch_init(laph_ctx *c);
 // layout.hip
 void links_to_eo(laph_ctx *c, const double *U, double2 *g64);
 void eo64_to_eo32(laph_ctx *c, const double2 *g64, float2 *g32, long n);

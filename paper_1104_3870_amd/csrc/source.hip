@@ -1,5 +1,6 @@
 // Z4 noise, diluted LapH sources and the sink projection V_s^dag X (Sec. II, Sec. IV).
 #include <algorithm>
+#include <mutex>
 
 #include "laph_impl.h"
 
@@ -250,25 +251,81 @@ size_t sink_scratch_bytes(const Geom &g, int nv, int n_rhs)
 
 size_t source_scratch_bytes(const Geom &g, int nv) { return ws_align(sizeof(double2) * g.nt * 4 * nv); }
 
-extern "C" int sink_project(laph_ctx_t c, const double *evecs, int nv, const double *X, int n_rhs, double *coef)
+// the tiled product and the fixed-order reduction of its site ranges, partials in part
+// (room for nz_max ranges of m values; the range count is cut to fit)
+static void sink_launch(laph_ctx *c, const double *evecs, int nv, const double *X, int n_rhs, double *coef,
+                        double2 *part, long nz_max)
 {
-    LAPH_API_BEGIN(c)
-    g_current_ctx = c;
-    LAPH_CHECK(evecs && X && coef && nv > 0 && n_rhs > 0, LAPH_EINVAL, "bad arguments");
-    LAPH_CHECK(n_rhs <= 65535, LAPH_EINVAL, "n_rhs too large for one call");
-    // tiled product: one block per (t, row tile x column tile, site range); the site
-    // ranges give about 2048 blocks in all
     const int mtiles = (n_rhs * 4 + kSinkM - 1) / kSinkM, ntiles = (nv + kSinkN - 1) / kSinkN;
     long xper;
-    const long nz = sink_ranges(c->g, nv, n_rhs, xper);
+    long nz = sink_ranges(c->g, nv, n_rhs, xper);
+    if (nz > nz_max) {
+        xper = (c->g.V3 + nz_max - 1) / nz_max;
+        xper = (xper + kSinkX - 1) / kSinkX * kSinkX;
+        nz = (c->g.V3 + xper - 1) / xper;
+    }
     LAPH_CHECK(mtiles * ntiles <= 65535 && nz <= 65535, LAPH_EINVAL, "sink projection too large for one call");
     const long m = (long)n_rhs * c->g.nt * 4 * nv;
-    double2 *part = (double2 *)ctx_named(c, "sink.part", sizeof(double2) * m * nz);
     hipLaunchKernelGGL(k_sink_tiled, dim3(c->g.nt, mtiles * ntiles, nz), dim3(256), 0, c->stream,
                        (const double2 *)evecs, (const double2 *)X, c->g.V3, c->g.nt, nv, n_rhs, (int)xper, part);
     LAPH_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_sink_reduce, dim3(nblocks_for(m, 256)), dim3(256), 0, c->stream, (const double2 *)part,
                        (int)nz, m, (double2 *)coef);
     LAPH_HIP(hipGetLastError());
+}
+
+extern "C" int sink_project(laph_ctx_t c, const double *evecs, int nv, const double *X, int n_rhs, double *coef)
+{
+    LAPH_API_BEGIN(c)
+    g_current_ctx = c;
+    LAPH_CHECK(evecs && X && coef && nv > 0 && n_rhs > 0, LAPH_EINVAL, "bad arguments");
+    LAPH_CHECK(n_rhs <= 65535, LAPH_EINVAL, "n_rhs too large for one call");
+    long xper;
+    const long nz = sink_ranges(c->g, nv, n_rhs, xper);
+    const long m = (long)n_rhs * c->g.nt * 4 * nv;
+    double2 *part = (double2 *)ctx_named(c, "sink.part", sizeof(double2) * m * nz);
+    sink_launch(c, evecs, nv, X, n_rhs, coef, part, nz);
+    LAPH_API_END(c)
+}
+
+// ---------------------------------------------- sink projection without a workspace
+// The partial products of sink_project_noalloc live in this array, one copy per device,
+// held until the process ends.  Host code must not pass the array's name to a kernel (it
+// is a host-side stand-in there): it uses the device address that sink_scratch_init looks
+// up once per device.  k_sink_tiled writes every partial it sums, so nothing needs to
+// start at zero.
+constexpr size_t kSinkScratchBytes = (size_t)LAPH_SINK_NOALLOC_BYTES;
+static __device__ __align__(256) double2 scratch[kSinkScratchBytes / sizeof(double2)];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[64];  // device address of `scratch` per device ordinal
+
+// once per device, with that device current (laph_create)
+void sink_scratch_init(laph_ctx *c)
+{
+    LAPH_CHECK(c->device >= 0 && c->device < 64, LAPH_EINVAL, "device ordinal %d out of range", c->device);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[c->device]) {
+        void *ptr = nullptr;
+        LAPH_HIP(hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)));
+        LAPH_CHECK(ptr != nullptr, LAPH_EHIP, "no device address for the sink scratch array");
+        g_scratch_ptr[c->device] = ptr;
+    }
+    c->sink_scratch = g_scratch_ptr[c->device];
+}
+
+extern "C" int sink_project_noalloc(laph_ctx_t c, const double *evecs, int nv, const double *X, int n_rhs,
+                                    double *coef)
+{
+    LAPH_API_BEGIN(c)
+    g_current_ctx = c;
+    LAPH_CHECK(evecs && X && coef && nv > 0 && n_rhs > 0, LAPH_EINVAL, "bad arguments");
+    LAPH_CHECK(c->sink_scratch, LAPH_EHIP, "sink scratch array not set up on device %d", c->device);
+    const size_t m = (size_t)n_rhs * c->g.nt * 4 * nv;
+    LAPH_CHECK(m * sizeof(double2) <= kSinkScratchBytes, LAPH_EINVAL,
+               "n_rhs * Nt * 4 * nv * 16 = %zu bytes of partial sums exceed the fixed scratch of %zu bytes",
+               m * sizeof(double2), kSinkScratchBytes);
+    const long nz_max = (long)(kSinkScratchBytes / (m * sizeof(double2)));
+    sink_launch(c, evecs, nv, X, n_rhs, coef, (double2 *)c->sink_scratch, nz_max);
     LAPH_API_END(c)
 }

@@ -70,6 +70,7 @@ def _load():
                 "or_omega": (None, [_P, _P, _I, _I, _D, _D, _I, _P, _P]),
                 "or_dense_operator": (None, [_P, _P, _I, _I, _D, _D, _I, _P]),
                 "or_cgnr": (_I, [_P, _P, _I, _I, _D, _D, _P, _P, _D, _I, _P]),
+                "or_meson_function": (None, [_P, _P, _I, _I, _P, _P, _P, _P, _P]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(lib, name)
@@ -374,6 +375,26 @@ class Dirac:
         return np.linalg.norm(r) / np.linalg.norm(eta)
 
 
+def dense_solve(dirac: Dirac, B):
+    """Omega^-1 B for the columns of B [12 V, k] by dense LU (tiny lattices only)."""
+    import scipy.linalg as sla
+
+    M = dirac.dense(omega=True)
+    return sla.lu_solve(sla.lu_factor(M, check_finite=False), B, check_finite=False)
+
+
+def laph_basis(evecs):
+    """V_s as a dense [12 V, Nt 4 Nv] matrix: column (t, alpha, n) is eigenvector n of slice t
+    placed in spin alpha (canonical spinor layout)."""
+    nt, nv, ns = evecs.shape[0], evecs.shape[1], evecs.shape[2]
+    V3 = ns ** 3
+    Vfull = np.zeros((nt, V3, 4, 3, nt, 4, nv), dtype=np.complex128)
+    for t in range(nt):
+        for a in range(4):
+            Vfull[t, :, a, :, t, a, :] = evecs[t].reshape(nv, V3, 3).transpose(1, 2, 0)
+    return Vfull.reshape(nt * V3 * 12, nt * 4 * nv)
+
+
 def perambulator(dirac: Dirac, evecs):
     """Exact tau = V_s^dag Omega^-1 V_s over (t,alpha,n) x (t',alpha',n') by dense LU
     (Sec. II, exact treatment of a quark line).  Only for tiny lattices."""
@@ -394,3 +415,53 @@ def perambulator(dirac: Dirac, evecs):
 
     X = sla.lu_solve(sla.lu_factor(M, check_finite=False), Vfull, check_finite=False)
     return Vfull.conj().T @ X
+
+
+# ------------------------------------------------------------ hadron functions
+
+def spin_apply(S, f):
+    """S (4x4) applied to the spin index of a spinor field [..., 4, 3] or of LapH
+    coefficients [..., 4, Nv] (axis -2 is the spin axis in both)."""
+    return np.einsum("ab,...bc->...ac", np.asarray(S, dtype=np.complex128), f)
+
+
+def smeared_field(evecs, coef):
+    """The spinor field V_s coef of LapH coefficients coef[t, alpha, n]:
+    f(x, t, c, alpha) = sum_n V_{t,n}(x, c) coef[t, alpha, n]."""
+    nt, nv, ns = evecs.shape[0], evecs.shape[1], evecs.shape[2]
+    V = evecs.reshape(nt, nv, ns ** 3, 3)
+    f = np.einsum("tnxc,tan->txac", V, coef)
+    return np.ascontiguousarray(f.reshape(nt, ns, ns, ns, 4, 3))
+
+
+def quark_source(evecs, rho, scheme, b, bar=False):
+    """The displaced-smeared-diluted quark source of Sec. II (Eq. varrhodef) with the
+    trivial displacement, varrho^[b] = V_s P^(b) rho, as a full spinor field; with bar the
+    source of the gamma_5-Hermitian estimate, -gamma_5 gamma_4 varrho^[b] (Eq. laphpropg5)."""
+    f = source(evecs, rho, scheme, b)
+    return -spin_apply(gamma(4) @ gamma(3), f) if bar else f
+
+
+def quark_sink(evecs, X, bar=False):
+    """The quark sink of Sec. II (Eq. varphidef) with the trivial displacement,
+    varphi = S Omega^-1 V_s P^(b) rho with the LapH smearing S = V_s V_s^dag, for the
+    solution X = Omega^-1 V_s P^(b) rho; with bar gamma_5 gamma_4 varphi (Eq. laphpropg5)."""
+    f = smeared_field(evecs, sink_project(evecs, X))
+    return spin_apply(gamma(4) @ gamma(3), f) if bar else f
+
+
+def meson_function(f1, f2, c, k=(0, 0, 0), d1=(0, 0, 0), d2=(0, 0, 0)):
+    """M(t) of Sec. III.B (Eq. mesonfunc) for full spinor fields f1, f2 [Nt,Ns,Ns,Ns,4,3]
+    (f1 enters complex conjugated), spin matrix c (4x4), momentum 2 pi k / Ns and field
+    displacements d1, d2."""
+    lib = _load()
+    f1 = _c(f1)
+    f2 = _c(f2)
+    nt, ns = f1.shape[0], f1.shape[1]
+    c16 = _c(np.asarray(c, dtype=np.complex128).reshape(16))
+    ka = np.ascontiguousarray(k, dtype=np.int32)
+    a1 = np.ascontiguousarray(d1, dtype=np.int32)
+    a2 = np.ascontiguousarray(d2, dtype=np.int32)
+    out = np.empty(nt, dtype=np.complex128)
+    lib.or_meson_function(_ptr(f1), _ptr(f2), ns, nt, _ptr(c16), _ptr(ka), _ptr(a1), _ptr(a2), _ptr(out))
+    return out

@@ -387,6 +387,41 @@ void or_sink_project(const cplx *evecs, const cplx *X, int ns, int nt, int nv, c
         }
 }
 
+/* ---------------------------------------------------------- meson function
+ * Sec. III.B (Eq. mesonfunc): for two full-lattice spinor fields f1 (its complex
+ * conjugate enters) and f2,
+ *   M(t) = sum_{alpha,beta} c_{alpha beta} sum_x exp(-i p.(x + (d1 + d2)/2))
+ *          sum_a conj(f1(x,t,a,alpha)) f2(x,t,a,beta),
+ * c a 4x4 spin matrix (row-major), p = 2 pi k / Ns with k an integer triple, d1 and d2
+ * the spatial displacement vectors of the two fields in lattice units.
+ */
+void or_meson_function(const cplx *f1, const cplx *f2, int ns, int nt, const cplx *c16, const int *k,
+                       const int *d1, const int *d2, cplx *out)
+{
+    long V3 = (long)ns * ns * ns;
+    const double tw = 2.0 * acos(-1.0) / ns;
+    for (int t = 0; t < nt; t++) {
+        cplx acc = 0;
+        for (long xyz = 0; xyz < V3; xyz++) {
+            int c[4];
+            or_coords(ns, xyz, c);
+            double ph = 0;
+            for (int i = 0; i < 3; i++) ph += tw * k[i] * (c[i] + 0.5 * (d1[i] + d2[i]));
+            cplx e = cexp(-I * ph);
+            long s = xyz + V3 * t;
+            for (int al = 0; al < 4; al++)
+                for (int be = 0; be < 4; be++) {
+                    cplx g = c16[al * 4 + be];
+                    if (g == 0) continue;
+                    cplx sum = 0;
+                    for (int a = 0; a < 3; a++) sum += conj(f1[(s * 4 + al) * 3 + a]) * f2[(s * 4 + be) * 3 + a];
+                    acc += g * e * sum;
+                }
+        }
+        out[t] = acc;
+    }
+}
+
 /* ----------------------------------------------------- Dirac gamma matrices
  * The paper does not print its Dirac matrix (it names an improved anisotropic
  * clover action and Omega = gamma_4 K).  Frozen reading: Hermitian Euclidean

@@ -355,6 +355,41 @@ LAPH_API int laph_autotune(laph_ctx_t ctx, const double *U, const laph_dirac *di
 LAPH_API int sink_project(laph_ctx_t ctx, const double *evecs, int nv, const double *X, int n_rhs,
                  double *coef);
 
+/* ------------------------------------------------ hadron functions (Sec. II, III.B)
+ * Quark sources and sinks in LapH coordinates, with the trivial displacement: a quark
+ * source varrho^[b] = V_s P^(b) rho (Eq. varrhodef) has the coefficients
+ * V_s^dag varrho^[b] = P^(b) rho, and a LapH-smeared quark sink varphi^[b] = V_s V_s^dag X^[b]
+ * (Eq. varphidef) has the coefficients sink_project(X^[b]).  Coefficient arrays are
+ * device [n][Nt][4][Nv] complex (the layout of sink_project); spin matrices are HOST
+ * row-major 4x4 complex (32 doubles).
+ *
+ * laph_quark_source: the coefficients of varrho^[b] for b = b_first .. b_first + n_src - 1
+ * (noise as laph_z4_noise), or with bar = 1 those of varrho-bar = -gamma_5 gamma_4 varrho
+ * of the gamma_5-Hermitian estimate (Eq. laphpropg5). */
+LAPH_API int laph_quark_source(laph_ctx_t ctx, int nv, uint16_t noise_s, uint16_t config_k,
+                               const laph_dilution *dil, int64_t b_first, int n_src, int bar, double *out);
+/* out[r][t][alpha][n] = sum_beta S[alpha][beta] in[r][t][beta][n] for n fields (in == out
+ * allowed): e.g. S = gamma_5 gamma_4 gives the coefficients of varphi-bar (Eq. laphpropg5). */
+LAPH_API int laph_spin_apply(laph_ctx_t ctx, const double *S, const double *in, int n, int nv, double *out);
+/* Meson functions at zero momentum (Sec. III.B, Eq. mesonfunc with trivial displacements)
+ * for fields f1 = V_s a_i (entering complex conjugated) and f2 = V_s b_j:
+ *   M[t][i][j] = sum_{alpha,beta} c_{alpha beta} sum_{x,colour} conj(f1_i) f2_j
+ *              = sum_{alpha,beta} c_{alpha beta} sum_n conj(a_i[t][alpha][n]) b_j[t][beta][n]
+ * (the sums over sites and colours reduce to the LapH index, V_s^dag V_s = 1 per slice).
+ * out: device [Nt][n1][n2]; with diag = 1 (n1 == n2) only i = j: out [Nt][n1] (the
+ * internal loops of same-time quark lines). */
+LAPH_API int laph_meson_function(laph_ctx_t ctx, const double *c, const double *a, int n1, const double *b, int n2,
+                                 int nv, int diag, double *out);
+/* Meson correlator terms (Sec. III.B, Eq. mesoncorr) from meson functions, for every sink
+ * slice t_F and the source slice t0, summed over the dilution indices:
+ *   diag = 0: C[t_F] = - sum_{i,j} snk[t_F][i][j] conj(src[t0][i][j])  (snk, src [Nt][n1][n2])
+ *   diag = 1: C[t_F] = (sum_i snk[t_F][i]) conj(sum_i src[t0][i])       (snk, src [Nt][n1])
+ * (the connected term with snk = M(varphi-bar_1, varphi_2), src = M(varrho-bar_1, varrho_2);
+ * the internal-line term of isoscalars with snk = M(varrho_1, varphi_1), src = M(varphi_2,
+ * varrho_2)).  out: device [Nt] complex. */
+LAPH_API int laph_meson_correlator(laph_ctx_t ctx, const double *snk, const double *src, int n1, int n2, int diag,
+                                   int t0, double *out);
+
 /* Sink projection for callers that cannot allocate or hand over a workspace (code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation): the same
  * coefficients as sink_project (sums over site ranges may be grouped differently, so

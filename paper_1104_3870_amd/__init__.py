@@ -137,6 +137,11 @@ EXPORTS = {
                          ctypes.POINTER(laph_solve_stats)]),
     "sink_project": (_I, [_P, _P, _I, _P, _I, _P]),
     "sink_project_noalloc": (_I, [_P, _P, _I, _P, _I, _P]),
+    "laph_quark_source": (_I, [_P, _I, ctypes.c_uint16, ctypes.c_uint16, ctypes.POINTER(laph_dilution), ctypes.c_int64,
+                               _I, _I, _P]),
+    "laph_spin_apply": (_I, [_P, _P, _P, _I, _I, _P]),
+    "laph_meson_function": (_I, [_P, _P, _P, _I, _P, _I, _I, _I, _P]),
+    "laph_meson_correlator": (_I, [_P, _P, _P, _I, _I, _I, _I, _P]),
     "laph_ptnet_create": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.c_uint64, ctypes.POINTER(_P)]),
     "laph_ptnet_destroy": (_I, [_P]),
     "laph_ptnet_num_weights": (_I, [_P, ctypes.POINTER(ctypes.c_size_t)]),
@@ -382,6 +387,34 @@ def sink_project(ctx, evecs, nv, X, n_rhs, coef):
 def sink_project_noalloc(ctx, evecs, nv, X, n_rhs, coef):
     """sink_project with its partial sums in the library's fixed device array (no workspace)."""
     _check(lib().sink_project_noalloc(ctx, _dptr(evecs), nv, _dptr(X), n_rhs, _dptr(coef)), ctx)
+
+
+def _spin16(S):
+    import numpy as np
+
+    a = np.ascontiguousarray(np.asarray(S, dtype=np.complex128).reshape(16))
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def laph_quark_source(ctx, nv, noise_s, config_k, dil, b_first, n_src, out, bar=False):
+    """LapH coefficients of the quark sources varrho^[b] (or varrho-bar); out [n, Nt, 4, Nv]."""
+    ensure_workspace(ctx, LAPH_WS_SOURCE, nv=nv)
+    _check(lib().laph_quark_source(ctx, nv, noise_s, config_k, ctypes.byref(dil), b_first, n_src, int(bar),
+                                   _dptr(out)), ctx)
+
+
+def laph_spin_apply(ctx, S, inp, n, nv, out):
+    keep, p = _spin16(S)
+    _check(lib().laph_spin_apply(ctx, p, _dptr(inp), n, nv, _dptr(out)), ctx)
+
+
+def laph_meson_function(ctx, c, a, n1, b, n2, nv, out, diag=False):
+    keep, p = _spin16(c)
+    _check(lib().laph_meson_function(ctx, p, _dptr(a), n1, _dptr(b), n2, nv, int(diag), _dptr(out)), ctx)
+
+
+def laph_meson_correlator(ctx, snk, src, n1, n2, t0, out, diag=False):
+    _check(lib().laph_meson_correlator(ctx, _dptr(snk), _dptr(src), n1, n2, int(diag), t0, _dptr(out)), ctx)
 
 
 def laph_autotune(ctx, U, dirac, precision="f16"):

@@ -81,6 +81,40 @@ __global__ void k_source(const double2 *__restrict__ evecs, const double2 *__res
     for (int a = 0; a < 4; a++) out[a * 3 + c] = acc[a];
 }
 
+// LapH coefficients of the diluted quark sources varrho^[b] = V_s P^(b) rho (or, with the
+// spin matrix S set, of S varrho^[b]): out[j][t][alpha][n] = sum_beta S[alpha][beta]
+// (P^(b) rho)(t, beta, n), b = b_first + j; one lane per (j, t, n)
+struct SpinM {
+    double2 m[16];
+    int identity;
+};
+
+__global__ void k_quark_coef(const double2 *__restrict__ rho, Dil d, long b_first, int nsrc, int nt, int nv,
+                             SpinM S, double2 *__restrict__ out)
+{
+    long q = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (q >= (long)nsrc * nt * nv) return;
+    const int n = (int)(q % nv);
+    const long jt = q / nv;
+    const int t = (int)(jt % nt), j = (int)(jt / nt);
+    const long b = b_first + j;
+    const int bL = (int)(b % d.cnt[2]);
+    const int bS = (int)((b / d.cnt[2]) % d.cnt[1]);
+    const int bT = (int)(b / ((long)d.cnt[2] * d.cnt[1]));
+    const bool on = member(d, 0, t, bT) && member(d, 2, n, bL);
+    double2 v[4];
+    for (int a = 0; a < 4; a++)
+        v[a] = (on && member(d, 1, a, bS)) ? rho[((long)t * 4 + a) * nv + n] : make_double2(0.0, 0.0);
+    for (int a = 0; a < 4; a++) {
+        double2 o = v[a];
+        if (!S.identity) {
+            o = make_double2(0.0, 0.0);
+            for (int bb = 0; bb < 4; bb++) o = cadd(o, cmul(S.m[a * 4 + bb], v[bb]));
+        }
+        out[(jt * 4 + a) * nv + n] = o;
+    }
+}
+
 // Tiled sink projection: per time slice t the coefficients form the product
 // C[(r, alpha)][n] = sum_{x, c} X[r][t][x][alpha][c] conj(V[t][n][x][c]), rows (RHS, spin),
 // columns eigenvectors, contraction over the slice's sites and colours.  A block owns one
@@ -227,6 +261,42 @@ extern "C" int make_diluted_source(laph_ctx_t c, const double *evecs, int nv, ui
     long n = c->g.V * 3 * n_src;
     hipLaunchKernelGGL(k_source, dim3(nblocks_for(n, 256)), dim3(256), 0, c->stream, (const double2 *)evecs,
                        (const double2 *)rho, d, (long)b_first, n_src, c->g.V3, c->g.nt, nv, (double2 *)eta);
+    LAPH_HIP(hipGetLastError());
+    LAPH_API_END(c)
+}
+
+// The quark-source coefficients of the gamma_5-Hermitian estimate (Sec. II): varrho-bar =
+// -gamma_5 gamma_4 varrho, with the chiral-basis matrices gamma_4 = [[0, 1], [1, 0]] (2x2
+// blocks) and gamma_5 = diag(1, 1, -1, -1) written as data and multiplied here.
+static SpinM bar_matrix()
+{
+    const double g4[4][4] = {{0, 0, 1, 0}, {0, 0, 0, 1}, {1, 0, 0, 0}, {0, 1, 0, 0}};
+    const double g5[4] = {1, 1, -1, -1};
+    SpinM S;
+    S.identity = 0;
+    for (int a = 0; a < 4; a++)
+        for (int b = 0; b < 4; b++) S.m[a * 4 + b] = make_double2(-g5[a] * g4[a][b], 0.0);
+    return S;
+}
+
+extern "C" int laph_quark_source(laph_ctx_t c, int nv, uint16_t s, uint16_t k, const laph_dilution *dil,
+                                 int64_t b_first, int n_src, int bar, double *out)
+{
+    LAPH_API_BEGIN(c)
+    g_current_ctx = c;
+    LAPH_CHECK(out && dil && nv > 0 && n_src > 0, LAPH_EINVAL, "bad arguments");
+    long nb = laph_dilution_count(dil, c->g.nt, nv);
+    LAPH_CHECK(nb > 0, LAPH_EDIVIDE, "invalid dilution scheme (N/J not an integer)");
+    LAPH_CHECK(b_first >= 0 && b_first + n_src <= nb, LAPH_EINVAL, "projector index out of range");
+    double2 *rho = (double2 *)ctx_named(c, "src.rho", sizeof(double2) * c->g.nt * 4 * nv);
+    launch_z4(c, s, k, nv, rho);
+    Dil d = make_dil(dil, c->g.nt, nv);
+    SpinM S{};
+    S.identity = 1;
+    if (bar) S = bar_matrix();
+    const long n = (long)n_src * c->g.nt * nv;
+    hipLaunchKernelGGL(k_quark_coef, dim3(nblocks_for(n, 256)), dim3(256), 0, c->stream, (const double2 *)rho, d,
+                       (long)b_first, n_src, c->g.nt, nv, S, (double2 *)out);
     LAPH_HIP(hipGetLastError());
     LAPH_API_END(c)
 }

@@ -61,46 +61,103 @@ def measured_traffic(kernel):
     return {"bytes_per_launch": rec["bytes_per_launch"], "source": "%s (%s)" % (TRAFFIC, rec["profile"])}
 
 
-def cpu_baseline(cfg, U, evecs_np, dil_text, iters_sample, log_fn):
-    """The oracle timed on a bounded sample of the same workload: its CG on the normal
-    equations of Omega for source b = 0, `iters_sample` iterations, extrapolated to the
-    number of iterations the oracle needs for a full solve of that source."""
-    import numpy as np
+def _golden_iters(cfg, suffix):
+    path = os.path.join(ROOT, "tests", "golden", "oracle_cgnr_iters_%s%s.json" % (cfg.name, suffix))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if abs(rec.get("m0", 1e9) - cfg.m0) > 1e-12 or not rec.get("converged"):
+        return None
+    return rec
 
+
+def _oracle_sample(cfg, U, evecs_np, iters):
+    """Seconds per iteration of the oracle's CG on Omega^dag Omega for source b = 0."""
     import oracle
 
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     rho = oracle.z4_noise(cfg.noise_s, cfg.noise_k, cfg.nt, cfg.nv)
-    sch = oracle.parse_dilution(dil_text, cfg.nt, cfg.nv)
+    sch = oracle.parse_dilution(cfg.dilution, cfg.nt, cfg.nv)
     eta = oracle.source(evecs_np, rho, sch, 0)
     D = oracle.Dirac(U, cfg.m0, cfg.xi, cfg.csw, cfg.bc_t)
     t0 = time.time()
-    x, it, tr = D.solve(eta, tol=1e-10, maxiter=iters_sample)
+    x, it, tr = D.solve(eta, tol=1e-10, maxiter=iters)
     dt = time.time() - t0
-    n = abs(it)
+    return abs(it), dt
+
+
+def cpu_baseline(cfg, U, evecs_np, iters_sample, iters_one_core, log_fn):
+    """The oracle timed on a bounded sample of the same workload: its (unpreconditioned,
+    full-lattice) CG on the normal equations of Omega for LapH source b = 0, a few
+    iterations on all host threads (and, in a child process, on one), scaled by the
+    iterations the oracle needs for a full solve of that source."""
+    import subprocess
+
+    import numpy as np
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    n, dt = _oracle_sample(cfg, U, evecs_np, iters_sample)
     per_iter = dt / max(n, 1)
-    full = None
-    path = os.path.join(ROOT, "tests", "golden", "oracle_cgnr_iters_%s.json" % cfg.name)
-    if os.path.exists(path):
-        with open(path) as f:
-            rec = json.load(f)
-        if abs(rec.get("m0", 1e9) - cfg.m0) < 1e-12:
-            full = int(rec["iterations"])
-    est_iters = full if full else None
-    value = (1.0 / (per_iter * est_iters)) if est_iters else None
+    rec = _golden_iters(cfg, "_laph")
+    what = "that LapH source"
+    if rec is None:
+        rec = _golden_iters(cfg, "")
+        what = "a Gaussian source of this workload (no count for the LapH source is stored)"
+    full = int(rec["iterations"]) if rec else None
+    value = (1.0 / (per_iter * full)) if full else None
+    one = None
+    if iters_one_core > 0:
+        # one thread: a child process (the oracle's OpenMP pool is sized at load time)
+        tmp = os.path.join("/tmp", "laph_oracle_sample_%d.npz" % os.getpid())
+        np.savez(tmp, U=U, V=evecs_np)
+        code = ("import sys, json, numpy as np; sys.path.insert(0, %r); import bench, synth; "
+                "d = np.load(%r); cfg = synth.CONFIGS[%r]; "
+                "print(json.dumps(bench._oracle_sample(cfg, d['U'], d['V'], %d)))" % (ROOT, tmp, cfg.name,
+                                                                                      iters_one_core))
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        try:
+            out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+            n1, dt1 = json.loads(out.stdout.strip().splitlines()[-1])
+            one = {"value": (1.0 / (dt1 / max(n1, 1) * full)) if full else None, "cores": 1,
+                   "seconds_per_iteration": dt1 / max(n1, 1), "sample_iterations": n1}
+        except Exception as e:  # the one-core figure is context only
+            log_fn("one-core oracle sample failed: %s" % e)
+        finally:
+            if os.path.exists(tmp):
+                os.remove(tmp)
     log_fn("cpu oracle: %d CGNR iterations in %.1f s (%.2f s/iter), full solve %s iterations"
-           % (n, dt, per_iter, est_iters))
+           % (n, dt, per_iter, full))
     return {
         "value": value,
         "unit": "sources/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": "%d iterations of the oracle's CG on Omega^dag Omega for source b=0 of the %s workload "
-                  "(%.1f s, %.3f s/iteration), scaled by the %s iterations the oracle needs for that "
-                  "source at true residual 1e-10" % (n, cfg.name, dt, per_iter,
-                                                     est_iters if est_iters else "(unknown)"),
+        "sample": "%d iterations of the oracle's CG on Omega^dag Omega (full lattice, no even-odd "
+                  "preconditioning) for LapH source b=0 of the %s workload (%.1f s, %.3f s/iteration), "
+                  "scaled by the %s iterations the oracle needs at true residual 1e-10 for %s; the GPU "
+                  "solves the even-odd system, whose CG needs ~366 iterations" % (
+                      n, cfg.name, dt, per_iter, full if full else "(unknown)", what),
         "seconds_per_iteration": per_iter,
+        "one_core": one,
     }
+
+
+def hop_roofline(k):
+    """HBM roofline of one kernel from the library's per-kernel event timing: algorithmic
+    bytes per launch over the average launch duration, and the counter traffic when a
+    summary for the kernel's current source exists."""
+    avg_ms = k["ms"] / max(k["launches"], 1)
+    bpl = k["bytes"] / max(k["launches"], 1)
+    achieved = bpl / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    traffic = measured_traffic(k["kernel"])
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic["bytes_per_launch"] if traffic else None,
+            "traffic_source": traffic["source"] if traffic else None,
+            "traffic_rate_frac": (round(traffic["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                  if traffic and avg_ms > 0 else None),
+            "kernel": k["kernel"], "avg_launch_ms": round(avg_ms, 4), "launches": k["launches"],
+            "algorithmic_bytes_per_launch": bpl}
 
 
 def main():
@@ -110,20 +167,24 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ns24_nt128")
     ap.add_argument("--precision", default="f16")
-    ap.add_argument("--block", type=int, default=32)
+    ap.add_argument("--block", type=int, default=0, help="right-hand sides per batch (0: the autotuner's choice)")
+    ap.add_argument("--graph", type=int, default=1, help="replay the CG iteration from HIP graphs")
     ap.add_argument("--solver", default="cgnr", choices=["cgnr", "bicgstab"],
                     help="Krylov method of both forms (BiCGStab breaks down near the critical mass "
                          "of this workload; CG on the normal equations is the paper's fallback)")
     ap.add_argument("--fp64-steps", type=int, default=1, help="batches timed with the plain FP64 solver")
     ap.add_argument("--cpu-iters", type=int, default=8, help="oracle CG iterations in the CPU sample (0: skip)")
+    ap.add_argument("--cpu-iters-1core", type=int, default=2, help="oracle CG iterations on one thread (0: skip)")
+    ap.add_argument("--hadron-reps", type=int, default=20, help="timed meson-function launches (0: skip)")
     ap.add_argument("--m0", type=float, default=None)
     ap.add_argument("--reliable-delta", type=float, default=0.03,
                     help="reliable-update threshold (measured best on this workload; library default 0.1)")
     ap.add_argument("--reliable-every", type=int, default=50)
     ap.add_argument("--guess", default="none", choices=["none", "net"],
                     help="initial guess of the headline form: zero, or the trained network's N(gamma_4 eta)")
-    ap.add_argument("--learned-mixed-steps", type=int, default=1,
-                    help="steps of the headline form with the trained network's initial guess (0: skip)")
+    ap.add_argument("--learned-mixed-steps", type=int, default=-1,
+                    help="steps of the headline form with the trained network's initial guess (0: skip; "
+                         "-1: as many as the headline)")
     ap.add_argument("--learned-sources", type=int, default=2,
                     help="sources solved with FGMRES and the learned preconditioner (0: skip)")
     args = ap.parse_args()
@@ -188,8 +249,17 @@ def main():
         w, guess_meta = T.load(os.path.join(ROOT, "paper_1104_3870_amd", "weights", "ptnet.npz"))
         guess_net = P.PTNet(L.ctx, guess_meta["channels"])
         guess_net.set_weights(w)
-    best = P.solver_params(net=guess_net, tol=cfg.solve_tol, maxiter=6000, precision=args.precision, block_rhs=args.block,
-                           solver=kind, reliable_every=args.reliable_every, reliable_delta=args.reliable_delta)
+    tune = None
+    if args.block == 0:
+        # the autotuner picks the block size and tile (the solve reuses its choice)
+        t_tune = time.time()
+        tune = P.laph_autotune(L.ctx, Ud, prm, args.precision)
+        tune["seconds"] = round(time.time() - t_tune, 2)
+        log("autotuner: R = %d, %d sites per block" % (tune["best_block_rhs"], tune["best_sites_per_block"]))
+    block = args.block if args.block else tune["best_block_rhs"]
+    best = P.solver_params(net=guess_net, tol=cfg.solve_tol, maxiter=6000, precision=args.precision,
+                           block_rhs=args.block, solver=kind, reliable_every=args.reliable_every,
+                           reliable_delta=args.reliable_delta, use_graph=args.graph)
     plain = P.solver_params(tol=cfg.solve_tol, maxiter=6000, precision="f64", block_rhs=1, solver=kind)
     t_setup = time.time() - t_setup
 
@@ -197,9 +267,7 @@ def main():
     for k in range(args.warmup):
         st = step(k, best)
         log("warmup %d: iters %s" % (k, sorted(s.iters for s in st)[::8]))
-    torch.cuda.synchronize()
-    P.laph_set_timing(L.ctx, True)
-    P.laph_get_timing(L.ctx, reset=True)
+    # the production form: no per-kernel events (they would also switch the graphs off)
     iters, resid = [], []
     torch.cuda.synchronize()
     t0 = time.time()
@@ -210,29 +278,47 @@ def main():
         log("step %d done (%.1f s): max true residual %.2e" % (k, time.time() - t0, max(s.true_resid for s in st)))
     torch.cuda.synchronize()
     elapsed = time.time() - t0
+    value = nsrc * args.steps / elapsed
+
+    # ---------------- instrumented step: the same kernels and launch shapes with HIP events
+    # around every hopping launch on the library's stream (graphs off), for the roofline
+    P.laph_set_timing(L.ctx, True)
+    P.laph_get_timing(L.ctx, reset=True)
+    torch.cuda.synchronize()
+    t_ins = time.time()
+    step(args.warmup + args.steps, best)
+    torch.cuda.synchronize()
+    t_ins = time.time() - t_ins
     tm = P.laph_get_timing(L.ctx, reset=True)
     P.laph_set_timing(L.ctx, False)
-    value = nsrc * args.steps / elapsed
 
     # ---------------- plain FP64 solver, one right-hand side at a time
     fp64 = None
     if args.fp64_steps > 0:
+        # its hops are timed too (events cost far less than these latency-bound launches)
+        P.laph_set_timing(L.ctx, True)
+        P.laph_get_timing(L.ctx, reset=True)
         torch.cuda.synchronize()
         t1 = time.time()
-        it64 = []
+        it64, r64 = [], []
         for k in range(args.fp64_steps):
             st = step(k, plain)
             it64 += [s.iters for s in st]
+            r64 += [s.true_resid for s in st]
             log("fp64 step %d done (%.1f s)" % (k, time.time() - t1))
         torch.cuda.synchronize()
         e64 = time.time() - t1
+        tm64 = P.laph_get_timing(L.ctx, reset=True)
+        P.laph_set_timing(L.ctx, False)
         fp64 = {"value": nsrc * args.fp64_steps / e64, "unit": "sources/s", "steps": args.fp64_steps,
                 "ms_per_step": 1000 * e64 / args.fp64_steps, "mean_iters": float(np.mean(it64)),
-                "form": "FP64 even-odd %s, one right-hand side at a time" % args.solver.upper()}
+                "max_true_resid": float(max(r64)),
+                "form": "FP64 even-odd %s, one right-hand side at a time" % args.solver.upper(),
+                "roofline": hop_roofline(tm64[0]) if tm64 else None}
 
     # ---------------- learned + mixed + multi-RHS: the headline form started from N(gamma_4 eta)
     learned_mixed = None
-    if args.learned_mixed_steps > 0 and guess_net is None:
+    if args.learned_mixed_steps != 0 and guess_net is None:
         from paper_1104_3870_amd import train_ptnet as T
 
         w, meta = T.load(os.path.join(ROOT, "paper_1104_3870_amd", "weights", "ptnet.npz"))
@@ -240,17 +326,20 @@ def main():
         gnet.set_weights(w)
         svg = P.solver_params(net=gnet, tol=cfg.solve_tol, maxiter=6000, precision=args.precision,
                               block_rhs=args.block, solver=kind, reliable_every=args.reliable_every,
-                              reliable_delta=args.reliable_delta)
+                              reliable_delta=args.reliable_delta, use_graph=args.graph)
+        nlm = args.learned_mixed_steps if args.learned_mixed_steps > 0 else args.steps
+        step(0, svg)  # warm-up of the network's path
         torch.cuda.synchronize()
         t3 = time.time()
-        itg = []
-        for k in range(args.learned_mixed_steps):
-            st = step(k, svg)
+        itg, rg = [], []
+        for k in range(nlm):
+            st = step(args.warmup + k, svg)
             itg += [q.iters for q in st]
+            rg += [q.true_resid for q in st]
         torch.cuda.synchronize()
         eg = time.time() - t3
-        learned_mixed = {"value": round(nsrc * args.learned_mixed_steps / eg, 4), "unit": "sources/s",
-                         "steps": args.learned_mixed_steps, "mean_iters": float(np.mean(itg)),
+        learned_mixed = {"value": round(nsrc * nlm / eg, 4), "unit": "sources/s",
+                         "steps": nlm, "mean_iters": float(np.mean(itg)), "max_true_resid": float(max(rg)),
                          "form": "headline form with the initial guess x0 = N(gamma_4 eta) of the trained PT-net"}
         log("learned + mixed: %.3f sources/s, %.1f iterations" % (learned_mixed["value"], learned_mixed["mean_iters"]))
         gnet.close()
@@ -296,32 +385,68 @@ def main():
         log("learned: %d sources in %.2f s, iterations %s" % (nl, el, [q.iters for q in st]))
         net.close()
 
-    # roofline of the dominant kernel (largest summed duration in the timed region)
-    traffic = measured_traffic(tm[0]["kernel"] if tm else None)
+    # ---------------- hadron functions on the last step's quark lines (Sec. III.B): the
+    # meson function of the barred sinks with themselves and of the barred sources, then
+    # the connected correlator; timed with events on the library's (torch's current) stream
+    hadron = None
+    if args.hadron_reps > 0:
+        nv, nt = cfg.nv, cfg.nt
+        t_src = times[(args.warmup + args.steps) % len(times)]
+        b0 = t_src * 4 * 8
+        g5 = np.diag([1.0, 1.0, -1.0, -1.0]).astype(np.complex128)
+        g5g4 = g5 @ np.array([[0, 0, 1, 0], [0, 0, 0, 1], [1, 0, 0, 0], [0, 1, 0, 0]], dtype=np.complex128)
+        sbar = torch.empty_like(coef)
+        P.laph_spin_apply(L.ctx, g5g4, coef, nsrc, nv, sbar)
+        rbar = torch.empty_like(coef)
+        r2 = torch.empty_like(coef)
+        P.laph_quark_source(L.ctx, nv, cfg.noise_s, cfg.noise_k, dil, b0, nsrc, rbar, bar=True)
+        P.laph_quark_source(L.ctx, nv, cfg.noise_s, cfg.noise_k, dil, b0, nsrc, r2)
+        msnk = torch.empty((nt, nsrc, nsrc), dtype=torch.complex128, device="cuda")
+        msrc = torch.empty_like(msnk)
+        corr = torch.empty(nt, dtype=torch.complex128, device="cuda")
+        P.laph_meson_function(L.ctx, g5, sbar, nsrc, coef, nsrc, nv, msnk)  # warm-up
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(args.hadron_reps):
+            P.laph_meson_function(L.ctx, g5, sbar, nsrc, coef, nsrc, nv, msnk)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms_m = ev0.elapsed_time(ev1) / args.hadron_reps
+        P.laph_meson_function(L.ctx, g5, rbar, nsrc, r2, nsrc, nv, msrc)
+        P.laph_meson_correlator(L.ctx, msnk, msrc, nsrc, nsrc, t_src, corr)
+        torch.cuda.synchronize()
+        mbytes = (2 * nsrc * nt * 4 * nv + nt * nsrc * nsrc) * 16.0
+        mflops = 8.0 * nt * nsrc * nsrc * 4 * nv + 2 * 4 * 4 * 8.0 * nsrc * nt * nv
+        hadron = {"kernel": "meson_function (%d x %d quark lines, Nt = %d, N_v = %d)" % (nsrc, nsrc, nt, nv),
+                  "avg_launch_ms": round(ms_m, 4),
+                  "roofline": {"bound": "hbm", "achieved": round(mbytes / (ms_m * 1e-3) / 1e9, 1),
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(mbytes / (ms_m * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                               "algorithmic_bytes_per_launch": mbytes},
+                  "gflops": round(mflops / (ms_m * 1e-3) / 1e9, 1),
+                  "fp64_frac": round(mflops / (ms_m * 1e-3) / 78.6e12, 4)}
+        log("meson function: %.3f ms per launch" % ms_m)
+
+    # roofline of the dominant kernel (largest summed duration in the instrumented step)
     dom = tm[0] if tm else {"kernel": "none", "ms": 0.0, "launches": 0, "bytes": 0.0}
-    avg_ms = dom["ms"] / max(dom["launches"], 1)
-    bytes_per_launch = dom["bytes"] / max(dom["launches"], 1)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic["bytes_per_launch"] if traffic else None,
-                "traffic_source": traffic["source"] if traffic else None,
-                "traffic_rate_frac": (round(traffic["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-                                      if traffic and avg_ms > 0 else None),
-                "kernel": dom["kernel"], "avg_launch_ms": round(avg_ms, 4), "launches": dom["launches"],
-                "algorithmic_bytes_per_launch": bytes_per_launch,
-                "share_of_timed_region": round(dom["ms"] / (1000 * elapsed), 3),
-                "other_kernels": [{"kernel": k["kernel"], "launches": k["launches"],
-                                   "avg_launch_ms": round(k["ms"] / max(k["launches"], 1), 4)} for k in tm[1:]]}
+    roofline = hop_roofline(dom)
+    roofline["measured"] = ("HIP events around every hopping launch on the library's stream during one "
+                            "instrumented step after the timed region (same kernels and launch shapes; "
+                            "graphs off in that step)")
+    roofline["share_of_instrumented_step"] = round(dom["ms"] / (1000 * t_ins), 3) if t_ins > 0 else None
+    roofline["other_kernels"] = [{"kernel": k["kernel"], "launches": k["launches"],
+                                  "avg_launch_ms": round(k["ms"] / max(k["launches"], 1), 4)} for k in tm[1:]]
 
     # the same kernel against the FP32 vector peak: the multi-RHS hop is bound by VALU issue
     # (SQ counters), not by HBM. Algorithmic flops per output site and RHS: 1320 for the
     # hopping term, 504 per clover(-inverse) block application
+    avg_ms = roofline["avg_launch_ms"]
     flops_site = {"plain": 1320, "plain_cg": 1320, "inv": 1824, "inv_dag": 2328}
     mode = dom["kernel"].split(",")[1] if dom["kernel"].count(",") >= 2 else None
+    rb = int(dom["kernel"].rsplit("R", 1)[1].rstrip(">")) if "R" in dom["kernel"] else block
     roofline_alu = None
     if mode in flops_site and dom["kernel"].startswith("dslash_lds") and avg_ms > 0:
-        fl = flops_site[mode] * (cfg.ns ** 3 * cfg.nt // 2) * args.block
+        fl = flops_site[mode] * (cfg.ns ** 3 * cfg.nt // 2) * rb
         tf = fl / (avg_ms * 1e-3) / 1e12
         roofline_alu = {"bound": "alu", "achieved": round(tf, 2), "peak": FP32_VECTOR_PEAK_TFS, "unit": "TFLOP/s",
                         "frac": round(tf / FP32_VECTOR_PEAK_TFS, 4), "flops_per_launch": fl,
@@ -330,7 +455,7 @@ def main():
 
     cpu = None
     if args.cpu_iters > 0:
-        cpu = cpu_baseline(cfg, U, evecs.cpu().numpy(), cfg.dilution, args.cpu_iters, log)
+        cpu = cpu_baseline(cfg, U, evecs.cpu().numpy(), args.cpu_iters, args.cpu_iters_1core, log)
 
     out = {
         "metric": "LapH sources solved/s @ FP64 resid 1e-10",
@@ -349,18 +474,24 @@ def main():
                                "32 sources per step" if cfg.name == "ns24_nt128" else cfg.name,
                    "lattice": [cfg.ns, cfg.ns, cfg.ns, cfg.nt], "nv": cfg.nv, "m0": cfg.m0,
                    "dilution": cfg.dilution, "sources_per_step": nsrc,
-                   "form": "even-odd %s, %s inner vectors, %d right-hand sides per batch, FP64 reliable "
-                           "updates%s" % (args.solver.upper(), args.precision, args.block,
-                                          ", initial guess from the trained PT-net" if guess_net else "")},
+                   "form": "even-odd %s, %s inner vectors, %d right-hand sides per batch (%s), FP64 reliable "
+                           "updates, CG iteration %s%s" % (
+                               args.solver.upper(), args.precision, block,
+                               "autotuned" if args.block == 0 else "fixed",
+                               "replayed from HIP graphs" if args.graph else "launched eagerly",
+                               ", initial guess from the trained PT-net" if guess_net else "")},
         "mean_iters": float(np.mean(iters)),
         "max_true_resid": float(max(resid)),
         "fp64_plain": fp64,
         "speedup_vs_fp64": round(value / fp64["value"], 3) if fp64 else None,
         "learned_mixed": learned_mixed,
         "learned": learned,
+        "ms_per_step_instrumented": round(1000 * t_ins, 2),
+        "autotune": tune,
         "setup_s": {"total": round(t_setup, 2), "eigvecs": round(t_eig, 2), "eig_restarts": est.restarts},
         "roofline": roofline,
         "roofline_alu": roofline_alu,
+        "hadron_functions": hadron,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

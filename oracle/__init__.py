@@ -71,6 +71,8 @@ def _load():
                 "or_dense_operator": (None, [_P, _P, _I, _I, _D, _D, _I, _P]),
                 "or_cgnr": (_I, [_P, _P, _I, _I, _D, _D, _P, _P, _D, _I, _P]),
                 "or_meson_function": (None, [_P, _P, _I, _I, _P, _P, _P, _P, _P]),
+                "or_displace": (None, [_P, _I, _I, _I, _I, _I, _P, _P]),
+                "or_mom_overlap": (None, [_P, _P, _I, _I, _I, _I, _P, _P]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(lib, name)
@@ -464,4 +466,49 @@ def meson_function(f1, f2, c, k=(0, 0, 0), d1=(0, 0, 0), d2=(0, 0, 0)):
     a2 = np.ascontiguousarray(d2, dtype=np.int32)
     out = np.empty(nt, dtype=np.complex128)
     lib.or_meson_function(_ptr(f1), _ptr(f2), ns, nt, _ptr(c16), _ptr(ka), _ptr(a1), _ptr(a2), _ptr(out))
+    return out
+
+
+def displace(U, v, direction, sign, length=3):
+    """Covariant displacement of a colour field v [Nt,Ns,Ns,Ns,3] by `length` links along
+    spatial direction 0..2 with sign +-1 (Sec. II, displacement types D^(j))."""
+    lib = _load()
+    U = _c(U)
+    v = _c(v)
+    ns, nt = dims_from_links(U)
+    out = np.empty_like(v)
+    lib.or_displace(_ptr(U), ns, nt, int(direction), int(sign), int(length), _ptr(v), _ptr(out))
+    return out
+
+
+def displace_spinor(U, f, direction, sign, length=3):
+    """The displacement applied to every spin component of a spinor field [...,4,3]."""
+    out = np.empty_like(f)
+    for a in range(4):
+        out[..., a, :] = displace(U, np.ascontiguousarray(f[..., a, :]), direction, sign, length)
+    return out
+
+
+def displace_evecs(U, evecs, direction, sign, length=3):
+    """The displacement of every vector of an eigenvector-layout array [Nt,n,Ns,Ns,Ns,3]
+    (vectors of one slice stay on that slice)."""
+    nt, n = evecs.shape[0], evecs.shape[1]
+    out = np.empty_like(evecs)
+    for j in range(n):
+        full = np.ascontiguousarray(evecs[:, j])  # [Nt, Ns, Ns, Ns, 3]: a field on the whole lattice
+        out[:, j] = displace(U, full, direction, sign, length)
+    return out
+
+
+def mom_overlap(a, b, k=(0, 0, 0)):
+    """O[t][n][m] = sum_x exp(-i 2 pi k.x / Ns) sum_c conj(a_n) b_m on every slice, for
+    eigenvector-layout arrays a [Nt,na,Ns,Ns,Ns,3] and b [Nt,nb,...]."""
+    lib = _load()
+    a = _c(a)
+    b = _c(b)
+    nt, na, ns = a.shape[0], a.shape[1], a.shape[2]
+    nb = b.shape[1]
+    ka = np.ascontiguousarray(k, dtype=np.int32)
+    out = np.empty((nt, na, nb), dtype=np.complex128)
+    lib.or_mom_overlap(_ptr(a), _ptr(b), ns, nt, na, nb, _ptr(ka), _ptr(out))
     return out

@@ -387,6 +387,70 @@ void or_sink_project(const cplx *evecs, const cplx *X, int ns, int nt, int nv, c
         }
 }
 
+/* ------------------------------------------------------ covariant displacement
+ * Sec. II (quark lines D^(j) S Omega^-1 S D^(k)dag): a displacement of type j moves a field
+ * by `len` links along spatial direction dir (0, 1, 2 = x, y, z) with sign +1 or -1, in a
+ * gauge-covariant way:
+ *   (D v)(x) = U_dir(x) U_dir(x+e) ... U_dir(x+(len-1)e) v(x+len e)                 (+)
+ *   (D v)(x) = U_dir(x-e)^dag U_dir(x-2e)^dag ... U_dir(x-len e)^dag v(x-len e)       (-)
+ * on colour fields v[s*3 + c] over the whole lattice (each time slice separately; the
+ * links are the caller's, e.g. the stout-smeared ones of the LapH subspace).
+ */
+void or_displace(const cplx *U, int ns, int nt, int dir, int sign, int len, const cplx *v, cplx *out)
+{
+    long V = (long)ns * ns * ns * nt;
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; s++) {
+        /* walk to the far end, then apply the links back towards s */
+        long far = s;
+        for (int k = 0; k < len; k++) far = or_neighbor(ns, nt, far, dir, sign);
+        cplx w[3] = {v[far * 3], v[far * 3 + 1], v[far * 3 + 2]};
+        long cur = far;
+        for (int k = 0; k < len; k++) {
+            long prev = or_neighbor(ns, nt, cur, dir, -sign); /* one step back towards s */
+            cplx L[9];
+            if (sign > 0)
+                memcpy(L, or_link(U, prev, dir), sizeof(L)); /* U_dir(prev) w(prev + e) */
+            else
+                m3_dag(or_link(U, cur, dir), L);             /* U_dir(cur)^dag w(cur), cur = prev - e */
+            cplx r[3];
+            for (int a = 0; a < 3; a++) r[a] = L[a * 3] * w[0] + L[a * 3 + 1] * w[1] + L[a * 3 + 2] * w[2];
+            memcpy(w, r, sizeof(w));
+            cur = prev;
+        }
+        memcpy(out + s * 3, w, sizeof(w));
+    }
+}
+
+/* -------------------------------------------------------- momentum overlaps
+ * The momentum projection of the meson function (Sec. III.B, Eq. mesonfunc) between two
+ * sets of colour fields on every slice:
+ *   O[t][n][m] = sum_{x in slice t} exp(-i p.x) sum_c conj(a_n(x,c)) b_m(x,c),
+ * p = 2 pi k / Ns; a, b in the eigenvector layout [Nt][n][Ns^3][3].
+ */
+void or_mom_overlap(const cplx *a, const cplx *b, int ns, int nt, int na, int nb, const int *k, cplx *out)
+{
+    long V3 = (long)ns * ns * ns;
+    const double tw = 2.0 * acos(-1.0) / ns;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int t = 0; t < nt; t++)
+        for (int n = 0; n < na; n++)
+            for (int m = 0; m < nb; m++) {
+                const cplx *va = a + ((long)t * na + n) * V3 * 3;
+                const cplx *vb = b + ((long)t * nb + m) * V3 * 3;
+                cplx acc = 0;
+                for (long xyz = 0; xyz < V3; xyz++) {
+                    int c[4];
+                    or_coords(ns, xyz, c);
+                    cplx e = cexp(-I * tw * (k[0] * c[0] + k[1] * c[1] + k[2] * c[2]));
+                    cplx sum = 0;
+                    for (int cc = 0; cc < 3; cc++) sum += conj(va[xyz * 3 + cc]) * vb[xyz * 3 + cc];
+                    acc += e * sum;
+                }
+                out[((long)t * na + n) * nb + m] = acc;
+            }
+}
+
 /* ---------------------------------------------------------- meson function
  * Sec. III.B (Eq. mesonfunc): for two full-lattice spinor fields f1 (its complex
  * conjugate enters) and f2,

@@ -426,6 +426,38 @@ def main():
                   "gflops": round(mflops / (ms_m * 1e-3) / 1e9, 1),
                   "fp64_frac": round(mflops / (ms_m * 1e-3) / 78.6e12, 4)}
         log("meson function: %.3f ms per launch" % ms_m)
+        # displaced LapH vectors and their momentum overlaps (Sec. II displacement types,
+        # Sec. III.B momentum projection) on the stout-smeared field
+        Usm = torch.empty_like(Ud)
+        P.laph_stout_smear(L.ctx, Ud, cfg.stout_rho, cfg.stout_steps, Usm)
+        Vdisp = torch.empty_like(evecs)
+        O = torch.empty((nt, nv, nv), dtype=torch.complex128, device="cuda")
+        P.laph_displace(L.ctx, Usm, 0, 1, 3, evecs, nv, Vdisp)  # warm-up
+        P.laph_mom_overlap(L.ctx, evecs, nv, Vdisp, nv, (1, 0, 0), O)
+        ev0.record()
+        P.laph_displace(L.ctx, Usm, 0, 1, 3, evecs, nv, Vdisp)
+        ev1.record()
+        ev2 = torch.cuda.Event(enable_timing=True)
+        P.laph_mom_overlap(L.ctx, evecs, nv, Vdisp, nv, (1, 0, 0), O)
+        ev2.record()
+        torch.cuda.synchronize()
+        ms_d, ms_o = ev0.elapsed_time(ev1), ev1.elapsed_time(ev2)
+        V3 = cfg.ns ** 3
+        dbytes = nt * V3 * (2 * nv * 48.0 + 3 * 144.0)  # vectors in and out, three links per site once
+        obytes = 2 * nt * nv * V3 * 48.0 + nt * nv * nv * 16.0
+        oflops = 8.0 * nt * nv * nv * 3 * V3
+        hadron["displace"] = {"kernel": "displace (%d vectors per slice, 3 links)" % nv, "ms": round(ms_d, 3),
+                              "roofline": {"bound": "hbm", "achieved": round(dbytes / (ms_d * 1e-3) / 1e9, 1),
+                                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                           "frac": round(dbytes / (ms_d * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+        hadron["mom_overlap"] = {"kernel": "mom_overlap (%d x %d per slice, K = 3 Ns^3)" % (nv, nv),
+                                 "ms": round(ms_o, 3),
+                                 "roofline": {"bound": "fp64", "achieved": round(oflops / (ms_o * 1e-3) / 1e12, 2),
+                                              "peak": 78.6, "unit": "TFLOP/s",
+                                              "frac": round(oflops / (ms_o * 1e-3) / 78.6e12, 4)},
+                                 "hbm_GBs": round(obytes / (ms_o * 1e-3) / 1e9, 1)}
+        log("displace %.3f ms, overlap %.3f ms" % (ms_d, ms_o))
+        del Usm, Vdisp, O
 
     # roofline of the dominant kernel (largest summed duration in the instrumented step)
     dom = tm[0] if tm else {"kernel": "none", "ms": 0.0, "launches": 0, "bytes": 0.0}

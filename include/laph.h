@@ -390,6 +390,29 @@ LAPH_API int laph_meson_function(laph_ctx_t ctx, const double *c, const double *
 LAPH_API int laph_meson_correlator(laph_ctx_t ctx, const double *snk, const double *src, int n1, int n2, int diag,
                                    int t0, double *out);
 
+/* Covariant displacements (Sec. II, displacement types D^(j) of the quark lines
+ * D^(j) S Omega^-1 S D^(k)dag; the paper's are typically 3 links along one spatial axis):
+ *   (D v)(x) = U_d(x) U_d(x+e) ... U_d(x+(len-1)e) v(x+len e)             sign = +1
+ *   (D v)(x) = U_d(x-e)^dag ... U_d(x-len e)^dag v(x-len e)                sign = -1
+ * for n colour fields per time slice in the eigenvector layout v[((t*n + j)*Ns^3 + xyz)*3 + c]
+ * (dir 0, 1, 2 = x, y, z; U in the ABI link layout, e.g. the stout-smeared field of the
+ * LapH subspace).  out may not alias v. */
+LAPH_API int laph_displace(laph_ctx_t ctx, const double *U, int dir, int sign, int length, const double *v, int n,
+                           double *out);
+/* Momentum overlaps of two sets of colour fields on every slice (the momentum projection
+ * of Eq. mesonfunc): O[t][i][j] = sum_{x,c} exp(-2 pi i k.x / Ns) conj(a_i(x,c)) b_j(x,c),
+ * k an integer triple (HOST int[3]); a [Nt][na][Ns^3][3], b [Nt][nb][Ns^3][3], out [Nt][na][nb].
+ * With a = D^(j) V_s and b = D^(k) V_s the displaced, momentum-projected meson function
+ * of fields D^(j) V_s a' and D^(k) V_s b' is exp(-i p.(d_j + d_k)/2) sum c conj(a') O b'. */
+LAPH_API int laph_mom_overlap(laph_ctx_t ctx, const double *a, int na, const double *b, int nb, const int *k,
+                              double *out);
+/* out[r][t][beta][i] = sum_j O[t][i][j] b[r][t][beta][j] for n coefficient arrays b with nb
+ * LapH vectors (O [Nt][na][nb] from laph_mom_overlap; out has na).  Followed by
+ * laph_meson_function(c exp(-i p.(d_j + d_k)/2), a', ., out, ...) it gives the displaced,
+ * momentum-projected meson function. */
+LAPH_API int laph_overlap_apply(laph_ctx_t ctx, const double *O, int na, int nb, const double *b, int n,
+                                double *out);
+
 /* Sink projection for callers that cannot allocate or hand over a workspace (code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation): the same
  * coefficients as sink_project (sums over site ranges may be grouped differently, so
@@ -422,7 +445,7 @@ LAPH_API int sink_project_noalloc(laph_ctx_t ctx, const double *evecs, int nv, c
  *   LAPH_WS_DIRAC_APPLY: n (= n_fields);   LAPH_WS_HOP_APPLY: hop, n (= n_fields);
  *   LAPH_WS_SOLVE: solver, n (= n_rhs) (a learned network is taken from solver->net);
  *   LAPH_WS_AUTOTUNE: precision;   LAPH_WS_PTNET_FORWARD / _BACKWARD / _TRAIN: net, n
- *   (= n_fields or n_pairs).
+ *   (= n_fields or n_pairs);   LAPH_WS_MOM_OVERLAP: none.  The other calls need no workspace.
  * Returns 0 for an unknown op or missing parameters. */
 enum {
     LAPH_WS_STOUT = 0,
@@ -438,7 +461,8 @@ enum {
     LAPH_WS_SINK = 10,
     LAPH_WS_PTNET_FORWARD = 11,
     LAPH_WS_PTNET_BACKWARD = 12,
-    LAPH_WS_PTNET_TRAIN = 13
+    LAPH_WS_PTNET_TRAIN = 13,
+    LAPH_WS_MOM_OVERLAP = 14
 };
 
 typedef struct {

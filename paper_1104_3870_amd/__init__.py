@@ -140,6 +140,9 @@ EXPORTS = {
     "laph_quark_source": (_I, [_P, _I, ctypes.c_uint16, ctypes.c_uint16, ctypes.POINTER(laph_dilution), ctypes.c_int64,
                                _I, _I, _P]),
     "laph_spin_apply": (_I, [_P, _P, _P, _I, _I, _P]),
+    "laph_displace": (_I, [_P, _P, _I, _I, _I, _P, _I, _P]),
+    "laph_mom_overlap": (_I, [_P, _P, _I, _P, _I, _P, _P]),
+    "laph_overlap_apply": (_I, [_P, _P, _I, _I, _P, _I, _P]),
     "laph_meson_function": (_I, [_P, _P, _P, _I, _P, _I, _I, _I, _P]),
     "laph_meson_correlator": (_I, [_P, _P, _P, _I, _I, _I, _I, _P]),
     "laph_ptnet_create": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.c_uint64, ctypes.POINTER(_P)]),
@@ -211,7 +214,7 @@ def _hptr(a):
 # ------------------------------------------------------------------ workspace
 (LAPH_WS_STOUT, LAPH_WS_LAPLACIAN, LAPH_WS_CHEBYSHEV, LAPH_WS_EIGVECS, LAPH_WS_NOISE, LAPH_WS_SOURCE,
  LAPH_WS_DIRAC_APPLY, LAPH_WS_HOP_APPLY, LAPH_WS_SOLVE, LAPH_WS_AUTOTUNE, LAPH_WS_SINK, LAPH_WS_PTNET_FORWARD,
- LAPH_WS_PTNET_BACKWARD, LAPH_WS_PTNET_TRAIN) = range(14)
+ LAPH_WS_PTNET_BACKWARD, LAPH_WS_PTNET_TRAIN, LAPH_WS_MOM_OVERLAP) = range(15)
 
 _WS = {}  # context handle value -> workspace tensor
 
@@ -415,6 +418,24 @@ def laph_meson_function(ctx, c, a, n1, b, n2, nv, out, diag=False):
 
 def laph_meson_correlator(ctx, snk, src, n1, n2, t0, out, diag=False):
     _check(lib().laph_meson_correlator(ctx, _dptr(snk), _dptr(src), n1, n2, int(diag), t0, _dptr(out)), ctx)
+
+
+def laph_displace(ctx, U, direction, sign, length, v, n, out):
+    """Covariant displacement of n colour fields per slice (eigenvector layout)."""
+    _check(lib().laph_displace(ctx, _dptr(U), direction, sign, length, _dptr(v), n, _dptr(out)), ctx)
+
+
+def laph_mom_overlap(ctx, a, na, b, nb, k, out):
+    ensure_workspace(ctx, LAPH_WS_MOM_OVERLAP)
+    import numpy as np
+
+    ka = np.ascontiguousarray(k, dtype=np.int32)
+    _check(lib().laph_mom_overlap(ctx, _dptr(a), na, _dptr(b), nb, ka.ctypes.data_as(ctypes.c_void_p), _dptr(out)),
+           ctx)
+
+
+def laph_overlap_apply(ctx, O, na, nb, b, n, out):
+    _check(lib().laph_overlap_apply(ctx, _dptr(O), na, nb, _dptr(b), n, _dptr(out)), ctx)
 
 
 def laph_autotune(ctx, U, dirac, precision="f16"):

@@ -23,6 +23,7 @@ extern "C" size_t laph_workspace_bytes(laph_ctx_t c, int op, const void *params)
         case LAPH_WS_LAPLACIAN: return ws_align((size_t)27 * g.V * 16);
         case LAPH_WS_CHEBYSHEV: return ws_align((size_t)27 * g.V * 16) + 2 * ws_align((size_t)g.V * 3 * 16);
         case LAPH_WS_NOISE: return 256;
+        case LAPH_WS_MOM_OVERLAP: return ws_align(sizeof(double2) * g.V3);
         case LAPH_WS_EIGVECS:
             if (!p || p->nv <= 0 || p->krylov_dim <= 0) return 0;
             return eig_scratch_bytes(g, p->krylov_dim, p->nv);

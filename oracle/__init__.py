@@ -72,6 +72,7 @@ def _load():
                 "or_cgnr": (_I, [_P, _P, _I, _I, _D, _D, _P, _P, _D, _I, _P]),
                 "or_meson_function": (None, [_P, _P, _I, _I, _P, _P, _P, _P, _P]),
                 "or_displace": (None, [_P, _I, _I, _I, _I, _I, _P, _P]),
+                "or_baryon_function": (None, [_P, _P, _P, _I, _I, _P, _P, _P]),
                 "or_mom_overlap": (None, [_P, _P, _I, _I, _I, _I, _P, _P]),
             }
             for name, (res, args) in sig.items():
@@ -511,4 +512,38 @@ def mom_overlap(a, b, k=(0, 0, 0)):
     ka = np.ascontiguousarray(k, dtype=np.int32)
     out = np.empty((nt, na, nb), dtype=np.complex128)
     lib.or_mom_overlap(_ptr(a), _ptr(b), ns, nt, na, nb, _ptr(ka), _ptr(out))
+    return out
+
+
+def baryon_function(f1, f2, f3, c, k=(0, 0, 0)):
+    """B(t) of Sec. III.A (Eq. baryonfunc) for three full spinor fields [Nt,Ns,Ns,Ns,4,3],
+    spin tensor c (4x4x4) and momentum 2 pi k / Ns."""
+    lib = _load()
+    f1, f2, f3 = _c(f1), _c(f2), _c(f3)
+    nt, ns = f1.shape[0], f1.shape[1]
+    c64 = _c(np.asarray(c, dtype=np.complex128).reshape(64))
+    ka = np.ascontiguousarray(k, dtype=np.int32)
+    out = np.empty(nt, dtype=np.complex128)
+    lib.or_baryon_function(_ptr(f1), _ptr(f2), _ptr(f3), ns, nt, _ptr(c64), _ptr(ka), _ptr(out))
+    return out
+
+
+# the six orderings of Eq. baryoncorr's source functions: (order of the noises 1, 2, 3 in
+# the function, sign of the Wick contraction)
+BARYON_PERMUTATIONS = [((0, 1, 2), +1), ((0, 2, 1), -1), ((1, 0, 2), -1), ((2, 1, 0), -1), ((1, 2, 0), +1),
+                       ((2, 0, 1), +1)]
+
+
+def baryon_correlator(snk, src, t0):
+    """Eq. baryoncorr for three quark lines of one flavour: snk[t][b1][b2][b3] =
+    B^[b1 b2 b3](varphi_1, varphi_2, varphi_3; t), src[s] (s over BARYON_PERMUTATIONS) =
+    B(varrho_s1, varrho_s2, varrho_s3; t) indexed by the dilution indices in that order;
+    C[tF] = sum_{b1 b2 b3} snk[tF][b1][b2][b3] conj(sum_s sign_s src[s][t0][b_s1][b_s2][b_s3])."""
+    nt = snk.shape[0]
+    out = np.zeros(nt, dtype=np.complex128)
+    for (order, sign), S in zip(BARYON_PERMUTATIONS, src):
+        # src[s][t0][b_order0][b_order1][b_order2] as a function of (b1, b2, b3)
+        inv = np.argsort(order)
+        St = np.transpose(S[t0], inv)
+        out += sign * np.einsum("tijk,ijk->t", snk, St.conj())
     return out

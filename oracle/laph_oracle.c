@@ -387,6 +387,42 @@ void or_sink_project(const cplx *evecs, const cplx *X, int ns, int nt, int nv, c
         }
 }
 
+/* ---------------------------------------------------------- baryon function
+ * Sec. III.A (Eq. baryonfunc) for three full-lattice spinor fields:
+ *   B(t) = sum_{alpha,beta,gamma} c_{alpha beta gamma} sum_x exp(-i p.x)
+ *          sum_{a,b,c} eps_abc f1(x,t,a,alpha) f2(x,t,b,beta) f3(x,t,c,gamma),
+ * c a 4x4x4 spin tensor c[(alpha*4 + beta)*4 + gamma], p = 2 pi k / Ns.
+ */
+void or_baryon_function(const cplx *f1, const cplx *f2, const cplx *f3, int ns, int nt, const cplx *c64,
+                        const int *k, cplx *out)
+{
+    static const int perm[6][3] = {{0, 1, 2}, {1, 2, 0}, {2, 0, 1}, {0, 2, 1}, {2, 1, 0}, {1, 0, 2}};
+    static const double sgn[6] = {1, 1, 1, -1, -1, -1};
+    long V3 = (long)ns * ns * ns;
+    const double tw = 2.0 * acos(-1.0) / ns;
+    for (int t = 0; t < nt; t++) {
+        cplx acc = 0;
+        for (long xyz = 0; xyz < V3; xyz++) {
+            int c[4];
+            or_coords(ns, xyz, c);
+            cplx e = cexp(-I * tw * (k[0] * c[0] + k[1] * c[1] + k[2] * c[2]));
+            long s = xyz + V3 * t;
+            for (int al = 0; al < 4; al++)
+                for (int be = 0; be < 4; be++)
+                    for (int ga = 0; ga < 4; ga++) {
+                        cplx g = c64[(al * 4 + be) * 4 + ga];
+                        if (g == 0) continue;
+                        cplx sum = 0;
+                        for (int q = 0; q < 6; q++)
+                            sum += sgn[q] * f1[(s * 4 + al) * 3 + perm[q][0]] * f2[(s * 4 + be) * 3 + perm[q][1]] *
+                                   f3[(s * 4 + ga) * 3 + perm[q][2]];
+                        acc += g * e * sum;
+                    }
+        }
+        out[t] = acc;
+    }
+}
+
 /* ------------------------------------------------------ covariant displacement
  * Sec. II (quark lines D^(j) S Omega^-1 S D^(k)dag): a displacement of type j moves a field
  * by `len` links along spatial direction dir (0, 1, 2 = x, y, z) with sign +1 or -1, in a

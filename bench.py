@@ -458,6 +458,34 @@ def main():
                                  "hbm_GBs": round(obytes / (ms_o * 1e-3) / 1e9, 1)}
         log("displace %.3f ms, overlap %.3f ms" % (ms_d, ms_o))
         del Usm, Vdisp, O
+        # baryon functions (Sec. III.A): the eigenvector tensor once, then the sink
+        # functions of the step's 32 quark lines taken as all three quarks
+        T = torch.empty((nt, nv, nv, nv), dtype=torch.complex128, device="cuda")
+        cb = np.zeros((4, 4, 4), dtype=np.complex128)
+        cb[0, 1, 0], cb[1, 0, 0] = 1.0, -1.0
+        nbq = nsrc
+        Bout = torch.empty((nt, nbq, nbq, nbq), dtype=torch.complex128, device="cuda")
+        ev0.record()
+        P.laph_baryon_tensor(L.ctx, evecs, nv, (0, 0, 0), T)
+        ev1.record()
+        P.laph_baryon_function(L.ctx, T, nv, cb, coef, nbq, coef, nbq, coef, nbq, Bout)
+        ev2.record()
+        torch.cuda.synchronize()
+        ms_t, ms_b = ev0.elapsed_time(ev1), ev1.elapsed_time(ev2)
+        tflops = 8.0 * nt * (nv * (nv + 16) / 2.0) * nv * 3 * V3  # n1 < n2 tiles, all n3
+        bflops = 8.0 * nt * (nv * nv * nv * 4 * nbq + nv * nv * 16 * nbq * nbq + 4 * nbq * nv * 16 * nbq * nbq)
+        hadron["baryon_tensor"] = {"kernel": "baryon_tensor (N_v = %d, K = 3 Ns^3)" % nv, "ms": round(ms_t, 2),
+                                   "roofline": {"bound": "fp64", "achieved": round(tflops / (ms_t * 1e-3) / 1e12, 2),
+                                                "peak": 78.6, "unit": "TFLOP/s",
+                                                "frac": round(tflops / (ms_t * 1e-3) / 78.6e12, 4)}}
+        hadron["baryon_function"] = {"kernel": "baryon_function (%d^3 dilution triples, N_v = %d)" % (nbq, nv),
+                                     "ms": round(ms_b, 2),
+                                     "roofline": {"bound": "fp64",
+                                                  "achieved": round(bflops / (ms_b * 1e-3) / 1e12, 2),
+                                                  "peak": 78.6, "unit": "TFLOP/s",
+                                                  "frac": round(bflops / (ms_b * 1e-3) / 78.6e12, 4)}}
+        log("baryon tensor %.1f ms, baryon function %.1f ms" % (ms_t, ms_b))
+        del T, Bout
 
     # roofline of the dominant kernel (largest summed duration in the instrumented step)
     dom = tm[0] if tm else {"kernel": "none", "ms": 0.0, "launches": 0, "bytes": 0.0}

@@ -413,6 +413,29 @@ LAPH_API int laph_mom_overlap(laph_ctx_t ctx, const double *a, int na, const dou
 LAPH_API int laph_overlap_apply(laph_ctx_t ctx, const double *O, int na, int nb, const double *b, int n,
                                 double *out);
 
+/* Baryon functions (Sec. III.A, Eq. baryonfunc) with the trivial displacement, from LapH
+ * coefficients.  laph_baryon_tensor: the eigenvector tensor
+ *   T[t][n1][n2][n3] = sum_x exp(-2 pi i k.x / Ns) eps_abc V_n1(x,a) V_n2(x,b) V_n3(x,c)
+ * (totally antisymmetric), T: device [Nt][nv][nv][nv], k HOST int[3].
+ * laph_baryon_function: for quark sinks varphi_k = V_s f_k (coefficients f1 [n1][Nt][4][nv],
+ * f2, f3 as sink_project writes them) and a spin tensor c (HOST 4x4x4 complex,
+ * c[(alpha*4 + beta)*4 + gamma]):
+ *   B[t][i][j][k] = sum_{abg} c_abg sum_{n1 n2 n3} T[t][n1][n2][n3] f1_i[t][a][n1] f2_j[t][b][n2] f3_k[t][g][n3]
+ * = the baryon function of Eq. baryonfunc for every dilution triple; out: device
+ * [Nt][n1][n2][n3].  With quark sources (laph_quark_source coefficients) in place of the
+ * sinks it gives the source functions.
+ * laph_baryon_correlator: Eq. baryoncorr for three quark lines of one flavour from the sink
+ * functions snk [Nt][n][n][n] and the source functions of the six noise orderings
+ * src [6][Nt][n][n][n], in the order (1,2,3)+, (1,3,2)-, (2,1,3)-, (3,2,1)-, (2,3,1)+,
+ * (3,1,2)+ with src[s][t][i][j][k] indexed by the dilution indices of the noises in that
+ * order: C[t_F] = sum_{b1 b2 b3} snk[t_F][b1][b2][b3] conj(sum_s sign_s src[s][t0][b_s1][b_s2][b_s3]).
+ * out: device [Nt] complex. */
+LAPH_API int laph_baryon_tensor(laph_ctx_t ctx, const double *evecs, int nv, const int *k, double *T);
+LAPH_API int laph_baryon_function(laph_ctx_t ctx, const double *T, int nv, const double *c, const double *f1, int n1,
+                                  const double *f2, int n2, const double *f3, int n3, double *out);
+LAPH_API int laph_baryon_correlator(laph_ctx_t ctx, const double *snk, const double *src, int n, int t0,
+                                    double *out);
+
 /* Sink projection for callers that cannot allocate or hand over a workspace (code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation): the same
  * coefficients as sink_project (sums over site ranges may be grouped differently, so
@@ -445,7 +468,9 @@ LAPH_API int sink_project_noalloc(laph_ctx_t ctx, const double *evecs, int nv, c
  *   LAPH_WS_DIRAC_APPLY: n (= n_fields);   LAPH_WS_HOP_APPLY: hop, n (= n_fields);
  *   LAPH_WS_SOLVE: solver, n (= n_rhs) (a learned network is taken from solver->net);
  *   LAPH_WS_AUTOTUNE: precision;   LAPH_WS_PTNET_FORWARD / _BACKWARD / _TRAIN: net, n
- *   (= n_fields or n_pairs);   LAPH_WS_MOM_OVERLAP: none.  The other calls need no workspace.
+ *   (= n_fields or n_pairs);   LAPH_WS_MOM_OVERLAP, LAPH_WS_BARYON_TENSOR: none;
+ *   LAPH_WS_BARYON_FUNCTION: nv, n, n2, n3 (the three dilution counts).  The other calls
+ *   need no workspace.
  * Returns 0 for an unknown op or missing parameters. */
 enum {
     LAPH_WS_STOUT = 0,
@@ -462,7 +487,9 @@ enum {
     LAPH_WS_PTNET_FORWARD = 11,
     LAPH_WS_PTNET_BACKWARD = 12,
     LAPH_WS_PTNET_TRAIN = 13,
-    LAPH_WS_MOM_OVERLAP = 14
+    LAPH_WS_MOM_OVERLAP = 14,
+    LAPH_WS_BARYON_TENSOR = 15,
+    LAPH_WS_BARYON_FUNCTION = 16
 };
 
 typedef struct {
@@ -473,6 +500,7 @@ typedef struct {
     const laph_solver *solver; /* solve parameters */
     const laph_hop *hop;       /* hopping-launch parameters */
     laph_ptnet_t net;          /* network */
+    int n2, n3;                /* second and third field counts (baryon functions) */
 } laph_ws_params;
 
 LAPH_API size_t laph_workspace_bytes(laph_ctx_t ctx, int op, const void *params);

@@ -69,7 +69,8 @@ class laph_hop(ctypes.Structure):
 
 class laph_ws_params(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("nv", ctypes.c_int), ("krylov_dim", ctypes.c_int), ("precision", ctypes.c_int),
-                ("solver", ctypes.c_void_p), ("hop", ctypes.c_void_p), ("net", ctypes.c_void_p)]
+                ("solver", ctypes.c_void_p), ("hop", ctypes.c_void_p), ("net", ctypes.c_void_p),
+                ("n2", ctypes.c_int), ("n3", ctypes.c_int)]
 
 
 class laph_solver(ctypes.Structure):
@@ -141,6 +142,9 @@ EXPORTS = {
                                _I, _I, _P]),
     "laph_spin_apply": (_I, [_P, _P, _P, _I, _I, _P]),
     "laph_displace": (_I, [_P, _P, _I, _I, _I, _P, _I, _P]),
+    "laph_baryon_tensor": (_I, [_P, _P, _I, _P, _P]),
+    "laph_baryon_function": (_I, [_P, _P, _I, _P, _P, _I, _P, _I, _P, _I, _P]),
+    "laph_baryon_correlator": (_I, [_P, _P, _P, _I, _I, _P]),
     "laph_mom_overlap": (_I, [_P, _P, _I, _P, _I, _P, _P]),
     "laph_overlap_apply": (_I, [_P, _P, _I, _I, _P, _I, _P]),
     "laph_meson_function": (_I, [_P, _P, _P, _I, _P, _I, _I, _I, _P]),
@@ -214,7 +218,8 @@ def _hptr(a):
 # ------------------------------------------------------------------ workspace
 (LAPH_WS_STOUT, LAPH_WS_LAPLACIAN, LAPH_WS_CHEBYSHEV, LAPH_WS_EIGVECS, LAPH_WS_NOISE, LAPH_WS_SOURCE,
  LAPH_WS_DIRAC_APPLY, LAPH_WS_HOP_APPLY, LAPH_WS_SOLVE, LAPH_WS_AUTOTUNE, LAPH_WS_SINK, LAPH_WS_PTNET_FORWARD,
- LAPH_WS_PTNET_BACKWARD, LAPH_WS_PTNET_TRAIN, LAPH_WS_MOM_OVERLAP) = range(15)
+ LAPH_WS_PTNET_BACKWARD, LAPH_WS_PTNET_TRAIN, LAPH_WS_MOM_OVERLAP, LAPH_WS_BARYON_TENSOR,
+ LAPH_WS_BARYON_FUNCTION) = range(17)
 
 _WS = {}  # context handle value -> workspace tensor
 
@@ -223,11 +228,12 @@ def _key(ctx):
     return ctx.value if isinstance(ctx, ctypes.c_void_p) else int(ctx)
 
 
-def laph_workspace_bytes(ctx, op, n=0, nv=0, krylov_dim=0, precision=0, solver=None, hop=None, net=None):
+def laph_workspace_bytes(ctx, op, n=0, nv=0, krylov_dim=0, precision=0, solver=None, hop=None, net=None, n2=0,
+                         n3=0):
     p = laph_ws_params(n, nv, krylov_dim, precision,
                        ctypes.cast(ctypes.pointer(solver), ctypes.c_void_p) if solver is not None else None,
                        ctypes.cast(ctypes.pointer(hop), ctypes.c_void_p) if hop is not None else None,
-                       net.handle if isinstance(net, PTNet) else net)
+                       net.handle if isinstance(net, PTNet) else net, n2, n3)
     need = lib().laph_workspace_bytes(ctx, op, ctypes.byref(p))
     if need == 0:
         raise LaphError(LAPH_EINVAL, "laph_workspace_bytes: invalid op or parameters")
@@ -436,6 +442,28 @@ def laph_mom_overlap(ctx, a, na, b, nb, k, out):
 
 def laph_overlap_apply(ctx, O, na, nb, b, n, out):
     _check(lib().laph_overlap_apply(ctx, _dptr(O), na, nb, _dptr(b), n, _dptr(out)), ctx)
+
+
+def laph_baryon_tensor(ctx, evecs, nv, k, T):
+    """T[t][n1][n2][n3] = sum_x e^{-ip.x} eps V_n1 V_n2 V_n3 (device [Nt, nv, nv, nv])."""
+    import numpy as np
+
+    ensure_workspace(ctx, LAPH_WS_BARYON_TENSOR)
+    ka = np.ascontiguousarray(k, dtype=np.int32)
+    _check(lib().laph_baryon_tensor(ctx, _dptr(evecs), nv, ka.ctypes.data_as(ctypes.c_void_p), _dptr(T)), ctx)
+
+
+def laph_baryon_function(ctx, T, nv, c, f1, n1, f2, n2, f3, n3, out):
+    import numpy as np
+
+    ensure_workspace(ctx, LAPH_WS_BARYON_FUNCTION, nv=nv, n=n1, n2=n2, n3=n3)
+    c64 = np.ascontiguousarray(np.asarray(c, dtype=np.complex128).reshape(64))
+    _check(lib().laph_baryon_function(ctx, _dptr(T), nv, c64.ctypes.data_as(ctypes.c_void_p), _dptr(f1), n1,
+                                      _dptr(f2), n2, _dptr(f3), n3, _dptr(out)), ctx)
+
+
+def laph_baryon_correlator(ctx, snk, src, n, t0, out):
+    _check(lib().laph_baryon_correlator(ctx, _dptr(snk), _dptr(src), n, t0, _dptr(out)), ctx)
 
 
 def laph_autotune(ctx, U, dirac, precision="f16"):

@@ -1,0 +1,333 @@
+// Baryon functions in LapH space (Sec. III.A: Eq. baryonfunc, and the baryon correlator
+// of Eq. baryoncorr with its six noise orderings).
+//
+// With the trivial displacement every LapH-smeared quark sink is varphi = V_s f, so
+//   B(t) = sum_{abg} c_abg sum_{n1 n2 n3} T[t][n1][n2][n3] f1[t][a][n1] f2[t][b][n2] f3[t][g][n3]
+// with the eigenvector tensor T[t][n1][n2][n3] = sum_x e^{-ip.x} eps_abc V_n1(x,a) V_n2(x,b)
+// V_n3(x,c) (totally antisymmetric: computed for n1 < n2, the rest by symmetry).  The
+// contraction over (n1, n2, n3) for all dilution triples is three batched complex products:
+//   X[n1 n2][k g]   = sum_n3 T[n1 n2][n3] F3[n3][k g]
+//   Y[n1][j b][k g] = sum_n2 F2[n2][j b] X[n1 n2][k g]
+//   Z[i a][j b k g] = sum_n1 F1[n1][i a] Y[n1][j b k g],   B[i][j][k] = sum c_abg Z[i a][j b][k g]
+#include <algorithm>
+#include <cmath>
+
+#include "laph_impl.h"
+
+namespace {
+
+// ------------------------------------------------------- batched complex product
+// C[b](m, n) = sum_k op(A[b](m, k)) B[b](k, n), op = conj when conjA; every operand is
+// addressed by strides (in complex elements); the batch index b splits into (b / nbi, b % nbi)
+// with a stride per part.  16 x 16 output tile per block, K staged in LDS 16 at a time.
+struct Zgemm {
+    const double2 *A;
+    long sAo, sAi, sAm, sAk;
+    const double2 *B;
+    long sBo, sBi, sBk, sBn;
+    double2 *C;
+    long sCo, sCi, sCm, sCn;
+    int M, N, K, nbi, conjA;
+};
+
+constexpr int kZT = 16;
+
+__global__ __launch_bounds__(kZT *kZT) void k_zgemm(Zgemm g)
+{
+    __shared__ double2 sa[kZT][kZT + 1];
+    __shared__ double2 sb[kZT][kZT + 1];
+    const long b = blockIdx.z;
+    const long bo = b / g.nbi, bi = b - bo * g.nbi;
+    const double2 *A = g.A + bo * g.sAo + bi * g.sAi;
+    const double2 *B = g.B + bo * g.sBo + bi * g.sBi;
+    double2 *C = g.C + bo * g.sCo + bi * g.sCi;
+    const int m0 = blockIdx.x * kZT, n0 = blockIdx.y * kZT;
+    const int tm = threadIdx.x % kZT, tn = threadIdx.x / kZT;
+    const int sk = threadIdx.x % kZT, sr = threadIdx.x / kZT;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int k0 = 0; k0 < g.K; k0 += kZT) {
+        const int k = k0 + sk;
+        double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
+        if (k < g.K) {
+            if (m0 + sr < g.M) {
+                va = A[(m0 + sr) * g.sAm + (long)k * g.sAk];
+                if (g.conjA) va.y = -va.y;
+            }
+            if (n0 + sr < g.N) vb = B[(long)k * g.sBk + (n0 + sr) * g.sBn];
+        }
+        sa[sk][sr] = va;
+        sb[sk][sr] = vb;
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kZT; kk++) {
+            const double2 x = sa[kk][tm], y = sb[kk][tn];
+            acc.x = fma(x.x, y.x, fma(-x.y, y.y, acc.x));
+            acc.y = fma(x.x, y.y, fma(x.y, y.x, acc.y));
+        }
+        __syncthreads();
+    }
+    if (m0 + tm < g.M && n0 + tn < g.N) C[(m0 + tm) * g.sCm + (n0 + tn) * g.sCn] = acc;
+}
+
+void zgemm(laph_ctx *c, const Zgemm &g, long batch)
+{
+    if (g.M <= 0 || g.N <= 0 || batch <= 0) return;
+    const unsigned gm = (g.M + kZT - 1) / kZT, gn = (g.N + kZT - 1) / kZT;
+    LAPH_CHECK(gn <= 65535 && batch <= 65535, LAPH_EINVAL, "product too large for one launch");
+    hipLaunchKernelGGL(k_zgemm, dim3(gm, gn, (unsigned)batch), dim3(kZT * kZT), 0, c->stream, g);
+    LAPH_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------- eigenvector tensor
+constexpr int kTX = 8;  // sites staged per LDS step (K = 3 kTX)
+
+// T[t][n1][n2][n3] for one n1, a tile of 16 n2 > n1 and a tile of 16 n3:
+// sum_{x,c} (e^{-ip.x} V_n1(x) x V_n2(x))_c V_n3(x, c), (u x w)_c = eps_abc u_a w_b
+__global__ __launch_bounds__(256) void k_baryon_tensor(const double2 *__restrict__ V, const double2 *__restrict__ ph,
+                                                       int nv, long V3, int nt, double2 *__restrict__ T)
+{
+    __shared__ double2 sa[3 * kTX][17];  // cross products [x c][n2 in tile]
+    __shared__ double2 sb[3 * kTX][17];  // V_n3 [x c][n3 in tile]
+    __shared__ double2 s1[kTX][3];       // V_n1 on the staged sites
+    const int n1 = blockIdx.x;
+    const int n2t = blockIdx.y / ((nv + 15) / 16), n3t = blockIdx.y % ((nv + 15) / 16);
+    const int t = blockIdx.z;
+    const int n20 = n2t * 16, n30 = n3t * 16;
+    if (n20 + 15 <= n1) return;  // every n2 of the tile is <= n1: filled by symmetry
+    const int tm = threadIdx.x % 16, tn = threadIdx.x / 16;
+    const double2 *Vt = V + (long)t * nv * V3 * 3;
+    double2 acc = make_double2(0.0, 0.0);
+    for (long x0 = 0; x0 < V3; x0 += kTX) {
+        if (threadIdx.x < kTX * 3) {
+            const int xs = threadIdx.x / 3, cc = threadIdx.x % 3;
+            const long x = x0 + xs;
+            s1[xs][cc] = x < V3 ? cmul(ph[x], Vt[((long)n1 * V3 + x) * 3 + cc]) : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        // stage: lanes (row r = lane / 16 picks the vector, site q = lane % 16 < kTX)
+        {
+            const int r = threadIdx.x / 16, q = threadIdx.x % 16;
+            if (q < kTX) {
+                const long x = x0 + q;
+                double2 w[3] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
+                double2 u[3] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
+                const int n2 = n20 + r, n3 = n30 + r;
+                if (x < V3 && n2 < nv)
+                    for (int cc = 0; cc < 3; cc++) w[cc] = Vt[((long)n2 * V3 + x) * 3 + cc];
+                if (x < V3 && n3 < nv)
+                    for (int cc = 0; cc < 3; cc++) u[cc] = Vt[((long)n3 * V3 + x) * 3 + cc];
+                const double2 *v1 = s1[q];
+                // cross product e^{-ip.x} V_n1 x V_n2
+                sa[q * 3 + 0][r] = csub(cmul(v1[1], w[2]), cmul(v1[2], w[1]));
+                sa[q * 3 + 1][r] = csub(cmul(v1[2], w[0]), cmul(v1[0], w[2]));
+                sa[q * 3 + 2][r] = csub(cmul(v1[0], w[1]), cmul(v1[1], w[0]));
+                for (int cc = 0; cc < 3; cc++) sb[q * 3 + cc][r] = u[cc];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 3 * kTX; kk++) {
+            const double2 a = sa[kk][tm], bv = sb[kk][tn];
+            acc.x = fma(a.x, bv.x, fma(-a.y, bv.y, acc.x));
+            acc.y = fma(a.x, bv.y, fma(a.y, bv.x, acc.y));
+        }
+        __syncthreads();
+    }
+    const int n2 = n20 + tm, n3 = n30 + tn;
+    if (n2 < nv && n3 < nv && n2 > n1) {
+        const long base = (long)t * nv * nv * nv;
+        T[base + ((long)n1 * nv + n2) * nv + n3] = acc;
+        T[base + ((long)n2 * nv + n1) * nv + n3] = make_double2(-acc.x, -acc.y);
+    }
+    if (n2 == n1 && n3 < nv) T[(long)t * nv * nv * nv + ((long)n1 * nv + n1) * nv + n3] = make_double2(0.0, 0.0);
+}
+
+__global__ void k_phase3(double2 *ph, int ns, int k0, int k1, int k2)
+{
+    const long V3 = (long)ns * ns * ns;
+    const long x = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (x >= V3) return;
+    const int cx = (int)(x % ns), cy = (int)((x / ns) % ns), cz = (int)(x / ((long)ns * ns));
+    const long m = (((long)k0 * cx + (long)k1 * cy + (long)k2 * cz) % ns + ns) % ns;
+    double s, c;
+    sincospi(-2.0 * (double)m / ns, &s, &c);
+    ph[x] = make_double2(c, s);
+}
+
+// Ft[tl][n][i*4 + alpha] = f[i][t0 + tl][alpha][n] for tc slices
+__global__ void k_coef_t(const double2 *__restrict__ f, int nf, int nt, int nv, int t0, int tc,
+                         double2 *__restrict__ Ft)
+{
+    const long q = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const long per = (long)nv * nf * 4;
+    if (q >= tc * per) return;
+    const int tl = (int)(q / per);
+    const long r = q - tl * per;
+    const int n = (int)(r / (nf * 4));
+    const int ia = (int)(r - (long)n * nf * 4);
+    const int i = ia / 4, a = ia % 4;
+    Ft[q] = f[(((long)i * nt + t0 + tl) * 4 + a) * nv + n];
+}
+
+struct Spin64 {
+    double2 c[64];
+};
+
+// B[t][i][j][k] = sum_{abg} c_abg Z[tl][(i a)][(j b)(k g)]
+__global__ void k_spin3(Spin64 s, const double2 *__restrict__ Z, int n1, int n2, int n3, int t0, int tc,
+                        double2 *__restrict__ out)
+{
+    const long q = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const long per = (long)n1 * n2 * n3;
+    if (q >= tc * per) return;
+    const int tl = (int)(q / per);
+    const long r = q - tl * per;
+    const int i = (int)(r / ((long)n2 * n3)), j = (int)((r / n3) % n2), k = (int)(r % n3);
+    const long ncol = 16L * n2 * n3;
+    const double2 *Zt = Z + (long)tl * (4L * n1) * ncol;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int a = 0; a < 4; a++)
+        for (int b = 0; b < 4; b++)
+            for (int g = 0; g < 4; g++) {
+                const double2 cc = s.c[(a * 4 + b) * 4 + g];
+                if (cc.x == 0.0 && cc.y == 0.0) continue;
+                acc = cadd(acc, cmul(cc, Zt[((long)i * 4 + a) * ncol + ((long)j * 4 + b) * (4L * n3) + k * 4 + g]));
+            }
+    out[(long)(t0 + tl) * per + r] = acc;
+}
+
+// C[tF] = sum_{b1 b2 b3} snk[tF][b1][b2][b3] conj(sum_s sign_s src[s][t0][b_s1][b_s2][b_s3]),
+// the six orderings s of Eq. baryoncorr in a fixed order (noise order, sign)
+__constant__ int kBPerm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {2, 1, 0}, {1, 2, 0}, {2, 0, 1}};
+__constant__ double kBSign[6] = {1, -1, -1, -1, 1, 1};
+
+__global__ __launch_bounds__(256) void k_baryon_corr(const double2 *__restrict__ snk, const double2 *__restrict__ src,
+                                                     int n, int nt, int t0, double2 *__restrict__ out)
+{
+    const int tf = blockIdx.x;
+    const long n3 = (long)n * n * n;
+    double2 acc = make_double2(0.0, 0.0);
+    for (long q = threadIdx.x; q < n3; q += 256) {
+        const int bidx[3] = {(int)(q / ((long)n * n)), (int)((q / n) % n), (int)(q % n)};
+        double2 s = make_double2(0.0, 0.0);
+        for (int p = 0; p < 6; p++) {
+            const long idx = ((long)bidx[kBPerm[p][0]] * n + bidx[kBPerm[p][1]]) * n + bidx[kBPerm[p][2]];
+            const double2 v = src[((long)p * nt + t0) * n3 + idx];
+            s.x += kBSign[p] * v.x;
+            s.y += kBSign[p] * v.y;
+        }
+        acc = cadd(acc, cconjmul(s, snk[(long)tf * n3 + q]));
+    }
+    __shared__ double2 red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[tf] = red[0];
+}
+
+}  // namespace
+
+// slices per pass of laph_baryon_function: as many as fit a scratch budget of 1 GiB
+static int baryon_chunk(int nt, int nv, int n1, int n2, int n3)
+{
+    const double per = 16.0 * ((double)nv * nv * 4 * n3 + (double)nv * 16 * n2 * n3 + 4.0 * n1 * 16 * n2 * n3 +
+                               4.0 * nv * (n1 + n2 + n3));
+    int tc = (int)std::max(1.0, std::floor((double)(1u << 30) / per));
+    return std::min(tc, nt);
+}
+
+size_t baryon_scratch_bytes(const Geom &g, int nv, int n1, int n2, int n3)
+{
+    const long tc = baryon_chunk(g.nt, nv, n1, n2, n3);
+    return ws_align(16 * tc * nv * 4 * n1) + ws_align(16 * tc * nv * 4 * n2) + ws_align(16 * tc * nv * 4 * n3) +
+           ws_align(16 * tc * nv * nv * 4 * n3) + ws_align(16 * tc * nv * 16 * n2 * n3) +
+           ws_align(16 * tc * 4 * n1 * 16 * n2 * n3);
+}
+
+extern "C" int laph_baryon_tensor(laph_ctx_t c, const double *evecs, int nv, const int *k, double *T)
+{
+    LAPH_API_BEGIN(c)
+    g_current_ctx = c;
+    LAPH_CHECK(evecs && k && T && nv > 0, LAPH_EINVAL, "bad arguments");
+    const long V3 = c->g.V3;
+    double2 *ph = (double2 *)ctx_named(c, "bar.phase", sizeof(double2) * V3);
+    hipLaunchKernelGGL(k_phase3, dim3(nblocks_for(V3, 256)), dim3(256), 0, c->stream, ph, c->g.ns, k[0], k[1], k[2]);
+    const int tiles = (nv + 15) / 16;
+    LAPH_CHECK((long)tiles * tiles <= 65535 && c->g.nt <= 65535, LAPH_EINVAL, "nv too large for one launch");
+    hipLaunchKernelGGL(k_baryon_tensor, dim3(nv, tiles * tiles, c->g.nt), dim3(256), 0, c->stream,
+                       (const double2 *)evecs, (const double2 *)ph, nv, V3, c->g.nt, (double2 *)T);
+    LAPH_HIP(hipGetLastError());
+    LAPH_API_END(c)
+}
+
+extern "C" int laph_baryon_function(laph_ctx_t c, const double *T, int nv, const double *cs, const double *f1, int n1,
+                                    const double *f2, int n2, const double *f3, int n3, double *out)
+{
+    LAPH_API_BEGIN(c)
+    g_current_ctx = c;
+    LAPH_CHECK(T && cs && f1 && f2 && f3 && out && nv > 0 && n1 > 0 && n2 > 0 && n3 > 0, LAPH_EINVAL,
+               "bad arguments");
+    Spin64 s;
+    for (int q = 0; q < 64; q++) {
+        LAPH_CHECK(std::isfinite(cs[2 * q]) && std::isfinite(cs[2 * q + 1]), LAPH_EINVAL, "spin tensor not finite");
+        s.c[q] = make_double2(cs[2 * q], cs[2 * q + 1]);
+    }
+    const int nt = c->g.nt;
+    const int tc = baryon_chunk(nt, nv, n1, n2, n3);
+    const long c1 = 4L * n1, c2 = 4L * n2, c3 = 4L * n3;
+    double2 *F1 = (double2 *)ctx_named(c, "bar.F1", 16 * (size_t)tc * nv * c1);
+    double2 *F2 = (double2 *)ctx_named(c, "bar.F2", 16 * (size_t)tc * nv * c2);
+    double2 *F3 = (double2 *)ctx_named(c, "bar.F3", 16 * (size_t)tc * nv * c3);
+    double2 *X = (double2 *)ctx_named(c, "bar.X", 16 * (size_t)tc * nv * nv * c3);
+    double2 *Y = (double2 *)ctx_named(c, "bar.Y", 16 * (size_t)tc * nv * c2 * c3);
+    double2 *Z = (double2 *)ctx_named(c, "bar.Z", 16 * (size_t)tc * c1 * c2 * c3);
+    const double2 *Td = (const double2 *)T;
+    for (int t0 = 0; t0 < nt; t0 += tc) {
+        const int tcn = std::min(tc, nt - t0);
+        hipLaunchKernelGGL(k_coef_t, dim3(nblocks_for((long)tcn * nv * c1, 256)), dim3(256), 0, c->stream,
+                           (const double2 *)f1, n1, nt, nv, t0, tcn, F1);
+        hipLaunchKernelGGL(k_coef_t, dim3(nblocks_for((long)tcn * nv * c2, 256)), dim3(256), 0, c->stream,
+                           (const double2 *)f2, n2, nt, nv, t0, tcn, F2);
+        hipLaunchKernelGGL(k_coef_t, dim3(nblocks_for((long)tcn * nv * c3, 256)), dim3(256), 0, c->stream,
+                           (const double2 *)f3, n3, nt, nv, t0, tcn, F3);
+        LAPH_HIP(hipGetLastError());
+        // X[tl][n1 n2][k g] = sum_n3 T[t][n1 n2][n3] F3[tl][n3][k g]
+        Zgemm gx{Td + (size_t)t0 * nv * nv * nv, (long)nv * nv * nv, 0, nv, 1,
+                 F3, nv * c3, 0, c3, 1,
+                 X, (long)nv * nv * c3, 0, c3, 1,
+                 nv * nv, (int)c3, nv, 1, 0};
+        zgemm(c, gx, tcn);
+        // Y[tl][n1][j b][k g] = sum_n2 F2[tl][n2][j b] X[tl][n1 n2][k g]
+        Zgemm gy{F2, nv * c2, 0, 1, c2,
+                 X, (long)nv * nv * c3, (long)nv * c3, c3, 1,
+                 Y, (long)nv * c2 * c3, c2 * c3, c3, 1,
+                 (int)c2, (int)c3, nv, nv, 0};
+        zgemm(c, gy, (long)tcn * nv);
+        // Z[tl][i a][(j b)(k g)] = sum_n1 F1[tl][n1][i a] Y[tl][n1][(j b)(k g)]
+        Zgemm gz{F1, nv * c1, 0, 1, c1,
+                 Y, (long)nv * c2 * c3, 0, c2 * c3, 1,
+                 Z, c1 * c2 * c3, 0, c2 * c3, 1,
+                 (int)c1, (int)(c2 * c3), nv, 1, 0};
+        zgemm(c, gz, tcn);
+        const long nout = (long)tcn * n1 * n2 * n3;
+        hipLaunchKernelGGL(k_spin3, dim3(nblocks_for(nout, 256)), dim3(256), 0, c->stream, s, (const double2 *)Z, n1,
+                           n2, n3, t0, tcn, (double2 *)out);
+        LAPH_HIP(hipGetLastError());
+    }
+    LAPH_API_END(c)
+}
+
+extern "C" int laph_baryon_correlator(laph_ctx_t c, const double *snk, const double *src, int n, int t0, double *out)
+{
+    LAPH_API_BEGIN(c)
+    g_current_ctx = c;
+    LAPH_CHECK(snk && src && out && n > 0, LAPH_EINVAL, "bad arguments");
+    LAPH_CHECK(t0 >= 0 && t0 < c->g.nt, LAPH_EINVAL, "t0 out of range");
+    hipLaunchKernelGGL(k_baryon_corr, dim3(c->g.nt), dim3(256), 0, c->stream, (const double2 *)snk,
+                       (const double2 *)src, n, c->g.nt, t0, (double2 *)out);
+    LAPH_HIP(hipGetLastError());
+    LAPH_API_END(c)
+}

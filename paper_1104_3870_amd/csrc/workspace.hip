@@ -10,6 +10,7 @@ size_t apply_scratch_bytes(laph_ctx *c, int n_fields);
 size_t hop_scratch_bytes(laph_ctx *c, const laph_hop *h, int R);
 size_t tune_scratch_bytes(laph_ctx *c, int prec);
 size_t solve_scratch_bytes(laph_ctx *c, int n_rhs, const laph_solver *sv);
+size_t baryon_scratch_bytes(const Geom &g, int nv, int n1, int n2, int n3);
 
 extern "C" size_t laph_workspace_bytes(laph_ctx_t c, int op, const void *params)
 {
@@ -23,7 +24,11 @@ extern "C" size_t laph_workspace_bytes(laph_ctx_t c, int op, const void *params)
         case LAPH_WS_LAPLACIAN: return ws_align((size_t)27 * g.V * 16);
         case LAPH_WS_CHEBYSHEV: return ws_align((size_t)27 * g.V * 16) + 2 * ws_align((size_t)g.V * 3 * 16);
         case LAPH_WS_NOISE: return 256;
-        case LAPH_WS_MOM_OVERLAP: return ws_align(sizeof(double2) * g.V3);
+        case LAPH_WS_MOM_OVERLAP:
+        case LAPH_WS_BARYON_TENSOR: return ws_align(sizeof(double2) * g.V3);
+        case LAPH_WS_BARYON_FUNCTION:
+            if (!p || p->nv <= 0 || p->n <= 0 || p->n2 <= 0 || p->n3 <= 0) return 0;
+            return baryon_scratch_bytes(g, p->nv, p->n, p->n2, p->n3);
         case LAPH_WS_EIGVECS:
             if (!p || p->nv <= 0 || p->krylov_dim <= 0) return 0;
             return eig_scratch_bytes(g, p->krylov_dim, p->nv);

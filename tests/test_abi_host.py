@@ -101,7 +101,7 @@ def test_create_rejects_odd_extents(L):
 
 _STRUCTS = ["laph_geom", "laph_stout", "laph_lanczos", "laph_eig_stats", "laph_dilution", "laph_dirac", "laph_hop",
             "laph_solver", "laph_solve_stats", "laph_adam", "laph_tune_entry", "laph_tune_report",
-            "laph_kernel_timing", "laph_timing"]
+            "laph_kernel_timing", "laph_timing", "laph_ws_params"]
 
 
 def test_binding_structs_match_header(tmp_path):

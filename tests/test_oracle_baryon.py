@@ -14,10 +14,8 @@ import pytest
 
 import oracle
 import synth
-
-EPS = np.zeros((3, 3, 3))
-for (a, b, c), s in zip(itertools.permutations(range(3)), (1, -1, -1, 1, 1, -1)):
-    EPS[a, b, c] = s  # itertools order: 012 021 102 120 201 210
+import wick
+from wick import EPS
 
 
 def _fields(seed, n=3, ns=4, nt=2):
@@ -87,7 +85,7 @@ def exact3():
 
 def test_baryon_correlator_full_dilution_is_exact(exact3):
     cfg, nv, V, X, Q = exact3
-    nt, ns, V3 = cfg.nt, cfg.ns, cfg.ns ** 3
+    nt, ns = cfg.nt, cfg.ns
     t0, k = 3, (1, 0, 0)
     c, cp = _tensor(6, sparse=True), _tensor(7, sparse=True)
     sch = oracle.parse_dilution("TF,SF,LF", nt, nv)
@@ -108,32 +106,5 @@ def test_baryon_correlator_full_dilution_is_exact(exact3):
         src.append(S)
     est = oracle.baryon_correlator(snk, src, t0)
     # brute force: six Wick terms of three dense quark lines Q(x tF, x0 t0)
-    Qr = Q.reshape(nt, V3, 4, 3, nt, V3, 4, 3)
-    cz = np.arange(V3)
-    coord = np.stack([cz % ns, (cz // ns) % ns, cz // ns ** 2], axis=1)
-    ph = np.exp(-2j * np.pi * coord @ np.array(k) / ns)  # e^{-ip.x}
-    ref = np.zeros(nt, dtype=np.complex128)
-    nzc = list(zip(*np.nonzero(c)))
-    nzp = list(zip(*np.nonzero(cp)))
-    for tf in range(nt):
-        q = Qr[tf, :, :, :, t0]  # [x, spin, colour, x0, spin0, colour0]
-        tot = 0
-        for (al, be, ga) in nzc:
-            for (a0, b0, g0) in nzp:
-                w = c[al, be, ga] * np.conj(cp[a0, b0, g0])
-                # line between sink quark (spin s) and source quark (spin s0): q[:, s, :, :, s0, :]
-                def L(s, s0):
-                    return q[:, s, :, :, s0, :]
-                terms = [(+1, L(al, a0), L(be, b0), L(ga, g0), "xau,xbv,xcw"),
-                         (-1, L(al, a0), L(be, g0), L(ga, b0), "xau,xbw,xcv"),
-                         (-1, L(al, b0), L(be, a0), L(ga, g0), "xav,xbu,xcw"),
-                         (-1, L(al, g0), L(be, b0), L(ga, a0), "xaw,xbv,xcu"),
-                         (+1, L(al, g0), L(be, a0), L(ga, b0), "xaw,xbu,xcv"),
-                         (+1, L(al, b0), L(be, g0), L(ga, a0), "xav,xbw,xcu")]
-                for sign, A1, A2, A3, spec in terms:
-                    # A[x, colour, x0, colour0] with x0 summed with phase e^{+ip.x0}
-                    s1, s2, s3 = spec.split(",")
-                    expr = "abc,uvw,x,y,{0},{1},{2}->".format(*[s[0] + s[1] + "y" + s[2] for s in (s1, s2, s3)])
-                    tot += sign * w * np.einsum(expr, EPS, EPS, ph, ph.conj(), A1, A2, A3)
-        ref[tf] = tot
+    ref = wick.baryon_wick(Q, ns, nt, t0, c, cp, k)
     assert np.abs(est - ref).max() <= 1e-10 * np.abs(ref).max()

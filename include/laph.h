@@ -156,11 +156,17 @@ LAPH_API long laph_dilution_count(const laph_dilution *dil, int nt, int nv);
  * rho: device [Nt][4][Nv]. */
 LAPH_API int laph_z4_noise(laph_ctx_t ctx, uint16_t noise_s, uint16_t config_k, int nv, double *rho);
 
+/* element type of a field written by the library */
+enum { LAPH_DTYPE_C128 = 0, LAPH_DTYPE_C64 = 1 };
+
 /* eta^[b] = V_s P^(b) rho for the n_src projector indices b_first .. b_first+n_src-1
- * (Sec. IV, right-hand side y = V_s P^[b] rho).  eta: device, n_src spinor fields. */
+ * (Sec. IV, right-hand side y = V_s P^[b] rho).  eta: device, n_src spinor fields of
+ * complex128 (dtype LAPH_DTYPE_C128, what dirac_solve takes) or complex64
+ * (LAPH_DTYPE_C64: the FP64 sums rounded once, for callers with their own solver);
+ * another dtype gives LAPH_EINVAL. */
 LAPH_API int make_diluted_source(laph_ctx_t ctx, const double *evecs, int nv, uint16_t noise_s,
                         uint16_t config_k, const laph_dilution *dil, int64_t b_first,
-                        int n_src, double *eta);
+                        int n_src, void *eta, int dtype);
 
 /* ------------------------------------------------------------- Dirac operator
  * K = A + H, the anisotropic Wilson-clover matrix (frozen reading; the paper names an

@@ -23,6 +23,7 @@ LAPH_OP_K, LAPH_OP_OMEGA, LAPH_OP_KDAG = range(3)
 LAPH_PREC_F64, LAPH_PREC_F32, LAPH_PREC_F16, LAPH_PREC_BF16 = range(4)
 LAPH_SOLVER_BICGSTAB, LAPH_SOLVER_CGNR, LAPH_SOLVER_FGMRES = range(3)
 LAPH_HOP_PLAIN, LAPH_HOP_INV, LAPH_HOP_INV_DAG, LAPH_HOP_PLAIN_CG = range(4)
+LAPH_DTYPE_C128, LAPH_DTYPE_C64 = range(2)
 LAPH_SINK_NOALLOC_BYTES = 64 << 20  # fixed scratch of sink_project_noalloc (include/laph.h)
 PRECISIONS = {"f64": LAPH_PREC_F64, "f32": LAPH_PREC_F32, "f16": LAPH_PREC_F16, "bf16": LAPH_PREC_BF16}
 
@@ -130,7 +131,7 @@ EXPORTS = {
     "laph_dilution_count": (ctypes.c_long, [ctypes.POINTER(laph_dilution), _I, _I]),
     "laph_z4_noise": (_I, [_P, ctypes.c_uint16, ctypes.c_uint16, _I, _P]),
     "make_diluted_source": (_I, [_P, _P, _I, ctypes.c_uint16, ctypes.c_uint16, ctypes.POINTER(laph_dilution),
-                                 ctypes.c_int64, _I, _P]),
+                                 ctypes.c_int64, _I, _P, _I]),
     "laph_dirac_apply": (_I, [_P, _P, ctypes.POINTER(laph_dirac), _I, _P, _P, _I]),
     "laph_hop_apply": (_I, [_P, _P, ctypes.POINTER(laph_dirac), ctypes.POINTER(laph_hop), _P, _P, _P, _P, _P, _P,
                             _I]),
@@ -343,9 +344,16 @@ def laph_z4_noise(ctx, s, k, nv, rho):
 
 
 def make_diluted_source(ctx, evecs, nv, noise_s, config_k, dil, b_first, n_src, eta):
+    """eta: device complex128 or complex64 tensor [n_src, Nt, Ns, Ns, Ns, 4, 3]; its dtype
+    selects the element type the library writes."""
+    import torch
+
+    dt = {torch.complex128: LAPH_DTYPE_C128, torch.complex64: LAPH_DTYPE_C64}.get(eta.dtype)
+    if dt is None:
+        raise TypeError("eta must be complex128 or complex64")
     ensure_workspace(ctx, LAPH_WS_SOURCE, nv=nv)
     _check(lib().make_diluted_source(ctx, _dptr(evecs), nv, noise_s, config_k, ctypes.byref(dil), b_first, n_src,
-                                     _dptr(eta)), ctx)
+                                     _dptr(eta), dt), ctx)
 
 
 def laph_dirac_apply(ctx, U, dirac, op, x, out, n_fields=1):

@@ -52,8 +52,10 @@ __device__ __forceinline__ bool member(const Dil &d, int k, int i, int b)
 }
 
 // eta_j(x, t, c, alpha) = sum_{n in L(b_L)} V_{t,n}(x, c) rho(t, alpha, n), j = 0..nsrc-1
+// T2: double2 (complex128 output) or float2 (complex64: the FP64 sums rounded once)
+template <class T2>
 __global__ void k_source(const double2 *__restrict__ evecs, const double2 *__restrict__ rho, Dil d, long b_first,
-                         int nsrc, long V3, int nt, int nv, double2 *__restrict__ eta)
+                         int nsrc, long V3, int nt, int nv, T2 *__restrict__ eta)
 {
     long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
     long per = V3 * nt * 3;
@@ -68,7 +70,7 @@ __global__ void k_source(const double2 *__restrict__ evecs, const double2 *__res
     int bL = (int)(b % d.cnt[2]);
     int bS = (int)((b / d.cnt[2]) % d.cnt[1]);
     int bT = (int)(b / ((long)d.cnt[2] * d.cnt[1]));
-    double2 *out = eta + ((long)j * V3 * nt + s) * 12;
+    T2 *out = eta + ((long)j * V3 * nt + s) * 12;
     double2 acc[4] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
     if (member(d, 0, t, bT)) {
         for (int n = 0; n < nv; n++) {
@@ -78,7 +80,12 @@ __global__ void k_source(const double2 *__restrict__ evecs, const double2 *__res
                 if (member(d, 1, a, bS)) acc[a] = cadd(acc[a], cmul(v, rho[((long)t * 4 + a) * nv + n]));
         }
     }
-    for (int a = 0; a < 4; a++) out[a * 3 + c] = acc[a];
+    for (int a = 0; a < 4; a++) {
+        T2 o;
+        o.x = acc[a].x;
+        o.y = acc[a].y;
+        out[a * 3 + c] = o;
+    }
 }
 
 // LapH coefficients of the diluted quark sources varrho^[b] = V_s P^(b) rho (or, with the
@@ -247,11 +254,12 @@ extern "C" int laph_z4_noise(laph_ctx_t c, uint16_t s, uint16_t k, int nv, doubl
 }
 
 extern "C" int make_diluted_source(laph_ctx_t c, const double *evecs, int nv, uint16_t s, uint16_t k,
-                                   const laph_dilution *dil, int64_t b_first, int n_src, double *eta)
+                                   const laph_dilution *dil, int64_t b_first, int n_src, void *eta, int dtype)
 {
     LAPH_API_BEGIN(c)
     g_current_ctx = c;
     LAPH_CHECK(evecs && eta && dil && nv > 0 && n_src > 0, LAPH_EINVAL, "bad arguments");
+    LAPH_CHECK(dtype == LAPH_DTYPE_C128 || dtype == LAPH_DTYPE_C64, LAPH_EINVAL, "unknown dtype");
     long nb = laph_dilution_count(dil, c->g.nt, nv);
     LAPH_CHECK(nb > 0, LAPH_EDIVIDE, "invalid dilution scheme (N/J not an integer)");
     LAPH_CHECK(b_first >= 0 && b_first + n_src <= nb, LAPH_EINVAL, "projector index out of range");
@@ -259,8 +267,14 @@ extern "C" int make_diluted_source(laph_ctx_t c, const double *evecs, int nv, ui
     launch_z4(c, s, k, nv, rho);
     Dil d = make_dil(dil, c->g.nt, nv);
     long n = c->g.V * 3 * n_src;
-    hipLaunchKernelGGL(k_source, dim3(nblocks_for(n, 256)), dim3(256), 0, c->stream, (const double2 *)evecs,
-                       (const double2 *)rho, d, (long)b_first, n_src, c->g.V3, c->g.nt, nv, (double2 *)eta);
+    if (dtype == LAPH_DTYPE_C128)
+        hipLaunchKernelGGL(k_source<double2>, dim3(nblocks_for(n, 256)), dim3(256), 0, c->stream,
+                           (const double2 *)evecs, (const double2 *)rho, d, (long)b_first, n_src, c->g.V3, c->g.nt,
+                           nv, (double2 *)eta);
+    else
+        hipLaunchKernelGGL(k_source<float2>, dim3(nblocks_for(n, 256)), dim3(256), 0, c->stream,
+                           (const double2 *)evecs, (const double2 *)rho, d, (long)b_first, n_src, c->g.V3, c->g.nt,
+                           nv, (float2 *)eta);
     LAPH_HIP(hipGetLastError());
     LAPH_API_END(c)
 }

@@ -153,6 +153,24 @@ def test_source_parity(P, ns4_nt8_evecs, spec, b0, nsrc):
         assert np.abs(host(eta)[j] - ref).max() < 1e-15
 
 
+def test_source_complex64(P, ns4_nt8_evecs):
+    """The complex64 form is the oracle's FP64 source rounded once to FP32."""
+    import torch
+
+    cfg, U, V = ns4_nt8_evecs
+    L = _ctx(P, cfg.ns, cfg.nt)
+    spec, b0, nsrc = "TI4,SB2,LI4", 5, 6
+    dil = P.laph_parse_dilution(spec, cfg.nt, cfg.nv)
+    eta = torch.empty((nsrc, cfg.nt, cfg.ns, cfg.ns, cfg.ns, 4, 3), dtype=torch.complex64, device="cuda")
+    P.make_diluted_source(L.ctx, dev(V), cfg.nv, 0, 1, dil, b0, nsrc, eta)
+    rho = oracle.z4_noise(0, 1, cfg.nt, cfg.nv)
+    sch = oracle.parse_dilution(spec, cfg.nt, cfg.nv)
+    got = host(eta)
+    for j in range(nsrc):
+        ref = oracle.source(V, rho, sch, b0 + j).astype(np.complex64)
+        assert np.abs(got[j] - ref).max() <= 2.0 ** -23 * np.abs(ref).max()
+
+
 def test_source_rejects_bad_index(P, ns4_nt8_evecs):
     import torch
 

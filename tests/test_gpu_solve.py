@@ -195,3 +195,38 @@ def test_graph_replay_matches_eager(P, setup, prec):
         assert np.array_equal(x0, x1)
     for r in range(4):
         assert D.true_residual(etas[r], x1[r]) <= 1e-10
+
+
+@pytest.fixture(scope="module")
+def mid():
+    """16^3 x 32 field of the mid-size workload at its mass (a few hundred CG iterations)
+    and four Gaussian sources."""
+    cfg = synth.CONFIGS["ns16_nt32"]
+    U = synth.gauge_field(cfg.ns, cfg.nt, cfg.eps, cfg.seed)
+    D = oracle.Dirac(U, cfg.m0, cfg.xi, cfg.csw, cfg.bc_t)
+    etas = synth.random_spinor(cfg.ns, cfg.nt, 31, nrhs=4)
+    return cfg, U, D, etas
+
+
+def test_mixed_iterations_bound(P, mid):
+    """Low-precision inner vectors cost at most a few percent more CG iterations than the
+    FP64 solver on the same block (Sec. IV: mixed precision with reliable updates must not
+    change the method).  A sign or index error in a low-precision hop would be repaired by
+    the FP64 reliable updates and show only here, as extra iterations.  Bars on the mean
+    over the block: FP32 and FP16 within 5% of FP64; BF16 (8-bit mantissa, so the CG
+    recurrence drifts from the true residual an order of magnitude faster and every
+    reliable update restarts the search direction) within 20%."""
+    cfg, U, D, etas = mid
+    mean = {}
+    for prec in ("f64", "f32", "f16", "bf16"):
+        say("iterations", prec)
+        x, st = _solve(P, cfg, U, etas, precision=prec, block_rhs=4, solver=P.LAPH_SOLVER_CGNR)
+        for r in range(etas.shape[0]):
+            assert st[r].status == 0 and st[r].fallback_used == 0
+            assert D.true_residual(etas[r], x[r]) <= 1e-10
+        mean[prec] = float(np.mean([q.iters for q in st]))
+        say("  iters", [q.iters for q in st], "mean", mean[prec])
+    assert mean["f64"] > 100, mean
+    assert mean["f32"] <= 1.05 * mean["f64"], mean
+    assert mean["f16"] <= 1.05 * mean["f64"], mean
+    assert mean["bf16"] <= 1.20 * mean["f64"], mean

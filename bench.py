@@ -185,6 +185,10 @@ def main():
     ap.add_argument("--learned-mixed-steps", type=int, default=-1,
                     help="steps of the headline form with the trained network's initial guess (0: skip; "
                          "-1: as many as the headline)")
+    ap.add_argument("--bicgstab-probe", type=int, default=0,
+                    help="only run the paper's solver, FP64 BiCGStab on the even-odd system, on the first "
+                         "LapH source with this many iterations at most, and print its outcome (with "
+                         "LAPH_VERBOSE=1 the library logs the residual every 256 iterations)")
     ap.add_argument("--learned-sources", type=int, default=2,
                     help="sources solved with FGMRES and the learned preconditioner (0: skip)")
     args = ap.parse_args()
@@ -232,6 +236,21 @@ def main():
     eta = torch.empty(shape, dtype=torch.complex128, device="cuda")
     x = torch.empty(shape, dtype=torch.complex128, device="cuda")
     coef = torch.empty((nsrc, cfg.nt, 4, cfg.nv), dtype=torch.complex128, device="cuda")
+
+    if args.bicgstab_probe > 0:
+        sv = P.solver_params(tol=cfg.solve_tol, maxiter=args.bicgstab_probe, precision="f64", block_rhs=1,
+                             solver=P.LAPH_SOLVER_BICGSTAB)
+        P.make_diluted_source(L.ctx, evecs, cfg.nv, cfg.noise_s, cfg.noise_k, dil, 0, 1, eta[:1])
+        torch.cuda.synchronize()
+        t0 = time.time()
+        st = P.dirac_solve(L.ctx, Ud, prm, eta[:1], x[:1], 1, sv)
+        torch.cuda.synchronize()
+        print(json.dumps({"bicgstab_probe": {
+            "workload": cfg.name, "m0": cfg.m0, "source": "LapH source b = 0 of (%s)" % cfg.dilution,
+            "iters": st[0].iters, "fallback_used": st[0].fallback_used, "status": st[0].status,
+            "true_resid": st[0].true_resid, "seconds": round(time.time() - t0, 2),
+            "note": "fallback_used = 1: BiCGStab diverged or stalled and CG on the normal equations finished"}}))
+        return 0
 
     def step(k, sv):
         t0 = times[k % len(times)]

@@ -547,3 +547,109 @@ def baryon_correlator(snk, src, t0):
         St = np.transpose(S[t0], inv)
         out += sign * np.einsum("tijk,ijk->t", snk, St.conj())
     return out
+
+
+# ------------------------------------------------------- Krylov reference solvers
+
+def bicgstab(apply, b, tol=1e-10, maxiter=10000):
+    """BiCGStab (van der Vorst, SIAM J. Sci. Stat. Comput. 13 (1992) 631), the solver the
+    paper names for Omega x = eta (Sec. IV), here unpreconditioned, from x = 0 with the
+    shadow residual equal to the first residual.  apply(v) -> A v on flat vectors.
+    Stops when the iterated residual |r_k| <= tol |b|, on a breakdown (rho, <r0, v> or
+    omega exactly zero) or at maxiter.  Returns (x, k, history): k > 0 converged after k
+    iterations, k < 0 stopped after |k| without converging; history[k] = |r_k| / |b|."""
+    b = np.asarray(b, dtype=np.complex128).reshape(-1)
+    nb = np.linalg.norm(b)
+    x = np.zeros_like(b)
+    r = b.copy()
+    r0 = r.copy()
+    p = np.zeros_like(b)
+    v = np.zeros_like(b)
+    rho = alpha = omega = 1.0 + 0j
+    hist = [1.0]
+    for k in range(1, maxiter + 1):
+        rho_new = np.vdot(r0, r)
+        if rho_new == 0:
+            return x, -k, hist
+        beta = (rho_new / rho) * (alpha / omega)
+        p = r + beta * (p - omega * v)
+        v = apply(p)
+        den = np.vdot(r0, v)
+        if den == 0:
+            return x, -k, hist
+        alpha = rho_new / den
+        s = r - alpha * v
+        t = apply(s)
+        tt = np.vdot(t, t).real
+        omega = np.vdot(t, s) / tt if tt > 0 else 0.0
+        x = x + alpha * p + omega * s
+        r = s - omega * t
+        rho = rho_new
+        hist.append(float(np.linalg.norm(r) / nb))
+        if hist[-1] <= tol:
+            return x, k, hist
+        if omega == 0:
+            return x, -k, hist
+    return x, -maxiter, hist
+
+
+class EvenOdd:
+    """The Schur complement of K = A + H on odd sites ((x + y + z + t) odd), the system the
+    paper's even-odd preconditioned solver iterates (Sec. IV), written as the library's
+    form Mhat = 1 - A_oo^-1 H_oe A_ee^-1 H_eo.  For Omega x = eta (K x = y with
+    y = gamma_4 eta, Sec. II) the odd part of x solves Mhat x_o = bhat with
+    bhat = A_oo^-1 (y_o - H_oe A_ee^-1 y_e), and x_e = A_ee^-1 (y_e - H_eo x_o).
+    Fields are full-lattice arrays [Nt,Ns,Ns,Ns,4,3] (zero off their parity); H is K - A
+    applied through the oracle's K, A^-1 is the site-wise inverse of the clover matrix."""
+
+    def __init__(self, dirac: Dirac):
+        self.D = dirac
+        ns, nt = dirac.ns, dirac.nt
+        t, z, y, x = np.meshgrid(*(np.arange(n) for n in (nt, ns, ns, ns)), indexing="ij")
+        self.odd = (((x + y + z + t) % 2) == 1)[..., None, None].astype(np.float64)
+        self.even = 1.0 - self.odd
+        self.Ainv = np.linalg.inv(dirac.A)
+        self.g4 = gamma(3)
+
+    def _site(self, M, psi):
+        sh = psi.shape
+        return np.einsum("...ij,...j->...i", M, psi.reshape(sh[:-2] + (12,))).reshape(sh)
+
+    def hop(self, psi):
+        return self.D.K(psi) - self._site(self.D.A, psi)
+
+    def mhat(self, xo):
+        xo = xo.reshape(self.D.shape) * self.odd
+        w = self._site(self.Ainv, self.hop(xo) * self.even)
+        return xo - self._site(self.Ainv, self.hop(w) * self.odd)
+
+    def y(self, eta):
+        return np.einsum("ab,...bc->...ac", self.g4, eta.reshape(self.D.shape))
+
+    def bhat(self, eta):
+        y = self.y(eta)
+        w = self._site(self.Ainv, y * self.even)
+        return self._site(self.Ainv, (y - self.hop(w)) * self.odd)
+
+    def full(self, xo, eta):
+        xo = xo.reshape(self.D.shape) * self.odd
+        y = self.y(eta)
+        return xo + self._site(self.Ainv, (y - self.hop(xo)) * self.even)
+
+
+def bicgstab_solve(dirac: Dirac, eta, tol=1e-10, maxiter=10000, even_odd=True):
+    """Omega^-1 eta by BiCGStab, on the even-odd system (the paper's form, Sec. IV) or on
+    the full K x = gamma_4 eta (the same x; Omega = gamma_4 K itself is indefinite, and
+    BiCGStab stalls on it even far from the critical mass).  The iteration stops at tol
+    on its own residual (of Mhat x_o = bhat, or of K x = y).  Returns (x, k, history,
+    true relative residual of Omega x = eta)."""
+    if even_odd:
+        eo = EvenOdd(dirac)
+        b = eo.bhat(eta)
+        xo, k, hist = bicgstab(lambda v: eo.mhat(v).reshape(-1), b, tol, maxiter)
+        x = eo.full(xo, eta)
+    else:
+        y = np.einsum("ab,...bc->...ac", gamma(3), np.asarray(eta).reshape(dirac.shape))
+        x, k, hist = bicgstab(lambda v: dirac.K(v).reshape(-1), y, tol, maxiter)
+        x = x.reshape(dirac.shape)
+    return x, k, hist, dirac.true_residual(eta, x)

@@ -142,6 +142,91 @@ def cpu_baseline(cfg, U, evecs_np, iters_sample, iters_one_core, log_fn):
     }
 
 
+def _oracle_path(cfg, slices, sources):
+    """The oracle's whole path for the dilution indices `sources`: stout smearing, the
+    eigenvectors of `slices` (those the sources and sinks use), then per source its
+    construction, its CG solve to the workload's bar and its sink projection.  Seconds per
+    part and the CG iterations."""
+    import numpy as np
+
+    import oracle
+    import synth
+
+    U = synth.gauge_field(cfg.ns, cfg.nt, cfg.eps, cfg.seed)
+    t = {}
+    t0 = time.time()
+    S = oracle.stout_spatial(U, cfg.stout_rho, cfg.stout_steps)
+    t["stout_s"] = time.time() - t0
+    t0 = time.time()
+    ev, V0 = oracle.laph_eigpairs(S, cfg.nv, slices=slices)
+    t["eigvecs_s"] = time.time() - t0
+    V = np.zeros((cfg.nt, cfg.nv, cfg.ns, cfg.ns, cfg.ns, 3), dtype=np.complex128)
+    V[slices] = V0
+    rho = oracle.z4_noise(cfg.noise_s, cfg.noise_k, cfg.nt, cfg.nv)
+    sch = oracle.parse_dilution(cfg.dilution, cfg.nt, cfg.nv)
+    D = oracle.Dirac(U, cfg.m0, cfg.xi, cfg.csw, cfg.bc_t)
+    t["source_s"] = t["solve_s"] = t["sink_s"] = 0.0
+    its = []
+    for b in sources:
+        t0 = time.time()
+        eta = oracle.source(V, rho, sch, b)
+        t1 = time.time()
+        x, it, tr = D.solve(eta, tol=cfg.solve_tol, maxiter=20000)
+        t2 = time.time()
+        oracle.sink_project(V, x)
+        t3 = time.time()
+        t["source_s"] += t1 - t0
+        t["solve_s"] += t2 - t1
+        t["sink_s"] += t3 - t2
+        its.append(abs(it))
+    t["iterations"] = its
+    return t
+
+
+def cpu_report(log_fn):
+    """The oracle end to end on the host cores for the two smaller workloads: 4^3 x 8 in full
+    (all 256 sources, all slices) on all cores, and on one core for 16 of its sources; for
+    16^3 x 32 the eigenvectors of the two slices and the one source of dilution index 0,
+    extrapolated to 32 slices and 512 sources (on one core: its CG iterations alone,
+    extrapolated the same way)."""
+    import subprocess
+
+    import synth
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+    def one_core(name, slices, sources):
+        code = ("import sys, json; sys.path.insert(0, %r); import bench, synth; "
+                "print(json.dumps(bench._oracle_path(synth.CONFIGS[%r], %r, %r)))" % (ROOT, name, slices, sources))
+        out = subprocess.run([sys.executable, "-c", code], env=dict(os.environ, OMP_NUM_THREADS="1"),
+                             capture_output=True, text=True, timeout=1200)
+        return json.loads(out.stdout.strip().splitlines()[-1])
+
+    rep = {"cores": threads}
+    cfg = synth.CONFIGS["ns4_nt8"]
+    nsrc = 256
+    t = _oracle_path(cfg, list(range(cfg.nt)), list(range(nsrc)))
+    tot = sum(t[k] for k in ("stout_s", "eigvecs_s", "source_s", "solve_s", "sink_s"))
+    t1 = one_core(cfg.name, list(range(cfg.nt)), list(range(16)))
+    tot1 = t1["stout_s"] + t1["eigvecs_s"] + (t1["source_s"] + t1["solve_s"] + t1["sink_s"]) * nsrc / 16
+    rep[cfg.name] = {"measured": "all %d sources, all slices" % nsrc, "seconds": round(tot, 2),
+                     "sources_per_s": round(nsrc / tot, 3), "mean_iterations": sum(t["iterations"]) / nsrc,
+                     "parts_s": {k: round(v, 2) for k, v in t.items() if k.endswith("_s")},
+                     "one_core": {"seconds": round(tot1, 2), "sources_per_s": round(nsrc / tot1, 3),
+                                  "measured": "16 sources, scaled to 256"}}
+    log_fn("cpu report %s: %.1f s all cores, %.1f s one core" % (cfg.name, tot, tot1))
+    cfg = synth.CONFIGS["ns16_nt32"]
+    nsrc = 512
+    t = _oracle_path(cfg, [0, cfg.nt // 2], [0])
+    tot = t["stout_s"] + t["eigvecs_s"] * cfg.nt / 2 + (t["source_s"] + t["solve_s"] + t["sink_s"]) * nsrc
+    rep[cfg.name] = {"measured": "eigenvectors of 2 slices, source 0 (CG %d iterations); extrapolated to %d "
+                                 "slices and %d sources" % (t["iterations"][0], cfg.nt, nsrc),
+                     "seconds": round(tot, 1), "sources_per_s": round(nsrc / tot, 5),
+                     "parts_s": {k: round(v, 2) for k, v in t.items() if k.endswith("_s")}}
+    log_fn("cpu report %s: %.0f s all cores (extrapolated)" % (cfg.name, tot))
+    return rep
+
+
 def hop_roofline(k):
     """HBM roofline of one kernel from the library's per-kernel event timing: algorithmic
     bytes per launch over the average launch duration, and the counter traffic when a
@@ -189,9 +274,18 @@ def main():
                     help="only run the paper's solver, FP64 BiCGStab on the even-odd system, on the first "
                          "LapH source with this many iterations at most, and print its outcome (with "
                          "LAPH_VERBOSE=1 the library logs the residual every 256 iterations)")
+    ap.add_argument("--mass-scan", default="",
+                    help="only solve the first LapH source with FP64 even-odd CGNR at each of these comma-"
+                         "separated masses m0 (the workload's eigenvectors) and print the iteration counts")
+    ap.add_argument("--cpu-report", action="store_true",
+                    help="only time the oracle end to end on the host cores for the two smaller workloads "
+                         "and print the figures (no GPU)")
     ap.add_argument("--learned-sources", type=int, default=2,
                     help="sources solved with FGMRES and the learned preconditioner (0: skip)")
     args = ap.parse_args()
+    if args.cpu_report:
+        print(json.dumps({"cpu_report": cpu_report(log)}))
+        return 0
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path (LapH sources "
               "are independent solves; several GPUs would each take their own share of the "
@@ -236,6 +330,29 @@ def main():
     eta = torch.empty(shape, dtype=torch.complex128, device="cuda")
     x = torch.empty(shape, dtype=torch.complex128, device="cuda")
     coef = torch.empty((nsrc, cfg.nt, 4, cfg.nv), dtype=torch.complex128, device="cuda")
+
+    if args.mass_scan:
+        sv = P.solver_params(tol=cfg.solve_tol, maxiter=8000, precision="f64", block_rhs=1,
+                             solver=P.LAPH_SOLVER_CGNR)
+        P.make_diluted_source(L.ctx, evecs, cfg.nv, cfg.noise_s, cfg.noise_k, dil, 0, 1, eta[:1])
+        scan = []
+        for m0 in [float(v) for v in args.mass_scan.split(",")]:
+            pm = P.laph_dirac(m0, cfg.xi, cfg.csw, cfg.bc_t)
+            torch.cuda.synchronize()
+            t0 = time.time()
+            try:
+                st = P.dirac_solve(L.ctx, Ud, pm, eta[:1], x[:1], 1, sv)
+                rec = {"m0": m0, "iters": st[0].iters, "true_resid": st[0].true_resid, "status": st[0].status}
+            except P.LaphError as e:
+                rec = {"m0": m0, "error": str(e)}
+            torch.cuda.synchronize()
+            rec["seconds"] = round(time.time() - t0, 2)
+            log("mass scan: %s" % rec)
+            scan.append(rec)
+        print(json.dumps({"mass_scan": {"workload": cfg.name, "source": "LapH source b = 0 of (%s)" % cfg.dilution,
+                                        "solver": "FP64 CG on the normal equations of the even-odd system",
+                                        "points": scan}}))
+        return 0
 
     if args.bicgstab_probe > 0:
         sv = P.solver_params(tol=cfg.solve_tol, maxiter=args.bicgstab_probe, precision="f64", block_rhs=1,

@@ -297,3 +297,58 @@ def test_trained_network_gain_held_out(P):
         net.close()
     assert iters["trained"] <= 0.5 * iters["untrained"]
 
+
+
+@pytest.mark.parametrize("seeds", [range(200, 205), range(205, 210)])
+def test_trained_network_vs_plain_solver_production(P, seeds):
+    """What the trained network gains over the method without it, on the held-out gauge
+    seeds 200-209 at the production lattice 24^3 x 128 (the network was trained on 8^3 x 16
+    fields of seeds 100-199; its layers are gauge equivariant and translation invariant,
+    so they apply at any size): one Gaussian source per seed, solved by FGMRES with the
+    trained network as right preconditioner (FP64, one right-hand side) and by the plain
+    FP64 solver (CG on the normal equations of the even-odd system), both judged by the
+    oracle's true residual <= 1e-10.  Reported per seed: iterations, applications of the
+    even-odd operator (FGMRES one per iteration plus one network application, CGNR two) and
+    wall time.  Asserted: the network cuts operator applications at least in half; the
+    wall time is reported, not asserted (the network application costs more than the two
+    operator applications it saves)."""
+    import time
+
+    import torch
+
+    from paper_1104_3870_amd import train_ptnet as T
+
+    w, meta = T.load(T.os.path.join(T.ROOT, "paper_1104_3870_amd", "weights", "ptnet.npz"))
+    cfg = synth.CONFIGS["ns24_nt128"]
+    ns, nt = cfg.ns, cfg.nt
+    L = P.Lattice(ns, nt)
+    prm = P.laph_dirac(cfg.m0, cfg.xi, cfg.csw, cfg.bc_t)
+    net = P.PTNet(L.ctx, meta["channels"], seed=0)
+    net.set_weights(w)
+    forms = {"fgmres+net": P.solver_params(tol=1e-10, maxiter=3000, solver=P.LAPH_SOLVER_FGMRES, net=net, restart=32),
+             "cgnr": P.solver_params(tol=1e-10, maxiter=6000, precision="f64", block_rhs=1,
+                                     solver=P.LAPH_SOLVER_CGNR)}
+    apps = {"fgmres+net": 1, "cgnr": 2}
+    tot = {k: [0, 0.0] for k in forms}
+    for seed in seeds:
+        U = synth.gauge_field(ns, nt, cfg.eps, seed)
+        D = oracle.Dirac(U, cfg.m0, cfg.xi, cfg.csw, cfg.bc_t)
+        eta = synth.random_spinor(ns, nt, 1_000_003 * seed + 5, nrhs=1)
+        Ud, ed = dev(U), dev(eta)
+        for name, sv in forms.items():
+            x = torch.empty(eta.shape, dtype=torch.complex128, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.time()
+            st = P.dirac_solve(L.ctx, Ud, prm, ed, x, 1, sv)
+            torch.cuda.synchronize()
+            dt = time.time() - t0
+            tr = D.true_residual(eta[0], host(x)[0])
+            say("  seed", seed, name, "iters", st[0].iters, "operator applications", apps[name] * st[0].iters,
+                "seconds %.2f" % dt, "oracle resid %.2e" % tr, "fallback", st[0].fallback_used)
+            assert st[0].status == 0 and st[0].fallback_used == 0 and tr <= 1e-10
+            tot[name][0] += apps[name] * st[0].iters
+            tot[name][1] += dt
+        del Ud, ed, D
+    net.close()
+    say("  totals (operator applications, seconds):", tot)
+    assert tot["fgmres+net"][0] <= 0.5 * tot["cgnr"][0]

@@ -13,13 +13,14 @@
 #include <cmath>
 
 #include "laph_impl.h"
+#include "zgemm_mfma.h"
 
 namespace {
 
 // ------------------------------------------------------- batched complex product
 // C[b](m, n) = sum_k op(A[b](m, k)) B[b](k, n), op = conj when conjA; every operand is
 // addressed by strides (in complex elements); the batch index b splits into (b / nbi, b % nbi)
-// with a stride per part.  16 x 16 output tile per block, K staged in LDS 16 at a time.
+// with a stride per part.  Computed on the FP64 matrix cores (zgemm_mfma.h).
 struct Zgemm {
     const double2 *A;
     long sAo, sAi, sAm, sAk;
@@ -30,117 +31,125 @@ struct Zgemm {
     int M, N, K, nbi, conjA;
 };
 
-constexpr int kZT = 16;
-
-__global__ __launch_bounds__(kZT *kZT) void k_zgemm(Zgemm g)
-{
-    __shared__ double2 sa[kZT][kZT + 1];
-    __shared__ double2 sb[kZT][kZT + 1];
-    const long b = blockIdx.z;
-    const long bo = b / g.nbi, bi = b - bo * g.nbi;
-    const double2 *A = g.A + bo * g.sAo + bi * g.sAi;
-    const double2 *B = g.B + bo * g.sBo + bi * g.sBi;
-    double2 *C = g.C + bo * g.sCo + bi * g.sCi;
-    const int m0 = blockIdx.x * kZT, n0 = blockIdx.y * kZT;
-    const int tm = threadIdx.x % kZT, tn = threadIdx.x / kZT;
-    const int sk = threadIdx.x % kZT, sr = threadIdx.x / kZT;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int k0 = 0; k0 < g.K; k0 += kZT) {
-        const int k = k0 + sk;
-        double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
-        if (k < g.K) {
-            if (m0 + sr < g.M) {
-                va = A[(m0 + sr) * g.sAm + (long)k * g.sAk];
-                if (g.conjA) va.y = -va.y;
-            }
-            if (n0 + sr < g.N) vb = B[(long)k * g.sBk + (n0 + sr) * g.sBn];
-        }
-        sa[sk][sr] = va;
-        sb[sk][sr] = vb;
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < kZT; kk++) {
-            const double2 x = sa[kk][tm], y = sb[kk][tn];
-            acc.x = fma(x.x, y.x, fma(-x.y, y.y, acc.x));
-            acc.y = fma(x.x, y.y, fma(x.y, y.x, acc.y));
-        }
-        __syncthreads();
+struct GemmS {
+    Zgemm g;
+    int M, N, K;
+    __device__ bool tile(long &bt, int &m0, int &n0) const
+    {
+        bt = blockIdx.z;
+        m0 = blockIdx.x * zg::kTM;
+        n0 = blockIdx.y * zg::kTN;
+        return true;
     }
-    if (m0 + tm < g.M && n0 + tn < g.N) C[(m0 + tm) * g.sCm + (n0 + tn) * g.sCn] = acc;
-}
+    template <int KT>
+    __device__ void stage(zg::Tile<KT> &t, long bt, int m0, int n0, int k0) const
+    {
+        const long bo = bt / g.nbi, bi = bt - bo * g.nbi;
+        const double2 *A = g.A + bo * g.sAo + bi * g.sAi;
+        const double2 *B = g.B + bo * g.sBo + bi * g.sBi;
+        const double sg = g.conjA ? -1.0 : 1.0;
+        // the index running along the operand's unit stride varies fastest across lanes
+        const bool ak = g.sAk == 1;
+        for (int e = threadIdx.x; e < zg::kTM * KT; e += blockDim.x) {
+            const int m = ak ? e / KT : e % zg::kTM, k = ak ? e % KT : e / zg::kTM;
+            double2 v = make_double2(0.0, 0.0);
+            if (m0 + m < M && k0 + k < K) v = A[(m0 + m) * g.sAm + (long)(k0 + k) * g.sAk];
+            t.ar[k][m] = v.x;
+            t.ai[k][m] = sg * v.y;
+        }
+        for (int e = threadIdx.x; e < zg::kTN * KT; e += blockDim.x) {
+            const int n = e % zg::kTN, k = e / zg::kTN;
+            double2 v = make_double2(0.0, 0.0);
+            if (n0 + n < N && k0 + k < K) v = B[(long)(k0 + k) * g.sBk + (n0 + n) * g.sBn];
+            t.br[k][n] = v.x;
+            t.bi[k][n] = v.y;
+        }
+    }
+    __device__ void store(long bt, int m, int n, double re, double im) const
+    {
+        const long bo = bt / g.nbi, bi = bt - bo * g.nbi;
+        g.C[bo * g.sCo + bi * g.sCi + m * g.sCm + n * g.sCn] = make_double2(re, im);
+    }
+};
 
 void zgemm(laph_ctx *c, const Zgemm &g, long batch)
 {
     if (g.M <= 0 || g.N <= 0 || batch <= 0) return;
-    const unsigned gm = (g.M + kZT - 1) / kZT, gn = (g.N + kZT - 1) / kZT;
+    const unsigned gm = (g.M + zg::kTM - 1) / zg::kTM, gn = (g.N + zg::kTN - 1) / zg::kTN;
     LAPH_CHECK(gn <= 65535 && batch <= 65535, LAPH_EINVAL, "product too large for one launch");
-    hipLaunchKernelGGL(k_zgemm, dim3(gm, gn, (unsigned)batch), dim3(kZT * kZT), 0, c->stream, g);
+    GemmS s{g, g.M, g.N, g.K};
+    hipLaunchKernelGGL((zg::k_zgemm<16, GemmS>), dim3(gm, gn, (unsigned)batch), dim3(256), 0, c->stream, s);
     LAPH_HIP(hipGetLastError());
 }
 
 // ------------------------------------------------------- eigenvector tensor
-constexpr int kTX = 8;  // sites staged per LDS step (K = 3 kTX)
-
-// T[t][n1][n2][n3] for one n1, a tile of 16 n2 > n1 and a tile of 16 n3:
-// sum_{x,c} (e^{-ip.x} V_n1(x) x V_n2(x))_c V_n3(x, c), (u x w)_c = eps_abc u_a w_b
-__global__ __launch_bounds__(256) void k_baryon_tensor(const double2 *__restrict__ V, const double2 *__restrict__ ph,
-                                                       int nv, long V3, int nt, double2 *__restrict__ T)
-{
-    __shared__ double2 sa[3 * kTX][17];  // cross products [x c][n2 in tile]
-    __shared__ double2 sb[3 * kTX][17];  // V_n3 [x c][n3 in tile]
-    __shared__ double2 s1[kTX][3];       // V_n1 on the staged sites
-    const int n1 = blockIdx.x;
-    const int n2t = blockIdx.y / ((nv + 15) / 16), n3t = blockIdx.y % ((nv + 15) / 16);
-    const int t = blockIdx.z;
-    const int n20 = n2t * 16, n30 = n3t * 16;
-    if (n20 + 15 <= n1) return;  // every n2 of the tile is <= n1: filled by symmetry
-    const int tm = threadIdx.x % 16, tn = threadIdx.x / 16;
-    const double2 *Vt = V + (long)t * nv * V3 * 3;
-    double2 acc = make_double2(0.0, 0.0);
-    for (long x0 = 0; x0 < V3; x0 += kTX) {
-        if (threadIdx.x < kTX * 3) {
-            const int xs = threadIdx.x / 3, cc = threadIdx.x % 3;
+// T[t][n1][n2][n3] = sum_{x,c} (e^{-ip.x} V_n1(x) x V_n2(x))_c V_n3(x, c), (u x w)_c =
+// eps_abc u_a w_b: for one n1 and slice the product of A[n2][(x c)] (the cross products,
+// formed while staging, eight sites per K tile) with B[(x c)][n3] = V_n3(x, c) on the
+// FP64 matrix cores.  Blocks whose n2 all lie below n1 return (those entries follow by
+// antisymmetry); the rest write n2 > n1 and its mirror, and zero at n2 = n1.
+struct TensorS {
+    const double2 *V, *ph;
+    double2 *T;
+    int nv, ntile;
+    long V3;
+    int M, N, K;  // nv, nv, 3 V3
+    __device__ bool tile(long &bt, int &m0, int &n0) const
+    {
+        const int n1 = blockIdx.x;
+        m0 = (blockIdx.y / ntile) * zg::kTM;
+        n0 = (blockIdx.y % ntile) * zg::kTN;
+        bt = blockIdx.z;
+        return (m0 + zg::kTM < nv ? m0 + zg::kTM : nv) - 1 >= n1;
+    }
+    template <int KT>
+    __device__ void stage(zg::Tile<KT> &t, long bt, int m0, int n0, int k0) const
+    {
+        static_assert(KT % 3 == 0, "whole sites per K tile");
+        constexpr int XS = KT / 3;
+        const int n1 = blockIdx.x;
+        const long x0 = k0 / 3;
+        const double2 *Vt = V + bt * nv * V3 * 3;
+        for (int e = threadIdx.x; e < zg::kTM * XS; e += blockDim.x) {
+            const int m = e / XS, xs = e - m * XS;
             const long x = x0 + xs;
-            s1[xs][cc] = x < V3 ? cmul(ph[x], Vt[((long)n1 * V3 + x) * 3 + cc]) : make_double2(0.0, 0.0);
-        }
-        __syncthreads();
-        // stage: lanes (row r = lane / 16 picks the vector, site q = lane % 16 < kTX)
-        {
-            const int r = threadIdx.x / 16, q = threadIdx.x % 16;
-            if (q < kTX) {
-                const long x = x0 + q;
-                double2 w[3] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
-                double2 u[3] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
-                const int n2 = n20 + r, n3 = n30 + r;
-                if (x < V3 && n2 < nv)
-                    for (int cc = 0; cc < 3; cc++) w[cc] = Vt[((long)n2 * V3 + x) * 3 + cc];
-                if (x < V3 && n3 < nv)
-                    for (int cc = 0; cc < 3; cc++) u[cc] = Vt[((long)n3 * V3 + x) * 3 + cc];
-                const double2 *v1 = s1[q];
-                // cross product e^{-ip.x} V_n1 x V_n2
-                sa[q * 3 + 0][r] = csub(cmul(v1[1], w[2]), cmul(v1[2], w[1]));
-                sa[q * 3 + 1][r] = csub(cmul(v1[2], w[0]), cmul(v1[0], w[2]));
-                sa[q * 3 + 2][r] = csub(cmul(v1[0], w[1]), cmul(v1[1], w[0]));
-                for (int cc = 0; cc < 3; cc++) sb[q * 3 + cc][r] = u[cc];
+            double2 cr[3] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
+            if (x < V3 && m0 + m < nv) {
+                const double2 p = ph[x];
+                const double2 *u = Vt + ((long)n1 * V3 + x) * 3, *w = Vt + ((long)(m0 + m) * V3 + x) * 3;
+                const double2 u0 = cmul(p, u[0]), u1 = cmul(p, u[1]), u2 = cmul(p, u[2]);
+                const double2 w0 = w[0], w1 = w[1], w2 = w[2];
+                cr[0] = csub(cmul(u1, w2), cmul(u2, w1));
+                cr[1] = csub(cmul(u2, w0), cmul(u0, w2));
+                cr[2] = csub(cmul(u0, w1), cmul(u1, w0));
+            }
+#pragma unroll
+            for (int cc = 0; cc < 3; cc++) {
+                t.ar[3 * xs + cc][m] = cr[cc].x;
+                t.ai[3 * xs + cc][m] = cr[cc].y;
             }
         }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < 3 * kTX; kk++) {
-            const double2 a = sa[kk][tm], bv = sb[kk][tn];
-            acc.x = fma(a.x, bv.x, fma(-a.y, bv.y, acc.x));
-            acc.y = fma(a.x, bv.y, fma(a.y, bv.x, acc.y));
+        for (int e = threadIdx.x; e < zg::kTN * KT; e += blockDim.x) {
+            const int n = e / KT, k = e - n * KT;
+            const long kk = (long)k0 + k;
+            double2 v = make_double2(0.0, 0.0);
+            if (kk < K && n0 + n < nv) v = Vt[(long)(n0 + n) * K + kk];
+            t.br[k][n] = v.x;
+            t.bi[k][n] = v.y;
         }
-        __syncthreads();
     }
-    const int n2 = n20 + tm, n3 = n30 + tn;
-    if (n2 < nv && n3 < nv && n2 > n1) {
-        const long base = (long)t * nv * nv * nv;
-        T[base + ((long)n1 * nv + n2) * nv + n3] = acc;
-        T[base + ((long)n2 * nv + n1) * nv + n3] = make_double2(-acc.x, -acc.y);
+    __device__ void store(long bt, int n2, int n3, double re, double im) const
+    {
+        const int n1 = blockIdx.x;
+        const long base = bt * nv * nv * nv;
+        if (n2 > n1) {
+            T[base + ((long)n1 * nv + n2) * nv + n3] = make_double2(re, im);
+            T[base + ((long)n2 * nv + n1) * nv + n3] = make_double2(-re, -im);
+        } else if (n2 == n1) {
+            T[base + ((long)n1 * nv + n1) * nv + n3] = make_double2(0.0, 0.0);
+        }
     }
-    if (n2 == n1 && n3 < nv) T[(long)t * nv * nv * nv + ((long)n1 * nv + n1) * nv + n3] = make_double2(0.0, 0.0);
-}
+};
 
 __global__ void k_phase3(double2 *ph, int ns, int k0, int k1, int k2)
 {
@@ -255,10 +264,11 @@ extern "C" int laph_baryon_tensor(laph_ctx_t c, const double *evecs, int nv, con
     const long V3 = c->g.V3;
     double2 *ph = (double2 *)ctx_named(c, "bar.phase", sizeof(double2) * V3);
     hipLaunchKernelGGL(k_phase3, dim3(nblocks_for(V3, 256)), dim3(256), 0, c->stream, ph, c->g.ns, k[0], k[1], k[2]);
-    const int tiles = (nv + 15) / 16;
+    const int tiles = (nv + zg::kTM - 1) / zg::kTM;
     LAPH_CHECK((long)tiles * tiles <= 65535 && c->g.nt <= 65535, LAPH_EINVAL, "nv too large for one launch");
-    hipLaunchKernelGGL(k_baryon_tensor, dim3(nv, tiles * tiles, c->g.nt), dim3(256), 0, c->stream,
-                       (const double2 *)evecs, (const double2 *)ph, nv, V3, c->g.nt, (double2 *)T);
+    LAPH_CHECK(3 * V3 < (1L << 31), LAPH_EINVAL, "slice too large");
+    TensorS ts{(const double2 *)evecs, (const double2 *)ph, (double2 *)T, nv, tiles, V3, nv, nv, (int)(3 * V3)};
+    hipLaunchKernelGGL((zg::k_zgemm<24, TensorS>), dim3(nv, tiles * tiles, c->g.nt), dim3(256), 0, c->stream, ts);
     LAPH_HIP(hipGetLastError());
     LAPH_API_END(c)
 }

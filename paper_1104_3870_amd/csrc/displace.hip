@@ -9,6 +9,7 @@
 #include <cmath>
 
 #include "laph_impl.h"
+#include "zgemm_mfma.h"
 
 namespace {
 
@@ -84,48 +85,43 @@ __global__ void k_phase(double2 *ph, int ns, int k0, int k1, int k2)
     ph[x] = make_double2(c, s);
 }
 
-constexpr int kOT = 16;  // overlap tile (n, m) per block
-constexpr int kOK = 16;  // K values staged per LDS step
-
 // O[t][n][m] = sum_{x, c} conj(a[t][n][x][c]) ph[x] b[t][m][x][c]: per slice the product
-// A^dag (ph B) over K = 3 Ns^3; one block per slice and kOT x kOT tile
-__global__ __launch_bounds__(kOT *kOT) void k_overlap(const double2 *__restrict__ a, int na,
-                                                      const double2 *__restrict__ b, int nb,
-                                                      const double2 *__restrict__ ph, long V3,
-                                                      double2 *__restrict__ out)
-{
-    __shared__ double2 sa[kOK][kOT + 1];
-    __shared__ double2 sb[kOK][kOT + 1];
-    const int t = blockIdx.z;
-    const int n0 = blockIdx.x * kOT, m0 = blockIdx.y * kOT;
-    const int tn = threadIdx.x % kOT, tm = threadIdx.x / kOT;
-    const long K = 3 * V3;
-    double2 acc = make_double2(0.0, 0.0);
-    for (long k0 = 0; k0 < K; k0 += kOK) {
-        {
-            const int sk = threadIdx.x % kOK, sr = threadIdx.x / kOK;
-            const long k = k0 + sk;
-            double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
-            if (k < K) {
-                const int n = n0 + sr, m = m0 + sr;
-                if (n < na) va = a[((long)t * na + n) * K + k];
-                if (m < nb) vb = cmul(ph[k / 3], b[((long)t * nb + m) * K + k]);
-            }
-            sa[sk][sr] = va;
-            sb[sk][sr] = vb;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < kOK; kk++) {
-            const double2 x = sa[kk][tn], y = sb[kk][tm];
-            acc.x = fma(x.x, y.x, fma(x.y, y.y, acc.x));
-            acc.y = fma(x.x, y.y, fma(-x.y, y.x, acc.y));
-        }
-        __syncthreads();
+// A^dag (ph B) over K = 3 Ns^3 on the FP64 matrix cores; one block per slice and 64 x 64
+// tile, the conjugate and the phase applied while staging
+struct OverlapS {
+    const double2 *a, *b, *ph;
+    double2 *out;
+    int M, N, K;  // na, nb, 3 Ns^3
+    __device__ bool tile(long &bt, int &m0, int &n0) const
+    {
+        bt = blockIdx.z;
+        m0 = blockIdx.x * zg::kTM;
+        n0 = blockIdx.y * zg::kTN;
+        return true;
     }
-    const int n = n0 + tn, m = m0 + tm;
-    if (n < na && m < nb) out[((long)t * na + n) * nb + m] = acc;
-}
+    template <int KT>
+    __device__ void stage(zg::Tile<KT> &t, long bt, int m0, int n0, int k0) const
+    {
+        static_assert(zg::kTM == zg::kTN, "one loop stages both operands");
+        for (int e = threadIdx.x; e < zg::kTM * KT; e += blockDim.x) {
+            const int r = e / KT, k = e - r * KT;  // k fastest: KT consecutive values of a row
+            const long kk = (long)k0 + k;
+            double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
+            if (kk < K) {
+                if (m0 + r < M) va = a[(bt * M + m0 + r) * (long)K + kk];
+                if (n0 + r < N) vb = cmul(ph[kk / 3], b[(bt * N + n0 + r) * (long)K + kk]);
+            }
+            t.ar[k][r] = va.x;
+            t.ai[k][r] = -va.y;
+            t.br[k][r] = vb.x;
+            t.bi[k][r] = vb.y;
+        }
+    }
+    __device__ void store(long bt, int m, int n, double re, double im) const
+    {
+        out[(bt * M + m) * (long)N + n] = make_double2(re, im);
+    }
+};
 
 // out[j][t][beta][p] = sum_m O[t][p][m] b[j][t][beta][m]; one lane per output element
 __global__ void k_overlap_apply(const double2 *__restrict__ O, int na, int nb, const double2 *__restrict__ b,
@@ -169,10 +165,11 @@ extern "C" int laph_mom_overlap(laph_ctx_t c, const double *a, int na, const dou
     const long V3 = c->g.V3;
     double2 *ph = (double2 *)ctx_named(c, "ovl.phase", sizeof(double2) * V3);
     hipLaunchKernelGGL(k_phase, dim3(nblocks_for(V3, 256)), dim3(256), 0, c->stream, ph, c->g.ns, k[0], k[1], k[2]);
-    const unsigned gn = (na + kOT - 1) / kOT, gm = (nb + kOT - 1) / kOT;
+    const unsigned gn = (na + zg::kTM - 1) / zg::kTM, gm = (nb + zg::kTN - 1) / zg::kTN;
     LAPH_CHECK(gm <= 65535 && c->g.nt <= 65535, LAPH_EINVAL, "too many fields for one launch");
-    hipLaunchKernelGGL(k_overlap, dim3(gn, gm, c->g.nt), dim3(kOT * kOT), 0, c->stream, (const double2 *)a, na,
-                       (const double2 *)b, nb, (const double2 *)ph, V3, (double2 *)out);
+    LAPH_CHECK(3 * V3 < (1L << 31), LAPH_EINVAL, "slice too large");
+    OverlapS os{(const double2 *)a, (const double2 *)b, (const double2 *)ph, (double2 *)out, na, nb, (int)(3 * V3)};
+    hipLaunchKernelGGL((zg::k_zgemm<16, OverlapS>), dim3(gn, gm, c->g.nt), dim3(256), 0, c->stream, os);
     LAPH_HIP(hipGetLastError());
     LAPH_API_END(c)
 }

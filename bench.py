@@ -608,7 +608,7 @@ def main():
         ev2.record()
         torch.cuda.synchronize()
         ms_t, ms_b = ev0.elapsed_time(ev1), ev1.elapsed_time(ev2)
-        tflops = 8.0 * nt * (nv * (nv + 16) / 2.0) * nv * 3 * V3  # n1 < n2 tiles, all n3
+        tflops = 8.0 * nt * (nv * (nv - 1) * (nv - 2) / 6.0) * 3 * V3  # useful: n1 < n2 < n3
         bflops = 8.0 * nt * (nv * nv * nv * 4 * nbq + nv * nv * 16 * nbq * nbq + 4 * nbq * nv * 16 * nbq * nbq)
         hadron["baryon_tensor"] = {"kernel": "baryon_tensor (N_v = %d, K = 3 Ns^3)" % nv, "ms": round(ms_t, 2),
                                    "roofline": {"bound": "fp64", "achieved": round(tflops / (ms_t * 1e-3) / 1e12, 2),

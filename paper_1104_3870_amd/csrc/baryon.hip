@@ -84,72 +84,130 @@ void zgemm(laph_ctx *c, const Zgemm &g, long batch)
 
 // ------------------------------------------------------- eigenvector tensor
 // T[t][n1][n2][n3] = sum_{x,c} (e^{-ip.x} V_n1(x) x V_n2(x))_c V_n3(x, c), (u x w)_c =
-// eps_abc u_a w_b: for one n1 and slice the product of A[n2][(x c)] (the cross products,
-// formed while staging, eight sites per K tile) with B[(x c)][n3] = V_n3(x, c) on the
-// FP64 matrix cores.  Blocks whose n2 all lie below n1 return (those entries follow by
-// antisymmetry); the rest write n2 > n1 and its mirror, and zero at n2 = n1.
-struct TensorS {
-    const double2 *V, *ph;
-    double2 *T;
-    int nv, ntile;
-    long V3;
-    int M, N, K;  // nv, nv, 3 V3
-    __device__ bool tile(long &bt, int &m0, int &n0) const
-    {
-        const int n1 = blockIdx.x;
-        m0 = (blockIdx.y / ntile) * zg::kTM;
-        n0 = (blockIdx.y % ntile) * zg::kTN;
-        bt = blockIdx.z;
-        return (m0 + zg::kTM < nv ? m0 + zg::kTM : nv) - 1 >= n1;
+// eps_abc u_a w_b, is totally antisymmetric, so only n1 < n2 < n3 is computed and each
+// value is written to its six images (the tensor is zeroed first, which leaves every entry
+// with a repeated index at zero).  One block per (n1, slice, chunk of tile pairs): for the
+// 16-row tiles a <= b of n2 and n3 that can hold n1 < n2 < n3, the products
+// A[n2][(x c)] B[(x c)][n3] with A the cross products (formed while staging) and
+// B = V_n3, on the FP64 matrix cores; all N_v rows of A and B are staged through LDS
+// four sites at a time, and the block's four waves take the pairs in turn.
+constexpr int kBT = 16;  // MFMA tile
+constexpr int kBK = 12;  // K per stage: four sites x three colours
+constexpr int kBP = 6;   // tile pairs per wave and block
+
+__host__ __device__ inline int tri_pairs(int u) { return u * (u + 1) / 2; }
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_baryon_tensor_tri(const double2 *__restrict__ V,
+                                                           const double2 *__restrict__ ph, int nv, long V3, int T,
+                                                           double2 *__restrict__ out)
+{
+    extern __shared__ double lds[];
+    const int NP = T * kBT + 4;  // LDS row stride (doubles)
+    double *ar = lds, *ai = ar + kBK * NP, *br = ai + kBK * NP, *bi = br + kBK * NP;
+    const int n1 = blockIdx.x, t = blockIdx.z;
+    const int amin = (n1 + 1) / kBT;  // first n2 tile holding an n2 > n1
+    if (amin >= T) return;
+    const int np = tri_pairs(T - amin);
+    const int p0 = blockIdx.y * 4 * kBP;
+    if (p0 >= np) return;  // uniform over the block
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lk = l >> 4;
+    // this wave's pairs p = p0 + wave + 4 j, decoded to (a, b), a <= b
+    int pa[kBP], pb[kBP];
+#pragma unroll
+    for (int j = 0; j < kBP; j++) {
+        int p = p0 + wave + 4 * j, a = amin;
+        pa[j] = -1;
+        pb[j] = -1;
+        if (p < np && p < p0 + 4 * kBP) {
+            while (p >= T - a) {
+                p -= T - a;
+                a++;
+            }
+            pa[j] = a;
+            pb[j] = a + p;
+        }
     }
-    template <int KT>
-    __device__ void stage(zg::Tile<KT> &t, long bt, int m0, int n0, int k0) const
-    {
-        static_assert(KT % 3 == 0, "whole sites per K tile");
-        constexpr int XS = KT / 3;
-        const int n1 = blockIdx.x;
+    zg::d4 cr[kBP], ci[kBP];
+#pragma unroll
+    for (int j = 0; j < kBP; j++) {
+        cr[j] = zg::d4{0.0, 0.0, 0.0, 0.0};
+        ci[j] = zg::d4{0.0, 0.0, 0.0, 0.0};
+    }
+    const long K = 3 * V3;
+    const double2 *Vt = V + (long)t * nv * K;
+    const int rows = T * kBT;
+    for (long k0 = 0; k0 < K; k0 += kBK) {
         const long x0 = k0 / 3;
-        const double2 *Vt = V + bt * nv * V3 * 3;
-        for (int e = threadIdx.x; e < zg::kTM * XS; e += blockDim.x) {
-            const int m = e / XS, xs = e - m * XS;
+        // A: cross products of e^{-ip.x} V_n1 with V_n2 on the four sites
+        for (int e = threadIdx.x; e < rows * 4; e += blockDim.x) {
+            const int m = e >> 2, xs = e & 3;
             const long x = x0 + xs;
-            double2 cr[3] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
-            if (x < V3 && m0 + m < nv) {
+            double2 c3[3] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
+            if (x < V3 && m < nv) {
                 const double2 p = ph[x];
-                const double2 *u = Vt + ((long)n1 * V3 + x) * 3, *w = Vt + ((long)(m0 + m) * V3 + x) * 3;
+                const double2 *u = Vt + ((long)n1 * V3 + x) * 3, *w = Vt + ((long)m * V3 + x) * 3;
                 const double2 u0 = cmul(p, u[0]), u1 = cmul(p, u[1]), u2 = cmul(p, u[2]);
                 const double2 w0 = w[0], w1 = w[1], w2 = w[2];
-                cr[0] = csub(cmul(u1, w2), cmul(u2, w1));
-                cr[1] = csub(cmul(u2, w0), cmul(u0, w2));
-                cr[2] = csub(cmul(u0, w1), cmul(u1, w0));
+                c3[0] = csub(cmul(u1, w2), cmul(u2, w1));
+                c3[1] = csub(cmul(u2, w0), cmul(u0, w2));
+                c3[2] = csub(cmul(u0, w1), cmul(u1, w0));
             }
 #pragma unroll
             for (int cc = 0; cc < 3; cc++) {
-                t.ar[3 * xs + cc][m] = cr[cc].x;
-                t.ai[3 * xs + cc][m] = cr[cc].y;
+                ar[(3 * xs + cc) * NP + m] = c3[cc].x;
+                ai[(3 * xs + cc) * NP + m] = c3[cc].y;
             }
         }
-        for (int e = threadIdx.x; e < zg::kTN * KT; e += blockDim.x) {
-            const int n = e / KT, k = e - n * KT;
-            const long kk = (long)k0 + k;
+        // B: V_n3 on the same four sites (K contiguous per vector)
+        for (int e = threadIdx.x; e < rows * kBK; e += blockDim.x) {
+            const int n = e / kBK, k = e - n * kBK;
+            const long kk = k0 + k;
             double2 v = make_double2(0.0, 0.0);
-            if (kk < K && n0 + n < nv) v = Vt[(long)(n0 + n) * K + kk];
-            t.br[k][n] = v.x;
-            t.bi[k][n] = v.y;
+            if (kk < K && n < nv) v = Vt[(long)n * K + kk];
+            br[k * NP + n] = v.x;
+            bi[k * NP + n] = v.y;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kBK; kk += 4) {
+#pragma unroll
+            for (int j = 0; j < kBP; j++) {
+                if (pa[j] < 0) continue;  // uniform over the wave
+                const int ia = (kk + lk) * NP + kBT * pa[j] + lr, ib = (kk + lk) * NP + kBT * pb[j] + lr;
+                const double xr = ar[ia], xi = ai[ia], yr = br[ib], yi = bi[ib];
+                cr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr, yr, cr[j], 0, 0, 0);
+                cr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-xi, yi, cr[j], 0, 0, 0);
+                ci[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr, yi, ci[j], 0, 0, 0);
+                ci[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi, yr, ci[j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // element v of lane l: C[lk + 4 v][lr] of the pair's tile (see zgemm_mfma.h)
+    const long nv2 = (long)nv * nv, base = (long)t * nv * nv2;
+#pragma unroll
+    for (int j = 0; j < kBP; j++) {
+        if (pa[j] < 0) continue;
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int n2 = kBT * pa[j] + lk + 4 * v, n3 = kBT * pb[j] + lr;
+            if (n2 <= n1 || n3 <= n2 || n3 >= nv) continue;
+            const double2 q = make_double2(cr[j][v], ci[j][v]), mq = make_double2(-cr[j][v], -ci[j][v]);
+            out[base + n1 * nv2 + (long)n2 * nv + n3] = q;
+            out[base + n1 * nv2 + (long)n3 * nv + n2] = mq;
+            out[base + n2 * nv2 + (long)n1 * nv + n3] = mq;
+            out[base + n2 * nv2 + (long)n3 * nv + n1] = q;
+            out[base + n3 * nv2 + (long)n1 * nv + n2] = q;
+            out[base + n3 * nv2 + (long)n2 * nv + n1] = mq;
         }
     }
-    __device__ void store(long bt, int n2, int n3, double re, double im) const
-    {
-        const int n1 = blockIdx.x;
-        const long base = bt * nv * nv * nv;
-        if (n2 > n1) {
-            T[base + ((long)n1 * nv + n2) * nv + n3] = make_double2(re, im);
-            T[base + ((long)n2 * nv + n1) * nv + n3] = make_double2(-re, -im);
-        } else if (n2 == n1) {
-            T[base + ((long)n1 * nv + n1) * nv + n3] = make_double2(0.0, 0.0);
-        }
-    }
-};
+}
+
+__global__ void k_zero2(double2 *p, long n)
+{
+    const long q = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (q < n) p[q] = make_double2(0.0, 0.0);
+}
 
 __global__ void k_phase3(double2 *ph, int ns, int k0, int k1, int k2)
 {
@@ -264,11 +322,18 @@ extern "C" int laph_baryon_tensor(laph_ctx_t c, const double *evecs, int nv, con
     const long V3 = c->g.V3;
     double2 *ph = (double2 *)ctx_named(c, "bar.phase", sizeof(double2) * V3);
     hipLaunchKernelGGL(k_phase3, dim3(nblocks_for(V3, 256)), dim3(256), 0, c->stream, ph, c->g.ns, k[0], k[1], k[2]);
-    const int tiles = (nv + zg::kTM - 1) / zg::kTM;
-    LAPH_CHECK((long)tiles * tiles <= 65535 && c->g.nt <= 65535, LAPH_EINVAL, "nv too large for one launch");
-    LAPH_CHECK(3 * V3 < (1L << 31), LAPH_EINVAL, "slice too large");
-    TensorS ts{(const double2 *)evecs, (const double2 *)ph, (double2 *)T, nv, tiles, V3, nv, nv, (int)(3 * V3)};
-    hipLaunchKernelGGL((zg::k_zgemm<24, TensorS>), dim3(nv, tiles * tiles, c->g.nt), dim3(256), 0, c->stream, ts);
+    const int tiles = (nv + kBT - 1) / kBT;
+    const size_t lds = sizeof(double) * 4 * kBK * (size_t)(tiles * kBT + 4);
+    LAPH_CHECK(lds <= 160 * 1024, LAPH_EINVAL, "nv too large: the tensor kernel stages all N_v vectors in LDS");
+    LAPH_CHECK(c->g.nt <= 65535 && 3 * V3 < (1L << 31), LAPH_EINVAL, "lattice too large for one launch");
+    if (lds > 64 * 1024)
+        LAPH_HIP(hipFuncSetAttribute((const void *)k_baryon_tensor_tri, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds));
+    const long total = (long)c->g.nt * nv * nv * nv;
+    hipLaunchKernelGGL(k_zero2, dim3(nblocks_for(total, 256)), dim3(256), 0, c->stream, (double2 *)T, total);
+    const int chunks = (tri_pairs(tiles) + 4 * kBP - 1) / (4 * kBP);
+    hipLaunchKernelGGL(k_baryon_tensor_tri, dim3(nv, chunks, c->g.nt), dim3(256), lds, c->stream,
+                       (const double2 *)evecs, (const double2 *)ph, nv, V3, tiles, (double2 *)T);
     LAPH_HIP(hipGetLastError());
     LAPH_API_END(c)
 }

@@ -132,6 +132,8 @@ struct DslashArgs {
     double wt, ws;  // hop weights (time, space), including the -1/2
     double bct;     // sign on hops across the time boundary
     int g5d;        // 1: gamma_5 applied to D psi before the epilogue
+    int wby, wbz;   // site walk: tiles of Ns x wby x wbz sites through all time slices (set
+                    // by the launcher; 0: checkerboard order)
 };
 
 // launcher (dslash.hip); SPI = storage of in/out/x

@@ -217,6 +217,27 @@ __device__ __forceinline__ void hop_rolled(const DslashArgs &P, long i, int r, i
     }
 }
 
+// checkerboard index and coordinates of position pos of the tiled site walk: tiles of
+// Ns x by x bz sites (x halved by the parity), one after the other, each visited slice by
+// slice through all Nt slices; the time neighbours of a tile slice are the tile slices just
+// before and after it in the walk, so that with many right-hand sides per site they are
+// still in L2 (in checkerboard order they are Ns^3 / 2 sites away)
+__device__ __forceinline__ long walk_coords(unsigned pos, int ns, int nt, int par, int by, int bz, int &x, int &y,
+                                            int &z, int &t)
+{
+    const unsigned nsh = (unsigned)ns >> 1, A = nsh * by * bz;
+    const unsigned q = pos / A, loc = pos - q * A;
+    const unsigned tile = q / (unsigned)nt;
+    t = (int)(q - tile * nt);
+    const unsigned q1 = loc / nsh, xh = loc - q1 * nsh;
+    const unsigned zz = q1 / (unsigned)by, yy = q1 - zz * by;
+    const unsigned nty = (unsigned)ns / by, tz = tile / nty, ty = tile - tz * nty;
+    y = (int)(ty * by + yy);
+    z = (int)(tz * bz + zz);
+    x = 2 * (int)xh + ((y + z + t + par) & 1);
+    return (long)xh + (long)nsh * (y + (long)ns * (z + (long)ns * t));
+}
+
 template <class SP, class GP, class CP, int MODE, bool O32>
 __global__ __launch_bounds__(256) void k_dslash(const DslashArgs P)
 {
@@ -226,11 +247,18 @@ __global__ __launch_bounds__(256) void k_dslash(const DslashArgs P)
     const int R = P.R;
     const long Vh = P.Vh;
     if (tid >= Vh * R) return;
-    long i = tid / R;
-    int r = (int)(tid - i * R);
+    // 32-bit lane arithmetic: the launcher guarantees Vh R < 2^28
+    const unsigned pos = (unsigned)tid / (unsigned)R;
+    const int r = (int)((unsigned)tid - pos * (unsigned)R);
     const int ns = P.ns, nt = P.nt, par = P.par, opar = par ^ 1;
     int x, y, z, t;
-    cb_coords(i, par, ns, x, y, z, t);
+    long i;
+    if (P.wby) {
+        i = walk_coords(pos, ns, nt, par, P.wby, P.wbz, x, y, z, t);
+    } else {
+        i = pos;
+        cb_coords(i, par, ns, x, y, z, t);
+    }
     const auto *in = (const typename SP::E *)P.in;
     const auto *g = (const typename GP::E *)P.gauge;
 
@@ -359,7 +387,13 @@ void launch_dslash(laph_ctx *c, int mode, const DslashArgs &a, hipStream_t st)
     // and clover planes are smaller); callers split larger batches
     LAPH_CHECK((unsigned long long)n * sizeof(double2) < (1ull << 32), LAPH_EINVAL,
                "%d FP64 fields of %ld sites exceed the hopping kernel's 32-bit offsets", a.R, a.Vh);
-    launch_modes<SP, GP, CP, true>(mode, grid, block, st, a);
+    // many right-hand sides per site: a site's records span R x 192 B, so the time
+    // neighbours of checkerboard order (Ns^3 / 2 sites away) fall out of L2; walk tiles
+    // through time instead (3 x 3 where Ns allows it, else 2 x 2)
+    DslashArgs b = a;
+    b.wby = b.wbz = 0;
+    if (a.R >= 8) b.wby = b.wbz = (a.ns % 3 == 0) ? 3 : 2;
+    launch_modes<SP, GP, CP, true>(mode, grid, block, st, b);
     LAPH_HIP(hipGetLastError());
     bool has_x = a.x != nullptr && (mode != M_PLAIN || a.x);
     if (e0)

@@ -1,4 +1,4 @@
-"""HBM traffic of a kernel from rocprofv3 counter runs.
+"""HBM traffic and VALU issue of a kernel from rocprofv3 counter runs.
 
 Two programs run under `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` (one counter
 per run): the workload, and a device copy of known size that calibrates what each counter
@@ -9,6 +9,9 @@ timing label, with a hash of the kernel's sources so that a changed kernel is
 not credited with old counters.
 
     python -m paper_1104_3870_amd.profile_traffic copy            # calibration program
+    python -m paper_1104_3870_amd.profile_traffic sq --dir DIR --match 'k_dslash_lds<S16, 1, false>' ...
+        # mean SQ_WAVES, SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU, SQ_BUSY_CYCLES, GRBM_GUI_ACTIVE per
+        # dispatch of each matched kernel, and VALU instructions per wave
     python -m paper_1104_3870_amd.profile_traffic summarize --label 'dslash_lds<f16,inv,R32>' \\
         --match 'k_dslash_lds<S16, 1, false>' --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR \\
         --sources paper_1104_3870_amd/csrc/dslash_mr.hip --profile NAME
@@ -41,7 +44,8 @@ def copy_program(reps=5):
 
 
 def counter_avg(directory, match, counter):
-    """Mean counter value (KB) per dispatch of kernels whose name contains `match`."""
+    """Mean counter value per dispatch (FETCH_SIZE, WRITE_SIZE: KB) of kernels whose name
+    contains `match`."""
     dbs = glob.glob(os.path.join(directory, "**", "*.db"), recursive=True)
     if not dbs:
         raise FileNotFoundError("no rocprofv3 database under %s" % directory)
@@ -89,6 +93,24 @@ def summarize(a):
     print(json.dumps({a.label: rec}, indent=1))
 
 
+SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_BUSY_CYCLES", "GRBM_GUI_ACTIVE")
+
+
+def sq(a):
+    out = {}
+    for m in a.match:
+        rec = {}
+        for ctr in SQ_COUNTERS:
+            try:
+                rec[ctr], rec["dispatches"] = counter_avg(a.dir, m, ctr)
+            except ValueError:
+                rec[ctr] = None
+        if rec.get("SQ_WAVES") and rec.get("SQ_INSTS_VALU") is not None:
+            rec["valu_insts_per_wave"] = rec["SQ_INSTS_VALU"] / rec["SQ_WAVES"]
+        out[m] = rec
+    print(json.dumps(out, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -100,9 +122,14 @@ def main():
         s.add_argument("--" + k, required=True)
     s.add_argument("--sources", nargs="+", required=True)
     s.add_argument("--profile", required=True)
+    q = sub.add_parser("sq")
+    q.add_argument("--dir", required=True)
+    q.add_argument("--match", nargs="+", required=True)
     a = ap.parse_args()
     if a.cmd == "copy":
         copy_program()
+    elif a.cmd == "sq":
+        sq(a)
     else:
         summarize(a)
     return 0

@@ -86,7 +86,8 @@ class Calls:
                                         evals.ctypes.data_as(ctypes.c_void_p), d(self.evecs),
                                         c(P.laph_eig_stats()))),
             ("source", P.LAPH_WS_SOURCE, dict(nv=self.nv),
-             lambda ctx: L.make_diluted_source(ctx, d(self.evecs), self.nv, 0, 1, c(self.dil), 3, 4, d(self.out))),
+             lambda ctx: L.make_diluted_source(ctx, d(self.evecs), self.nv, 0, 1, c(self.dil), 3, 4, d(self.out),
+                                               P.LAPH_DTYPE_C128)),
             ("apply", P.LAPH_WS_DIRAC_APPLY, dict(n=4),
              lambda ctx: L.laph_dirac_apply(ctx, d(self.U), c(self.prm), P.LAPH_OP_OMEGA, d(self.psi), d(self.out),
                                             4)),

@@ -227,6 +227,13 @@ def cpu_report(log_fn):
     return rep
 
 
+def guess_weights():
+    """weights of the network's initial guess: those trained on LapH sources when present
+    (train_ptnet.py --sources laph), else the preconditioner's"""
+    p = os.path.join(ROOT, "paper_1104_3870_amd", "weights", "ptnet_guess.npz")
+    return p if os.path.exists(p) else os.path.join(ROOT, "paper_1104_3870_amd", "weights", "ptnet.npz")
+
+
 def hop_roofline(k):
     """HBM roofline of one kernel from the library's per-kernel event timing: algorithmic
     bytes per launch over the average launch duration, and the counter traffic when a
@@ -382,7 +389,7 @@ def main():
     if args.guess == "net":
         from paper_1104_3870_amd import train_ptnet as T
 
-        w, guess_meta = T.load(os.path.join(ROOT, "paper_1104_3870_amd", "weights", "ptnet.npz"))
+        w, guess_meta = T.load(guess_weights())
         guess_net = P.PTNet(L.ctx, guess_meta["channels"])
         guess_net.set_weights(w)
     tune = None
@@ -457,7 +464,7 @@ def main():
     if args.learned_mixed_steps != 0 and guess_net is None:
         from paper_1104_3870_amd import train_ptnet as T
 
-        w, meta = T.load(os.path.join(ROOT, "paper_1104_3870_amd", "weights", "ptnet.npz"))
+        w, meta = T.load(guess_weights())
         gnet = P.PTNet(L.ctx, meta["channels"])
         gnet.set_weights(w)
         svg = P.solver_params(net=gnet, tol=cfg.solve_tol, maxiter=6000, precision=args.precision,
@@ -476,7 +483,9 @@ def main():
         eg = time.time() - t3
         learned_mixed = {"value": round(nsrc * nlm / eg, 4), "unit": "sources/s",
                          "steps": nlm, "mean_iters": float(np.mean(itg)), "max_true_resid": float(max(rg)),
-                         "form": "headline form with the initial guess x0 = N(gamma_4 eta) of the trained PT-net"}
+                         "form": "headline form with the initial guess x0 = N(gamma_4 eta) of the trained PT-net",
+                         "weights": "%s (trained on %s sources)" % (os.path.relpath(guess_weights(), ROOT),
+                                                                     meta.get("sources", "gauss"))}
         log("learned + mixed: %.3f sources/s, %.1f iterations" % (learned_mixed["value"], learned_mixed["mean_iters"]))
         gnet.close()
 

@@ -2,14 +2,19 @@
 forward / backward / Adam kernels.
 
 Data: for each gauge seed a field of the workload's generator (near-unit SU(3) links,
-eps 0.4) on a small lattice, and `pairs` Gaussian sources b supported on odd sites with
-their solutions x = K^-1 b (dirac_solve with eta = gamma_4 b, since Omega = gamma_4 K).
-The network is translation invariant and local (four nearest-neighbour hops), so weights
-trained on the small lattice apply unchanged to 24^3 x 128.  In the even-odd solve the
-network sees odd-site inputs and only its odd-site output is used, hence sources on odd
-sites and loss on odd sites.
+eps 0.4) on a small lattice, and `pairs` sources b with their solutions x = K^-1 b
+(dirac_solve with eta = gamma_4 b, since Omega = gamma_4 K).  The network is translation
+invariant and local (four nearest-neighbour hops), so weights trained on the small
+lattice apply unchanged to 24^3 x 128.  Two source distributions, one per use:
+* gauss (FGMRES preconditioner): Gaussian sources on odd sites, the vectors the
+  preconditioner is applied to in the even-odd solve;
+* laph (initial guess of the solve): b = gamma_4 eta for LapH sources eta = V_s P^(b) rho
+  (Sec. II) of (TF,SF,LI8) dilution built on the field's own stout-smeared LapH vectors,
+  the input the solver gives the network for its guess.
+The loss is taken on odd sites (only the odd part of the output is used).
 
     python -m paper_1104_3870_amd.train_ptnet --out paper_1104_3870_amd/weights/ptnet.npz
+    python -m paper_1104_3870_amd.train_ptnet --sources laph --out paper_1104_3870_amd/weights/ptnet_guess.npz
 """
 from __future__ import annotations
 
@@ -33,23 +38,39 @@ def _odd_mask(ns, nt):
     return (((t + z + y + x) & 1) == 1)[..., None, None]
 
 
-def make_pairs(P, L, cfg, ns, nt, seed, pairs, block=32):
+LAPH_NV = 16  # LapH vectors per slice of the small training lattice
+
+
+def make_pairs(P, L, cfg, ns, nt, seed, pairs, block=32, kind="gauss"):
     """(U, b, x) on the device for one gauge seed."""
     import torch
 
     import synth
 
     U = synth.gauge_field(ns, nt, cfg.eps, seed)
-    b = synth.random_spinor(ns, nt, 1_000_003 * seed + 17, nrhs=pairs) * _odd_mask(ns, nt)
-    eta = np.ascontiguousarray(b[..., [2, 3, 0, 1], :])  # gamma_4 b (chiral basis)
     Ud = torch.from_numpy(U).cuda()
-    bd = torch.from_numpy(np.ascontiguousarray(b)).cuda()
+    P.laph_forget_gauge(L.ctx)
+    if kind == "laph":
+        nv = LAPH_NV
+        evals = np.zeros((nt, nv))
+        evecs = torch.empty((nt, nv, ns, ns, ns, 3), dtype=torch.complex128, device="cuda")
+        P.laph_eigvecs(L.ctx, Ud, cfg.stout_rho, cfg.stout_steps, nv, evals, evecs, krylov=60, lam_c=1.0, tol=1e-9,
+                       max_restarts=200)
+        dil = P.laph_parse_dilution("TF,SF,LI8", nt, nv)
+        nb = P.laph_dilution_count(dil, nt, nv)
+        b0 = int(np.random.default_rng(seed).integers(0, nb - pairs + 1))
+        etad = torch.empty((pairs, nt, ns, ns, ns, 4, 3), dtype=torch.complex128, device="cuda")
+        P.make_diluted_source(L.ctx, evecs, nv, seed & 0xFFFF, 1, dil, b0, pairs, etad)
+        bd = etad[..., [2, 3, 0, 1], :].contiguous()  # gamma_4 eta (chiral basis)
+    else:
+        b = synth.random_spinor(ns, nt, 1_000_003 * seed + 17, nrhs=pairs) * _odd_mask(ns, nt)
+        bd = torch.from_numpy(np.ascontiguousarray(b)).cuda()
+        etad = bd[..., [2, 3, 0, 1], :].contiguous()  # gamma_4 b
     xd = torch.empty_like(bd)
     prm = P.laph_dirac(cfg.m0, cfg.xi, cfg.csw, cfg.bc_t)
     sv = P.solver_params(tol=1e-9, maxiter=6000, precision="f32", solver=P.LAPH_SOLVER_CGNR,
                          block_rhs=min(block, 32))
-    P.laph_forget_gauge(L.ctx)
-    P.dirac_solve(L.ctx, Ud, prm, torch.from_numpy(eta).cuda(), xd, pairs, sv)
+    P.dirac_solve(L.ctx, Ud, prm, etad, xd, pairs, sv)
     return Ud, bd, xd
 
 
@@ -70,7 +91,7 @@ def eval_loss(P, L, net, data, mask_dev, bc_t):
 
 
 def train(workload="ns24_nt128", ns=8, nt=16, train_seeds=range(100, 200), test_seeds=range(200, 210), pairs=20,
-          epochs=60, lr=2e-3, channels=DEFAULT_CHANNELS, seed=0, log=print):
+          epochs=60, lr=2e-3, channels=DEFAULT_CHANNELS, seed=0, log=print, kind="gauss"):
     import torch
 
     import paper_1104_3870_amd as P
@@ -80,8 +101,8 @@ def train(workload="ns24_nt128", ns=8, nt=16, train_seeds=range(100, 200), test_
     torch.cuda.set_device(0)
     L = P.Lattice(ns, nt)
     t0 = time.time()
-    data = [make_pairs(P, L, cfg, ns, nt, s, pairs) for s in train_seeds]
-    test = [make_pairs(P, L, cfg, ns, nt, s, pairs) for s in test_seeds]
+    data = [make_pairs(P, L, cfg, ns, nt, s, pairs, kind=kind) for s in train_seeds]
+    test = [make_pairs(P, L, cfg, ns, nt, s, pairs, kind=kind) for s in test_seeds]
     t_data = time.time() - t0
     log("data: %d train pairs, %d test pairs in %.1f s" % (pairs * len(data), pairs * len(test), t_data))
     mask = torch.from_numpy(np.ascontiguousarray(_odd_mask(ns, nt))).cuda()
@@ -104,7 +125,7 @@ def train(workload="ns24_nt128", ns=8, nt=16, train_seeds=range(100, 200), test_
                                                                      time.time() - t1))
     t_train = time.time() - t1
     w = net.get_weights()
-    meta = {"channels": list(channels), "workload": workload, "lattice": [ns, nt], "m0": cfg.m0,
+    meta = {"channels": list(channels), "workload": workload, "lattice": [ns, nt], "m0": cfg.m0, "sources": kind,
             "train_seeds": [min(train_seeds), max(train_seeds)], "test_seeds": [min(test_seeds), max(test_seeds)],
             "pairs_per_seed": pairs, "epochs": epochs, "lr": lr, "data_s": round(t_data, 1),
             "train_s": round(t_train, 1), "history": hist}
@@ -125,7 +146,8 @@ def load(path):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default=os.path.join(ROOT, "paper_1104_3870_amd", "weights", "ptnet.npz"))
+    ap.add_argument("--out", default=None, help="default: weights/ptnet.npz (gauss), weights/ptnet_guess.npz (laph)")
+    ap.add_argument("--sources", default="gauss", choices=["gauss", "laph"])
     ap.add_argument("--workload", default="ns24_nt128")
     ap.add_argument("--ns", type=int, default=8)
     ap.add_argument("--nt", type=int, default=16)
@@ -136,8 +158,10 @@ def main():
     a = ap.parse_args()
     ch = tuple(int(c) for c in a.channels.split(","))
     w, meta = train(a.workload, a.ns, a.nt, pairs=a.pairs, epochs=a.epochs, lr=a.lr, channels=ch,
-                    log=lambda *x: print(*x, flush=True))
-    save(a.out, w, meta)
+                    log=lambda *x: print(*x, flush=True), kind=a.sources)
+    out = a.out or os.path.join(ROOT, "paper_1104_3870_amd", "weights",
+                                "ptnet_guess.npz" if a.sources == "laph" else "ptnet.npz")
+    save(out, w, meta)
     print(json.dumps({k: v for k, v in meta.items() if k != "history"}))
     return 0
 

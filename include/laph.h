@@ -206,6 +206,12 @@ enum { LAPH_PREC_F64 = 0, LAPH_PREC_F32 = 1, LAPH_PREC_F16 = 2, LAPH_PREC_BF16 =
  *                      both from out as stored in the storage precision
  *   LAPH_HOP_PLAIN_CG: r -= alpha_r (c g5 D in + a x) with r = out on entry (x required),
  *                      norm2[r] = |r_r|^2 after the update, from r as stored
+ *   LAPH_HOP_INV_DOT:  as LAPH_HOP_INV (x required), and the two inner products of a
+ *                      BiCGStab step (Sec. IV) from out as stored: out2 is an INPUT here,
+ *                      a field y read on parity p, and norm2 (3 n_fields values) receives
+ *                      per field Re <y_r, out_r>, Im <y_r, out_r>, |out_r|^2, with
+ *                      <y, out> = sum conj(y) out (out2 == x: y is x, the kernel's
+ *                      form that reuses the loaded x)
  * The input is read on the sites of parity 1-p, x and r on parity p; every output is
  * written on parity p and zero on parity 1-p.  Fields are converted to the storage
  * precision (FP16 records carry one FP32 scale per site and field), the kernel runs in
@@ -219,7 +225,7 @@ enum { LAPH_PREC_F64 = 0, LAPH_PREC_F32 = 1, LAPH_PREC_F16 = 2, LAPH_PREC_BF16 =
  * n_fields <= 256).
  * in, x, out, out2: device, n_fields canonical spinor fields each; alpha, norm2: HOST
  * arrays of n_fields (norm2 may be NULL).  n_fields: a power of two <= 32 (one launch). */
-enum { LAPH_HOP_PLAIN = 0, LAPH_HOP_INV = 1, LAPH_HOP_INV_DAG = 2, LAPH_HOP_PLAIN_CG = 3 };
+enum { LAPH_HOP_PLAIN = 0, LAPH_HOP_INV = 1, LAPH_HOP_INV_DAG = 2, LAPH_HOP_PLAIN_CG = 3, LAPH_HOP_INV_DOT = 4 };
 
 typedef struct {
     int precision;       /* LAPH_PREC_* of the fields the kernel reads and writes */

@@ -22,7 +22,7 @@ LAPH_DIL_NONE, LAPH_DIL_FULL, LAPH_DIL_BLOCK, LAPH_DIL_INTERLACE = range(4)
 LAPH_OP_K, LAPH_OP_OMEGA, LAPH_OP_KDAG = range(3)
 LAPH_PREC_F64, LAPH_PREC_F32, LAPH_PREC_F16, LAPH_PREC_BF16 = range(4)
 LAPH_SOLVER_BICGSTAB, LAPH_SOLVER_CGNR, LAPH_SOLVER_FGMRES = range(3)
-LAPH_HOP_PLAIN, LAPH_HOP_INV, LAPH_HOP_INV_DAG, LAPH_HOP_PLAIN_CG = range(4)
+LAPH_HOP_PLAIN, LAPH_HOP_INV, LAPH_HOP_INV_DAG, LAPH_HOP_PLAIN_CG, LAPH_HOP_INV_DOT = range(5)
 LAPH_DTYPE_C128, LAPH_DTYPE_C64 = range(2)
 LAPH_SINK_NOALLOC_BYTES = 64 << 20  # fixed scratch of sink_project_noalloc (include/laph.h)
 PRECISIONS = {"f64": LAPH_PREC_F64, "f32": LAPH_PREC_F32, "f16": LAPH_PREC_F16, "bf16": LAPH_PREC_BF16}
@@ -363,7 +363,8 @@ def laph_dirac_apply(ctx, U, dirac, op, x, out, n_fields=1):
 
 def laph_hop_apply(ctx, U, dirac, precision, mode, parity, inp, out, x=None, out2=None, alpha=None, gamma5=0,
                    temporal_gauge=0, walk=0, sites_per_block=0, a=0.0, c=1.0):
-    """One even-odd hopping launch (see laph.h); returns the host norm2 array (list)."""
+    """One even-odd hopping launch (see laph.h); returns the host norm2 array (n values; for
+    LAPH_HOP_INV_DOT 3 n: Re <y, out>, Im <y, out>, |out|^2 per field, y passed as out2)."""
     import numpy as np
 
     n = inp.shape[0]
@@ -374,7 +375,7 @@ def laph_hop_apply(ctx, U, dirac, precision, mode, parity, inp, out, x=None, out
         al = np.ascontiguousarray(np.asarray(alpha, dtype=np.float64))
         if al.size != n:
             raise ValueError("alpha needs one value per field")
-    nrm = np.zeros(n)
+    nrm = np.zeros(3 * n if mode == LAPH_HOP_INV_DOT else n)
     if n <= 32:
         ensure_workspace(ctx, LAPH_WS_HOP_APPLY, n=n, hop=h)
     _check(lib().laph_hop_apply(ctx, _dptr(U), ctypes.byref(dirac), ctypes.byref(h), _dptr(inp),

@@ -282,9 +282,9 @@ void timing_end(laph_ctx *c, hipEvent_t a, hipEvent_t b, double bytes, const cha
 const char *timing_label(const char *kernel, const char *prec, int mode, int R)
 {
     static std::map<std::string, std::string> names;
-    static const char *modes[] = {"plain", "inv", "inv_of_sum", "clov_add", "inv_dag", "plain_cg"};
+    static const char *modes[] = {"plain", "inv", "inv_of_sum", "clov_add", "inv_dag", "plain_cg", "inv_dot"};
     char buf[96];
-    snprintf(buf, sizeof(buf), "%s<%s,%s,R%d>", kernel, prec, (mode >= 0 && mode < 6) ? modes[mode] : "?", R);
+    snprintf(buf, sizeof(buf), "%s<%s,%s,R%d>", kernel, prec, (mode >= 0 && mode < 7) ? modes[mode] : "?", R);
     auto &v = names[buf];
     if (v.empty()) v = buf;
     return v.c_str();

@@ -4,8 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
-// most directions whose steps the CG solution increment may still owe (the current one
-// included)
+// most directions whose steps the CG or BiCGStab solution increment may still owe (the
+// current one included)
 constexpr int kMaxDirs = 8;
 
 struct Scal {
@@ -18,6 +18,8 @@ struct Scal {
     double b2;        // |bhat|^2
     double alpha_prev[kMaxDirs - 1];  // alpha of the previous CG iterations, latest first (steps
                                       // the direction update still owes x)
+    double2 bs_alpha_prev[kMaxDirs - 1];  // the same for BiCGStab: alpha and omega of the
+    double2 bs_omega_prev[kMaxDirs - 1];  // previous iterations, latest first
     int active;
     int iters;
     int breakdown;

@@ -111,8 +111,11 @@ enum {
     M_CLOV_ADD = 3,   // out = A x + c D psi
     M_INV_AFTER_DAG = 4, // as M_INV_AFTER, and also out2 = A^-1 gamma_5 out and per-block
                          // partial sums of |out|^2 (multi-RHS low-precision kernel only)
-    M_PLAIN_CG = 5       // as M_PLAIN with out consumed by a CG update instead of stored
+    M_PLAIN_CG = 5,      // as M_PLAIN with out consumed by a CG update instead of stored
                          // (multi-RHS low-precision kernel only)
+    M_INV_AFTER_DOT = 6  // as M_INV_AFTER, and also per-block partial sums of <y, out> and
+                         // |out|^2 for a second own-site field y (BiCGStab; multi-RHS
+                         // low-precision kernel only)
 };
 
 struct DslashArgs {

@@ -31,6 +31,11 @@ struct MrArgs {
     const Scal *sc;
     void *cg_r;
     float *cg_r_nrm;
+    // M_INV_AFTER_DOT: the field y (same parity and layout as out); partial[(q R + r) *
+    // nblocks + block] holds the block's sum of Re <y_r, out_r> (q = 0), Im (q = 1) and
+    // |out_r|^2 (q = 2), <y, out> = sum conj(y) out, from out as stored
+    const void *dot_y;
+    const float *dot_y_nrm;
     // order in which the LDS-staged kernel visits output sites: wby = 0 walks the
     // checkerboard index; otherwise spatial tiles of ns x wby x wbz sites are walked slice
     // by slice through all time slices, one tile after the other
@@ -59,7 +64,8 @@ void launch_clover_mr(laph_ctx *c, const void *cl, const void *x, const float *x
 // FP64 even-odd links / packed clover inverse -> the low-precision layouts above
 void build_lp_operator(laph_ctx *c, const double2 *g64, const double *clinv64, float4 *links12, float *clinv_aos);
 
-double dslash_mr_bytes(long Vh, int R, int sbytes, bool has_norm, int mode, bool has_x);
+// algorithmic HBM bytes of one launch (y_is_x: the dot epilogue's y is the own-site x)
+double dslash_mr_bytes(long Vh, int R, int sbytes, bool has_norm, int mode, bool has_x, bool y_is_x = false);
 
 // sites per block of the LDS-staged hopping kernel for (precision, R); S R <= 256 lanes
 int lds_tile_sites(laph_ctx *c, int prec, int R);

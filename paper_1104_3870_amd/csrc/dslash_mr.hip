@@ -342,16 +342,17 @@ __device__ __forceinline__ void dir_lds(__amdgpu_buffer_rsrc_t rin, __amdgpu_buf
 }
 
 // neighbour records kept in flight by the software-pipelined direction loop (0: the
-// compiler's own schedule), measured on gfx950 at 24^3 x 128, R = 32, FP16: every hop
-// runs the pipeline except those with both the clover-inverse epilogue and an own-site
-// addend, which need more registers than 3 waves per SIMD allow
+// compiler's own schedule), measured on gfx950 at 24^3 x 128, R = 32, FP16.  Every mode
+// runs the pipeline: with the clover-inverse epilogue and an own-site addend it takes
+// 109-116 VGPRs (4 waves per SIMD, no spills) and cut those hops from 1.75-2.0 ms to
+// 1.6-1.7 ms against the compiler's schedule, which waits on every neighbour load
 #ifndef LAPH_PIPE_D
 #define LAPH_PIPE_D 2
 #endif
 template <int MODE, bool HX>
 constexpr int lds_pipe_depth()
 {
-    return ((MODE == M_INV_AFTER || MODE == M_INV_AFTER_DAG) && HX) ? 0 : LAPH_PIPE_D;
+    return LAPH_PIPE_D;
 }
 
 __device__ __forceinline__ void clover_one(const float4 *p, const Cx<float> (&in)[4][3], Cx<float> (&out)[4][3])
@@ -456,7 +457,7 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
     const int ns = P.ns, nt = P.nt, par = P.par, opar = par ^ 1;
     const long pos0 = (long)xcd_block(blockIdx.x, gridDim.x) * S;  // walk position of lane-site 0
     const float4 *lk = (const float4 *)P.links;
-    constexpr bool kInv = MODE == M_INV_AFTER || MODE == M_INV_AFTER_DAG;
+    constexpr bool kInv = MODE == M_INV_AFTER || MODE == M_INV_AFTER_DAG || MODE == M_INV_AFTER_DOT;
     const float fout = kInv ? 1.0f : (float)P.c;  // folded into the links
     for (int k = threadIdx.x; k < S * 8; k += blockDim.x) {
         const int sl = k >> 3, d = k & 7, mu = d & 3;
@@ -511,13 +512,15 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
     __syncthreads();
     const int sl = threadIdx.x / R, r = threadIdx.x - sl * R;
     const bool valid = sl < S && pos0 + sl < Vh;
-    constexpr bool kRed = MODE == M_INV_AFTER_DAG || MODE == M_PLAIN_CG;  // block reduction
+    // block reduction of NQ values per lane
+    constexpr bool kRed = MODE == M_INV_AFTER_DAG || MODE == M_PLAIN_CG || MODE == M_INV_AFTER_DOT;
+    constexpr int NQ = MODE == M_INV_AFTER_DOT ? 3 : 1;
     if constexpr (!kRed) {
         if (!valid) return;
     }
-    // this lane's |out|^2 (DAG) or |r|^2 (CG): 24 terms of one site and right-hand side in
-    // FP32, the sums over sites in FP64
-    float nq = 0.0f;
+    // this lane's |out|^2 (DAG) or |r|^2 (CG), or Re, Im <y, out> and |out|^2 (DOT): 24
+    // terms of one site and right-hand side in FP32, the sums over sites in FP64
+    float nq = 0.0f, dre = 0.0f, dim = 0.0f;
     if (valid) {
     // 32-bit site arithmetic (the host checks Vh * R * 12 < 2^31): neighbour checkerboard
     // indices from the site's own, lex = 2 cb + (x & 1) since Ns is even
@@ -620,9 +623,13 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
     }
     // a run-time test even when HX holds: an unconditional load of x is hoisted to the
     // start of the kernel, where its registers push the pipelined loop into spills
+    // DOT with y = x (BiCGStab's t = M s, <s, t>): x as loaded serves as y
+    Cx<float> xkeep[4][3];
+    float xkeep_s = 0.0f;
     if (HX && P.x) {
         Cx<float> xv[4][3];
-        float sx = (float)P.a * ld_raw<SP>((const typename SP::E *)P.x, P.x_nrm, R, i, r, xv);
+        const float xn = ld_raw<SP>((const typename SP::E *)P.x, P.x_nrm, R, i, r, xv);
+        const float sx = (float)P.a * xn;
 #pragma unroll
         for (int a = 0; a < 4; a++)
 #pragma unroll
@@ -630,6 +637,13 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
                 res[a][c].re = fmaf(sx, xv[a][c].re, res[a][c].re);
                 res[a][c].im = fmaf(sx, xv[a][c].im, res[a][c].im);
             }
+        if constexpr (MODE == M_INV_AFTER_DOT) {
+#pragma unroll
+            for (int a = 0; a < 4; a++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) xkeep[a][c] = xv[a][c];
+            xkeep_s = xn;
+        }
     }
     Cx<float> v[12];
 #pragma unroll
@@ -662,20 +676,47 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
 #pragma unroll
             for (int k = 0; k < 12; k++) nq = fmaf(a[k].re, a[k].re, fmaf(a[k].im, a[k].im, nq));
         }
+    } else if constexpr (MODE == M_INV_AFTER_DOT) {
+        // out as stored; <y, out> and |out|^2 from the rounded values
+        st_spinor12_round<SP, nt_out<MODE>()>((typename SP::E *)P.out, P.out_nrm, Vh, R, i, r, v);
+        Cx<float> y[12];
+        if (P.dot_y == P.x) {
+            // the stored value of each component is its raw value times the site's scale
+#pragma unroll
+            for (int k = 0; k < 12; k++)
+                y[k] = {xkeep[k / 3][k % 3].re * xkeep_s, xkeep[k / 3][k % 3].im * xkeep_s};
+        } else {
+            ld_spinor12<SP, float>((const typename SP::E *)P.dot_y, P.dot_y_nrm, Vh, R, i, r, y);
+        }
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            nq = fmaf(v[k].re, v[k].re, fmaf(v[k].im, v[k].im, nq));
+            dre = fmaf(y[k].re, v[k].re, fmaf(y[k].im, v[k].im, dre));
+            dim = fmaf(y[k].re, v[k].im, fmaf(-y[k].im, v[k].re, dim));
+        }
     } else {
         st_spinor12<SP, float, nt_out<MODE>()>((typename SP::E *)P.out, P.out_nrm, Vh, R, i, r, v);
     }
     }  // valid
     if constexpr (kRed) {
         // deterministic block sum per right-hand side over the lanes sl = 0 .. S-1 of each
-        // r; partials stored right-hand-side major
-        __shared__ double red[256];
-        red[threadIdx.x] = (double)nq;
+        // r; partials stored right-hand-side major, value-major across the NQ values
+        __shared__ double red[NQ][256];
+        if constexpr (NQ == 3) {
+            red[0][threadIdx.x] = (double)dre;
+            red[1][threadIdx.x] = (double)dim;
+            red[2][threadIdx.x] = (double)nq;
+        } else {
+            red[0][threadIdx.x] = (double)nq;
+        }
         __syncthreads();
         if ((int)threadIdx.x < R) {
-            double s2 = 0.0;
-            for (int q = 0; q < S; q++) s2 += red[q * R + threadIdx.x];
-            P.partial[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s2;
+#pragma unroll
+            for (int e = 0; e < NQ; e++) {
+                double s2 = 0.0;
+                for (int q = 0; q < S; q++) s2 += red[e][q * R + threadIdx.x];
+                P.partial[((size_t)e * R + threadIdx.x) * gridDim.x + blockIdx.x] = s2;
+            }
         }
     }
 }
@@ -731,12 +772,13 @@ __global__ void k_links12(const double2 *__restrict__ g64, float4 *__restrict__ 
 
 }  // namespace
 
-double dslash_mr_bytes(long Vh, int R, int sbytes, bool has_norm, int mode, bool has_x)
+double dslash_mr_bytes(long Vh, int R, int sbytes, bool has_norm, int mode, bool has_x, bool y_is_x)
 {
     double site = 8.0 * 48;  // reconstruct-12 FP32 links
-    if (mode == M_INV_AFTER || mode == M_INV_AFTER_DAG) site += 72.0 * 4;
-    // in, out[, x][, out2]; the CG form also reads r (and writes it instead of out)
-    int streams = 2 + (has_x ? 1 : 0) + (mode == M_INV_AFTER_DAG ? 1 : 0);
+    if (mode == M_INV_AFTER || mode == M_INV_AFTER_DAG || mode == M_INV_AFTER_DOT) site += 72.0 * 4;
+    // in, out[, x][, out2 or a y other than x]; the CG form also reads r (and writes it
+    // instead of out)
+    int streams = 2 + (has_x ? 1 : 0) + (mode == M_INV_AFTER_DAG || (mode == M_INV_AFTER_DOT && !y_is_x) ? 1 : 0);
     if (mode == M_PLAIN_CG) streams += 1;
     double per_rhs = 12.0 * sbytes * streams + (has_norm ? 4.0 * streams : 0.0);
     return (double)Vh * (site + R * per_rhs);
@@ -853,9 +895,12 @@ void launch_dslash_mr(laph_ctx *c, int mode, const MrArgs &a, hipStream_t st)
     hipEvent_t e0, e1;
     timing_begin(c, &e0, &e1);
     const bool hx = a.x != nullptr;
-    LAPH_CHECK(hx || (mode != M_INV_AFTER_DAG && mode != M_PLAIN_CG), LAPH_EINVAL,
+    LAPH_CHECK(hx || (mode != M_INV_AFTER_DAG && mode != M_PLAIN_CG && mode != M_INV_AFTER_DOT), LAPH_EINVAL,
                "fused hopping epilogues need the own-site operand");
-    if (mode == M_INV_AFTER_DAG)
+    LAPH_CHECK(mode != M_INV_AFTER_DOT || (a.dot_y && a.partial), LAPH_EINVAL, "the dot epilogue needs y");
+    if (mode == M_INV_AFTER_DOT)
+        hipLaunchKernelGGL((k_dslash_lds<SP, M_INV_AFTER_DOT, true>), grid, block, lds_bytes(S), st, b);
+    else if (mode == M_INV_AFTER_DAG)
         hipLaunchKernelGGL((k_dslash_lds<SP, M_INV_AFTER_DAG, true>), grid, block, lds_bytes(S), st, b);
     else if (mode == M_PLAIN_CG)
         hipLaunchKernelGGL((k_dslash_lds<SP, M_PLAIN_CG, true>), grid, block, lds_bytes(S), st, b);
@@ -869,7 +914,9 @@ void launch_dslash_mr(laph_ctx *c, int mode, const MrArgs &a, hipStream_t st)
         hipLaunchKernelGGL((k_dslash_lds<SP, M_PLAIN, false>), grid, block, lds_bytes(S), st, b);
     LAPH_HIP(hipGetLastError());
     if (e0)
-        timing_end(c, e0, e1, dslash_mr_bytes(a.Vh, a.R, SP::bytes, SP::kNorm, mode, a.x != nullptr),
+        timing_end(c, e0, e1,
+                   dslash_mr_bytes(a.Vh, a.R, SP::bytes, SP::kNorm, mode, a.x != nullptr,
+                                   mode == M_INV_AFTER_DOT && a.dot_y == a.x),
                    timing_label("dslash_lds", prec_name<SP>(), mode, a.R));
 }
 

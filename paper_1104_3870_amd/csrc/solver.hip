@@ -416,7 +416,8 @@ __global__ __launch_bounds__(kBS) void k_fold_x_step(Vec xhi, Vec xlo, Dirs dirs
 }
 
 // r = b - m (FP64; m.d null: m = 0), partial |r|^2; restricted to masked right-hand sides
-// unless all_rhs; with rlo.d set also r converted to the storage precision SP
+// unless all_rhs; with rlo.d set also r converted to the storage precision SP (r.d null:
+// that conversion alone is stored)
 template <class SP>
 __global__ __launch_bounds__(kBS) void k_resid64(Vec b, Vec m, Vec r, Vec rlo, long Vh, int R, double *partial,
                                                  const Scal *sc, int all_rhs)
@@ -441,7 +442,7 @@ __global__ __launch_bounds__(kBS) void k_resid64(Vec b, Vec m, Vec r, Vec rlo, l
             a[k] = a[k] - c[k];
             acc[0] += a[k].re * a[k].re + a[k].im * a[k].im;
         }
-        st_site<S64>(r, Vh, R, i, rr, a);
+        if (r.d) st_site<S64>(r, Vh, R, i, rr, a);
         if (rlo.d) st_site<SP>(rlo, Vh, R, i, rr, a);
     }
     block_partial<1>(acc, R, partial);
@@ -614,6 +615,265 @@ __global__ __launch_bounds__(kBS) void k_prereduce(const double *partial, int nb
         __syncthreads();
     }
     if (threadIdx.x == 0) out[(long)r * kChunks + ch] = lds[0];
+}
+
+// ------------------------------------------------- fused multi-RHS BiCGStab (Sec. IV)
+// The low-precision BiCGStab iteration takes its inner products <r0, v>, <t, s>, |t|^2 from
+// the epilogues of the hops that form v = M p and t = M s (M_INV_AFTER_DOT), and keeps its
+// solution steps alpha p + omega s owed in a ring of K (p, s) buffer pairs, taken K at a
+// time, as the CG loop does with its directions.
+
+// (p, s) pairs whose steps the solution increment still owes, latest first: pair 0 takes
+// the current alpha and omega, pair j >= 1 those of j iterations back
+struct BsDirs {
+    Vec p[kMaxDirs], s[kMaxDirs];
+    int n = 0;
+};
+
+// o += sum_{j < n} alpha_j p_j + omega_j s_j
+template <class SP>
+__device__ __forceinline__ void add_bs_steps(const BsDirs &d, int n, const Scal &q, long Vh, int R, long i, int r,
+                                             Cx<double> (&o)[12])
+{
+#pragma unroll
+    for (int j = 0; j < kMaxDirs; j++) {
+        if (j >= n) break;
+        const Cx<double> al = cx(j ? q.bs_alpha_prev[j - 1] : q.alpha);
+        const Cx<double> om = cx(j ? q.bs_omega_prev[j - 1] : q.omega);
+        Cx<double> b[12];
+        ld_site<SP>(d.p[j], Vh, R, i, r, b);
+#pragma unroll
+        for (int k = 0; k < 12; k++) o[k] = o[k] + al * b[k];
+        ld_site<SP>(d.s[j], Vh, R, i, r, b);
+#pragma unroll
+        for (int k = 0; k < 12; k++) o[k] = o[k] + om * b[k];
+    }
+}
+
+// the three value rows of right-hand side r in partials laid out [(e R + r) * nblk + b]
+__device__ __forceinline__ void sum_rows3(const double *partial, int nblk, int R, int r, double (&out)[3])
+{
+    __shared__ double lds[3][kBS];
+    double v[3] = {0, 0, 0};
+    for (int b = threadIdx.x; b < nblk; b += kBS)
+#pragma unroll
+        for (int e = 0; e < 3; e++) v[e] += partial[((long)e * R + r) * nblk + b];
+#pragma unroll
+    for (int e = 0; e < 3; e++) lds[e][threadIdx.x] = v[e];
+    __syncthreads();
+    for (int h = kBS / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+#pragma unroll
+            for (int e = 0; e < 3; e++) lds[e][threadIdx.x] += lds[e][threadIdx.x + h];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int e = 0; e < 3; e++) out[e] = lds[e][0];
+}
+
+// alpha = rho / <r0, v> from the epilogue partials of v = M p; the previous alpha and
+// omega move into the step history first
+__global__ void k_fin_bs_alpha(const double *partial, int nblk, int R, Scal *sc)
+{
+    const int r = blockIdx.x;
+    double s[3];
+    sum_rows3(partial, nblk, R, r, s);
+    if (threadIdx.x) return;
+    Scal &q = sc[r];
+    if (!q.active) {
+        q.alpha = make_double2(0, 0);
+        return;
+    }
+    for (int j = kMaxDirs - 2; j > 0; j--) {
+        q.bs_alpha_prev[j] = q.bs_alpha_prev[j - 1];
+        q.bs_omega_prev[j] = q.bs_omega_prev[j - 1];
+    }
+    q.bs_alpha_prev[0] = q.alpha;
+    q.bs_omega_prev[0] = q.omega;
+    const double2 den = make_double2(s[0], s[1]);
+    if (cnorm2(den) == 0.0 || !std::isfinite(den.x) || !std::isfinite(den.y)) {
+        q.alpha = make_double2(0, 0);
+        q.breakdown = 1;
+        q.active = 0;
+        return;
+    }
+    q.alpha = cdiv(q.rho, den);
+}
+
+// omega = <t, s> / |t|^2 from the epilogue partials of t = M s, which hold <s, t> = conj <t, s>
+__global__ void k_fin_bs_omega(const double *partial, int nblk, int R, Scal *sc)
+{
+    const int r = blockIdx.x;
+    double s[3];
+    sum_rows3(partial, nblk, R, r, s);
+    if (threadIdx.x) return;
+    Scal &q = sc[r];
+    if (!q.active) {
+        q.omega = make_double2(0, 0);
+        return;
+    }
+    if (!(s[2] > 0.0) || !std::isfinite(s[2])) {
+        q.omega = make_double2(0, 0);
+        q.breakdown = 1;
+        q.active = 0;
+        return;
+    }
+    q.omega = make_double2(s[0] / s[2], -s[1] / s[2]);
+}
+
+// r = s - omega t; per-block partials of <r0, r> and |r|^2 of the stored r, rows
+// value-major as the hopping epilogues write them (a block: kBS / R sites x R RHS)
+template <class SP>
+__global__ __launch_bounds__(kBS) void k_bs_r(Vec s, Vec t, Vec r, Vec r0, long Vh, int R, double *partial,
+                                              const Scal *sc)
+{
+    const long tid = blockIdx.x * (long)kBS + threadIdx.x;
+    const long i = tid / R;
+    const int rr = (int)(threadIdx.x & (R - 1));
+    double acc[3] = {0, 0, 0};
+    if (i < Vh && sc[rr].active) {
+        const Cx<double> om = cx(sc[rr].omega);
+        Cx<double> a[12], b[12];
+        ld_site<SP>(s, Vh, R, i, rr, a);
+        ld_site<SP>(t, Vh, R, i, rr, b);
+#pragma unroll
+        for (int k = 0; k < 12; k++) a[k] = a[k] - om * b[k];
+        st_site<SP>(r, Vh, R, i, rr, a);
+        ld_site<SP>(r, Vh, R, i, rr, a);  // the stored value
+        ld_site<SP>(r0, Vh, R, i, rr, b);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            acc[0] += b[k].re * a[k].re + b[k].im * a[k].im;
+            acc[1] += b[k].re * a[k].im - b[k].im * a[k].re;
+            acc[2] += a[k].re * a[k].re + a[k].im * a[k].im;
+        }
+    }
+    __shared__ double red[3][kBS];
+#pragma unroll
+    for (int e = 0; e < 3; e++) red[e][threadIdx.x] = acc[e];
+    __syncthreads();
+    if ((int)threadIdx.x < R) {
+#pragma unroll
+        for (int e = 0; e < 3; e++) {
+            double v = 0.0;
+            for (int q = threadIdx.x; q < kBS; q += R) v += red[e][q];
+            partial[((long)e * R + threadIdx.x) * gridDim.x + blockIdx.x] = v;
+        }
+    }
+}
+
+// rho_new = <r0, r>, beta = (rho_new / rho)(alpha / omega), |r|^2 from the prereduced
+// partials of k_bs_r
+__global__ void k_fin_bs_beta(const double *partial, int nblk, int R, Scal *sc)
+{
+    const int r = blockIdx.x;
+    double s[3];
+    sum_rows3(partial, nblk, R, r, s);
+    if (threadIdx.x) return;
+    Scal &q = sc[r];
+    if (!q.active) {
+        q.beta = make_double2(0, 0);
+        return;
+    }
+    const double2 rn = make_double2(s[0], s[1]);
+    q.iters += 1;
+    q.r2 = s[2];
+    if (!std::isfinite(s[0]) || !std::isfinite(s[1]) || !std::isfinite(s[2]) || cnorm2(q.rho) == 0.0 ||
+        cnorm2(q.omega) == 0.0) {
+        q.breakdown = 1;
+        q.active = 0;
+        q.beta = make_double2(0, 0);
+        return;
+    }
+    q.beta = cmul(cdiv(rn, q.rho), cdiv(q.alpha, q.omega));
+    q.rho = rn;
+}
+
+// pout = r + beta (p - omega v) with p = d.p[0]; pout may be d.p[0] or, when the owed steps
+// are taken first (nsteps > 0: x += the steps of pairs 0 .. nsteps - 1), the oldest pair's p
+template <class SP, class XP>
+__global__ __launch_bounds__(kBS) void k_bs_p(Vec pout, BsDirs d, Vec r, Vec v, Vec x, long Vh, int R,
+                                              const Scal *sc, int nsteps)
+{
+    long n = Vh * R;
+    long tid = blockIdx.x * (long)kBS + threadIdx.x;
+    if (tid >= n) return;
+    long i = tid / R;
+    int rr = (int)(tid - i * R);
+    if (!sc[rr].active) return;
+    const Cx<double> be = cx(sc[rr].beta), om = cx(sc[rr].omega);
+    Cx<double> a[12], b[12];
+    if (nsteps) {
+        ld_site<XP>(x, Vh, R, i, rr, b);
+        add_bs_steps<SP>(d, nsteps, sc[rr], Vh, R, i, rr, b);
+        st_site<XP>(x, Vh, R, i, rr, b);
+    }
+    ld_site<SP>(d.p[0], Vh, R, i, rr, a);
+    ld_site<SP>(v, Vh, R, i, rr, b);
+#pragma unroll
+    for (int k = 0; k < 12; k++) a[k] = a[k] - om * b[k];
+    ld_site<SP>(r, Vh, R, i, rr, b);
+#pragma unroll
+    for (int k = 0; k < 12; k++) a[k] = b[k] + be * a[k];
+    st_site<SP>(pout, Vh, R, i, rr, a);
+}
+
+// xhi += xlo + the owed steps; xlo = 0 (right-hand sides with mask set)
+template <class XP, class SP>
+__global__ __launch_bounds__(kBS) void k_fold_x_bs(Vec xhi, Vec xlo, BsDirs d, long Vh, int R, const Scal *sc)
+{
+    long n = Vh * R;
+    long tid = blockIdx.x * (long)kBS + threadIdx.x;
+    if (tid >= n) return;
+    long i = tid / R;
+    int rr = (int)(tid - i * R);
+    if (!sc[rr].active) return;
+    Cx<double> a[12], b[12], z[12];
+    ld_site<S64>(xhi, Vh, R, i, rr, a);
+    ld_site<XP>(xlo, Vh, R, i, rr, b);
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        a[k] = a[k] + b[k];
+        z[k] = {0, 0};
+    }
+    add_bs_steps<SP>(d, d.n, sc[rr], Vh, R, i, rr, a);
+    st_site<S64>(xhi, Vh, R, i, rr, a);
+    st_site<XP>(xlo, Vh, R, i, rr, z);
+}
+
+// partial <a, b>, |b|^2
+template <class SP>
+__global__ __launch_bounds__(kBS) void k_dot_nb(Vec a, Vec b, long Vh, int R, double *partial, const Scal *sc)
+{
+    double acc[3] = {0, 0, 0};
+    long n = Vh * R, stride = (long)gridDim.x * kBS;
+    int rr = (int)((blockIdx.x * (long)kBS + threadIdx.x) % R);
+    const bool act = sc[rr].active;
+    for (long tid = blockIdx.x * (long)kBS + threadIdx.x; tid < n; tid += stride) {
+        if (!act) break;
+        long i = tid / R;
+        Cx<double> u[12], w[12];
+        ld_site<SP>(a, Vh, R, i, rr, u);
+        ld_site<SP>(b, Vh, R, i, rr, w);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            acc[0] += u[k].re * w[k].re + u[k].im * w[k].im;
+            acc[1] += u[k].re * w[k].im - u[k].im * w[k].re;
+            acc[2] += w[k].re * w[k].re + w[k].im * w[k].im;
+        }
+    }
+    block_partial<3>(acc, R, partial);
+}
+
+// the host's divergence verdicts, in stream order: right-hand sides in mask stop with a
+// breakdown (handed to the fallback)
+__global__ void k_bs_drop(Scal *sc, int R, unsigned mask)
+{
+    const int r = threadIdx.x;
+    if (r < R && ((mask >> r) & 1u) && sc[r].active) {
+        sc[r].active = 0;
+        sc[r].breakdown = 1;
+    }
 }
 
 // rmajor: partials of the fused hopping epilogue (one value per block and RHS)
@@ -1009,6 +1269,21 @@ struct Op {
         dslash(M_INV_AFTER, 0, in, te, nullptr, 0.0, 1.0, 0);
         dslash_ext(M_INV_AFTER_DAG, 1, te, out, &in, 1.0, -1.0, 0, &to, partial);
     }
+    // mhat with per-block partials of <y, out> and |out|^2 from the second hop's epilogue
+    // (low precision, LDS-staged kernel; rows value-major, see MrArgs)
+    void mhat_dot(Vec in, Vec out, Vec y, double *partial) const
+    {
+        dslash(M_INV_AFTER, 0, in, te, nullptr, 0.0, 1.0, 0);
+        if constexpr (kLow) {
+            MrArgs m = mr_args(1, te, out, &in, 1.0, -1.0, 0);
+            m.dot_y = y.d;
+            m.dot_y_nrm = y.n;
+            m.partial = partial;
+            launch_dslash_mr<SP>(c, M_INV_AFTER_DOT, m, st);
+        } else {
+            laph_fail(LAPH_EINVAL, "fused BiCGStab products are low precision only");
+        }
+    }
 };
 
 using Op64 = Op<S64, G64, C64>;
@@ -1077,19 +1352,48 @@ static Scal *pinned_scal(laph_ctx *c, int R)
 constexpr int kDefaultDirs = 8;
 
 // A reliable update serves the whole block, so it waits until this percentage of the
-// active right-hand sides have their residual below reliable_delta of its last FP64
-// value, unless one fell 100 times further, converged, or reliable_every iterations
-// passed.  On 32 LapH sources of the 24^3 x 128 workload a quarter cut the updates per
-// solve by a tenth for 0.3% more iterations (+1.2% sources/s against any one).
-constexpr int kUpdateQuorum = 25;
+// active right-hand sides want one: their iterated residual fell below reliable_delta of
+// its last FP64 value, or below the target (a candidate for convergence, which only the
+// FP64 residual can confirm and which meanwhile keeps iterating with the block).  It comes
+// at once when one non-candidate fell 100 times further (the storage precision could no
+// longer follow it) or every active one is a candidate, and after reliable_every
+// iterations.  On 32 LapH sources of the 24^3 x 128 workload (FP16 inner vectors)
+// counting candidates into the quorum instead of updating for each cut the updates of
+// BiCGStab, whose right-hand sides reach the target over a wider spread of iterations,
+// from 22-30 to 15-16 per solve (reliable_delta 0.03); at reliable_delta 0.1 a half
+// instead of a quarter cut them from 19-21 to 15 at the same iteration count.  CG needs
+// 9 to 11 either way.
+constexpr int kUpdateQuorum = 50;
+
+// the rule above on the scalars of one iteration (active right-hand sides only)
+struct UpdateVote {
+    int nact = 0, nwant = 0, nconv = 0;
+    bool deep = false;
+    double worst = 0;  // largest |res| / target
+    void add(const Scal &q, double r2_last, double delta2)
+    {
+        nact++;
+        worst = std::max(worst, q.tol2 > 0 ? std::sqrt(q.r2 / q.tol2) : 0.0);
+        if (q.r2 <= q.tol2) {
+            nconv++;
+            nwant++;
+        } else if (q.r2 < delta2 * r2_last) {
+            nwant++;
+            deep |= q.r2 < 0.01 * delta2 * r2_last;
+        }
+    }
+    bool quorum() const { return nwant > 0 && nwant * 100 >= kUpdateQuorum * nact; }
+    bool all_conv() const { return nact > 0 && nconv == nact; }
+    bool want() const { return deep || all_conv() || quorum(); }
+};
 
 void write_scal(laph_ctx *c, Scal *d, const std::vector<Scal> &h)
 {
     LAPH_HIP(hipMemcpyAsync(d, h.data(), sizeof(Scal) * h.size(), hipMemcpyHostToDevice, c->stream));
 }
 
-// rhi = bhat - Mhat xhi for masked RHS (FP64), then r2hi / masks
-// (rlo: also the residual in storage precision SP, for the right-hand sides it is formed for)
+// rhi = bhat - Mhat xhi for masked RHS (FP64), then r2hi / masks (rlo: the residual in
+// storage precision SP instead of rhi, for the right-hand sides it is formed for)
 template <class SP = S64>
 void true_eo_residual(Work &w, const Op64 &hi, Vec bhat, Vec xhi, Vec tmp, Vec rhi, int all_rhs, Vec rlo = Vec{})
 {
@@ -1101,8 +1405,189 @@ void true_eo_residual(Work &w, const Op64 &hi, Vec bhat, Vec xhi, Vec tmp, Vec r
         hi.mhat(xhi, tmp);
     w.x_zero = false;  // the caller goes on to change x_hi
     long n = w.Vh * w.R;
-    launch_red(w.c, k_resid64<SP>, n, bhat, m, rhi, rlo, w.Vh, w.R, w.part, (const Scal *)w.sc, all_rhs);
+    // with a storage-precision copy requested the callers use that copy alone
+    launch_red(w.c, k_resid64<SP>, n, bhat, m, rlo.d ? Vec{} : rhi, rlo, w.Vh, w.R, w.part, (const Scal *)w.sc,
+               all_rhs);
     launch_fin(w.c, k_fin_r2hi, w.R, (const double *)w.part, (int)red_blocks(n), w.R, w.sc, 0);
+}
+
+// Low-precision BiCGStab (Sec. IV) on the even-odd system, fused for the multi-RHS
+// kernels: per iteration two hops form v = M p with <r0, v> from its epilogue, a pass forms
+// s = r - alpha v, two hops form t = M s with <t, s> and |t|^2 from its epilogue, a pass
+// forms r = s - omega t with <r0, r> and |r|^2, and the direction update forms
+// p = r + beta (p - omega v).  The steps alpha p + omega s are owed to the FP32 increment
+// in a ring of K (p, s) pairs and taken K at a time; FP64 reliable updates (quorum rule of
+// the CG loop) fold them with the increment into x_hi and replace r by the FP64 residual.
+// Decisions read the previous iteration's scalars, as in the CG loop.
+template <class SP, class GP, class CP, class XP>
+void bicgstab_fused(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, Vec rhi, Vec tmp64,
+                    int maxiter, int reliable_every, std::vector<Scal> &hs)
+{
+    const bool nrm = SP::kNorm;
+    laph_ctx *c = w.c;
+    const long n = w.Vh * w.R;
+    const int nblk = (int)red_blocks(n);
+    const int K = w.dirs > 0 ? w.dirs : kDefaultDirs;
+    Vec r = w.make("r", SP::bytes, nrm), r0 = w.make("r0", SP::bytes, nrm);
+    Vec v = w.make("v", SP::bytes, nrm), t = w.make("t", SP::bytes, nrm);
+    Vec pb[kMaxDirs], sb[kMaxDirs];
+    pb[0] = w.make("p", SP::bytes, nrm);
+    sb[0] = w.make("s", SP::bytes, nrm);
+    for (int j = 1; j < K; j++) {
+        pb[j] = w.make(("p" + std::to_string(j + 1)).c_str(), SP::bytes, nrm);
+        sb[j] = w.make(("s" + std::to_string(j + 1)).c_str(), SP::bytes, nrm);
+    }
+    Vec xlo = w.make("xlo", XP::bytes, false);
+    // per-block partials of the hopping epilogues and of the residual update (three rows
+    // per RHS each), then kChunks per row
+    const int nblk_hop = (int)lds_dag_blocks(c, prec_of<SP>(), w.R), nblk_el = (int)nblocks_for(n, kBS);
+    double *part_hop =
+        (double *)ctx_named(c, "slv.bs_part_hop", sizeof(double) * 3 * std::max(nblk_hop, nblk_el) * w.R);
+    double *part_pre = (double *)ctx_named(c, "slv.bs_part_pre", sizeof(double) * 3 * kChunks * w.R);
+    // r = r0 = p = the FP64 residual in storage precision, x = 0
+    launch_red(c, k_bicg_init<SP, XP>, n, rhi, r, r0, pb[0], xlo, w.Vh, w.R, w.part, (const Scal *)w.sc);
+    launch_fin(c, k_fin_init, w.R, (const double *)w.part, nblk, w.R, w.sc);
+    read_scal(c, w.sc, hs);
+    std::vector<double> r2_last(w.R), r2_min(w.R);
+    for (int q = 0; q < w.R; q++) r2_last[q] = r2_min[q] = hs[q].r2;
+    int cur = 0;    // p is pb[cur]; this iteration's s goes to sb[cur]
+    int nowed = 0;  // steps owed to x by earlier iterations, pairs cur - 1, ..., cur - nowed
+    // cnt pairs, latest first, starting first pairs behind cur
+    auto owed = [&](int first, int cnt) {
+        BsDirs d;
+        for (int j = 0; j < cnt; j++) {
+            const int b = ((cur - first - j) % K + K) % K;
+            d.p[j] = pb[b];
+            d.s[j] = sb[b];
+        }
+        d.n = cnt;
+        return d;
+    };
+    auto body = [&](const Op<SP, GP, CP> &op, int b) {
+        op.mhat_dot(pb[b], v, r0, part_hop);
+        hipLaunchKernelGGL(k_prereduce, dim3(kChunks, 3 * w.R), dim3(kBS), 0, c->stream, (const double *)part_hop,
+                           nblk_hop, part_pre);
+        launch_fin(c, k_fin_bs_alpha, w.R, (const double *)part_pre, kChunks, w.R, w.sc);
+        launch_el(c, k_s_update<SP>, n, r, v, sb[b], w.Vh, w.R, (const Scal *)w.sc);
+        op.mhat_dot(sb[b], t, sb[b], part_hop);
+        hipLaunchKernelGGL(k_prereduce, dim3(kChunks, 3 * w.R), dim3(kBS), 0, c->stream, (const double *)part_hop,
+                           nblk_hop, part_pre);
+        launch_fin(c, k_fin_bs_omega, w.R, (const double *)part_pre, kChunks, w.R, w.sc);
+        launch_el(c, k_bs_r<SP>, n, sb[b], t, r, r0, w.Vh, w.R, part_hop, (const Scal *)w.sc);
+        hipLaunchKernelGGL(k_prereduce, dim3(kChunks, 3 * w.R), dim3(kBS), 0, c->stream, (const double *)part_hop,
+                           nblk_el, part_pre);
+        launch_fin(c, k_fin_bs_beta, w.R, (const double *)part_pre, kChunks, w.R, w.sc);
+    };
+    Scal *pin = pinned_scal(c, w.R);
+    int slot = 0;
+    bool prev_ok = false;
+    hipGraphExec_t gexecs[kMaxDirs] = {};  // the body captured for each ring position
+    const bool graph_ok = w.use_graph && !c->timing;
+    if (graph_ok && !c->cap_stream) LAPH_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    struct GraphGuard {
+        hipGraphExec_t *g;
+        ~GraphGuard()
+        {
+            for (int k = 0; k < kMaxDirs; k++)
+                if (g[k]) (void)hipGraphExecDestroy(g[k]);
+        }
+    } guard{gexecs};
+    const double kDelta2 = w.delta2;
+    int since = 0;
+    int why[4] = {0, 0, 0, 0};  // reliable updates by trigger: all converged, deep drop, quorum, count
+    for (int it = 0; it < maxiter; it++) {
+        hipGraphExec_t &gexec = gexecs[cur];
+        if (gexec) {
+            LAPH_HIP(hipGraphLaunch(gexec, c->stream));
+        } else if (graph_ok) {
+            hipStream_t main = c->stream;
+            Op<SP, GP, CP> cap = lo;
+            cap.st = c->cap_stream;
+            c->stream = c->cap_stream;
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
+            if (e == hipSuccess) {
+                body(cap, cur);
+                e = hipStreamEndCapture(c->cap_stream, &g);
+            }
+            c->stream = main;
+            LAPH_HIP(e);
+            e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            LAPH_HIP(e);
+            LAPH_HIP(hipGraphLaunch(gexec, c->stream));
+        } else {
+            body(lo, cur);
+        }
+        // the direction update writes the next pair's p; with every pair owed it first
+        // takes all K steps (the oldest pair is the one overwritten)
+        const bool take = nowed + 1 == K;
+        const int nxt = (cur + 1) % K;
+        launch_el(c, k_bs_p<SP, XP>, n, pb[nxt], owed(0, take ? K : 1), r, v, xlo, w.Vh, w.R, (const Scal *)w.sc,
+                  take ? K : 0);
+        cur = nxt;
+        nowed = take ? 0 : nowed + 1;
+        since++;
+        LAPH_HIP(hipMemcpyAsync(pin + (size_t)slot * w.R, w.sc, sizeof(Scal) * w.R, hipMemcpyDeviceToHost,
+                                c->stream));
+        LAPH_HIP(hipEventRecord(c->pin_ev[slot], c->stream));
+        const int use = prev_ok ? slot ^ 1 : slot;
+        LAPH_HIP(hipEventSynchronize(c->pin_ev[use]));
+        std::copy(pin + (size_t)use * w.R, pin + (size_t)use * w.R + w.R, hs.begin());
+        prev_ok = true;
+        slot ^= 1;
+        // divergence: the iterated residual grew 1e4-fold above its minimum; the RHS is
+        // handed to the fallback
+        unsigned drop = 0;
+        UpdateVote vote;
+        for (int q = 0; q < w.R; q++) {
+            if (!hs[q].active) continue;
+            r2_min[q] = std::min(r2_min[q], hs[q].r2);
+            if (!(hs[q].r2 <= 1e8 * r2_min[q])) {
+                drop |= 1u << q;
+                continue;
+            }
+            vote.add(hs[q], r2_last[q], kDelta2);
+        }
+        const bool any = vote.nact > 0, want_update = vote.want();
+        const int nact = vote.nact;
+        const double worst = vote.worst;
+        if (drop) {
+            hipLaunchKernelGGL(k_bs_drop, dim3(1), dim3(32), 0, c->stream, w.sc, w.R, drop);
+            LAPH_HIP(hipGetLastError());
+        }
+        if (laph_verbose() && (it % 256 == 0 || !any || laph_verbose_level() > 1))
+            fprintf(stderr, "[laph] bicgstab it=%d active=%d/%d max |r|/target=%.3g upd=%d\n", it, nact, w.R, worst,
+                    (int)want_update);
+        if (!any) break;
+        if (want_update || since >= reliable_every) {
+            why[vote.all_conv() ? 0 : vote.deep ? 1 : vote.quorum() ? 2 : 3]++;
+            // reliable update: x_hi += x_lo + the owed steps, r = the FP64 residual in storage
+            // precision, rho = <r0, r>; p is kept
+            launch_el(c, k_fold_x_bs<XP, SP>, n, xhi, xlo, owed(1, nowed), w.Vh, w.R, (const Scal *)w.sc);
+            nowed = 0;
+            true_eo_residual<SP>(w, hi, bhat, xhi, tmp64, rhi, 0, r);
+            launch_red(c, k_dot_nb<SP>, n, r0, r, w.Vh, w.R, w.part, (const Scal *)w.sc);
+            launch_fin(c, k_fin_rho, w.R, (const double *)w.part, nblk, w.R, w.sc);
+            since = 0;
+            read_scal(c, w.sc, hs);
+            prev_ok = false;  // the slots predate the update
+            bool left = false;
+            for (int q = 0; q < w.R; q++) {
+                left |= hs[q].active != 0;
+                r2_last[q] = hs[q].r2;
+                r2_min[q] = std::min(r2_min[q], hs[q].r2);
+            }
+            if (!left) break;
+        }
+    }
+    if (laph_verbose())
+        fprintf(stderr, "[laph] bicgstab reliable updates: all converged %d, deep drop %d, quorum %d, count %d\n", why[0],
+                why[1], why[2], why[3]);
+    // steps still owed after the last iteration, then the increment of every RHS (inactive
+    // ones hold what they had when they stopped)
+    if (nowed) launch_el(c, k_fold_x_bs<XP, SP>, n, xhi, xlo, owed(1, nowed), w.Vh, w.R, (const Scal *)w.sc);
+    launch_el(c, k_fold_x<XP>, n, xhi, xlo, w.Vh, w.R, (const Scal *)w.sc, 1);
 }
 
 // BiCGStab in storage SP on the even-odd system; x_hi accumulates the FP64 solution.
@@ -1112,6 +1597,10 @@ void bicgstab(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec x
               int maxiter, int reliable_every, int check_every, std::vector<Scal> &hs)
 {
     const bool plain = std::is_same<SP, S64>::value;
+    if constexpr (!std::is_same<SP, S64>::value) {
+        bicgstab_fused<SP, GP, CP, XP>(w, lo, hi, bhat, xhi, rhi, tmp64, maxiter, reliable_every, hs);
+        return;
+    }
     const bool nrm = SP::kNorm;
     Vec r = w.make("r", SP::bytes, nrm), r0 = w.make("r0", SP::bytes, nrm), p = w.make("p", SP::bytes, nrm);
     Vec v = w.make("v", SP::bytes, nrm), s = w.make("s", SP::bytes, nrm), t = w.make("t", SP::bytes, nrm);
@@ -1295,8 +1784,8 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
     // slot behind its hops; the update rule at iteration k reads iteration k - 1's slot,
     // long complete, so the host never waits for the queue to drain (an update or the
     // convergence test comes one iteration later, which the rule tolerates)
-    const int quorum = kUpdateQuorum;
     const bool lag = !plain;
+    int nupd = 0;  // reliable updates (reported under LAPH_VERBOSE)
     Scal *pin = lag ? pinned_scal(c, w.R) : nullptr;
     int slot = 0;
     bool prev_ok = false;  // the other slot holds the previous iteration's scalars
@@ -1357,18 +1846,12 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
         } else {
             read_scal(c, w.sc, hs);
         }
-        bool any = false, want_update = false;
-        int nact = 0, nwant = 0;
-        double worst = 0;
-        for (int k = 0; k < w.R; k++) {
-            if (!hs[k].active) continue;
-            any = true;
-            nact++;
-            worst = std::max(worst, hs[k].tol2 > 0 ? std::sqrt(hs[k].r2 / hs[k].tol2) : 0.0);
-            if (hs[k].r2 <= hs[k].tol2 || hs[k].r2 < 0.01 * kDelta2 * r2_last[k]) want_update = true;
-            if (hs[k].r2 < kDelta2 * r2_last[k]) nwant++;
-        }
-        if (nwant > 0 && nwant * 100 >= quorum * nact) want_update = true;
+        UpdateVote vote;
+        for (int k = 0; k < w.R; k++)
+            if (hs[k].active) vote.add(hs[k], r2_last[k], kDelta2);
+        const bool any = vote.nact > 0, want_update = vote.want();
+        const int nact = vote.nact;
+        const double worst = vote.worst;
         if (laph_verbose() && (it % 256 < check_every || !any || laph_verbose_level() > 1))
             fprintf(stderr, "[laph] cgnr it=%d active=%d/%d max |res|/target=%.3g rhs0: rho=%.3e alpha=%.3e r2=%.3e "
                     "aux=%.3e upd=%d\n", it, nact, w.R, worst, hs[0].rho.x, hs[0].alpha.x, hs[0].r2, hs[0].aux.x,
@@ -1376,6 +1859,7 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
         if (!any) break;
         if (plain) continue;
         if (want_update || since >= reliable_every) {
+            nupd++;
             // reliable update between the residual and the direction update: fold the
             // increment, replace r and res by FP64 residuals, take beta from the new |r|^2
             // and keep the old direction orthogonal to the new residual
@@ -1422,6 +1906,7 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
             nowed = take ? 0 : nowed + 1;
         }
     }
+    if (laph_verbose() && !plain) fprintf(stderr, "[laph] cgnr reliable updates: %d\n", nupd);
     // steps still owed after the last iteration (the latest takes the current alpha)
     if (nowed)
         launch_el(c, k_fold_x_step<XP, SP>, n, xhi, xlo, owed_dirs(1, nowed), w.Vh, w.R, (const Scal *)w.sc);
@@ -2122,7 +2607,8 @@ size_t hop_scratch_bytes(laph_ctx *c, const laph_hop *h, int R)
     if (h->precision != LAPH_PREC_F64) {
         s += 5 * vec_bytes(Vh, R, h->precision);
         const int S = h->sites_per_block > 0 ? h->sites_per_block : lds_tile_sites(c, h->precision, R);
-        s += ws_align(sizeof(double) * ((Vh + S - 1) / S) * R) + ws_align(sizeof(Scal) * R);
+        const int nq = h->mode == LAPH_HOP_INV_DOT ? 3 : 1;  // partial sums per field
+        s += ws_align(sizeof(double) * nq * ((Vh + S - 1) / S) * R) + ws_align(sizeof(Scal) * R);
     }
     return s;
 }
@@ -2168,7 +2654,15 @@ size_t solve_scratch_bytes(laph_ctx *c, int n_rhs, const laph_solver *sv)
     s += ws_align(sizeof(Scal) * Rb) + ws_align(sizeof(double) * kMaxBlocks * Rb * 4);
     s += 10 * vec_bytes(Vh, Rb, LAPH_PREC_F64) + vec_bytes(Vh, Rb, prec);
     if (guess) s += 2 * ws_align(sizeof(float2) * 12 * V * Rb);
-    if (sv->solver == LAPH_SOLVER_BICGSTAB) s += 6 * vec_bytes(Vh, Rb, prec) + vec_bytes(Vh, Rb, xp);
+    if (sv->solver == LAPH_SOLVER_BICGSTAB && !low) s += 6 * vec_bytes(Vh, Rb, prec) + vec_bytes(Vh, Rb, xp);
+    if (sv->solver == LAPH_SOLVER_BICGSTAB && low) {
+        // r, r0, v, t and the ring of K (p, s) pairs; epilogue partials (three rows per RHS)
+        const int K = sv->dir_buffers > 0 ? sv->dir_buffers : kDefaultDirs;
+        s += (4 + 2 * K) * vec_bytes(Vh, Rb, prec) + vec_bytes(Vh, Rb, xp);
+        const int S = lds_tile_sites(c, prec, Rb);
+        const long nb = std::max<long>((Vh + S - 1) / S, nblocks_for(Vh * Rb, kBS));
+        s += ws_align(sizeof(double) * 3 * nb * Rb) + ws_align(sizeof(double) * 3 * kChunks * Rb);
+    }
     if (fg) {
         const long n = 12 * Vh;
         const int m = sv->restart > 0 ? sv->restart : 24;
@@ -2195,7 +2689,7 @@ size_t solve_scratch_bytes(laph_ctx *c, int n_rhs, const laph_solver *sv)
 // One even-odd hopping launch of the solver's kernels on caller fields (see laph.h).
 template <class SP>
 static void hop_launch_lo(laph_ctx *c, const DiracCache &dc, const laph_hop *h, int R, Vec in, const Vec *x, Vec out,
-                          Vec out2, Vec r, const Scal *sc, double *partial)
+                          Vec out2, Vec r, Vec y, const Scal *sc, double *partial)
 {
     Op<SP, G32, C32> lo{c, c->stream, c->g.Vh, R, nullptr, nullptr, nullptr, -0.5 / dc.prm.xi, -0.5, dc.prm.bc_t,
                         Vec{}};
@@ -2222,6 +2716,12 @@ static void hop_launch_lo(laph_ctx *c, const DiracCache &dc, const laph_hop *h, 
         m.sc = sc;
         m.partial = partial;
         break;
+    case LAPH_HOP_INV_DOT:
+        mode = M_INV_AFTER_DOT;
+        m.dot_y = y.d;
+        m.dot_y_nrm = y.n;
+        m.partial = partial;
+        break;
     default: break;
     }
     launch_dslash_mr<SP>(c, mode, m, c->stream);
@@ -2235,18 +2735,20 @@ extern "C" int laph_hop_apply(laph_ctx_t c, const double *U, const laph_dirac *d
     LAPH_CHECK(U && h && in && out, LAPH_EINVAL, "null pointer");
     check_dirac(d);
     LAPH_CHECK(h->precision >= LAPH_PREC_F64 && h->precision <= LAPH_PREC_BF16, LAPH_EINVAL, "bad precision");
-    LAPH_CHECK(h->mode >= LAPH_HOP_PLAIN && h->mode <= LAPH_HOP_PLAIN_CG, LAPH_EINVAL, "bad mode");
+    LAPH_CHECK(h->mode >= LAPH_HOP_PLAIN && h->mode <= LAPH_HOP_INV_DOT, LAPH_EINVAL, "bad mode");
     LAPH_CHECK(h->parity == 0 || h->parity == 1, LAPH_EINVAL, "parity must be 0 or 1");
     LAPH_CHECK(h->walk == 0 || h->walk == 1, LAPH_EINVAL, "walk must be 0 or 1");
     LAPH_CHECK(h->sites_per_block >= 0, LAPH_EINVAL, "sites_per_block must be >= 0");
     LAPH_CHECK(n >= 1 && n <= 32 && (n & (n - 1)) == 0, LAPH_EINVAL, "n_fields must be a power of two <= 32");
     LAPH_CHECK(n <= max_block_rhs(c, h->precision), LAPH_EINVAL, "%d fields exceed the kernel's 32-bit offsets", n);
     const bool low = h->precision != LAPH_PREC_F64;
-    const bool fused = h->mode == LAPH_HOP_INV_DAG || h->mode == LAPH_HOP_PLAIN_CG;
+    const bool fused = h->mode == LAPH_HOP_INV_DAG || h->mode == LAPH_HOP_PLAIN_CG || h->mode == LAPH_HOP_INV_DOT;
+    const bool dot = h->mode == LAPH_HOP_INV_DOT;
     LAPH_CHECK(low || !fused, LAPH_EINVAL, "fused epilogues exist for the low precisions only");
     LAPH_CHECK(!fused || x, LAPH_EINVAL, "the fused epilogues need the own-site operand x");
     LAPH_CHECK(h->mode != LAPH_HOP_INV_DAG || (out2 && h->c != 0), LAPH_EINVAL, "INV_DAG needs out2 and c != 0");
     LAPH_CHECK(h->mode != LAPH_HOP_PLAIN_CG || alpha, LAPH_EINVAL, "PLAIN_CG needs alpha");
+    LAPH_CHECK(!dot || (out2 && norm2), LAPH_EINVAL, "INV_DOT needs the field y in out2 and norm2");
     if (h->temporal_gauge)
         dirac_prepare_tgauge(c, U, d);
     else
@@ -2278,11 +2780,13 @@ extern "C" int laph_hop_apply(laph_ctx_t c, const double *U, const laph_dirac *d
         LAPH_HIP(hipMemcpyAsync(xh.d, p ? o64.d : e64.d, half64, hipMemcpyDeviceToDevice, c->stream));
     }
     Vec r64{ctx_named(c, "hop.r64", half64)};
-    if (h->mode == LAPH_HOP_PLAIN_CG) {
-        spinor_to_eo(c, out, R, 0, (double2 *)e64.d, (double2 *)o64.d, G);
+    if (h->mode == LAPH_HOP_PLAIN_CG || dot) {
+        // r (PLAIN_CG: the residual in out) or y (INV_DOT: the field in out2), parity p
+        spinor_to_eo(c, dot ? out2 : out, R, 0, (double2 *)e64.d, (double2 *)o64.d, G);
         LAPH_HIP(hipMemcpyAsync(r64.d, p ? o64.d : e64.d, half64, hipMemcpyDeviceToDevice, c->stream));
     }
-    std::vector<double> nrm(R, 0.0);
+    const int nq = dot ? 3 : 1;  // partial sums per field
+    std::vector<double> nrm((size_t)nq * R, 0.0);
     Vec res64 = p ? o64 : e64;   // result half in FP64
     Vec zero64 = p ? e64 : o64;  // the other parity of every output: zero
     if (!low) {
@@ -2311,7 +2815,7 @@ extern "C" int laph_hop_apply(laph_ctx_t c, const double *U, const laph_dirac *d
         double *part = nullptr;
         const long nblk = lds_dag_blocks(c, h->precision, R);
         if (fused) {
-            part = (double *)ctx_named(c, "hop.part", sizeof(double) * nblk * R);
+            part = (double *)ctx_named(c, "hop.part", sizeof(double) * nblk * R * nq);
             if (h->mode == LAPH_HOP_PLAIN_CG) {
                 std::vector<Scal> hs(R);
                 for (int q = 0; q < R; q++) {
@@ -2327,8 +2831,10 @@ extern "C" int laph_hop_apply(laph_ctx_t c, const double *U, const laph_dirac *d
             using SP = decltype(tag);
             launch_el(c, k_store_lo<SP>, nl, in64, lin, Vh, R);
             if (x) launch_el(c, k_store_lo<SP>, nl, xh, lx, Vh, R);
-            if (h->mode == LAPH_HOP_PLAIN_CG) launch_el(c, k_store_lo<SP>, nl, r64, lr, Vh, R);
-            hop_launch_lo<SP>(c, dc, h, R, lin, x ? &lx : nullptr, lout, lout2, lr, sc, part);
+            // INV_DOT with y the caller's x itself: the kernel's y = x form
+            const bool y_is_x = dot && (const double *)out2 == x;
+            if (h->mode == LAPH_HOP_PLAIN_CG || (dot && !y_is_x)) launch_el(c, k_store_lo<SP>, nl, r64, lr, Vh, R);
+            hop_launch_lo<SP>(c, dc, h, R, lin, x ? &lx : nullptr, lout, lout2, lr, y_is_x ? lx : lr, sc, part);
             launch_el(c, k_load_lo<SP>, nl, h->mode == LAPH_HOP_PLAIN_CG ? lr : lout, res64, Vh, R);
             if (h->mode == LAPH_HOP_INV_DAG) launch_el(c, k_load_lo<SP>, nl, lout2, r64, Vh, R);
         };
@@ -2339,10 +2845,10 @@ extern "C" int laph_hop_apply(laph_ctx_t c, const double *U, const laph_dirac *d
         else
             run(SB16{});
         if (fused) {
-            std::vector<double> hp((size_t)nblk * R);
+            std::vector<double> hp((size_t)nblk * R * nq);
             LAPH_HIP(hipMemcpyAsync(hp.data(), part, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, c->stream));
             LAPH_HIP(hipStreamSynchronize(c->stream));
-            for (int q = 0; q < R; q++)
+            for (int q = 0; q < nq * R; q++)
                 for (long b = 0; b < nblk; b++) nrm[q] += hp[(size_t)q * nblk + b];
         }
     }
@@ -2354,8 +2860,13 @@ extern "C" int laph_hop_apply(laph_ctx_t c, const double *U, const laph_dirac *d
                        p ? (const double2 *)r64.d : (const double2 *)zero64.d, R, 0, out2, G);
     }
     LAPH_HIP(hipStreamSynchronize(c->stream));
-    if (norm2)
+    if (norm2 && dot) {
+        // partial rows are value-major: Re <y, out> of every field, then Im, then |out|^2
+        for (int q = 0; q < R; q++)
+            for (int e = 0; e < 3; e++) norm2[3 * q + e] = nrm[(size_t)e * R + q];
+    } else if (norm2) {
         for (int q = 0; q < R; q++) norm2[q] = nrm[q];
+    }
     LAPH_API_END(c)
 }
 

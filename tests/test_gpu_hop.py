@@ -19,7 +19,9 @@ with e_arith = 2e-5 (|a| + |c|) for inputs of magnitude <= 1 (FP32 sums of ~100 
 with FP32 operands).  In temporal gauge the rotated inputs are rounded too, which adds
 8 u (|c| + |a|) max|input| per element.  Norms of the fused epilogues are checked against
 the sum of squares of the returned (stored) outputs to 1e-6 relative and against the
-reference within the propagated rounding.  FP64 hops: 1e-13 relative.
+reference within the propagated rounding; the inner products <y, out> of the BiCGStab
+epilogue (INV_DOT) against those of the stored outputs to 4e-6 of sum |y| |out|.  FP64
+hops: 1e-13 relative.
 """
 import zlib
 
@@ -107,15 +109,18 @@ def check_out(got, ref, prec, p, par, e_site):
                              % (tuple(i), got[tuple(i)], ref[tuple(i)], np.abs(d).max(), e_site))
 
 
-def run_case(P, ref, prec, mode, p, R, gamma5, tg, walk, spb, a, c, seed):
+def run_case(P, ref, prec, mode, p, R, gamma5, tg, walk, spb, a, c, seed, y_is_x=False):
     import torch
 
     say("hop", ref.ns, ref.nt, prec, mode, "p", p, "R", R, "g5", gamma5, "tg", tg, "walk", walk, "S", spb)
     rng = np.random.default_rng(seed)
     shape = (R, ref.nt, ref.ns, ref.ns, ref.ns, 4)
     inp = exact_fields(rng, prec, shape + (3,))
-    use_x = mode in (P.LAPH_HOP_INV_DAG, P.LAPH_HOP_PLAIN_CG) or (seed % 2 == 0)
+    use_x = mode in (P.LAPH_HOP_INV_DAG, P.LAPH_HOP_PLAIN_CG, P.LAPH_HOP_INV_DOT) or (seed % 2 == 0)
     x = exact_fields(rng, prec, shape + (3,)) if use_x else None
+    y = exact_fields(rng, prec, shape + (3,)) if mode == P.LAPH_HOP_INV_DOT else None
+    if y_is_x:
+        y = x
     r0 = exact_fields(rng, prec, shape + (3,)) if mode == P.LAPH_HOP_PLAIN_CG else None
     alpha = rng.uniform(0.2, 1.5, size=R) if mode == P.LAPH_HOP_PLAIN_CG else None
     if alpha is not None and prec != "f64":
@@ -125,7 +130,12 @@ def run_case(P, ref, prec, mode, p, R, gamma5, tg, walk, spb, a, c, seed):
     prm = P.laph_dirac(ref.m0, XI, CSW, BC)
     out = dev(r0) if r0 is not None else torch.empty(shape + (3,), dtype=torch.complex128, device="cuda")
     out2 = torch.empty_like(out) if mode == P.LAPH_HOP_INV_DAG else None
-    nrm = P.laph_hop_apply(L.ctx, dev(ref.U), prm, prec, mode, p, dev(inp), out, x=dev(x) if use_x else None,
+    if y is not None:
+        out2 = dev(y)  # INV_DOT: the field y, an input
+    xd = dev(x) if use_x else None
+    if y_is_x:
+        out2 = xd  # the same device field: the kernel's y = x form
+    nrm = P.laph_hop_apply(L.ctx, dev(ref.U), prm, prec, mode, p, dev(inp), out, x=xd,
                            out2=out2, alpha=alpha, gamma5=gamma5, temporal_gauge=tg, walk=walk, sites_per_block=spb,
                            a=a, c=c)
     got = host(out)
@@ -135,7 +145,7 @@ def run_case(P, ref, prec, mode, p, R, gamma5, tg, walk, spb, a, c, seed):
     hop = np.stack([ref.hop(inp[r], p) for r in range(R)])
     if gamma5:
         hop = ref.gamma5(hop)
-    inv = mode in (P.LAPH_HOP_INV, P.LAPH_HOP_INV_DAG)
+    inv = mode in (P.LAPH_HOP_INV, P.LAPH_HOP_INV_DAG, P.LAPH_HOP_INV_DOT)
     body = c * (ref.ainv(hop) if inv else hop)
     xs = ref.mask(x, p) if use_x else 0.0
     v = body + a * xs
@@ -161,6 +171,24 @@ def run_case(P, ref, prec, mode, p, R, gamma5, tg, walk, spb, a, c, seed):
         np.testing.assert_allclose(nrm, stored, rtol=1e-6, atol=0)
         exact = np.sum(np.abs(want) ** 2, axis=(1, 2, 3, 4, 5, 6))
         np.testing.assert_allclose(nrm, exact, rtol=8 * U_IN[prec] + 1e-5 + (2e-3 if tg else 0.0), atol=0)
+    if mode == P.LAPH_HOP_INV_DOT:
+        # <y, out> and |out|^2 per field from the stored out (FP32 sums of 24 products per
+        # site and field, FP64 beyond: 4e-6 of sum |y| |out|), and against the exact out
+        # within sum |y| |got - want| (+ the rounding of the rotated y in temporal gauge)
+        assert np.array_equal(host(out2), y), "INV_DOT changed its input y"
+        ym = ref.mask(y, p)
+        ax = (1, 2, 3, 4, 5, 6)
+        dots = nrm.reshape(R, 3)
+        got_dot = np.sum(np.conj(ym) * got, axis=ax)
+        mag = np.sum(np.abs(ym) * np.abs(got), axis=ax)
+        e_tg = 8 * U_IN[prec] * mag if tg else 0.0
+        for e, val in ((0, got_dot.real), (1, got_dot.imag)):
+            assert np.all(np.abs(dots[:, e] - val) <= 4e-6 * mag + e_tg), (e, dots[:, e], val)
+        stored = np.sum(np.abs(got) ** 2, axis=ax)
+        np.testing.assert_allclose(dots[:, 2], stored, rtol=1e-6 + (8 * U_IN[prec] if tg else 0.0), atol=0)
+        exact = np.sum(np.conj(ym) * want, axis=ax)
+        dev_ = np.sum(np.abs(ym) * np.abs(got - want), axis=ax)
+        assert np.all(np.abs(dots[:, 0] + 1j * dots[:, 1] - exact) <= dev_ + 4e-6 * mag + e_tg)
     if mode == P.LAPH_HOP_INV_DAG:
         # out2 = A^-1 gamma_5 out; the reference applies them to the exact out, so the
         # rounding of the stored out enters through |A^-1|
@@ -181,7 +209,7 @@ def get_ref(ns, nt, m0=-0.05):
     return _REFS[key]
 
 
-MODES = ["PLAIN", "INV", "INV_DAG", "PLAIN_CG"]
+MODES = ["PLAIN", "INV", "INV_DAG", "PLAIN_CG", "INV_DOT"]
 
 
 @pytest.mark.parametrize("prec", ["f16", "bf16", "f32"])
@@ -203,7 +231,7 @@ def test_hop_small(P, prec, mode, ns, nt, tg, walk):
 def test_hop_blocks_and_tiles(P, prec, R, S):
     """Other block sizes and explicit tiles (S sites x R lanes, S not dividing Vh)."""
     ref = get_ref(6, 4)
-    for mode in (P.LAPH_HOP_INV, P.LAPH_HOP_INV_DAG, P.LAPH_HOP_PLAIN_CG):
+    for mode in (P.LAPH_HOP_INV, P.LAPH_HOP_INV_DAG, P.LAPH_HOP_PLAIN_CG, P.LAPH_HOP_INV_DOT):
         run_case(P, ref, prec, mode, 1, R, 0, 1, 0, S, 1.0, -1.0, seed=R * 100 + S)
 
 
@@ -226,6 +254,16 @@ def test_hop_16x32(P, prec, mode):
         run_case(P, ref, prec, m, 0, 32, 0, 0, 0, 0, 1.0, -1.0, seed=4)
 
 
+@pytest.mark.parametrize("prec", ["f16", "bf16", "f32"])
+@pytest.mark.parametrize("tg", [0, 1])
+def test_hop_dot_y_is_x(P, prec, tg):
+    """INV_DOT with y the own-site operand x itself (BiCGStab's <s, M s>): the kernel
+    takes y from the loaded x instead of a second load."""
+    ref = get_ref(6, 4)
+    for R, p in ((4, 0), (32, 1)):
+        run_case(P, ref, prec, P.LAPH_HOP_INV_DOT, p, R, 0, tg, 0, 0, 1.0, -1.0, seed=40 + R + tg, y_is_x=True)
+
+
 def test_hop_fp64_16x32(P):
     ref = get_ref(16, 32, -0.12)
     run_case(P, ref, "f64", P.LAPH_HOP_INV, 1, 32, 0, 1, 0, 0, 1.0, -1.0, seed=5)
@@ -246,7 +284,9 @@ def test_hop_rejects_bad_arguments(P):
                dict(mode=P.LAPH_HOP_PLAIN_CG, x=inp),  # needs alpha
                dict(mode=P.LAPH_HOP_INV, parity=2),
                dict(mode=P.LAPH_HOP_INV, sites_per_block=128),  # 128 x 4 lanes > 256
-               dict(mode=P.LAPH_HOP_INV_DAG, precision="f64", x=inp, out2=out)):
+               dict(mode=P.LAPH_HOP_INV_DAG, precision="f64", x=inp, out2=out),
+               dict(mode=P.LAPH_HOP_INV_DOT, x=inp),  # needs y in out2
+               dict(mode=P.LAPH_HOP_INV_DOT, precision="f64", x=inp, out2=out)):
         args = dict(precision="f16", parity=0)
         args.update(kw)
         prec, mode, parity = args.pop("precision"), args.pop("mode"), args.pop("parity")

@@ -92,6 +92,46 @@ def test_cgnr_direction_buffers(P, setup, prec):
         _solve(P, cfg, U, etas[:1], precision=prec, solver=P.LAPH_SOLVER_CGNR, dir_buffers=9)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_bicgstab_step_ring(P, setup, prec):
+    """The fused low-precision BiCGStab owes its steps alpha p + omega s to the solution
+    increment in a ring of dir_buffers (p, s) pairs and takes them together.  Every ring
+    size must give the same iterate up to rounding (a step lost or taken twice would be
+    repaired only by the next reliable update, at the cost of extra iterations): the
+    iteration counts must agree within a few and every answer must meet the bar.  FP16
+    records make the update decisions, and with them the count, vary with the rounding
+    order of the increment by a few more iterations than FP32."""
+    cfg, U, D, etas, xs = setup
+    its = {}
+    for k in (1, 2, 3, 5, 8):
+        x, st = _solve(P, cfg, U, etas, precision=prec, block_rhs=8, dir_buffers=k)
+        its[k] = [q.iters for q in st]
+        say("  bicgstab dir_buffers", k, "iters", its[k])
+        for r in range(5):
+            assert st[r].status == 0 and st[r].fallback_used == 0
+            assert D.true_residual(etas[r], x[r]) <= 1e-10
+            assert rel_err(x[r], xs[r]) <= 1e-8
+    slack = 3 if prec == "f32" else 5
+    for r in range(5):
+        col = [its[k][r] for k in its]
+        assert max(col) - min(col) <= max(slack, min(col) // 20), its
+
+
+def test_bicgstab_graph_replay_matches_eager(P, setup):
+    """The fused BiCGStab iteration replayed from HIP graphs (one per ring position) gives
+    bit-identical solutions and iteration counts to eager launches."""
+    cfg, U, D, etas, xs = setup
+    kw = dict(precision="f16", block_rhs=4, solver=P.LAPH_SOLVER_BICGSTAB)
+    x0, s0 = _solve(P, cfg, U, etas[:4], use_graph=0, **kw)
+    for rep in range(2):
+        x1, s1 = _solve(P, cfg, U, etas[:4], use_graph=1, **kw)
+        say("  bicgstab iters eager", [q.iters for q in s0], "graph", [q.iters for q in s1])
+        assert [q.iters for q in s0] == [q.iters for q in s1]
+        assert np.array_equal(x0, x1)
+    for r in range(4):
+        assert s1[r].fallback_used == 0 and D.true_residual(etas[r], x1[r]) <= 1e-10
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
 def test_multi_rhs_masked(P, setup, prec):
     """5 right-hand sides in blocks of 8 (padded, uneven convergence): each equals the
@@ -230,3 +270,24 @@ def test_mixed_iterations_bound(P, mid):
     assert mean["f32"] <= 1.05 * mean["f64"], mean
     assert mean["f16"] <= 1.05 * mean["f64"], mean
     assert mean["bf16"] <= 1.20 * mean["f64"], mean
+
+
+def test_bicgstab_mixed_iterations_bound(P, mid):
+    """The same for BiCGStab (Sec. IV), the paper's solver: the fused low-precision
+    iteration (inner products from the hopping epilogues, owed steps, FP64 reliable
+    updates) on the block of four against FP64 BiCGStab, without the fallback.  FP32
+    within 5%; FP16 within 20%: BiCGStab's two-sided recurrence (the shadow residual)
+    loses the rounding of 11-bit records faster than CG's, which FP16 CG absorbs at +1%."""
+    cfg, U, D, etas = mid
+    mean = {}
+    for prec in ("f64", "f32", "f16"):
+        say("bicgstab iterations", prec)
+        x, st = _solve(P, cfg, U, etas, precision=prec, block_rhs=4, solver=P.LAPH_SOLVER_BICGSTAB)
+        for r in range(etas.shape[0]):
+            assert st[r].status == 0 and st[r].fallback_used == 0
+            assert D.true_residual(etas[r], x[r]) <= 1e-10
+        mean[prec] = float(np.mean([q.iters for q in st]))
+        say("  iters", [q.iters for q in st], "mean", mean[prec])
+    assert mean["f64"] > 50, mean
+    assert mean["f32"] <= 1.05 * mean["f64"], mean
+    assert mean["f16"] <= 1.20 * mean["f64"], mean

@@ -22,18 +22,17 @@ struct MrArgs {
     int g5d;
     // M_INV_AFTER_DAG: second output A^-1 gamma_5 out (same parity and layout as out).
     // M_PLAIN_CG: out is not stored; for active right-hand sides cg_r -= alpha out (alpha
-    // and the mask from sc[r]).  Both write partial[r * nblocks + block] = sum over the
-    // block's sites of |out_r|^2 (DAG) or |cg_r|^2 after the update (CG), from the stored
-    // values.
+    // and the mask from sc[r]).  Both write partial[block * R + r] = sum over the block's
+    // sites of |out_r|^2 (DAG) or |cg_r|^2 after the update (CG), from the stored values.
     void *out2;
     float *out2_nrm;
     double *partial;
     const Scal *sc;
     void *cg_r;
     float *cg_r_nrm;
-    // M_INV_AFTER_DOT: the field y (same parity and layout as out); partial[(q R + r) *
-    // nblocks + block] holds the block's sum of Re <y_r, out_r> (q = 0), Im (q = 1) and
-    // |out_r|^2 (q = 2), <y, out> = sum conj(y) out, from out as stored
+    // M_INV_AFTER_DOT: the field y (same parity and layout as out); partial[(block * 3 + q)
+    // * R + r] holds the block's sum of Re <y_r, out_r> (q = 0), Im (q = 1) and |out_r|^2
+    // (q = 2), <y, out> = sum conj(y) out, from out as stored
     const void *dot_y;
     const float *dot_y_nrm;
     // order in which the LDS-staged kernel visits output sites: wby = 0 walks the

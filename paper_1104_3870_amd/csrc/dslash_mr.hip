@@ -700,7 +700,8 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
     }  // valid
     if constexpr (kRed) {
         // deterministic block sum per right-hand side over the lanes sl = 0 .. S-1 of each
-        // r; partials stored right-hand-side major, value-major across the NQ values
+        // r; each block stores its NQ x R sums contiguously ([block][value][RHS]: whole cache
+        // lines, where one value per line for every block cost a fifth of the output bytes)
         __shared__ double red[NQ][256];
         if constexpr (NQ == 3) {
             red[0][threadIdx.x] = (double)dre;
@@ -715,7 +716,7 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
             for (int e = 0; e < NQ; e++) {
                 double s2 = 0.0;
                 for (int q = 0; q < S; q++) s2 += red[e][q * R + threadIdx.x];
-                P.partial[((size_t)e * R + threadIdx.x) * gridDim.x + blockIdx.x] = s2;
+                P.partial[((size_t)blockIdx.x * NQ + e) * R + threadIdx.x] = s2;
             }
         }
     }

@@ -598,23 +598,26 @@ __device__ __forceinline__ double sum_partials_rmajor(const double *partial, int
     return lds[0];
 }
 
-// partial[r][nblk] -> out[r][nchunk], chunk ch = fixed-order sum of its contiguous share of
-// the partials (the first stage of a deterministic two-stage reduction)
-constexpr int kChunks = 64;
-__global__ __launch_bounds__(kBS) void k_prereduce(const double *partial, int nblk, double *out)
+// partial[b][row] (nrow values per block, block-major as the fused epilogues write them)
+// -> out[row][kChunks], chunk ch = fixed-order sum of its contiguous share of the blocks
+// (the first stage of a deterministic two-stage reduction; nrow <= kBS)
+constexpr int kChunks = 1024;
+__global__ __launch_bounds__(kBS) void k_prereduce(const double *partial, int nblk, int nrow, double *out)
 {
-    const int r = blockIdx.y, ch = blockIdx.x;
+    const int ch = blockIdx.x, t = threadIdx.x;
     const long beg = (long)nblk * ch / kChunks, end = (long)nblk * (ch + 1) / kChunks;
+    const int G = kBS / nrow, g = t / nrow, row = t - g * nrow;  // G groups of nrow lanes
     double v = 0;
-    for (long b = beg + threadIdx.x; b < end; b += kBS) v += partial[(long)r * nblk + b];
+    if (g < G)
+        for (long b = beg + g; b < end; b += G) v += partial[b * nrow + row];
     __shared__ double lds[kBS];
-    lds[threadIdx.x] = v;
+    lds[t] = v;
     __syncthreads();
-    for (int s = kBS / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
-        __syncthreads();
+    if (t < nrow) {
+        double s2 = 0;
+        for (int q = 0; q < G; q++) s2 += lds[q * nrow + t];
+        out[(long)t * kChunks + ch] = s2;
     }
-    if (threadIdx.x == 0) out[(long)r * kChunks + ch] = lds[0];
 }
 
 // ------------------------------------------------- fused multi-RHS BiCGStab (Sec. IV)
@@ -650,7 +653,7 @@ __device__ __forceinline__ void add_bs_steps(const BsDirs &d, int n, const Scal 
     }
 }
 
-// the three value rows of right-hand side r in partials laid out [(e R + r) * nblk + b]
+// the three value rows of right-hand side r in prereduced partials [(e R + r) * nblk + b]
 __device__ __forceinline__ void sum_rows3(const double *partial, int nblk, int R, int r, double (&out)[3])
 {
     __shared__ double lds[3][kBS];
@@ -721,8 +724,8 @@ __global__ void k_fin_bs_omega(const double *partial, int nblk, int R, Scal *sc)
     q.omega = make_double2(s[0] / s[2], -s[1] / s[2]);
 }
 
-// r = s - omega t; per-block partials of <r0, r> and |r|^2 of the stored r, rows
-// value-major as the hopping epilogues write them (a block: kBS / R sites x R RHS)
+// r = s - omega t; per-block partials of <r0, r> and |r|^2 of the stored r, laid out as
+// the hopping epilogues write them, [block][value][RHS] (a block: kBS / R sites x R RHS)
 template <class SP>
 __global__ __launch_bounds__(kBS) void k_bs_r(Vec s, Vec t, Vec r, Vec r0, long Vh, int R, double *partial,
                                               const Scal *sc)
@@ -757,7 +760,7 @@ __global__ __launch_bounds__(kBS) void k_bs_r(Vec s, Vec t, Vec r, Vec r0, long 
         for (int e = 0; e < 3; e++) {
             double v = 0.0;
             for (int q = threadIdx.x; q < kBS; q += R) v += red[e][q];
-            partial[((long)e * R + threadIdx.x) * gridDim.x + blockIdx.x] = v;
+            partial[((long)blockIdx.x * 3 + e) * R + threadIdx.x] = v;
         }
     }
 }
@@ -1270,7 +1273,7 @@ struct Op {
         dslash_ext(M_INV_AFTER_DAG, 1, te, out, &in, 1.0, -1.0, 0, &to, partial);
     }
     // mhat with per-block partials of <y, out> and |out|^2 from the second hop's epilogue
-    // (low precision, LDS-staged kernel; rows value-major, see MrArgs)
+    // (low precision, LDS-staged kernel; partials [block][value][RHS], see MrArgs)
     void mhat_dot(Vec in, Vec out, Vec y, double *partial) const
     {
         dslash(M_INV_AFTER, 0, in, te, nullptr, 0.0, 1.0, 0);
@@ -1465,17 +1468,17 @@ void bicgstab_fused(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat,
     };
     auto body = [&](const Op<SP, GP, CP> &op, int b) {
         op.mhat_dot(pb[b], v, r0, part_hop);
-        hipLaunchKernelGGL(k_prereduce, dim3(kChunks, 3 * w.R), dim3(kBS), 0, c->stream, (const double *)part_hop,
-                           nblk_hop, part_pre);
+        hipLaunchKernelGGL(k_prereduce, dim3(kChunks), dim3(kBS), 0, c->stream, (const double *)part_hop, nblk_hop,
+                           3 * w.R, part_pre);
         launch_fin(c, k_fin_bs_alpha, w.R, (const double *)part_pre, kChunks, w.R, w.sc);
         launch_el(c, k_s_update<SP>, n, r, v, sb[b], w.Vh, w.R, (const Scal *)w.sc);
         op.mhat_dot(sb[b], t, sb[b], part_hop);
-        hipLaunchKernelGGL(k_prereduce, dim3(kChunks, 3 * w.R), dim3(kBS), 0, c->stream, (const double *)part_hop,
-                           nblk_hop, part_pre);
+        hipLaunchKernelGGL(k_prereduce, dim3(kChunks), dim3(kBS), 0, c->stream, (const double *)part_hop, nblk_hop,
+                           3 * w.R, part_pre);
         launch_fin(c, k_fin_bs_omega, w.R, (const double *)part_pre, kChunks, w.R, w.sc);
         launch_el(c, k_bs_r<SP>, n, sb[b], t, r, r0, w.Vh, w.R, part_hop, (const Scal *)w.sc);
-        hipLaunchKernelGGL(k_prereduce, dim3(kChunks, 3 * w.R), dim3(kBS), 0, c->stream, (const double *)part_hop,
-                           nblk_el, part_pre);
+        hipLaunchKernelGGL(k_prereduce, dim3(kChunks), dim3(kBS), 0, c->stream, (const double *)part_hop, nblk_el,
+                           3 * w.R, part_pre);
         launch_fin(c, k_fin_bs_beta, w.R, (const double *)part_pre, kChunks, w.R, w.sc);
     };
     Scal *pin = pinned_scal(c, w.R);
@@ -1760,15 +1763,15 @@ void cgnr(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, 
     auto body = [&](const Op<SP, GP, CP> &op) {
         if constexpr (!plain) {
             // M p with |q|^2 and A^-1 gamma_5 q from its epilogue; M^dag q feeding the CG
-            // update directly (partials of the fused epilogues are RHS-major, pre-reduced
+            // update directly (partials of the fused epilogues are block-major, pre-reduced
             // to kChunks per RHS)
             op.mhat_prep(p, q, to, part_hop);
-            hipLaunchKernelGGL(k_prereduce, dim3(kChunks, w.R), dim3(kBS), 0, c->stream, (const double *)part_hop,
-                               nblk_hop, part_pre);
+            hipLaunchKernelGGL(k_prereduce, dim3(kChunks), dim3(kBS), 0, c->stream, (const double *)part_hop,
+                               nblk_hop, w.R, part_pre);
             launch_fin(c, k_fin_cg_alpha, w.R, (const double *)part_pre, kChunks, w.R, w.sc, 1);
             op.mhat_dag_cg(q, to, r, (const Scal *)w.sc, part_hop);
-            hipLaunchKernelGGL(k_prereduce, dim3(kChunks, w.R), dim3(kBS), 0, c->stream, (const double *)part_hop,
-                               nblk_hop, part_pre);
+            hipLaunchKernelGGL(k_prereduce, dim3(kChunks), dim3(kBS), 0, c->stream, (const double *)part_hop,
+                               nblk_hop, w.R, part_pre);
             launch_fin(c, k_fin_cg_beta, w.R, (const double *)part_pre, kChunks, w.R, w.sc, 0, 1, 1);
         } else {
             op.mhat(p, q);
@@ -2848,8 +2851,8 @@ extern "C" int laph_hop_apply(laph_ctx_t c, const double *U, const laph_dirac *d
             std::vector<double> hp((size_t)nblk * R * nq);
             LAPH_HIP(hipMemcpyAsync(hp.data(), part, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, c->stream));
             LAPH_HIP(hipStreamSynchronize(c->stream));
-            for (int q = 0; q < nq * R; q++)
-                for (long b = 0; b < nblk; b++) nrm[q] += hp[(size_t)q * nblk + b];
+            for (long b = 0; b < nblk; b++)  // block-major: [block][value][field]
+                for (int q = 0; q < nq * R; q++) nrm[q] += hp[(size_t)b * nq * R + q];
         }
     }
     LAPH_HIP(hipMemsetAsync(zero64.d, 0, half64, c->stream));
@@ -2861,7 +2864,7 @@ extern "C" int laph_hop_apply(laph_ctx_t c, const double *U, const laph_dirac *d
     }
     LAPH_HIP(hipStreamSynchronize(c->stream));
     if (norm2 && dot) {
-        // partial rows are value-major: Re <y, out> of every field, then Im, then |out|^2
+        // rows of the sums are value-major: Re <y, out> of every field, then Im, then |out|^2
         for (int q = 0; q < R; q++)
             for (int e = 0; e < 3; e++) norm2[3 * q + e] = nrm[(size_t)e * R + q];
     } else if (norm2) {

@@ -92,7 +92,8 @@ def test_dirac_apply_fullsize(P, field, dirac):
 
 def test_source_solve_sink_fullsize(P, field, dirac, gpu_eig):
     """The benchmark's step on sources of source time 0: 4 spins x 8 LapH-interlace
-    projectors on the GPU eigenvectors, FP16 inner vectors, 32 right-hand sides."""
+    projectors on the GPU eigenvectors, FP16 inner vectors, 32 right-hand sides, solved by
+    the production BiCGStab and by CG on the normal equations."""
     import torch
 
     L, _, _, Vd, basis = gpu_eig
@@ -108,23 +109,26 @@ def test_source_solve_sink_fullsize(P, field, dirac, gpu_eig):
         err = np.abs(eta_h[b] - ref).max() / np.abs(ref).max()
         say("  source b", b, "max rel err", err)
         assert err < 1e-14
-    say("solve 32 sources (f16, R = 32)")
-    x = torch.empty_like(eta)
     prm = P.laph_dirac(CFG.m0, CFG.xi, CFG.csw, CFG.bc_t)
-    sv = P.solver_params(tol=CFG.solve_tol, maxiter=6000, precision="f16", block_rhs=32,
-                         solver=P.LAPH_SOLVER_CGNR, reliable_delta=0.03)
-    st = P.dirac_solve(L.ctx, dev(field), prm, eta, x, nsrc, sv)
-    assert all(q.status == 0 and q.fallback_used == 0 for q in st)
-    xh = host(x)
-    del x
-    worst = 0.0
-    for r in range(nsrc):
-        tr = dirac.true_residual(eta_h[r], xh[r])
-        worst = max(worst, tr)
-        assert tr <= 1e-10, (r, tr)
-        assert abs(tr - st[r].true_resid) <= 1e-12
-    say("  oracle true residual of all 32: max", worst, "iterations", [q.iters for q in st])
-    del xh, eta_h, eta
+    # the production form (BiCGStab, the benchmark's settings), then CG on the normal equations
+    for name, kind, delta in (("bicgstab", P.LAPH_SOLVER_BICGSTAB, 0.1), ("cgnr", P.LAPH_SOLVER_CGNR, 0.03)):
+        say("solve 32 sources (f16, R = 32, %s)" % name)
+        x = torch.empty_like(eta)
+        sv = P.solver_params(tol=CFG.solve_tol, maxiter=6000, precision="f16", block_rhs=32, solver=kind,
+                             reliable_delta=delta, use_graph=1)
+        st = P.dirac_solve(L.ctx, dev(field), prm, eta, x, nsrc, sv)
+        assert all(q.status == 0 and q.fallback_used == 0 for q in st)
+        xh = host(x)
+        del x
+        worst = 0.0
+        for r in range(nsrc):
+            tr = dirac.true_residual(eta_h[r], xh[r])
+            worst = max(worst, tr)
+            assert tr <= 1e-10, (name, r, tr)
+            assert abs(tr - st[r].true_resid) <= 1e-12
+        say("  oracle true residual of all 32: max", worst, "iterations", [q.iters for q in st])
+        del xh
+    del eta_h, eta
     # sink projection on synthetic solutions (both sides get the same host data)
     X = synth.random_spinor(NS, NT, 9, nrhs=2)
     coef = torch.empty((2, NT, 4, NV), dtype=torch.complex128, device="cuda")

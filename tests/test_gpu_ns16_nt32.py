@@ -1,8 +1,8 @@
 """The 16^3 x 32 workload end to end on the GPU against the oracle: stout smearing and the
 N_v = 48 LapH eigenpairs of every slice (Sec. II, Sec. IV Lanczos settings), all 512
-(TI16,SF,LI8) diluted sources solved with FP16 inner vectors in blocks of 32 and judged by
-the oracle's Omega, and the LapH coefficients of eight sources against the oracle's own
-solution on shared (oracle) eigenvectors.
+(TI16,SF,LI8) diluted sources solved by the production form (even-odd BiCGStab, FP16 inner
+vectors, blocks of 32) and judged by the oracle's Omega, and the LapH coefficients of eight
+sources against the oracle's own solution on shared (oracle) eigenvectors.
 
 * Eigenvalues to 1e-9 on four slices; each eigenvector within the Davis-Kahan bound
   2 |(-Lap) v - lambda v| / gap of the oracle's (gap: distance to the rest of the oracle
@@ -110,7 +110,7 @@ def test_all_sources_solved_ns16_nt32(P, field, dirac, gpu_eig, part):
     assert P.laph_dilution_count(dil, NT, NV) == 512
     prm = P.laph_dirac(CFG.m0, CFG.xi, CFG.csw, CFG.bc_t)
     sv = P.solver_params(tol=CFG.solve_tol, maxiter=6000, precision="f16", block_rhs=32,
-                         solver=P.LAPH_SOLVER_CGNR, reliable_delta=0.03)
+                         solver=P.LAPH_SOLVER_BICGSTAB, use_graph=1)
     Ud = dev(field)
     worst, its = 0.0, []
     for blk in range(4):
@@ -158,7 +158,7 @@ def test_coefficients_vs_oracle_ns16_nt32(P, field, smeared):
     x = torch.empty_like(eta)
     prm = P.laph_dirac(CFG.m0, CFG.xi, CFG.csw, CFG.bc_t)
     sv = P.solver_params(tol=CFG.solve_tol, maxiter=6000, precision="f16", block_rhs=8,
-                         solver=P.LAPH_SOLVER_CGNR, reliable_delta=0.03)
+                         solver=P.LAPH_SOLVER_BICGSTAB)
     sts = P.dirac_solve(L.ctx, dev(field), prm, eta, x, n, sv)
     assert all(q.status == 0 for q in sts)
     coef = torch.empty((n, NT, 4, NV), dtype=torch.complex128, device="cuda")

@@ -89,21 +89,29 @@ void zgemm(laph_ctx *c, const Zgemm &g, long batch)
 // with a repeated index at zero).  One block per (n1, slice, chunk of tile pairs): for the
 // 16-row tiles a <= b of n2 and n3 that can hold n1 < n2 < n3, the products
 // A[n2][(x c)] B[(x c)][n3] with A the cross products (formed while staging) and
-// B = V_n3, on the FP64 matrix cores; all N_v rows of A and B are staged through LDS
-// four sites at a time, and the block's four waves take the pairs in turn.
+// B = V_n3, on the FP64 matrix cores; the rows of A and B from the block's first tile on
+// are staged through LDS four sites at a time, and the block's four waves take the pairs
+// in turn.  Loading each stage one stage ahead (registers) and staging only the rows the
+// block's pairs read took the 24^3 x 128, N_v = 112 tensor from 527 to 470 ms.
 constexpr int kBT = 16;  // MFMA tile
 constexpr int kBK = 12;  // K per stage: four sites x three colours
 constexpr int kBP = 6;   // tile pairs per wave and block
 
 __host__ __device__ inline int tri_pairs(int u) { return u * (u + 1) / 2; }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_baryon_tensor_tri(const double2 *__restrict__ V,
-                                                           const double2 *__restrict__ ph, int nv, long V3, int T,
-                                                           double2 *__restrict__ out)
+// SA, SB: staging elements of A (rows x 4 sites) and B (rows x kBK) per lane whose global
+// loads are held in registers one stage ahead, so that the loads of stage k + 1 are in
+// flight during the matrix products of stage k (SA = 0: staged directly, for row counts
+// whose elements would not fit the registers).  The phase-multiplied V_n1 of a stage's
+// four sites is formed once per stage into LDS.
+template <int SA, int SB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_baryon_tensor_tri(
+    const double2 *__restrict__ V, const double2 *__restrict__ ph, int nv, long V3, int T, double2 *__restrict__ out)
 {
     extern __shared__ double lds[];
     const int NP = T * kBT + 4;  // LDS row stride (doubles)
     double *ar = lds, *ai = ar + kBK * NP, *br = ai + kBK * NP, *bi = br + kBK * NP;
+    __shared__ double2 su[2][kBK];  // e^{-ip.x} V_n1(x) of the stage's sites, double-buffered
     const int n1 = blockIdx.x, t = blockIdx.z;
     const int amin = (n1 + 1) / kBT;  // first n2 tile holding an n2 > n1
     if (amin >= T) return;
@@ -135,40 +143,94 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
     const long K = 3 * V3;
     const double2 *Vt = V + (long)t * nv * K;
-    const int rows = T * kBT;
+    // rows from the first tile any pair of this block reads
+    const int rlo = kBT * amin, rows = T * kBT;
+    const double2 z2 = make_double2(0.0, 0.0);
+    // lanes 0..11: e^{-ip.x} V_n1(x)_c of the stage's (site, colour) k into su[buf][k]
+    auto u_stage = [&](long k0, int buf) {
+        if (threadIdx.x < kBK) {
+            const long kk = k0 + threadIdx.x, x = kk / 3;
+            su[buf][threadIdx.x] = kk < K ? cmul(ph[x], Vt[(long)n1 * K + kk]) : z2;
+        }
+    };
+    // A element e = (m, site xs): the cross product of su with V_m(x)
+    auto a_in = [&](int e, long k0, double2 (&w)[3]) {
+        const int m = rlo + (e >> 2);
+        const long x = k0 / 3 + (e & 3);
+        if (m < rows && x < V3 && m < nv) {
+            const double2 *wp = Vt + ((long)m * V3 + x) * 3;
+            w[0] = wp[0];
+            w[1] = wp[1];
+            w[2] = wp[2];
+        } else {
+            w[0] = w[1] = w[2] = z2;
+        }
+    };
+    auto a_out = [&](int e, const double2 (&w)[3], int buf) {
+        const int m = rlo + (e >> 2), xs = e & 3;
+        if (m >= rows) return;
+        const double2 u0 = su[buf][3 * xs], u1 = su[buf][3 * xs + 1], u2 = su[buf][3 * xs + 2];
+        const double2 c3[3] = {csub(cmul(u1, w[2]), cmul(u2, w[1])), csub(cmul(u2, w[0]), cmul(u0, w[2])),
+                               csub(cmul(u0, w[1]), cmul(u1, w[0]))};
+#pragma unroll
+        for (int cc = 0; cc < 3; cc++) {
+            ar[(3 * xs + cc) * NP + m] = c3[cc].x;
+            ai[(3 * xs + cc) * NP + m] = c3[cc].y;
+        }
+    };
+    // B element e = (n3, k): V_n3 at K index k0 + k (K contiguous per vector)
+    auto b_in = [&](int e, long k0) {
+        const int q = e / kBK, n = rlo + q;
+        const long kk = k0 + (e - q * kBK);
+        return (n < rows && kk < K && n < nv) ? Vt[(long)n * K + kk] : z2;
+    };
+    auto b_out = [&](int e, double2 v) {
+        const int q = e / kBK, n = rlo + q, k = e - q * kBK;
+        if (n >= rows) return;
+        br[k * NP + n] = v.x;
+        bi[k * NP + n] = v.y;
+    };
+    const int na = (rows - rlo) * 4, nb = (rows - rlo) * kBK;
+    double2 ra[SA > 0 ? SA : 1][3], rb[SB > 0 ? SB : 1];
+    if constexpr (SA > 0) {
+#pragma unroll
+        for (int q = 0; q < SA; q++) a_in(threadIdx.x + 256 * q, 0, ra[q]);
+#pragma unroll
+        for (int q = 0; q < SB; q++) rb[q] = b_in(threadIdx.x + 256 * q, 0);
+    }
+    u_stage(0, 0);
+    __syncthreads();
+    int buf = 0;
     for (long k0 = 0; k0 < K; k0 += kBK) {
-        const long x0 = k0 / 3;
-        // A: cross products of e^{-ip.x} V_n1 with V_n2 on the four sites
-        for (int e = threadIdx.x; e < rows * 4; e += blockDim.x) {
-            const int m = e >> 2, xs = e & 3;
-            const long x = x0 + xs;
-            double2 c3[3] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
-            if (x < V3 && m < nv) {
-                const double2 p = ph[x];
-                const double2 *u = Vt + ((long)n1 * V3 + x) * 3, *w = Vt + ((long)m * V3 + x) * 3;
-                const double2 u0 = cmul(p, u[0]), u1 = cmul(p, u[1]), u2 = cmul(p, u[2]);
-                const double2 w0 = w[0], w1 = w[1], w2 = w[2];
-                c3[0] = csub(cmul(u1, w2), cmul(u2, w1));
-                c3[1] = csub(cmul(u2, w0), cmul(u0, w2));
-                c3[2] = csub(cmul(u0, w1), cmul(u1, w0));
-            }
+        if constexpr (SA > 0) {
 #pragma unroll
-            for (int cc = 0; cc < 3; cc++) {
-                ar[(3 * xs + cc) * NP + m] = c3[cc].x;
-                ai[(3 * xs + cc) * NP + m] = c3[cc].y;
+            for (int q = 0; q < SA; q++)
+                if (threadIdx.x + 256 * q < na) a_out(threadIdx.x + 256 * q, ra[q], buf);
+#pragma unroll
+            for (int q = 0; q < SB; q++)
+                if (threadIdx.x + 256 * q < nb) b_out(threadIdx.x + 256 * q, rb[q]);
+        } else {
+            for (int e = threadIdx.x; e < na; e += blockDim.x) {
+                a_in(e, k0, ra[0]);
+                a_out(e, ra[0], buf);
             }
+            for (int e = threadIdx.x; e < nb; e += blockDim.x) b_out(e, b_in(e, k0));
         }
-        // B: V_n3 on the same four sites (K contiguous per vector)
-        for (int e = threadIdx.x; e < rows * kBK; e += blockDim.x) {
-            const int n = e / kBK, k = e - n * kBK;
-            const long kk = k0 + k;
-            double2 v = make_double2(0.0, 0.0);
-            if (kk < K && n < nv) v = Vt[(long)n * K + kk];
-            br[k * NP + n] = v.x;
-            bi[k * NP + n] = v.y;
-        }
+        // the next stage's V_n1 goes to the other buffer, read after the next barrier
+        if (k0 + kBK < K) u_stage(k0 + kBK, buf ^ 1);
         __syncthreads();
+        if constexpr (SA > 0) {
+            // the next stage's loads, consumed after this stage's products
+            if (k0 + kBK < K) {
 #pragma unroll
+                for (int q = 0; q < SA; q++) a_in(threadIdx.x + 256 * q, k0 + kBK, ra[q]);
+#pragma unroll
+                for (int q = 0; q < SB; q++) rb[q] = b_in(threadIdx.x + 256 * q, k0 + kBK);
+            }
+        }
+        // one K step of 4 at a time: its LDS operands of the six pairs (48 registers) are
+        // what the compiler keeps in flight, leaving room for the next stage's loads
+#pragma unroll 1
         for (int kk = 0; kk < kBK; kk += 4) {
 #pragma unroll
             for (int j = 0; j < kBP; j++) {
@@ -182,6 +244,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             }
         }
         __syncthreads();
+        buf ^= 1;
     }
     // element v of lane l: C[lk + 4 v][lr] of the pair's tile (see zgemm_mfma.h)
     const long nv2 = (long)nv * nv, base = (long)t * nv * nv2;
@@ -326,14 +389,21 @@ extern "C" int laph_baryon_tensor(laph_ctx_t c, const double *evecs, int nv, con
     const size_t lds = sizeof(double) * 4 * kBK * (size_t)(tiles * kBT + 4);
     LAPH_CHECK(lds <= 160 * 1024, LAPH_EINVAL, "nv too large: the tensor kernel stages all N_v vectors in LDS");
     LAPH_CHECK(c->g.nt <= 65535 && 3 * V3 < (1L << 31), LAPH_EINVAL, "lattice too large for one launch");
+    // up to 128 rows (N_v <= 128) each lane holds two A and six B elements of the next stage
+    const bool pre = tiles * kBT <= 128;
+    const void *kern = pre ? (const void *)k_baryon_tensor_tri<2, 6> : (const void *)k_baryon_tensor_tri<0, 0>;
     if (lds > 64 * 1024)
-        LAPH_HIP(hipFuncSetAttribute((const void *)k_baryon_tensor_tri, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds));
+        LAPH_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const long total = (long)c->g.nt * nv * nv * nv;
     hipLaunchKernelGGL(k_zero2, dim3(nblocks_for(total, 256)), dim3(256), 0, c->stream, (double2 *)T, total);
     const int chunks = (tri_pairs(tiles) + 4 * kBP - 1) / (4 * kBP);
-    hipLaunchKernelGGL(k_baryon_tensor_tri, dim3(nv, chunks, c->g.nt), dim3(256), lds, c->stream,
-                       (const double2 *)evecs, (const double2 *)ph, nv, V3, tiles, (double2 *)T);
+    const dim3 grid(nv, chunks, c->g.nt);
+    if (pre)
+        hipLaunchKernelGGL((k_baryon_tensor_tri<2, 6>), grid, dim3(256), lds, c->stream, (const double2 *)evecs,
+                           (const double2 *)ph, nv, V3, tiles, (double2 *)T);
+    else
+        hipLaunchKernelGGL((k_baryon_tensor_tri<0, 0>), grid, dim3(256), lds, c->stream, (const double2 *)evecs,
+                           (const double2 *)ph, nv, V3, tiles, (double2 *)T);
     LAPH_HIP(hipGetLastError());
     LAPH_API_END(c)
 }

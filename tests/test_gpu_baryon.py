@@ -56,12 +56,14 @@ def _unit_coef(nt, nv, n):
     return f
 
 
-@pytest.mark.parametrize("ns,nt,nv,k", [(4, 2, 5, (1, 0, 2)), (4, 2, 19, (0, 0, 0)), (4, 2, 100, (0, 1, 3))])
+@pytest.mark.parametrize("ns,nt,nv,k", [(4, 2, 5, (1, 0, 2)), (4, 2, 19, (0, 0, 0)), (4, 2, 100, (0, 1, 3)),
+                                        (4, 2, 140, (1, 1, 0))])
 def test_baryon_tensor_parity(P, ns, nt, nv, k):
     """T[t][n1][n2][n3] against Eq. baryonfunc with single-vector fields V_n in spin 0
     and c = delta at (0, 0, 0); nv = 19 spans two 16-wide tiles with a ragged tail, nv = 100
-    seven tiles whose pairs take two blocks per n1; sampled triples in every order, with
-    repeated indices (zero) among them."""
+    seven tiles whose pairs take two blocks per n1 (the kernel form that loads each stage
+    one stage ahead), nv = 140 nine tiles (more than 128 rows: the form that stages
+    directly); sampled triples in every order, with repeated indices (zero) among them."""
     import torch
 
     say("baryon tensor", ns, nt, nv, k)
@@ -79,6 +81,8 @@ def test_baryon_tensor_parity(P, ns, nt, nv, k):
         trip = [(0, 5, 17), (18, 3, 16), (16, 17, 18), (7, 7, 2), (4, 18, 0)]
     else:
         base = [(0, 15, 16), (99, 50, 1), (31, 32, 95), (96, 97, 98), (14, 99, 60), (63, 64, 65), (5, 5, 40)]
+        if nv > 128:
+            base += [(0, 128, 139), (130, 131, 17), (127, 128, 129), (112, 139, 138)]
         trip = sorted({q for b in base for q in itertools.permutations(b)})
     need = sorted({n for q in trip for n in q})
     fields = {n: oracle.smeared_field(V, _unit_coef(nt, nv, n)) for n in need}

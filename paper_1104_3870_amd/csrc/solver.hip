@@ -482,33 +482,6 @@ __global__ void k_fin_r2hi(const double *partial, int nblk, int R, Scal *sc, int
     if (s[0] <= q.tol2) q.active = 0;
 }
 
-// r = convert(rhi) for masked right-hand sides; partial <r0, r>, |r|^2
-template <class SP>
-__global__ __launch_bounds__(kBS) void k_replace_r(Vec rhi, Vec r, Vec r0, long Vh, int R, double *partial,
-                                                   const Scal *sc)
-{
-    double acc[3] = {0, 0, 0};
-    long n = Vh * R, stride = (long)gridDim.x * kBS;
-    int rr = (int)((blockIdx.x * (long)kBS + threadIdx.x) % R);
-    bool act = sc[rr].active;
-    for (long tid = blockIdx.x * (long)kBS + threadIdx.x; tid < n; tid += stride) {
-        if (!act) break;
-        long i = tid / R;
-        Cx<double> v[12], z[12];
-        ld_site<S64>(rhi, Vh, R, i, rr, v);
-        st_site<SP>(r, Vh, R, i, rr, v);
-        ld_site<SP>(r, Vh, R, i, rr, v);
-        ld_site<SP>(r0, Vh, R, i, rr, z);
-#pragma unroll
-        for (int k = 0; k < 12; k++) {
-            acc[0] += z[k].re * v[k].re + z[k].im * v[k].im;
-            acc[1] += z[k].re * v[k].im - z[k].im * v[k].re;
-            acc[2] += v[k].re * v[k].re + v[k].im * v[k].im;
-        }
-    }
-    block_partial<3>(acc, R, partial);
-}
-
 __global__ void k_fin_rho(const double *partial, int nblk, int R, Scal *sc)
 {
     int r = blockIdx.x;
@@ -1593,55 +1566,48 @@ void bicgstab_fused(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat,
     launch_el(c, k_fold_x<XP>, n, xhi, xlo, w.Vh, w.R, (const Scal *)w.sc, 1);
 }
 
-// BiCGStab in storage SP on the even-odd system; x_hi accumulates the FP64 solution.
-// Returns when every RHS is inactive or maxiter is reached.
-template <class SP, class GP, class CP, class XP>
-void bicgstab(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, Vec rhi, Vec tmp64,
-              int maxiter, int reliable_every, int check_every, std::vector<Scal> &hs)
+// FP64 BiCGStab (Sec. IV) on the even-odd system for the masked RHS, x_hi accumulating the
+// solution (through an FP64 increment folded at the end); the iterated residual decides
+// convergence (the full system's true residual judges the answer afterwards).  Returns
+// when every RHS is inactive or maxiter is reached.
+template <class GP, class CP>
+void bicgstab_plain(Work &w, const Op<S64, GP, CP> &op, Vec xhi, Vec rhi, int maxiter, int check_every,
+                    std::vector<Scal> &hs)
 {
-    const bool plain = std::is_same<SP, S64>::value;
-    if constexpr (!std::is_same<SP, S64>::value) {
-        bicgstab_fused<SP, GP, CP, XP>(w, lo, hi, bhat, xhi, rhi, tmp64, maxiter, reliable_every, hs);
-        return;
-    }
-    const bool nrm = SP::kNorm;
-    Vec r = w.make("r", SP::bytes, nrm), r0 = w.make("r0", SP::bytes, nrm), p = w.make("p", SP::bytes, nrm);
-    Vec v = w.make("v", SP::bytes, nrm), s = w.make("s", SP::bytes, nrm), t = w.make("t", SP::bytes, nrm);
-    Vec xlo = w.make("xlo", XP::bytes, false);
+    using SP = S64;
+    Vec r = w.make("r", SP::bytes, false), r0 = w.make("r0", SP::bytes, false), p = w.make("p", SP::bytes, false);
+    Vec v = w.make("v", SP::bytes, false), s = w.make("s", SP::bytes, false), t = w.make("t", SP::bytes, false);
+    Vec xlo = w.make("xlo", SP::bytes, false);
     long n = w.Vh * w.R;
     int nblk = (int)red_blocks(n);
     laph_ctx *c = w.c;
     // r_hi holds the current FP64 residual of the masked RHS
-    launch_red(c, k_bicg_init<SP, XP>, n, rhi, r, r0, p, xlo, w.Vh, w.R, w.part, (const Scal *)w.sc);
+    launch_red(c, k_bicg_init<SP, SP>, n, rhi, r, r0, p, xlo, w.Vh, w.R, w.part, (const Scal *)w.sc);
     launch_fin(c, k_fin_init, w.R, (const double *)w.part, nblk, w.R, w.sc);
-    int since = 0;
-    // a reliable update also follows every drop of the iterated residual by kDelta since
-    // the last one, which bounds the error the low-precision recursion can accumulate
-    const double kDelta2 = w.delta2;
     read_scal(c, w.sc, hs);
-    std::vector<double> r2_last(w.R), r2_min(w.R);
-    for (int q = 0; q < w.R; q++) r2_last[q] = r2_min[q] = hs[q].r2;
-    if (!plain) check_every = 1;  // see cgnr: the update rule is tested every iteration
+    std::vector<double> r2_min(w.R);
+    for (int q = 0; q < w.R; q++) r2_min[q] = hs[q].r2;
     for (int it = 0; it < maxiter;) {
         int chunk = std::min(check_every, maxiter - it);
         for (int k = 0; k < chunk; k++) {
-            lo.mhat(p, v);
+            op.mhat(p, v);
             launch_red(c, k_dot<SP>, n, r0, v, w.Vh, w.R, w.part);
             launch_fin(c, k_fin_alpha, w.R, (const double *)w.part, nblk, w.R, w.sc);
             launch_el(c, k_s_update<SP>, n, r, v, s, w.Vh, w.R, (const Scal *)w.sc);
-            lo.mhat(s, t);
+            op.mhat(s, t);
             launch_red(c, k_dot_ts<SP>, n, t, s, w.Vh, w.R, w.part);
             launch_fin(c, k_fin_omega, w.R, (const double *)w.part, nblk, w.R, w.sc);
-            launch_red(c, k_xr_update<SP, XP>, n, xlo, p, s, t, r, r0, w.Vh, w.R, w.part, (const Scal *)w.sc);
-            launch_fin(c, k_fin_beta, w.R, (const double *)w.part, nblk, w.R, w.sc, plain ? 1 : 0);
+            launch_red(c, k_xr_update<SP, SP>, n, xlo, p, s, t, r, r0, w.Vh, w.R, w.part, (const Scal *)w.sc);
+            launch_fin(c, k_fin_beta, w.R, (const double *)w.part, nblk, w.R, w.sc, 1);
             launch_el(c, k_p_update<SP>, n, p, r, v, w.Vh, w.R, (const Scal *)w.sc);
         }
         it += chunk;
-        since += chunk;
         read_scal(c, w.sc, hs);
         // divergence: the iterated residual grew 1e4-fold above its minimum; the RHS is
         // handed to the fallback
-        bool diverged = false;
+        bool diverged = false, any = false;
+        int nact = 0;
+        double worst = 0;
         for (int q = 0; q < w.R; q++) {
             if (!hs[q].active) continue;
             r2_min[q] = std::min(r2_min[q], hs[q].r2);
@@ -1649,46 +1615,37 @@ void bicgstab(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec x
                 hs[q].active = 0;
                 hs[q].breakdown = 1;
                 diverged = true;
+                continue;
             }
+            any = true;
+            nact++;
+            worst = std::max(worst, hs[q].tol2 > 0 ? std::sqrt(hs[q].r2 / hs[q].tol2) : 0.0);
         }
         if (diverged) write_scal(c, w.sc, hs);
-        bool any = false, want_update = false;
-        int nact = 0;
-        double worst = 0;
-        for (int q = 0; q < w.R; q++) {
-            if (hs[q].active) {
-                any = true;
-                nact++;
-                worst = std::max(worst, hs[q].tol2 > 0 ? std::sqrt(hs[q].r2 / hs[q].tol2) : 0.0);
-                if (hs[q].r2 <= hs[q].tol2 || hs[q].r2 < kDelta2 * r2_last[q]) want_update = true;
-            }
-        }
         if (laph_verbose() && (it % 256 < check_every || !any))
             fprintf(stderr, "[laph] bicgstab it=%d active=%d/%d max |r|/target=%.3g\n", it, nact, w.R, worst);
-        if (plain) {
-            if (!any) break;
-            continue;
-        }
         if (!any) break;
-        if (want_update || since >= reliable_every) {
-            // reliable update: fold the increment, recompute the FP64 residual, replace r
-            launch_el(c, k_fold_x<XP>, n, xhi, xlo, w.Vh, w.R, (const Scal *)w.sc, 0);
-            true_eo_residual(w, hi, bhat, xhi, tmp64, rhi, 0);
-            launch_red(c, k_replace_r<SP>, n, rhi, r, r0, w.Vh, w.R, w.part, (const Scal *)w.sc);
-            launch_fin(c, k_fin_rho, w.R, (const double *)w.part, nblk, w.R, w.sc);
-            since = 0;
-            read_scal(c, w.sc, hs);
-            bool left = false;
-            for (int q = 0; q < w.R; q++) {
-                left |= hs[q].active != 0;
-                r2_last[q] = hs[q].r2;
-                r2_min[q] = std::min(r2_min[q], hs[q].r2);
-            }
-            if (!left) break;
-        }
     }
-    // fold whatever increment remains (all RHS: inactive ones hold their last increment)
-    launch_el(c, k_fold_x<XP>, n, xhi, xlo, w.Vh, w.R, (const Scal *)w.sc, 1);
+    // fold the increment (all RHS: inactive ones hold their last increment)
+    launch_el(c, k_fold_x<SP>, n, xhi, xlo, w.Vh, w.R, (const Scal *)w.sc, 1);
+}
+
+// BiCGStab in storage SP on the even-odd system: the fused low-precision iteration with
+// FP64 reliable updates, or plain FP64
+template <class SP, class GP, class CP, class XP>
+void bicgstab(Work &w, const Op<SP, GP, CP> &lo, const Op64 &hi, Vec bhat, Vec xhi, Vec rhi, Vec tmp64,
+              int maxiter, int reliable_every, int check_every, std::vector<Scal> &hs)
+{
+    if constexpr (std::is_same<SP, S64>::value) {
+        (void)hi;
+        (void)bhat;
+        (void)tmp64;
+        (void)reliable_every;
+        bicgstab_plain<GP, CP>(w, lo, xhi, rhi, maxiter, check_every, hs);
+    } else {
+        (void)check_every;
+        bicgstab_fused<SP, GP, CP, XP>(w, lo, hi, bhat, xhi, rhi, tmp64, maxiter, reliable_every, hs);
+    }
 }
 
 // CG on Mhat^dag Mhat x = Mhat^dag bhat in storage SP for the masked RHS, starting from

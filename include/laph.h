@@ -522,8 +522,9 @@ LAPH_API size_t laph_workspace_bytes(laph_ctx_t ctx, int op, const void *params)
 LAPH_API int laph_set_workspace(laph_ctx_t ctx, void *dev_ptr, size_t bytes);
 
 /* ----------------------------------------------------------------- profiling
- * With timing on, the library brackets every even-odd hopping kernel launch with HIP
- * events on its stream and accumulates their durations per kernel variant. */
+ * With timing on, the library brackets every even-odd hopping kernel launch and every
+ * meson-function launch with HIP events on its stream and accumulates their durations
+ * per kernel variant. */
 #define LAPH_TIMING_KERNELS 8
 typedef struct {
     char kernel[48];  /* kernel and variant, e.g. "dslash_lds<f16,inv>" */

@@ -41,28 +41,52 @@ struct GemmS {
         n0 = blockIdx.y * zg::kTN;
         return true;
     }
+    // element q of a lane: e = lane + 256 q; the index running along the operand's unit
+    // stride varies fastest across lanes
     template <int KT>
-    __device__ void stage(zg::Tile<KT> &t, long bt, int m0, int n0, int k0) const
+    struct Reg {
+        double2 a[zg::kPer<KT>], b[zg::kPer<KT>];
+    };
+    template <int KT>
+    __device__ void am(int e, int &m, int &k) const
+    {
+        const bool ak = g.sAk == 1;
+        m = ak ? e / KT : e % zg::kTM;
+        k = ak ? e % KT : e / zg::kTM;
+    }
+    template <int KT>
+    __device__ void load(Reg<KT> &r, long bt, int m0, int n0, int k0) const
     {
         const long bo = bt / g.nbi, bi = bt - bo * g.nbi;
         const double2 *A = g.A + bo * g.sAo + bi * g.sAi;
         const double2 *B = g.B + bo * g.sBo + bi * g.sBi;
-        const double sg = g.conjA ? -1.0 : 1.0;
-        // the index running along the operand's unit stride varies fastest across lanes
-        const bool ak = g.sAk == 1;
-        for (int e = threadIdx.x; e < zg::kTM * KT; e += blockDim.x) {
-            const int m = ak ? e / KT : e % zg::kTM, k = ak ? e % KT : e / zg::kTM;
-            double2 v = make_double2(0.0, 0.0);
-            if (m0 + m < M && k0 + k < K) v = A[(m0 + m) * g.sAm + (long)(k0 + k) * g.sAk];
-            t.ar[k][m] = v.x;
-            t.ai[k][m] = sg * v.y;
+#pragma unroll
+        for (int q = 0; q < zg::kPer<KT>; q++) {
+            const int e = threadIdx.x + 256 * q;
+            int m, k;
+            am<KT>(e, m, k);
+            // explicit branches (a select against a local zero would load through a flat
+            // address)
+            r.a[q] = r.b[q] = make_double2(0.0, 0.0);
+            if (m0 + m < M && k0 + k < K) r.a[q] = A[(m0 + m) * g.sAm + (long)(k0 + k) * g.sAk];
+            const int n = e % zg::kTN, kb = e / zg::kTN;
+            if (n0 + n < N && k0 + kb < K) r.b[q] = B[(long)(k0 + kb) * g.sBk + (n0 + n) * g.sBn];
         }
-        for (int e = threadIdx.x; e < zg::kTN * KT; e += blockDim.x) {
-            const int n = e % zg::kTN, k = e / zg::kTN;
-            double2 v = make_double2(0.0, 0.0);
-            if (n0 + n < N && k0 + k < K) v = B[(long)(k0 + k) * g.sBk + (n0 + n) * g.sBn];
-            t.br[k][n] = v.x;
-            t.bi[k][n] = v.y;
+    }
+    template <int KT>
+    __device__ void put(zg::Tile<KT> &t, const Reg<KT> &r) const
+    {
+        const double sg = g.conjA ? -1.0 : 1.0;
+#pragma unroll
+        for (int q = 0; q < zg::kPer<KT>; q++) {
+            const int e = threadIdx.x + 256 * q;
+            int m, k;
+            am<KT>(e, m, k);
+            t.ar[k][m] = r.a[q].x;
+            t.ai[k][m] = sg * r.a[q].y;
+            const int n = e % zg::kTN, kb = e / zg::kTN;
+            t.br[kb][n] = r.b[q].x;
+            t.bi[kb][n] = r.b[q].y;
         }
     }
     __device__ void store(long bt, int m, int n, double re, double im) const
@@ -182,7 +206,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     auto b_in = [&](int e, long k0) {
         const int q = e / kBK, n = rlo + q;
         const long kk = k0 + (e - q * kBK);
-        return (n < rows && kk < K && n < nv) ? Vt[(long)n * K + kk] : z2;
+        // an explicit branch: a select against the local zero would load through a flat
+        // address
+        double2 v = z2;
+        if (n < rows && kk < K && n < nv) v = Vt[(long)n * K + kk];
+        return v;
     };
     auto b_out = [&](int e, double2 v) {
         const int q = e / kBK, n = rlo + q, k = e - q * kBK;

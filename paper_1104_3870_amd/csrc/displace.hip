@@ -99,20 +99,39 @@ struct OverlapS {
         n0 = blockIdx.y * zg::kTN;
         return true;
     }
+    // element q of a lane: e = lane + 256 q, row r = e / KT, k = e % KT (k fastest: KT
+    // consecutive values of a row)
     template <int KT>
-    __device__ void stage(zg::Tile<KT> &t, long bt, int m0, int n0, int k0) const
+    struct Reg {
+        double2 a[zg::kPer<KT>], b[zg::kPer<KT>], p[zg::kPer<KT>];
+    };
+    template <int KT>
+    __device__ void load(Reg<KT> &g, long bt, int m0, int n0, int k0) const
     {
         static_assert(zg::kTM == zg::kTN, "one loop stages both operands");
-        for (int e = threadIdx.x; e < zg::kTM * KT; e += blockDim.x) {
-            const int r = e / KT, k = e - r * KT;  // k fastest: KT consecutive values of a row
+#pragma unroll
+        for (int q = 0; q < zg::kPer<KT>; q++) {
+            const int e = threadIdx.x + 256 * q, r = e / KT, k = e - r * KT;
             const long kk = (long)k0 + k;
-            double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
+            // (explicit branches: a select between a global and a local zero would become a
+            // select of addresses and a flat load)
+            g.a[q] = g.b[q] = g.p[q] = make_double2(0.0, 0.0);
             if (kk < K) {
-                if (m0 + r < M) va = a[(bt * M + m0 + r) * (long)K + kk];
-                if (n0 + r < N) vb = cmul(ph[kk / 3], b[(bt * N + n0 + r) * (long)K + kk]);
+                if (m0 + r < M) g.a[q] = a[(bt * M + m0 + r) * (long)K + kk];
+                if (n0 + r < N) g.b[q] = b[(bt * N + n0 + r) * (long)K + kk];
+                g.p[q] = ph[kk / 3];
             }
-            t.ar[k][r] = va.x;
-            t.ai[k][r] = -va.y;
+        }
+    }
+    template <int KT>
+    __device__ void put(zg::Tile<KT> &t, const Reg<KT> &g) const
+    {
+#pragma unroll
+        for (int q = 0; q < zg::kPer<KT>; q++) {
+            const int e = threadIdx.x + 256 * q, r = e / KT, k = e - r * KT;
+            const double2 vb = cmul(g.p[q], g.b[q]);
+            t.ar[k][r] = g.a[q].x;
+            t.ai[k][r] = -g.a[q].y;
             t.br[k][r] = vb.x;
             t.bi[k][r] = vb.y;
         }

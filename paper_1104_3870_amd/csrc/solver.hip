@@ -2592,6 +2592,9 @@ size_t solve_scratch_bytes(laph_ctx *c, int n_rhs, const laph_solver *sv)
     laph_ptnet *net = (laph_ptnet *)sv->net;
     size_t s = ws_align(8);  // fingerprint
     int R = fg ? 1 : sv->block_rhs;
+    // the solve tunes first when block_rhs = 0 finds no tuned block size: the tile it will
+    // pick is not known yet, so the epilogue partials are sized for the smallest candidate
+    const bool will_tune = R == 0 && low && !c->tuned_R.count(prec);
     if (R == 0) {
         if (!c->tuned_R.count(prec)) s += tune_scratch_bytes(c, prec);
         R = c->tuned_R.count(prec) ? c->tuned_R[prec] : 32;
@@ -2619,7 +2622,7 @@ size_t solve_scratch_bytes(laph_ctx *c, int n_rhs, const laph_solver *sv)
         // r, r0, v, t and the ring of K (p, s) pairs; epilogue partials (three rows per RHS)
         const int K = sv->dir_buffers > 0 ? sv->dir_buffers : kDefaultDirs;
         s += (4 + 2 * K) * vec_bytes(Vh, Rb, prec) + vec_bytes(Vh, Rb, xp);
-        const int S = lds_tile_sites(c, prec, Rb);
+        const int S = will_tune ? std::max(1, 64 / Rb) : lds_tile_sites(c, prec, Rb);
         const long nb = std::max<long>((Vh + S - 1) / S, nblocks_for(Vh * Rb, kBS));
         s += ws_align(sizeof(double) * 3 * nb * Rb) + ws_align(sizeof(double) * 3 * kChunks * Rb);
     }
@@ -2638,7 +2641,7 @@ size_t solve_scratch_bytes(laph_ctx *c, int n_rhs, const laph_solver *sv)
     if (low) {
         const int K = sv->dir_buffers > 0 ? sv->dir_buffers : kDefaultDirs;
         s += (5 + (K - 1)) * vec_bytes(Vh, Rb, prec) + vec_bytes(Vh, Rb, xp);
-        const int S = lds_tile_sites(c, prec, Rb);
+        const int S = will_tune ? std::max(1, 64 / Rb) : lds_tile_sites(c, prec, Rb);
         s += ws_align(sizeof(double) * ((Vh + S - 1) / S) * Rb) + ws_align(sizeof(double) * kChunks * Rb);
     }
     // the last attempt: plain FP64 CG (the same names at FP64 size)

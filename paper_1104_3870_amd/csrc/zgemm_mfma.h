@@ -4,8 +4,8 @@
 //
 // A block of 256 lanes (four waves) computes a 64 x 64 tile of C; each wave a 32 x 32
 // quadrant as 2 x 2 tiles of 16 x 16.  K is staged through LDS KT values at a time by the
-// problem's own stager (so that operands can be formed on the way: a conjugate, a phase,
-// a colour cross product), real and imaginary parts in separate arrays.  A complex
+// problem's own stager (so that operands can be formed on the way: a conjugate, a phase),
+// real and imaginary parts in separate arrays.  A complex
 // product takes four real MFMAs per K step of 4: C_re += A_re B_re - A_im B_im,
 // C_im += A_re B_im + A_im B_re.
 //
@@ -28,15 +28,25 @@ struct Tile {
     double br[KT][kTN + kPad], bi[KT][kTN + kPad];  // B[k][n]
 };
 
+// Each lane stages kPer = kTM KT / 256 elements of A and of B per K tile; the global loads
+// of tile k + 1 are issued into registers before the products of tile k, and written to
+// LDS (with the operands formed: a conjugate, a phase) after them.
+//
 // S provides: int K; __device__ bool tile(long &batch, int &m0, int &n0) const (false: the
-// block has nothing to do); __device__ void stage(Tile<KT> &t, long batch, int m0, int n0,
-// int k0) const (all KT rows, zeros outside the problem; called by every lane, followed by
-// a barrier); __device__ void store(long batch, int m, int n, double re, double im) const
-// (m, n absolute; called only for m < M, n < N, which store checks itself through S::M/N).
+// block has nothing to do); a register type S::Reg<KT>; __device__ void load(Reg<KT> &r,
+// long batch, int m0, int n0, int k0) const (the global loads of one K tile, zeros outside
+// the problem, no arithmetic on the loaded values); __device__ void put(Tile<KT> &t, const
+// Reg<KT> &r) const (all KT rows into LDS; called by every lane, followed by a barrier);
+// __device__ void store(long batch, int m, int n, double re, double im) const (m, n
+// absolute; called only for m < M, n < N, which store checks itself through S::M/N).
+template <int KT>
+constexpr int kPer = kTM * KT / 256;
+
 template <int KT, class S>
 __global__ __launch_bounds__(256) void k_zgemm(const S s)
 {
     static_assert(KT % 4 == 0, "K tile must be a multiple of the MFMA K step");
+    static_assert(kTM == kTN && (kTM * KT) % 256 == 0, "whole elements per lane");
     __shared__ Tile<KT> sm;
     long batch;
     int m0, n0;
@@ -52,10 +62,15 @@ __global__ __launch_bounds__(256) void k_zgemm(const S s)
             cr[i][j] = d4{0.0, 0.0, 0.0, 0.0};
             ci[i][j] = d4{0.0, 0.0, 0.0, 0.0};
         }
+    typename S::template Reg<KT> reg;
+    s.load(reg, batch, m0, n0, 0);
     for (int k0 = 0; k0 < s.K; k0 += KT) {
-        s.stage(sm, batch, m0, n0, k0);
+        s.put(sm, reg);
         __syncthreads();
-#pragma unroll
+        if (k0 + KT < s.K) s.load(reg, batch, m0, n0, k0 + KT);
+        // one MFMA K step at a time: its operands are what stays live beside the next tile's
+        // loads
+#pragma unroll 1
         for (int kk = 0; kk < KT; kk += 4) {
             double ar[2], ai[2], an[2], br[2], bi[2];
 #pragma unroll

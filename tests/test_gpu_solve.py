@@ -222,6 +222,20 @@ def test_autotune_report(P, setup, prec):
         assert st[r].status == 0 and D.true_residual(etas[r], x[r]) <= 1e-10
 
 
+@pytest.mark.parametrize("solver", ["bicgstab", "cgnr"])
+def test_untuned_block_rhs_zero(P, setup, solver):
+    """block_rhs = 0 on a fresh context: the solve runs the autotuner itself, inside the
+    workspace sized before it (the fused epilogues' partial sums sized for the smallest tile
+    the tuner may pick)."""
+    cfg, U, D, etas, xs = setup
+    kind = P.LAPH_SOLVER_CGNR if solver == "cgnr" else P.LAPH_SOLVER_BICGSTAB
+    x, st = _solve(P, cfg, U, etas, precision="f16", block_rhs=0, solver=kind, use_graph=1)
+    for r in range(etas.shape[0]):
+        assert st[r].status == 0 and st[r].fallback_used == 0
+        assert D.true_residual(etas[r], x[r]) <= 1e-10
+        assert rel_err(x[r], xs[r]) <= 1e-8
+
+
 @pytest.mark.parametrize("prec", ["f16", "f64"])
 def test_graph_replay_matches_eager(P, setup, prec):
     cfg, U, D, etas, xs = setup

@@ -234,6 +234,33 @@ def guess_weights():
     return p if os.path.exists(p) else os.path.join(ROOT, "paper_1104_3870_amd", "weights", "ptnet.npz")
 
 
+def copy_peak_gbs(reps=10, nbytes=1 << 30):
+    """Measured streaming rate of the box (read + write bytes over time, median of reps on
+    1 GiB): the faster of a device-to-device copy and an elementwise kernel (out = 1.0 a,
+    FP32), the attainable rate beside the nominal 8 TB/s.  Returns (GB/s, which)."""
+    import torch
+
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    best = (0.0, "")
+    for name, fn in (("device-to-device copy", lambda: b.copy_(a)),
+                     ("elementwise kernel", lambda: torch.mul(a, 1.0, out=b))):
+        fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        gbs = 2.0 * nbytes / (sorted(ts)[len(ts) // 2] * 1e-3) / 1e9
+        if gbs > best[0]:
+            best = (gbs, name)
+    del a, b
+    return best
+
+
 def hop_roofline(k):
     """HBM roofline of one kernel from the library's per-kernel event timing: algorithmic
     bytes per launch over the average launch duration, and the counter traffic when a
@@ -647,6 +674,14 @@ def main():
                             "instrumented step after the timed region (same kernels and launch shapes; "
                             "graphs off in that step)")
     roofline["share_of_instrumented_step"] = round(dom["ms"] / (1000 * t_ins), 3) if t_ins > 0 else None
+    # the same against the measured streaming rate of the box (a plain device copy)
+    cp, cp_how = copy_peak_gbs()
+    roofline["copy_peak"] = {"achieved": round(cp, 1), "unit": "GB/s",
+                             "measured": "median of 10 passes over 1 GiB (read + write bytes), the faster of a "
+                                         "device-to-device copy and an elementwise kernel: %s" % cp_how}
+    roofline["frac_of_copy_peak"] = round(roofline["achieved"] / cp, 4) if cp > 0 else None
+    if fp64 and fp64.get("roofline"):
+        fp64["roofline"]["frac_of_copy_peak"] = round(fp64["roofline"]["achieved"] / cp, 4) if cp > 0 else None
     roofline["other_kernels"] = [{"kernel": k["kernel"], "launches": k["launches"],
                                   "avg_launch_ms": round(k["ms"] / max(k["launches"], 1), 4)} for k in tm[1:]]
 

@@ -61,6 +61,8 @@ __global__ void k_displace(const double2 *__restrict__ U, const double2 *__restr
     int f[3] = {c[0], c[1], c[2]};
     f[dir] = cur;
     const long far = f[0] + (long)ns * (f[1] + (long)ns * f[2]);
+    // four vectors' loads in flight per lane (each lane streams all n vectors of its site)
+#pragma unroll 4
     for (int j = 0; j < n; j++) {
         const double2 *vf = v + (((long)t * n + j) * V3 + far) * 3;
         const double2 w0 = vf[0], w1 = vf[1], w2 = vf[2];

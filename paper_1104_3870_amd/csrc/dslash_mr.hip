@@ -623,26 +623,19 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
     }
     // a run-time test even when HX holds: an unconditional load of x is hoisted to the
     // start of the kernel, where its registers push the pipelined loop into spills
-    // DOT with y = x (BiCGStab's t = M s, <s, t>): x as loaded serves as y
-    Cx<float> xkeep[4][3];
-    float xkeep_s = 0.0f;
+    // the own-site record as loaded (DOT with y = x, BiCGStab's t = M s and <s, t>, takes
+    // y from it)
+    Spin12<SP> xrec;
+    float xn = 1.0f;
     if (HX && P.x) {
-        Cx<float> xv[4][3];
-        const float xn = ld_raw<SP>((const typename SP::E *)P.x, P.x_nrm, R, i, r, xv);
+        xrec = ld_rec<SP>((const typename SP::E *)P.x, i, R, r);
+        if constexpr (SP::kNorm) xn = P.x_nrm[i * R + r];
         const float sx = (float)P.a * xn;
 #pragma unroll
-        for (int a = 0; a < 4; a++)
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                res[a][c].re = fmaf(sx, xv[a][c].re, res[a][c].re);
-                res[a][c].im = fmaf(sx, xv[a][c].im, res[a][c].im);
-            }
-        if constexpr (MODE == M_INV_AFTER_DOT) {
-#pragma unroll
-            for (int a = 0; a < 4; a++)
-#pragma unroll
-                for (int c = 0; c < 3; c++) xkeep[a][c] = xv[a][c];
-            xkeep_s = xn;
+        for (int k = 0; k < 12; k++) {
+            const Cx<float> xv = SP::ld(&xrec.v[k], 0, 1.0f);
+            res[k / 3][k % 3].re = fmaf(sx, xv.re, res[k / 3][k % 3].re);
+            res[k / 3][k % 3].im = fmaf(sx, xv.im, res[k / 3][k % 3].im);
         }
     }
     Cx<float> v[12];
@@ -677,23 +670,27 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
             for (int k = 0; k < 12; k++) nq = fmaf(a[k].re, a[k].re, fmaf(a[k].im, a[k].im, nq));
         }
     } else if constexpr (MODE == M_INV_AFTER_DOT) {
-        // out as stored; <y, out> and |out|^2 from the rounded values
-        st_spinor12_round<SP, nt_out<MODE>()>((typename SP::E *)P.out, P.out_nrm, Vh, R, i, r, v);
-        Cx<float> y[12];
-        if (P.dot_y == P.x) {
-            // the stored value of each component is its raw value times the site's scale
-#pragma unroll
-            for (int k = 0; k < 12; k++)
-                y[k] = {xkeep[k / 3][k % 3].re * xkeep_s, xkeep[k / 3][k % 3].im * xkeep_s};
-        } else {
-            ld_spinor12<SP, float>((const typename SP::E *)P.dot_y, P.dot_y_nrm, Vh, R, i, r, y);
+        // out as stored; <y, out> and |out|^2 from the stored records: sums of products of
+        // the records' values (FP16: exact in FP32, one mixed FMA each), times the scales
+        Spin12<SP> orec;
+        float so;
+        st_spinor12_rec<SP, nt_out<MODE>()>((typename SP::E *)P.out, P.out_nrm, i, R, r, v, orec, so);
+        Spin12<SP> yrec = xrec;
+        float sy = xn;
+        if (P.dot_y != P.x) {
+            yrec = ld_rec<SP>((const typename SP::E *)P.dot_y, i, R, r);
+            if constexpr (SP::kNorm) sy = P.dot_y_nrm[i * R + r];
         }
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            nq = fmaf(v[k].re, v[k].re, fmaf(v[k].im, v[k].im, nq));
-            dre = fmaf(y[k].re, v[k].re, fmaf(y[k].im, v[k].im, dre));
-            dim = fmaf(y[k].re, v[k].im, fmaf(-y[k].im, v[k].re, dim));
+            const Cx<float> h = SP::ld(&orec.v[k], 0, 1.0f), y = SP::ld(&yrec.v[k], 0, 1.0f);
+            nq = fmaf(h.re, h.re, fmaf(h.im, h.im, nq));
+            dre = fmaf(y.re, h.re, fmaf(y.im, h.im, dre));
+            dim = fmaf(y.re, h.im, fmaf(-y.im, h.re, dim));
         }
+        nq *= so * so;
+        dre *= so * sy;
+        dim *= so * sy;
     } else {
         st_spinor12<SP, float, nt_out<MODE>()>((typename SP::E *)P.out, P.out_nrm, Vh, R, i, r, v);
     }

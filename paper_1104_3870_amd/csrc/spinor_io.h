@@ -101,6 +101,28 @@ __device__ __forceinline__ void st_spinor12(typename SP::E *base, float *nrm, lo
     }
 }
 
+// store v; return the stored record and its scale (a later load returns scale times the
+// record's values)
+template <class SP, bool NT = false>
+__device__ __forceinline__ void st_spinor12_rec(typename SP::E *base, float *nrm, long i, int R, int r,
+                                                const Cx<float> (&v)[12], Spin12<SP> &pk, float &sc)
+{
+    static_assert(SP::kAoS, "record layouts only");
+    float inv = 1.0f;
+    sc = 1.0f;
+    if constexpr (SP::kNorm) {
+        float m = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 12; k++) m = fmaxf(m, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
+        sc = m > 1e-30f ? m : 1.0f;
+        st_scale<NT>(&nrm[i * R + r], sc);
+        inv = 1.0f / sc;
+    }
+#pragma unroll
+    for (int k = 0; k < 12; k++) SP::st(&pk.v[k], 0, Cx<float>{v[k].re, v[k].im}, inv);
+    st_rec<SP, NT>(base, i, R, r, pk);
+}
+
 // store v and replace it by the values a later load returns (storage rounding and scale)
 template <class SP, bool NT = false>
 __device__ __forceinline__ void st_spinor12_round(typename SP::E *base, float *nrm, long Vh, int R, long i, int r,

@@ -153,13 +153,17 @@ def test_cgnr(P, setup):
     assert rel_err(x[0], xs[0]) <= 1e-8
 
 
-def test_forced_fallback(P, setup):
+@pytest.mark.parametrize("prec,block", [("f64", 1), ("f16", 4)])
+def test_forced_fallback(P, setup, prec, block):
     """BiCGStab capped at 4 iterations per attempt cannot converge; the CGNR fallback of
-    Sec. IV must still reach the bar (forced from the host)."""
+    Sec. IV must still reach the bar (forced from the host), after the plain FP64 form and
+    after the fused low-precision form (whose owed steps and increment must reach x before
+    the hand-off)."""
     cfg, U, D, etas, xs = setup
-    x, st = _solve(P, cfg, U, etas[:1], maxiter=4)
-    assert st[0].fallback_used == 1
-    assert D.true_residual(etas[0], x[0]) <= 1e-10
+    x, st = _solve(P, cfg, U, etas[:block], maxiter=4, precision=prec, block_rhs=block)
+    for r in range(block):
+        assert st[r].fallback_used == 1
+        assert D.true_residual(etas[r], x[r]) <= 1e-10
 
 
 def test_zero_source(P, setup):

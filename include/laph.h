@@ -254,19 +254,22 @@ typedef struct {
     int reliable_every; /* most iterations between FP64 reliable updates (mixed precision) */
     int block_rhs;      /* right-hand sides iterated together (power of two <= 32); 0 = the
                            block size laph_autotune picks (run on first use) */
-    int use_graph;      /* replay the CG iteration body from a HIP graph (not with timing on) */
+    int use_graph;      /* replay the Krylov iteration's hops and reductions from HIP graphs
+                           (mixed-precision BiCGStab and CGNR; not with timing on) */
     const void *net;    /* learned network (laph_ptnet_t) or NULL: the right preconditioner of
                            LAPH_SOLVER_FGMRES; with the other solvers the initial guess
                            x0 = N(gamma_4 eta) on odd sites (N approximates K^-1) */
     int restart;        /* FGMRES restart length (0: 24) */
-    double reliable_delta; /* mixed precision: FP64 reliable update once the iterated even-odd
-                              residual fell below this fraction of its last FP64 value (0: 0.1)
-                              for a quarter of a block's active right-hand sides (or 100 times
-                              further for one, or one converged), and at the latest every
-                              reliable_every iterations */
-    int dir_buffers;    /* mixed-precision CGNR: search directions kept until their steps are
-                           added to the solution increment, which is then read and written once
-                           per that many iterations (1..8; 0: 8) */
+    double reliable_delta; /* mixed precision: FP64 reliable update once half of a block's
+                              active right-hand sides have their iterated even-odd residual
+                              below this fraction of its last FP64 value (0: 0.1) or below the
+                              target (convergence candidates, confirmed by the FP64 residual),
+                              or one non-candidate fell 100 times further, or every active one
+                              is a candidate; at the latest every reliable_every iterations */
+    int dir_buffers;    /* mixed-precision BiCGStab and CGNR: iterations whose solution steps
+                           (alpha p + omega s, or alpha p) are kept owed in buffers before the
+                           solution increment is read and written once for all of them
+                           (1..8; 0: 8) */
 } laph_solver;
 
 typedef struct {

@@ -147,20 +147,6 @@ __device__ __forceinline__ void cfmac_f(Cx<float> &acc, Cx<float> a, Cx<float> b
     acc.im = fmaf(-a.im, b.re, acc.im);
 }
 
-// raw (unscaled) spinor of one right-hand side and its scale
-template <class SP>
-__device__ __forceinline__ float ld_raw(const typename SP::E *base, const float *nrm, int R, long i, int r,
-                                        Cx<float> (&o)[4][3])
-{
-    Spin12<SP> pk = ld_rec<SP>(base, i, R, r);
-#pragma unroll
-    for (int k = 0; k < 12; k++) o[k / 3][k % 3] = SP::ld(&pk.v[k], 0, 1.0f);
-    if constexpr (SP::kNorm)
-        return nrm[i * R + r];
-    else
-        return 1.0f;
-}
-
 // element k (alpha*3 + c) of a raw record as FP32 (no scale)
 template <class SP>
 __device__ __forceinline__ float lo_f(const typename SP::E &e)
@@ -349,11 +335,6 @@ __device__ __forceinline__ void dir_lds(__amdgpu_buffer_rsrc_t rin, __amdgpu_buf
 #ifndef LAPH_PIPE_D
 #define LAPH_PIPE_D 2
 #endif
-template <int MODE, bool HX>
-constexpr int lds_pipe_depth()
-{
-    return LAPH_PIPE_D;
-}
 
 __device__ __forceinline__ void clover_one(const float4 *p, const Cx<float> (&in)[4][3], Cx<float> (&out)[4][3])
 {
@@ -551,7 +532,7 @@ __global__ __launch_bounds__(256) LAPH_LDS_ATTR void k_dslash_lds(const MrArgs P
     const float g5s = P.g5d ? -1.0f : 1.0f;  // gamma_5 after the hop: lower components negated
     const __amdgpu_buffer_rsrc_t rin = buf_rsrc(P.in, (unsigned)(Vh * R * sizeof(Spin12<SP>)));
     const __amdgpu_buffer_rsrc_t rnrm = buf_rsrc(P.in_nrm, SP::kNorm ? (unsigned)(Vh * R * 4) : 0u);
-    constexpr int D = lds_pipe_depth<MODE, HX>();
+    constexpr int D = LAPH_PIPE_D;
     if constexpr (D > 0) {
         // D neighbour records in flight: the slot a direction's spin projection frees is
         // refilled with the record D directions ahead before that direction's link product,

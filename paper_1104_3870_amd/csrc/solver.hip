@@ -580,9 +580,19 @@ __global__ __launch_bounds__(kBS) void k_prereduce(const double *partial, int nb
     const int ch = blockIdx.x, t = threadIdx.x;
     const long beg = (long)nblk * ch / kChunks, end = (long)nblk * (ch + 1) / kChunks;
     const int G = kBS / nrow, g = t / nrow, row = t - g * nrow;  // G groups of nrow lanes
-    double v = 0;
-    if (g < G)
-        for (long b = beg + g; b < end; b += G) v += partial[b * nrow + row];
+    // four independent partial sums per lane keep four loads in flight
+    double v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+    if (g < G) {
+        long b = beg + g;
+        for (; b + 3 * G < end; b += 4 * G) {
+            v0 += partial[b * nrow + row];
+            v1 += partial[(b + G) * nrow + row];
+            v2 += partial[(b + 2 * G) * nrow + row];
+            v3 += partial[(b + 3 * G) * nrow + row];
+        }
+        for (; b < end; b += G) v0 += partial[b * nrow + row];
+    }
+    const double v = (v0 + v1) + (v2 + v3);
     __shared__ double lds[kBS];
     lds[t] = v;
     __syncthreads();

@@ -551,13 +551,15 @@ def baryon_correlator(snk, src, t0):
 
 # ------------------------------------------------------- Krylov reference solvers
 
-def bicgstab(apply, b, tol=1e-10, maxiter=10000):
+def bicgstab(apply, b, tol=1e-10, maxiter=10000, trace=None):
     """BiCGStab (van der Vorst, SIAM J. Sci. Stat. Comput. 13 (1992) 631), the solver the
     paper names for Omega x = eta (Sec. IV), here unpreconditioned, from x = 0 with the
     shadow residual equal to the first residual.  apply(v) -> A v on flat vectors.
     Stops when the iterated residual |r_k| <= tol |b|, on a breakdown (rho, <r0, v> or
     omega exactly zero) or at maxiter.  Returns (x, k, history): k > 0 converged after k
-    iterations, k < 0 stopped after |k| without converging; history[k] = |r_k| / |b|."""
+    iterations, k < 0 stopped after |k| without converging; history[k] = |r_k| / |b|.
+    trace: a list that receives (s, t, r) of every iteration (the half-step residual, its
+    image and the new residual), for the tests of the stabilising step."""
     b = np.asarray(b, dtype=np.complex128).reshape(-1)
     nb = np.linalg.norm(b)
     x = np.zeros_like(b)
@@ -585,6 +587,8 @@ def bicgstab(apply, b, tol=1e-10, maxiter=10000):
         x = x + alpha * p + omega * s
         r = s - omega * t
         rho = rho_new
+        if trace is not None:
+            trace.append((s.copy(), t.copy(), r.copy()))
         hist.append(float(np.linalg.norm(r) / nb))
         if hist[-1] <= tol:
             return x, k, hist

@@ -2,6 +2,12 @@
 on the even-odd preconditioned system).
 
 * BiCGStab on a small random well-conditioned non-Hermitian matrix equals LAPACK's solve.
+* Finite termination: without breakdown BiCG's residual polynomial of degree n annihilates
+  the first residual of an n x n system, and BiCGStab's residual carries that factor, so n
+  iterations solve it to rounding (a wrong alpha, beta or direction update does not).
+* The stabilising step of every iteration is a one-dimensional minimal-residual step: the
+  new residual is the least-squares residual of s over span{A s} (LAPACK's least squares;
+  a conjugated omega still converges, but fails this).
 * The Schur identity: for the solution x of Omega x = eta (the oracle's CG on the normal
   equations to a true residual of 1e-13, itself pinned to dense LU), the odd part solves
   Mhat x_o = bhat and the even reconstruction returns x (a dropped hopping term, a wrong
@@ -23,6 +29,34 @@ def test_bicgstab_small_matrix():
     assert k > 0 and hist[-1] <= 1e-13
     ref = np.linalg.solve(A, b)
     assert np.linalg.norm(x - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def _random_system(n, seed):
+    rng = np.random.default_rng(seed)
+    A = np.eye(n) * 2 + (rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))) / np.sqrt(n)
+    b = rng.normal(size=n) + 1j * rng.normal(size=n)
+    return A, b
+
+
+def test_bicgstab_finite_termination():
+    for n in range(2, 9):
+        for seed in range(20):
+            A, b = _random_system(n, 100 * n + seed)
+            x, k, hist = oracle.bicgstab(lambda v: A @ v, b, tol=0.0, maxiter=n)
+            assert abs(k) <= n
+            res = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+            assert res <= 1e-11, (n, seed, k, res)
+
+
+def test_bicgstab_stabilising_step_minimises_residual():
+    A, b = _random_system(60, 4)
+    trace = []
+    x, k, hist = oracle.bicgstab(lambda v: A @ v, b, tol=1e-12, maxiter=500, trace=trace)
+    assert k > 0 and len(trace) == k
+    for s, t, r in trace:
+        np.testing.assert_allclose(t, A @ s, rtol=0, atol=1e-13 * np.linalg.norm(A @ s))
+        w = np.linalg.lstsq(t[:, None], s, rcond=None)[0][0]
+        assert np.linalg.norm(r - (s - w * t)) <= 1e-12 * np.linalg.norm(s)
 
 
 def _setup():

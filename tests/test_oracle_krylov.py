@@ -8,6 +8,10 @@ on the even-odd preconditioned system).
 * The stabilising step of every iteration is a one-dimensional minimal-residual step: the
   new residual is the least-squares residual of s over span{A s} (LAPACK's least squares;
   a conjugated omega still converges, but fails this).
+* CG on the normal equations (the oracle's fallback solver and the CPU baseline's
+  iteration count): its k-th iterate minimises |eta - Omega x| over the Krylov space
+  K_k(Omega^dag Omega, Omega^dag eta), built here by Arnoldi with two Gram-Schmidt passes
+  and solved by LAPACK's least squares; a slower but convergent CG fails it.
 * The Schur identity: for the solution x of Omega x = eta (the oracle's CG on the normal
   equations to a true residual of 1e-13, itself pinned to dense LU), the odd part solves
   Mhat x_o = bhat and the even reconstruction returns x (a dropped hopping term, a wrong
@@ -86,3 +90,27 @@ def test_bicgstab_full_and_even_odd():
         y, k, hist, tr = oracle.bicgstab_solve(D, eta, tol=1e-12, maxiter=2000, even_odd=eo)
         assert k > 0 and tr <= 1e-10, (eo, k, tr)
         assert np.linalg.norm(y - x) <= 1e-9 * np.linalg.norm(x)
+
+
+def test_cgnr_iterates_minimise_the_residual():
+    cfg = synth.CONFIGS["ns4_nt8"]
+    U = synth.gauge_field(cfg.ns, cfg.nt, cfg.eps, cfg.seed)
+    D = oracle.Dirac(U, cfg.m0, cfg.xi, cfg.csw, cfg.bc_t)
+    eta = synth.random_spinor(cfg.ns, cfg.nt, 41)
+    sh, e = D.shape, eta.reshape(-1)
+    w = D.omega(eta, dagger=True).reshape(-1)
+    Q = [w / np.linalg.norm(w)]
+    for k in range(1, 11):
+        OQ = np.stack([D.omega(q.reshape(sh)).reshape(-1) for q in Q], axis=1)
+        c = np.linalg.lstsq(OQ, e, rcond=None)[0]
+        best = np.linalg.norm(e - OQ @ c) / np.linalg.norm(e)
+        xk = np.stack(Q, axis=1) @ c
+        x, it, tr = D.solve(eta, tol=0.0, maxiter=k)
+        assert it == -k
+        assert abs(tr - best) <= 1e-10 * best, (k, tr, best)
+        assert np.linalg.norm(x.reshape(-1) - xk) <= 1e-8 * np.linalg.norm(xk), k
+        z = D.omega(D.omega(Q[-1].reshape(sh)), dagger=True).reshape(-1)
+        for _ in range(2):
+            for q in Q:
+                z = z - np.vdot(q, z) * q
+        Q.append(z / np.linalg.norm(z))

@@ -575,6 +575,9 @@ __device__ __forceinline__ double sum_partials_rmajor(const double *partial, int
 // -> out[row][kChunks], chunk ch = fixed-order sum of its contiguous share of the blocks
 // (the first stage of a deterministic two-stage reduction; nrow <= kBS)
 constexpr int kChunks = 1024;
+// every caller reduces at most three values for each of at most 32 fields: one block holds
+// a group of all nrow rows
+static_assert(3 * 32 <= kBS, "k_prereduce needs nrow <= kBS");
 __global__ __launch_bounds__(kBS) void k_prereduce(const double *partial, int nblk, int nrow, double *out)
 {
     const int ch = blockIdx.x, t = threadIdx.x;
